@@ -1,0 +1,187 @@
+"""Serial FP64 oracle for the mixed-precision multigrid / iterative-refinement
+method of Oo & Vogel (arXiv 2007.07539).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+CPU-baseline leg of ``bench.py``.  The GPU library never imports or calls it,
+and it shares no code with the GPU library.
+
+The arithmetic lives in ``mg_ref.c`` (plain C, double precision, physical
+units); this module only marshals numpy arrays through ctypes.  Arrays are
+numpy float64 of shape ``(n, n)`` (2-D, index ``[y, x]``) or ``(n, n, n)``
+(3-D, index ``[z, y, x]``), x fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mg_ref.c")
+_LIB = os.path.join(_HERE, "libmgref.so")
+
+OK, ERR_ARG, ERR_SHAPE, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_NOMEM = 0, -1, -2, -6, -7, -9
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (serial, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _IrOpts(ctypes.Structure):
+    _fields_ = [
+        ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
+        ("residual_scaling", ctypes.c_int), ("recursive_residual", ctypes.c_int),
+        ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("use_initial_guess", ctypes.c_int),
+    ]
+
+
+class _IrResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("true_rel_residual", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        dp = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        lib.ref_points.argtypes, lib.ref_points.restype = [i, i], ctypes.c_long
+        lib.ref_levels.argtypes, lib.ref_levels.restype = [i], i
+        lib.ref_apply_A.argtypes = [i, i, dp, dp]
+        lib.ref_residual.argtypes = [i, i, dp, dp, dp]
+        lib.ref_jacobi.argtypes = [i, i, ctypes.c_double, dp, dp, dp]
+        lib.ref_restrict.argtypes = [i, i, dp, dp]
+        lib.ref_prolong.argtypes = [i, i, dp, dp]
+        lib.ref_vcycle.argtypes, lib.ref_vcycle.restype = [i, i, i, i, ctypes.c_double, dp, dp], i
+        lib.ref_norm2.argtypes, lib.ref_norm2.restype = [dp, ctypes.c_long], ctypes.c_double
+        lib.ref_norminf.argtypes, lib.ref_norminf.restype = [dp, ctypes.c_long], ctypes.c_double
+        lib.ref_ir_solve.argtypes = [i, i, dp, dp, ctypes.POINTER(_IrOpts), ctypes.POINTER(_IrResult), dp, i]
+        lib.ref_ir_solve.restype = i
+        for f in ("ref_apply_A", "ref_residual", "ref_jacobi", "ref_restrict", "ref_prolong"):
+            getattr(lib, f).restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _shape(a: np.ndarray):
+    if a.ndim not in (2, 3) or any(s != a.shape[0] for s in a.shape):
+        raise ValueError(f"expected an (n,n) or (n,n,n) array, got {a.shape}")
+    return a.ndim, a.shape[0]
+
+
+def apply_A(v):
+    """A v for the finite-difference Laplacian with zero Dirichlet boundary (Section 5)."""
+    v = _f64(v)
+    dim, n = _shape(v)
+    out = np.empty_like(v)
+    _load().ref_apply_A(dim, n, _ptr(v), _ptr(out))
+    return out
+
+
+def residual(b, c):
+    """b - A c."""
+    b, c = _f64(b), _f64(c)
+    dim, n = _shape(b)
+    out = np.empty_like(b)
+    _load().ref_residual(dim, n, _ptr(b), _ptr(c), _ptr(out))
+    return out
+
+
+def jacobi(b, c, omega=0.8):
+    """One damped-Jacobi sweep c + omega (b - A c) / diag(A) (Section 4.2)."""
+    b, c = _f64(b), _f64(c)
+    dim, n = _shape(b)
+    out = np.empty_like(b)
+    _load().ref_jacobi(dim, n, float(omega), _ptr(b), _ptr(c), _ptr(out))
+    return out
+
+
+def restrict(r):
+    """Full-weighting restriction to the next coarser grid."""
+    r = _f64(r)
+    dim, n = _shape(r)
+    nc = (n - 1) // 2
+    out = np.empty((nc,) * dim)
+    _load().ref_restrict(dim, n, _ptr(r), _ptr(out))
+    return out
+
+
+def prolong(e):
+    """Linear interpolation to the next finer grid."""
+    e = _f64(e)
+    dim, nc = _shape(e)
+    out = np.empty((2 * nc + 1,) * dim)
+    _load().ref_prolong(dim, nc, _ptr(e), _ptr(out))
+    return out
+
+
+def vcycle(b, nu1=2, nu2=2, omega=0.8):
+    """One V-cycle from a zero initial guess (Algorithm 1, recursive), physical units."""
+    b = _f64(b)
+    dim, n = _shape(b)
+    c = np.empty_like(b)
+    st = _load().ref_vcycle(dim, n, int(nu1), int(nu2), float(omega), _ptr(b), _ptr(c))
+    if st != OK:
+        raise ValueError(f"ref_vcycle failed with status {st}")
+    return c
+
+
+def norm2(v) -> float:
+    v = _f64(v).ravel()
+    return _load().ref_norm2(_ptr(v), v.size)
+
+
+def norminf(v) -> float:
+    v = _f64(v).ravel()
+    return _load().ref_norminf(_ptr(v), v.size)
+
+
+def levels(n: int) -> int:
+    return _load().ref_levels(int(n))
+
+
+@dataclass
+class IrResult:
+    status: int
+    u: np.ndarray
+    iterations: int
+    rel_residual: float
+    true_rel_residual: float
+    history: np.ndarray
+
+
+def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
+             recursive_residual=False, max_iter=100, rtol=1e-10) -> IrResult:
+    """Iterative refinement with residuum scaling and one V-cycle per step
+    (Algorithm 2), all in FP64.  Stops when ||r||_2 <= rtol ||b||_2."""
+    b = _f64(b)
+    dim, n = _shape(b)
+    u = np.zeros_like(b) if u0 is None else _f64(u0).copy()
+    opts = _IrOpts(int(nu1), int(nu2), float(omega), int(bool(residual_scaling)),
+                   int(bool(recursive_residual)), int(max_iter), float(rtol), int(u0 is not None))
+    res = _IrResult()
+    hist = np.zeros(max_iter + 2)
+    st = _load().ref_ir_solve(dim, n, _ptr(b), _ptr(u), ctypes.byref(opts), ctypes.byref(res),
+                              _ptr(hist), hist.size)
+    k = res.iterations
+    return IrResult(st, u, k, res.rel_residual, res.true_rel_residual, hist[: k + 1].copy())

@@ -1,0 +1,310 @@
+/*
+ * Serial FP64 reference implementation of the method of Oo & Vogel,
+ * "Accelerating Geometric Multigrid Preconditioning with Half-Precision
+ * Arithmetic on GPUs" (arXiv 2007.07539).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no source, header, table or helper
+ * with the GPU library, and the GPU library never calls it.
+ *
+ * Everything is computed in IEEE double precision, in physical units, with
+ * the plainest loops that state the definitions:
+ *
+ *   Model problem (Section 5): -Laplace(u) = f on the unit square (D = 2) or
+ *   unit cube (D = 3), u = 0 on the boundary.  Discretised with the standard
+ *   (2D+1)-point finite-difference stencil on n^D interior points, n = 2^m - 1,
+ *   mesh width h = 1/(n+1):
+ *       (A v)_i = (2D v_i - sum_{j face neighbour of i} v_j) / h^2,
+ *   with v_j = 0 for neighbours on the boundary (homogeneous Dirichlet).
+ *
+ *   Grid hierarchy (Section 4.2): level l has n_l = 2^(l+1) - 1 points per
+ *   dimension; level 0 (the base level) has a single interior point.  Coarse
+ *   operators are the same stencil rediscretised with h_l = 1/(n_l + 1).
+ *
+ *   Smoother (Section 4.2): damped Jacobi,  c <- c + omega * D^-1 (b - A c),
+ *   with D = diag(A) = 2D/h^2.
+ *
+ *   Transfers: full-weighting restriction (tensor product of the 1-D weights
+ *   1/4, 1/2, 1/4 centred on the coarse point's fine twin) and linear
+ *   (bi-/tri-linear) interpolation for prolongation.
+ *
+ *   V-cycle: the two-grid method of Algorithm 1 applied recursively, with an
+ *   exact solve on the one-point base level.
+ *
+ *   Outer solver: mixed-precision iterative refinement with residuum scaling,
+ *   Algorithm 2 (Section 4.3), run here entirely in FP64.
+ *
+ * Array layout: dense n^D, x fastest: index (k*n + j)*n + i in 3-D, j*n + i in
+ * 2-D.  All arrays are caller-owned.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define REF_OK 0
+#define REF_ERR_ARG -1
+#define REF_ERR_SHAPE -2
+#define REF_ERR_NOT_CONVERGED -6
+#define REF_ERR_NONFINITE -7
+#define REF_ERR_NOMEM -9
+
+/* n must be 2^m - 1 with m >= 1 so that coarsening by two ends on one point. */
+static int ref_valid_n(int n) { return n >= 1 && (((long)n + 1) & (long)n) == 0; }
+
+long ref_points(int dim, int n) {
+    return dim == 2 ? (long)n * n : (long)n * n * n;
+}
+
+/* Number of levels of the full hierarchy, finest n down to the 1-point base. */
+int ref_levels(int n) {
+    int L = 0;
+    while (n > 1) { n = (n - 1) / 2; L++; }
+    return L + 1;
+}
+
+static double ref_h(int n) { return 1.0 / (double)(n + 1); }
+
+/* v at interior coordinates (i, j, k); zero outside: homogeneous Dirichlet. */
+static double ref_get(int dim, int n, const double *v, int i, int j, int k) {
+    if (i < 0 || i >= n || j < 0 || j >= n) return 0.0;
+    if (dim == 2) return v[(long)j * n + i];
+    if (k < 0 || k >= n) return 0.0;
+    return v[((long)k * n + j) * n + i];
+}
+
+/* out = A v  (Section 5, finite-difference discretisation of -Laplace). */
+void ref_apply_A(int dim, int n, const double *v, double *out) {
+    double h = ref_h(n);
+    double inv_h2 = 1.0 / (h * h);
+    int nk = dim == 2 ? 1 : n;
+    for (int k = 0; k < nk; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                double centre = ref_get(dim, n, v, i, j, k);
+                double nb = ref_get(dim, n, v, i - 1, j, k) + ref_get(dim, n, v, i + 1, j, k) +
+                            ref_get(dim, n, v, i, j - 1, k) + ref_get(dim, n, v, i, j + 1, k);
+                if (dim == 3)
+                    nb += ref_get(dim, n, v, i, j, k - 1) + ref_get(dim, n, v, i, j, k + 1);
+                long idx = dim == 2 ? (long)j * n + i : ((long)k * n + j) * n + i;
+                out[idx] = (2.0 * dim * centre - nb) * inv_h2;
+            }
+}
+
+/* r = b - A c  (residual, Algorithm 1 step 2 and Algorithm 2). */
+void ref_residual(int dim, int n, const double *b, const double *c, double *r) {
+    long N = ref_points(dim, n);
+    ref_apply_A(dim, n, c, r);
+    for (long p = 0; p < N; p++) r[p] = b[p] - r[p];
+}
+
+/* One damped-Jacobi sweep (Section 4.2): out = c + omega * (b - A c) / diag(A).
+ * The update is simultaneous, so out must not alias c. */
+void ref_jacobi(int dim, int n, double omega, const double *b, const double *c, double *out) {
+    long N = ref_points(dim, n);
+    double h = ref_h(n);
+    double diag = 2.0 * dim / (h * h);
+    double *r = (double *)malloc(sizeof(double) * N);
+    ref_residual(dim, n, b, c, r);
+    for (long p = 0; p < N; p++) out[p] = c[p] + omega * r[p] / diag;
+    free(r);
+}
+
+/* Full-weighting restriction from a fine grid of n_f points per dimension to
+ * the coarse grid of n_c = (n_f - 1)/2 points.  Coarse point I sits on fine
+ * point 2I+1 (0-based); the 1-D weights are 1/4, 1/2, 1/4. */
+void ref_restrict(int dim, int n_f, const double *r_f, double *b_c) {
+    int n_c = (n_f - 1) / 2;
+    static const double w[3] = {0.25, 0.5, 0.25};
+    int nK = dim == 2 ? 1 : n_c;
+    for (int K = 0; K < nK; K++)
+        for (int J = 0; J < n_c; J++)
+            for (int I = 0; I < n_c; I++) {
+                double s = 0.0;
+                int oz_lo = dim == 2 ? 1 : 0, oz_hi = dim == 2 ? 1 : 2;
+                for (int oz = oz_lo; oz <= oz_hi; oz++)
+                    for (int oy = 0; oy < 3; oy++)
+                        for (int ox = 0; ox < 3; ox++) {
+                            double wt = w[ox] * w[oy] * (dim == 3 ? w[oz] : 1.0);
+                            int fi = 2 * I + ox, fj = 2 * J + oy, fk = 2 * K + oz;
+                            s += wt * ref_get(dim, n_f, r_f, fi, fj, dim == 3 ? fk : 0);
+                        }
+                long idx = dim == 2 ? (long)J * n_c + I : ((long)K * n_c + J) * n_c + I;
+                b_c[idx] = s;
+            }
+}
+
+/* Linear interpolation weight of coarse point I for fine point i (0-based):
+ * the fine twin of I is 2I+1; distance 0 -> 1, distance 1 -> 1/2. */
+static double ref_lin_w(int i, int I) {
+    int d = i - (2 * I + 1);
+    if (d == 0) return 1.0;
+    if (d == 1 || d == -1) return 0.5;
+    return 0.0;
+}
+
+/* Prolongation by bi-/tri-linear interpolation from n_c to n_f = 2 n_c + 1:
+ * e_f = P e_c, with coarse values outside the grid taken as zero. */
+void ref_prolong(int dim, int n_c, const double *e_c, double *e_f) {
+    int n_f = 2 * n_c + 1;
+    int nk = dim == 2 ? 1 : n_f;
+    for (int k = 0; k < nk; k++)
+        for (int j = 0; j < n_f; j++)
+            for (int i = 0; i < n_f; i++) {
+                /* The coarse points that can touch fine index i are
+                 * floor((i-1)/2) and floor((i-1)/2) + 1 in each dimension. */
+                int I0 = (i + 1) / 2 - 1, J0 = (j + 1) / 2 - 1, K0 = (k + 1) / 2 - 1;
+                double s = 0.0;
+                for (int dz = 0; dz < (dim == 3 ? 2 : 1); dz++)
+                    for (int dy = 0; dy < 2; dy++)
+                        for (int dx = 0; dx < 2; dx++) {
+                            int I = I0 + dx, J = J0 + dy, K = K0 + dz;
+                            double wt = ref_lin_w(i, I) * ref_lin_w(j, J);
+                            if (dim == 3) wt *= ref_lin_w(k, K);
+                            if (wt == 0.0) continue;
+                            s += wt * ref_get(dim, n_c, e_c, I, J, dim == 3 ? K : 0);
+                        }
+                long idx = dim == 2 ? (long)j * n_f + i : ((long)k * n_f + j) * n_f + i;
+                e_f[idx] = s;
+            }
+}
+
+/* Exact solve on the one-point base level: A_0 = 2D/h_0^2 is 1x1. */
+static void ref_base_solve(int dim, int n, const double *b, double *c) {
+    double h = ref_h(n);
+    long N = ref_points(dim, n);
+    if (N != 1) return;
+    c[0] = b[0] / (2.0 * dim / (h * h));
+}
+
+/* One V-cycle for A_l c = b on the level with n points per dimension
+ * (Algorithm 1 applied recursively, Section 4.2), starting from c = 0:
+ *   1. pre-smooth nu1 times,
+ *   2. residual, restrict to the coarse grid,
+ *   3. coarse correction by the same cycle one level down (exact on 1 point),
+ *   4. prolongate and add,
+ *   5. post-smooth nu2 times.
+ * Returns REF_OK or an error code. */
+int ref_vcycle(int dim, int n, int nu1, int nu2, double omega, const double *b, double *c) {
+    if ((dim != 2 && dim != 3) || !ref_valid_n(n) || nu1 < 0 || nu2 < 0) return REF_ERR_ARG;
+    long N = ref_points(dim, n);
+    if (n == 1) { ref_base_solve(dim, n, b, c); return REF_OK; }
+    int n_c = (n - 1) / 2;
+    long Nc = ref_points(dim, n_c);
+    double *tmp = (double *)malloc(sizeof(double) * N);
+    double *bc = (double *)malloc(sizeof(double) * Nc);
+    double *ec = (double *)malloc(sizeof(double) * Nc);
+    if (!tmp || !bc || !ec) { free(tmp); free(bc); free(ec); return REF_ERR_NOMEM; }
+
+    memset(c, 0, sizeof(double) * N);
+    for (int s = 0; s < nu1; s++) {                 /* step 1 */
+        ref_jacobi(dim, n, omega, b, c, tmp);
+        memcpy(c, tmp, sizeof(double) * N);
+    }
+    ref_residual(dim, n, b, c, tmp);                /* step 2 */
+    ref_restrict(dim, n, tmp, bc);
+    int st = ref_vcycle(dim, n_c, nu1, nu2, omega, bc, ec);   /* step 3 */
+    if (st == REF_OK) {
+        ref_prolong(dim, n_c, ec, tmp);             /* step 4 */
+        for (long p = 0; p < N; p++) c[p] += tmp[p];
+        for (int s = 0; s < nu2; s++) {             /* step 5 */
+            ref_jacobi(dim, n, omega, b, c, tmp);
+            memcpy(c, tmp, sizeof(double) * N);
+        }
+    }
+    free(tmp); free(bc); free(ec);
+    return st;
+}
+
+/* Pairwise sum of squares (accurate Euclidean norm). */
+static double ref_sumsq(const double *v, long N) {
+    if (N <= 8) {
+        double s = 0.0;
+        for (long p = 0; p < N; p++) s += v[p] * v[p];
+        return s;
+    }
+    long m = N / 2;
+    return ref_sumsq(v, m) + ref_sumsq(v + m, N - m);
+}
+
+double ref_norm2(const double *v, long N) { return sqrt(ref_sumsq(v, N)); }
+
+double ref_norminf(const double *v, long N) {
+    double m = 0.0;
+    for (long p = 0; p < N; p++) {
+        double a = fabs(v[p]);
+        if (a > m || a != a) m = a;          /* NaN propagates */
+    }
+    return m;
+}
+
+/* Options and result of the iterative-refinement solve. */
+typedef struct {
+    int nu1, nu2;
+    double omega;
+    int residual_scaling;      /* 1: alpha = ||r||_inf (Algorithm 2 line 4); 0: alpha = 1 */
+    int recursive_residual;    /* 1: r -= alpha A c (Algorithm 2 line 7); 0: r = b - A u */
+    int max_iter;
+    double rtol;               /* stop when ||r||_2 <= rtol ||b||_2 */
+    int use_initial_guess;     /* 0: u starts at zero */
+} ref_ir_opts;
+
+typedef struct {
+    int iterations;            /* V-cycles applied */
+    double rel_residual;       /* ||r||_2 / ||b||_2 of the returned iterate (as tracked) */
+    double true_rel_residual;  /* ||b - A u||_2 / ||b||_2 recomputed at the end */
+} ref_ir_result;
+
+/* Mixed-precision iterative refinement with residuum scaling (Algorithm 2),
+ * every step in FP64.  history (optional, length hist_cap) receives
+ * ||r||_2/||b||_2 before each V-cycle and after the last one. */
+int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *o,
+                 ref_ir_result *res, double *history, int hist_cap) {
+    if ((dim != 2 && dim != 3) || !o || !res) return REF_ERR_ARG;
+    if (!ref_valid_n(n)) return REF_ERR_SHAPE;
+    long N = ref_points(dim, n);
+    memset(res, 0, sizeof(*res));
+    double nb = ref_norm2(b, N);
+    if (nb != nb || isinf(nb)) return REF_ERR_NONFINITE;
+    if (nb == 0.0) {                      /* A u = 0 has the solution u = 0 */
+        memset(u, 0, sizeof(double) * N);
+        if (history && hist_cap > 0) history[0] = 0.0;
+        return REF_OK;
+    }
+    double *r = (double *)malloc(sizeof(double) * N);
+    double *rl = (double *)malloc(sizeof(double) * N);
+    double *c = (double *)malloc(sizeof(double) * N);
+    double *ac = (double *)malloc(sizeof(double) * N);
+    if (!r || !rl || !c || !ac) { free(r); free(rl); free(c); free(ac); return REF_ERR_NOMEM; }
+
+    if (!o->use_initial_guess) memset(u, 0, sizeof(double) * N);
+    ref_residual(dim, n, b, u, r);        /* r_high := b_high - A_high u_high */
+    int st = REF_OK;
+    int k = 0;
+    for (;;) {
+        double rn = ref_norm2(r, N);
+        if (history && k < hist_cap) history[k] = rn / nb;
+        res->rel_residual = rn / nb;
+        if (rn != rn || isinf(rn)) { st = REF_ERR_NONFINITE; break; }
+        if (rn <= o->rtol * nb) break;
+        if (k >= o->max_iter) { st = REF_ERR_NOT_CONVERGED; break; }
+        double alpha = o->residual_scaling ? ref_norminf(r, N) : 1.0;
+        double inv_alpha = 1.0 / alpha;
+        for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];        /* line 4 */
+        int vs = ref_vcycle(dim, n, o->nu1, o->nu2, o->omega, rl, c);  /* line 5 */
+        if (vs != REF_OK) { st = vs; break; }
+        for (long p = 0; p < N; p++) u[p] += alpha * c[p];             /* line 6 */
+        if (o->recursive_residual) {                                   /* line 7 */
+            ref_apply_A(dim, n, c, ac);
+            for (long p = 0; p < N; p++) r[p] -= alpha * ac[p];
+        } else {
+            ref_residual(dim, n, b, u, r);
+        }
+        k++;
+    }
+    res->iterations = k;
+    ref_residual(dim, n, b, u, ac);
+    res->true_rel_residual = ref_norm2(ac, N) / nb;
+    free(r); free(rl); free(c); free(ac);
+    return st;
+}

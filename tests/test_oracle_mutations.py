@@ -1,0 +1,46 @@
+"""The oracle pins must catch plausible mistakes: each case plants one mistake
+in a copy of the oracle's C source (on the CPU only), rebuilds the copy and
+runs the pin suite against it, which has to fail."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = {
+    "operator_diagonal": ("out[idx] = (2.0 * dim * centre - nb) * inv_h2;",
+                          "out[idx] = (2.0 * dim * centre + nb) * inv_h2;"),
+    "operator_h_scale": ("double inv_h2 = 1.0 / (h * h);", "double inv_h2 = 1.0 / h;"),
+    "jacobi_damping": ("out[p] = c[p] + omega * r[p] / diag;", "out[p] = c[p] + r[p] / diag;"),
+    "restrict_weights": ("static const double w[3] = {0.25, 0.5, 0.25};",
+                         "static const double w[3] = {0.25, 0.25, 0.5};"),
+    "restrict_offset": ("int fi = 2 * I + ox, fj = 2 * J + oy", "int fi = 2 * I + ox + 1, fj = 2 * J + oy"),
+    "prolong_weight": ("if (d == 1 || d == -1) return 0.5;", "if (d == 1 || d == -1) return 0.25;"),
+    "coarse_correction_sign": ("for (long p = 0; p < N; p++) c[p] += tmp[p];",
+                               "for (long p = 0; p < N; p++) c[p] -= tmp[p];"),
+    "base_solve": ("c[0] = b[0] / (2.0 * dim / (h * h));", "c[0] = b[0] / (2.0 * dim / h);"),
+    "no_post_smoothing": ("for (int s = 0; s < nu2; s++) {             /* step 5 */",
+                          "for (int s = 0; s < 0; s++) {             /* step 5 */"),
+    "scaling_not_compensated": ("u[p] += alpha * c[p];", "u[p] += c[p];"),
+    "recursive_residual_sign": ("r[p] -= alpha * ac[p];", "r[p] += alpha * ac[p];"),
+    "norm_without_sqrt": ("return sqrt(ref_sumsq(v, N));", "return ref_sumsq(v, N);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(tmp_path, name):
+    old, new = MUTATIONS[name]
+    dst = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), dst,
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = (dst / "mg_ref.c").read_text()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    (dst / "mg_ref.c").write_text(src.replace(old, new))
+    env = dict(os.environ, MGREF_ORACLE_DIR=str(dst))
+    proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert proc.returncode != 0, f"pins did not catch mutation {name}:\n{proc.stdout[-2000:]}"

@@ -1,0 +1,306 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+closed forms of the discrete Laplacian and its transfer operators, dense
+linear algebra on tiny grids, an exact discrete solve through the type-I sine
+transform, the paper's Table 1, and the paper's claims about scaling."""
+import os
+from decimal import Decimal
+
+import numpy as np
+import pytest
+import scipy.fft
+
+from tests import dense_ref
+from paper_2007_07539_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _mode(dim, n, k):
+    return W.sine_mode(dim, n, k)
+
+
+def _lam(dim, n, k):
+    """Eigenvalue of the FD Laplacian for mode k: (4/h^2) sum_d sin^2(k_d pi h/2)."""
+    h = 1.0 / (n + 1)
+    return 4.0 / h**2 * sum(np.sin(kd * np.pi * h / 2) ** 2 for kd in k[:dim])
+
+
+# --- Table 1 -----------------------------------------------------------------
+
+def test_table1_formats_match_ieee():
+    """Table 1 of the paper lists r_min, r_max and unit roundoff of FP16/32/64."""
+    rows = {}
+    with open(os.path.join(GOLDEN, "table1_fp_formats.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, rmin, rmax, ulog = line.split()
+                rows[name] = (Decimal(rmin), Decimal(rmax), int(ulog))
+    for name, dt in (("FP16", np.float16), ("FP32", np.float32), ("FP64", np.float64)):
+        fi = np.finfo(dt)
+        rmin, rmax, ulog = rows[name]
+        # the table prints three significant digits (FP64's r_max rounds above DBL_MAX)
+        assert abs(Decimal(float(fi.tiny)) / rmin - 1) < Decimal("5e-3")
+        assert abs(Decimal(float(fi.max)) / rmax - 1) < Decimal("5e-3")
+        assert float(fi.eps) / 2 == 2.0**ulog
+
+
+# --- operator, smoother, transfers on eigenmodes ------------------------------
+
+@pytest.mark.parametrize("dim,n,k", [(2, 15, (1, 1, 1)), (2, 31, (3, 7, 1)), (3, 15, (1, 2, 3)),
+                                     (3, 7, (7, 1, 4)), (3, 31, (5, 31, 2))])
+def test_operator_eigenmodes(ref, dim, n, k):
+    v = _mode(dim, n, k)
+    Av = ref.apply_A(v)
+    np.testing.assert_allclose(Av, _lam(dim, n, k) * v, rtol=0, atol=1e-12 * np.abs(Av).max())
+
+
+@pytest.mark.parametrize("dim,n,k", [(2, 15, (2, 9, 1)), (3, 7, (1, 2, 3)), (3, 15, (15, 15, 15)),
+                                     (3, 15, (8, 1, 12))])
+def test_jacobi_eigenmode_factor(ref, dim, n, k):
+    """One sweep with b = 0 multiplies mode k by 1 - (2 omega / D) sum sin^2(k pi h / 2)."""
+    omega = 0.8
+    h = 1.0 / (n + 1)
+    v = _mode(dim, n, k)
+    out = ref.jacobi(np.zeros_like(v), v, omega)
+    g = 1 - (2 * omega / dim) * sum(np.sin(kd * np.pi * h / 2) ** 2 for kd in k[:dim])
+    np.testing.assert_allclose(out, g * v, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim,mu", [(2, 0.6), (3, 11 / 15)])
+def test_smoothing_factor(ref, dim, mu):
+    """Damped Jacobi (omega = 0.8) damps the oscillatory half of the spectrum by
+    at most mu = max(|1 - omega/D|, |1 - 2 omega|): 0.6 in 2-D, 11/15 in 3-D.
+    The oracle's worst factor over those modes on 7^D equals the closed form
+    over the same modes, which approaches mu from below as h -> 0."""
+    n, omega = 7, 0.8
+    h = 1.0 / (n + 1)
+    worst, worst_cf = 0.0, 0.0
+    for k in np.ndindex(*(n,) * dim):
+        k = tuple(x + 1 for x in k)
+        if max(k) <= (n + 1) // 2:
+            continue
+        v = _mode(dim, n, k)
+        out = ref.jacobi(np.zeros_like(v), v, omega)
+        worst = max(worst, np.abs(out).max() / np.abs(v).max())
+        g = 1 - (2 * omega / dim) * sum(np.sin(kd * np.pi * h / 2) ** 2 for kd in k)
+        worst_cf = max(worst_cf, abs(g))
+    assert worst == pytest.approx(worst_cf, abs=1e-13)
+    assert worst_cf <= mu + 1e-15
+    big = 4095
+    hb = 1.0 / (big + 1)
+    kk = [(big + 1) // 2 + 1] + [1] * (dim - 1)
+    g = 1 - (2 * omega / dim) * sum(np.sin(kd * np.pi * hb / 2) ** 2 for kd in kk)
+    assert max(abs(g), abs(1 - 2 * omega)) == pytest.approx(mu, abs=2e-3)
+
+
+@pytest.mark.parametrize("dim,nf,k", [(2, 15, (1, 3, 1)), (3, 15, (2, 5, 7)), (3, 31, (1, 1, 1)),
+                                      (2, 63, (30, 17, 1))])
+def test_restriction_of_smooth_modes(ref, dim, nf, k):
+    """Full weighting maps fine mode k (k <= n_c) to prod cos^2(k pi h/2) times coarse mode k."""
+    h = 1.0 / (nf + 1)
+    nc = (nf - 1) // 2
+    out = ref.restrict(_mode(dim, nf, k))
+    g = np.prod([np.cos(kd * np.pi * h / 2) ** 2 for kd in k[:dim]])
+    np.testing.assert_allclose(out, g * _mode(dim, nc, k), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("nc,k", [(7, 1), (7, 5), (15, 3), (15, 15)])
+def test_prolongation_of_coarse_modes_1d_factor(ref, nc, k):
+    """Interpolation maps coarse mode k to cos^2(k pi h/2) v_k - sin^2(k pi h/2) v_{n+1-k};
+    checked through the 2-D tensor product with a second factor mode 1."""
+    nf = 2 * nc + 1
+    h = 1.0 / (nf + 1)
+    e = _mode(2, nc, (k, 1))
+    out = ref.prolong(e)
+    c2, s2 = np.cos(k * np.pi * h / 2) ** 2, np.sin(k * np.pi * h / 2) ** 2
+    c1, s1 = np.cos(np.pi * h / 2) ** 2, np.sin(np.pi * h / 2) ** 2
+    # P is the tensor product of the 1-D rule along x (mode k) and y (mode 1)
+    expect = (c1 * (c2 * _mode(2, nf, (k, 1)) - s2 * _mode(2, nf, (nf + 1 - k, 1)))
+              - s1 * (c2 * _mode(2, nf, (k, nf)) - s2 * _mode(2, nf, (nf + 1 - k, nf))))
+    np.testing.assert_allclose(out, expect, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim,nc", [(2, 3), (2, 7), (3, 3)])
+def test_prolongation_is_scaled_restriction_transpose(ref, dim, nc):
+    """P = 2^D R^T, column by column, between the oracle's two separately written loops."""
+    nf = 2 * nc + 1
+    Nc, Nf = nc**dim, nf**dim
+    P = np.zeros((Nf, Nc))
+    for j in range(Nc):
+        e = np.zeros(Nc)
+        e[j] = 1
+        P[:, j] = ref.prolong(e.reshape((nc,) * dim)).ravel()
+    R = np.zeros((Nc, Nf))
+    for i in range(Nf):
+        e = np.zeros(Nf)
+        e[i] = 1
+        R[:, i] = ref.restrict(e.reshape((nf,) * dim)).ravel()
+    np.testing.assert_array_equal(P, 2**dim * R.T)
+    np.testing.assert_array_equal(P, dense_ref.prolong(dim, nc))
+    np.testing.assert_array_equal(R, dense_ref.restrict(dim, nf))
+
+
+# --- dense checks on tiny grids ------------------------------------------------
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (2, 7), (3, 3), (3, 7)])
+def test_operator_matches_dense(ref, dim, n):
+    N = n**dim
+    A = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1
+        A[:, j] = ref.apply_A(e.reshape((n,) * dim)).ravel()
+    np.testing.assert_allclose(A, dense_ref.lap(dim, n), rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (2, 7), (3, 3), (3, 7)])
+def test_vcycle_operator_matches_two_grid_recursion(ref, dim, n):
+    """Columns of the oracle's V-cycle equal (I - E) A^-1 with
+    E = S^nu2 (I - P M_c R A) S^nu1, recursively (Algorithm 1); the operator is
+    symmetric and positive definite."""
+    N = n**dim
+    M = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1
+        M[:, j] = ref.vcycle(e.reshape((n,) * dim)).ravel()
+    Md = dense_ref.vcycle_matrix(dim, n)
+    scale = np.abs(Md).max()
+    np.testing.assert_allclose(M, Md, rtol=0, atol=1e-14 * scale)
+    np.testing.assert_allclose(M, M.T, rtol=0, atol=1e-14 * scale)
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (2, 7), (3, 3), (3, 7)])
+def test_ir_matches_dense_solve(ref, dim, n):
+    rng = np.random.default_rng(100 + n + dim)
+    b = rng.uniform(-1, 1, (n,) * dim)
+    res = ref.ir_solve(b, rtol=1e-14, max_iter=200)
+    assert res.status == 0
+    x = np.linalg.solve(dense_ref.lap(dim, n), b.ravel()).reshape(b.shape)
+    assert np.abs(res.u - x).max() <= 1e-12 * np.abs(x).max()
+
+
+# --- exact discrete solve by the type-I sine transform --------------------------
+
+def _dst_solve(b):
+    """A^-1 b exactly (up to rounding): the type-I DST diagonalises the Dirichlet
+    FD Laplacian with eigenvalues (4/h^2) sum_d sin^2(k_d pi h / 2)."""
+    dim, n = b.ndim, b.shape[0]
+    h = 1.0 / (n + 1)
+    bh = scipy.fft.dstn(b, type=1)
+    k = np.arange(1, n + 1)
+    s = 4.0 / h**2 * np.sin(k * np.pi * h / 2) ** 2
+    lam = sum(np.expand_dims(s, tuple(a for a in range(dim) if a != ax)) for ax in range(dim))
+    return scipy.fft.idstn(bh / lam, type=1)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 63), (3, 31), (3, 63)])
+def test_ir_matches_sine_transform_solve(ref, dim, n):
+    b = W.uniform_rhs(dim, n, seed=7)
+    res = ref.ir_solve(b, rtol=1e-13, max_iter=100)
+    assert res.status == 0 and res.true_rel_residual <= 1e-13
+    x = _dst_solve(b)
+    assert np.abs(res.u - x).max() <= 1e-10 * np.abs(x).max()
+
+
+def test_torsion_function_limit(ref):
+    """max of A^-1 1 approaches the centre value of the torsion function of the
+    unit square, sum over odd j,k of 16 (-1)^((j+k)/2-1) / (pi^4 j k (j^2+k^2)),
+    with O(h^2) error."""
+    j = np.arange(1, 1600, 2)
+    J, K = np.meshgrid(j, j)
+    sign = (-1.0) ** ((J - 1) // 2 + (K - 1) // 2)
+    exact = np.sum(16 * sign / (np.pi**4 * J * K * (J**2 + K**2)))
+    assert exact == pytest.approx(0.0736713532, abs=1e-8)
+    for n, tol in ((31, 2e-4), (63, 5e-5)):
+        u = ref.ir_solve(np.ones((n, n)), rtol=1e-12).u
+        assert abs(u.max() - exact) < tol
+
+
+# --- closed-form workloads ------------------------------------------------------
+
+def test_poisson2d_closed_form(ref):
+    """f = 2 pi^2 sin(pi x) sin(pi y) is an eigenvector of A, so the discrete
+    solution is [(pi h/2)^2 / sin^2(pi h/2)] sin(pi x) sin(pi y) exactly."""
+    n = 255
+    h = 1.0 / (n + 1)
+    b = W.poisson2d_sine_rhs(n)
+    res = ref.ir_solve(b)
+    assert res.status == 0 and res.rel_residual <= 1e-10
+    amp = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2
+    assert amp == pytest.approx(1.0000125499454737, rel=1e-15)
+    uh = amp * W.sine_mode(2, n, (1, 1))
+    assert np.abs(res.u - uh).max() <= 1e-9
+    # discretisation error against the continuous solution: (amp - 1), O(h^2)
+    err = np.abs(res.u - W.sine_mode(2, n, (1, 1))).max()
+    assert err == pytest.approx(amp - 1, rel=1e-3)
+
+
+def test_poisson3d_sine_mode_amplitude(ref):
+    n = 31
+    b = W.poisson3d_sine_noise_rhs(n, noise=0.0)
+    res = ref.ir_solve(b, rtol=1e-12)
+    amp = 14 * np.pi**2 / _lam(3, n, (1, 2, 3))
+    np.testing.assert_allclose(res.u, amp * W.sine_mode(3, n, (1, 2, 3)), rtol=0, atol=1e-10)
+
+
+# --- invariants and the paper's qualitative claims --------------------------------
+
+def test_vcycle_power_of_two_scaling_is_exact(ref):
+    b = W.uniform_rhs(3, 15, seed=11)
+    c = ref.vcycle(b)
+    for j in (-20, -3, 5, 17):
+        np.testing.assert_array_equal(ref.vcycle(b * 2.0**j), c * 2.0**j)
+
+
+def test_vcycle_linearity(ref):
+    a, b = W.uniform_rhs(3, 15, seed=12), W.uniform_rhs(3, 15, seed=13)
+    np.testing.assert_allclose(ref.vcycle(a + 3 * b), ref.vcycle(a) + 3 * ref.vcycle(b),
+                               rtol=0, atol=1e-15 * np.abs(ref.vcycle(a)).max() * 10)
+
+
+def test_scaling_on_and_off_same_iteration(ref):
+    """In FP64 the residuum scaling changes nothing but rounding: the FP64
+    baseline without scaling takes the same iterations (Section 6)."""
+    b = W.uniform_rhs(3, 31, seed=2)
+    on = ref.ir_solve(b, residual_scaling=True)
+    off = ref.ir_solve(b, residual_scaling=False)
+    assert on.iterations == off.iterations
+    assert np.abs(on.u - off.u).max() <= 1e-12 * np.abs(on.u).max()
+
+
+def test_recursive_and_true_residual_agree(ref):
+    """Algorithm 2 updates r recursively; recomputing b - A u instead gives the
+    same iterates up to rounding."""
+    b = W.uniform_rhs(3, 31, seed=3)
+    rec = ref.ir_solve(b, recursive_residual=True)
+    tru = ref.ir_solve(b, recursive_residual=False)
+    assert rec.iterations == tru.iterations
+    assert rec.true_rel_residual <= 1e-10 and tru.true_rel_residual <= 1e-10
+    assert np.abs(rec.u - tru.u).max() <= 1e-11 * np.abs(tru.u).max()
+
+
+def test_ir_edge_cases(ref):
+    z = np.zeros((7, 7, 7))
+    r = ref.ir_solve(z)
+    assert r.status == 0 and r.iterations == 0 and not r.u.any()
+    b = W.uniform_rhs(3, 7, seed=1)
+    r = ref.ir_solve(b, max_iter=2)
+    assert r.status == -6 and r.iterations == 2
+    b[3, 3, 3] = np.nan
+    assert ref.ir_solve(b).status == -7
+    one = ref.ir_solve(np.full((1, 1, 1), 6.0))
+    assert one.iterations == 1 and one.u[0, 0, 0] == pytest.approx(6.0 / (6 / 0.25))
+
+
+def test_fp16_flush_without_scaling():
+    """Small residual entries vanish in FP16 without scaling (Section 4.3); with
+    the inf-norm scaling the largest entry becomes 1 and the rest stay in range."""
+    rng = np.random.default_rng(0)
+    r = 1e-9 * rng.uniform(-1, 1, 10000)
+    assert not r.astype(np.float16).any()
+    a = np.abs(r).max()
+    q = (r * (1 / a)).astype(np.float16)
+    assert np.abs(q).max() == 1.0
+    assert np.count_nonzero(q) > 0.999 * r.size
