@@ -1,0 +1,164 @@
+"""Benchmark: solved DoF/s of the mixed-precision iterative-refinement solve
+(FP64 refinement, FP16 V-cycle) against the FP64 solve on the same GPU, on the
+3-D 511^3 Poisson problem with f = 14 pi^2 sin(pi x) sin(2 pi y) sin(3 pi z)
+plus 1e-3 uniform noise (9 levels, V(2,2), omega = 0.8, rel. residual 1e-10).
+
+One step = one complete solve (every kernel of the refinement loop and the
+V-cycle) from u = 0 with b resident in HBM.  Prints one JSON line on stdout;
+progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_solves(solver, bt, u, steps, warmup, torch):
+    for _ in range(warmup):
+        solver.solve(bt, u)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    results = []
+    start.record()
+    for _ in range(steps):
+        _, r = solver.solve(bt, u)
+        results.append(r)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps, results
+
+
+def kernel_table(prof, level=0):
+    """Aggregate one profiled refinement step by kernel name on one level."""
+    agg = {}
+    for name, lvl, ms, by in prof:
+        if lvl != level:
+            continue
+        a = agg.setdefault(name, {"launches": 0, "ms": 0.0, "bytes": 0.0})
+        a["launches"] += 1
+        a["ms"] += ms
+        a["bytes"] += by
+    for a in agg.values():
+        a["avg_ms"] = a["ms"] / a["launches"]
+        a["GBps"] = a["bytes"] / (a["ms"] * 1e-3) / 1e9 if a["ms"] > 0 else 0.0
+    return agg
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=511)
+    ap.add_argument("--map", default="f16")
+    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle IR iterations timed for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="only run the mixed solve (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2007_07539_amd import mgir
+    from paper_2007_07539_amd import workloads as W
+
+    n = args.n
+    L = W.levels_for(n)
+    N = n**3
+    log(f"[bench] generating RHS n={n}")
+    b = W.poisson3d_sine_noise_rhs(n, seed=3)
+    dev = torch.device("cuda:0")
+    bt = torch.from_numpy(b).to(dev)
+    u = torch.zeros_like(bt)
+
+    log("[bench] setup mixed solver")
+    mixed = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=True, device=dev)
+    ms_mixed, res_mixed = timed_solves(mixed, bt, u, args.steps, args.warmup, torch)
+    log(f"[bench] mixed: {ms_mixed:.2f} ms/solve, {res_mixed[-1].iterations} it, rel {res_mixed[-1].rel_residual:.2e}")
+    prof = mixed.profile_step()
+    kt = kernel_table(prof)
+    del mixed
+    torch.cuda.empty_cache()
+
+    fp64 = None
+    if not args.profile_only:
+        log("[bench] setup FP64 solver")
+        fp64 = mgir.Solver(3, n, W.precision_map("f64", L), residual_scaling=False, device=dev)
+        ms64, res64 = timed_solves(fp64, bt, u, args.steps, args.warmup, torch)
+        log(f"[bench] fp64: {ms64:.2f} ms/solve, {res64[-1].iterations} it, rel {res64[-1].rel_residual:.2e}")
+        kt64 = kernel_table(fp64.profile_step())
+        del fp64
+        torch.cuda.empty_cache()
+
+    dofs_mixed = N / (ms_mixed * 1e-3)
+    # dominant kernel: the finest-level kernel with the largest share of the step
+    dom_name = max(kt, key=lambda k: kt[k]["ms"])
+    dom = kt[dom_name]
+    achieved = dom["bytes"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "solved DoF/s to rel. residual 1e-10, mixed vs FP64 on GPU; achieved HBM GB/s",
+        "value": dofs_mixed,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mixed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 refinement + f16 V-cycle (f32 accumulate)" if args.map == "f16" else args.map,
+        "data": "synthetic",
+        "config": {"workload": f"poisson3d_{n}_sine_noise", "n": n, "levels": L, "map": args.map,
+                   "cycle": "V(2,2) damped Jacobi omega=0.8", "rtol": 1e-10},
+        "iterations_mixed": res_mixed[-1].iterations,
+        "rel_residual_mixed": res_mixed[-1].rel_residual,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_ms": dom["avg_ms"], "bytes_per_launch": dom["bytes"] / dom["launches"]},
+        "kernels_finest": {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1),
+                               "launches": v["launches"]} for k, v in kt.items()},
+    }
+    if not args.profile_only:
+        out["fp64_value"] = N / (ms64 * 1e-3)
+        out["fp64_ms_per_step"] = ms64
+        out["iterations_fp64"] = res64[-1].iterations
+        out["speedup_mixed_vs_fp64"] = ms64 / ms_mixed
+        out["kernels_finest_fp64"] = {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1)}
+                                      for k, v in kt64.items()}
+    if not args.no_cpu_baseline and not args.profile_only:
+        import oracle
+        oracle.build()
+        k = args.cpu_iters
+        log(f"[bench] oracle: {k} FP64 IR iterations at n={n} on the host (1 thread)")
+        t0 = time.perf_counter()
+        o = oracle.ir_solve(b, residual_scaling=False, recursive_residual=True, max_iter=k)
+        t = time.perf_counter() - t0
+        iters = res64[-1].iterations
+        out["cpu_baseline"] = {
+            "value": N / (t / max(o.iterations, 1) * iters), "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{o.iterations} FP64 IR iterations of the serial C oracle on the same {n}^3 RHS "
+                      f"({t:.1f} s incl. the initial residual), extrapolated to the FP64 solve's {iters} iterations",
+            "host_cpus": os.cpu_count(),
+        }
+        log(f"[bench] oracle: {t:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

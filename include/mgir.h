@@ -1,0 +1,193 @@
+/*
+ * mgir.h - C ABI of the MI355X (gfx950) mixed-precision geometric-multigrid /
+ * iterative-refinement Poisson solver.
+ *
+ * Method: Oo & Vogel, "Accelerating Geometric Multigrid Preconditioning with
+ * Half-Precision Arithmetic on GPUs" (arXiv 2007.07539).  The outer solver is
+ * iterative refinement with residuum scaling (Algorithm 2, Section 4.3) in
+ * FP64; its correction equation is approximated by one multigrid V-cycle
+ * (Algorithm 1 applied recursively, Section 4.2) whose levels store vectors in
+ * FP64, FP32, FP16 or BF16 (the per-level precision variants of Table 2 and
+ * Section 6).
+ *
+ * Problem: -Laplace(u) = f on the unit square (dim = 2) or cube (dim = 3) with
+ * u = 0 on the boundary (Section 5), discretised by the 5-/7-point finite-
+ * difference stencil on n^dim interior points, n = 2^m - 1, h = 1/(n+1):
+ *     (A u)_i = (2 dim u_i - sum of face neighbours) / h^2.
+ * The hierarchy coarsens by two per dimension down to one interior point,
+ * where the base-level solve is exact.
+ *
+ * Conventions for every function below:
+ *   - Every function returns an mg_status_t; no C++ exception crosses the ABI.
+ *     On error, mg_last_error() returns a thread-local message.
+ *   - Validation errors (MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_PREC,
+ *     MG_ERR_WORKSPACE, MG_ERR_STATE) leave the handle unchanged.
+ *   - "device" pointers are HIP device memory of the GPU that was current at
+ *     mg_setup; the caller owns them and all workspace memory.  The library
+ *     owns only the handle and what hangs off it (plan, HIP graph, a small
+ *     pinned host buffer for the residual norms).
+ *   - Dense arrays at the ABI are n^dim values, x fastest:
+ *     index (z*n + y)*n + x in 3-D, y*n + x in 2-D.
+ *   - stream is a hipStream_t passed as void*; NULL means the null stream.
+ *     Work is enqueued on that stream; see each function for synchronisation.
+ */
+#ifndef MGIR_H
+#define MGIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_ERR_ARG = -1,            /* null pointer, out-of-range option or index */
+    MG_ERR_SHAPE = -2,          /* n is not 2^m - 1, or dim is not 2 or 3 */
+    MG_ERR_PREC = -3,           /* unknown precision code in a level map */
+    MG_ERR_WORKSPACE = -4,      /* no workspace bound, or bound one too small / misaligned */
+    MG_ERR_HIP = -5,            /* a HIP runtime call failed (message in mg_last_error) */
+    MG_ERR_NOT_CONVERGED = -6,  /* max_iter reached; u holds the last iterate, stats filled */
+    MG_ERR_NONFINITE = -7,      /* a residual norm became NaN or Inf */
+    MG_ERR_STATE = -8           /* call not valid in the handle's current state */
+} mg_status_t;
+
+/* Storage format of one level's vectors.  FP16/BF16/FP32 levels accumulate in
+ * FP32 registers, FP64 levels in FP64; every store rounds to nearest even. */
+typedef enum { MG_F64 = 0, MG_F32 = 1, MG_F16 = 2, MG_BF16 = 3 } mg_prec_t;
+
+typedef struct {
+    int nu1;                 /* pre-smoothing sweeps (Algorithm 1 step 1), default 2 */
+    int nu2;                 /* post-smoothing sweeps (Algorithm 1 step 5), default 2 */
+    double omega;            /* damped-Jacobi weight, default 0.8 */
+    int residual_scaling;    /* 1: alpha = ||r||_inf before the cast (Algorithm 2 line 4);
+                                0: alpha = 1 (the FP64 baseline omits scaling, Section 6) */
+    int max_iter;            /* V-cycles at most, default 100 */
+    double rtol;             /* stop when ||r||_2 <= rtol * ||b||_2 (FP64), default 1e-10 */
+    int use_initial_guess;   /* 0: ir_solve starts from u = 0 (default); 1: from the given u */
+    int use_graph;           /* 1: replay one captured HIP graph per refinement step (default) */
+    int autotune;            /* 1: time launch shapes at mg_bind_workspace (synchronises) */
+} mg_options_t;
+
+typedef struct {
+    int iterations;          /* V-cycles applied */
+    double rel_residual;     /* ||b - A u||_2 / ||b||_2 of the returned u, recomputed in FP64 */
+    double seconds;          /* host wall time of the call, to the final synchronisation */
+    double *history;         /* optional caller-owned host array: ||r_k||_2/||b||_2, k = 0.. */
+    int history_cap;         /* its capacity; entries beyond it are dropped */
+} mg_stats_t;
+
+typedef struct mg_ctx *mg_handle;
+
+/* Fill *opt with the defaults listed above. */
+void mg_default_options(mg_options_t *opt);
+
+/* Create a solver for one grid.
+ *   dim        2 or 3.
+ *   n          interior points per dimension, 2^m - 1 with 2 <= m <= 12 in
+ *              2-D and 2 <= m <= 10 in 3-D (n >= 3: the finest level is
+ *              smoothed and restricted at least once).
+ *   nlevels    0 for the full hierarchy n, (n-1)/2, ..., 1 (m levels);
+ *              otherwise it must equal m (a partial hierarchy would need a
+ *              base solver other than the exact one-point solve).
+ *   level_prec m entries, FINEST FIRST: level_prec[0] is the finest grid
+ *              (the paper's level L), level_prec[m-1] the one-point base
+ *              level (the paper's level 0).  NULL means all MG_F64.
+ *   opt        NULL for defaults.
+ * No device memory is allocated: query mg_workspace_size, allocate, then
+ * mg_bind_workspace.  Errors: MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_PREC. */
+mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_t *level_prec,
+                     const mg_options_t *opt);
+
+/* Bytes of device workspace the handle needs (all levels' right-hand side and
+ * correction vectors in their storage formats, the FP64 solution and residual
+ * of the finest level, reduction partials). */
+mg_status_t mg_workspace_size(mg_handle h, size_t *bytes);
+
+/* Bind caller-owned device memory (at least mg_workspace_size bytes, 256-byte
+ * aligned).  Zero-fills it on stream and waits for that; with opt.autotune it
+ * also times launch shapes.  May be called again with another buffer; the
+ * previous one is no longer referenced afterwards. */
+mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *stream);
+
+/* One V-cycle from a zero initial guess for A_L e = b (Algorithm 1, recursive).
+ *   b  device, dense, n^dim values in level_prec[0]'s format (FP16/BF16 as
+ *      IEEE binary16 / bfloat16 bit patterns).
+ *   c  device, dense, n^dim values in the same format; receives the
+ *      correction in grid-scaled units c = e / h^2 (so the physical
+ *      correction is h^2 c; this keeps FP16 values away from underflow).
+ * Asynchronous on stream.  Errors: MG_ERR_ARG, MG_ERR_WORKSPACE, MG_ERR_HIP. */
+mg_status_t mg_vcycle(mg_handle h, const void *b, void *c, void *stream);
+
+/* Solve A u = b by iterative refinement with residuum scaling (Algorithm 2):
+ * r = b - A u;  while ||r||_2 > rtol ||b||_2:  alpha = ||r||_inf (or 1);
+ * c = V-cycle(r / alpha) in the level formats;  u += alpha c;  r -= alpha A c.
+ * Residual, update, norms and the stop test are FP64.  The recursively
+ * updated residual of Algorithm 2 line 7 drives the loop; before returning,
+ * b - A u is recomputed from scratch and iteration continues if it does not
+ * meet the tolerance.
+ *   b  device, dense FP64, n^dim.
+ *   u  device, dense FP64, n^dim; input guess if opt.use_initial_guess,
+ *      output solution (also on MG_ERR_NOT_CONVERGED: the last iterate).
+ *   stats may be NULL.
+ * b == 0 returns MG_OK with u = 0 and 0 iterations.  Synchronises stream once
+ * per iteration (the 32-byte norm readback).  Errors: MG_ERR_ARG,
+ * MG_ERR_WORKSPACE, MG_ERR_HIP, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE. */
+mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats, void *stream);
+
+/* Release the handle (never frees caller memory).  NULL is accepted. */
+mg_status_t mg_destroy(mg_handle h);
+
+const char *mg_status_string(mg_status_t s);
+const char *mg_last_error(void);
+
+/* ---- Stage-level access, for per-kernel checks and custom cycles ----------
+ * Level index `level` counts from the finest (0) to the base (levels-1), as in
+ * level_prec.  Buffers: */
+typedef enum {
+    MG_BUF_RHS = 0,   /* b_l: right-hand side of level l's correction equation */
+    MG_BUF_COR = 1,   /* c_l: level l's current correction, grid-scaled (e_l / h_l^2) */
+    MG_BUF_RES = 2,   /* finest level only: FP64 residual r of the refinement loop */
+    MG_BUF_SOL = 3    /* finest level only: FP64 iterate u of the refinement loop */
+} mg_buffer_t;
+
+typedef enum {
+    MG_STAGE_SMOOTH_FIRST = 0,   /* c_l = nu1 damped-Jacobi sweeps on L c = b_l from c = 0 */
+    MG_STAGE_SWEEP = 1,          /* c_l = one damped-Jacobi sweep of c_l */
+    MG_STAGE_RESTRICT = 2,       /* b_{l+1} = round(FW(b_l - L c_l)), full weighting */
+    MG_STAGE_PROLONG_SWEEP = 3,  /* c_l = round(c_l + 4 P c_{l+1}), then one sweep if nu2 >= 1 */
+    MG_STAGE_COARSE = 4          /* base level: c = b / (2 dim), the exact one-point solve */
+} mg_stage_t;
+
+/* Copy a dense device array (n_l^dim values in format src_prec) into a level
+ * buffer, rounding to nearest even into the level's format.  Async. */
+mg_status_t mg_level_write(mg_handle h, int level, mg_buffer_t buf, const void *src,
+                           mg_prec_t src_prec, void *stream);
+
+/* Copy a level buffer out to a dense device array in format dst_prec
+ * (rounding to nearest even if narrower).  Async. */
+mg_status_t mg_level_read(mg_handle h, int level, mg_buffer_t buf, void *dst, mg_prec_t dst_prec,
+                          void *stream);
+
+/* Run one stage of the cycle on the bound workspace.  Async. */
+mg_status_t mg_stage(mg_handle h, mg_stage_t stage, int level, void *stream);
+
+/* Levels of the handle, and n of one level. */
+mg_status_t mg_levels(mg_handle h, int *nlevels);
+mg_status_t mg_level_n(mg_handle h, int level, int *n);
+
+/* ---- Measurement --------------------------------------------------------
+ * Run one refinement step eagerly with a HIP event pair around every kernel
+ * launch, on stream, and return per-kernel durations.  The step uses the
+ * workspace state left by the last ir_solve (it updates u and r like a real
+ * step).  names/ms/bytes are caller arrays of capacity cap; *count receives the
+ * number of kernels launched.  bytes[i] is the algorithmic HBM traffic of
+ * launch i (each array read or written once).  Synchronises. */
+mg_status_t mg_profile_step(mg_handle h, void *stream, int cap, int *count, const char **names,
+                            double *ms, double *bytes, int *levels_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGIR_H */

@@ -1,0 +1,182 @@
+// Device-side building blocks of the gfx950 multigrid kernels: storage
+// formats and their rounding, vector row loads/stores, the padded level
+// layout, and wave64 reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// Storage formats.  FP16 uses the compiler's _Float16; BF16 is stored as its
+// 16-bit pattern and converted by hand (exact widening, RNE narrowing).
+struct bf16 {
+    uint16_t u;
+};
+typedef _Float16 f16;
+
+template <class T> struct acc_of { typedef float type; };
+template <> struct acc_of<double> { typedef double type; };
+template <class T> using acc_t = typename acc_of<T>::type;
+
+__device__ __forceinline__ float widen(f16 v) { return (float)v; }
+__device__ __forceinline__ float widen(bf16 v) { return __uint_as_float((uint32_t)v.u << 16); }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ double widen(double v) { return v; }
+
+// float -> bf16, round to nearest even (integer bias method); NaN stays NaN.
+__device__ __forceinline__ bf16 f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    bf16 r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        r.u = (uint16_t)((u >> 16) | 0x40u);
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        r.u = (uint16_t)(u >> 16);
+    }
+    return r;
+}
+
+// double -> float rounded to odd: a double rounding through this float and
+// then to a format with at most 22 significand bits equals a single correct
+// rounding of the double (the round-to-odd method).
+__device__ __forceinline__ float f64_to_f32_odd(double d) {
+    float f = (float)d;
+    double back = (double)f;
+    if (back != d && d == d) {
+        uint32_t u = __float_as_uint(f);
+        if (fabs(back) > fabs(d)) u -= 1u;   // rounded away from zero: step back
+        u |= 1u;
+        f = __uint_as_float(u);
+    }
+    return f;
+}
+
+// Round an accumulator value into storage format T (nearest even).
+template <class T> struct Store;
+template <> struct Store<double> {
+    __device__ static double from_acc(double v) { return v; }
+    __device__ static double from_f64(double v) { return v; }
+};
+template <> struct Store<float> {
+    __device__ static float from_acc(float v) { return v; }
+    __device__ static float from_f64(double v) { return (float)v; }
+};
+template <> struct Store<f16> {
+    __device__ static f16 from_acc(float v) { return (f16)v; }
+    __device__ static f16 from_f64(double v) { return (f16)f64_to_f32_odd(v); }
+};
+template <> struct Store<bf16> {
+    __device__ static bf16 from_acc(float v) { return f32_to_bf16(v); }
+    __device__ static bf16 from_f64(double v) { return f32_to_bf16(f64_to_f32_odd(v)); }
+};
+
+// Round a float or double into storage format T (a single correct rounding).
+template <class T> __device__ __forceinline__ T store_as(double v) { return Store<T>::from_f64(v); }
+template <class T> __device__ __forceinline__ T store_as(float v) { return Store<T>::from_acc((acc_t<T>)v); }
+
+// Round a value of any accumulator type into T and widen it back: the value a
+// store followed by a load would produce.
+template <class T> __device__ __forceinline__ acc_t<T> round_to(float v) {
+    return widen(Store<T>::from_acc((acc_t<T>)v));
+}
+template <class T> __device__ __forceinline__ acc_t<T> round_to(double v) {
+    return widen(Store<T>::from_f64(v));
+}
+
+// ---------------------------------------------------------------------------
+// Row-vector loads and stores of V consecutive elements starting at an
+// address aligned to V * sizeof(T) (guaranteed by the padded layout below).
+template <int BYTES> struct RawChunk;
+template <> struct RawChunk<2> { typedef uint16_t type; };
+template <> struct RawChunk<4> { typedef uint32_t type; };
+template <> struct RawChunk<8> { typedef uint2 type; };
+template <> struct RawChunk<16> { typedef uint4 type; };
+
+template <class T, int V, class A>
+__device__ __forceinline__ void load_row(const T *__restrict__ p, A (&o)[V]) {
+    constexpr int B = V * (int)sizeof(T);
+    constexpr int CB = B >= 16 ? 16 : B;
+    static_assert(B % CB == 0, "row bytes");
+    typedef typename RawChunk<CB>::type C;
+    union {
+        C c[B / CB];
+        T t[V];
+    } u;
+    const C *q = reinterpret_cast<const C *>(p);
+#pragma unroll
+    for (int i = 0; i < B / CB; ++i) u.c[i] = q[i];
+#pragma unroll
+    for (int i = 0; i < V; ++i) o[i] = (A)widen(u.t[i]);
+}
+
+template <class T, int V>
+__device__ __forceinline__ void store_row(T *__restrict__ p, const T (&v)[V]) {
+    constexpr int B = V * (int)sizeof(T);
+    constexpr int CB = B >= 16 ? 16 : B;
+    typedef typename RawChunk<CB>::type C;
+    union {
+        C c[B / CB];
+        T t[V];
+    } u;
+#pragma unroll
+    for (int i = 0; i < V; ++i) u.t[i] = v[i];
+    C *q = reinterpret_cast<C *>(p);
+#pragma unroll
+    for (int i = 0; i < B / CB; ++i) q[i] = u.c[i];
+}
+
+// ---------------------------------------------------------------------------
+// Padded level layout.  A level with n = 2^m - 1 interior points per
+// dimension uses pitch P = 2^m.  Interior coordinates run 1..P-1; coordinate 0
+// is a zero ghost.  Element (x, y, z) sits at (z*P + y)*P + x in 3-D and
+// (z*P + x) in 2-D (the 2-D grid's rows are indexed by z).  Because the pitch
+// is P, the ghost x = 0 of the next row doubles as the ghost x = P of this
+// row, and row 0 of the next plane as row P of this plane; plane P is an
+// explicit ghost plane, and one more plane of slack follows it.
+template <int D> struct Grid {
+    int P;
+    __device__ __forceinline__ size_t at(int x, int y, int z) const {
+        return D == 3 ? ((size_t)z * P + (size_t)y) * P + (size_t)x : (size_t)z * P + (size_t)x;
+    }
+    // true for rows that lie on the boundary or outside the interior
+    __device__ __forceinline__ bool ghost_row(int y, int z) const {
+        return z <= 0 || z >= P || (D == 3 && (y <= 0 || y >= P));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// wave64 and block reductions with a fixed combination order.
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__device__ __forceinline__ void wave_reduce(double &s, double &m) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        m = nanmax(m, __shfl_xor(m, off, 64));
+    }
+}
+
+// Reduce (sum, max) over the block; thread 0 gets the result.  Every thread
+// of the block must call it.  Needs 2 * (blockDim.x / 64) doubles of LDS.
+__device__ __forceinline__ void block_reduce(double &s, double &m, double *lds) {
+    wave_reduce(s, m);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        lds[2 * w] = s;
+        lds[2 * w + 1] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ss = 0.0, mm = 0.0;
+        for (int i = 0; i < nw; ++i) {
+            ss += lds[2 * i];
+            mm = nanmax(mm, lds[2 * i + 1]);
+        }
+        s = ss;
+        m = mm;
+    }
+}
+
+}  // namespace mg

@@ -1,0 +1,896 @@
+// gfx950 kernels of the mixed-precision multigrid V-cycle and the FP64
+// iterative-refinement loop (Oo & Vogel, arXiv 2007.07539: Algorithm 1 for the
+// cycle, Algorithm 2 for the refinement, Section 6 for the per-level formats).
+//
+// All level operators are matrix-free.  Corrections are kept in grid-scaled
+// units c = e / h^2, so that on every level the operator is the integer
+// stencil L = [2D on the centre, -1 on each face neighbour]; damped Jacobi is
+// c' = c + k (b - L c) with k = omega / (2D); prolongation gains the factor
+// (h_coarse / h_fine)^2 = 4.  Powers of two only, so the change of units is
+// exact in every binary format.
+//
+// Work decomposition (all stencil kernels): a thread owns V consecutive x
+// values of one row and marches along z, keeping the z-1, z, z+1 values of its
+// own row in registers; the y and x neighbours come from the cache hierarchy
+// (the same rows are the centre rows of neighbouring threads).  The
+// residual+restriction kernel stages fine residual rows in LDS.
+#include "mg_device.h"
+#include "mg_launch.h"
+
+#include <type_traits>
+
+namespace mg {
+
+template <class A> __device__ __forceinline__ A fmaT(A a, A b, A c);
+template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ===========================================================================
+// Field policies: the value of a grid function at a position, in accumulator
+// type `acc`, already rounded to the format it would be stored in.  Positions
+// on the boundary evaluate to zero.
+// ===========================================================================
+
+// A stored array.
+template <class T, class A> struct FArr {
+    typedef A acc;
+    const T *__restrict__ p;
+    template <int D, int V> __device__ __forceinline__ void row(const Grid<D> &g, int x0, int y, int z, A (&o)[V]) const {
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) o[i] = A(0);
+            return;
+        }
+        load_row<T, V>(p + g.at(x0, y, z), o);  // x = 0 is a stored zero ghost
+    }
+    template <int D> __device__ __forceinline__ A one(const Grid<D> &g, int x, int y, int z) const {
+        if (x <= 0 || x >= g.P || g.ghost_row(y, z)) return A(0);
+        return (A)widen(p[g.at(x, y, z)]);
+    }
+};
+
+// Right-hand side of the finest level inside the refinement loop:
+// round_T(r * (1/alpha)) from the FP64 residual (Algorithm 2 line 4).
+template <class T> struct FScaled {
+    typedef acc_t<T> acc;
+    const double *__restrict__ r;
+    const double *__restrict__ scal;  // scal[1] = 1/alpha
+    template <int D, int V> __device__ __forceinline__ void row(const Grid<D> &g, int x0, int y, int z, acc (&o)[V]) const {
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) o[i] = acc(0);
+            return;
+        }
+        double rv[V];
+        load_row<double, V>(r + g.at(x0, y, z), rv);
+        const double inv = scal[1];
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = widen(Store<T>::from_f64(rv[i] * inv));
+    }
+    template <int D> __device__ __forceinline__ acc one(const Grid<D> &g, int x, int y, int z) const {
+        if (x <= 0 || x >= g.P || g.ghost_row(y, z)) return acc(0);
+        return widen(Store<T>::from_f64(r[g.at(x, y, z)] * scal[1]));
+    }
+};
+
+// First Jacobi iterate from c = 0: round_T(k * b).
+template <class T, class R> struct FJac0 {
+    typedef acc_t<T> acc;
+    R rhs;
+    acc k;
+    template <int D, int V> __device__ __forceinline__ void row(const Grid<D> &g, int x0, int y, int z, acc (&o)[V]) const {
+        rhs.template row<D, V>(g, x0, y, z, o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = round_to<T>(k * o[i]);
+    }
+    template <int D> __device__ __forceinline__ acc one(const Grid<D> &g, int x, int y, int z) const {
+        return round_to<T>(k * rhs.one(g, x, y, z));
+    }
+};
+
+// Corrected fine correction round_TF(c + 4 P e_c): linear interpolation of
+// the coarse correction (fine coordinate q sits on coarse q/2 when even,
+// between (q-1)/2 and (q+1)/2 when odd).  Interpolation runs in FP64 when
+// either level is FP64, else in FP32.
+template <class TF, class TC> struct FProl {
+    typedef acc_t<TF> acc;
+    typedef typename std::conditional<std::is_same<TC, double>::value || std::is_same<TF, double>::value,
+                                      double, float>::type PA;
+    const TF *__restrict__ c;
+    const TC *__restrict__ ec;
+    int Pc;
+
+    __device__ __forceinline__ static int split(int q, int (&Q)[2]) {
+        if ((q & 1) == 0) {
+            Q[0] = q >> 1;
+            return 1;
+        }
+        Q[0] = (q - 1) >> 1;
+        Q[1] = (q + 1) >> 1;
+        return 2;
+    }
+
+    // coarse-row sum S(X) = sum over contributing (Z, Y) of w_Z w_Y e_c(X, Y, Z)
+    // for X = X0 .. X0 + V/2 (the last one may be the ghost Pc).
+    template <int D, int V> __device__ __forceinline__ void rowsum(int x0, int y, int z, PA (&s)[V / 2 + 1]) const {
+        constexpr int H = V / 2;
+        Grid<D> gc{Pc};
+#pragma unroll
+        for (int j = 0; j <= H; ++j) s[j] = PA(0);
+        int Zs[2], Ys[2] = {0, 0};
+        const int nz = split(z, Zs);
+        const int ny = D == 3 ? split(y, Ys) : 1;
+        const PA wz = nz == 1 ? PA(1) : PA(0.5), wy = ny == 1 ? PA(1) : PA(0.5);
+        const int X0 = x0 >> 1;
+        for (int a = 0; a < nz; ++a) {
+            const int Z = Zs[a];
+            if (Z < 1 || Z >= Pc) continue;
+            for (int bb = 0; bb < ny; ++bb) {
+                const int Y = D == 3 ? Ys[bb] : 0;
+                if (D == 3 && (Y < 1 || Y >= Pc)) continue;
+                const PA w = wz * wy;
+                const TC *base = ec + gc.at(X0, Y, Z);
+                PA v[H];
+                load_row<TC, H>(base, v);
+#pragma unroll
+                for (int j = 0; j < H; ++j) s[j] += w * v[j];
+                const PA last = (X0 + H < Pc) ? (PA)widen(base[H]) : PA(0);
+                s[H] += w * last;
+            }
+        }
+    }
+
+    template <int D, int V> __device__ __forceinline__ void row(const Grid<D> &g, int x0, int y, int z, acc (&o)[V]) const {
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) o[i] = acc(0);
+            return;
+        }
+        PA s[V / 2 + 1];
+        rowsum<D, V>(x0, y, z, s);
+        acc cv[V];
+        load_row<TF, V>(c + g.at(x0, y, z), cv);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const PA p = (i & 1) ? PA(0.5) * (s[i >> 1] + s[(i >> 1) + 1]) : s[i >> 1];
+            o[i] = round_to<TF>((PA)cv[i] + PA(4) * p);
+        }
+        if (x0 == 0) o[0] = acc(0);
+    }
+
+    // coarse column value sum over (Z, Y) at one coarse X
+    template <int D> __device__ __forceinline__ PA colsum(int X, int y, int z) const {
+        Grid<D> gc{Pc};
+        PA s = PA(0);
+        if (X < 1 || X >= Pc) return s;
+        int Zs[2], Ys[2] = {0, 0};
+        const int nz = split(z, Zs);
+        const int ny = D == 3 ? split(y, Ys) : 1;
+        const PA wz = nz == 1 ? PA(1) : PA(0.5), wy = ny == 1 ? PA(1) : PA(0.5);
+        for (int a = 0; a < nz; ++a) {
+            const int Z = Zs[a];
+            if (Z < 1 || Z >= Pc) continue;
+            for (int bb = 0; bb < ny; ++bb) {
+                const int Y = D == 3 ? Ys[bb] : 0;
+                if (D == 3 && (Y < 1 || Y >= Pc)) continue;
+                s += (wz * wy) * (PA)widen(ec[gc.at(X, Y, Z)]);
+            }
+        }
+        return s;
+    }
+
+    template <int D> __device__ __forceinline__ acc one(const Grid<D> &g, int x, int y, int z) const {
+        if (x <= 0 || x >= g.P || g.ghost_row(y, z)) return acc(0);
+        PA p;
+        if ((x & 1) == 0) {
+            p = colsum<D>(x >> 1, y, z);
+        } else {
+            p = PA(0.5) * (colsum<D>((x - 1) >> 1, y, z) + colsum<D>((x + 1) >> 1, y, z));
+        }
+        return round_to<TF>((PA)widen(c[g.at(x, y, z)]) + PA(4) * p);
+    }
+};
+
+// ===========================================================================
+// Emit policies: what a stencil kernel does with the centre values c and the
+// neighbour sums nb of its row.
+// ===========================================================================
+struct NoState {};
+
+// Damped-Jacobi sweep out = round_T(c + k (b - (2D c - nb))); optionally also
+// stores the right-hand side it used (the scaled-and-cast residual).
+template <class T, class R, bool WRITE_B> struct ESweep {
+    typedef acc_t<T> A;
+    typedef NoState State;
+    R rhs;
+    T *__restrict__ out;
+    T *__restrict__ bout;
+    A k;
+    __device__ __forceinline__ void init(State &) const {}
+    __device__ __forceinline__ void finish(State &, double *) const {}
+    template <int D, int V>
+    __device__ __forceinline__ void emit(const Grid<D> &g, State &, int x0, int y, int z, const A (&c)[V],
+                                         const A (&nb)[V]) const {
+        A b[V];
+        rhs.template row<D, V>(g, x0, y, z, b);
+        T o[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const A lc = fmaT<A>(A(2 * D), c[i], -nb[i]);
+            o[i] = Store<T>::from_acc(fmaT<A>(k, b[i] - lc, c[i]));
+        }
+        if (x0 == 0) o[0] = Store<T>::from_acc(A(0));
+        const size_t at = g.at(x0, y, z);
+        store_row<T, V>(out + at, o);
+        if (WRITE_B) {
+            T bo[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) bo[i] = Store<T>::from_acc(b[i]);
+            if (x0 == 0) bo[0] = Store<T>::from_acc(A(0));
+            store_row<T, V>(bout + at, bo);
+        }
+    }
+};
+
+// Store the field itself (the first Jacobi iterate, or a correction without
+// post-smoothing); optionally the right-hand side too.
+template <class T, class R, bool WRITE_B> struct ECopy {
+    typedef acc_t<T> A;
+    typedef NoState State;
+    R rhs;
+    T *__restrict__ out;
+    T *__restrict__ bout;
+    __device__ __forceinline__ void init(State &) const {}
+    __device__ __forceinline__ void finish(State &, double *) const {}
+    template <int D, int V>
+    __device__ __forceinline__ void emit(const Grid<D> &g, State &, int x0, int y, int z, const A (&c)[V],
+                                         const A (&)[V]) const {
+        T o[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = Store<T>::from_acc(c[i]);
+        if (x0 == 0) o[0] = Store<T>::from_acc(A(0));
+        const size_t at = g.at(x0, y, z);
+        store_row<T, V>(out + at, o);
+        if (WRITE_B) {
+            A b[V];
+            rhs.template row<D, V>(g, x0, y, z, b);
+            T bo[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) bo[i] = Store<T>::from_acc(b[i]);
+            if (x0 == 0) bo[0] = Store<T>::from_acc(A(0));
+            store_row<T, V>(bout + at, bo);
+        }
+    }
+};
+
+// Refinement update of Algorithm 2 lines 6-7 in FP64 (grid-scaled c):
+// u += alpha h^2 c,  r -= alpha (2D c - nb), plus per-block norm partials.
+struct EOuter {
+    typedef double A;
+    struct State {
+        double ss, mx;
+    };
+    double *__restrict__ R;
+    double *__restrict__ U;
+    const double *__restrict__ scal;
+    double h2;
+    double *__restrict__ part;
+    __device__ __forceinline__ void init(State &s) const { s.ss = 0.0, s.mx = 0.0; }
+    template <int D, int V>
+    __device__ __forceinline__ void emit(const Grid<D> &g, State &st, int x0, int y, int z, const A (&c)[V],
+                                         const A (&nb)[V]) const {
+        const double a = scal[0];
+        const double ah2 = a * h2;
+        const size_t at = g.at(x0, y, z);
+        double r[V], u[V];
+        load_row<double, V>(R + at, r);
+        load_row<double, V>(U + at, u);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const double lc = fmaT<double>(double(2 * D), c[i], -nb[i]);
+            r[i] = fmaT<double>(-a, lc, r[i]);
+            u[i] = fmaT<double>(ah2, c[i], u[i]);
+        }
+        if (x0 == 0) r[0] = 0.0, u[0] = 0.0;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            st.ss += r[i] * r[i];
+            st.mx = nanmax(st.mx, fabs(r[i]));
+        }
+        store_row<double, V>(R + at, r);
+        store_row<double, V>(U + at, u);
+    }
+    __device__ __forceinline__ void finish(State &s, double *lds) const {
+        block_reduce(s.ss, s.mx, lds);
+        if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = s.ss;
+            part[2 * blockIdx.x + 1] = s.mx;
+        }
+    }
+};
+
+// ===========================================================================
+// The z-marching stencil kernel.  Thread t of the grid owns x chunk
+// (t mod P/V) of line (t div P/V); a line is a row y (3-D) of one z chunk, or
+// one z chunk (2-D).  The neighbour sum is formed in the fixed order
+// x-, x+, y-, y+, z-, z+ (2-D: x-, x+, then the two row neighbours).
+// ===========================================================================
+template <int D, int V, class F, class E>
+__global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nchunks, int xcd) {
+    typedef typename F::acc A;
+    __shared__ double red[8];
+    const Grid<D> g{P};
+    const int TXR = P / V;
+    const int NY = D == 3 ? P : 1;
+    long blk = blockIdx.x;
+    if (xcd) {
+        // blocks are dealt round-robin to the 8 XCDs: give each XCD a
+        // contiguous range of tiles so neighbouring rows share an L2
+        const long nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    const long t = blk * blockDim.x + threadIdx.x;
+    const int xc = (int)(t % TXR);
+    const long line = t / TXR;
+    const int y = (int)(line % NY);
+    const int chunk = (int)(line / NY);
+    const bool active = chunk < nchunks && (D == 2 || y >= 1);
+    typename E::State st;
+    e.init(st);
+    if (active) {
+        const int z0 = 1 + chunk * zc;
+        const int z1 = min(z0 + zc, P);
+        const int x0 = xc * V;
+        A cm[V], cc[V], cp[V];
+        f.template row<D, V>(g, x0, y, z0 - 1, cm);
+        f.template row<D, V>(g, x0, y, z0, cc);
+        for (int z = z0; z < z1; ++z) {
+            f.template row<D, V>(g, x0, y, z + 1, cp);
+            A nb[V];
+            const A xl = f.template one<D>(g, x0 - 1, y, z);
+            const A xr = f.template one<D>(g, x0 + V, y, z);
+#pragma unroll
+            for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cc[i - 1] : xl) + (i < V - 1 ? cc[i + 1] : xr);
+            if constexpr (D == 3) {
+                A ym[V], yp[V];
+                f.template row<D, V>(g, x0, y - 1, z, ym);
+                f.template row<D, V>(g, x0, y + 1, z, yp);
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    nb[i] += ym[i];
+                    nb[i] += yp[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                nb[i] += cm[i];
+                nb[i] += cp[i];
+            }
+            e.template emit<D, V>(g, st, x0, y, z, cc, nb);
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                cm[i] = cc[i];
+                cc[i] = cp[i];
+            }
+        }
+    }
+    e.finish(st, red);
+}
+
+// ===========================================================================
+// Residual + full-weighting restriction + cast (Algorithm 1 step 2).  A block
+// owns `tyc` coarse rows (3-D) and `zcc` coarse planes.  Its threads first act
+// as fine-row threads: 2 tyc + 1 fine rows (2-D: one), each thread V fine x
+// values, marching the fine planes 2Z0-1 .. 2Z1-1 and writing the fine
+// residual b - L c of every plane into an LDS row buffer (double-buffered).
+// After a barrier the first tyc * P/V threads act as coarse threads with V/2
+// coarse x values each: they apply the x and y weights (1/4, 1/2, 1/4) from
+// LDS and accumulate the z weights in registers across the march.
+// ===========================================================================
+template <int D, int V, class TF, class TC>
+__global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, const TF *__restrict__ c,
+                                                   TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles) {
+    typedef acc_t<TF> A;
+    constexpr int VC = V / 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *rs = reinterpret_cast<A *>(smem_raw);
+    const int Pc = P >> 1;
+    const int TXR = P / V;
+    const int G = D == 3 ? 2 * tyc + 1 : 1;
+    const Grid<D> g{P};
+    const Grid<D> gc{Pc};
+    const int ytile = blockIdx.x % ytiles, zch = blockIdx.x / ytiles;
+    const int Y0 = D == 3 ? 1 + ytile * tyc : 0;
+    const int Z0 = 1 + zch * zcc;
+    const int Z1 = min(Z0 + zcc, Pc);
+    const int tid = threadIdx.x;
+    const int xc = tid % TXR, gi = tid / TXR;
+    const bool fine_active = gi < G;
+    const int y = D == 3 ? 2 * Y0 - 1 + gi : 0;
+    const bool rowok = fine_active && !(D == 3 && y >= P);
+    const int x0 = xc * V;
+    const bool coarse_active = D == 3 ? (gi < tyc && Y0 + gi < Pc) : (gi == 0);
+    const int Yc = D == 3 ? Y0 + gi : 0;
+    const int X0 = xc * VC;
+    const FArr<TF, A> cf{c};
+    const FArr<TF, A> bf{b};
+    A acc[VC];
+#pragma unroll
+    for (int j = 0; j < VC; ++j) acc[j] = A(0);
+    const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
+    A cm[V], cc[V], cp[V];
+    if (rowok) {
+        cf.template row<D, V>(g, x0, y, zf0 - 1, cm);
+        cf.template row<D, V>(g, x0, y, zf0, cc);
+    }
+    for (int zf = zf0; zf <= zf1; ++zf) {
+        A *buf = rs + (size_t)((zf - zf0) & 1) * G * P;
+        if (fine_active) {
+            A r[V];
+            if (rowok) {
+                cf.template row<D, V>(g, x0, y, zf + 1, cp);
+                A nb[V];
+                const A xl = cf.template one<D>(g, x0 - 1, y, zf);
+                const A xr = cf.template one<D>(g, x0 + V, y, zf);
+#pragma unroll
+                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cc[i - 1] : xl) + (i < V - 1 ? cc[i + 1] : xr);
+                if constexpr (D == 3) {
+                    A ym[V], yp[V];
+                    cf.template row<D, V>(g, x0, y - 1, zf, ym);
+                    cf.template row<D, V>(g, x0, y + 1, zf, yp);
+#pragma unroll
+                    for (int i = 0; i < V; ++i) {
+                        nb[i] += ym[i];
+                        nb[i] += yp[i];
+                    }
+                }
+                A bb[V];
+                bf.template row<D, V>(g, x0, y, zf, bb);
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    nb[i] += cm[i];
+                    nb[i] += cp[i];
+                    r[i] = bb[i] - fmaT<A>(A(2 * D), cc[i], -nb[i]);
+                }
+                if (x0 == 0) r[0] = A(0);
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    cm[i] = cc[i];
+                    cc[i] = cp[i];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < V; ++i) r[i] = A(0);
+            }
+            A *dst = buf + (size_t)gi * P + x0;
+#pragma unroll
+            for (int i = 0; i < V; ++i) dst[i] = r[i];
+        }
+        __syncthreads();
+        if (coarse_active) {
+            const bool last_of_z = zf > zf0 && ((zf - zf0) & 1) == 0;  // zf = 2Z + 1
+            TC out[VC];
+#pragma unroll
+            for (int j = 0; j < VC; ++j) {
+                const int X = X0 + j;
+                A q = A(0);
+                if (X >= 1) {
+                    if constexpr (D == 3) {
+                        A rsum[3];
+#pragma unroll
+                        for (int oy = 0; oy < 3; ++oy) {
+                            const A *row = buf + (size_t)(2 * gi + oy) * P;
+                            rsum[oy] = A(0.25) * (row[2 * X - 1] + row[2 * X + 1]) + A(0.5) * row[2 * X];
+                        }
+                        q = A(0.25) * (rsum[0] + rsum[2]) + A(0.5) * rsum[1];
+                    } else {
+                        const A *row = buf;
+                        q = A(0.25) * (row[2 * X - 1] + row[2 * X + 1]) + A(0.5) * row[2 * X];
+                    }
+                }
+                if (zf == zf0) {
+                    acc[j] = A(0.25) * q;
+                } else if (!last_of_z) {
+                    acc[j] += A(0.5) * q;
+                } else {
+                    const A v = acc[j] + A(0.25) * q;
+                    out[j] = store_as<TC>(v);
+                    acc[j] = A(0.25) * q;
+                }
+            }
+            if (last_of_z) {
+                if (X0 == 0) out[0] = store_as<TC>(A(0));
+                const int Z = (zf - 1) >> 1;
+                store_row<TC, VC>(bc + gc.at(X0, Yc, Z), out);
+            }
+        }
+    }
+}
+
+// Base level: the single interior point of an n = 1 grid (P = 2) at (1,1[,1]).
+template <int D, class T> __global__ void k_coarse(const T *__restrict__ b, T *__restrict__ c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int i = D == 3 ? 7 : 3;
+        typedef acc_t<T> A;
+        c[i] = Store<T>::from_acc(widen(b[i]) / A(2 * D));
+    }
+}
+
+// r = b - A U with the FP64 operator (2D u - nb) / h^2, thread per dense point.
+template <int D>
+__global__ __launch_bounds__(256) void k_resid_flat(const double *__restrict__ b, const double *__restrict__ U,
+                                                    double *__restrict__ R, double *__restrict__ uout, int n, int P,
+                                                    double inv_h2, long N, double *__restrict__ part) {
+    __shared__ double red[8];
+    const Grid<D> g{P};
+    const size_t plane = D == 3 ? (size_t)P * P : (size_t)P;
+    double ss = 0.0, mx = 0.0;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
+        const int x = (int)(idx % n) + 1;
+        const long rest = idx / n;
+        int y = 0, z;
+        if (D == 3) {
+            y = (int)(rest % n) + 1;
+            z = (int)(rest / n) + 1;
+        } else {
+            z = (int)rest + 1;
+        }
+        const size_t p = g.at(x, y, z);
+        double r = b[idx];
+        if (U) {
+            double nb = U[p - 1] + U[p + 1];
+            if (D == 3) {
+                nb += U[p - P];
+                nb += U[p + P];
+            }
+            nb += U[p - plane];
+            nb += U[p + plane];
+            r = r - (double(2 * D) * U[p] - nb) * inv_h2;
+            if (uout) uout[idx] = U[p];
+        }
+        if (R) R[p] = r;
+        ss += r * r;
+        mx = nanmax(mx, fabs(r));
+    }
+    block_reduce(ss, mx, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss;
+        part[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ part, int nparts, double *__restrict__ scal,
+                                                  int scaling) {
+    __shared__ double red[8];
+    double s = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        s += part[2 * i];
+        m = nanmax(m, part[2 * i + 1]);
+    }
+    block_reduce(s, m, red);
+    if (threadIdx.x == 0) {
+        double a = scaling ? m : 1.0;
+        if (!(a > 0.0) || a > 1.7e308) a = 1.0;
+        scal[0] = a;
+        scal[1] = 1.0 / a;
+        scal[2] = sqrt(s);
+        scal[3] = m;
+    }
+}
+
+template <int D, class TS, class TD>
+__global__ __launch_bounds__(256) void k_pack(const TS *__restrict__ src, TD *__restrict__ dst, int n, int P, long N) {
+    const Grid<D> g{P};
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
+        const int x = (int)(idx % n) + 1;
+        const long rest = idx / n;
+        const int y = D == 3 ? (int)(rest % n) + 1 : 0;
+        const int z = D == 3 ? (int)(rest / n) + 1 : (int)rest + 1;
+        dst[g.at(x, y, z)] = Store<TD>::from_f64((double)widen(src[idx]));
+    }
+}
+
+template <int D, class TS, class TD>
+__global__ __launch_bounds__(256) void k_unpack(const TS *__restrict__ src, TD *__restrict__ dst, int n, int P, long N) {
+    const Grid<D> g{P};
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
+        const int x = (int)(idx % n) + 1;
+        const long rest = idx / n;
+        const int y = D == 3 ? (int)(rest % n) + 1 : 0;
+        const int z = D == 3 ? (int)(rest / n) + 1 : (int)rest + 1;
+        dst[idx] = Store<TD>::from_f64((double)widen(src[g.at(x, y, z)]));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(uint4 *__restrict__ p, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ===========================================================================
+// Host launchers.
+// ===========================================================================
+static int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+static int stencil_chunks(int P, int zc) { return ceil_div(P - 1, zc); }
+
+int stencil_blocks(int D, int P, const Shape &s) {
+    const long lines = (long)(D == 3 ? P : 1) * stencil_chunks(P, s.zc);
+    return ceil_div((long)(P / s.V) * lines, s.bs);
+}
+
+int restrict_blocks(int D, int P, const RShape &s) {
+    const int Pc = P / 2;
+    const int ytiles = D == 3 ? ceil_div(Pc - 1, s.tyc) : 1;
+    return ytiles * ceil_div(Pc - 1, s.zcc);
+}
+
+size_t restrict_lds_bytes(int D, int P, int pf, const RShape &s) {
+    const int G = D == 3 ? 2 * s.tyc + 1 : 1;
+    return 2 * (size_t)G * P * (pf == P_F64 ? 8 : 4);
+}
+
+int flat_blocks(long N) {
+    long b = (N + 255) / 256;
+    return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+template <int D, int V, class F, class E>
+static hipError_t run_stencil(const F &f, const E &e, int P, const Shape &s, hipStream_t st) {
+    const int nch = stencil_chunks(P, s.zc);
+    const int blocks = stencil_blocks(D, P, s);
+    hipLaunchKernelGGL((k_stencil<D, V, F, E>), dim3(blocks), dim3(s.bs), 0, st, f, e, P, s.zc, nch, s.xcd);
+    return hipGetLastError();
+}
+
+// Dispatch a (D, V) pair to a functor templated on them.
+#define MG_DISPATCH_DV(D, V, CALL)                                   \
+    do {                                                             \
+        if ((D) == 3) {                                              \
+            if ((V) == 8) { constexpr int DD = 3, VV = 8; CALL; }    \
+            else { constexpr int DD = 3, VV = 4; CALL; }             \
+        } else {                                                     \
+            if ((V) == 8) { constexpr int DD = 2, VV = 8; CALL; }    \
+            else { constexpr int DD = 2, VV = 4; CALL; }             \
+        }                                                            \
+    } while (0)
+
+template <class T>
+static hipError_t smooth_first_t(int D, int P, const void *b, const double *r, const double *scal, void *b_out,
+                                 void *c, double omega, bool two, const Shape &s, hipStream_t st) {
+    typedef acc_t<T> A;
+    const A k = (A)(omega / (2.0 * D));
+    T *cout = static_cast<T *>(c);
+    hipError_t err = hipSuccess;
+    if (r) {
+        typedef FScaled<T> R;
+        typedef FJac0<T, R> F;
+        const R rh{r, scal};
+        const F f{rh, k};
+        T *bo = static_cast<T *>(b_out);
+        if (two) {
+            const ESweep<T, R, true> e{rh, cout, bo, k};
+            MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+        } else {
+            const ECopy<T, R, true> e{rh, cout, bo};
+            MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+        }
+    } else {
+        typedef FArr<T, A> R;
+        typedef FJac0<T, R> F;
+        const R rh{static_cast<const T *>(b)};
+        const F f{rh, k};
+        if (two) {
+            const ESweep<T, R, false> e{rh, cout, nullptr, k};
+            MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+        } else {
+            const ECopy<T, R, false> e{rh, cout, nullptr};
+            MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+        }
+    }
+    return err;
+}
+
+#define MG_DISPATCH_T(prec, CALL)                 \
+    switch (prec) {                               \
+    case P_F64: { typedef double TT; CALL; break; } \
+    case P_F32: { typedef float TT; CALL; break; }  \
+    case P_F16: { typedef f16 TT; CALL; break; }    \
+    case P_BF16: { typedef bf16 TT; CALL; break; }  \
+    default: return hipErrorInvalidValue;         \
+    }
+
+hipError_t launch_smooth_first(int D, int prec, int P, const void *b, const double *r, const double *scal,
+                               void *b_out, void *c, double omega, bool two, const Shape &s, hipStream_t st) {
+    MG_DISPATCH_T(prec, return smooth_first_t<TT>(D, P, b, r, scal, b_out, c, omega, two, s, st));
+    return hipErrorInvalidValue;
+}
+
+template <class T>
+static hipError_t sweep_t(int D, int P, const void *b, const void *c, void *c_out, double omega, const Shape &s,
+                          hipStream_t st) {
+    typedef acc_t<T> A;
+    typedef FArr<T, A> R;
+    const R rh{static_cast<const T *>(b)};
+    const R f{static_cast<const T *>(c)};
+    const ESweep<T, R, false> e{rh, static_cast<T *>(c_out), nullptr, (A)(omega / (2.0 * D))};
+    hipError_t err = hipSuccess;
+    MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+    return err;
+}
+
+hipError_t launch_sweep(int D, int prec, int P, const void *b, const void *c, void *c_out, double omega,
+                        const Shape &s, hipStream_t st) {
+    MG_DISPATCH_T(prec, return sweep_t<TT>(D, P, b, c, c_out, omega, s, st));
+    return hipErrorInvalidValue;
+}
+
+template <class TF, class TC>
+static hipError_t prolong_t(int D, int P, const void *c, const void *ec, const void *b, void *c_out, double omega,
+                            bool sweep, const Shape &s, hipStream_t st) {
+    typedef acc_t<TF> A;
+    typedef FProl<TF, TC> F;
+    typedef FArr<TF, A> R;
+    const F f{static_cast<const TF *>(c), static_cast<const TC *>(ec), P / 2};
+    const R rh{static_cast<const TF *>(b)};
+    hipError_t err = hipSuccess;
+    if (sweep) {
+        const ESweep<TF, R, false> e{rh, static_cast<TF *>(c_out), nullptr, (A)(omega / (2.0 * D))};
+        MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+    } else {
+        const ECopy<TF, R, false> e{rh, static_cast<TF *>(c_out), nullptr};
+        MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+    }
+    return err;
+}
+
+template <class TF>
+static hipError_t prolong_tf(int D, int pc, int P, const void *c, const void *ec, const void *b, void *c_out,
+                             double omega, bool sweep, const Shape &s, hipStream_t st) {
+    switch (pc) {
+    case P_F64: return prolong_t<TF, double>(D, P, c, ec, b, c_out, omega, sweep, s, st);
+    case P_F32: return prolong_t<TF, float>(D, P, c, ec, b, c_out, omega, sweep, s, st);
+    case P_F16: return prolong_t<TF, f16>(D, P, c, ec, b, c_out, omega, sweep, s, st);
+    case P_BF16: return prolong_t<TF, bf16>(D, P, c, ec, b, c_out, omega, sweep, s, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_prolong(int D, int pf, int pc, int P, const void *c, const void *ec, const void *b, void *c_out,
+                          double omega, bool sweep, const Shape &s, hipStream_t st) {
+    MG_DISPATCH_T(pf, return prolong_tf<TT>(D, pc, P, c, ec, b, c_out, omega, sweep, s, st));
+    return hipErrorInvalidValue;
+}
+
+template <int D, int V, class TF, class TC>
+static hipError_t restrict_run(int P, const void *b, const void *c, void *bc, const RShape &s, hipStream_t st) {
+    const int Pc = P / 2;
+    const int ytiles = D == 3 ? ceil_div(Pc - 1, s.tyc) : 1;
+    const int blocks = ytiles * ceil_div(Pc - 1, s.zcc);
+    const int G = D == 3 ? 2 * s.tyc + 1 : 1;
+    const int threads = G * (P / V);
+    const size_t lds = 2 * (size_t)G * P * sizeof(acc_t<TF>);
+    hipLaunchKernelGGL((k_restrict<D, V, TF, TC>), dim3(blocks), dim3(threads), lds, st,
+                       static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P, s.tyc,
+                       s.zcc, ytiles);
+    return hipGetLastError();
+}
+
+template <class TF, class TC>
+static hipError_t restrict_t(int D, int P, const void *b, const void *c, void *bc, const RShape &s, hipStream_t st) {
+    hipError_t err = hipSuccess;
+    MG_DISPATCH_DV(D, s.V, err = (restrict_run<DD, VV, TF, TC>(P, b, c, bc, s, st)));
+    return err;
+}
+
+template <class TF>
+static hipError_t restrict_tf(int D, int pc, int P, const void *b, const void *c, void *bc, const RShape &s,
+                              hipStream_t st) {
+    switch (pc) {
+    case P_F64: return restrict_t<TF, double>(D, P, b, c, bc, s, st);
+    case P_F32: return restrict_t<TF, float>(D, P, b, c, bc, s, st);
+    case P_F16: return restrict_t<TF, f16>(D, P, b, c, bc, s, st);
+    case P_BF16: return restrict_t<TF, bf16>(D, P, b, c, bc, s, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_restrict(int D, int pf, int pc, int P, const void *b, const void *c, void *bc, const RShape &s,
+                           hipStream_t st) {
+    MG_DISPATCH_T(pf, return restrict_tf<TT>(D, pc, P, b, c, bc, s, st));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_coarse(int D, int prec, const void *b, void *c, hipStream_t st) {
+    MG_DISPATCH_T(prec, {
+        if (D == 3)
+            hipLaunchKernelGGL((k_coarse<3, TT>), dim3(1), dim3(64), 0, st, static_cast<const TT *>(b),
+                               static_cast<TT *>(c));
+        else
+            hipLaunchKernelGGL((k_coarse<2, TT>), dim3(1), dim3(64), 0, st, static_cast<const TT *>(b),
+                               static_cast<TT *>(c));
+        return hipGetLastError();
+    });
+    return hipErrorInvalidValue;
+}
+
+template <class T>
+static hipError_t outer_t(int D, int P, const void *c, double *R, double *U, const double *scal, double h2,
+                          double *part, const Shape &s, hipStream_t st) {
+    const FArr<T, double> f{static_cast<const T *>(c)};
+    const EOuter e{R, U, scal, h2, part};
+    hipError_t err = hipSuccess;
+    MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
+    return err;
+}
+
+hipError_t launch_outer_update(int D, int prec, int P, const void *c, double *R, double *U, const double *scal,
+                               double h2, double *part, const Shape &s, hipStream_t st) {
+    MG_DISPATCH_T(prec, return outer_t<TT>(D, P, c, R, U, scal, h2, part, s, st));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,
+                             double inv_h2, double *part, hipStream_t st) {
+    const long N = D == 3 ? (long)n * n * n : (long)n * n;
+    const int blocks = flat_blocks(N);
+    if (D == 3)
+        hipLaunchKernelGGL(k_resid_flat<3>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, N, part);
+    else
+        hipLaunchKernelGGL(k_resid_flat<2>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, N, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *part, int nparts, double *scal, int scaling, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, part, nparts, scal, scaling);
+    return hipGetLastError();
+}
+
+template <class TS, class TD>
+static hipError_t pack_t(int D, bool unpack, int n, int P, const void *src, void *dst, hipStream_t st) {
+    const long N = D == 3 ? (long)n * n * n : (long)n * n;
+    const int blocks = flat_blocks(N);
+    const TS *s = static_cast<const TS *>(src);
+    TD *d = static_cast<TD *>(dst);
+    if (D == 3) {
+        if (unpack) hipLaunchKernelGGL((k_unpack<3, TS, TD>), dim3(blocks), dim3(256), 0, st, s, d, n, P, N);
+        else hipLaunchKernelGGL((k_pack<3, TS, TD>), dim3(blocks), dim3(256), 0, st, s, d, n, P, N);
+    } else {
+        if (unpack) hipLaunchKernelGGL((k_unpack<2, TS, TD>), dim3(blocks), dim3(256), 0, st, s, d, n, P, N);
+        else hipLaunchKernelGGL((k_pack<2, TS, TD>), dim3(blocks), dim3(256), 0, st, s, d, n, P, N);
+    }
+    return hipGetLastError();
+}
+
+template <class TS>
+static hipError_t pack_ts(int D, bool unpack, int dp, int n, int P, const void *src, void *dst, hipStream_t st) {
+    switch (dp) {
+    case P_F64: return pack_t<TS, double>(D, unpack, n, P, src, dst, st);
+    case P_F32: return pack_t<TS, float>(D, unpack, n, P, src, dst, st);
+    case P_F16: return pack_t<TS, f16>(D, unpack, n, P, src, dst, st);
+    case P_BF16: return pack_t<TS, bf16>(D, unpack, n, P, src, dst, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack(int D, int sp, int dp, int n, int P, const void *src, void *dst, hipStream_t st) {
+    MG_DISPATCH_T(sp, return pack_ts<TT>(D, false, dp, n, P, src, dst, st));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_unpack(int D, int sp, int dp, int n, int P, const void *src, void *dst, hipStream_t st) {
+    MG_DISPATCH_T(sp, return pack_ts<TT>(D, true, dp, n, P, src, dst, st));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(p) % 16) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    long b = (long)((n16 + 255) / 256);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)b), dim3(256), 0, st, static_cast<uint4 *>(p), n16);
+    return hipGetLastError();
+}
+
+}  // namespace mg

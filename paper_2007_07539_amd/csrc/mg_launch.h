@@ -1,0 +1,75 @@
+// Host-side launch interface of the gfx950 multigrid kernels (internal to the
+// library; the public ABI is include/mgir.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace mg {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+
+inline size_t prec_bytes(int p) { return p == P_F64 ? 8 : p == P_F32 ? 4 : 2; }
+
+// Launch shape of one z-marching stencil kernel.
+struct Shape {
+    int V;    // elements per thread along x (4 or 8), V <= P
+    int zc;   // planes (3-D) or rows (2-D) marched by one thread
+    int bs;   // threads per block (multiple of 64, <= 256)
+    int xcd;  // 1: remap block ids so consecutive tiles share an XCD
+};
+
+// Launch shape of the residual + restriction kernel.
+struct RShape {
+    int V;    // fine elements per thread along x (4 or 8); the coarse side uses V/2
+    int tyc;  // coarse rows per block (3-D)
+    int zcc;  // coarse planes (3-D) or rows (2-D) per block
+};
+
+// Elements of a padded level array: (P + 2) planes of P*P (3-D) or (P + 2)
+// rows of P (2-D).
+inline size_t level_elems(int D, int P) { return D == 3 ? (size_t)(P + 2) * P * P : (size_t)(P + 2) * P; }
+
+// Number of blocks a stencil launch uses (= reduction partials it writes).
+int stencil_blocks(int D, int P, const Shape &s);
+int restrict_blocks(int D, int P, const RShape &s);
+size_t restrict_lds_bytes(int D, int P, int pf, const RShape &s);
+int flat_blocks(long N);
+
+// Pre-smoothing from zero: c = S^2(0) (two fused sweeps) or S(0) when
+// two == false.  The right-hand side is b (level format) or, when r != NULL,
+// b = round(r * scal[1]) from the FP64 residual r, which is then also written
+// to b_out (fused scale-and-cast of the refinement loop).
+hipError_t launch_smooth_first(int D, int prec, int P, const void *b, const double *r, const double *scal,
+                               void *b_out, void *c, double omega, bool two, const Shape &s,
+                               hipStream_t st);
+// One damped-Jacobi sweep: c_out = c + k (b - L c).
+hipError_t launch_sweep(int D, int prec, int P, const void *b, const void *c, void *c_out, double omega,
+                        const Shape &s, hipStream_t st);
+// b_c = round(FW(b - L c)) onto the coarse level.
+hipError_t launch_restrict(int D, int pf, int pc, int P, const void *b, const void *c, void *bc,
+                           const RShape &s, hipStream_t st);
+// c_out = S(round(c + 4 P e_c)) when sweep, else round(c + 4 P e_c).
+hipError_t launch_prolong(int D, int pf, int pc, int P, const void *c, const void *ec, const void *b,
+                          void *c_out, double omega, bool sweep, const Shape &s, hipStream_t st);
+// Base level (n = 1): c = b / (2D).
+hipError_t launch_coarse(int D, int prec, const void *b, void *c, hipStream_t st);
+// Refinement update (Algorithm 2 lines 6-7), FP64: U += a h^2 c, R -= a L c,
+// with a = scal[0]; writes one (sum r^2, max |r|) pair per block to part.
+hipError_t launch_outer_update(int D, int prec, int P, const void *c, double *R, double *U,
+                               const double *scal, double h2, double *part, const Shape &s,
+                               hipStream_t st);
+// Dense-index pass: r = b - A U (or r = b when U == NULL), optionally stored
+// to the padded R and U copied out to the dense uout; (sum r^2, max |r|)
+// partials per block.
+hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double *U, double *R,
+                             double *uout, double inv_h2, double *part, hipStream_t st);
+// Reduce partials: scal = {alpha, 1/alpha, ||r||_2, ||r||_inf}.
+hipError_t launch_finalize(const double *part, int nparts, double *scal, int scaling, hipStream_t st);
+// Dense <-> padded copies with format conversion (round to nearest even).
+hipError_t launch_pack(int D, int src_prec, int dst_prec, int n, int P, const void *src, void *dst,
+                       hipStream_t st);
+hipError_t launch_unpack(int D, int src_prec, int dst_prec, int n, int P, const void *src, void *dst,
+                         hipStream_t st);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+
+}  // namespace mg

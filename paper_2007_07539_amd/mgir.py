@@ -1,0 +1,229 @@
+"""Python binding of the C ABI in include/mgir.h (ctypes; argument marshalling only).
+
+Every step of the solver runs in the gfx950 kernels of ``libmgir.so``.  torch
+provides device memory (the workspace and the caller's vectors) and the
+current HIP stream.  There is no CPU fallback: if the library is missing the
+import of this module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgir.so")
+
+MG_OK, MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_PREC, MG_ERR_WORKSPACE, MG_ERR_HIP, MG_ERR_NOT_CONVERGED, \
+    MG_ERR_NONFINITE, MG_ERR_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+TORCH_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+BUF_RHS, BUF_COR, BUF_RES, BUF_SOL = 0, 1, 2, 3
+STAGE_SMOOTH_FIRST, STAGE_SWEEP, STAGE_RESTRICT, STAGE_PROLONG_SWEEP, STAGE_COARSE = 0, 1, 2, 3, 4
+EXPORTS = ("mg_default_options", "mg_setup", "mg_workspace_size", "mg_bind_workspace", "mg_vcycle", "ir_solve",
+           "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_write", "mg_level_read", "mg_stage",
+           "mg_levels", "mg_level_n", "mg_profile_step")
+
+
+class MgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
+                ("residual_scaling", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("use_initial_guess", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libmgir.so (built by paper_2007_07539_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_07539_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    H = ctypes.c_void_p
+    lib.mg_default_options.argtypes, lib.mg_default_options.restype = [ctypes.POINTER(Options)], None
+    lib.mg_setup.argtypes = [ctypes.POINTER(H), i, i, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Options)]
+    lib.mg_workspace_size.argtypes = [H, ctypes.POINTER(ctypes.c_size_t)]
+    lib.mg_bind_workspace.argtypes = [H, vp, ctypes.c_size_t, vp]
+    lib.mg_vcycle.argtypes = [H, vp, vp, vp]
+    lib.ir_solve.argtypes = [H, vp, vp, ctypes.POINTER(Stats), vp]
+    lib.mg_destroy.argtypes = [H]
+    lib.mg_status_string.argtypes, lib.mg_status_string.restype = [i], ctypes.c_char_p
+    lib.mg_last_error.argtypes, lib.mg_last_error.restype = [], ctypes.c_char_p
+    lib.mg_level_write.argtypes = [H, i, i, vp, i, vp]
+    lib.mg_level_read.argtypes = [H, i, i, vp, i, vp]
+    lib.mg_stage.argtypes = [H, i, i, vp]
+    lib.mg_levels.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
+    lib.mg_level_n.argtypes = [H, i, ctypes.POINTER(ctypes.c_int)]
+    lib.mg_profile_step.argtypes = [H, vp, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_char_p),
+                                    ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int)]
+    for f in EXPORTS:
+        if f not in ("mg_default_options", "mg_status_string", "mg_last_error"):
+            getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != MG_OK:
+        lib = load()
+        msg = lib.mg_last_error().decode(errors="replace")
+        raise MgError(status, f"{what}: {lib.mg_status_string(status).decode()}: {msg}")
+
+
+def default_options() -> Options:
+    o = Options()
+    load().mg_default_options(ctypes.byref(o))
+    return o
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iterations: int
+    rel_residual: float
+    seconds: float
+    history: list = field(default_factory=list)
+
+
+class Solver:
+    """One grid: ``mg_setup`` + a torch-allocated workspace bound with ``mg_bind_workspace``.
+
+    level_prec: list of 'f64' | 'f32' | 'f16' | 'bf16', finest level first
+    (None = all FP64).  Vectors are torch tensors of shape (n,)*dim on the GPU.
+    """
+
+    def __init__(self, dim: int, n: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
+                 max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False,
+                 device=None, stream=None):
+        self.lib = load()
+        self.dim, self.n = dim, n
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        o = default_options()
+        o.nu1, o.nu2, o.omega = nu1, nu2, omega
+        o.residual_scaling, o.max_iter, o.rtol = int(bool(residual_scaling)), max_iter, rtol
+        o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), \
+            int(bool(autotune))
+        self.options = o
+        self._h = ctypes.c_void_p()
+        m = int(n + 1).bit_length() - 1
+        if level_prec is None:
+            level_prec = ["f64"] * m
+        self.level_prec = list(level_prec)
+        if len(self.level_prec) != m:
+            raise ValueError(f"level_prec needs {m} entries (finest first), got {len(self.level_prec)}")
+        arr = (ctypes.c_int * m)(*[PREC[p] for p in self.level_prec])
+        _check(self.lib.mg_setup(ctypes.byref(self._h), dim, n, 0, arr, ctypes.byref(o)), "mg_setup")
+        nb = ctypes.c_size_t()
+        _check(self.lib.mg_workspace_size(self._h, ctypes.byref(nb)), "mg_workspace_size")
+        self.workspace_bytes = nb.value
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            off = (-base) % 256
+            _check(self.lib.mg_bind_workspace(self._h, ctypes.c_void_p(base + off), nb.value,
+                                              _stream_ptr(stream)), "mg_bind_workspace")
+        nl = ctypes.c_int()
+        _check(self.lib.mg_levels(self._h, ctypes.byref(nl)), "mg_levels")
+        self.nlevels = nl.value
+
+    # -- helpers ---------------------------------------------------------------
+    def level_n(self, level: int) -> int:
+        v = ctypes.c_int()
+        _check(self.lib.mg_level_n(self._h, level, ctypes.byref(v)), "mg_level_n")
+        return v.value
+
+    def level_shape(self, level: int):
+        return (self.level_n(level),) * self.dim
+
+    def close(self):
+        if self._h:
+            self.lib.mg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the three operations of the method ----------------------------------------
+    def vcycle(self, b: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """One V-cycle for A e = b from e = 0; returns c = e / h^2 in level_prec[0]."""
+        dt = TORCH_DTYPE[self.level_prec[0]]
+        if b.dtype != dt or tuple(b.shape) != (self.n,) * self.dim:
+            raise ValueError(f"b must be {dt} of shape {(self.n,) * self.dim}")
+        c = torch.empty_like(b) if out is None else out
+        _check(self.lib.mg_vcycle(self._h, _dptr(b), _dptr(c), _stream_ptr(stream)), "mg_vcycle")
+        return c
+
+    def solve(self, b: torch.Tensor, u: torch.Tensor | None = None, stream=None, history_cap: int = 256,
+              check: bool = True) -> tuple[torch.Tensor, SolveResult]:
+        """Iterative refinement to ||r||_2 <= rtol ||b||_2 (Algorithm 2)."""
+        if b.dtype != torch.float64 or tuple(b.shape) != (self.n,) * self.dim:
+            raise ValueError(f"b must be float64 of shape {(self.n,) * self.dim}")
+        if u is None:
+            u = torch.zeros_like(b)
+        hist = (ctypes.c_double * history_cap)()
+        st = Stats(0, 0.0, 0.0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), history_cap)
+        status = self.lib.ir_solve(self._h, _dptr(b), _dptr(u), ctypes.byref(st), _stream_ptr(stream))
+        res = SolveResult(status, st.iterations, st.rel_residual, st.seconds,
+                          [hist[i] for i in range(min(st.iterations + 1, history_cap))])
+        if check and status not in (MG_OK,):
+            _check(status, "ir_solve")
+        return u, res
+
+    # -- stage-level access ---------------------------------------------------------
+    def write(self, level: int, buf: int, src: torch.Tensor, stream=None):
+        rev = {v: k for k, v in TORCH_DTYPE.items()}
+        _check(self.lib.mg_level_write(self._h, level, buf, _dptr(src), PREC[rev[src.dtype]], _stream_ptr(stream)),
+               "mg_level_write")
+
+    def read(self, level: int, buf: int, dtype=torch.float64, stream=None) -> torch.Tensor:
+        rev = {v: k for k, v in TORCH_DTYPE.items()}
+        out = torch.empty(self.level_shape(level), dtype=dtype, device=self.device)
+        _check(self.lib.mg_level_read(self._h, level, buf, _dptr(out), PREC[rev[dtype]], _stream_ptr(stream)),
+               "mg_level_read")
+        return out
+
+    def stage(self, stage: int, level: int, stream=None):
+        _check(self.lib.mg_stage(self._h, stage, level, _stream_ptr(stream)), "mg_stage")
+
+    def profile_step(self, stream=None, cap: int = 512):
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        by = (ctypes.c_double * cap)()
+        lv = (ctypes.c_int * cap)()
+        cnt = ctypes.c_int()
+        _check(self.lib.mg_profile_step(self._h, _stream_ptr(stream), cap, ctypes.byref(cnt), names, ms, by, lv),
+               "mg_profile_step")
+        return [(names[i].decode(), lv[i], ms[i], by[i]) for i in range(min(cnt.value, cap))]

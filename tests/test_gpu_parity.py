@@ -1,0 +1,268 @@
+"""GPU parity: every kernel of the V-cycle and the refinement loop against the
+FP64 oracle on the same (upcast) inputs, through the C ABI.
+
+Tolerances (normwise inf-norm relative error of one kernel's output):
+FP64 1e-12, FP32 1e-6, FP16 2e-3, BF16 1.6e-2 (tests/helpers.py); outputs
+formed in an FP32 accumulator and stored as FP64 are held to 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2007_07539_amd import mgir
+from paper_2007_07539_amd import workloads as W
+from tests.helpers import TOL, rel_err, round_to
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["f64", "f32", "f16", "bf16"]
+ACC_TOL = {"f64": 1e-12, "f32": 1e-6, "f16": 1e-6, "bf16": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _solver(dim, n, fine, coarse=None, **kw):
+    m = W.levels_for(n)
+    prec = [fine] * m
+    if coarse is not None:
+        prec[1:] = [coarse] * (m - 1)
+    return mgir.Solver(dim, n, prec, **kw)
+
+
+def _put(s, level, buf, x, dev):
+    s.write(level, buf, torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev))
+    return s.read(level, buf).cpu().numpy()
+
+
+def _get(s, level, buf):
+    torch.cuda.synchronize()
+    return s.read(level, buf).cpu().numpy()
+
+
+CASES = [(3, 7), (3, 15), (3, 63), (3, 127), (2, 15), (2, 255)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,n", CASES)
+def test_sweep(dev, ref, prec, dim, n):
+    print(f"sweep prec={prec} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, prec)
+    rng = np.random.default_rng(10 * n + dim)
+    h2 = (1.0 / (n + 1)) ** 2
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    cq = _put(s, 0, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (n,) * dim), dev)
+    s.stage(mgir.STAGE_SWEEP, 0)
+    out = _get(s, 0, mgir.BUF_COR)
+    expect = ref.jacobi(bq, cq * h2, 0.8) / h2
+    assert rel_err(out, expect) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,n", CASES)
+def test_smooth_first(dev, ref, prec, dim, n):
+    print(f"smooth_first prec={prec} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, prec)
+    rng = np.random.default_rng(20 * n + dim)
+    h2 = (1.0 / (n + 1)) ** 2
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    s.stage(mgir.STAGE_SMOOTH_FIRST, 0)
+    out = _get(s, 0, mgir.BUF_COR)
+    c1 = round_to(ref.jacobi(bq, np.zeros_like(bq), 0.8) / h2, prec)
+    c2 = ref.jacobi(bq, c1 * h2, 0.8) / h2
+    assert rel_err(out, c2) <= TOL[prec]
+
+
+@pytest.mark.parametrize("pf,pc", [(a, b) for a in PRECS for b in PRECS])
+@pytest.mark.parametrize("dim,n", [(3, 15), (3, 63), (2, 63)])
+def test_resid_restrict(dev, ref, pf, pc, dim, n):
+    print(f"restrict {pf}->{pc} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, pf, pc)
+    rng = np.random.default_rng(30 * n + dim)
+    h2 = (1.0 / (n + 1)) ** 2
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    cq = _put(s, 0, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (n,) * dim), dev)
+    s.stage(mgir.STAGE_RESTRICT, 0)
+    out = _get(s, 1, mgir.BUF_RHS)
+    expect = ref.restrict(ref.residual(bq, cq * h2))
+    assert rel_err(out, expect) <= max(TOL[pc], ACC_TOL[pf])
+
+
+@pytest.mark.parametrize("pf,pc", [(a, b) for a in PRECS for b in PRECS])
+@pytest.mark.parametrize("dim,n", [(3, 15), (3, 63), (2, 63)])
+def test_prolong_sweep(dev, ref, pf, pc, dim, n):
+    print(f"prolong {pc}->{pf} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, pf, pc)
+    nc = (n - 1) // 2
+    rng = np.random.default_rng(40 * n + dim)
+    hf2, hc2 = (1.0 / (n + 1)) ** 2, (1.0 / (nc + 1)) ** 2
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    cq = _put(s, 0, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (n,) * dim), dev)
+    ecq = _put(s, 1, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (nc,) * dim), dev)
+    s.stage(mgir.STAGE_PROLONG_SWEEP, 0)
+    out = _get(s, 0, mgir.BUF_COR)
+    corrected = round_to((cq * hf2 + ref.prolong(ecq * hc2)) / hf2, pf)
+    expect = ref.jacobi(bq, corrected * hf2, 0.8) / hf2
+    assert rel_err(out, expect) <= TOL[pf]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarse_solve(dev, prec, dim):
+    s = _solver(dim, 7, "f64", prec)
+    base = s.nlevels - 1
+    bq = _put(s, base, mgir.BUF_RHS, np.full((1,) * dim, 0.7071), dev)
+    s.stage(mgir.STAGE_COARSE, base)
+    out = _get(s, base, mgir.BUF_COR)
+    assert rel_err(out, round_to(bq / (2 * dim), prec)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("dim,n", [(3, 7), (3, 31), (3, 63), (2, 63), (2, 255)])
+def test_vcycle_fp64(dev, ref, dim, n):
+    print(f"vcycle f64 dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, "f64")
+    b = W.uniform_rhs(dim, n, seed=50 + n)
+    c = s.vcycle(torch.from_numpy(b).to(dev)).cpu().numpy()
+    e = ref.vcycle(b)
+    h2 = (1.0 / (n + 1)) ** 2
+    assert rel_err(c * h2, e) <= 1e-12
+
+
+@pytest.mark.parametrize("name,tol", [("f32", 1e-5), ("f16", 2e-2), ("bf16", 1e-1), ("hsd", 2e-2),
+                                      ("h_mg", 2e-2)])
+def test_vcycle_mixed_close_to_fp64(dev, ref, name, tol):
+    n, dim = 63, 3
+    prec = W.precision_map(name, W.levels_for(n))
+    s = mgir.Solver(dim, n, prec)
+    b = W.uniform_rhs(dim, n, seed=60)
+    bq = round_to(b, prec[0])
+    bt = torch.from_numpy(bq).to(dev).to(mgir.TORCH_DTYPE[prec[0]])
+    c = s.vcycle(bt).to(torch.float64).cpu().numpy()
+    e = ref.vcycle(bq)
+    assert rel_err(c * (1.0 / (n + 1)) ** 2, e) <= tol
+
+
+def _true_rel(ref, b, u):
+    return ref.norm2(ref.residual(b, u)) / ref.norm2(b)
+
+
+@pytest.mark.parametrize("dim,n", [(3, 31), (3, 63), (3, 127), (2, 255)])
+def test_ir_solve_fp64_matches_oracle(dev, ref, dim, n):
+    print(f"ir f64 dim={dim} n={n}", flush=True)
+    b = W.poisson2d_sine_rhs(n) if dim == 2 else W.uniform_rhs(dim, n, seed=2)
+    s = _solver(dim, n, "f64", residual_scaling=False)
+    u, res = s.solve(torch.from_numpy(b).to(dev))
+    u = u.cpu().numpy()
+    o = ref.ir_solve(b, residual_scaling=False, recursive_residual=True)
+    assert res.status == 0 and o.status == 0
+    assert abs(res.iterations - o.iterations) <= 1
+    assert _true_rel(ref, b, u) <= 1e-10
+    assert res.rel_residual == pytest.approx(_true_rel(ref, b, u), rel=1e-9)
+    if res.iterations == o.iterations:
+        assert rel_err(u, o.u) <= 1e-12
+    if dim == 2:
+        # closed form of the discrete solution (f is an eigenvector of A)
+        h = 1.0 / (n + 1)
+        amp = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2
+        assert rel_err(u, amp * W.sine_mode(2, n, (1, 1))) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["f32", "f16", "bf16", "hsd", "h_mg"])
+@pytest.mark.parametrize("n", [63, 127])
+def test_ir_solve_mixed_reaches_tolerance(dev, ref, name, n):
+    print(f"ir {name} n={n}", flush=True)
+    b = W.uniform_rhs(3, n, seed=2)
+    s64 = _solver(3, n, "f64", residual_scaling=False)
+    _, r64 = s64.solve(torch.from_numpy(b).to(dev))
+    s = mgir.Solver(3, n, W.precision_map(name, W.levels_for(n)))
+    u, res = s.solve(torch.from_numpy(b).to(dev))
+    u = u.cpu().numpy()
+    assert res.status == 0
+    assert _true_rel(ref, b, u) <= 1e-10
+    assert res.iterations <= r64.iterations + 2
+    o = ref.ir_solve(b)
+    assert rel_err(u, o.u) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["f16", "bf16"])
+def test_ir_solve_mixed_smooth_rhs(dev, ref, name):
+    n = 127
+    b = W.poisson3d_sine_noise_rhs(n, seed=3)
+    s64 = _solver(3, n, "f64", residual_scaling=False)
+    _, r64 = s64.solve(torch.from_numpy(b).to(dev))
+    s = mgir.Solver(3, n, W.precision_map(name, W.levels_for(n)))
+    u, res = s.solve(torch.from_numpy(b).to(dev))
+    assert res.status == 0
+    assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
+    assert res.iterations <= r64.iterations + 2
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16", "f32", "f64"])
+def test_first_step_scale_cast_and_update(dev, ref, prec):
+    """One refinement step: the cast r/alpha (Algorithm 2 line 4) is correctly
+    rounded, and u = alpha h^2 c bitwise (line 6); the updated residual norm
+    matches the oracle's b - A u (line 7)."""
+    n, dim = 31, 3
+    prec_map = [prec] * (W.levels_for(n) - 1) + ["f64"]
+    b = W.uniform_rhs(dim, n, seed=70)
+    s = mgir.Solver(dim, n, prec_map, max_iter=1)
+    u1, res = s.solve(torch.from_numpy(b).to(dev), check=False)
+    assert res.status == mgir.MG_ERR_NOT_CONVERGED and res.iterations == 1
+    alpha = np.abs(b).max()
+    bh = round_to(b * (1.0 / alpha), prec)
+    c = s.vcycle(torch.from_numpy(bh).to(dev).to(mgir.TORCH_DTYPE[prec])).to(torch.float64).cpu().numpy()
+    h2 = (1.0 / (n + 1)) ** 2
+    np.testing.assert_array_equal(u1.cpu().numpy(), (alpha * h2) * c)
+    r1 = ref.residual(b, u1.cpu().numpy())
+    assert res.history[1] == pytest.approx(ref.norm2(r1) / ref.norm2(b), rel=1e-10)
+
+
+def test_graph_and_eager_agree_bitwise(dev):
+    n = 63
+    b = torch.from_numpy(W.uniform_rhs(3, n, seed=80)).to(dev)
+    prec = W.precision_map("f16", W.levels_for(n))
+    ug, rg = mgir.Solver(3, n, prec, use_graph=True).solve(b)
+    ue, re_ = mgir.Solver(3, n, prec, use_graph=False).solve(b)
+    assert rg.iterations == re_.iterations
+    assert torch.equal(ug, ue)
+    ug2, rg2 = mgir.Solver(3, n, prec, use_graph=True).solve(b)
+    assert torch.equal(ug, ug2) and rg2.history == rg.history
+
+
+def test_resume_from_iterate(dev, ref):
+    n = 63
+    b = W.uniform_rhs(3, n, seed=90)
+    bt = torch.from_numpy(b).to(dev)
+    prec = W.precision_map("f16", W.levels_for(n))
+    _, full = mgir.Solver(3, n, prec).solve(bt)
+    u4, r4 = mgir.Solver(3, n, prec, max_iter=4).solve(bt, check=False)
+    assert r4.status == mgir.MG_ERR_NOT_CONVERGED and r4.iterations == 4
+    u, rest = mgir.Solver(3, n, prec, use_initial_guess=True).solve(bt, u4.clone())
+    assert rest.status == 0
+    assert abs(4 + rest.iterations - full.iterations) <= 1
+    assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
+
+
+def test_edge_cases(dev):
+    n = 15
+    s = mgir.Solver(3, n, W.precision_map("f16", W.levels_for(n)))
+    z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)
+    u = torch.full_like(z, 3.0)
+    u, res = s.solve(z, u)
+    assert res.status == 0 and res.iterations == 0 and not u.any()
+    b = torch.from_numpy(W.uniform_rhs(3, n, seed=1)).to(dev)
+    bad = b.clone()
+    bad[3, 4, 5] = float("nan")
+    _, res = s.solve(bad, check=False)
+    assert res.status == mgir.MG_ERR_NONFINITE
+    s1 = mgir.Solver(3, n, W.precision_map("f16", W.levels_for(n)), max_iter=2)
+    u, res = s1.solve(b, check=False)
+    assert res.status == mgir.MG_ERR_NOT_CONVERGED and res.iterations == 2 and torch.isfinite(u).all()
+    # the smallest grid the library takes: n = 3 (two levels)
+    s3 = mgir.Solver(3, 3, ["f16", "f64"])
+    u, res = s3.solve(torch.from_numpy(W.uniform_rhs(3, 3, seed=2)).to(dev))
+    assert res.status == 0
