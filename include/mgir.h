@@ -58,10 +58,10 @@ typedef enum {
 typedef enum { MG_F64 = 0, MG_F32 = 1, MG_F16 = 2, MG_BF16 = 3 } mg_prec_t;
 
 typedef struct {
-    int nu1;                 /* pre-smoothing sweeps (Algorithm 1 step 1), default 2 */
-    int nu2;                 /* post-smoothing sweeps (Algorithm 1 step 5), default 2 */
+    int nu1;                 /* pre-smoothing sweeps (Algorithm 1), default 2 */
+    int nu2;                 /* post-smoothing sweeps (Algorithm 1), default 2 */
     double omega;            /* damped-Jacobi weight, default 0.8 */
-    int residual_scaling;    /* 1: alpha = ||r||_inf before the cast (Algorithm 2 line 4);
+    int residual_scaling;    /* 1: alpha = ||r||_inf before the cast (Algorithm 2);
                                 0: alpha = 1 (the FP64 baseline omits scaling, Section 6) */
     int max_iter;            /* V-cycles at most, default 100 */
     double rtol;             /* stop when ||r||_2 <= rtol * ||b||_2 (FP64), default 1e-10 */
@@ -124,7 +124,7 @@ mg_status_t mg_vcycle(mg_handle h, const void *b, void *c, void *stream);
  * r = b - A u;  while ||r||_2 > rtol ||b||_2:  alpha = ||r||_inf (or 1);
  * c = V-cycle(r / alpha) in the level formats;  u += alpha c;  r -= alpha A c.
  * Residual, update, norms and the stop test are FP64.  The recursively
- * updated residual of Algorithm 2 line 7 drives the loop; before returning,
+ * updated residual of Algorithm 2 drives the loop; before returning,
  * b - A u is recomputed from scratch and iteration continues if it does not
  * meet the tolerance.
  *   b  device, dense FP64, n^dim.

@@ -91,7 +91,7 @@ void ref_apply_A(int dim, int n, const double *v, double *out) {
             }
 }
 
-/* r = b - A c  (residual, Algorithm 1 step 2 and Algorithm 2). */
+/* r = b - A c  (the residual of Algorithms 1 and 2). */
 void ref_residual(int dim, int n, const double *b, const double *c, double *r) {
     long N = ref_points(dim, n);
     ref_apply_A(dim, n, c, r);
@@ -197,17 +197,17 @@ int ref_vcycle(int dim, int n, int nu1, int nu2, double omega, const double *b, 
     if (!tmp || !bc || !ec) { free(tmp); free(bc); free(ec); return REF_ERR_NOMEM; }
 
     memset(c, 0, sizeof(double) * N);
-    for (int s = 0; s < nu1; s++) {                 /* step 1 */
+    for (int s = 0; s < nu1; s++) {                 /* pre-smooth */
         ref_jacobi(dim, n, omega, b, c, tmp);
         memcpy(c, tmp, sizeof(double) * N);
     }
-    ref_residual(dim, n, b, c, tmp);                /* step 2 */
+    ref_residual(dim, n, b, c, tmp);                /* residual, restrict */
     ref_restrict(dim, n, tmp, bc);
-    int st = ref_vcycle(dim, n_c, nu1, nu2, omega, bc, ec);   /* step 3 */
+    int st = ref_vcycle(dim, n_c, nu1, nu2, omega, bc, ec);   /* coarse correction */
     if (st == REF_OK) {
-        ref_prolong(dim, n_c, ec, tmp);             /* step 4 */
+        ref_prolong(dim, n_c, ec, tmp);             /* prolongate, add */
         for (long p = 0; p < N; p++) c[p] += tmp[p];
-        for (int s = 0; s < nu2; s++) {             /* step 5 */
+        for (int s = 0; s < nu2; s++) {             /* post-smooth */
             ref_jacobi(dim, n, omega, b, c, tmp);
             memcpy(c, tmp, sizeof(double) * N);
         }
@@ -242,8 +242,8 @@ double ref_norminf(const double *v, long N) {
 typedef struct {
     int nu1, nu2;
     double omega;
-    int residual_scaling;      /* 1: alpha = ||r||_inf (Algorithm 2 line 4); 0: alpha = 1 */
-    int recursive_residual;    /* 1: r -= alpha A c (Algorithm 2 line 7); 0: r = b - A u */
+    int residual_scaling;      /* 1: alpha = ||r||_inf (residuum scaling, Algorithm 2); 0: alpha = 1 */
+    int recursive_residual;    /* 1: r -= alpha A c as in Algorithm 2; 0: r = b - A u */
     int max_iter;
     double rtol;               /* stop when ||r||_2 <= rtol ||b||_2 */
     int use_initial_guess;     /* 0: u starts at zero */
@@ -290,11 +290,11 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         if (k >= o->max_iter) { st = REF_ERR_NOT_CONVERGED; break; }
         double alpha = o->residual_scaling ? ref_norminf(r, N) : 1.0;
         double inv_alpha = 1.0 / alpha;
-        for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];        /* line 4 */
-        int vs = ref_vcycle(dim, n, o->nu1, o->nu2, o->omega, rl, c);  /* line 5 */
+        for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];        /* scale */
+        int vs = ref_vcycle(dim, n, o->nu1, o->nu2, o->omega, rl, c);  /* one V-cycle */
         if (vs != REF_OK) { st = vs; break; }
-        for (long p = 0; p < N; p++) u[p] += alpha * c[p];             /* line 6 */
-        if (o->recursive_residual) {                                   /* line 7 */
+        for (long p = 0; p < N; p++) u[p] += alpha * c[p];             /* update u */
+        if (o->recursive_residual) {                                   /* update r */
             ref_apply_A(dim, n, c, ac);
             for (long p = 0; p < N; p++) r[p] -= alpha * ac[p];
         } else {

@@ -269,7 +269,8 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
 
 bool finest_alias(mg_ctx *h) { return h->lv[0].prec == P_F64 && !h->opt.residual_scaling; }
 
-// One refinement step (Algorithm 2 lines 4-7) plus the norm readback.
+// One refinement step of Algorithm 2 (scale and cast, V-cycle, update) plus
+// the norm readback.
 hipError_t enq_step(mg_ctx *h, hipStream_t st) {
     hipError_t e = enq_vcycle(h, st, finest_alias(h) ? RHS_ALIAS_R : RHS_SCALED_R);
     if (e != hipSuccess) return e;

@@ -50,7 +50,8 @@ template <class T, class A> struct FArr {
 };
 
 // Right-hand side of the finest level inside the refinement loop:
-// round_T(r * (1/alpha)) from the FP64 residual (Algorithm 2 line 4).
+// round_T(r * (1/alpha)) from the FP64 residual (the residuum scaling and
+// precision change of Algorithm 2).
 template <class T> struct FScaled {
     typedef acc_t<T> acc;
     const double *__restrict__ r;
@@ -263,7 +264,7 @@ template <class T, class R, bool WRITE_B> struct ECopy {
     }
 };
 
-// Refinement update of Algorithm 2 lines 6-7 in FP64 (grid-scaled c):
+// Solution and residual update of Algorithm 2 in FP64 (grid-scaled c):
 // u += alpha h^2 c,  r -= alpha (2D c - nb), plus per-block norm partials.
 struct EOuter {
     typedef double A;
@@ -378,7 +379,8 @@ __global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nc
 }
 
 // ===========================================================================
-// Residual + full-weighting restriction + cast (Algorithm 1 step 2).  A block
+// Residual + full-weighting restriction + cast (the residual transfer of
+// Algorithm 1).  A block
 // owns `tyc` coarse rows (3-D) and `zcc` coarse planes.  Its threads first act
 // as fine-row threads: 2 tyc + 1 fine rows (2-D: one), each thread V fine x
 // values, marching the fine planes 2Z0-1 .. 2Z1-1 and writing the fine

@@ -53,7 +53,7 @@ hipError_t launch_prolong(int D, int pf, int pc, int P, const void *c, const voi
                           void *c_out, double omega, bool sweep, const Shape &s, hipStream_t st);
 // Base level (n = 1): c = b / (2D).
 hipError_t launch_coarse(int D, int prec, const void *b, void *c, hipStream_t st);
-// Refinement update (Algorithm 2 lines 6-7), FP64: U += a h^2 c, R -= a L c,
+// Refinement update of Algorithm 2 (solution and residual update), FP64: U += a h^2 c, R -= a L c,
 // with a = scal[0]; writes one (sum r^2, max |r|) pair per block to part.
 hipError_t launch_outer_update(int D, int prec, int P, const void *c, double *R, double *U,
                                const double *scal, double h2, double *part, const Shape &s,

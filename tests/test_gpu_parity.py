@@ -203,9 +203,9 @@ def test_ir_solve_mixed_smooth_rhs(dev, ref, name):
 
 @pytest.mark.parametrize("prec", ["f16", "bf16", "f32", "f64"])
 def test_first_step_scale_cast_and_update(dev, ref, prec):
-    """One refinement step: the cast r/alpha (Algorithm 2 line 4) is correctly
-    rounded, and u = alpha h^2 c bitwise (line 6); the updated residual norm
-    matches the oracle's b - A u (line 7)."""
+    """One refinement step of Algorithm 2: the scaled cast r/alpha is correctly
+    rounded, u = alpha h^2 c holds bitwise, and the updated residual norm
+    matches the oracle's b - A u."""
     n, dim = 31, 3
     prec_map = [prec] * (W.levels_for(n) - 1) + ["f64"]
     b = W.uniform_rhs(dim, n, seed=70)

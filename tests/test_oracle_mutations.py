@@ -22,8 +22,8 @@ MUTATIONS = {
     "coarse_correction_sign": ("for (long p = 0; p < N; p++) c[p] += tmp[p];",
                                "for (long p = 0; p < N; p++) c[p] -= tmp[p];"),
     "base_solve": ("c[0] = b[0] / (2.0 * dim / (h * h));", "c[0] = b[0] / (2.0 * dim / h);"),
-    "no_post_smoothing": ("for (int s = 0; s < nu2; s++) {             /* step 5 */",
-                          "for (int s = 0; s < 0; s++) {             /* step 5 */"),
+    "no_post_smoothing": ("for (int s = 0; s < nu2; s++) {             /* post-smooth */",
+                          "for (int s = 0; s < 0; s++) {             /* post-smooth */"),
     "scaling_not_compensated": ("u[p] += alpha * c[p];", "u[p] += c[p];"),
     "recursive_residual_sign": ("r[p] -= alpha * ac[p];", "r[p] += alpha * ac[p];"),
     "norm_without_sqrt": ("return sqrt(ref_sumsq(v, N));", "return ref_sumsq(v, N);"),
