@@ -177,8 +177,34 @@ mg_status_t mg_stage(mg_handle h, mg_stage_t stage, int level, void *stream);
 mg_status_t mg_levels(mg_handle h, int *nlevels);
 mg_status_t mg_level_n(mg_handle h, int level, int *n);
 
+/* ---- Launch shapes --------------------------------------------------------
+ * Each level except the base has two launch shapes; the autotuner and callers
+ * may change them (results do not depend on the shape: every shape forms the
+ * same roundings).  Changing a shape discards the captured graph. */
+typedef enum {
+    MG_SHAPE_STENCIL = 0,   /* smoothing, sweeps, prolongation, refinement update:
+                               {V (4|8 values per thread along x), zc (planes per
+                               thread), bs (threads per block, 64..256, register-queue
+                               kernel), xcd (0|1: keep neighbouring tiles on one XCD),
+                               ty (3-D: 0 = register-queue kernel, > 0 = LDS-plane
+                               kernel with ty output rows per block)} */
+    MG_SHAPE_RESTRICT = 1,  /* residual + restriction: {V (4|8), tyc (coarse rows per
+                               block, 3-D), zcc (coarse planes per block)} */
+    MG_SHAPE_UPDATE = 2     /* level 0 only: the FP64 refinement update, same five
+                               values as MG_SHAPE_STENCIL */
+} mg_shape_kind_t;
+mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
+mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);
+
 /* ---- Measurement --------------------------------------------------------
- * Run one refinement step eagerly with a HIP event pair around every kernel
+ * Bandwidth probe: one kernel launch that copies (kind 0), reads (1) or
+ * writes (2) `bytes` (a multiple of 16) of device memory with 16-byte lanes,
+ * `blocks` blocks of 256 threads in a grid-stride loop.  Used to measure the
+ * achievable HBM bandwidth and to calibrate traffic counters.  For kind 1 the
+ * first 4 bytes of dst may be written.  Async. */
+mg_status_t mg_bandwidth_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, void *stream);
+
+/* Run one refinement step eagerly with a HIP event pair around every kernel
  * launch, on stream, and return per-kernel durations.  The step uses the
  * workspace state left by the last ir_solve (it updates u and r like a real
  * step).  names/ms/bytes are caller arrays of capacity cap; *count receives the

@@ -45,7 +45,8 @@ struct LevelPlan {
     int n = 0, P = 0, prec = 0;
     size_t elems = 0;
     size_t off_b = 0, off_c[2] = {0, 0};
-    Shape sh;       // smoothing, sweeps, prolongation, outer update
+    Shape sh;       // smoothing, sweeps, prolongation
+    Shape osh;      // refinement update (finest level only)
     RShape rsh;     // residual + restriction onto the next level
 };
 
@@ -93,11 +94,25 @@ long points(int D, int n) { return D == 3 ? (long)n * n * n : (long)n * n; }
 
 bool valid_prec(int p) { return p >= 0 && p <= 3; }
 
-Shape pick_shape(int D, int P) {
+Shape pick_shape(int D, int P, int prec) {
     Shape s;
     s.V = P >= 8 ? 8 : 4;
     s.bs = 256;
     s.xcd = 1;
+    s.ty = 0;
+    if (D == 3 && P >= 16) {
+        // LDS-plane kernel: full rows, as many row groups as 1024 threads and
+        // 64 KiB of LDS allow (at most 14 output rows)
+        if (prec == P_F64) s.V = 4;
+        const int TXR = P / s.V;
+        int ty = std::min(14, P - 1);
+        while (ty > 1 && (TXR * (ty + 2) > 1024 || march_lds_bytes(P, ty, prec_bytes(prec)) > 65536)) --ty;
+        if (TXR * (ty + 2) <= 1024 && march_lds_bytes(P, ty, prec_bytes(prec)) <= 65536) {
+            s.ty = ty;
+            s.zc = std::max(1, std::min(8, P - 1));
+            return s;
+        }
+    }
     const long per_chunk = (long)(P / s.V) * (D == 3 ? P : 1);
     const long target = 1L << 19;  // threads in flight: about 32 waves on each of 256 CUs
     const long nch = (target + per_chunk - 1) / per_chunk;
@@ -279,7 +294,7 @@ hipError_t enq_step(mg_ctx *h, hipStream_t st) {
     const double N = (double)points(h->dim, L.n);
     RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
         launch_outer_update(h->dim, L.prec, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h), hh * hh, part(h),
-                            L.sh, st));
+                            L.osh, st));
     RUN(h, st, "norm_finalize", 0, 16.0 * h->outer_parts,
         launch_finalize(part(h), h->outer_parts, scal(h), h->opt.residual_scaling, st));
     return hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -403,7 +418,8 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         L.off_c[1] = off;
         off += bytes;
         if (nn > 1) {
-            L.sh = pick_shape(dim, L.P);
+            L.sh = pick_shape(dim, L.P, L.prec);
+            L.osh = pick_shape(dim, L.P, P_F64);  // FP64 rows dominate the update's registers
             L.rsh = pick_rshape(dim, L.P, L.prec);
         }
         nn = (nn - 1) / 2;
@@ -414,8 +430,11 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     h->off_U = off;
     off += fin;
     if (m > 1) {
-        h->outer_parts = stencil_blocks(dim, h->lv[0].P, h->lv[0].sh);
-        maxp = h->outer_parts;
+        h->outer_parts = stencil_blocks(dim, h->lv[0].P, h->lv[0].osh);
+        // room for the partials of any legal shape: V = 4, zc = 1, 64-thread blocks
+        const int P0 = h->lv[0].P;
+        const long worst = ((long)(P0 / 4) * (dim == 3 ? P0 : 1) * (P0 - 1) + 63) / 64;
+        maxp = (int)std::max<long>(h->outer_parts, worst);
     }
     maxp = std::max(maxp, flat_blocks(points(dim, n)));
     h->max_parts = maxp;
@@ -672,6 +691,69 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     rel = h->host_scal[2] / nb;
     finish_stats(k, rel);
     return result;
+}
+
+mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np) {
+    if (!h || !p) return fail(MG_ERR_ARG, "null argument");
+    if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
+    LevelPlan &L = h->lv[level];
+    const int D = h->dim;
+    if (kind == MG_SHAPE_STENCIL || kind == MG_SHAPE_UPDATE) {
+        if (kind == MG_SHAPE_UPDATE && level != 0) return fail(MG_ERR_ARG, "the update shape exists on level 0 only");
+        if (np != 5) return fail(MG_ERR_ARG, "stencil shape takes 5 values {V, zc, bs, xcd, ty}");
+        Shape s{p[0], p[1], p[2], p[3], p[4]};
+        if ((s.V != 4 && s.V != 8) || s.V > L.P) return fail(MG_ERR_ARG, "V must be 4 or 8 and <= P = %d", L.P);
+        if (s.zc < 1 || s.zc > L.P) return fail(MG_ERR_ARG, "zc out of range");
+        if (s.bs < 64 || s.bs > 256 || s.bs % 64) return fail(MG_ERR_ARG, "bs must be 64, 128, 192 or 256");
+        if (s.xcd != 0 && s.xcd != 1) return fail(MG_ERR_ARG, "xcd must be 0 or 1");
+        if (s.ty < 0 || (D == 2 && s.ty != 0)) return fail(MG_ERR_ARG, "ty must be 0 (2-D) or >= 0 (3-D)");
+        if (s.ty > 0 && ((L.P / s.V) * (s.ty + 2) > 1024 || march_lds_bytes(L.P, s.ty, prec_bytes(L.prec)) > 65536))
+            return fail(MG_ERR_ARG, "ty = %d exceeds 1024 threads or 64 KiB of LDS", s.ty);
+        if (kind == MG_SHAPE_UPDATE) {
+            if (stencil_blocks(D, L.P, s) > h->max_parts) return fail(MG_ERR_ARG, "too many blocks");
+            L.osh = s;
+            h->outer_parts = stencil_blocks(D, L.P, s);
+        } else {
+            L.sh = s;
+        }
+    } else if (kind == MG_SHAPE_RESTRICT) {
+        if (np != 3) return fail(MG_ERR_ARG, "restriction shape takes 3 values {V, tyc, zcc}");
+        RShape r{p[0], p[1], p[2]};
+        const int Pc = L.P / 2;
+        if ((r.V != 4 && r.V != 8) || r.V > L.P) return fail(MG_ERR_ARG, "V must be 4 or 8 and <= P = %d", L.P);
+        if (r.tyc < 1 || r.tyc > std::max(1, Pc - 1) || (D == 2 && r.tyc != 1)) return fail(MG_ERR_ARG, "tyc out of range");
+        if (r.zcc < 1 || r.zcc > std::max(1, Pc - 1)) return fail(MG_ERR_ARG, "zcc out of range");
+        const int G = D == 3 ? 2 * r.tyc + 1 : 1;
+        if (G * (L.P / r.V) > 1024) return fail(MG_ERR_ARG, "restriction block exceeds 1024 threads");
+        if (restrict_lds_bytes(D, L.P, L.prec, r) > 65536) return fail(MG_ERR_ARG, "restriction LDS exceeds 64 KiB");
+        L.rsh = r;
+    } else {
+        return fail(MG_ERR_ARG, "unknown shape kind %d", kind);
+    }
+    drop_graph(h);
+    return MG_OK;
+}
+
+mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
+    if (!h || !p) return fail(MG_ERR_ARG, "null argument");
+    if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
+    const LevelPlan &L = h->lv[level];
+    if ((kind == MG_SHAPE_STENCIL || (kind == MG_SHAPE_UPDATE && level == 0)) && np >= 5) {
+        const Shape &S = kind == MG_SHAPE_STENCIL ? L.sh : L.osh;
+        p[0] = S.V, p[1] = S.zc, p[2] = S.bs, p[3] = S.xcd, p[4] = S.ty;
+    } else if (kind == MG_SHAPE_RESTRICT && np >= 3) {
+        p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc;
+    } else {
+        return fail(MG_ERR_ARG, "bad kind or too few values");
+    }
+    return MG_OK;
+}
+
+mg_status_t mg_bandwidth_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, void *stream) {
+    if (!dst || !src || kind < 0 || kind > 2 || blocks < 1) return fail(MG_ERR_ARG, "bad argument");
+    if (bytes % 16) return fail(MG_ERR_ARG, "bytes must be a multiple of 16");
+    HIPCHK(launch_probe(dst, src, bytes, kind, blocks, static_cast<unsigned *>(dst), static_cast<hipStream_t>(stream)));
+    return MG_OK;
 }
 
 mg_status_t mg_profile_step(mg_handle h, void *stream, int cap, int *count, const char **names, double *ms,

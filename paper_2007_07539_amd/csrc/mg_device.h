@@ -63,7 +63,14 @@ template <> struct Store<float> {
     __device__ static float from_f64(double v) { return (float)v; }
 };
 template <> struct Store<f16> {
-    __device__ static f16 from_acc(float v) { return (f16)v; }
+    // The empty asm makes v opaque: without it the backend may fold the
+    // producing FP32 FMA and this narrowing into one mixed-precision FMA that
+    // rounds once instead of twice, so that the same source line would round
+    // differently in different kernels.
+    __device__ static f16 from_acc(float v) {
+        asm volatile("" : "+v"(v));
+        return (f16)v;
+    }
     __device__ static f16 from_f64(double v) { return (f16)f64_to_f32_odd(v); }
 };
 template <> struct Store<bf16> {
@@ -125,6 +132,24 @@ __device__ __forceinline__ void store_row(T *__restrict__ p, const T (&v)[V]) {
 #pragma unroll
     for (int i = 0; i < B / CB; ++i) q[i] = u.c[i];
 }
+
+// Raw (storage-format) row copies, for prefetching before conversion.
+template <class T, int V> __device__ __forceinline__ void load_raw(const T *__restrict__ p, T (&v)[V]) {
+    constexpr int B = V * (int)sizeof(T);
+    constexpr int CB = B >= 16 ? 16 : B;
+    typedef typename RawChunk<CB>::type C;
+    union {
+        C c[B / CB];
+        T t[V];
+    } u;
+    const C *q = reinterpret_cast<const C *>(p);
+#pragma unroll
+    for (int i = 0; i < B / CB; ++i) u.c[i] = q[i];
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] = u.t[i];
+}
+
+template <class T> __device__ __forceinline__ T zero_of() { return Store<T>::from_acc(acc_t<T>(0)); }
 
 // ---------------------------------------------------------------------------
 // Padded level layout.  A level with n = 2^m - 1 interior points per

@@ -379,6 +379,345 @@ __global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nc
 }
 
 // ===========================================================================
+// Pipelined 3-D z-march with the field's current plane staged in LDS.
+//
+// A block owns TY output rows of full length P and a chunk of zc planes; its
+// threads form TY + 2 row groups (the extra two produce the halo rows y0 - 1
+// and y0 + TY).  Per plane, every row group evaluates the field once for its
+// own row: the value stays in registers for the z-1 / z / z+1 queue and is
+// written to one of two LDS plane buffers, from which the x and y neighbours
+// are read after a barrier.  Global loads of the next plane are issued one
+// iteration ahead ("fetch" into raw registers, "value" converts), so they are
+// in flight across the barrier and the arithmetic.
+//
+// Policies (templated on V): a field provides Raw, fetch(), value() and the
+// LDS storage type lds_t (field values are exactly representable in it); an
+// emit provides Raw (per-row inputs of the output), fetch(), emit(), finish().
+// ===========================================================================
+
+// Stored array.
+template <class T, class A, int V> struct PArr {
+    typedef A acc;
+    typedef T lds_t;
+    struct Raw {
+        T v[V];
+    };
+    const T *__restrict__ p;
+    __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) r.v[i] = zero_of<T>();
+            return;
+        }
+        load_raw<T, V>(p + g.at(x0, y, z), r.v);
+    }
+    __device__ __forceinline__ void value(const Raw &r, int, int, int, A (&o)[V], A (&)[V]) const {
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = (A)widen(r.v[i]);
+    }
+};
+
+// First Jacobi iterate round_T(k b) from a stored right-hand side; aux = b.
+template <class T, int V> struct PJac0Arr {
+    typedef acc_t<T> acc;
+    typedef T lds_t;
+    struct Raw {
+        T v[V];
+    };
+    const T *__restrict__ b;
+    acc k;
+    __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) r.v[i] = zero_of<T>();
+            return;
+        }
+        load_raw<T, V>(b + g.at(x0, y, z), r.v);
+    }
+    __device__ __forceinline__ void value(const Raw &r, int, int, int, acc (&o)[V], acc (&aux)[V]) const {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            aux[i] = widen(r.v[i]);
+            o[i] = round_to<T>(k * aux[i]);
+        }
+    }
+};
+
+// First Jacobi iterate from the scaled-and-cast FP64 residual; aux = b-hat.
+template <class T, int V> struct PJac0Scaled {
+    typedef acc_t<T> acc;
+    typedef T lds_t;
+    struct Raw {
+        double v[V];
+    };
+    const double *__restrict__ r;
+    const double *__restrict__ scal;  // scal[1] = 1/alpha
+    acc k;
+    __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &rr) const {
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) rr.v[i] = 0.0;
+            return;
+        }
+        load_raw<double, V>(r + g.at(x0, y, z), rr.v);
+    }
+    __device__ __forceinline__ void value(const Raw &rr, int, int, int, acc (&o)[V], acc (&aux)[V]) const {
+        const double inv = scal[1];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            aux[i] = widen(Store<T>::from_f64(rr.v[i] * inv));
+            o[i] = round_to<T>(k * aux[i]);
+        }
+    }
+};
+
+// Corrected correction round_TF(c + 4 P e_c); same arithmetic as FProl::row.
+template <class TF, class TC, int V> struct PProl {
+    typedef acc_t<TF> acc;
+    typedef TF lds_t;
+    typedef typename FProl<TF, TC>::PA PA;
+    static constexpr int H = V / 2;
+    struct Raw {
+        TF c[V];
+        PA seg[4][H + 1];
+        int ok;  // bit a*2+b: coarse row (Z_a, Y_b) present
+    };
+    const TF *__restrict__ c;
+    const TC *__restrict__ ec;
+    int Pc;
+    __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
+        r.ok = 0;
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) r.c[i] = zero_of<TF>();
+            return;
+        }
+        load_raw<TF, V>(c + g.at(x0, y, z), r.c);
+        const Grid<3> gc{Pc};
+        int Zs[2], Ys[2];
+        const int nz = FProl<TF, TC>::split(z, Zs);
+        const int ny = FProl<TF, TC>::split(y, Ys);
+        const int X0 = x0 >> 1;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+                const int idx = a * 2 + bb;
+                const bool use = a < nz && bb < ny && Zs[a] >= 1 && Zs[a] < Pc && Ys[bb] >= 1 && Ys[bb] < Pc;
+                if (use) {
+                    const TC *base = ec + gc.at(X0, Ys[bb], Zs[a]);
+                    PA v[H];
+                    load_row<TC, H>(base, v);
+#pragma unroll
+                    for (int j = 0; j < H; ++j) r.seg[idx][j] = v[j];
+                    r.seg[idx][H] = (X0 + H < Pc) ? (PA)widen(base[H]) : PA(0);
+                    r.ok |= 1 << idx;
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void value(const Raw &r, int x0, int y, int z, acc (&o)[V], acc (&)[V]) const {
+        int Zs[2], Ys[2];
+        const int nz = FProl<TF, TC>::split(z, Zs);
+        const int ny = FProl<TF, TC>::split(y, Ys);
+        const PA wz = nz == 1 ? PA(1) : PA(0.5), wy = ny == 1 ? PA(1) : PA(0.5);
+        PA s[H + 1];
+#pragma unroll
+        for (int j = 0; j <= H; ++j) s[j] = PA(0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+                if (r.ok & (1 << (a * 2 + bb))) {
+                    const PA w = wz * wy;
+#pragma unroll
+                    for (int j = 0; j <= H; ++j) s[j] += w * r.seg[a * 2 + bb][j];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const PA p = (i & 1) ? PA(0.5) * (s[i >> 1] + s[(i >> 1) + 1]) : s[i >> 1];
+            o[i] = round_to<TF>((PA)widen(r.c[i]) + PA(4) * p);
+        }
+        if (x0 == 0) o[0] = acc(0);
+    }
+};
+
+// Damped-Jacobi output; the right-hand side is the field's aux (first
+// pre-smoothing) or a stored array fetched one plane ahead.
+template <class T, int V, bool RHS_AUX, bool WRITE_B> struct PSweep {
+    typedef acc_t<T> A;
+    typedef NoState State;
+    struct Raw {
+        T v[RHS_AUX ? 1 : V];
+    };
+    const T *__restrict__ b;
+    T *__restrict__ out;
+    T *__restrict__ bout;
+    A k;
+    __device__ __forceinline__ void init(State &) const {}
+    __device__ __forceinline__ void finish(State &, double *) const {}
+    __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
+        if constexpr (!RHS_AUX) load_raw<T, V>(b + g.at(x0, y, z), r.v);
+    }
+    __device__ __forceinline__ void emit(const Grid<3> &g, State &, int x0, int y, int z, const A (&c)[V],
+                                         const A (&nb)[V], const A (&aux)[V], const Raw &r) const {
+        T o[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const A bi = RHS_AUX ? aux[i] : (A)widen(r.v[RHS_AUX ? 0 : i]);
+            const A lc = fmaT<A>(A(6), c[i], -nb[i]);
+            o[i] = Store<T>::from_acc(fmaT<A>(k, bi - lc, c[i]));
+        }
+        if (x0 == 0) o[0] = zero_of<T>();
+        const size_t at = g.at(x0, y, z);
+        store_row<T, V>(out + at, o);
+        if constexpr (WRITE_B) {
+            T bo[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) bo[i] = Store<T>::from_acc(aux[i]);
+            if (x0 == 0) bo[0] = zero_of<T>();
+            store_row<T, V>(bout + at, bo);
+        }
+    }
+};
+
+// Refinement update (FP64), R and U rows fetched one plane ahead.
+template <int V> struct POuter {
+    typedef double A;
+    struct State {
+        double ss, mx;
+    };
+    struct Raw {
+        double r[V], u[V];
+    };
+    double *__restrict__ R;
+    double *__restrict__ U;
+    const double *__restrict__ scal;
+    double h2;
+    double *__restrict__ part;
+    __device__ __forceinline__ void init(State &s) const { s.ss = 0.0, s.mx = 0.0; }
+    __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
+        const size_t at = g.at(x0, y, z);
+        load_raw<double, V>(R + at, r.r);
+        load_raw<double, V>(U + at, r.u);
+    }
+    __device__ __forceinline__ void emit(const Grid<3> &g, State &st, int x0, int y, int z, const A (&c)[V],
+                                         const A (&nb)[V], const A (&)[V], const Raw &rw) const {
+        const double a = scal[0];
+        const double ah2 = a * h2;
+        double r[V], u[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const double lc = fmaT<double>(6.0, c[i], -nb[i]);
+            r[i] = fmaT<double>(-a, lc, rw.r[i]);
+            u[i] = fmaT<double>(ah2, c[i], rw.u[i]);
+        }
+        if (x0 == 0) r[0] = 0.0, u[0] = 0.0;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            st.ss += r[i] * r[i];
+            st.mx = nanmax(st.mx, fabs(r[i]));
+        }
+        const size_t at = g.at(x0, y, z);
+        store_row<double, V>(R + at, r);
+        store_row<double, V>(U + at, u);
+    }
+    __device__ __forceinline__ void finish(State &s, double *lds) const {
+        block_reduce(s.ss, s.mx, lds);
+        if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = s.ss;
+            part[2 * blockIdx.x + 1] = s.mx;
+        }
+    }
+};
+
+template <int V, class F, class E>
+__global__ __launch_bounds__(1024) void k_march(F f, E e, int P, int TY, int zc, int ytiles, int xcd) {
+    typedef typename F::acc A;
+    typedef typename F::lds_t LT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    LT *lds = reinterpret_cast<LT *>(smem_raw);
+    __shared__ double red[32];
+    const Grid<3> g{P};
+    const int TXR = P / V;
+    const int G = TY + 2;
+    int blk = blockIdx.x;
+    if (xcd) {
+        const int nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    const int yt = blk % ytiles, zch = blk / ytiles;
+    const int y0 = 1 + yt * TY;
+    const int z0 = 1 + zch * zc;
+    const int z1 = min(z0 + zc, P);
+    const int xc = threadIdx.x % TXR, gi = threadIdx.x / TXR;
+    const int y = y0 - 1 + gi;
+    const bool out_row = gi >= 1 && gi <= TY && y <= P - 1;
+    const int x0 = xc * V;
+    const size_t slot = (size_t)G * P;
+    typename E::State st;
+    e.init(st);
+    typename F::Raw fr;
+    typename E::Raw er;
+    A cm[V], cc[V], cp[V], ac[V], ap[V];
+    f.fetch(g, x0, y, z0 - 1, fr);
+    f.value(fr, x0, y, z0 - 1, cm, ac);
+    f.fetch(g, x0, y, z0, fr);
+    f.value(fr, x0, y, z0, cc, ac);
+    {
+        LT t[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) t[i] = store_as<LT>(cc[i]);
+        store_row<LT, V>(lds + (size_t)gi * P + x0, t);
+    }
+    f.fetch(g, x0, y, z0 + 1, fr);
+    if (out_row) e.fetch(g, x0, y, z0, er);
+    for (int z = z0; z < z1; ++z) {
+        const int it = z - z0;
+        f.value(fr, x0, y, z + 1, cp, ap);
+        if (z + 2 <= z1) f.fetch(g, x0, y, z + 2, fr);
+        const typename E::Raw ecur = er;
+        if (out_row && z + 1 < z1) e.fetch(g, x0, y, z + 1, er);
+        __syncthreads();
+        if (out_row) {
+            const LT *S = lds + (size_t)(it & 1) * slot;
+            const LT *row = S + (size_t)gi * P;
+            A nb[V];
+            const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
+            const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+#pragma unroll
+            for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cc[i - 1] : xl) + (i < V - 1 ? cc[i + 1] : xr);
+            A ym[V], yp[V];
+            load_row<LT, V>(row - P + x0, ym);
+            load_row<LT, V>(row + P + x0, yp);
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                nb[i] += ym[i];
+                nb[i] += yp[i];
+                nb[i] += cm[i];
+                nb[i] += cp[i];
+            }
+            e.emit(g, st, x0, y, z, cc, nb, ac, ecur);
+        }
+        {
+            LT t[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) t[i] = store_as<LT>(cp[i]);
+            store_row<LT, V>(lds + (size_t)((it + 1) & 1) * slot + (size_t)gi * P + x0, t);
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            cm[i] = cc[i];
+            cc[i] = cp[i];
+            ac[i] = ap[i];
+        }
+    }
+    e.finish(st, red);
+}
+
+// ===========================================================================
 // Residual + full-weighting restriction + cast (the residual transfer of
 // Algorithm 1).  A block
 // owns `tyc` coarse rows (3-D) and `zcc` coarse planes.  Its threads first act
@@ -609,6 +948,25 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4 *__restrict__ p, size_t
         p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Bandwidth probe: copy, read-only (sum kept live) or write-only passes over
+// 16-byte lanes; each thread handles `per` consecutive lanes per grid sweep.
+__global__ __launch_bounds__(256) void k_probe(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16,
+                                              int kind, unsigned *__restrict__ sink) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint32_t acc = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+        if (kind == 0) {
+            dst[i] = src[i];
+        } else if (kind == 1) {
+            const uint4 v = src[i];
+            acc ^= v.x ^ v.y ^ v.z ^ v.w;
+        } else {
+            dst[i] = make_uint4((uint32_t)i, 0u, 0u, 0u);
+        }
+    }
+    if (kind == 1 && acc == 0x9e3779b9u) sink[0] = acc;  // keeps the loads live
+}
+
 // ===========================================================================
 // Host launchers.
 // ===========================================================================
@@ -617,6 +975,7 @@ static int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 static int stencil_chunks(int P, int zc) { return ceil_div(P - 1, zc); }
 
 int stencil_blocks(int D, int P, const Shape &s) {
+    if (D == 3 && s.ty > 0) return ceil_div(P - 1, s.ty) * stencil_chunks(P, s.zc);
     const long lines = (long)(D == 3 ? P : 1) * stencil_chunks(P, s.zc);
     return ceil_div((long)(P / s.V) * lines, s.bs);
 }
@@ -645,6 +1004,23 @@ static hipError_t run_stencil(const F &f, const E &e, int P, const Shape &s, hip
     return hipGetLastError();
 }
 
+template <int V, class F, class E>
+static hipError_t run_march(const F &f, const E &e, int P, const Shape &s, hipStream_t st) {
+    const int ytiles = ceil_div(P - 1, s.ty);
+    const int nch = stencil_chunks(P, s.zc);
+    const int threads = (P / V) * (s.ty + 2);
+    const size_t lds = march_lds_bytes(P, s.ty, sizeof(typename F::lds_t));
+    hipLaunchKernelGGL((k_march<V, F, E>), dim3(ytiles * nch), dim3(threads), lds, st, f, e, P, s.ty, s.zc, ytiles,
+                       s.xcd);
+    return hipGetLastError();
+}
+
+#define MG_DISPATCH_V(V, CALL)                        \
+    do {                                              \
+        if ((V) == 8) { constexpr int VV = 8; CALL; } \
+        else { constexpr int VV = 4; CALL; }          \
+    } while (0)
+
 // Dispatch a (D, V) pair to a functor templated on them.
 #define MG_DISPATCH_DV(D, V, CALL)                                   \
     do {                                                             \
@@ -664,6 +1040,17 @@ static hipError_t smooth_first_t(int D, int P, const void *b, const double *r, c
     const A k = (A)(omega / (2.0 * D));
     T *cout = static_cast<T *>(c);
     hipError_t err = hipSuccess;
+    if (D == 3 && s.ty > 0 && two) {
+        if (r) {
+            MG_DISPATCH_V(s.V, err = (run_march<VV>(PJac0Scaled<T, VV>{r, scal, k},
+                                                   PSweep<T, VV, true, true>{nullptr, cout, static_cast<T *>(b_out), k},
+                                                   P, s, st)));
+        } else {
+            MG_DISPATCH_V(s.V, err = (run_march<VV>(PJac0Arr<T, VV>{static_cast<const T *>(b), k},
+                                                   PSweep<T, VV, true, false>{nullptr, cout, nullptr, k}, P, s, st)));
+        }
+        return err;
+    }
     if (r) {
         typedef FScaled<T> R;
         typedef FJac0<T, R> F;
@@ -717,6 +1104,14 @@ static hipError_t sweep_t(int D, int P, const void *b, const void *c, void *c_ou
     const R f{static_cast<const T *>(c)};
     const ESweep<T, R, false> e{rh, static_cast<T *>(c_out), nullptr, (A)(omega / (2.0 * D))};
     hipError_t err = hipSuccess;
+    if (D == 3 && s.ty > 0) {
+        MG_DISPATCH_V(s.V, err = (run_march<VV>(PArr<T, A, VV>{static_cast<const T *>(c)},
+                                               PSweep<T, VV, false, false>{static_cast<const T *>(b),
+                                                                           static_cast<T *>(c_out), nullptr,
+                                                                           (A)(omega / (2.0 * D))},
+                                               P, s, st)));
+        return err;
+    }
     MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
     return err;
 }
@@ -736,6 +1131,15 @@ static hipError_t prolong_t(int D, int P, const void *c, const void *ec, const v
     const F f{static_cast<const TF *>(c), static_cast<const TC *>(ec), P / 2};
     const R rh{static_cast<const TF *>(b)};
     hipError_t err = hipSuccess;
+    if (D == 3 && s.ty > 0 && sweep) {
+        MG_DISPATCH_V(s.V, err = (run_march<VV>(PProl<TF, TC, VV>{static_cast<const TF *>(c),
+                                                                  static_cast<const TC *>(ec), P / 2},
+                                               PSweep<TF, VV, false, false>{static_cast<const TF *>(b),
+                                                                            static_cast<TF *>(c_out), nullptr,
+                                                                            (A)(omega / (2.0 * D))},
+                                               P, s, st)));
+        return err;
+    }
     if (sweep) {
         const ESweep<TF, R, false> e{rh, static_cast<TF *>(c_out), nullptr, (A)(omega / (2.0 * D))};
         MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
@@ -822,6 +1226,11 @@ static hipError_t outer_t(int D, int P, const void *c, double *R, double *U, con
     const FArr<T, double> f{static_cast<const T *>(c)};
     const EOuter e{R, U, scal, h2, part};
     hipError_t err = hipSuccess;
+    if (D == 3 && s.ty > 0) {
+        MG_DISPATCH_V(s.V, err = (run_march<VV>(PArr<T, double, VV>{static_cast<const T *>(c)},
+                                               POuter<VV>{R, U, scal, h2, part}, P, s, st)));
+        return err;
+    }
     MG_DISPATCH_DV(D, s.V, err = (run_stencil<DD, VV>(f, e, P, s, st)));
     return err;
 }
@@ -883,6 +1292,15 @@ hipError_t launch_pack(int D, int sp, int dp, int n, int P, const void *src, voi
 hipError_t launch_unpack(int D, int sp, int dp, int n, int P, const void *src, void *dst, hipStream_t st) {
     MG_DISPATCH_T(sp, return pack_ts<TT>(D, true, dp, n, P, src, dst, st));
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, unsigned *sink,
+                        hipStream_t st) {
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint4 *>(dst),
+                       static_cast<const uint4 *>(src), bytes / 16, kind, sink);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {

@@ -14,9 +14,13 @@ inline size_t prec_bytes(int p) { return p == P_F64 ? 8 : p == P_F32 ? 4 : 2; }
 struct Shape {
     int V;    // elements per thread along x (4 or 8), V <= P
     int zc;   // planes (3-D) or rows (2-D) marched by one thread
-    int bs;   // threads per block (multiple of 64, <= 256)
+    int bs;   // threads per block (multiple of 64, <= 256), register-queue kernel only
     int xcd;  // 1: remap block ids so consecutive tiles share an XCD
+    int ty;   // 3-D only: > 0 selects the LDS-plane kernel with ty output rows per block
 };
+
+// LDS bytes of the LDS-plane kernel for a level of storage size sb bytes.
+inline size_t march_lds_bytes(int P, int ty, size_t sb) { return 2 * (size_t)(ty + 2) * P * sb; }
 
 // Launch shape of the residual + restriction kernel.
 struct RShape {
@@ -71,5 +75,8 @@ hipError_t launch_pack(int D, int src_prec, int dst_prec, int n, int P, const vo
 hipError_t launch_unpack(int D, int src_prec, int dst_prec, int n, int P, const void *src, void *dst,
                          hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+// Copy (kind 0), read (1) or write (2) `bytes` with 16-byte lanes.
+hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, unsigned *sink,
+                        hipStream_t st);
 
 }  // namespace mg

@@ -24,7 +24,8 @@ BUF_RHS, BUF_COR, BUF_RES, BUF_SOL = 0, 1, 2, 3
 STAGE_SMOOTH_FIRST, STAGE_SWEEP, STAGE_RESTRICT, STAGE_PROLONG_SWEEP, STAGE_COARSE = 0, 1, 2, 3, 4
 EXPORTS = ("mg_default_options", "mg_setup", "mg_workspace_size", "mg_bind_workspace", "mg_vcycle", "ir_solve",
            "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_write", "mg_level_read", "mg_stage",
-           "mg_levels", "mg_level_n", "mg_profile_step")
+           "mg_levels", "mg_level_n", "mg_profile_step", "mg_set_shape", "mg_get_shape", "mg_bandwidth_probe")
+SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE = 0, 1, 2
 
 
 class MgError(RuntimeError):
@@ -73,6 +74,9 @@ def load() -> ctypes.CDLL:
     lib.mg_level_n.argtypes = [H, i, ctypes.POINTER(ctypes.c_int)]
     lib.mg_profile_step.argtypes = [H, vp, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_char_p),
                                     ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int)]
+    lib.mg_set_shape.argtypes = [H, i, i, ctypes.POINTER(ctypes.c_int), i]
+    lib.mg_get_shape.argtypes = [H, i, i, ctypes.POINTER(ctypes.c_int), i]
+    lib.mg_bandwidth_probe.argtypes = [vp, vp, ctypes.c_size_t, i, i, vp]
     for f in EXPORTS:
         if f not in ("mg_default_options", "mg_status_string", "mg_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -218,6 +222,15 @@ class Solver:
     def stage(self, stage: int, level: int, stream=None):
         _check(self.lib.mg_stage(self._h, stage, level, _stream_ptr(stream)), "mg_stage")
 
+    def set_shape(self, level: int, kind: int, params):
+        arr = (ctypes.c_int * len(params))(*params)
+        _check(self.lib.mg_set_shape(self._h, level, kind, arr, len(params)), "mg_set_shape")
+
+    def get_shape(self, level: int, kind: int):
+        arr = (ctypes.c_int * 5)()
+        _check(self.lib.mg_get_shape(self._h, level, kind, arr, 5), "mg_get_shape")
+        return list(arr[: 3 if kind == SHAPE_RESTRICT else 5])
+
     def profile_step(self, stream=None, cap: int = 512):
         names = (ctypes.c_char_p * cap)()
         ms = (ctypes.c_double * cap)()
@@ -227,3 +240,10 @@ class Solver:
         _check(self.lib.mg_profile_step(self._h, _stream_ptr(stream), cap, ctypes.byref(cnt), names, ms, by, lv),
                "mg_profile_step")
         return [(names[i].decode(), lv[i], ms[i], by[i]) for i in range(min(cnt.value, cap))]
+
+
+def bandwidth_probe(dst: torch.Tensor, src: torch.Tensor, kind: int, blocks: int = 4096, stream=None):
+    """One copy (0) / read (1) / write (2) pass over src.numel() bytes' worth of 16-byte lanes."""
+    nbytes = src.numel() * src.element_size()
+    _check(load().mg_bandwidth_probe(_dptr(dst), _dptr(src), nbytes, kind, blocks, _stream_ptr(stream)),
+           "mg_bandwidth_probe")

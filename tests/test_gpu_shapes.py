@@ -1,0 +1,66 @@
+"""Launch-shape invariance (GPU): every launch shape of every kernel forms the
+same roundings, so V-cycles and refinement iterates must agree bitwise across
+shapes.  A race in an LDS-staged kernel or a tiling error shows up here."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2007_07539_amd import mgir
+from paper_2007_07539_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+STENCIL = [[V, zc, bs, xcd, ty] for V, zc, bs, xcd, ty in
+           [(8, 1, 256, 0, 0), (4, 3, 64, 1, 0), (8, 7, 128, 1, 0), (8, 64, 256, 1, 0),
+            (8, 1, 256, 0, 1), (4, 5, 256, 1, 2), (8, 8, 256, 1, 6), (8, 3, 256, 0, 14), (4, 16, 256, 1, 3)]]
+RESTRICT = [[4, 1, 1], [8, 2, 3], [8, 7, 5], [4, 3, 64]]
+
+
+def _apply(s, kind, shape):
+    applied = 0
+    for lvl in range(s.nlevels - 1):
+        if kind == mgir.SHAPE_UPDATE and lvl != 0:
+            continue
+        try:
+            s.set_shape(lvl, kind, shape)
+            applied += 1
+        except mgir.MgError:
+            pass
+    return applied
+
+
+@pytest.mark.parametrize("name,n", [("f16", 63), ("f64", 63), ("bf16", 31), ("f32", 31), ("hsd", 127)])
+def test_shapes_bitwise(dev, name, n):
+    prec = W.precision_map(name, W.levels_for(n))
+    b64 = torch.from_numpy(W.uniform_rhs(3, n, seed=5)).to(dev)
+    bl = b64.to(mgir.TORCH_DTYPE[prec[0]])
+    s = mgir.Solver(3, n, prec)
+    defaults = {k: [s.get_shape(l, k) for l in range(s.nlevels - 1) if k != mgir.SHAPE_UPDATE or l == 0]
+                for k in (mgir.SHAPE_STENCIL, mgir.SHAPE_RESTRICT, mgir.SHAPE_UPDATE)}
+    c_ref = s.vcycle(bl).clone()
+    u_ref, r_ref = s.solve(b64)
+    u_ref = u_ref.clone()
+    for kind, shapes in ((mgir.SHAPE_STENCIL, STENCIL), (mgir.SHAPE_RESTRICT, RESTRICT),
+                         (mgir.SHAPE_UPDATE, STENCIL)):
+        for shape in shapes:
+            print(f"{name} n={n} kind={kind} shape={shape}", flush=True)
+            if not _apply(s, kind, shape):
+                continue
+            if kind != mgir.SHAPE_UPDATE:
+                c = s.vcycle(bl)
+                assert torch.equal(c, c_ref), (kind, shape)
+            u, r = s.solve(b64)
+            assert r.iterations == r_ref.iterations, (kind, shape)
+            assert torch.equal(u, u_ref), (kind, shape)
+        for lvl, sh in enumerate(defaults[kind]):
+            s.set_shape(lvl, kind, sh)
