@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle IR iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only run the mixed solve (for rocprofv3)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
@@ -88,7 +89,11 @@ def main():
     u = torch.zeros_like(bt)
 
     log("[bench] setup mixed solver")
-    mixed = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=True, device=dev)
+    tune = not args.no_autotune
+    mixed = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=True, device=dev, autotune=tune)
+    shapes_mixed = {"stencil": mixed.get_shape(0, mgir.SHAPE_STENCIL),
+                    "restrict": mixed.get_shape(0, mgir.SHAPE_RESTRICT),
+                    "update": mixed.get_shape(0, mgir.SHAPE_UPDATE)}
     ms_mixed, res_mixed = timed_solves(mixed, bt, u, args.steps, args.warmup, torch)
     log(f"[bench] mixed: {ms_mixed:.2f} ms/solve, {res_mixed[-1].iterations} it, rel {res_mixed[-1].rel_residual:.2e}")
     prof = mixed.profile_step()
@@ -99,7 +104,7 @@ def main():
     fp64 = None
     if not args.profile_only:
         log("[bench] setup FP64 solver")
-        fp64 = mgir.Solver(3, n, W.precision_map("f64", L), residual_scaling=False, device=dev)
+        fp64 = mgir.Solver(3, n, W.precision_map("f64", L), residual_scaling=False, device=dev, autotune=tune)
         ms64, res64 = timed_solves(fp64, bt, u, args.steps, args.warmup, torch)
         log(f"[bench] fp64: {ms64:.2f} ms/solve, {res64[-1].iterations} it, rel {res64[-1].rel_residual:.2e}")
         kt64 = kernel_table(fp64.profile_step())
@@ -133,6 +138,8 @@ def main():
                      "avg_ms": dom["avg_ms"], "bytes_per_launch": dom["bytes"] / dom["launches"]},
         "kernels_finest": {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1),
                                "launches": v["launches"]} for k, v in kt.items()},
+        "launch_shapes_finest": shapes_mixed,
+        "autotune": tune,
     }
     if not args.profile_only:
         out["fp64_value"] = N / (ms64 * 1e-3)

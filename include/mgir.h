@@ -189,7 +189,9 @@ typedef enum {
                                ty (3-D: 0 = register-queue kernel, > 0 = LDS-plane
                                kernel with ty output rows per block)} */
     MG_SHAPE_RESTRICT = 1,  /* residual + restriction: {V (4|8), tyc (coarse rows per
-                               block, 3-D), zcc (coarse planes per block)} */
+                               block, 3-D), zcc (coarse planes per block), pipe (3-D:
+                               1 = correction plane staged in LDS, next plane
+                               prefetched)} */
     MG_SHAPE_UPDATE = 2     /* level 0 only: the FP64 refinement update, same five
                                values as MG_SHAPE_STENCIL */
 } mg_shape_kind_t;

@@ -125,6 +125,19 @@ RShape pick_rshape(int D, int P, int pf) {
     RShape r;
     // eight FP64 values per thread exceed the register budget of a 1024-thread block
     r.V = (P >= 8 && pf != P_F64) ? 8 : 4;
+    r.pipe = 0;
+    if (D == 3 && P >= 16) {
+        const int TXR = P / r.V, Pc = P / 2;
+        for (int tyc = std::min(7, Pc - 1); tyc >= 1; --tyc) {
+            RShape c{r.V, tyc, 1, 1};
+            if ((2 * tyc + 3) * TXR <= 1024 && restrict_lds_bytes(D, P, pf, c) <= 65536) {
+                const int ytiles = (Pc - 1 + tyc - 1) / tyc;
+                const int nzc = std::max(1, (1024 + ytiles - 1) / ytiles);
+                c.zcc = std::max(1, (Pc - 1 + nzc - 1) / nzc);
+                return c;
+            }
+        }
+    }
     const int TXR = P / r.V, Pc = P / 2;
     const size_t acc = pf == P_F64 ? 8 : 4;
     if (D == 3) {
@@ -332,6 +345,128 @@ mg_status_t need_ws(mg_ctx *h) {
 
 int level_prec_code(int p) { return p; }
 
+
+// ---- autotuner ------------------------------------------------------------
+// Times candidate launch shapes of each level with HIP events on the caller's
+// stream and keeps the fastest.  Every shape forms the same roundings, so the
+// choice changes speed only.  Workspace contents are scratch at this point.
+bool stencil_ok(const mg_ctx *h, const LevelPlan &L, const Shape &s) {
+    if ((s.V != 4 && s.V != 8) || s.V > L.P || s.zc < 1 || s.zc > L.P - 1) return false;
+    if (s.ty > 0) {
+        if (h->dim != 3) return false;
+        if ((L.P / s.V) * (s.ty + 2) > 1024 || march_lds_bytes(L.P, s.ty, prec_bytes(L.prec)) > 65536) return false;
+        if (s.ty > L.P - 1) return false;
+    }
+    return true;
+}
+
+bool restrict_ok(const mg_ctx *h, const LevelPlan &L, const RShape &r) {
+    const int Pc = L.P / 2;
+    if ((r.V != 4 && r.V != 8) || r.V > L.P || r.zcc < 1 || r.zcc > std::max(1, Pc - 1)) return false;
+    if (h->dim == 2 && (r.tyc != 1 || r.pipe)) return false;
+    if (r.pipe != 0 && r.pipe != 1) return false;
+    if (r.tyc < 1 || r.tyc > std::max(1, Pc - 1)) return false;
+    const int G = h->dim == 3 ? 2 * r.tyc + 1 + 2 * r.pipe : 1;
+    if (G * (L.P / r.V) > 1024 || restrict_lds_bytes(h->dim, L.P, L.prec, r) > 65536) return false;
+    if (L.prec == P_F64 && r.V == 8 && h->dim == 3) return false;  // spills registers
+    return true;
+}
+
+template <class F> float time_ms(hipStream_t st, F &&fn, int reps) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    if (fn() != hipSuccess) return 1e30f;
+    float best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(a, st);
+        if (fn() != hipSuccess) best = 1e30f;
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, a, b);
+        best = std::min(best, t);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+}
+
+std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool update) {
+    std::vector<Shape> out;
+    const int tys[] = {0, 2, 4, 6, 10, 14};
+    const int zcs[] = {2, 4, 8, 16, 32, 64};
+    for (int V : {4, 8})
+        for (int ty : tys)
+            for (int zc : zcs) {
+                Shape s{V, zc, 256, 1, ty};
+                if (ty == 0 && h->dim == 3 && zc < 8) continue;
+                if (update && V == 8 && ty > 0) continue;  // FP64 rows spill at V = 8
+                if (L.prec == P_F64 && V == 8 && ty > 0) continue;
+                if (stencil_ok(h, L, s)) out.push_back(s);
+            }
+    return out;
+}
+
+mg_status_t autotune(mg_ctx *h, hipStream_t st) {
+    const int D = h->dim;
+    for (int l = 0; l + 1 < h->nl; ++l) {
+        LevelPlan &L = h->lv[l];
+        if (L.P < 8) continue;
+        // smoothing family: first pre-smoothing + sweep + prolongation/sweep
+        float best = 1e30f;
+        Shape bs = L.sh;
+        for (const Shape &s : stencil_candidates(h, L, false)) {
+            L.sh = s;
+            const float t = time_ms(st, [&]() -> hipError_t {
+                hipError_t e = launch_smooth_first(D, L.prec, L.P, bbuf(h, l), nullptr, nullptr, nullptr,
+                                                   cbuf(h, l, 0), h->opt.omega, true, s, st);
+                if (e == hipSuccess)
+                    e = launch_sweep(D, L.prec, L.P, bbuf(h, l), cbuf(h, l, 0), cbuf(h, l, 1), h->opt.omega, s, st);
+                if (e == hipSuccess)
+                    e = launch_prolong(D, L.prec, h->lv[l + 1].prec, L.P, cbuf(h, l, 1), cbuf(h, l + 1, 0),
+                                       bbuf(h, l), cbuf(h, l, 0), h->opt.omega, true, s, st);
+                return e;
+            }, 3);
+            if (t < best) best = t, bs = s;
+        }
+        L.sh = bs;
+        // residual + restriction
+        best = 1e30f;
+        RShape br = L.rsh;
+        for (int V : {4, 8})
+            for (int tyc : {1, 2, 3, 4, 5, 7})
+                for (int zcc : {2, 4, 8, 16, 32})
+                    for (int pipe : {0, 1}) {
+                    RShape r{V, tyc, zcc, pipe};
+                    if (!restrict_ok(h, L, r)) continue;
+                    const float t = time_ms(st, [&]() {
+                        return launch_restrict(D, L.prec, h->lv[l + 1].prec, L.P, bbuf(h, l), cbuf(h, l, 0),
+                                               bbuf(h, l + 1), r, st);
+                    }, 3);
+                    if (t < best) best = t, br = r;
+                }
+        L.rsh = br;
+        if (l == 0) {
+            best = 1e30f;
+            Shape bo = L.osh;
+            const double hh = 1.0 / (double)(L.n + 1);
+            for (const Shape &s : stencil_candidates(h, L, true)) {
+                if (stencil_blocks(D, L.P, s) > h->max_parts) continue;
+                const float t = time_ms(st, [&]() {
+                    return launch_outer_update(D, L.prec, L.P, cbuf(h, 0, 0), Rbuf(h), Ubuf(h), scal(h), hh * hh,
+                                               part(h), s, st);
+                }, 3);
+                if (t < best) best = t, bo = s;
+            }
+            L.osh = bo;
+            h->outer_parts = stencil_blocks(D, L.P, bo);
+        }
+    }
+    HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return MG_OK;
+}
 }  // namespace
 
 // ============================================================================
@@ -465,6 +600,10 @@ mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *st
     HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int l = 0; l < h->nl; ++l) h->cur[l] = 0;
+    if (h->opt.autotune) {
+        mg_status_t s = autotune(h, st);
+        if (s != MG_OK) return s;
+    }
     return MG_OK;
 }
 
@@ -717,15 +856,11 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
             L.sh = s;
         }
     } else if (kind == MG_SHAPE_RESTRICT) {
-        if (np != 3) return fail(MG_ERR_ARG, "restriction shape takes 3 values {V, tyc, zcc}");
-        RShape r{p[0], p[1], p[2]};
-        const int Pc = L.P / 2;
-        if ((r.V != 4 && r.V != 8) || r.V > L.P) return fail(MG_ERR_ARG, "V must be 4 or 8 and <= P = %d", L.P);
-        if (r.tyc < 1 || r.tyc > std::max(1, Pc - 1) || (D == 2 && r.tyc != 1)) return fail(MG_ERR_ARG, "tyc out of range");
-        if (r.zcc < 1 || r.zcc > std::max(1, Pc - 1)) return fail(MG_ERR_ARG, "zcc out of range");
-        const int G = D == 3 ? 2 * r.tyc + 1 : 1;
-        if (G * (L.P / r.V) > 1024) return fail(MG_ERR_ARG, "restriction block exceeds 1024 threads");
-        if (restrict_lds_bytes(D, L.P, L.prec, r) > 65536) return fail(MG_ERR_ARG, "restriction LDS exceeds 64 KiB");
+        if (np != 4) return fail(MG_ERR_ARG, "restriction shape takes 4 values {V, tyc, zcc, pipe}");
+        RShape r{p[0], p[1], p[2], p[3]};
+        if (!restrict_ok(h, L, r))
+            return fail(MG_ERR_ARG, "restriction shape {%d, %d, %d, %d} is not valid on level %d", r.V, r.tyc,
+                        r.zcc, r.pipe, level);
         L.rsh = r;
     } else {
         return fail(MG_ERR_ARG, "unknown shape kind %d", kind);
@@ -741,8 +876,8 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
     if ((kind == MG_SHAPE_STENCIL || (kind == MG_SHAPE_UPDATE && level == 0)) && np >= 5) {
         const Shape &S = kind == MG_SHAPE_STENCIL ? L.sh : L.osh;
         p[0] = S.V, p[1] = S.zc, p[2] = S.bs, p[3] = S.xcd, p[4] = S.ty;
-    } else if (kind == MG_SHAPE_RESTRICT && np >= 3) {
-        p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc;
+    } else if (kind == MG_SHAPE_RESTRICT && np >= 4) {
+        p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc, p[3] = L.rsh.pipe;
     } else {
         return fail(MG_ERR_ARG, "bad kind or too few values");
     }

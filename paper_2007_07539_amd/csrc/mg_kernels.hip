@@ -848,6 +848,158 @@ __global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, con
     }
 }
 
+// ===========================================================================
+// Pipelined residual + restriction.  A block owns tyc coarse rows and zcc
+// coarse planes.  Its threads form G = 2 tyc + 3 fine row groups: the fine
+// rows 2Y0-2 .. 2Y0+2tyc whose correction values the residual rows
+// 2Y0-1 .. 2Y0+2tyc-1 need.  Per fine plane the correction plane goes through a
+// double-buffered LDS slot (as in k_march, with the next plane prefetched),
+// every residual row group writes b - L c into a double-buffered LDS row
+// buffer, and after the next barrier the first tyc * P/V threads combine three
+// residual rows with the x and y weights and accumulate the z weights of the
+// coarse plane in registers.  One barrier per fine plane.
+// ===========================================================================
+template <int V, class TF, class TC>
+__global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, const TF *__restrict__ c,
+                                                    TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles,
+                                                    int xcd) {
+    typedef acc_t<TF> A;
+    constexpr int VC = V / 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int G = 2 * tyc + 3, R = 2 * tyc + 1;
+    TF *cs = reinterpret_cast<TF *>(smem_raw);                                  // [2][G][P]
+    A *rs = reinterpret_cast<A *>(smem_raw + 2 * (size_t)G * P * sizeof(TF));   // [2][R][P]
+    const int Pc = P >> 1;
+    const int TXR = P / V;
+    const Grid<3> g{P};
+    const Grid<3> gc{Pc};
+    int blk = blockIdx.x;
+    if (xcd) {
+        const int nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    const int ytile = blk % ytiles, zch = blk / ytiles;
+    const int Y0 = 1 + ytile * tyc;
+    const int Z0 = 1 + zch * zcc;
+    const int Z1 = min(Z0 + zcc, Pc);
+    const int tid = threadIdx.x;
+    const int xc = tid % TXR, gi = tid / TXR;
+    const int y = 2 * Y0 - 2 + gi;
+    const bool res_row = gi >= 1 && gi <= G - 2 && y <= P - 1;
+    const int x0 = xc * V;
+    const bool coarse = gi < tyc && Y0 + gi < Pc;
+    const int Yc = Y0 + gi;
+    const int X0 = xc * VC;
+    const PArr<TF, A, V> f{c};
+    const size_t cslot = (size_t)G * P, rslot = (size_t)R * P;
+    const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
+    typename PArr<TF, A, V>::Raw fr;
+    TF braw[V], bnext[V];
+    A cm[V], cc[V], cp[V], dummy[V];
+    A acc[VC];
+#pragma unroll
+    for (int j = 0; j < VC; ++j) acc[j] = A(0);
+    f.fetch(g, x0, y, zf0 - 1, fr);
+    f.value(fr, x0, y, zf0 - 1, cm, dummy);
+    f.fetch(g, x0, y, zf0, fr);
+    f.value(fr, x0, y, zf0, cc, dummy);
+    {
+        TF t[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) t[i] = store_as<TF>(cc[i]);
+        store_row<TF, V>(cs + (size_t)gi * P + x0, t);
+    }
+    f.fetch(g, x0, y, zf0 + 1, fr);
+    if (res_row) load_raw<TF, V>(b + g.at(x0, y, zf0), bnext);
+
+    // coarse step: fold the residual rows of fine plane zf (in slot s) into acc
+    auto coarse_step = [&](int zf, int s) {
+        const A *rb = rs + (size_t)s * rslot;
+        const int j = zf - zf0;
+        const bool last_of_z = j > 0 && (j & 1) == 0;  // zf = 2Z + 1
+        TC out[VC];
+#pragma unroll
+        for (int jx = 0; jx < VC; ++jx) {
+            const int X = X0 + jx;
+            A q = A(0);
+            if (X >= 1) {
+                A rsum[3];
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) {
+                    const A *row = rb + (size_t)(2 * gi + oy) * P;
+                    rsum[oy] = A(0.25) * (row[2 * X - 1] + row[2 * X + 1]) + A(0.5) * row[2 * X];
+                }
+                q = A(0.25) * (rsum[0] + rsum[2]) + A(0.5) * rsum[1];
+            }
+            if (j == 0) {
+                acc[jx] = A(0.25) * q;
+            } else if (!last_of_z) {
+                acc[jx] += A(0.5) * q;
+            } else {
+                out[jx] = store_as<TC>(acc[jx] + A(0.25) * q);
+                acc[jx] = A(0.25) * q;
+            }
+        }
+        if (last_of_z) {
+            if (X0 == 0) out[0] = store_as<TC>(A(0));
+            store_row<TC, VC>(bc + gc.at(X0, Yc, (zf - 1) >> 1), out);
+        }
+    };
+
+    for (int zf = zf0; zf <= zf1; ++zf) {
+        const int it = zf - zf0;
+        f.value(fr, x0, y, zf + 1, cp, dummy);
+        if (zf + 2 <= zf1 + 1) f.fetch(g, x0, y, zf + 2, fr);
+#pragma unroll
+        for (int i = 0; i < V; ++i) braw[i] = bnext[i];
+        if (res_row && zf + 1 <= zf1) load_raw<TF, V>(b + g.at(x0, y, zf + 1), bnext);
+        __syncthreads();
+        if (coarse && it > 0) coarse_step(zf - 1, (it - 1) & 1);
+        if (res_row) {
+            const TF *row = cs + (size_t)(it & 1) * cslot + (size_t)gi * P;
+            A nb[V];
+            const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
+            const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+#pragma unroll
+            for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cc[i - 1] : xl) + (i < V - 1 ? cc[i + 1] : xr);
+            A ym[V], yp[V];
+            load_row<TF, V>(row - P + x0, ym);
+            load_row<TF, V>(row + P + x0, yp);
+            A r[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                nb[i] += ym[i];
+                nb[i] += yp[i];
+                nb[i] += cm[i];
+                nb[i] += cp[i];
+                r[i] = (A)widen(braw[i]) - fmaT<A>(A(6), cc[i], -nb[i]);
+            }
+            if (x0 == 0) r[0] = A(0);
+            A *dst = rs + (size_t)(it & 1) * rslot + (size_t)(gi - 1) * P + x0;
+#pragma unroll
+            for (int i = 0; i < V; ++i) dst[i] = r[i];
+        } else if (gi >= 1 && gi <= G - 2) {
+            // residual rows past the last interior row are zero
+            A *dst = rs + (size_t)(it & 1) * rslot + (size_t)(gi - 1) * P + x0;
+#pragma unroll
+            for (int i = 0; i < V; ++i) dst[i] = A(0);
+        }
+        {
+            TF t[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) t[i] = store_as<TF>(cp[i]);
+            store_row<TF, V>(cs + (size_t)((it + 1) & 1) * cslot + (size_t)gi * P + x0, t);
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            cm[i] = cc[i];
+            cc[i] = cp[i];
+        }
+    }
+    __syncthreads();
+    if (coarse) coarse_step(zf1, (zf1 - zf0) & 1);
+}
+
 // Base level: the single interior point of an n = 1 grid (P = 2) at (1,1[,1]).
 template <int D, class T> __global__ void k_coarse(const T *__restrict__ b, T *__restrict__ c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -857,41 +1009,49 @@ template <int D, class T> __global__ void k_coarse(const T *__restrict__ b, T *_
     }
 }
 
-// r = b - A U with the FP64 operator (2D u - nb) / h^2, thread per dense point.
+// r = b - A U with the FP64 operator (2D u - nb) / h^2.  One wave per grid row
+// (grid-stride over rows), consecutive lanes on consecutive x, so both the
+// dense arrays and the padded ones are read and written coalesced.
 template <int D>
-__global__ __launch_bounds__(256) void k_resid_flat(const double *__restrict__ b, const double *__restrict__ U,
+__global__ __launch_bounds__(256) void k_resid_rows(const double *__restrict__ b, const double *__restrict__ U,
                                                     double *__restrict__ R, double *__restrict__ uout, int n, int P,
-                                                    double inv_h2, long N, double *__restrict__ part) {
+                                                    double inv_h2, double *__restrict__ part) {
     __shared__ double red[8];
     const Grid<D> g{P};
     const size_t plane = D == 3 ? (size_t)P * P : (size_t)P;
+    const long rows = D == 3 ? (long)n * n : (long)n;
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
     double ss = 0.0, mx = 0.0;
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
-        const int x = (int)(idx % n) + 1;
-        const long rest = idx / n;
+    for (long row = wave; row < rows; row += nwaves) {
         int y = 0, z;
         if (D == 3) {
-            y = (int)(rest % n) + 1;
-            z = (int)(rest / n) + 1;
+            y = (int)(row % n) + 1;
+            z = (int)(row / n) + 1;
         } else {
-            z = (int)rest + 1;
+            z = (int)row + 1;
         }
-        const size_t p = g.at(x, y, z);
-        double r = b[idx];
-        if (U) {
-            double nb = U[p - 1] + U[p + 1];
-            if (D == 3) {
-                nb += U[p - P];
-                nb += U[p + P];
+        const size_t dbase = (size_t)row * n;
+        const size_t pbase = g.at(1, y, z);
+        for (int x = lane; x < n; x += 64) {
+            const size_t p = pbase + x;
+            double r = b[dbase + x];
+            if (U) {
+                double nb = U[p - 1] + U[p + 1];
+                if (D == 3) {
+                    nb += U[p - P];
+                    nb += U[p + P];
+                }
+                nb += U[p - plane];
+                nb += U[p + plane];
+                r = r - (double(2 * D) * U[p] - nb) * inv_h2;
+                if (uout) uout[dbase + x] = U[p];
             }
-            nb += U[p - plane];
-            nb += U[p + plane];
-            r = r - (double(2 * D) * U[p] - nb) * inv_h2;
-            if (uout) uout[idx] = U[p];
+            if (R) R[p] = r;
+            ss += r * r;
+            mx = nanmax(mx, fabs(r));
         }
-        if (R) R[p] = r;
-        ss += r * r;
-        mx = nanmax(mx, fabs(r));
     }
     block_reduce(ss, mx, red);
     if (threadIdx.x == 0) {
@@ -980,6 +1140,12 @@ int stencil_blocks(int D, int P, const Shape &s) {
     return ceil_div((long)(P / s.V) * lines, s.bs);
 }
 
+template <class T> static int prec_of();
+template <> int prec_of<double>() { return P_F64; }
+template <> int prec_of<float>() { return P_F32; }
+template <> int prec_of<f16>() { return P_F16; }
+template <> int prec_of<bf16>() { return P_BF16; }
+
 int restrict_blocks(int D, int P, const RShape &s) {
     const int Pc = P / 2;
     const int ytiles = D == 3 ? ceil_div(Pc - 1, s.tyc) : 1;
@@ -987,8 +1153,11 @@ int restrict_blocks(int D, int P, const RShape &s) {
 }
 
 size_t restrict_lds_bytes(int D, int P, int pf, const RShape &s) {
+    const size_t acc = pf == P_F64 ? 8 : 4;
+    if (D == 3 && s.pipe)
+        return 2 * (size_t)(2 * s.tyc + 3) * P * prec_bytes(pf) + 2 * (size_t)(2 * s.tyc + 1) * P * acc;
     const int G = D == 3 ? 2 * s.tyc + 1 : 1;
-    return 2 * (size_t)G * P * (pf == P_F64 ? 8 : 4);
+    return 2 * (size_t)G * P * acc;
 }
 
 int flat_blocks(long N) {
@@ -1171,6 +1340,16 @@ hipError_t launch_prolong(int D, int pf, int pc, int P, const void *c, const voi
 template <int D, int V, class TF, class TC>
 static hipError_t restrict_run(int P, const void *b, const void *c, void *bc, const RShape &s, hipStream_t st) {
     const int Pc = P / 2;
+    if (D == 3 && s.pipe) {
+        const int ytiles = ceil_div(Pc - 1, s.tyc);
+        const int blocks = ytiles * ceil_div(Pc - 1, s.zcc);
+        const int threads = (2 * s.tyc + 3) * (P / V);
+        const size_t lds = restrict_lds_bytes(D, P, prec_of<TF>(), s);
+        hipLaunchKernelGGL((k_restrict2<V, TF, TC>), dim3(blocks), dim3(threads), lds, st,
+                           static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P, s.tyc,
+                           s.zcc, ytiles, 1);
+        return hipGetLastError();
+    }
     const int ytiles = D == 3 ? ceil_div(Pc - 1, s.tyc) : 1;
     const int blocks = ytiles * ceil_div(Pc - 1, s.zcc);
     const int G = D == 3 ? 2 * s.tyc + 1 : 1;
@@ -1246,9 +1425,9 @@ hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double 
     const long N = D == 3 ? (long)n * n * n : (long)n * n;
     const int blocks = flat_blocks(N);
     if (D == 3)
-        hipLaunchKernelGGL(k_resid_flat<3>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, N, part);
+        hipLaunchKernelGGL(k_resid_rows<3>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, part);
     else
-        hipLaunchKernelGGL(k_resid_flat<2>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, N, part);
+        hipLaunchKernelGGL(k_resid_rows<2>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, part);
     return hipGetLastError();
 }
 

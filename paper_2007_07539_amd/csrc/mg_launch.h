@@ -24,9 +24,10 @@ inline size_t march_lds_bytes(int P, int ty, size_t sb) { return 2 * (size_t)(ty
 
 // Launch shape of the residual + restriction kernel.
 struct RShape {
-    int V;    // fine elements per thread along x (4 or 8); the coarse side uses V/2
-    int tyc;  // coarse rows per block (3-D)
-    int zcc;  // coarse planes (3-D) or rows (2-D) per block
+    int V;     // fine elements per thread along x (4 or 8); the coarse side uses V/2
+    int tyc;   // coarse rows per block (3-D)
+    int zcc;   // coarse planes (3-D) or rows (2-D) per block
+    int pipe;  // 3-D only: 1 selects the pipelined kernel (correction plane in LDS)
 };
 
 // Elements of a padded level array: (P + 2) planes of P*P (3-D) or (P + 2)

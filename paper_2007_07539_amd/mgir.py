@@ -229,7 +229,7 @@ class Solver:
     def get_shape(self, level: int, kind: int):
         arr = (ctypes.c_int * 5)()
         _check(self.lib.mg_get_shape(self._h, level, kind, arr, 5), "mg_get_shape")
-        return list(arr[: 3 if kind == SHAPE_RESTRICT else 5])
+        return list(arr[: 4 if kind == SHAPE_RESTRICT else 5])
 
     def profile_step(self, stream=None, cap: int = 512):
         names = (ctypes.c_char_p * cap)()

@@ -23,7 +23,8 @@ def dev():
 STENCIL = [[V, zc, bs, xcd, ty] for V, zc, bs, xcd, ty in
            [(8, 1, 256, 0, 0), (4, 3, 64, 1, 0), (8, 7, 128, 1, 0), (8, 64, 256, 1, 0),
             (8, 1, 256, 0, 1), (4, 5, 256, 1, 2), (8, 8, 256, 1, 6), (8, 3, 256, 0, 14), (4, 16, 256, 1, 3)]]
-RESTRICT = [[4, 1, 1], [8, 2, 3], [8, 7, 5], [4, 3, 64]]
+RESTRICT = [[4, 1, 1, 0], [8, 2, 3, 0], [8, 7, 5, 0], [4, 3, 64, 0], [8, 1, 1, 1], [4, 2, 7, 1], [8, 4, 16, 1],
+            [8, 6, 3, 1]]
 
 
 def _apply(s, kind, shape):
@@ -64,3 +65,13 @@ def test_shapes_bitwise(dev, name, n):
             assert torch.equal(u, u_ref), (kind, shape)
         for lvl, sh in enumerate(defaults[kind]):
             s.set_shape(lvl, kind, sh)
+
+
+def test_autotuned_solver_matches_default(dev):
+    n = 127
+    prec = W.precision_map("f16", W.levels_for(n))
+    b = torch.from_numpy(W.uniform_rhs(3, n, seed=6)).to(dev)
+    u0, r0 = mgir.Solver(3, n, prec).solve(b)
+    st = mgir.Solver(3, n, prec, autotune=True)
+    u1, r1 = st.solve(b)
+    assert r0.iterations == r1.iterations and torch.equal(u0, u1)
