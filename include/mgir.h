@@ -191,7 +191,8 @@ typedef enum {
     MG_SHAPE_RESTRICT = 1,  /* residual + restriction: {V (4|8), tyc (coarse rows per
                                block, 3-D), zcc (coarse planes per block), pipe (3-D:
                                1 = correction plane staged in LDS, next plane
-                               prefetched)} */
+                               prefetched; 2 = as 1 with the x weights applied in
+                               the fine threads, needs P/V <= 64)} */
     MG_SHAPE_UPDATE = 2     /* level 0 only: the FP64 refinement update, same five
                                values as MG_SHAPE_STENCIL */
 } mg_shape_kind_t;

@@ -128,8 +128,9 @@ RShape pick_rshape(int D, int P, int pf) {
     r.pipe = 0;
     if (D == 3 && P >= 16) {
         const int TXR = P / r.V, Pc = P / 2;
+        const int pipe = TXR <= 64 ? 2 : 1;
         for (int tyc = std::min(7, Pc - 1); tyc >= 1; --tyc) {
-            RShape c{r.V, tyc, 1, 1};
+            RShape c{r.V, tyc, 1, pipe};
             if ((2 * tyc + 3) * TXR <= 1024 && restrict_lds_bytes(D, P, pf, c) <= 65536) {
                 const int ytiles = (Pc - 1 + tyc - 1) / tyc;
                 const int nzc = std::max(1, (1024 + ytiles - 1) / ytiles);
@@ -364,7 +365,8 @@ bool restrict_ok(const mg_ctx *h, const LevelPlan &L, const RShape &r) {
     const int Pc = L.P / 2;
     if ((r.V != 4 && r.V != 8) || r.V > L.P || r.zcc < 1 || r.zcc > std::max(1, Pc - 1)) return false;
     if (h->dim == 2 && (r.tyc != 1 || r.pipe)) return false;
-    if (r.pipe != 0 && r.pipe != 1) return false;
+    if (r.pipe < 0 || r.pipe > 2) return false;
+    if (r.pipe == 2 && (L.P / r.V > 64 || r.V < 4)) return false;  // rows must not straddle waves
     if (r.tyc < 1 || r.tyc > std::max(1, Pc - 1)) return false;
     const int G = h->dim == 3 ? 2 * r.tyc + 1 + 2 * r.pipe : 1;
     if (G * (L.P / r.V) > 1024 || restrict_lds_bytes(h->dim, L.P, L.prec, r) > 65536) return false;
@@ -437,7 +439,7 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
         for (int V : {4, 8})
             for (int tyc : {1, 2, 3, 4, 5, 7})
                 for (int zcc : {2, 4, 8, 16, 32})
-                    for (int pipe : {0, 1}) {
+                    for (int pipe : {0, 1, 2}) {
                     RShape r{V, tyc, zcc, pipe};
                     if (!restrict_ok(h, L, r)) continue;
                     const float t = time_ms(st, [&]() {

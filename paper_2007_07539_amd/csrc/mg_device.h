@@ -151,6 +151,45 @@ template <class T, int V> __device__ __forceinline__ void load_raw(const T *__re
 
 template <class T> __device__ __forceinline__ T zero_of() { return Store<T>::from_acc(acc_t<T>(0)); }
 
+// A prefetched row kept packed in its storage format (e.g. eight FP16 values
+// in four 32-bit registers) until it is widened.
+template <class T, int V> struct RawRow {
+    static constexpr int B = V * (int)sizeof(T);
+    static constexpr int CB = B >= 16 ? 16 : B;
+    typedef typename RawChunk<CB>::type C;
+    C c[B / CB];
+};
+
+template <class T, int V> __device__ __forceinline__ void fetch_row(const T *__restrict__ p, RawRow<T, V> &r) {
+    typedef typename RawRow<T, V>::C C;
+    const C *q = reinterpret_cast<const C *>(p);
+#pragma unroll
+    for (int i = 0; i < RawRow<T, V>::B / RawRow<T, V>::CB; ++i) r.c[i] = q[i];
+}
+
+template <class T, int V> __device__ __forceinline__ void zero_row(RawRow<T, V> &r) {
+    // all-zero bits are +0 in every storage format
+    union {
+        typename RawRow<T, V>::C c[RawRow<T, V>::B / RawRow<T, V>::CB];
+        unsigned char bytes[RawRow<T, V>::B];
+    } u;
+#pragma unroll
+    for (int i = 0; i < RawRow<T, V>::B; ++i) u.bytes[i] = 0;
+#pragma unroll
+    for (int i = 0; i < RawRow<T, V>::B / RawRow<T, V>::CB; ++i) r.c[i] = u.c[i];
+}
+
+template <class T, int V, class A> __device__ __forceinline__ void widen_row(const RawRow<T, V> &r, A (&o)[V]) {
+    union {
+        typename RawRow<T, V>::C c[RawRow<T, V>::B / RawRow<T, V>::CB];
+        T t[V];
+    } u;
+#pragma unroll
+    for (int i = 0; i < RawRow<T, V>::B / RawRow<T, V>::CB; ++i) u.c[i] = r.c[i];
+#pragma unroll
+    for (int i = 0; i < V; ++i) o[i] = (A)widen(u.t[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Padded level layout.  A level with n = 2^m - 1 interior points per
 // dimension uses pitch P = 2^m.  Interior coordinates run 1..P-1; coordinate 0

@@ -111,8 +111,11 @@ template <class TF, class TC> struct FProl {
         return 2;
     }
 
-    // coarse-row sum S(X) = sum over contributing (Z, Y) of w_Z w_Y e_c(X, Y, Z)
-    // for X = X0 .. X0 + V/2 (the last one may be the ghost Pc).
+    // Canonical order of the interpolation sums (every kernel uses it, so all
+    // of them round alike): for each contributing coarse row Y_b, first the z
+    // sum t_b(X) = sum_a w_Z e_c(X, Y_b, Z_a) over the interior planes Z_a,
+    // then s(X) = sum_b w_Y t_b(X), then the x weights.
+    // rowsum: s(X) for X = x0/2 .. x0/2 + V/2 (the last may be the ghost Pc).
     template <int D, int V> __device__ __forceinline__ void rowsum(int x0, int y, int z, PA (&s)[V / 2 + 1]) const {
         constexpr int H = V / 2;
         Grid<D> gc{Pc};
@@ -123,21 +126,26 @@ template <class TF, class TC> struct FProl {
         const int ny = D == 3 ? split(y, Ys) : 1;
         const PA wz = nz == 1 ? PA(1) : PA(0.5), wy = ny == 1 ? PA(1) : PA(0.5);
         const int X0 = x0 >> 1;
-        for (int a = 0; a < nz; ++a) {
-            const int Z = Zs[a];
-            if (Z < 1 || Z >= Pc) continue;
-            for (int bb = 0; bb < ny; ++bb) {
-                const int Y = D == 3 ? Ys[bb] : 0;
-                if (D == 3 && (Y < 1 || Y >= Pc)) continue;
-                const PA w = wz * wy;
-                const TC *base = ec + gc.at(X0, Y, Z);
-                PA v[H];
-                load_row<TC, H>(base, v);
+        for (int bb = 0; bb < ny; ++bb) {
+            const int Y = D == 3 ? Ys[bb] : 0;
+            PA t[H + 1];
 #pragma unroll
-                for (int j = 0; j < H; ++j) s[j] += w * v[j];
-                const PA last = (X0 + H < Pc) ? (PA)widen(base[H]) : PA(0);
-                s[H] += w * last;
+            for (int j = 0; j <= H; ++j) t[j] = PA(0);
+            if (!(D == 3 && (Y < 1 || Y >= Pc))) {
+                for (int a = 0; a < nz; ++a) {
+                    const int Z = Zs[a];
+                    if (Z < 1 || Z >= Pc) continue;
+                    const TC *base = ec + gc.at(X0, Y, Z);
+                    PA v[H];
+                    load_row<TC, H>(base, v);
+#pragma unroll
+                    for (int j = 0; j < H; ++j) t[j] += wz * v[j];
+                    const PA last = (X0 + H < Pc) ? (PA)widen(base[H]) : PA(0);
+                    t[H] += wz * last;
+                }
             }
+#pragma unroll
+            for (int j = 0; j <= H; ++j) s[j] += wy * t[j];
         }
     }
 
@@ -159,23 +167,25 @@ template <class TF, class TC> struct FProl {
         if (x0 == 0) o[0] = acc(0);
     }
 
-    // coarse column value sum over (Z, Y) at one coarse X
+    // s(X) at one coarse X, in the canonical order
     template <int D> __device__ __forceinline__ PA colsum(int X, int y, int z) const {
         Grid<D> gc{Pc};
         PA s = PA(0);
-        if (X < 1 || X >= Pc) return s;
         int Zs[2], Ys[2] = {0, 0};
         const int nz = split(z, Zs);
         const int ny = D == 3 ? split(y, Ys) : 1;
         const PA wz = nz == 1 ? PA(1) : PA(0.5), wy = ny == 1 ? PA(1) : PA(0.5);
-        for (int a = 0; a < nz; ++a) {
-            const int Z = Zs[a];
-            if (Z < 1 || Z >= Pc) continue;
-            for (int bb = 0; bb < ny; ++bb) {
-                const int Y = D == 3 ? Ys[bb] : 0;
-                if (D == 3 && (Y < 1 || Y >= Pc)) continue;
-                s += (wz * wy) * (PA)widen(ec[gc.at(X, Y, Z)]);
+        for (int bb = 0; bb < ny; ++bb) {
+            const int Y = D == 3 ? Ys[bb] : 0;
+            PA t = PA(0);
+            if (X >= 1 && X < Pc && !(D == 3 && (Y < 1 || Y >= Pc))) {
+                for (int a = 0; a < nz; ++a) {
+                    const int Z = Zs[a];
+                    if (Z < 1 || Z >= Pc) continue;
+                    t += wz * (PA)widen(ec[gc.at(X, Y, Z)]);
+                }
             }
+            s += wy * t;
         }
         return s;
     }
@@ -399,76 +409,75 @@ __global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nc
 template <class T, class A, int V> struct PArr {
     typedef A acc;
     typedef T lds_t;
-    struct Raw {
-        T v[V];
-    };
+    typedef RawRow<T, V> Raw;
     const T *__restrict__ p;
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
         if (g.ghost_row(y, z)) {
-#pragma unroll
-            for (int i = 0; i < V; ++i) r.v[i] = zero_of<T>();
+            zero_row(r);
             return;
         }
-        load_raw<T, V>(p + g.at(x0, y, z), r.v);
+        fetch_row<T, V>(p + g.at(x0, y, z), r);
     }
     __device__ __forceinline__ void value(const Raw &r, int, int, int, A (&o)[V], A (&)[V]) const {
-#pragma unroll
-        for (int i = 0; i < V; ++i) o[i] = (A)widen(r.v[i]);
+        widen_row<T, V>(r, o);
     }
+    static constexpr bool kStaged = false;
+    __device__ __forceinline__ void bind_lds(unsigned char *, int, int, int) {}
+    __device__ __forceinline__ void stage(int, int, int) const {}
 };
 
 // First Jacobi iterate round_T(k b) from a stored right-hand side; aux = b.
 template <class T, int V> struct PJac0Arr {
     typedef acc_t<T> acc;
     typedef T lds_t;
-    struct Raw {
-        T v[V];
-    };
+    typedef RawRow<T, V> Raw;
     const T *__restrict__ b;
     acc k;
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
         if (g.ghost_row(y, z)) {
-#pragma unroll
-            for (int i = 0; i < V; ++i) r.v[i] = zero_of<T>();
+            zero_row(r);
             return;
         }
-        load_raw<T, V>(b + g.at(x0, y, z), r.v);
+        fetch_row<T, V>(b + g.at(x0, y, z), r);
     }
     __device__ __forceinline__ void value(const Raw &r, int, int, int, acc (&o)[V], acc (&aux)[V]) const {
+        widen_row<T, V>(r, aux);
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-            aux[i] = widen(r.v[i]);
-            o[i] = round_to<T>(k * aux[i]);
-        }
+        for (int i = 0; i < V; ++i) o[i] = round_to<T>(k * aux[i]);
     }
+    static constexpr bool kStaged = false;
+    __device__ __forceinline__ void bind_lds(unsigned char *, int, int, int) {}
+    __device__ __forceinline__ void stage(int, int, int) const {}
 };
 
 // First Jacobi iterate from the scaled-and-cast FP64 residual; aux = b-hat.
 template <class T, int V> struct PJac0Scaled {
     typedef acc_t<T> acc;
     typedef T lds_t;
-    struct Raw {
-        double v[V];
-    };
+    typedef RawRow<double, V> Raw;
     const double *__restrict__ r;
     const double *__restrict__ scal;  // scal[1] = 1/alpha
     acc k;
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &rr) const {
         if (g.ghost_row(y, z)) {
-#pragma unroll
-            for (int i = 0; i < V; ++i) rr.v[i] = 0.0;
+            zero_row(rr);
             return;
         }
-        load_raw<double, V>(r + g.at(x0, y, z), rr.v);
+        fetch_row<double, V>(r + g.at(x0, y, z), rr);
     }
     __device__ __forceinline__ void value(const Raw &rr, int, int, int, acc (&o)[V], acc (&aux)[V]) const {
         const double inv = scal[1];
+        double rv[V];
+        widen_row<double, V>(rr, rv);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-            aux[i] = widen(Store<T>::from_f64(rr.v[i] * inv));
+            aux[i] = widen(Store<T>::from_f64(rv[i] * inv));
             o[i] = round_to<T>(k * aux[i]);
         }
     }
+    static constexpr bool kStaged = false;
+    __device__ __forceinline__ void bind_lds(unsigned char *, int, int, int) {}
+    __device__ __forceinline__ void stage(int, int, int) const {}
 };
 
 // Corrected correction round_TF(c + 4 P e_c); same arithmetic as FProl::row.
@@ -478,8 +487,9 @@ template <class TF, class TC, int V> struct PProl {
     typedef typename FProl<TF, TC>::PA PA;
     static constexpr int H = V / 2;
     struct Raw {
-        TF c[V];
-        PA seg[4][H + 1];
+        RawRow<TF, V> c;
+        RawRow<TC, H> seg[4];
+        TC last[4];
         int ok;  // bit a*2+b: coarse row (Z_a, Y_b) present
     };
     const TF *__restrict__ c;
@@ -488,11 +498,10 @@ template <class TF, class TC, int V> struct PProl {
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
         r.ok = 0;
         if (g.ghost_row(y, z)) {
-#pragma unroll
-            for (int i = 0; i < V; ++i) r.c[i] = zero_of<TF>();
+            zero_row(r.c);
             return;
         }
-        load_raw<TF, V>(c + g.at(x0, y, z), r.c);
+        fetch_row<TF, V>(c + g.at(x0, y, z), r.c);
         const Grid<3> gc{Pc};
         int Zs[2], Ys[2];
         const int nz = FProl<TF, TC>::split(z, Zs);
@@ -506,11 +515,8 @@ template <class TF, class TC, int V> struct PProl {
                 const bool use = a < nz && bb < ny && Zs[a] >= 1 && Zs[a] < Pc && Ys[bb] >= 1 && Ys[bb] < Pc;
                 if (use) {
                     const TC *base = ec + gc.at(X0, Ys[bb], Zs[a]);
-                    PA v[H];
-                    load_row<TC, H>(base, v);
-#pragma unroll
-                    for (int j = 0; j < H; ++j) r.seg[idx][j] = v[j];
-                    r.seg[idx][H] = (X0 + H < Pc) ? (PA)widen(base[H]) : PA(0);
+                    fetch_row<TC, H>(base, r.seg[idx]);
+                    r.last[idx] = (X0 + H < Pc) ? base[H] : zero_of<TC>();
                     r.ok |= 1 << idx;
                 }
             }
@@ -525,20 +531,125 @@ template <class TF, class TC, int V> struct PProl {
 #pragma unroll
         for (int j = 0; j <= H; ++j) s[j] = PA(0);
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
+        for (int bb = 0; bb < 2; ++bb) {
+            if (bb < ny) {
+                PA t[H + 1];
 #pragma unroll
-            for (int bb = 0; bb < 2; ++bb) {
-                if (r.ok & (1 << (a * 2 + bb))) {
-                    const PA w = wz * wy;
+                for (int j = 0; j <= H; ++j) t[j] = PA(0);
 #pragma unroll
-                    for (int j = 0; j <= H; ++j) s[j] += w * r.seg[a * 2 + bb][j];
+                for (int a = 0; a < 2; ++a) {
+                    if (r.ok & (1 << (a * 2 + bb))) {
+                        PA v[H];
+                        widen_row<TC, H>(r.seg[a * 2 + bb], v);
+#pragma unroll
+                        for (int j = 0; j < H; ++j) t[j] += wz * v[j];
+                        t[H] += wz * (PA)widen(r.last[a * 2 + bb]);
+                    }
                 }
+#pragma unroll
+                for (int j = 0; j <= H; ++j) s[j] += wy * t[j];
             }
         }
+        acc cv[V];
+        widen_row<TF, V>(r.c, cv);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
             const PA p = (i & 1) ? PA(0.5) * (s[i >> 1] + s[(i >> 1) + 1]) : s[i >> 1];
-            o[i] = round_to<TF>((PA)widen(r.c[i]) + PA(4) * p);
+            o[i] = round_to<TF>((PA)cv[i] + PA(4) * p);
+        }
+        if (x0 == 0) o[0] = acc(0);
+    }
+    static constexpr bool kStaged = false;
+    __device__ __forceinline__ void bind_lds(unsigned char *, int, int, int) {}
+    __device__ __forceinline__ void stage(int, int, int) const {}
+};
+
+// Corrected correction with the coarse data staged in LDS: for every fine
+// plane z the block first writes the z-interpolated coarse rows
+// Ez(X, Y) = sum_a w_Z e_c(X, Y, Z_a) it needs (rows Ylo .. Ylo+NYc-1, all X,
+// ghost rows and columns zero) into one of three LDS slots, two planes ahead;
+// a fine row then reads one or two of those rows.  Same sums, same order as
+// FProl, so the result is identical.
+template <class TF, class TC, int V> struct PProlS {
+    typedef acc_t<TF> acc;
+    typedef TF lds_t;
+    typedef typename FProl<TF, TC>::PA PA;
+    static constexpr int H = V / 2;
+    static constexpr bool kStaged = true;
+    typedef RawRow<TF, V> Raw;
+    const TF *__restrict__ c;
+    const TC *__restrict__ ec;
+    int Pc;
+    PA *ez;        // [3][NYc][RSx]
+    int Ylo, NYc, RSx;
+    __device__ __forceinline__ static int ez_rows(int y0, int TY) { return (y0 + TY + 1) / 2 - (y0 - 1) / 2 + 1; }
+    __device__ __forceinline__ void bind_lds(unsigned char *p, int y0, int TY, int) {
+        ez = reinterpret_cast<PA *>(p);
+        Ylo = (y0 - 1) / 2;
+        NYc = ez_rows(y0, TY);
+        RSx = Pc + 4;
+    }
+    // write Ez of fine plane z into slot z mod 3 (all threads of the block)
+    __device__ __forceinline__ void stage(int z, int tid, int nthr) const {
+        const Grid<3> gc{Pc};
+        int Zs[2];
+        const int nz = FProl<TF, TC>::split(z, Zs);
+        const PA wz = nz == 1 ? PA(1) : PA(0.5);
+        PA *dst = ez + (size_t)(((z % 3) + 3) % 3) * NYc * RSx;
+        const bool plane_ok = z >= 1 && z < 2 * Pc;
+        for (int e = tid; e < NYc * RSx; e += nthr) {
+            const int r = e / RSx, X = e - r * RSx;
+            const int Y = Ylo + r;
+            PA t = PA(0);
+            if (plane_ok && X >= 1 && X < Pc && Y >= 1 && Y < Pc) {
+                for (int a = 0; a < nz; ++a) {
+                    const int Z = Zs[a];
+                    if (Z < 1 || Z >= Pc) continue;
+                    t += wz * (PA)widen(ec[gc.at(X, Y, Z)]);
+                }
+            }
+            dst[e] = t;
+        }
+    }
+    __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
+        if (g.ghost_row(y, z)) {
+            zero_row(r);
+            return;
+        }
+        fetch_row<TF, V>(c + g.at(x0, y, z), r);
+    }
+    __device__ __forceinline__ void value(const Raw &r, int x0, int y, int z, acc (&o)[V], acc (&)[V]) const {
+        const Grid<3> g{2 * Pc};
+        if (g.ghost_row(y, z)) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) o[i] = acc(0);
+            return;
+        }
+        int Ys[2];
+        const int ny = FProl<TF, TC>::split(y, Ys);
+        const PA wy = ny == 1 ? PA(1) : PA(0.5);
+        const PA *slot = ez + (size_t)(z % 3) * NYc * RSx;
+        const int X0 = x0 >> 1;
+        PA s[H + 1];
+#pragma unroll
+        for (int j = 0; j <= H; ++j) s[j] = PA(0);
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+            if (bb < ny) {
+                const PA *row = slot + (size_t)(Ys[bb] - Ylo) * RSx + X0;
+                PA t[H];
+                load_row<PA, H>(row, t);
+#pragma unroll
+                for (int j = 0; j < H; ++j) s[j] += wy * t[j];
+                s[H] += wy * row[H];
+            }
+        }
+        acc cv[V];
+        widen_row<TF, V>(r, cv);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const PA p = (i & 1) ? PA(0.5) * (s[i >> 1] + s[(i >> 1) + 1]) : s[i >> 1];
+            o[i] = round_to<TF>((PA)cv[i] + PA(4) * p);
         }
         if (x0 == 0) o[0] = acc(0);
     }
@@ -549,9 +660,7 @@ template <class TF, class TC, int V> struct PProl {
 template <class T, int V, bool RHS_AUX, bool WRITE_B> struct PSweep {
     typedef acc_t<T> A;
     typedef NoState State;
-    struct Raw {
-        T v[RHS_AUX ? 1 : V];
-    };
+    typedef RawRow<T, RHS_AUX ? 2 : V> Raw;
     const T *__restrict__ b;
     T *__restrict__ out;
     T *__restrict__ bout;
@@ -559,14 +668,16 @@ template <class T, int V, bool RHS_AUX, bool WRITE_B> struct PSweep {
     __device__ __forceinline__ void init(State &) const {}
     __device__ __forceinline__ void finish(State &, double *) const {}
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
-        if constexpr (!RHS_AUX) load_raw<T, V>(b + g.at(x0, y, z), r.v);
+        if constexpr (!RHS_AUX) fetch_row<T, V>(b + g.at(x0, y, z), r);
     }
     __device__ __forceinline__ void emit(const Grid<3> &g, State &, int x0, int y, int z, const A (&c)[V],
                                          const A (&nb)[V], const A (&aux)[V], const Raw &r) const {
         T o[V];
+        A bv[V];
+        if constexpr (!RHS_AUX) widen_row<T, V>(r, bv);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-            const A bi = RHS_AUX ? aux[i] : (A)widen(r.v[RHS_AUX ? 0 : i]);
+            const A bi = RHS_AUX ? aux[i] : bv[i];
             const A lc = fmaT<A>(A(6), c[i], -nb[i]);
             o[i] = Store<T>::from_acc(fmaT<A>(k, bi - lc, c[i]));
         }
@@ -590,7 +701,7 @@ template <int V> struct POuter {
         double ss, mx;
     };
     struct Raw {
-        double r[V], u[V];
+        RawRow<double, V> r, u;
     };
     double *__restrict__ R;
     double *__restrict__ U;
@@ -600,19 +711,21 @@ template <int V> struct POuter {
     __device__ __forceinline__ void init(State &s) const { s.ss = 0.0, s.mx = 0.0; }
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
         const size_t at = g.at(x0, y, z);
-        load_raw<double, V>(R + at, r.r);
-        load_raw<double, V>(U + at, r.u);
+        fetch_row<double, V>(R + at, r.r);
+        fetch_row<double, V>(U + at, r.u);
     }
     __device__ __forceinline__ void emit(const Grid<3> &g, State &st, int x0, int y, int z, const A (&c)[V],
                                          const A (&nb)[V], const A (&)[V], const Raw &rw) const {
         const double a = scal[0];
         const double ah2 = a * h2;
         double r[V], u[V];
+        widen_row<double, V>(rw.r, r);
+        widen_row<double, V>(rw.u, u);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
             const double lc = fmaT<double>(6.0, c[i], -nb[i]);
-            r[i] = fmaT<double>(-a, lc, rw.r[i]);
-            u[i] = fmaT<double>(ah2, c[i], rw.u[i]);
+            r[i] = fmaT<double>(-a, lc, r[i]);
+            u[i] = fmaT<double>(ah2, c[i], u[i]);
         }
         if (x0 == 0) r[0] = 0.0, u[0] = 0.0;
 #pragma unroll
@@ -634,7 +747,7 @@ template <int V> struct POuter {
 };
 
 template <int V, class F, class E>
-__global__ __launch_bounds__(1024) void k_march(F f, E e, int P, int TY, int zc, int ytiles, int xcd) {
+__global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int zc, int ytiles, int xcd) {
     typedef typename F::acc A;
     typedef typename F::lds_t LT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -662,6 +775,15 @@ __global__ __launch_bounds__(1024) void k_march(F f, E e, int P, int TY, int zc,
     typename F::Raw fr;
     typename E::Raw er;
     A cm[V], cc[V], cp[V], ac[V], ap[V];
+    F f = f_in;
+    const int nthr = blockDim.x;
+    if constexpr (F::kStaged) {
+        f.bind_lds(smem_raw + 2 * slot * sizeof(LT), y0, TY, 0);
+        f.stage(z0 - 1, threadIdx.x, nthr);
+        f.stage(z0, threadIdx.x, nthr);
+        f.stage(z0 + 1, threadIdx.x, nthr);
+        __syncthreads();
+    }
     f.fetch(g, x0, y, z0 - 1, fr);
     f.value(fr, x0, y, z0 - 1, cm, ac);
     f.fetch(g, x0, y, z0, fr);
@@ -674,9 +796,11 @@ __global__ __launch_bounds__(1024) void k_march(F f, E e, int P, int TY, int zc,
     }
     f.fetch(g, x0, y, z0 + 1, fr);
     if (out_row) e.fetch(g, x0, y, z0, er);
+    if constexpr (F::kStaged) __syncthreads();  // prologue reads of the staged slots are done
     for (int z = z0; z < z1; ++z) {
         const int it = z - z0;
         f.value(fr, x0, y, z + 1, cp, ap);
+        if constexpr (F::kStaged) f.stage(z + 2, threadIdx.x, nthr);
         if (z + 2 <= z1) f.fetch(g, x0, y, z + 2, fr);
         const typename E::Raw ecur = er;
         if (out_row && z + 1 < z1) e.fetch(g, x0, y, z + 1, er);
@@ -859,7 +983,12 @@ __global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, con
 // residual rows with the x and y weights and accumulate the z weights of the
 // coarse plane in registers.  One barrier per fine plane.
 // ===========================================================================
-template <int V, class TF, class TC>
+// XSH: the fine threads also apply the x weights, taking the residual at
+// x0 - 1 from the previous lane by a wave shuffle (needs P/V <= 64, so a
+// grid row never straddles two waves); the LDS row buffer then holds the
+// x-restricted values, P/2 per row, and the coarse threads read VC of them
+// per row as one vector.
+template <int V, class TF, class TC, bool XSH>
 __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, const TF *__restrict__ c,
                                                     TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles,
                                                     int xcd) {
@@ -867,8 +996,9 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
     constexpr int VC = V / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = 2 * tyc + 3, R = 2 * tyc + 1;
+    const int RW = XSH ? P / 2 : P;                                             // r row width
     TF *cs = reinterpret_cast<TF *>(smem_raw);                                  // [2][G][P]
-    A *rs = reinterpret_cast<A *>(smem_raw + 2 * (size_t)G * P * sizeof(TF));   // [2][R][P]
+    A *rs = reinterpret_cast<A *>(smem_raw + 2 * (size_t)G * P * sizeof(TF));   // [2][R][RW]
     const int Pc = P >> 1;
     const int TXR = P / V;
     const Grid<3> g{P};
@@ -891,10 +1021,10 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
     const int Yc = Y0 + gi;
     const int X0 = xc * VC;
     const PArr<TF, A, V> f{c};
-    const size_t cslot = (size_t)G * P, rslot = (size_t)R * P;
+    const size_t cslot = (size_t)G * P, rslot = (size_t)R * RW;
     const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
     typename PArr<TF, A, V>::Raw fr;
-    TF braw[V], bnext[V];
+    RawRow<TF, V> braw, bnext;
     A cm[V], cc[V], cp[V], dummy[V];
     A acc[VC];
 #pragma unroll
@@ -910,7 +1040,7 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
         store_row<TF, V>(cs + (size_t)gi * P + x0, t);
     }
     f.fetch(g, x0, y, zf0 + 1, fr);
-    if (res_row) load_raw<TF, V>(b + g.at(x0, y, zf0), bnext);
+    if (res_row) fetch_row<TF, V>(b + g.at(x0, y, zf0), bnext);
 
     // coarse step: fold the residual rows of fine plane zf (in slot s) into acc
     auto coarse_step = [&](int zf, int s) {
@@ -918,6 +1048,11 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
         const int j = zf - zf0;
         const bool last_of_z = j > 0 && (j & 1) == 0;  // zf = 2Z + 1
         TC out[VC];
+        A xs[3][VC];
+        if constexpr (XSH) {
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) load_row<A, VC>(rb + (size_t)(2 * gi + oy) * RW + X0, xs[oy]);
+        }
 #pragma unroll
         for (int jx = 0; jx < VC; ++jx) {
             const int X = X0 + jx;
@@ -926,8 +1061,12 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
                 A rsum[3];
 #pragma unroll
                 for (int oy = 0; oy < 3; ++oy) {
-                    const A *row = rb + (size_t)(2 * gi + oy) * P;
-                    rsum[oy] = A(0.25) * (row[2 * X - 1] + row[2 * X + 1]) + A(0.5) * row[2 * X];
+                    if constexpr (XSH) {
+                        rsum[oy] = xs[oy][jx];
+                    } else {
+                        const A *row = rb + (size_t)(2 * gi + oy) * P;
+                        rsum[oy] = A(0.25) * (row[2 * X - 1] + row[2 * X + 1]) + A(0.5) * row[2 * X];
+                    }
                 }
                 q = A(0.25) * (rsum[0] + rsum[2]) + A(0.5) * rsum[1];
             }
@@ -946,13 +1085,15 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
         }
     };
 
+    A rkeep[V];
     for (int zf = zf0; zf <= zf1; ++zf) {
         const int it = zf - zf0;
+#pragma unroll
+        for (int i = 0; i < V; ++i) rkeep[i] = A(0);
         f.value(fr, x0, y, zf + 1, cp, dummy);
         if (zf + 2 <= zf1 + 1) f.fetch(g, x0, y, zf + 2, fr);
-#pragma unroll
-        for (int i = 0; i < V; ++i) braw[i] = bnext[i];
-        if (res_row && zf + 1 <= zf1) load_raw<TF, V>(b + g.at(x0, y, zf + 1), bnext);
+        braw = bnext;
+        if (res_row && zf + 1 <= zf1) fetch_row<TF, V>(b + g.at(x0, y, zf + 1), bnext);
         __syncthreads();
         if (coarse && it > 0) coarse_step(zf - 1, (it - 1) & 1);
         if (res_row) {
@@ -965,24 +1106,44 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
             A ym[V], yp[V];
             load_row<TF, V>(row - P + x0, ym);
             load_row<TF, V>(row + P + x0, yp);
-            A r[V];
+            A r[V], bv[V];
+            widen_row<TF, V>(braw, bv);
 #pragma unroll
             for (int i = 0; i < V; ++i) {
                 nb[i] += ym[i];
                 nb[i] += yp[i];
                 nb[i] += cm[i];
                 nb[i] += cp[i];
-                r[i] = (A)widen(braw[i]) - fmaT<A>(A(6), cc[i], -nb[i]);
+                r[i] = bv[i] - fmaT<A>(A(6), cc[i], -nb[i]);
             }
             if (x0 == 0) r[0] = A(0);
-            A *dst = rs + (size_t)(it & 1) * rslot + (size_t)(gi - 1) * P + x0;
+            if constexpr (!XSH) {
+                A *dst = rs + (size_t)(it & 1) * rslot + (size_t)(gi - 1) * P + x0;
 #pragma unroll
-            for (int i = 0; i < V; ++i) dst[i] = r[i];
-        } else if (gi >= 1 && gi <= G - 2) {
+                for (int i = 0; i < V; ++i) dst[i] = r[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < V; ++i) rkeep[i] = r[i];
+            }
+        } else if (!XSH && gi >= 1 && gi <= G - 2) {
             // residual rows past the last interior row are zero
             A *dst = rs + (size_t)(it & 1) * rslot + (size_t)(gi - 1) * P + x0;
 #pragma unroll
             for (int i = 0; i < V; ++i) dst[i] = A(0);
+        }
+        if constexpr (XSH) {
+            // x weights in the fine thread: coarse X = x0/2 + j takes fine
+            // 2X-1, 2X, 2X+1 = x0+2j-1 .. x0+2j+1; x0-1 comes from the previous lane
+            const A left_in = __shfl_up(rkeep[V - 1], 1, 64);
+            const A left = x0 > 0 ? left_in : A(0);
+            A xq[VC];
+#pragma unroll
+            for (int j = 0; j < VC; ++j) {
+                const A lm = j > 0 ? rkeep[2 * j - 1] : left;
+                xq[j] = A(0.25) * (lm + rkeep[2 * j + 1]) + A(0.5) * rkeep[2 * j];
+            }
+            if (x0 == 0) xq[0] = A(0);
+            if (gi >= 1 && gi <= G - 2) store_row<A, VC>(rs + (size_t)(it & 1) * rslot + (size_t)(gi - 1) * RW + (x0 >> 1), xq);
         }
         {
             TF t[V];
@@ -1155,7 +1316,8 @@ int restrict_blocks(int D, int P, const RShape &s) {
 size_t restrict_lds_bytes(int D, int P, int pf, const RShape &s) {
     const size_t acc = pf == P_F64 ? 8 : 4;
     if (D == 3 && s.pipe)
-        return 2 * (size_t)(2 * s.tyc + 3) * P * prec_bytes(pf) + 2 * (size_t)(2 * s.tyc + 1) * P * acc;
+        return 2 * (size_t)(2 * s.tyc + 3) * P * prec_bytes(pf) +
+               2 * (size_t)(2 * s.tyc + 1) * (s.pipe == 2 ? P / 2 : P) * acc;
     const int G = D == 3 ? 2 * s.tyc + 1 : 1;
     return 2 * (size_t)G * P * acc;
 }
@@ -1173,12 +1335,23 @@ static hipError_t run_stencil(const F &f, const E &e, int P, const Shape &s, hip
     return hipGetLastError();
 }
 
+// Extra LDS of the staged prolongation field: three slots of z-interpolated
+// coarse rows.
+static size_t staged_ez_bytes(int P, int ty, size_t pa) { return 3 * (size_t)(ty / 2 + 3) * (P / 2 + 4) * pa; }
+
+template <class F> struct StagedBytes {
+    static size_t get(int P, int ty) { return 0; }
+};
+template <class TF, class TC, int V> struct StagedBytes<PProlS<TF, TC, V>> {
+    static size_t get(int P, int ty) { return staged_ez_bytes(P, ty, sizeof(typename PProlS<TF, TC, V>::PA)); }
+};
+
 template <int V, class F, class E>
 static hipError_t run_march(const F &f, const E &e, int P, const Shape &s, hipStream_t st) {
     const int ytiles = ceil_div(P - 1, s.ty);
     const int nch = stencil_chunks(P, s.zc);
     const int threads = (P / V) * (s.ty + 2);
-    const size_t lds = march_lds_bytes(P, s.ty, sizeof(typename F::lds_t));
+    const size_t lds = march_lds_bytes(P, s.ty, sizeof(typename F::lds_t)) + StagedBytes<F>::get(P, s.ty);
     hipLaunchKernelGGL((k_march<V, F, E>), dim3(ytiles * nch), dim3(threads), lds, st, f, e, P, s.ty, s.zc, ytiles,
                        s.xcd);
     return hipGetLastError();
@@ -1301,6 +1474,19 @@ static hipError_t prolong_t(int D, int P, const void *c, const void *ec, const v
     const R rh{static_cast<const TF *>(b)};
     hipError_t err = hipSuccess;
     if (D == 3 && s.ty > 0 && sweep) {
+        typedef typename FProl<TF, TC>::PA PA;
+        const bool staged = P / 2 >= 8 &&
+                            march_lds_bytes(P, s.ty, sizeof(TF)) + staged_ez_bytes(P, s.ty, sizeof(PA)) <= 65536;
+        if (staged) {
+            MG_DISPATCH_V(s.V, err = (run_march<VV>(PProlS<TF, TC, VV>{static_cast<const TF *>(c),
+                                                                       static_cast<const TC *>(ec), P / 2,
+                                                                       nullptr, 0, 0, 0},
+                                                   PSweep<TF, VV, false, false>{static_cast<const TF *>(b),
+                                                                                static_cast<TF *>(c_out), nullptr,
+                                                                                (A)(omega / (2.0 * D))},
+                                                   P, s, st)));
+            return err;
+        }
         MG_DISPATCH_V(s.V, err = (run_march<VV>(PProl<TF, TC, VV>{static_cast<const TF *>(c),
                                                                   static_cast<const TC *>(ec), P / 2},
                                                PSweep<TF, VV, false, false>{static_cast<const TF *>(b),
@@ -1345,9 +1531,14 @@ static hipError_t restrict_run(int P, const void *b, const void *c, void *bc, co
         const int blocks = ytiles * ceil_div(Pc - 1, s.zcc);
         const int threads = (2 * s.tyc + 3) * (P / V);
         const size_t lds = restrict_lds_bytes(D, P, prec_of<TF>(), s);
-        hipLaunchKernelGGL((k_restrict2<V, TF, TC>), dim3(blocks), dim3(threads), lds, st,
-                           static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P, s.tyc,
-                           s.zcc, ytiles, 1);
+        if (s.pipe == 2)
+            hipLaunchKernelGGL((k_restrict2<V, TF, TC, true>), dim3(blocks), dim3(threads), lds, st,
+                               static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P,
+                               s.tyc, s.zcc, ytiles, 1);
+        else
+            hipLaunchKernelGGL((k_restrict2<V, TF, TC, false>), dim3(blocks), dim3(threads), lds, st,
+                               static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P,
+                               s.tyc, s.zcc, ytiles, 1);
         return hipGetLastError();
     }
     const int ytiles = D == 3 ? ceil_div(Pc - 1, s.tyc) : 1;
