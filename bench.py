@@ -91,7 +91,8 @@ def main():
     log("[bench] setup mixed solver")
     tune = not args.no_autotune
     mixed = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=True, device=dev, autotune=tune)
-    shapes_mixed = {"stencil": mixed.get_shape(0, mgir.SHAPE_STENCIL),
+    shapes_mixed = {"smooth": mixed.get_shape(0, mgir.SHAPE_SMOOTH), "sweep": mixed.get_shape(0, mgir.SHAPE_SWEEP),
+                    "prolong": mixed.get_shape(0, mgir.SHAPE_PROLONG),
                     "restrict": mixed.get_shape(0, mgir.SHAPE_RESTRICT),
                     "update": mixed.get_shape(0, mgir.SHAPE_UPDATE)}
     ms_mixed, res_mixed = timed_solves(mixed, bt, u, args.steps, args.warmup, torch)

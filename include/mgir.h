@@ -136,6 +136,84 @@ mg_status_t mg_vcycle(mg_handle h, const void *b, void *c, void *stream);
  * MG_ERR_WORKSPACE, MG_ERR_HIP, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE. */
 mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats, void *stream);
 
+/* ---- Batched instances ----------------------------------------------------
+ * Many independent 3-D problems of different sizes solved together with the
+ * method of Algorithms 1 and 2 (the paper solves one grid at a time; the
+ * batch is an extension).  Stages are aligned from the finest level down:
+ * stage d is ONE kernel launch over level d of every instance that has it,
+ * so the small coarse grids of all instances share launches instead of each
+ * costing a launch per level.
+ *
+ * Create a batched solver.
+ *   ninst      1..4096 instances.
+ *   n          ninst sizes, each 2^m - 1 with 2 <= m <= 10.
+ *   level_prec Lmax entries (Lmax = the largest m), FINEST FIRST: instance i
+ *              with m_i levels stores its level l < m_i - 1 in level_prec[l]
+ *              and its one-point base level in level_prec[Lmax - 1] -- the
+ *              same map a single-grid solver gets from level_prec[0..m_i-2]
+ *              followed by level_prec[Lmax-1].  NULL means all MG_F64.
+ *   opt        NULL for defaults; needs nu1 >= 2.  use_graph captures one
+ *              refinement step of the whole batch; autotune is ignored.
+ * Each instance computes bit for bit what a single-grid solver with its size
+ * and map computes.  Workspace as for mg_setup (mg_workspace_size,
+ * mg_bind_workspace).  The single-grid calls (mg_vcycle, ir_solve, stage and
+ * shape access) refuse a batched handle with MG_ERR_STATE.
+ * Errors: MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_PREC. */
+mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, const mg_prec_t *level_prec,
+                             const mg_options_t *opt);
+
+/* Algorithm 2 for every instance of a batched handle: the iteration of
+ * ir_solve with per-instance alpha, norms, stop test and confirmation;
+ * converged instances drop out of the following launches.
+ *   b      host array of ninst device pointers, b[i] dense FP64 n_i^3.
+ *   u      host array of ninst device pointers, u[i] dense FP64 n_i^3
+ *          (input guess with opt.use_initial_guess; output as in ir_solve).
+ *   stats  NULL or ninst entries; history of each entry as in ir_solve;
+ *          seconds is the wall time of the whole batch.
+ * Returns MG_OK when every instance converged, else the first failing
+ * instance's status (every instance's u and stats are still written).
+ * Synchronises stream once per refinement step. */
+mg_status_t ir_solve_batched(mg_handle h, const double *const *b, double *const *u, mg_stats_t *stats,
+                             void *stream);
+
+/* Number of instances of a handle (1 for a single-grid handle). */
+mg_status_t mg_instances(mg_handle h, int *ninst);
+
+/* ---- Many right-hand sides -------------------------------------------------
+ * nrhs Poisson problems on one 3-D grid (same operator, different b), stored
+ * interleaved: value k of grid point (x, y, z) (0-based) at
+ * ((z*n + y)*n + x)*nrhs + k.  One kernel launch per V-cycle stage serves all
+ * right-hand sides; each one runs Algorithm 2 on its own (its own alpha_k,
+ * norms, stop test and confirmation), and column k computes what a
+ * single-grid solve of that right-hand side computes.  (The paper solves one
+ * right-hand side at a time; the interleaved batch is an extension.)
+ *
+ * Create a solver.
+ *   dim        3.
+ *   n          2^m - 1 with 2 <= m <= 9.
+ *   nrhs       4, 8, 16, 32 or 64, and at least 8 when any level is stored
+ *              in FP32, FP16 or BF16 (a thread handles 8 such columns).
+ *   level_prec m formats, finest first, as for mg_setup.
+ *   opt        NULL for defaults; needs nu1 >= 2; autotune is ignored.
+ * Errors: MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_PREC.  Workspace as for mg_setup;
+ * single-grid calls other than mg_levels / mg_level_n refuse the handle with
+ * MG_ERR_STATE. */
+mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_prec_t *level_prec,
+                           const mg_options_t *opt);
+
+/* Algorithm 2 for every right-hand side of a handle from mg_setup_multi.
+ *   b      device, FP64, n^3 * nrhs values, interleaved as above.
+ *   u      device, same layout; the guess with opt.use_initial_guess, and the
+ *          result on return.  A right-hand side that is zero gets u = 0; one
+ *          with a non-finite value keeps its guess (0 without one).
+ *   stats  NULL or nrhs entries, as for ir_solve (seconds: whole call).
+ * Returns MG_OK when every column converged, else the first failing
+ * column's status.  Synchronises stream once per refinement step. */
+mg_status_t ir_solve_multi(mg_handle h, const double *b, double *u, mg_stats_t *stats, void *stream);
+
+/* Number of right-hand sides of a handle (1 unless from mg_setup_multi). */
+mg_status_t mg_rhs_count(mg_handle h, int *nrhs);
+
 /* Release the handle (never frees caller memory).  NULL is accepted. */
 mg_status_t mg_destroy(mg_handle h);
 
@@ -193,8 +271,12 @@ typedef enum {
                                1 = correction plane staged in LDS, next plane
                                prefetched; 2 = as 1 with the x weights applied in
                                the fine threads, needs P/V <= 64)} */
-    MG_SHAPE_UPDATE = 2     /* level 0 only: the FP64 refinement update, same five
+    MG_SHAPE_UPDATE = 2,    /* level 0 only: the FP64 refinement update, same five
                                values as MG_SHAPE_STENCIL */
+    MG_SHAPE_SMOOTH = 3,    /* the first pre-smoothing kernel only (five values) */
+    MG_SHAPE_SWEEP = 4,     /* the single sweeps only (five values); MG_SHAPE_STENCIL
+                               sets SMOOTH, SWEEP and PROLONG together and reads SWEEP */
+    MG_SHAPE_PROLONG = 5    /* prolongation + correction + sweep only (five values) */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);

@@ -32,13 +32,17 @@ def _stale(obj, srcs):
     return any(os.path.getmtime(s) > t for s in srcs)
 
 
+SOURCES = (("mg_kernels.hip", True), ("mg_multi.hip", True), ("mg_api.cpp", False))
+
+
 def build(force: bool = True) -> str:
-    """Compile and link; with force=False only objects older than a source are rebuilt."""
+    """Compile (all sources in parallel) and link; with force=False only
+    objects older than a source or header are rebuilt."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    objs, jobs = [], []
     headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
     headers.append(os.path.join(ROOT, "include", "mgir.h"))
-    for src, dev in (("mg_kernels.hip", True), ("mg_api.cpp", False)):
+    for src, dev in SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
         if not force and not _stale(obj, [os.path.join(CSRC, src)] + headers):
@@ -46,8 +50,13 @@ def build(force: bool = True) -> str:
         if dev:
             cmd = [HIPCC, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE
         else:
-            cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON
-        _run(cmd)
+            cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
+                   os.path.join(CSRC, src), "-o", obj] + COMMON
+        print("+", " ".join(cmd), flush=True)
+        jobs.append((src, subprocess.Popen(cmd)))
+    failed = [src for src, p in jobs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc " + " ".join(failed))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, LIB)

@@ -41,11 +41,13 @@ mg_status_t fail(mg_status_t s, const char *fmt, ...) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+enum { SH_SMOOTH = 0, SH_SWEEP = 1, SH_PROLONG = 2 };
+
 struct LevelPlan {
     int n = 0, P = 0, prec = 0;
     size_t elems = 0;
     size_t off_b = 0, off_c[2] = {0, 0};
-    Shape sh;       // smoothing, sweeps, prolongation
+    Shape shs[3];   // kernel families: SH_SMOOTH (first pre-smoothing), SH_SWEEP, SH_PROLONG
     Shape osh;      // refinement update (finest level only)
     RShape rsh;     // residual + restriction onto the next level
 };
@@ -77,6 +79,39 @@ struct mg_ctx {
     // profiling
     bool prof = false;
     std::vector<ProfRec> recs;
+    // batched instances
+    bool batched = false;
+    struct Inst {
+        int n = 0, nl = 0;
+        std::vector<LevelPlan> lv;
+        size_t off_R = 0, off_U = 0;
+        int part_off = 0, parts = 0;
+        Shape osh;
+    };
+    std::vector<Inst> inst;
+    int Lmax = 0;
+    std::vector<int> bprec;  // batched level map (finest first, last = base)
+    struct BLaunch {
+        int what;  // 0 stencil, 1 restriction, 2 base solve, 3 finalize
+        int kind, V, pf, pc;
+        size_t off_desc, off_items;
+        int ndesc, nitems, grid, threads;
+        size_t lds;
+        const char *name;
+        int level;
+        double bytes;
+    };
+    std::vector<BLaunch> bl;
+    size_t off_bmeta = 0, bmeta_bytes = 0, off_active = 0, off_scal_all = 0, off_fin = 0;
+    int *host_active = nullptr;
+    double *host_scal_all = nullptr;
+    std::vector<unsigned char> bmeta_img_tmp;
+    // many right-hand sides (interleaved); nrhs == 0 for other handles
+    int nrhs = 0;
+    size_t off_act = 0, off_mask = 0, off_zmask = 0;
+    int m_upd_blocks = 0;
+    int *host_mask = nullptr;
+    double *host_scal_m = nullptr;
 };
 
 namespace {
@@ -201,16 +236,17 @@ hipError_t enq_presmooth(mg_ctx *h, hipStream_t st, int l, bool from_R) {
     if (from_R) {
         RUN(h, st, two ? "smooth2_scaled" : "smooth1_scaled", l, N * (8 + 2 * s),
             launch_smooth_first(D, L.prec, L.P, nullptr, Rbuf(h), scal(h), bbuf(h, l), cbuf(h, l, 0), h->opt.omega,
-                                two, L.sh, st));
+                                two, L.shs[SH_SMOOTH], st));
     } else {
         RUN(h, st, two ? "smooth2" : "smooth1", l, N * 2 * s,
             launch_smooth_first(D, L.prec, L.P, bbuf(h, l), nullptr, nullptr, nullptr, cbuf(h, l, 0), h->opt.omega,
-                                two, L.sh, st));
+                                two, L.shs[SH_SMOOTH], st));
     }
     int cur = 0;
     for (int k = two ? 2 : 1; k < h->opt.nu1; ++k) {
         RUN(h, st, "sweep", l, N * 3 * s,
-            launch_sweep(D, L.prec, L.P, bbuf(h, l), cbuf(h, l, cur), cbuf(h, l, cur ^ 1), h->opt.omega, L.sh, st));
+            launch_sweep(D, L.prec, L.P, bbuf(h, l), cbuf(h, l, cur), cbuf(h, l, cur ^ 1), h->opt.omega,
+                         L.shs[SH_SWEEP], st));
         cur ^= 1;
     }
     h->cur[l] = cur;
@@ -240,7 +276,7 @@ hipError_t enq_prolong(mg_ctx *h, hipStream_t st, int l, const void *b) {
     const int cur = h->cur[l];
     RUN(h, st, "prolong_sweep", l, bytes,
         launch_prolong(h->dim, L.prec, C.prec, L.P, cbuf(h, l, cur), cbuf(h, l + 1, h->cur[l + 1]), b,
-                       cbuf(h, l, cur ^ 1), h->opt.omega, true, L.sh, st));
+                       cbuf(h, l, cur ^ 1), h->opt.omega, true, L.shs[SH_PROLONG], st));
     h->cur[l] = cur ^ 1;
     return hipSuccess;
 }
@@ -251,7 +287,8 @@ hipError_t enq_post(mg_ctx *h, hipStream_t st, int l, const void *b) {
     for (int k = 1; k < h->opt.nu2; ++k) {
         const int cur = h->cur[l];
         RUN(h, st, "sweep", l, N * 3 * sb(L.prec),
-            launch_sweep(h->dim, L.prec, L.P, b, cbuf(h, l, cur), cbuf(h, l, cur ^ 1), h->opt.omega, L.sh, st));
+            launch_sweep(h->dim, L.prec, L.P, b, cbuf(h, l, cur), cbuf(h, l, cur ^ 1), h->opt.omega,
+                         L.shs[SH_SWEEP], st));
         h->cur[l] = cur ^ 1;
     }
     return hipSuccess;
@@ -274,12 +311,12 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
             const bool two = h->opt.nu1 >= 2;
             RUN(h, st, two ? "smooth2" : "smooth1", 0, N * 16,
                 launch_smooth_first(h->dim, P_F64, L.P, Rbuf(h), nullptr, nullptr, nullptr, cbuf(h, 0, 0),
-                                    h->opt.omega, two, L.sh, st));
+                                    h->opt.omega, two, L.shs[SH_SMOOTH], st));
             int cur = 0;
             for (int k = two ? 2 : 1; k < h->opt.nu1; ++k) {
                 RUN(h, st, "sweep", 0, N * 24,
                     launch_sweep(h->dim, P_F64, L.P, Rbuf(h), cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), h->opt.omega,
-                                 L.sh, st));
+                                 L.shs[SH_SWEEP], st));
                 cur ^= 1;
             }
             h->cur[0] = cur;
@@ -337,6 +374,10 @@ mg_status_t ensure_graph(mg_ctx *h) {
     HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
     return MG_OK;
 }
+
+void build_batched_plan(mg_ctx *h, char *base);
+hipError_t enq_batched_step(mg_ctx *h, hipStream_t st);
+hipError_t enq_multi_step(mg_ctx *h, hipStream_t st);
 
 mg_status_t need_ws(mg_ctx *h) {
     if (!h) return fail(MG_ERR_ARG, "null handle");
@@ -415,26 +456,31 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
     for (int l = 0; l + 1 < h->nl; ++l) {
         LevelPlan &L = h->lv[l];
         if (L.P < 8) continue;
-        // smoothing family: first pre-smoothing + sweep + prolongation/sweep
-        float best = 1e30f;
-        Shape bs = L.sh;
-        for (const Shape &s : stencil_candidates(h, L, false)) {
-            L.sh = s;
-            const float t = time_ms(st, [&]() -> hipError_t {
-                hipError_t e = launch_smooth_first(D, L.prec, L.P, bbuf(h, l), nullptr, nullptr, nullptr,
-                                                   cbuf(h, l, 0), h->opt.omega, true, s, st);
-                if (e == hipSuccess)
-                    e = launch_sweep(D, L.prec, L.P, bbuf(h, l), cbuf(h, l, 0), cbuf(h, l, 1), h->opt.omega, s, st);
-                if (e == hipSuccess)
-                    e = launch_prolong(D, L.prec, h->lv[l + 1].prec, L.P, cbuf(h, l, 1), cbuf(h, l + 1, 0),
-                                       bbuf(h, l), cbuf(h, l, 0), h->opt.omega, true, s, st);
-                return e;
-            }, 3);
-            if (t < best) best = t, bs = s;
+        // each smoothing-family kernel separately; on the finest level the
+        // first pre-smoothing is timed in the form the refinement loop uses
+        const bool scaled0 = l == 0 && !finest_alias(h);
+        const void *b0 = (l == 0 && finest_alias(h)) ? (const void *)Rbuf(h) : bbuf(h, l);
+        for (int fam = 0; fam < 3; ++fam) {
+            float best = 1e30f;
+            Shape bs = L.shs[fam];
+            for (const Shape &s : stencil_candidates(h, L, false)) {
+                const float t = time_ms(st, [&]() -> hipError_t {
+                    if (fam == SH_SMOOTH)
+                        return scaled0 ? launch_smooth_first(D, L.prec, L.P, nullptr, Rbuf(h), scal(h), bbuf(h, l),
+                                                             cbuf(h, l, 0), h->opt.omega, true, s, st)
+                                       : launch_smooth_first(D, L.prec, L.P, b0, nullptr, nullptr, nullptr,
+                                                             cbuf(h, l, 0), h->opt.omega, true, s, st);
+                    if (fam == SH_SWEEP)
+                        return launch_sweep(D, L.prec, L.P, b0, cbuf(h, l, 0), cbuf(h, l, 1), h->opt.omega, s, st);
+                    return launch_prolong(D, L.prec, h->lv[l + 1].prec, L.P, cbuf(h, l, 1), cbuf(h, l + 1, 0), b0,
+                                          cbuf(h, l, 0), h->opt.omega, true, s, st);
+                }, 3);
+                if (t < best) best = t, bs = s;
+            }
+            L.shs[fam] = bs;
         }
-        L.sh = bs;
         // residual + restriction
-        best = 1e30f;
+        float best = 1e30f;
         RShape br = L.rsh;
         for (int V : {4, 8})
             for (int tyc : {1, 2, 3, 4, 5, 7})
@@ -555,7 +601,7 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         L.off_c[1] = off;
         off += bytes;
         if (nn > 1) {
-            L.sh = pick_shape(dim, L.P, L.prec);
+            L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = pick_shape(dim, L.P, L.prec);
             L.osh = pick_shape(dim, L.P, P_F64);  // FP64 rows dominate the update's registers
             L.rsh = pick_rshape(dim, L.P, L.prec);
         }
@@ -602,6 +648,23 @@ mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *st
     HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int l = 0; l < h->nl; ++l) h->cur[l] = 0;
+    if (h->nrhs) {
+        const int K = h->nrhs;
+        if (!h->host_mask) HIPCHK(hipHostMalloc((void **)&h->host_mask, 2 * sizeof(int) * K, hipHostMallocDefault));
+        if (!h->host_scal_m) HIPCHK(hipHostMalloc((void **)&h->host_scal_m, 4 * sizeof(double) * K, hipHostMallocDefault));
+        return MG_OK;
+    }
+    if (h->batched) {
+        const int ni = (int)h->inst.size();
+        if (!h->host_active) HIPCHK(hipHostMalloc((void **)&h->host_active, sizeof(int) * ni, hipHostMallocDefault));
+        if (!h->host_scal_all)
+            HIPCHK(hipHostMalloc((void **)&h->host_scal_all, 4 * sizeof(double) * ni, hipHostMallocDefault));
+        build_batched_plan(h, h->ws);
+        HIPCHK(hipMemcpy(h->ws + h->off_bmeta, h->bmeta_img_tmp.data(), h->bmeta_img_tmp.size(),
+                         hipMemcpyHostToDevice));
+        h->bmeta_img_tmp.clear();
+        return MG_OK;
+    }
     if (h->opt.autotune) {
         mg_status_t s = autotune(h, st);
         if (s != MG_OK) return s;
@@ -614,6 +677,10 @@ mg_status_t mg_destroy(mg_handle h) {
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
+    if (h->host_active) (void)hipHostFree(h->host_active);
+    if (h->host_scal_all) (void)hipHostFree(h->host_scal_all);
+    if (h->host_mask) (void)hipHostFree(h->host_mask);
+    if (h->host_scal_m) (void)hipHostFree(h->host_scal_m);
     delete h;
     return MG_OK;
 }
@@ -626,6 +693,7 @@ mg_status_t mg_levels(mg_handle h, int *nlevels) {
 
 mg_status_t mg_level_n(mg_handle h, int level, int *n) {
     if (!h || !n) return fail(MG_ERR_ARG, "null argument");
+    if (h->batched) return fail(MG_ERR_STATE, "not available on a batched handle");
     if (level < 0 || level >= h->nl) return fail(MG_ERR_ARG, "level %d out of range", level);
     *n = h->lv[level].n;
     return MG_OK;
@@ -650,6 +718,7 @@ mg_status_t mg_level_write(mg_handle h, int level, mg_buffer_t buf, const void *
                            void *stream) {
     mg_status_t s = need_ws(h);
     if (s != MG_OK) return s;
+    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
     if (!src) return fail(MG_ERR_ARG, "src is null");
     if (!valid_prec(src_prec)) return fail(MG_ERR_PREC, "src_prec %d", (int)src_prec);
     void *p;
@@ -663,6 +732,7 @@ mg_status_t mg_level_write(mg_handle h, int level, mg_buffer_t buf, const void *
 mg_status_t mg_level_read(mg_handle h, int level, mg_buffer_t buf, void *dst, mg_prec_t dst_prec, void *stream) {
     mg_status_t s = need_ws(h);
     if (s != MG_OK) return s;
+    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
     if (!dst) return fail(MG_ERR_ARG, "dst is null");
     if (!valid_prec(dst_prec)) return fail(MG_ERR_PREC, "dst_prec %d", (int)dst_prec);
     void *p;
@@ -676,6 +746,7 @@ mg_status_t mg_level_read(mg_handle h, int level, mg_buffer_t buf, void *dst, mg
 mg_status_t mg_stage(mg_handle h, mg_stage_t stage, int level, void *stream) {
     mg_status_t s = need_ws(h);
     if (s != MG_OK) return s;
+    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
     if (level < 0 || level >= h->nl) return fail(MG_ERR_ARG, "level %d out of range", level);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool base = level == h->nl - 1;
@@ -690,7 +761,7 @@ mg_status_t mg_stage(mg_handle h, mg_stage_t stage, int level, void *stream) {
         LevelPlan &L = h->lv[level];
         const int cur = h->cur[level];
         e = launch_sweep(h->dim, L.prec, L.P, bbuf(h, level), cbuf(h, level, cur), cbuf(h, level, cur ^ 1),
-                         h->opt.omega, L.sh, st);
+                         h->opt.omega, L.shs[SH_SWEEP], st);
         if (e == hipSuccess) h->cur[level] = cur ^ 1;
         break;
     }
@@ -716,6 +787,7 @@ mg_status_t mg_stage(mg_handle h, mg_stage_t stage, int level, void *stream) {
 mg_status_t mg_vcycle(mg_handle h, const void *b, void *c, void *stream) {
     mg_status_t s = need_ws(h);
     if (s != MG_OK) return s;
+    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
     if (!b || !c) return fail(MG_ERR_ARG, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     LevelPlan &L = h->lv[0];
@@ -729,6 +801,8 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     auto t0 = std::chrono::steady_clock::now();
     mg_status_t s = need_ws(h);
     if (s != MG_OK) return s;
+    if (h->batched) return fail(MG_ERR_STATE, "use ir_solve_batched on a batched handle");
+    if (h->nrhs) return fail(MG_ERR_STATE, "use ir_solve_multi on a many-right-hand-side handle");
     if (!b || !u) return fail(MG_ERR_ARG, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     LevelPlan &L = h->lv[0];
@@ -836,10 +910,13 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
 
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np) {
     if (!h || !p) return fail(MG_ERR_ARG, "null argument");
+    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
     LevelPlan &L = h->lv[level];
     const int D = h->dim;
-    if (kind == MG_SHAPE_STENCIL || kind == MG_SHAPE_UPDATE) {
+    const bool stencil_kind = kind == MG_SHAPE_STENCIL || kind == MG_SHAPE_UPDATE || kind == MG_SHAPE_SMOOTH ||
+                              kind == MG_SHAPE_SWEEP || kind == MG_SHAPE_PROLONG;
+    if (stencil_kind) {
         if (kind == MG_SHAPE_UPDATE && level != 0) return fail(MG_ERR_ARG, "the update shape exists on level 0 only");
         if (np != 5) return fail(MG_ERR_ARG, "stencil shape takes 5 values {V, zc, bs, xcd, ty}");
         Shape s{p[0], p[1], p[2], p[3], p[4]};
@@ -854,8 +931,10 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
             if (stencil_blocks(D, L.P, s) > h->max_parts) return fail(MG_ERR_ARG, "too many blocks");
             L.osh = s;
             h->outer_parts = stencil_blocks(D, L.P, s);
+        } else if (kind == MG_SHAPE_STENCIL) {
+            L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = s;
         } else {
-            L.sh = s;
+            L.shs[kind == MG_SHAPE_SMOOTH ? SH_SMOOTH : kind == MG_SHAPE_SWEEP ? SH_SWEEP : SH_PROLONG] = s;
         }
     } else if (kind == MG_SHAPE_RESTRICT) {
         if (np != 4) return fail(MG_ERR_ARG, "restriction shape takes 4 values {V, tyc, zcc, pipe}");
@@ -873,10 +952,16 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
 
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
     if (!h || !p) return fail(MG_ERR_ARG, "null argument");
+    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
     const LevelPlan &L = h->lv[level];
-    if ((kind == MG_SHAPE_STENCIL || (kind == MG_SHAPE_UPDATE && level == 0)) && np >= 5) {
-        const Shape &S = kind == MG_SHAPE_STENCIL ? L.sh : L.osh;
+    const bool stencil_kind = kind == MG_SHAPE_STENCIL || kind == MG_SHAPE_SMOOTH || kind == MG_SHAPE_SWEEP ||
+                              kind == MG_SHAPE_PROLONG || (kind == MG_SHAPE_UPDATE && level == 0);
+    if (stencil_kind && np >= 5) {
+        const Shape &S = kind == MG_SHAPE_UPDATE   ? L.osh
+                         : kind == MG_SHAPE_SMOOTH  ? L.shs[SH_SMOOTH]
+                         : kind == MG_SHAPE_PROLONG ? L.shs[SH_PROLONG]
+                                                    : L.shs[SH_SWEEP];
         p[0] = S.V, p[1] = S.zc, p[2] = S.bs, p[3] = S.xcd, p[4] = S.ty;
     } else if (kind == MG_SHAPE_RESTRICT && np >= 4) {
         p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc, p[3] = L.rsh.pipe;
@@ -899,9 +984,20 @@ mg_status_t mg_profile_step(mg_handle h, void *stream, int cap, int *count, cons
     if (s != MG_OK) return s;
     if (!count || cap < 0) return fail(MG_ERR_ARG, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (h->batched) {
+        // profile a step of every instance from its current state
+        const int ni = (int)h->inst.size();
+        for (int i = 0; i < ni; ++i) h->host_active[i] = 1;
+        HIPCHK(hipMemcpyAsync(h->ws + h->off_active, h->host_active, sizeof(int) * ni, hipMemcpyHostToDevice, st));
+    }
     h->prof = true;
     h->recs.clear();
-    hipError_t e = enq_step(h, st);
+    if (h->nrhs) {
+        for (int k = 0; k < h->nrhs; ++k) h->host_mask[k] = 1;
+        HIPCHK(hipMemcpyAsync(h->ws + h->off_act, h->host_mask, sizeof(int) * h->nrhs, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    hipError_t e = h->batched ? enq_batched_step(h, st) : h->nrhs ? enq_multi_step(h, st) : enq_step(h, st);
     h->prof = false;
     hipError_t e2 = hipStreamSynchronize(st);
     int i = 0;
@@ -922,6 +1018,827 @@ mg_status_t mg_profile_step(mg_handle h, void *stream, int cap, int *count, cons
     h->recs.clear();
     if (e != hipSuccess) return fail(MG_ERR_HIP, "profiled step failed: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(MG_ERR_HIP, "profiled step failed: %s", hipGetErrorString(e2));
+    return MG_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batched instances
+// ============================================================================
+namespace {
+
+Shape batched_shape(int P, int prec) {
+    Shape s = pick_shape(3, P, prec);
+    // the batched path uses the register-queue kernel (block size fixed at 256)
+    s.ty = 0;
+    s.V = (P >= 8 && prec != P_F64) ? 8 : 4;
+    s.bs = 256;
+    const long per_chunk = (long)(P / s.V) * P;
+    const long nch = ((1L << 17) + per_chunk - 1) / per_chunk;
+    s.zc = std::max(1, std::min((int)((P - 1 + nch - 1) / nch), 32));
+    return s;
+}
+
+RShape batched_rshape(int P, int pf) {
+    RShape r;
+    r.V = (P >= 8 && pf != P_F64) ? 8 : 4;
+    r.pipe = 0;
+    const int TXR = P / r.V, Pc = P / 2;
+    const size_t acc = pf == P_F64 ? 8 : 4;
+    int tyc = std::max(1, std::min(7, Pc - 1));
+    while (tyc > 1 && ((2 * tyc + 1) * TXR > 1024 || 2 * (size_t)(2 * tyc + 1) * P * acc > 65536)) --tyc;
+    r.tyc = tyc;
+    const int ytiles = (Pc - 1 + tyc - 1) / tyc;
+    const int nzc = std::max(1, (256 + ytiles - 1) / ytiles);
+    r.zcc = std::max(1, (Pc - 1 + nzc - 1) / nzc);
+    return r;
+}
+
+int bprec_of(const mg_ctx *h, int i, int l) {
+    return l == h->inst[i].nl - 1 ? h->bprec[h->Lmax - 1] : h->bprec[l];
+}
+
+// Build the batched stage list and the descriptor / item image for the
+// workspace at `base` (nullptr only to size the image).
+void build_batched_plan(mg_ctx *h, char *base) {
+    const int ni = (int)h->inst.size();
+    const bool alias = h->bprec[0] == P_F64 && !h->opt.residual_scaling;
+    std::vector<BDesc> descs;
+    std::vector<BItem> items;
+    std::vector<BFin> fins;
+    h->bl.clear();
+    std::vector<std::vector<int>> cur(ni, std::vector<int>(h->Lmax, 0));
+    // addresses are formed as integers so that sizing with base == nullptr is defined
+    auto at = [&](size_t off) { return reinterpret_cast<char *>(reinterpret_cast<uintptr_t>(base) + off); };
+    auto B = [&](int i, int l) -> void * { return at(h->inst[i].lv[l].off_b); };
+    auto C = [&](int i, int l, int w) -> void * { return at(h->inst[i].lv[l].off_c[w]); };
+    auto Rp = [&](int i) { return reinterpret_cast<double *>(at(h->inst[i].off_R)); };
+    auto Up = [&](int i) { return reinterpret_cast<double *>(at(h->inst[i].off_U)); };
+    auto Sp = [&](int i) { return reinterpret_cast<double *>(at(h->off_scal_all + 32 * (size_t)i)); };
+    auto rhs = [&](int i, int l) -> const void * { return (l == 0 && alias) ? (const void *)Rp(i) : B(i, l); };
+    // group descriptors by (V, pc) into launches
+    struct Pend {
+        BDesc d;
+        int V, pc, nblk;
+    };
+    auto flush = [&](int what, int kind, int pf, const char *name, int level, std::vector<Pend> &pend,
+                     double bytes_per_point) {
+        std::vector<std::pair<int, int>> keys;
+        for (auto &p : pend)
+            if (std::find(keys.begin(), keys.end(), std::make_pair(p.V, p.pc)) == keys.end())
+                keys.push_back({p.V, p.pc});
+        for (auto &k : keys) {
+            mg_ctx::BLaunch L{};
+            L.what = what, L.kind = kind, L.V = k.first, L.pf = pf, L.pc = k.second;
+            L.off_desc = descs.size(), L.off_items = items.size();
+            L.name = name, L.level = level;
+            int maxthreads = 0;
+            size_t maxlds = 0;
+            double pts = 0;
+            for (auto &p : pend) {
+                if (p.V != k.first || p.pc != k.second) continue;
+                const int di = (int)(descs.size() - L.off_desc);
+                descs.push_back(p.d);
+                for (int b = 0; b < p.nblk; ++b) items.push_back(BItem{di, b});
+                pts += (double)(p.d.P - 1) * (p.d.P - 1) * (p.d.P - 1);
+                if (what == 1) {
+                    maxthreads = std::max(maxthreads, (2 * p.d.tyc + 1) * (p.d.P / p.V));
+                    maxlds = std::max(maxlds, 2 * (size_t)(2 * p.d.tyc + 1) * p.d.P * (pf == P_F64 ? 8 : 4));
+                }
+            }
+            L.ndesc = (int)(descs.size() - L.off_desc);
+            L.nitems = (int)(items.size() - L.off_items);
+            L.grid = std::max(1, std::min(L.nitems, what == 1 ? 1024 : 4096));
+            L.threads = what == 1 ? ((maxthreads + 63) / 64) * 64 : 256;
+            L.lds = maxlds;
+            L.bytes = pts * bytes_per_point;
+            h->bl.push_back(L);
+        }
+        pend.clear();
+    };
+    std::vector<Pend> pend;
+    const double omega = h->opt.omega;
+    (void)omega;
+    for (int d = 0; d + 1 < h->Lmax; ++d) {
+        const int pf = h->bprec[d];
+        const double s = (double)prec_bytes(pf);
+        // first pre-smoothing (two sweeps fused)
+        for (int i = 0; i < ni; ++i) {
+            if (d > h->inst[i].nl - 2) continue;
+            const LevelPlan &L = h->inst[i].lv[d];
+            BDesc x{};
+            x.b = (d == 0) ? (const void *)Rp(i) : B(i, d);
+            x.cout = C(i, d, 0);
+            x.bout = B(i, d);
+            x.scal = Sp(i);
+            x.P = L.P, x.zc = L.shs[SH_SMOOTH].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
+            pend.push_back({x, L.shs[SH_SMOOTH].V, P_F64, stencil_blocks(3, L.P, L.shs[SH_SMOOTH])});
+            cur[i][d] = 0;
+        }
+        const bool scaled = d == 0 && !alias;
+        flush(0, scaled ? BK_SMOOTH2_SCALED : BK_SMOOTH2, pf, scaled ? "smooth2_scaled" : "smooth2", d, pend,
+              scaled ? 8 + 2 * s : 2 * s);
+        for (int k = 2; k < h->opt.nu1; ++k) {
+            for (int i = 0; i < ni; ++i) {
+                if (d > h->inst[i].nl - 2) continue;
+                const LevelPlan &L = h->inst[i].lv[d];
+                BDesc x{};
+                x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = C(i, d, cur[i][d] ^ 1);
+                x.P = L.P, x.zc = L.shs[SH_SWEEP].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
+                pend.push_back({x, L.shs[SH_SWEEP].V, P_F64, stencil_blocks(3, L.P, L.shs[SH_SWEEP])});
+                cur[i][d] ^= 1;
+            }
+            flush(0, BK_SWEEP, pf, "sweep", d, pend, 3 * s);
+        }
+        for (int i = 0; i < ni; ++i) {
+            if (d > h->inst[i].nl - 2) continue;
+            const LevelPlan &L = h->inst[i].lv[d];
+            BDesc x{};
+            x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = B(i, d + 1);
+            x.P = L.P, x.tyc = L.rsh.tyc, x.zcc = L.rsh.zcc;
+            x.ytiles = (L.P / 2 - 1 + x.tyc - 1) / x.tyc, x.inst = i;
+            pend.push_back({x, L.rsh.V, bprec_of(h, i, d + 1), restrict_blocks(3, L.P, L.rsh)});
+        }
+        flush(1, 0, pf, "resid_restrict", d, pend, 2 * s);
+    }
+    for (int i = 0; i < ni; ++i) {
+        const int lb = h->inst[i].nl - 1;
+        BDesc x{};
+        x.b = B(i, lb), x.cout = C(i, lb, 0), x.inst = i;
+        cur[i][lb] = 0;
+        descs.push_back(x);
+    }
+    {
+        mg_ctx::BLaunch L{};
+        L.what = 2, L.pf = h->bprec[h->Lmax - 1], L.off_desc = descs.size() - ni, L.ndesc = ni, L.name = "coarse_solve";
+        L.level = h->Lmax - 1;
+        h->bl.push_back(L);
+    }
+    for (int d = h->Lmax - 2; d >= 0; --d) {
+        const int pf = h->bprec[d];
+        const double s = (double)prec_bytes(pf);
+        for (int i = 0; i < ni; ++i) {
+            if (d > h->inst[i].nl - 2) continue;
+            const LevelPlan &L = h->inst[i].lv[d];
+            BDesc x{};
+            x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.ec = C(i, d + 1, cur[i][d + 1]);
+            x.cout = C(i, d, cur[i][d] ^ 1);
+            x.P = L.P, x.zc = L.shs[SH_PROLONG].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
+            pend.push_back({x, L.shs[SH_PROLONG].V, bprec_of(h, i, d + 1), stencil_blocks(3, L.P, L.shs[SH_PROLONG])});
+            cur[i][d] ^= 1;
+        }
+        flush(0, BK_PROLONG, pf, "prolong_sweep", d, pend, 3 * s);
+        for (int k = 1; k < h->opt.nu2; ++k) {
+            for (int i = 0; i < ni; ++i) {
+                if (d > h->inst[i].nl - 2) continue;
+                const LevelPlan &L = h->inst[i].lv[d];
+                BDesc x{};
+                x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = C(i, d, cur[i][d] ^ 1);
+                x.P = L.P, x.zc = L.shs[SH_SWEEP].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
+                pend.push_back({x, L.shs[SH_SWEEP].V, P_F64, stencil_blocks(3, L.P, L.shs[SH_SWEEP])});
+                cur[i][d] ^= 1;
+            }
+            flush(0, BK_SWEEP, pf, "sweep", d, pend, 3 * s);
+        }
+    }
+    double *part_base = reinterpret_cast<double *>(at(h->off_part));
+    for (int i = 0; i < ni; ++i) {
+        const LevelPlan &L = h->inst[i].lv[0];
+        const double hh = 1.0 / (double)(L.n + 1);
+        BDesc x{};
+        x.cin = C(i, 0, cur[i][0]), x.R = Rp(i), x.U = Up(i), x.scal = Sp(i), x.h2 = hh * hh;
+        x.P = L.P, x.zc = h->inst[i].osh.zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc;
+        x.part_off = h->inst[i].part_off, x.inst = i;
+        pend.push_back({x, h->inst[i].osh.V, P_F64, stencil_blocks(3, L.P, h->inst[i].osh)});
+        fins.push_back(
+            BFin{part_base + 2 * (size_t)h->inst[i].part_off, stencil_blocks(3, L.P, h->inst[i].osh), Sp(i)});
+    }
+    flush(0, BK_OUTER, h->bprec[0], "ir_update", 0, pend, 32 + (double)prec_bytes(h->bprec[0]));
+    {
+        mg_ctx::BLaunch L{};
+        L.what = 3, L.name = "norm_finalize", L.level = 0;
+        h->bl.push_back(L);
+    }
+    // image: descriptors, then items, then finalize records
+    const size_t nd = descs.size() * sizeof(BDesc), nit = items.size() * sizeof(BItem), nf = fins.size() * sizeof(BFin);
+    const size_t off_items = align_up(nd, 256), off_fin = off_items + align_up(nit, 256);
+    h->bmeta_bytes = off_fin + align_up(nf, 256);
+    if (base) {
+        std::vector<unsigned char> img(h->bmeta_bytes, 0);
+        std::memcpy(img.data(), descs.data(), nd);
+        std::memcpy(img.data() + off_items, items.data(), nit);
+        std::memcpy(img.data() + off_fin, fins.data(), nf);
+        const BDesc *dd = reinterpret_cast<const BDesc *>(at(h->off_bmeta));
+        const BItem *ii = reinterpret_cast<const BItem *>(at(h->off_bmeta + off_items));
+        for (auto &L : h->bl) {
+            L.off_desc = reinterpret_cast<size_t>(dd + L.off_desc);
+            L.off_items = reinterpret_cast<size_t>(ii + L.off_items);
+        }
+        h->off_fin = h->off_bmeta + off_fin;
+        // the caller copies img into the workspace
+        h->bmeta_img_tmp = std::move(img);
+    }
+}
+
+hipError_t enq_batched_step(mg_ctx *h, hipStream_t st) {
+    const int *act = reinterpret_cast<const int *>(h->ws + h->off_active);
+    double *part_base = reinterpret_cast<double *>(h->ws + h->off_part);
+    for (auto &L : h->bl) {
+        const BDesc *d = reinterpret_cast<const BDesc *>(L.off_desc);
+        const BItem *it = reinterpret_cast<const BItem *>(L.off_items);
+        if (L.what == 0) {
+            RUN(h, st, L.name, L.level, L.bytes,
+                launch_batched_stencil(L.kind, L.V, L.pf, L.pc, d, it, L.nitems, act, h->opt.omega, part_base,
+                                       L.grid, st));
+        } else if (L.what == 1) {
+            RUN(h, st, L.name, L.level, L.bytes,
+                launch_batched_restrict(L.V, L.pf, L.pc, d, it, L.nitems, act, L.grid, L.threads, L.lds, st));
+        } else if (L.what == 2) {
+            RUN(h, st, L.name, L.level, 0.0, launch_batched_coarse(L.pf, d, L.ndesc, act, st));
+        } else {
+            RUN(h, st, L.name, 0, 0.0,
+                launch_batched_finalize(reinterpret_cast<const BFin *>(h->ws + h->off_fin), (int)h->inst.size(), act,
+                                        h->opt.residual_scaling, st));
+        }
+    }
+    return hipMemcpyAsync(h->host_scal_all, h->ws + h->off_scal_all, 4 * sizeof(double) * h->inst.size(),
+                          hipMemcpyDeviceToHost, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, const mg_prec_t *level_prec,
+                             const mg_options_t *opt) {
+    if (!out || !n) return fail(MG_ERR_ARG, "null argument");
+    if (dim != 3) return fail(MG_ERR_SHAPE, "batched instances are 3-D (dim = 3)");
+    if (ninst < 1 || ninst > 4096) return fail(MG_ERR_ARG, "ninst must be in 1..4096");
+    mg_options_t o;
+    mg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
+        return fail(MG_ERR_ARG, "batched solves need 2 <= nu1 <= 16 and 1 <= nu2 <= 16");
+    if (!(o.omega > 0.0 && o.omega < 2.0) || o.max_iter < 0 || !(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "bad options");
+    int Lmax = 0;
+    for (int i = 0; i < ninst; ++i) {
+        if (n[i] < 3 || n[i] > 1023 || ((n[i] + 1) & n[i]) != 0)
+            return fail(MG_ERR_SHAPE, "instance %d: n must be 2^m - 1 with 2 <= m <= 10, got %d", i, n[i]);
+        int m = 0;
+        while ((1 << m) < n[i] + 1) ++m;
+        Lmax = std::max(Lmax, m);
+    }
+    std::vector<int> prec(Lmax, P_F64);
+    if (level_prec)
+        for (int l = 0; l < Lmax; ++l) {
+            if (!valid_prec((int)level_prec[l])) return fail(MG_ERR_PREC, "level_prec[%d] is not a format", l);
+            prec[l] = (int)level_prec[l];
+        }
+    mg_ctx *h = new mg_ctx();
+    h->batched = true;
+    h->dim = 3;
+    h->opt = o;
+    h->Lmax = Lmax;
+    h->bprec = prec;
+    h->inst.resize(ninst);
+    size_t off = 0;
+    int parts = 0;
+    for (int i = 0; i < ninst; ++i) {
+        auto &I = h->inst[i];
+        I.n = n[i];
+        int m = 0;
+        while ((1 << m) < n[i] + 1) ++m;
+        I.nl = m;
+        I.lv.resize(m);
+        int nn = n[i];
+        for (int l = 0; l < m; ++l) {
+            LevelPlan &L = I.lv[l];
+            L.n = nn, L.P = nn + 1;
+            L.prec = l == m - 1 ? prec[Lmax - 1] : prec[l];
+            L.elems = level_elems(3, L.P);
+            const size_t bytes = align_up(L.elems * prec_bytes(L.prec), 256);
+            L.off_b = off, off += bytes;
+            L.off_c[0] = off, off += bytes;
+            L.off_c[1] = off, off += bytes;
+            if (nn > 1) {
+                L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = batched_shape(L.P, L.prec);
+                L.rsh = batched_rshape(L.P, L.prec);
+            }
+            nn = (nn - 1) / 2;
+        }
+        const size_t fin = align_up(I.lv[0].elems * sizeof(double), 256);
+        I.off_R = off, off += fin;
+        I.off_U = off, off += fin;
+        I.osh = batched_shape(I.lv[0].P, P_F64);
+        I.osh.V = 4;
+        I.part_off = parts;
+        I.parts = std::max(stencil_blocks(3, I.lv[0].P, I.osh), flat_blocks(points(3, n[i])));
+        parts += I.parts;
+    }
+    h->max_parts = parts;
+    h->off_part = off, off += align_up((size_t)parts * 2 * sizeof(double), 256);
+    h->off_scal_all = off, off += align_up((size_t)ninst * 4 * sizeof(double), 256);
+    h->off_active = off, off += align_up((size_t)ninst * sizeof(int), 256);
+    h->off_bmeta = off;
+    build_batched_plan(h, nullptr);
+    off += h->bmeta_bytes;
+    h->ws_need = off;
+    h->nl = Lmax;
+    h->n = n[0];
+    *out = h;
+    return MG_OK;
+}
+
+mg_status_t ir_solve_batched(mg_handle h, const double *const *b, double *const *u, mg_stats_t *stats,
+                             void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!h) return fail(MG_ERR_ARG, "null handle");
+    if (!h->batched) return fail(MG_ERR_STATE, "ir_solve_batched needs a handle from mg_setup_batched");
+    mg_status_t s = need_ws(h);
+    if (s != MG_OK) return s;
+    if (!b || !u) return fail(MG_ERR_ARG, "null argument");
+    const int ni = (int)h->inst.size();
+    for (int i = 0; i < ni; ++i)
+        if (!b[i] || !u[i]) return fail(MG_ERR_ARG, "null pointer for instance %d", i);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int scaling = h->opt.residual_scaling;
+    double *part_base = reinterpret_cast<double *>(h->ws + h->off_part);
+    double *scal_all = reinterpret_cast<double *>(h->ws + h->off_scal_all);
+    int *act_dev = reinterpret_cast<int *>(h->ws + h->off_active);
+    const double *hs = h->host_scal_all;
+    // per instance: ACTIVE (stepping), CHECK (recursive residual below tolerance,
+    // to be confirmed from u), DONE (u written), STOP (failed, u still to be
+    // written), DEAD (failed before any step; u untouched)
+    enum { ACTIVE, CHECK, DONE, STOP, DEAD };
+    std::vector<double> nb(ni, 0.0), rel(ni, 0.0);
+    std::vector<int> k(ni, 0), state(ni, ACTIVE);
+    std::vector<mg_status_t> st_i(ni, MG_OK);
+    auto hist = [&](int i, int kk, double v) {
+        if (stats && stats[i].history && kk < stats[i].history_cap) stats[i].history[kk] = v;
+    };
+    auto readback = [&]() -> mg_status_t {
+        HIPCHK(hipMemcpyAsync(h->host_scal_all, scal_all, 4 * sizeof(double) * ni, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return MG_OK;
+    };
+    // r = b - A u of instance i into R (and u copied out to uout) with its norms;
+    // with use_u == false, r = b
+    auto resid = [&](int i, bool use_u, double *uout) -> hipError_t {
+        const auto &I = h->inst[i];
+        const LevelPlan &L = I.lv[0];
+        const double hh = 1.0 / (double)(L.n + 1);
+        double *part = part_base + 2 * (size_t)I.part_off;
+        hipError_t e = launch_resid_flat(3, L.n, L.P, b[i], use_u ? (const double *)(h->ws + I.off_U) : nullptr,
+                                         reinterpret_cast<double *>(h->ws + I.off_R), uout, 1.0 / (hh * hh), part, st);
+        if (e == hipSuccess) e = launch_finalize(part, flat_blocks(points(3, L.n)), scal_all + 4 * i, scaling, st);
+        return e;
+    };
+    // ||b||_2 of every instance, and the initial residual
+    for (int i = 0; i < ni; ++i) {
+        const auto &I = h->inst[i];
+        if (h->opt.use_initial_guess) {
+            HIPCHK(launch_resid_flat(3, I.n, I.lv[0].P, b[i], nullptr, nullptr, nullptr, 1.0,
+                                     part_base + 2 * (size_t)I.part_off, st));
+            HIPCHK(launch_finalize(part_base + 2 * (size_t)I.part_off, flat_blocks(points(3, I.n)), scal_all + 4 * i,
+                                   scaling, st));
+        } else {
+            HIPCHK(resid(i, false, nullptr));
+            HIPCHK(launch_fill_zero(h->ws + I.off_U, align_up(I.lv[0].elems * sizeof(double), 16), st));
+        }
+    }
+    if ((s = readback()) != MG_OK) return s;
+    bool any_guess = false;
+    for (int i = 0; i < ni; ++i) {
+        nb[i] = hs[4 * i + 2];
+        if (!std::isfinite(nb[i])) {
+            state[i] = DEAD, st_i[i] = MG_ERR_NONFINITE, rel[i] = NAN;
+        } else if (nb[i] == 0.0) {
+            HIPCHK(hipMemsetAsync(u[i], 0, sizeof(double) * points(3, h->inst[i].n), st));
+            state[i] = DONE;
+            hist(i, 0, 0.0);
+        } else if (h->opt.use_initial_guess) {
+            const auto &I = h->inst[i];
+            HIPCHK(launch_pack(3, P_F64, P_F64, I.n, I.lv[0].P, u[i], h->ws + I.off_U, st));
+            HIPCHK(resid(i, true, nullptr));
+            any_guess = true;
+        }
+    }
+    if (any_guess && (s = readback()) != MG_OK) return s;
+    const bool graph = h->opt.use_graph && !h->prof;
+    if (graph && !h->gexec) {
+        if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enq_batched_step(h, h->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(MG_ERR_HIP, "capture of the batched step failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        h->graph = g;
+        HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    }
+    for (;;) {
+        // classify the stepping instances on their latest residual norms
+        int nact = 0, ncheck = 0;
+        for (int i = 0; i < ni; ++i) {
+            if (state[i] != ACTIVE) continue;
+            const double rn = hs[4 * i + 2];
+            rel[i] = rn / nb[i];
+            hist(i, k[i], rel[i]);
+            if (!std::isfinite(rn)) {
+                state[i] = STOP, st_i[i] = MG_ERR_NONFINITE;
+            } else if (rn <= h->opt.rtol * nb[i]) {
+                // a residual that was updated recursively is confirmed from u
+                state[i] = k[i] > 0 ? CHECK : STOP;
+                ncheck += k[i] > 0;
+            } else if (k[i] >= h->opt.max_iter) {
+                state[i] = STOP, st_i[i] = MG_ERR_NOT_CONVERGED;
+            } else {
+                ++nact;
+            }
+        }
+        if (ncheck > 0) {
+            for (int i = 0; i < ni; ++i)
+                if (state[i] == CHECK) HIPCHK(resid(i, true, u[i]));
+            if ((s = readback()) != MG_OK) return s;
+            for (int i = 0; i < ni; ++i) {
+                if (state[i] != CHECK) continue;
+                const double rn = hs[4 * i + 2];
+                rel[i] = rn / nb[i];
+                hist(i, k[i], rel[i]);
+                if (rn <= h->opt.rtol * nb[i]) {
+                    state[i] = DONE;
+                } else if (!std::isfinite(rn) || k[i] >= h->opt.max_iter) {
+                    state[i] = DONE;  // u and rel already hold the final values
+                    st_i[i] = std::isfinite(rn) ? MG_ERR_NOT_CONVERGED : MG_ERR_NONFINITE;
+                } else {
+                    state[i] = ACTIVE;  // continue from the true residual
+                    ++nact;
+                }
+            }
+        }
+        if (nact == 0) break;
+        for (int i = 0; i < ni; ++i) h->host_active[i] = state[i] == ACTIVE;
+        HIPCHK(hipMemcpyAsync(act_dev, h->host_active, sizeof(int) * ni, hipMemcpyHostToDevice, st));
+        if (graph) {
+            HIPCHK(hipGraphLaunch(h->gexec, st));
+        } else {
+            hipError_t e = enq_batched_step(h, st);
+            if (e != hipSuccess) return fail(MG_ERR_HIP, "batched step failed: %s", hipGetErrorString(e));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i < ni; ++i)
+            if (state[i] == ACTIVE) ++k[i];
+    }
+    // instances that stopped without a confirmation: true residual and u
+    bool pending = false;
+    for (int i = 0; i < ni; ++i)
+        if (state[i] == STOP) {
+            HIPCHK(resid(i, true, u[i]));
+            pending = true;
+        }
+    if (pending) {
+        if ((s = readback()) != MG_OK) return s;
+        for (int i = 0; i < ni; ++i)
+            if (state[i] == STOP) rel[i] = hs[4 * i + 2] / nb[i];
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    mg_status_t result = MG_OK;
+    int first_bad = -1;
+    for (int i = 0; i < ni; ++i) {
+        if (stats) {
+            stats[i].iterations = k[i];
+            stats[i].rel_residual = nb[i] == 0.0 ? 0.0 : rel[i];
+            stats[i].seconds = secs;
+        }
+        if (st_i[i] != MG_OK && result == MG_OK) result = st_i[i], first_bad = i;
+    }
+    if (result != MG_OK) return fail(result, "%s (first in instance %d)", mg_status_string(result), first_bad);
+    return MG_OK;
+}
+
+mg_status_t mg_instances(mg_handle h, int *ninst) {
+    if (!h || !ninst) return fail(MG_ERR_ARG, "null argument");
+    *ninst = h->batched ? (int)h->inst.size() : 1;
+    return MG_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Many right-hand sides, interleaved
+// ============================================================================
+namespace {
+
+int m_zc(int prec, int P, int K) {
+    const long per_chunk = (long)(P - 1) * (K / m_vec(prec)) * (P - 1);
+    const long nch = std::max(1L, ((1L << 19) + per_chunk - 1) / per_chunk);
+    return std::max(1, std::min((int)((P - 1 + nch - 1) / nch), 64));
+}
+
+hipError_t enq_multi_step(mg_ctx *h, hipStream_t st) {
+    const int K = h->nrhs, nl = h->nl;
+    const bool alias = finest_alias(h);
+    double *sc = scal(h);
+    const int *act = at_ws<int>(h, h->off_act);
+    auto rhs = [&](int l) -> const void * { return (l == 0 && alias) ? (const void *)Rbuf(h) : bbuf(h, l); };
+    for (int l = 0; l + 1 < nl; ++l) {
+        LevelPlan &L = h->lv[l];
+        const double N = (double)points(3, L.n) * K;
+        const double s = sb(L.prec);
+        MArgs a;
+        a.prec = L.prec, a.P = L.P, a.K = K, a.zc = L.shs[SH_SMOOTH].zc, a.omega = h->opt.omega;
+        a.cout = cbuf(h, l, 0);
+        if (l == 0 && !alias) {
+            a.r = Rbuf(h), a.inv = sc + K, a.act = act, a.bout = bbuf(h, 0);
+            RUN(h, st, "smooth2_scaled", l, N * (8 + 2 * s), launch_m_stage(MS_SMOOTH2, a, st));
+        } else {
+            a.b = rhs(l);
+            RUN(h, st, "smooth2", l, N * 2 * s, launch_m_stage(MS_SMOOTH2, a, st));
+        }
+        int cur = 0;
+        for (int k = 2; k < h->opt.nu1; ++k) {
+            MArgs w;
+            w.prec = L.prec, w.P = L.P, w.K = K, w.zc = L.shs[SH_SWEEP].zc, w.omega = h->opt.omega;
+            w.b = rhs(l), w.cin = cbuf(h, l, cur), w.cout = cbuf(h, l, cur ^ 1);
+            RUN(h, st, "sweep", l, N * 3 * s, launch_m_stage(MS_SWEEP, w, st));
+            cur ^= 1;
+        }
+        h->cur[l] = cur;
+        MArgs r;
+        r.prec = L.prec, r.pc = h->lv[l + 1].prec, r.P = L.P, r.K = K, r.zc = L.rsh.zcc;
+        r.b = rhs(l), r.cin = cbuf(h, l, cur), r.cout = bbuf(h, l + 1);
+        RUN(h, st, "resid_restrict", l, N * 2 * s + (double)points(3, h->lv[l + 1].n) * K * sb(r.pc),
+            launch_m_stage(MS_RESTRICT, r, st));
+    }
+    RUN(h, st, "coarse_solve", nl - 1, 2.0 * K * sb(h->lv[nl - 1].prec),
+        launch_m_coarse(h->lv[nl - 1].prec, K, bbuf(h, nl - 1), cbuf(h, nl - 1, 0), st));
+    h->cur[nl - 1] = 0;
+    for (int l = nl - 2; l >= 0; --l) {
+        LevelPlan &L = h->lv[l];
+        const double N = (double)points(3, L.n) * K;
+        const double s = sb(L.prec);
+        int cur = h->cur[l];
+        MArgs a;
+        a.prec = L.prec, a.pc = h->lv[l + 1].prec, a.P = L.P, a.K = K, a.zc = L.shs[SH_PROLONG].zc;
+        a.omega = h->opt.omega;
+        a.b = rhs(l), a.cin = cbuf(h, l, cur), a.ec = cbuf(h, l + 1, h->cur[l + 1]), a.cout = cbuf(h, l, cur ^ 1);
+        RUN(h, st, "prolong_sweep", l, N * 3 * s + (double)points(3, h->lv[l + 1].n) * K * sb(a.pc),
+            launch_m_stage(MS_PROLONG, a, st));
+        cur ^= 1;
+        for (int k = 1; k < h->opt.nu2; ++k) {
+            MArgs w;
+            w.prec = L.prec, w.P = L.P, w.K = K, w.zc = L.shs[SH_SWEEP].zc, w.omega = h->opt.omega;
+            w.b = rhs(l), w.cin = cbuf(h, l, cur), w.cout = cbuf(h, l, cur ^ 1);
+            RUN(h, st, "sweep", l, N * 3 * s, launch_m_stage(MS_SWEEP, w, st));
+            cur ^= 1;
+        }
+        h->cur[l] = cur;
+    }
+    LevelPlan &L = h->lv[0];
+    const double hh = 1.0 / (double)(L.n + 1);
+    const double N = (double)points(3, L.n) * K;
+    MArgs u;
+    u.prec = L.prec, u.P = L.P, u.K = K, u.zc = L.osh.zc, u.cin = cbuf(h, 0, h->cur[0]), u.act = act;
+    RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)), launch_m_update(u, Rbuf(h), Ubuf(h), sc, hh * hh, part(h), st));
+    RUN(h, st, "norm_finalize", 0, 16.0 * h->m_upd_blocks * K,
+        launch_m_finalize(part(h), h->m_upd_blocks, K, sc, act, h->opt.residual_scaling, st));
+    return hipMemcpyAsync(h->host_scal_m, sc, 4 * sizeof(double) * K, hipMemcpyDeviceToHost, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_prec_t *level_prec,
+                           const mg_options_t *opt) {
+    if (!out) return fail(MG_ERR_ARG, "null argument");
+    if (dim != 3) return fail(MG_ERR_SHAPE, "many right-hand sides are 3-D (dim = 3)");
+    if (n < 3 || n > 511 || ((n + 1) & n) != 0) return fail(MG_ERR_SHAPE, "n must be 2^m - 1 with 2 <= m <= 9, got %d", n);
+    if (nrhs < 4 || nrhs > 64 || (nrhs & (nrhs - 1)))
+        return fail(MG_ERR_ARG, "nrhs must be 4, 8, 16, 32 or 64 (got %d)", nrhs);
+    mg_options_t o;
+    mg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
+        return fail(MG_ERR_ARG, "many right-hand sides need 2 <= nu1 <= 16 and 1 <= nu2 <= 16");
+    if (!(o.omega > 0.0 && o.omega < 2.0) || o.max_iter < 0 || !(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "bad options");
+    int m = 0;
+    while ((1 << m) < n + 1) ++m;
+    std::vector<int> prec(m, P_F64);
+    if (level_prec)
+        for (int l = 0; l < m; ++l) {
+            if (!valid_prec((int)level_prec[l])) return fail(MG_ERR_PREC, "level_prec[%d] is not a format", l);
+            prec[l] = (int)level_prec[l];
+        }
+    for (int l = 0; l < m; ++l)
+        if (!m_supported(prec[l], nrhs))
+            return fail(MG_ERR_ARG, "nrhs = %d is below the %d columns a thread of level %d handles", nrhs,
+                        m_vec(prec[l]), l);
+    mg_ctx *h = new mg_ctx();
+    h->dim = 3, h->n = n, h->nl = m, h->opt = o, h->nrhs = nrhs;
+    h->lv.resize(m);
+    const int K = nrhs;
+    size_t off = 0;
+    int nn = n;
+    for (int l = 0; l < m; ++l) {
+        LevelPlan &L = h->lv[l];
+        L.n = nn, L.P = nn + 1, L.prec = prec[l];
+        L.elems = level_elems(3, L.P) * K;
+        const size_t bytes = align_up(L.elems * prec_bytes(L.prec), 256);
+        L.off_b = off, off += bytes;
+        L.off_c[0] = off, off += bytes;
+        L.off_c[1] = off, off += bytes;
+        if (nn > 1) {
+            Shape s{m_vec(L.prec), m_zc(L.prec, L.P, K), 256, 0, 0};
+            L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = s;
+            L.osh = Shape{4, m_zc(P_F64, L.P, K), 256, 0, 0};
+            L.rsh = RShape{m_vec(L.prec), 1, m_zc(L.prec, L.P / 2, K), 0};
+        }
+        nn = (nn - 1) / 2;
+    }
+    const size_t fin = align_up(h->lv[0].elems * sizeof(double), 256);
+    h->off_R = off, off += fin;
+    h->off_U = off, off += fin;
+    h->m_upd_blocks = m_stencil_blocks(h->lv[0].prec, h->lv[0].P, K, h->lv[0].osh.zc);
+    h->max_parts = std::max(h->m_upd_blocks, m_resid_blocks(n));
+    h->off_part = off, off += align_up((size_t)h->max_parts * K * 2 * sizeof(double), 256);
+    h->off_scal = off, off += align_up(4 * sizeof(double) * K, 256);
+    h->off_act = off, off += 256;
+    h->off_mask = off, off += 256;
+    h->off_zmask = off, off += 256;
+    h->ws_need = off;
+    *out = h;
+    return MG_OK;
+}
+
+mg_status_t ir_solve_multi(mg_handle h, const double *b, double *u, mg_stats_t *stats, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!h) return fail(MG_ERR_ARG, "null handle");
+    if (!h->nrhs) return fail(MG_ERR_STATE, "ir_solve_multi needs a handle from mg_setup_multi");
+    mg_status_t s = need_ws(h);
+    if (s != MG_OK) return s;
+    if (!b || !u) return fail(MG_ERR_ARG, "null argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int K = h->nrhs;
+    const LevelPlan &L = h->lv[0];
+    const int n = L.n, P = L.P;
+    const double hh = 1.0 / (double)(n + 1);
+    const double inv_h2 = 1.0 / (hh * hh);
+    const int scaling = h->opt.residual_scaling;
+    const int rparts = m_resid_blocks(n);
+    double *sc = scal(h);
+    const double *hs = h->host_scal_m;
+    int *act_dev = at_ws<int>(h, h->off_act);
+    int *mask_dev = at_ws<int>(h, h->off_mask);
+    const int *zmask = at_ws<int>(h, h->off_zmask);
+    int *hact = h->host_mask, *hmask = h->host_mask + K;
+    enum { ACTIVE, CHECK, DONE, STOP, DEAD };
+    std::vector<double> nb(K, 0.0), rel(K, 0.0);
+    std::vector<int> it(K, 0), state(K, ACTIVE);
+    std::vector<mg_status_t> st_k(K, MG_OK);
+    auto hist = [&](int k, int kk, double v) {
+        if (stats && stats[k].history && kk < stats[k].history_cap) stats[k].history[kk] = v;
+    };
+    auto readback = [&]() -> mg_status_t {
+        HIPCHK(hipMemcpyAsync(h->host_scal_m, sc, 4 * sizeof(double) * K, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return MG_OK;
+    };
+    // true residual and norms of the columns in `which` (mask uploaded first)
+    auto resid_cols = [&](const std::vector<int> &which) -> mg_status_t {
+        HIPCHK(hipStreamSynchronize(st));  // an earlier copy may still read hmask
+        for (int k = 0; k < K; ++k) hmask[k] = which[k];
+        HIPCHK(hipMemcpyAsync(mask_dev, hmask, sizeof(int) * K, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_m_resid(n, P, K, b, Ubuf(h), Rbuf(h), nullptr, mask_dev, inv_h2, part(h), st));
+        HIPCHK(launch_m_finalize(part(h), rparts, K, sc, mask_dev, scaling, st));
+        return readback();
+    };
+    // ||b||_2 per column (r = b when starting from zero)
+    if (h->opt.use_initial_guess) {
+        HIPCHK(launch_m_resid(n, P, K, b, nullptr, nullptr, nullptr, nullptr, inv_h2, part(h), st));
+    } else {
+        HIPCHK(launch_m_resid(n, P, K, b, nullptr, Rbuf(h), nullptr, nullptr, inv_h2, part(h), st));
+        HIPCHK(launch_fill_zero(Ubuf(h), align_up(L.elems * sizeof(double), 16), st));
+    }
+    HIPCHK(launch_m_finalize(part(h), rparts, K, sc, nullptr, scaling, st));
+    if ((s = readback()) != MG_OK) return s;
+    for (int k = 0; k < K; ++k) {
+        nb[k] = hs[2 * K + k];
+        if (!std::isfinite(nb[k])) {
+            state[k] = DEAD, st_k[k] = MG_ERR_NONFINITE, rel[k] = NAN;
+        } else if (nb[k] == 0.0) {
+            state[k] = DONE;  // u = 0: its column of U is (made) zero
+            hist(k, 0, 0.0);
+        }
+    }
+    if (h->opt.use_initial_guess) {
+        for (int k = 0; k < K; ++k) hmask[k] = nb[k] != 0.0;
+        HIPCHK(hipMemcpyAsync(mask_dev, hmask, sizeof(int) * K, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_m_pack(n, P, K, u, Ubuf(h), mask_dev, st));
+        std::vector<int> all(K, 1);
+        if ((s = resid_cols(all)) != MG_OK) return s;
+    }
+    const bool graph = h->opt.use_graph && !h->prof;
+    if (graph && !h->gexec) {
+        if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enq_multi_step(h, h->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(MG_ERR_HIP, "capture of the interleaved step failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        h->graph = g;
+        HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    }
+    for (;;) {
+        int nact = 0, ncheck = 0;
+        std::vector<int> check(K, 0);
+        for (int k = 0; k < K; ++k) {
+            if (state[k] != ACTIVE) continue;
+            const double rn = hs[2 * K + k];
+            rel[k] = rn / nb[k];
+            hist(k, it[k], rel[k]);
+            if (!std::isfinite(rn)) {
+                state[k] = STOP, st_k[k] = MG_ERR_NONFINITE;
+            } else if (rn <= h->opt.rtol * nb[k]) {
+                state[k] = it[k] > 0 ? CHECK : STOP;
+                if (it[k] > 0) check[k] = 1, ++ncheck;
+            } else if (it[k] >= h->opt.max_iter) {
+                state[k] = STOP, st_k[k] = MG_ERR_NOT_CONVERGED;
+            } else {
+                ++nact;
+            }
+        }
+        if (ncheck > 0) {
+            // confirm from u; only these columns' R and norms are rewritten
+            if ((s = resid_cols(check)) != MG_OK) return s;
+            for (int k = 0; k < K; ++k) {
+                if (!check[k]) continue;
+                const double rn = hs[2 * K + k];
+                rel[k] = rn / nb[k];
+                hist(k, it[k], rel[k]);
+                if (rn <= h->opt.rtol * nb[k]) {
+                    state[k] = DONE;
+                } else if (!std::isfinite(rn) || it[k] >= h->opt.max_iter) {
+                    state[k] = DONE;
+                    st_k[k] = std::isfinite(rn) ? MG_ERR_NOT_CONVERGED : MG_ERR_NONFINITE;
+                } else {
+                    state[k] = ACTIVE;
+                    ++nact;
+                }
+            }
+        }
+        if (nact == 0) break;
+        for (int k = 0; k < K; ++k) hact[k] = state[k] == ACTIVE;
+        HIPCHK(hipMemcpyAsync(act_dev, hact, sizeof(int) * K, hipMemcpyHostToDevice, st));
+        if (graph) {
+            HIPCHK(hipGraphLaunch(h->gexec, st));
+        } else {
+            hipError_t e = enq_multi_step(h, st);
+            if (e != hipSuccess) return fail(MG_ERR_HIP, "interleaved step failed: %s", hipGetErrorString(e));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        for (int k = 0; k < K; ++k)
+            if (state[k] == ACTIVE) ++it[k];
+    }
+    std::vector<int> stop(K, 0);
+    bool any_stop = false;
+    for (int k = 0; k < K; ++k)
+        if (state[k] == STOP) stop[k] = 1, any_stop = true;
+    if (any_stop) {
+        if ((s = resid_cols(stop)) != MG_OK) return s;
+        for (int k = 0; k < K; ++k)
+            if (stop[k]) rel[k] = hs[2 * K + k] / nb[k];
+    }
+    // u out, every column (held columns keep their last iterate)
+    HIPCHK(launch_m_resid(n, P, K, b, Ubuf(h), nullptr, u, zmask, inv_h2, part(h), st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    mg_status_t result = MG_OK;
+    int first_bad = -1;
+    for (int k = 0; k < K; ++k) {
+        if (stats) {
+            stats[k].iterations = it[k];
+            stats[k].rel_residual = nb[k] == 0.0 ? 0.0 : rel[k];
+            stats[k].seconds = secs;
+        }
+        if (st_k[k] != MG_OK && result == MG_OK) result = st_k[k], first_bad = k;
+    }
+    if (result != MG_OK) return fail(result, "%s (first in right-hand side %d)", mg_status_string(result), first_bad);
+    return MG_OK;
+}
+
+mg_status_t mg_rhs_count(mg_handle h, int *nrhs) {
+    if (!h || !nrhs) return fail(MG_ERR_ARG, "null argument");
+    *nrhs = h->nrhs ? h->nrhs : 1;
     return MG_OK;
 }
 

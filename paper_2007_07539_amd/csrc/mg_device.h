@@ -91,6 +91,12 @@ template <class T> __device__ __forceinline__ acc_t<T> round_to(double v) {
     return widen(Store<T>::from_f64(v));
 }
 
+// Explicit fused multiply-add (the library is built with contraction off, so
+// every other product and sum rounds separately and all kernels agree).
+template <class A> __device__ __forceinline__ A fmaT(A a, A b, A c);
+template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ---------------------------------------------------------------------------
 // Row-vector loads and stores of V consecutive elements starting at an
 // address aligned to V * sizeof(T) (guaranteed by the padded layout below).

@@ -21,10 +21,6 @@
 
 namespace mg {
 
-template <class A> __device__ __forceinline__ A fmaT(A a, A b, A c);
-template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
 // ===========================================================================
 // Field policies: the value of a grid function at a position, in accumulator
 // type `acc`, already rounded to the format it would be stored in.  Positions
@@ -218,7 +214,7 @@ template <class T, class R, bool WRITE_B> struct ESweep {
     T *__restrict__ bout;
     A k;
     __device__ __forceinline__ void init(State &) const {}
-    __device__ __forceinline__ void finish(State &, double *) const {}
+    __device__ __forceinline__ void finish(State &, double *, long) const {}
     template <int D, int V>
     __device__ __forceinline__ void emit(const Grid<D> &g, State &, int x0, int y, int z, const A (&c)[V],
                                          const A (&nb)[V]) const {
@@ -252,7 +248,7 @@ template <class T, class R, bool WRITE_B> struct ECopy {
     T *__restrict__ out;
     T *__restrict__ bout;
     __device__ __forceinline__ void init(State &) const {}
-    __device__ __forceinline__ void finish(State &, double *) const {}
+    __device__ __forceinline__ void finish(State &, double *, long) const {}
     template <int D, int V>
     __device__ __forceinline__ void emit(const Grid<D> &g, State &, int x0, int y, int z, const A (&c)[V],
                                          const A (&)[V]) const {
@@ -311,11 +307,11 @@ struct EOuter {
         store_row<double, V>(R + at, r);
         store_row<double, V>(U + at, u);
     }
-    __device__ __forceinline__ void finish(State &s, double *lds) const {
+    __device__ __forceinline__ void finish(State &s, double *lds, long pidx) const {
         block_reduce(s.ss, s.mx, lds);
         if (threadIdx.x == 0) {
-            part[2 * blockIdx.x] = s.ss;
-            part[2 * blockIdx.x + 1] = s.mx;
+            part[2 * pidx] = s.ss;
+            part[2 * pidx + 1] = s.mx;
         }
     }
 };
@@ -327,19 +323,12 @@ struct EOuter {
 // x-, x+, y-, y+, z-, z+ (2-D: x-, x+, then the two row neighbours).
 // ===========================================================================
 template <int D, int V, class F, class E>
-__global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nchunks, int xcd) {
+__device__ __forceinline__ void stencil_body(const F &f, const E &e, int P, int zc, int nchunks, long blk,
+                                             double *red, long pidx) {
     typedef typename F::acc A;
-    __shared__ double red[8];
     const Grid<D> g{P};
     const int TXR = P / V;
     const int NY = D == 3 ? P : 1;
-    long blk = blockIdx.x;
-    if (xcd) {
-        // blocks are dealt round-robin to the 8 XCDs: give each XCD a
-        // contiguous range of tiles so neighbouring rows share an L2
-        const long nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
-    }
     const long t = blk * blockDim.x + threadIdx.x;
     const int xc = (int)(t % TXR);
     const long line = t / TXR;
@@ -385,7 +374,20 @@ __global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nc
             }
         }
     }
-    e.finish(st, red);
+    e.finish(st, red, pidx);
+}
+
+template <int D, int V, class F, class E>
+__global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nchunks, int xcd) {
+    __shared__ double red[8];
+    long blk = blockIdx.x;
+    if (xcd) {
+        // blocks are dealt round-robin to the 8 XCDs: give each XCD a
+        // contiguous range of tiles so neighbouring rows share an L2
+        const long nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    stencil_body<D, V>(f, e, P, zc, nchunks, blk, red, (long)blockIdx.x);
 }
 
 // ===========================================================================
@@ -589,27 +591,53 @@ template <class TF, class TC, int V> struct PProlS {
         NYc = ez_rows(y0, TY);
         RSx = Pc + 4;
     }
-    // write Ez of fine plane z into slot z mod 3 (all threads of the block)
-    __device__ __forceinline__ void stage(int z, int tid, int nthr) const {
+    // Staging is software-pipelined: stage_fetch loads the coarse values a
+    // thread needs for Ez of fine plane z into registers (elements
+    // e = tid + k * nthr of the slot, k < KS), stage_store combines and
+    // writes them into slot z mod 3 one iteration later.
+    static constexpr int KS = 4;
+    struct Stage {
+        TC v[KS][2];
+    };
+    __device__ __forceinline__ void stage_fetch(int z, int tid, int nthr, Stage &S) const {
         const Grid<3> gc{Pc};
-        int Zs[2];
+        int Zs[2] = {0, 0};
         const int nz = FProl<TF, TC>::split(z, Zs);
-        const PA wz = nz == 1 ? PA(1) : PA(0.5);
-        PA *dst = ez + (size_t)(((z % 3) + 3) % 3) * NYc * RSx;
         const bool plane_ok = z >= 1 && z < 2 * Pc;
-        for (int e = tid; e < NYc * RSx; e += nthr) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int e = tid + k * nthr;
             const int r = e / RSx, X = e - r * RSx;
             const int Y = Ylo + r;
-            PA t = PA(0);
-            if (plane_ok && X >= 1 && X < Pc && Y >= 1 && Y < Pc) {
-                for (int a = 0; a < nz; ++a) {
-                    const int Z = Zs[a];
-                    if (Z < 1 || Z >= Pc) continue;
-                    t += wz * (PA)widen(ec[gc.at(X, Y, Z)]);
-                }
+            const bool ok = plane_ok && e < NYc * RSx && X >= 1 && X < Pc && Y >= 1 && Y < Pc;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int Z = Zs[a];
+                S.v[k][a] = (ok && a < nz && Z >= 1 && Z < Pc) ? ec[gc.at(X, Y, Z)] : zero_of<TC>();
             }
-            dst[e] = t;
         }
+    }
+    __device__ __forceinline__ void stage_store(int z, int tid, int nthr, const Stage &S) const {
+        int Zs[2] = {0, 0};
+        const int nz = FProl<TF, TC>::split(z, Zs);
+        const PA wz = nz == 1 ? PA(1) : PA(0.5);
+        PA *dst = ez + (size_t)(z % 3) * NYc * RSx;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int e = tid + k * nthr;
+            if (e < NYc * RSx) {
+                PA t = PA(0);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    if (a < nz && Zs[a] >= 1 && Zs[a] < Pc) t += wz * (PA)widen(S.v[k][a]);
+                dst[e] = t;
+            }
+        }
+    }
+    __device__ __forceinline__ void stage(int z, int tid, int nthr) const {
+        Stage S;
+        stage_fetch(z, tid, nthr, S);
+        stage_store(z, tid, nthr, S);
     }
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
         if (g.ghost_row(y, z)) {
@@ -746,6 +774,13 @@ template <int V> struct POuter {
     }
 };
 
+template <class F, class = void> struct StageOf {
+    struct type {};
+};
+template <class F> struct StageOf<F, typename std::enable_if<F::kStaged>::type> {
+    typedef typename F::Stage type;
+};
+
 template <int V, class F, class E>
 __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int zc, int ytiles, int xcd) {
     typedef typename F::acc A;
@@ -777,11 +812,13 @@ __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int 
     A cm[V], cc[V], cp[V], ac[V], ap[V];
     F f = f_in;
     const int nthr = blockDim.x;
+    typename StageOf<F>::type S;
     if constexpr (F::kStaged) {
         f.bind_lds(smem_raw + 2 * slot * sizeof(LT), y0, TY, 0);
         f.stage(z0 - 1, threadIdx.x, nthr);
         f.stage(z0, threadIdx.x, nthr);
         f.stage(z0 + 1, threadIdx.x, nthr);
+        f.stage_fetch(z0 + 2, threadIdx.x, nthr, S);
         __syncthreads();
     }
     f.fetch(g, x0, y, z0 - 1, fr);
@@ -800,7 +837,10 @@ __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int 
     for (int z = z0; z < z1; ++z) {
         const int it = z - z0;
         f.value(fr, x0, y, z + 1, cp, ap);
-        if constexpr (F::kStaged) f.stage(z + 2, threadIdx.x, nthr);
+        if constexpr (F::kStaged) {
+            f.stage_store(z + 2, threadIdx.x, nthr, S);
+            if (z + 3 <= z1) f.stage_fetch(z + 3, threadIdx.x, nthr, S);
+        }
         if (z + 2 <= z1) f.fetch(g, x0, y, z + 2, fr);
         const typename E::Raw ecur = er;
         if (out_row && z + 1 < z1) e.fetch(g, x0, y, z + 1, er);
@@ -853,18 +893,18 @@ __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int 
 // LDS and accumulate the z weights in registers across the march.
 // ===========================================================================
 template <int D, int V, class TF, class TC>
-__global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, const TF *__restrict__ c,
-                                                   TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles) {
+__device__ __forceinline__ void restrict_body(const TF *__restrict__ b, const TF *__restrict__ c,
+                                              TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles, int blk,
+                                              unsigned char *smem_raw) {
     typedef acc_t<TF> A;
     constexpr int VC = V / 2;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     A *rs = reinterpret_cast<A *>(smem_raw);
     const int Pc = P >> 1;
     const int TXR = P / V;
     const int G = D == 3 ? 2 * tyc + 1 : 1;
     const Grid<D> g{P};
     const Grid<D> gc{Pc};
-    const int ytile = blockIdx.x % ytiles, zch = blockIdx.x / ytiles;
+    const int ytile = blk % ytiles, zch = blk / ytiles;
     const int Y0 = D == 3 ? 1 + ytile * tyc : 0;
     const int Z0 = 1 + zch * zcc;
     const int Z1 = min(Z0 + zcc, Pc);
@@ -970,6 +1010,13 @@ __global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, con
             }
         }
     }
+}
+
+template <int D, int V, class TF, class TC>
+__global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, const TF *__restrict__ c,
+                                                   TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    restrict_body<D, V, TF, TC>(b, c, bc, P, tyc, zcc, ytiles, blockIdx.x, smem_raw);
 }
 
 // ===========================================================================
@@ -1475,8 +1522,10 @@ static hipError_t prolong_t(int D, int P, const void *c, const void *ec, const v
     hipError_t err = hipSuccess;
     if (D == 3 && s.ty > 0 && sweep) {
         typedef typename FProl<TF, TC>::PA PA;
+        const int nthr = (P / s.V) * (s.ty + 2);
         const bool staged = P / 2 >= 8 &&
-                            march_lds_bytes(P, s.ty, sizeof(TF)) + staged_ez_bytes(P, s.ty, sizeof(PA)) <= 65536;
+                            march_lds_bytes(P, s.ty, sizeof(TF)) + staged_ez_bytes(P, s.ty, sizeof(PA)) <= 65536 &&
+                            (s.ty / 2 + 3) * (P / 2 + 4) <= 4 * nthr;
         if (staged) {
             MG_DISPATCH_V(s.V, err = (run_march<VV>(PProlS<TF, TC, VV>{static_cast<const TF *>(c),
                                                                        static_cast<const TC *>(ec), P / 2,
@@ -1680,6 +1729,208 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
     long b = (long)((n16 + 255) / 256);
     if (b > 8192) b = 8192;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)b), dim3(256), 0, st, static_cast<uint4 *>(p), n16);
+    return hipGetLastError();
+}
+
+}  // namespace mg
+
+// ===========================================================================
+// Batched instances: one persistent launch per V-cycle stage walks a work list
+// of (descriptor, tile) items that spans all instances whose grids have that
+// stage; the per-tile work is the same device code as the single-grid
+// kernels, so a batched instance computes exactly what it would alone.
+// Instances whose device flag active[inst] is 0 are skipped (converged).
+// ===========================================================================
+namespace mg {
+
+template <int V, int KIND, class T, class TC>
+__global__ __launch_bounds__(256) void k_batched_stencil(const BDesc *__restrict__ descs,
+                                                         const BItem *__restrict__ items, int nitems,
+                                                         const int *__restrict__ active, double omega,
+                                                         double *__restrict__ part) {
+    __shared__ double red[8];
+    typedef acc_t<T> A;
+    const A k = (A)(omega / 6.0);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem item = items[it];
+        const BDesc &d = descs[item.d];
+        if (!active[d.inst]) continue;
+        if constexpr (KIND == BK_SMOOTH2) {
+            typedef FArr<T, A> R;
+            const R rh{static_cast<const T *>(d.b)};
+            const FJac0<T, R> f{rh, k};
+            const ESweep<T, R, false> e{rh, static_cast<T *>(d.cout), nullptr, k};
+            stencil_body<3, V>(f, e, d.P, d.zc, d.nchunks, item.blk, red, 0);
+        } else if constexpr (KIND == BK_SMOOTH2_SCALED) {
+            typedef FScaled<T> R;
+            const R rh{static_cast<const double *>(d.b), d.scal};
+            const FJac0<T, R> f{rh, k};
+            const ESweep<T, R, true> e{rh, static_cast<T *>(d.cout), static_cast<T *>(d.bout), k};
+            stencil_body<3, V>(f, e, d.P, d.zc, d.nchunks, item.blk, red, 0);
+        } else if constexpr (KIND == BK_SWEEP) {
+            typedef FArr<T, A> R;
+            const R f{static_cast<const T *>(d.cin)};
+            const ESweep<T, R, false> e{R{static_cast<const T *>(d.b)}, static_cast<T *>(d.cout), nullptr, k};
+            stencil_body<3, V>(f, e, d.P, d.zc, d.nchunks, item.blk, red, 0);
+        } else if constexpr (KIND == BK_PROLONG) {
+            typedef FArr<T, A> R;
+            const FProl<T, TC> f{static_cast<const T *>(d.cin), static_cast<const TC *>(d.ec), d.P / 2};
+            const ESweep<T, R, false> e{R{static_cast<const T *>(d.b)}, static_cast<T *>(d.cout), nullptr, k};
+            stencil_body<3, V>(f, e, d.P, d.zc, d.nchunks, item.blk, red, 0);
+        } else {
+            const FArr<T, double> f{static_cast<const T *>(d.cin)};
+            const EOuter e{d.R, d.U, d.scal, d.h2, part};
+            stencil_body<3, V>(f, e, d.P, d.zc, d.nchunks, item.blk, red, (long)d.part_off + item.blk);
+        }
+    }
+}
+
+template <int V, class TF, class TC>
+__global__ __launch_bounds__(1024) void k_batched_restrict(const BDesc *__restrict__ descs,
+                                                           const BItem *__restrict__ items, int nitems,
+                                                           const int *__restrict__ active) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem item = items[it];
+        const BDesc &d = descs[item.d];
+        if (!active[d.inst]) continue;
+        restrict_body<3, V, TF, TC>(static_cast<const TF *>(d.b), static_cast<const TF *>(d.cin),
+                                    static_cast<TC *>(d.cout), d.P, d.tyc, d.zcc, d.ytiles, item.blk, smem_raw);
+        __syncthreads();  // the next item reuses the LDS rows
+    }
+}
+
+template <class T>
+__global__ void k_batched_coarse(const BDesc *__restrict__ descs, int n, const int *__restrict__ active) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !active[descs[i].inst]) return;
+    typedef acc_t<T> A;
+    const T *b = static_cast<const T *>(descs[i].b);
+    T *c = static_cast<T *>(descs[i].cout);
+    c[7] = Store<T>::from_acc(widen(b[7]) / A(6));
+}
+
+// One block per instance: reduce its partials into its scalars.
+__global__ __launch_bounds__(256) void k_batched_finalize(const BFin *__restrict__ fin,
+                                                          const int *__restrict__ active, int scaling) {
+    __shared__ double red[8];
+    if (!active[blockIdx.x]) return;
+    const BFin f = fin[blockIdx.x];
+    double s = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < f.count; i += blockDim.x) {
+        s += f.part[2 * i];
+        m = nanmax(m, f.part[2 * i + 1]);
+    }
+    block_reduce(s, m, red);
+    if (threadIdx.x == 0) {
+        double a = scaling ? m : 1.0;
+        if (!(a > 0.0) || a > 1.7e308) a = 1.0;
+        f.scal[0] = a;
+        f.scal[1] = 1.0 / a;
+        f.scal[2] = sqrt(s);
+        f.scal[3] = m;
+    }
+}
+
+#define MG_BT(prec, ...)                                   \
+    switch (prec) {                                        \
+    case P_F64: { typedef double TB; __VA_ARGS__; break; } \
+    case P_F32: { typedef float TB; __VA_ARGS__; break; }  \
+    case P_F16: { typedef f16 TB; __VA_ARGS__; break; }    \
+    case P_BF16: { typedef bf16 TB; __VA_ARGS__; break; }  \
+    default: return hipErrorInvalidValue;                  \
+    }
+
+template <int V, int KIND, class T>
+static hipError_t bst_tc(int pc, const BDesc *d, const BItem *it, int n, const int *act, double omega, double *part,
+                         int grid, hipStream_t st) {
+    switch (pc) {
+    case P_F64:
+        hipLaunchKernelGGL((k_batched_stencil<V, KIND, T, double>), dim3(grid), dim3(256), 0, st, d, it, n, act,
+                           omega, part);
+        break;
+    case P_F32:
+        hipLaunchKernelGGL((k_batched_stencil<V, KIND, T, float>), dim3(grid), dim3(256), 0, st, d, it, n, act,
+                           omega, part);
+        break;
+    case P_F16:
+        hipLaunchKernelGGL((k_batched_stencil<V, KIND, T, f16>), dim3(grid), dim3(256), 0, st, d, it, n, act,
+                           omega, part);
+        break;
+    case P_BF16:
+        hipLaunchKernelGGL((k_batched_stencil<V, KIND, T, bf16>), dim3(grid), dim3(256), 0, st, d, it, n, act,
+                           omega, part);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t bst_kind(int V, int pf, int pc, const BDesc *d, const BItem *it, int n, const int *act,
+                           double omega, double *part, int grid, hipStream_t st) {
+    if (KIND != BK_PROLONG) pc = P_F64;  // the coarse format only matters for prolongation
+    MG_BT(pf, {
+        if (V == 8) return bst_tc<8, KIND, TB>(pc, d, it, n, act, omega, part, grid, st);
+        return bst_tc<4, KIND, TB>(pc, d, it, n, act, omega, part, grid, st);
+    });
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_stencil(int kind, int V, int pf, int pc, const BDesc *d, const BItem *items, int nitems,
+                                  const int *active, double omega, double *part, int grid, hipStream_t st) {
+    switch (kind) {
+    case BK_SMOOTH2: return bst_kind<BK_SMOOTH2>(V, pf, pc, d, items, nitems, active, omega, part, grid, st);
+    case BK_SMOOTH2_SCALED:
+        return bst_kind<BK_SMOOTH2_SCALED>(V, pf, pc, d, items, nitems, active, omega, part, grid, st);
+    case BK_SWEEP: return bst_kind<BK_SWEEP>(V, pf, pc, d, items, nitems, active, omega, part, grid, st);
+    case BK_PROLONG: return bst_kind<BK_PROLONG>(V, pf, pc, d, items, nitems, active, omega, part, grid, st);
+    case BK_OUTER: return bst_kind<BK_OUTER>(V, pf, pc, d, items, nitems, active, omega, part, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int V, class TF>
+static hipError_t brs_tc(int pc, const BDesc *d, const BItem *it, int n, const int *act, int grid, int threads,
+                         size_t lds, hipStream_t st) {
+    switch (pc) {
+    case P_F64:
+        hipLaunchKernelGGL((k_batched_restrict<V, TF, double>), dim3(grid), dim3(threads), lds, st, d, it, n, act);
+        break;
+    case P_F32:
+        hipLaunchKernelGGL((k_batched_restrict<V, TF, float>), dim3(grid), dim3(threads), lds, st, d, it, n, act);
+        break;
+    case P_F16:
+        hipLaunchKernelGGL((k_batched_restrict<V, TF, f16>), dim3(grid), dim3(threads), lds, st, d, it, n, act);
+        break;
+    case P_BF16:
+        hipLaunchKernelGGL((k_batched_restrict<V, TF, bf16>), dim3(grid), dim3(threads), lds, st, d, it, n, act);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_restrict(int V, int pf, int pc, const BDesc *d, const BItem *items, int nitems,
+                                   const int *active, int grid, int threads, size_t lds, hipStream_t st) {
+    MG_BT(pf, {
+        if (V == 8) return brs_tc<8, TB>(pc, d, items, nitems, active, grid, threads, lds, st);
+        return brs_tc<4, TB>(pc, d, items, nitems, active, grid, threads, lds, st);
+    });
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_coarse(int prec, const BDesc *d, int n, const int *active, hipStream_t st) {
+    const int grid = (n + 63) / 64;
+    MG_BT(prec, {
+        hipLaunchKernelGGL((k_batched_coarse<TB>), dim3(grid), dim3(64), 0, st, d, n, active);
+        return hipGetLastError();
+    });
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_finalize(const BFin *fin, int ninst, const int *active, int scaling, hipStream_t st) {
+    hipLaunchKernelGGL(k_batched_finalize, dim3(ninst), dim3(256), 0, st, fin, active, scaling);
     return hipGetLastError();
 }
 

@@ -80,4 +80,70 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, unsigned *sink,
                         hipStream_t st);
 
+// ---- batched instances -------------------------------------------------------
+// Per-(instance, level) arguments of one batched launch.
+struct BDesc {
+    const void *b;       // right-hand side (level format); FP64 residual for the scaled first smoothing
+    const void *cin;     // input correction (sweep, prolongation, update, restriction)
+    void *cout;          // output correction; coarse right-hand side for the restriction
+    const void *ec;      // coarse correction (prolongation)
+    void *bout;          // scaled right-hand side written by the first smoothing
+    const double *scal;  // alpha, 1/alpha, ||r||_2, ||r||_inf of the instance
+    double *R, *U;       // FP64 residual and iterate (update)
+    double h2;
+    int P, zc, nchunks;  // stencil launch shape of this grid
+    int tyc, zcc, ytiles;
+    int part_off;        // first reduction partial of the instance (update)
+    int inst;
+};
+struct BItem {
+    int d, blk;  // descriptor, tile
+};
+struct BFin {
+    const double *part;
+    int count;
+    double *scal;
+};
+enum { BK_SMOOTH2 = 0, BK_SMOOTH2_SCALED = 1, BK_SWEEP = 2, BK_PROLONG = 3, BK_OUTER = 4 };
+
+hipError_t launch_batched_stencil(int kind, int V, int pf, int pc, const BDesc *d, const BItem *items, int nitems,
+                                  const int *active, double omega, double *part, int grid, hipStream_t st);
+hipError_t launch_batched_restrict(int V, int pf, int pc, const BDesc *d, const BItem *items, int nitems,
+                                   const int *active, int grid, int threads, size_t lds, hipStream_t st);
+hipError_t launch_batched_coarse(int prec, const BDesc *d, int n, const int *active, hipStream_t st);
+hipError_t launch_batched_finalize(const BFin *fin, int ninst, const int *active, int scaling, hipStream_t st);
+
+// ---- many right-hand sides, interleaved [z][y][x][k] -------------------------
+// Arguments of one interleaved stage launch (unused members may stay null).
+struct MArgs {
+    int prec = 0;        // level storage format
+    int pc = 0;          // coarse format (prolongation: of ec; restriction: of cout)
+    int P = 0, K = 0;    // pitch of the level, number of right-hand sides
+    int zc = 1;          // planes per thread (restriction: coarse planes)
+    const void *b = nullptr;       // right-hand side (level format, or FP64 residual when aliased)
+    const double *r = nullptr;     // scaled first smoothing: FP64 residual
+    const double *inv = nullptr;   // 1/alpha_k (K values)
+    const int *act = nullptr;      // per-column flags (K values)
+    void *bout = nullptr;          // scaled first smoothing: round(r/alpha) out
+    const void *cin = nullptr;     // input correction
+    const void *ec = nullptr;      // coarse correction (prolongation)
+    void *cout = nullptr;          // output correction, or coarse right-hand side (restriction)
+    double omega = 0.8;
+};
+enum { MS_SMOOTH2 = 0, MS_SWEEP = 1, MS_PROLONG = 2, MS_RESTRICT = 3 };
+
+int m_vec(int prec);
+bool m_supported(int prec, int K);
+int m_stencil_blocks(int prec, int P, int K, int zc);
+int m_resid_blocks(int n);
+hipError_t launch_m_stage(int kind, const MArgs &a, hipStream_t st);
+hipError_t launch_m_update(const MArgs &a, double *R, double *U, const double *alpha, double h2, double *part,
+                           hipStream_t st);
+hipError_t launch_m_coarse(int prec, int K, const void *b, void *c, hipStream_t st);
+hipError_t launch_m_resid(int n, int P, int K, const double *b, const double *U, double *R, double *uout,
+                          const int *mask, double inv_h2, double *part, hipStream_t st);
+hipError_t launch_m_pack(int n, int P, int K, const double *src, double *dst, const int *keep, hipStream_t st);
+hipError_t launch_m_finalize(const double *part, int nparts, int K, double *scal, const int *mask, int scaling,
+                             hipStream_t st);
+
 }  // namespace mg

@@ -24,8 +24,10 @@ BUF_RHS, BUF_COR, BUF_RES, BUF_SOL = 0, 1, 2, 3
 STAGE_SMOOTH_FIRST, STAGE_SWEEP, STAGE_RESTRICT, STAGE_PROLONG_SWEEP, STAGE_COARSE = 0, 1, 2, 3, 4
 EXPORTS = ("mg_default_options", "mg_setup", "mg_workspace_size", "mg_bind_workspace", "mg_vcycle", "ir_solve",
            "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_write", "mg_level_read", "mg_stage",
-           "mg_levels", "mg_level_n", "mg_profile_step", "mg_set_shape", "mg_get_shape", "mg_bandwidth_probe")
-SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE = 0, 1, 2
+           "mg_levels", "mg_level_n", "mg_profile_step", "mg_set_shape", "mg_get_shape", "mg_bandwidth_probe",
+           "mg_setup_batched", "ir_solve_batched", "mg_instances", "mg_setup_multi", "ir_solve_multi",
+           "mg_rhs_count")
+SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE, SHAPE_SMOOTH, SHAPE_SWEEP, SHAPE_PROLONG = 0, 1, 2, 3, 4, 5
 
 
 class MgError(RuntimeError):
@@ -77,6 +79,13 @@ def load() -> ctypes.CDLL:
     lib.mg_set_shape.argtypes = [H, i, i, ctypes.POINTER(ctypes.c_int), i]
     lib.mg_get_shape.argtypes = [H, i, i, ctypes.POINTER(ctypes.c_int), i]
     lib.mg_bandwidth_probe.argtypes = [vp, vp, ctypes.c_size_t, i, i, vp]
+    lib.mg_setup_batched.argtypes = [ctypes.POINTER(H), i, i, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Options)]
+    lib.ir_solve_batched.argtypes = [H, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(Stats), vp]
+    lib.mg_instances.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
+    lib.mg_setup_multi.argtypes = [ctypes.POINTER(H), i, i, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Options)]
+    lib.ir_solve_multi.argtypes = [H, vp, vp, ctypes.POINTER(Stats), vp]
+    lib.mg_rhs_count.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
     for f in EXPORTS:
         if f not in ("mg_default_options", "mg_status_string", "mg_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -240,6 +249,159 @@ class Solver:
         _check(self.lib.mg_profile_step(self._h, _stream_ptr(stream), cap, ctypes.byref(cnt), names, ms, by, lv),
                "mg_profile_step")
         return [(names[i].decode(), lv[i], ms[i], by[i]) for i in range(min(cnt.value, cap))]
+
+
+def _bind(lib, h, device, stream):
+    nb = ctypes.c_size_t()
+    _check(lib.mg_workspace_size(h, ctypes.byref(nb)), "mg_workspace_size")
+    with torch.cuda.device(device):
+        ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=device)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        _check(lib.mg_bind_workspace(h, ctypes.c_void_p(base + off), nb.value, _stream_ptr(stream)),
+               "mg_bind_workspace")
+    return ws, nb.value
+
+
+class BatchedSolver:
+    """Many 3-D grids of different sizes: ``mg_setup_batched`` + ``ir_solve_batched``.
+
+    sizes: list of n_i = 2^m_i - 1.  level_prec: Lmax formats (finest first,
+    the last one for every instance's base level), None = all FP64.
+    """
+
+    def __init__(self, sizes, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True, max_iter=100,
+                 rtol=1e-10, use_initial_guess=False, use_graph=True, device=None, stream=None):
+        self.lib = load()
+        self.sizes = [int(n) for n in sizes]
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        o = default_options()
+        o.nu1, o.nu2, o.omega = nu1, nu2, omega
+        o.residual_scaling, o.max_iter, o.rtol = int(bool(residual_scaling)), max_iter, rtol
+        o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), 0
+        self.options = o
+        lmax = max(int(n + 1).bit_length() - 1 for n in self.sizes)
+        if level_prec is None:
+            level_prec = ["f64"] * lmax
+        self.level_prec = list(level_prec)
+        if len(self.level_prec) != lmax:
+            raise ValueError(f"level_prec needs {lmax} entries (finest first), got {len(self.level_prec)}")
+        self._h = ctypes.c_void_p()
+        ns = (ctypes.c_int * len(self.sizes))(*self.sizes)
+        arr = (ctypes.c_int * lmax)(*[PREC[p] for p in self.level_prec])
+        _check(self.lib.mg_setup_batched(ctypes.byref(self._h), 3, len(self.sizes), ns, arr, ctypes.byref(o)),
+               "mg_setup_batched")
+        self.workspace, self.workspace_bytes = _bind(self.lib, self._h, self.device, stream)
+
+    def instance_prec(self, i: int):
+        """The single-grid level map that instance i follows."""
+        m = int(self.sizes[i] + 1).bit_length() - 1
+        return self.level_prec[: m - 1] + [self.level_prec[-1]]
+
+    def close(self):
+        if self._h:
+            self.lib.mg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, us=None, stream=None, history_cap: int = 256, check: bool = True):
+        """Algorithm 2 for every instance; returns (us, [SolveResult per instance], status)."""
+        k = len(self.sizes)
+        if len(bs) != k:
+            raise ValueError(f"expected {k} right-hand sides")
+        for b, n in zip(bs, self.sizes):
+            if b.dtype != torch.float64 or tuple(b.shape) != (n, n, n):
+                raise ValueError(f"b must be float64 of shape {(n, n, n)}")
+        if us is None:
+            us = [torch.zeros_like(b) for b in bs]
+        bp = (ctypes.c_void_p * k)(*[_dptr(b).value for b in bs])
+        up = (ctypes.c_void_p * k)(*[_dptr(u).value for u in us])
+        hists = [(ctypes.c_double * history_cap)() for _ in range(k)]
+        stats = (Stats * k)()
+        for i in range(k):
+            stats[i].history = ctypes.cast(hists[i], ctypes.POINTER(ctypes.c_double))
+            stats[i].history_cap = history_cap
+        status = self.lib.ir_solve_batched(self._h, bp, up, stats, _stream_ptr(stream))
+        res = [SolveResult(status, stats[i].iterations, stats[i].rel_residual, stats[i].seconds,
+                           [hists[i][j] for j in range(min(stats[i].iterations + 1, history_cap))])
+               for i in range(k)]
+        if check and status != MG_OK:
+            _check(status, "ir_solve_batched")
+        return us, res, status
+
+    def profile_step(self, stream=None, cap: int = 1024):
+        return Solver.profile_step(self, stream, cap)
+
+
+class MultiSolver:
+    """Many right-hand sides on one 3-D grid: ``mg_setup_multi`` + ``ir_solve_multi``.
+
+    Vectors are FP64 device tensors of shape (n, n, n, nrhs), index [z, y, x, k]
+    (right-hand sides interleaved).
+    """
+
+    def __init__(self, n: int, nrhs: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
+                 max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, device=None, stream=None):
+        self.lib = load()
+        self.n, self.nrhs = int(n), int(nrhs)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        o = default_options()
+        o.nu1, o.nu2, o.omega = nu1, nu2, omega
+        o.residual_scaling, o.max_iter, o.rtol = int(bool(residual_scaling)), max_iter, rtol
+        o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), 0
+        self.options = o
+        m = int(n + 1).bit_length() - 1
+        if level_prec is None:
+            level_prec = ["f64"] * m
+        self.level_prec = list(level_prec)
+        if len(self.level_prec) != m:
+            raise ValueError(f"level_prec needs {m} entries (finest first), got {len(self.level_prec)}")
+        self._h = ctypes.c_void_p()
+        arr = (ctypes.c_int * m)(*[PREC[p] for p in self.level_prec])
+        _check(self.lib.mg_setup_multi(ctypes.byref(self._h), 3, self.n, self.nrhs, arr, ctypes.byref(o)),
+               "mg_setup_multi")
+        self.workspace, self.workspace_bytes = _bind(self.lib, self._h, self.device, stream)
+
+    def close(self):
+        if self._h:
+            self.lib.mg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b: torch.Tensor, u: torch.Tensor | None = None, stream=None, history_cap: int = 256,
+              check: bool = True):
+        """Algorithm 2 per right-hand side; returns (u, [SolveResult per column], status)."""
+        shape = (self.n,) * 3 + (self.nrhs,)
+        if b.dtype != torch.float64 or tuple(b.shape) != shape:
+            raise ValueError(f"b must be float64 of shape {shape}")
+        if u is None:
+            u = torch.zeros_like(b)
+        k = self.nrhs
+        hists = [(ctypes.c_double * history_cap)() for _ in range(k)]
+        stats = (Stats * k)()
+        for i in range(k):
+            stats[i].history = ctypes.cast(hists[i], ctypes.POINTER(ctypes.c_double))
+            stats[i].history_cap = history_cap
+        status = self.lib.ir_solve_multi(self._h, _dptr(b), _dptr(u), stats, _stream_ptr(stream))
+        res = [SolveResult(status, stats[i].iterations, stats[i].rel_residual, stats[i].seconds,
+                           [hists[i][j] for j in range(min(stats[i].iterations + 1, history_cap))])
+               for i in range(k)]
+        if check and status != MG_OK:
+            _check(status, "ir_solve_multi")
+        return u, res, status
+
+    def profile_step(self, stream=None, cap: int = 1024):
+        return Solver.profile_step(self, stream, cap)
 
 
 def bandwidth_probe(dst: torch.Tensor, src: torch.Tensor, kind: int, blocks: int = 4096, stream=None):

@@ -93,3 +93,85 @@ def test_status_strings(lib):
     for s in range(-8, 1):
         assert lib.mg_status_string(s)
     assert lib.mg_status_string(-99) == b"unknown status"
+
+
+def _setup_batched(lib, sizes, prec=None, opt=None, dim=3):
+    h = ctypes.c_void_p()
+    ns = (ctypes.c_int * max(1, len(sizes)))(*sizes)
+    pa = None if prec is None else (ctypes.c_int * len(prec))(*prec)
+    st = lib.mg_setup_batched(ctypes.byref(h), dim, len(sizes), ns, pa, None if opt is None else ctypes.byref(opt))
+    return st, h
+
+
+def test_batched_setup_validation(lib):
+    for sizes in ([], [15, 16], [15, 1], [15, 2047]):
+        st, h = _setup_batched(lib, sizes)
+        assert st in (mgir.MG_ERR_ARG, mgir.MG_ERR_SHAPE) and not h.value
+    assert _setup_batched(lib, [15, 7], dim=2)[0] == mgir.MG_ERR_SHAPE
+    assert _setup_batched(lib, [15, 7], prec=[0, 2, 9, 0])[0] == mgir.MG_ERR_PREC
+    o = mgir.default_options()
+    o.nu1 = 1
+    assert _setup_batched(lib, [15, 7], opt=o)[0] == mgir.MG_ERR_ARG
+
+
+def test_batched_workspace_and_refusals(lib):
+    sizes = [63, 7, 127, 15]
+    st, h = _setup_batched(lib, sizes, prec=[2] * 6 + [0])
+    assert st == mgir.MG_OK
+    try:
+        nb = ctypes.c_size_t()
+        assert lib.mg_workspace_size(h, ctypes.byref(nb)) == mgir.MG_OK
+        # every instance's finest level: three FP16 arrays plus FP64 u and r
+        need = sum((n + 3) * (n + 1) ** 2 * (3 * 2 + 2 * 8) for n in sizes)
+        assert nb.value >= need
+        k = ctypes.c_int()
+        assert lib.mg_instances(h, ctypes.byref(k)) == 0 and k.value == 4
+        nl = ctypes.c_int()
+        assert lib.mg_levels(h, ctypes.byref(nl)) == 0 and nl.value == 7
+        ptrs = (ctypes.c_void_p * 4)(*([16] * 4))
+        assert lib.ir_solve_batched(h, ptrs, ptrs, None, None) == mgir.MG_ERR_WORKSPACE
+        assert lib.mg_level_n(h, 0, ctypes.byref(k)) == mgir.MG_ERR_STATE
+        assert lib.mg_get_shape(h, 0, 0, (ctypes.c_int * 5)(), 5) == mgir.MG_ERR_STATE
+    finally:
+        assert lib.mg_destroy(h) == mgir.MG_OK
+    # a single-grid handle refuses the batched solve
+    h = ctypes.c_void_p()
+    assert lib.mg_setup(ctypes.byref(h), 3, 15, 0, None, None) == mgir.MG_OK
+    try:
+        k = ctypes.c_int()
+        assert lib.mg_instances(h, ctypes.byref(k)) == 0 and k.value == 1
+        ptrs = (ctypes.c_void_p * 1)(16)
+        assert lib.ir_solve_batched(h, ptrs, ptrs, None, None) == mgir.MG_ERR_STATE
+    finally:
+        lib.mg_destroy(h)
+
+
+def test_multi_setup_validation_and_workspace(lib):
+    h = ctypes.c_void_p()
+    for n, k in ((15, 3), (15, 12), (15, 128), (16, 8), (1023, 8)):
+        st = lib.mg_setup_multi(ctypes.byref(h), 3, n, k, None, None)
+        assert st in (mgir.MG_ERR_ARG, mgir.MG_ERR_SHAPE) and not h.value
+    assert lib.mg_setup_multi(ctypes.byref(h), 2, 15, 8, None, None) == mgir.MG_ERR_SHAPE
+    f16 = (ctypes.c_int * 4)(2, 2, 2, 0)
+    # FP16 levels need at least 8 columns (one thread's chunk)
+    assert lib.mg_setup_multi(ctypes.byref(h), 3, 15, 4, f16, None) == mgir.MG_ERR_ARG
+    assert lib.mg_setup_multi(ctypes.byref(h), 3, 15, 4, None, None) == mgir.MG_OK  # FP64: 4 columns
+    lib.mg_destroy(h)
+    assert lib.mg_setup_multi(ctypes.byref(h), 3, 127, 32, (ctypes.c_int * 7)(2, 2, 2, 2, 2, 2, 0), None) == 0
+    try:
+        nb = ctypes.c_size_t()
+        assert lib.mg_workspace_size(h, ctypes.byref(nb)) == mgir.MG_OK
+        P = 128
+        assert nb.value >= (P + 2) * P * P * 32 * (3 * 2 + 2 * 8)
+        k = ctypes.c_int()
+        assert lib.mg_rhs_count(h, ctypes.byref(k)) == 0 and k.value == 32
+        assert lib.mg_level_n(h, 1, ctypes.byref(k)) == 0 and k.value == 63
+        assert lib.ir_solve_multi(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == mgir.MG_ERR_WORKSPACE
+        assert lib.mg_vcycle(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == mgir.MG_ERR_WORKSPACE
+    finally:
+        lib.mg_destroy(h)
+    assert lib.mg_setup(ctypes.byref(h), 3, 15, 0, None, None) == mgir.MG_OK
+    try:
+        assert lib.ir_solve_multi(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == mgir.MG_ERR_STATE
+    finally:
+        lib.mg_destroy(h)
