@@ -41,6 +41,26 @@ def timed_solves(solver, bt, u, steps, warmup, torch):
     return start.elapsed_time(end) / steps, results
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when that summary covers another kernel or older kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ir_update_poisson3d_511_f16_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", " ", "#", "`")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("mg_kernels.hip", "mg_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_2007_07539_amd", "csrc", f), "rb").read())
+    if fields.get("traffic_kernel") != kernel or fields.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def kernel_table(prof, level=0):
     """Aggregate one profiled refinement step by kernel name on one level."""
     agg = {}
@@ -101,6 +121,15 @@ def main():
     kt = kernel_table(prof)
     del mixed
     torch.cuda.empty_cache()
+    if args.profile_only:
+        # a plain 1 GiB device copy: the reference that scales hardware traffic
+        # counters (FETCH_SIZE, WRITE_SIZE) of the solver kernels to bytes
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        mgir.bandwidth_probe(dst, src, 0)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written by k_probe")
+        del src, dst
 
     fp64 = None
     if not args.profile_only:
@@ -135,7 +164,7 @@ def main():
         "iterations_mixed": res_mixed[-1].iterations,
         "rel_residual_mixed": res_mixed[-1].rel_residual,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom_name),
                      "avg_ms": dom["avg_ms"], "bytes_per_launch": dom["bytes"] / dom["launches"]},
         "kernels_finest": {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1),
                                "launches": v["launches"]} for k, v in kt.items()},
