@@ -270,13 +270,22 @@ typedef enum {
                                block, 3-D), zcc (coarse planes per block), pipe (3-D:
                                1 = correction plane staged in LDS, next plane
                                prefetched; 2 = as 1 with the x weights applied in
-                               the fine threads, needs P/V <= 64)} */
+                               the fine threads, needs P/V <= 64; 3, 4 = as 2 with
+                               2 or 3 planes prefetched)} */
     MG_SHAPE_UPDATE = 2,    /* level 0 only: the FP64 refinement update, same five
                                values as MG_SHAPE_STENCIL */
     MG_SHAPE_SMOOTH = 3,    /* the first pre-smoothing kernel only (five values) */
     MG_SHAPE_SWEEP = 4,     /* the single sweeps only (five values); MG_SHAPE_STENCIL
                                sets SMOOTH, SWEEP and PROLONG together and reads SWEEP */
-    MG_SHAPE_PROLONG = 5    /* prolongation + correction + sweep only (five values) */
+    MG_SHAPE_PROLONG = 5,   /* prolongation + correction + sweep only (five values) */
+    MG_SHAPE_TAIL = 6       /* 3-D, level argument 0: {on (0|1)}.  When on (the
+                               default), the coarse end of the V-cycle -- from the
+                               first level of pitch <= 16 (<= 8 for FP64 levels)
+                               whose levels share one format, down to the base and
+                               back -- runs as one single-workgroup kernel with the
+                               levels in LDS; bitwise the same result.  The
+                               workspace copies of those levels are then not
+                               updated. */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);

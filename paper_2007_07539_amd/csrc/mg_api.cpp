@@ -75,7 +75,11 @@ struct mg_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph2 = nullptr;      // single grid: the update part of a step
+    hipGraphExec_t gexec2 = nullptr;
+    hipEvent_t ev_norm = nullptr;     // single grid: the norm readback of a step is done
     int outer_parts = 0;
+    bool tail_on = true;
     // profiling
     bool prof = false;
     std::vector<ProfRec> recs;
@@ -297,33 +301,74 @@ hipError_t enq_post(mg_ctx *h, hipStream_t st, int l, const void *b) {
 // Finest-level right-hand side modes of a V-cycle.
 enum RhsMode { RHS_B = 0, RHS_SCALED_R = 1, RHS_ALIAS_R = 2 };
 
+// Pre-smoothing of level l and restriction of its residual to level l + 1.
+hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const void *rhs) {
+    hipError_t e;
+    if (l == 0 && mode == RHS_ALIAS_R) {
+        // FP64 baseline without scaling: the residual is the right-hand side
+        LevelPlan &L = h->lv[0];
+        const double N = (double)points(h->dim, L.n);
+        const bool two = h->opt.nu1 >= 2;
+        RUN(h, st, two ? "smooth2" : "smooth1", 0, N * 16,
+            launch_smooth_first(h->dim, P_F64, L.P, Rbuf(h), nullptr, nullptr, nullptr, cbuf(h, 0, 0), h->opt.omega,
+                                two, L.shs[SH_SMOOTH], st));
+        int cur = 0;
+        for (int k = two ? 2 : 1; k < h->opt.nu1; ++k) {
+            RUN(h, st, "sweep", 0, N * 24,
+                launch_sweep(h->dim, P_F64, L.P, Rbuf(h), cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), h->opt.omega,
+                             L.shs[SH_SWEEP], st));
+            cur ^= 1;
+        }
+        h->cur[0] = cur;
+    } else {
+        if ((e = enq_presmooth(h, st, l, l == 0 && mode == RHS_SCALED_R)) != hipSuccess) return e;
+    }
+    return enq_restrict(h, st, l, rhs);
+}
+
+// First level of the fused coarse end (see launch_tail), or nl - 1 when the
+// V-cycle has none: the first level l >= 1 of pitch <= 16 (<= 8 for FP64)
+// from which all levels above the base share one format and fit in LDS.
+int tail_level(const mg_ctx *h) {
+    const int nl = h->nl;
+    if (!h->tail_on || h->dim != 3 || nl < 3) return nl - 1;
+    for (int l = 1; l < nl - 1; ++l) {
+        const int P = h->lv[l].P, prec = h->lv[l].prec;
+        if (P > (prec == P_F64 ? 8 : 16)) continue;
+        bool same = true;
+        for (int j = l; j < nl - 1; ++j) same = same && h->lv[j].prec == prec;
+        if (!same) continue;
+        const size_t lds = tail_lds_bytes(prec, h->lv[nl - 1].prec, P, nl - 1 - l);
+        if (lds > 0 && lds <= 65536) return l;
+    }
+    return nl - 1;
+}
+
 hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
     const int nl = h->nl;
     std::vector<const void *> rhs(nl);
     for (int l = 0; l < nl; ++l) rhs[l] = bbuf(h, l);
     if (mode == RHS_ALIAS_R) rhs[0] = Rbuf(h);
     hipError_t e;
-    for (int l = 0; l < nl - 1; ++l) {
-        if (l == 0 && mode == RHS_ALIAS_R) {
-            // FP64 baseline without scaling: the residual is the right-hand side
-            LevelPlan &L = h->lv[0];
-            const double N = (double)points(h->dim, L.n);
-            const bool two = h->opt.nu1 >= 2;
-            RUN(h, st, two ? "smooth2" : "smooth1", 0, N * 16,
-                launch_smooth_first(h->dim, P_F64, L.P, Rbuf(h), nullptr, nullptr, nullptr, cbuf(h, 0, 0),
-                                    h->opt.omega, two, L.shs[SH_SMOOTH], st));
-            int cur = 0;
-            for (int k = two ? 2 : 1; k < h->opt.nu1; ++k) {
-                RUN(h, st, "sweep", 0, N * 24,
-                    launch_sweep(h->dim, P_F64, L.P, Rbuf(h), cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), h->opt.omega,
-                                 L.shs[SH_SWEEP], st));
-                cur ^= 1;
-            }
-            h->cur[0] = cur;
-        } else {
-            if ((e = enq_presmooth(h, st, l, l == 0 && mode == RHS_SCALED_R)) != hipSuccess) return e;
+    const int lt = tail_level(h);
+    if (lt < nl - 1) {
+        // levels 0 .. lt-1 as separate launches, lt .. base fused
+        for (int l = 0; l < lt; ++l) {
+            if ((e = enq_vcycle_down(h, st, mode, l, rhs[l])) != hipSuccess) return e;
         }
-        if ((e = enq_restrict(h, st, l, rhs[l])) != hipSuccess) return e;
+        const LevelPlan &T = h->lv[lt];
+        RUN(h, st, "coarse_tail", lt, 0.0,
+            launch_tail(T.prec, h->lv[nl - 1].prec, T.P, nl - 1 - lt, bbuf(h, lt), cbuf(h, lt, 0), h->opt.nu1,
+                        h->opt.nu2, h->opt.omega, st));
+        h->cur[lt] = 0;
+        for (int l = lt - 1; l >= 0; --l) {
+            if ((e = enq_prolong(h, st, l, rhs[l])) != hipSuccess) return e;
+            if ((e = enq_post(h, st, l, rhs[l])) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    for (int l = 0; l < nl - 1; ++l) {
+        if ((e = enq_vcycle_down(h, st, mode, l, rhs[l])) != hipSuccess) return e;
     }
     if ((e = enq_coarse(h, st, nl - 1)) != hipSuccess) return e;
     for (int l = nl - 2; l >= 0; --l) {
@@ -337,9 +382,13 @@ bool finest_alias(mg_ctx *h) { return h->lv[0].prec == P_F64 && !h->opt.residual
 
 // One refinement step of Algorithm 2 (scale and cast, V-cycle, update) plus
 // the norm readback.
-hipError_t enq_step(mg_ctx *h, hipStream_t st) {
-    hipError_t e = enq_vcycle(h, st, finest_alias(h) ? RHS_ALIAS_R : RHS_SCALED_R);
-    if (e != hipSuccess) return e;
+// The V-cycle part of a refinement step (writes only level vectors).
+hipError_t enq_cycle(mg_ctx *h, hipStream_t st) {
+    return enq_vcycle(h, st, finest_alias(h) ? RHS_ALIAS_R : RHS_SCALED_R);
+}
+
+// The update part: u, r, norms, alpha, and the norm readback.
+hipError_t enq_update(mg_ctx *h, hipStream_t st) {
     LevelPlan &L = h->lv[0];
     const double hh = 1.0 / (double)(L.n + 1);
     const double N = (double)points(h->dim, L.n);
@@ -351,27 +400,42 @@ hipError_t enq_step(mg_ctx *h, hipStream_t st) {
     return hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st);
 }
 
+// One refinement step of Algorithm 2 (scale and cast, V-cycle, update) plus
+// the norm readback.
+hipError_t enq_step(mg_ctx *h, hipStream_t st) {
+    hipError_t e = enq_cycle(h, st);
+    return e != hipSuccess ? e : enq_update(h, st);
+}
+
 void drop_graph(mg_ctx *h) {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
+    if (h->gexec2) (void)hipGraphExecDestroy(h->gexec2);
+    if (h->graph2) (void)hipGraphDestroy(h->graph2);
+    h->gexec = h->gexec2 = nullptr;
+    h->graph = h->graph2 = nullptr;
 }
 
+// Capture the cycle part and the update part of a refinement step as two
+// graphs, so that the next cycle can be queued before the host has read the
+// current step's norm.
 mg_status_t ensure_graph(mg_ctx *h) {
-    if (h->gexec) return MG_OK;
+    if (h->gexec && h->gexec2) return MG_OK;
+    drop_graph(h);
     if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enq_step(h, h->cap_stream);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
-    if (e != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(MG_ERR_HIP, "capture of the refinement step failed: %s", hipGetErrorString(e));
+    for (int part = 0; part < 2; ++part) {
+        HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = part == 0 ? enq_cycle(h, h->cap_stream) : enq_update(h, h->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(MG_ERR_HIP, "capture of the refinement step failed: %s", hipGetErrorString(e));
+        }
+        if (e2 != hipSuccess) return fail(MG_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+        (part == 0 ? h->graph : h->graph2) = g;
+        HIPCHK(hipGraphInstantiate(part == 0 ? &h->gexec : &h->gexec2, g, nullptr, nullptr, 0));
     }
-    if (e2 != hipSuccess) return fail(MG_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
-    h->graph = g;
-    HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
     return MG_OK;
 }
 
@@ -406,10 +470,10 @@ bool restrict_ok(const mg_ctx *h, const LevelPlan &L, const RShape &r) {
     const int Pc = L.P / 2;
     if ((r.V != 4 && r.V != 8) || r.V > L.P || r.zcc < 1 || r.zcc > std::max(1, Pc - 1)) return false;
     if (h->dim == 2 && (r.tyc != 1 || r.pipe)) return false;
-    if (r.pipe < 0 || r.pipe > 2) return false;
-    if (r.pipe == 2 && (L.P / r.V > 64 || r.V < 4)) return false;  // rows must not straddle waves
+    if (r.pipe < 0 || r.pipe > 4) return false;
+    if (r.pipe >= 2 && (L.P / r.V > 64 || r.V < 4)) return false;  // rows must not straddle waves
     if (r.tyc < 1 || r.tyc > std::max(1, Pc - 1)) return false;
-    const int G = h->dim == 3 ? 2 * r.tyc + 1 + 2 * r.pipe : 1;
+    const int G = h->dim == 3 ? 2 * r.tyc + 1 + (r.pipe ? 2 : 0) : 1;
     if (G * (L.P / r.V) > 1024 || restrict_lds_bytes(h->dim, L.P, L.prec, r) > 65536) return false;
     if (L.prec == P_F64 && r.V == 8 && h->dim == 3) return false;  // spills registers
     return true;
@@ -485,7 +549,7 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
         for (int V : {4, 8})
             for (int tyc : {1, 2, 3, 4, 5, 7})
                 for (int zcc : {2, 4, 8, 16, 32})
-                    for (int pipe : {0, 1, 2}) {
+                    for (int pipe : {0, 1, 2, 3, 4}) {
                     RShape r{V, tyc, zcc, pipe};
                     if (!restrict_ok(h, L, r)) continue;
                     const float t = time_ms(st, [&]() {
@@ -676,6 +740,7 @@ mg_status_t mg_destroy(mg_handle h) {
     if (!h) return MG_OK;
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->ev_norm) (void)hipEventDestroy(h->ev_norm);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
     if (h->host_active) (void)hipHostFree(h->host_active);
     if (h->host_scal_all) (void)hipHostFree(h->host_scal_all);
@@ -856,10 +921,17 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
         s = ensure_graph(h);
         if (s != MG_OK) return s;
     }
+    if (!h->ev_norm) HIPCHK(hipEventCreateWithFlags(&h->ev_norm, hipEventDisableTiming));
     int k = 0;
-    bool recursive = false;  // whether R holds a recursively updated residual
+    bool recursive = false;      // whether R holds a recursively updated residual
+    bool cycle_queued = false;   // the V-cycle of the next step is already on the stream
+    double prev_rn = -1.0;
     mg_status_t result = MG_OK;
     double rel = h->host_scal[2] / nb;
+    auto launch = [&](bool cycle) -> hipError_t {
+        if (graph) return hipGraphLaunch(cycle ? h->gexec : h->gexec2, st);
+        return cycle ? enq_cycle(h, st) : enq_update(h, st);
+    };
     for (;;) {
         const double rn = h->host_scal[2];
         rel = rn / nb;
@@ -870,12 +942,15 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
         }
         if (rn <= h->opt.rtol * nb) {
             if (!recursive) break;
-            // confirm with the residual recomputed from u
+            // confirm with the residual recomputed from u (a queued V-cycle
+            // only wrote level vectors and is discarded)
+            cycle_queued = false;
             HIPCHK(launch_resid_flat(D, L.n, L.P, b, Ubuf(h), Rbuf(h), u, inv_h2, part(h), st));
             HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
             HIPCHK(hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             recursive = false;
+            prev_rn = -1.0;
             rel = h->host_scal[2] / nb;
             hist(k, rel);
             if (h->host_scal[2] <= h->opt.rtol * nb) {
@@ -888,16 +963,29 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
             result = fail(MG_ERR_NOT_CONVERGED, "not converged in %d iterations (rel. residual %.3e)", k, rel);
             break;
         }
-        if (graph) {
-            HIPCHK(hipGraphLaunch(h->gexec, st));
-        } else {
-            hipError_t e = enq_step(h, st);
-            if (e != hipSuccess) return fail(MG_ERR_HIP, "refinement step launch failed: %s", hipGetErrorString(e));
+        hipError_t e = hipSuccess;
+        if (!cycle_queued) e = launch(true);
+        if (e == hipSuccess) e = launch(false);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_norm, st);
+        // Queue the next step's V-cycle before reading this step's norm when
+        // the residual is unlikely to reach the tolerance in this step (the
+        // prediction uses the last contraction factor; a wrong guess costs
+        // one discarded V-cycle, never a different result).
+        cycle_queued = false;
+        if (e == hipSuccess && k + 1 < h->opt.max_iter) {
+            const double rho = prev_rn > 0.0 ? std::min(1.0, rn / prev_rn) : 0.5;
+            if (rn * rho > 8.0 * h->opt.rtol * nb) {
+                e = launch(true);
+                cycle_queued = e == hipSuccess;
+            }
         }
-        HIPCHK(hipStreamSynchronize(st));
+        if (e != hipSuccess) return fail(MG_ERR_HIP, "refinement step launch failed: %s", hipGetErrorString(e));
+        HIPCHK(hipEventSynchronize(h->ev_norm));
+        prev_rn = rn;
         recursive = true;
         ++k;
     }
+    if (cycle_queued) HIPCHK(hipStreamSynchronize(st));
     // final: recompute the true residual and copy u out
     HIPCHK(launch_resid_flat(D, L.n, L.P, b, Ubuf(h), Rbuf(h), u, inv_h2, part(h), st));
     HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
@@ -911,6 +999,12 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np) {
     if (!h || !p) return fail(MG_ERR_ARG, "null argument");
     if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
+    if (kind == MG_SHAPE_TAIL) {
+        if (np != 1 || (p[0] != 0 && p[0] != 1)) return fail(MG_ERR_ARG, "the tail shape is {0|1}");
+        h->tail_on = p[0] != 0;
+        drop_graph(h);
+        return MG_OK;
+    }
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
     LevelPlan &L = h->lv[level];
     const int D = h->dim;
@@ -953,6 +1047,11 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
     if (!h || !p) return fail(MG_ERR_ARG, "null argument");
     if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
+    if (kind == MG_SHAPE_TAIL) {
+        if (np < 1) return fail(MG_ERR_ARG, "too few values");
+        p[0] = h->tail_on ? 1 : 0;
+        return MG_OK;
+    }
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
     const LevelPlan &L = h->lv[level];
     const bool stencil_kind = kind == MG_SHAPE_STENCIL || kind == MG_SHAPE_SMOOTH || kind == MG_SHAPE_SWEEP ||

@@ -1035,7 +1035,9 @@ __global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, con
 // grid row never straddles two waves); the LDS row buffer then holds the
 // x-restricted values, P/2 per row, and the coarse threads read VC of them
 // per row as one vector.
-template <int V, class TF, class TC, bool XSH>
+// DP: planes of c and b in flight ahead of the plane being processed (the
+// loads for plane zf + 1 + DP are issued while plane zf is computed).
+template <int V, class TF, class TC, bool XSH, int DP = 1>
 __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, const TF *__restrict__ c,
                                                     TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles,
                                                     int xcd) {
@@ -1070,8 +1072,8 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
     const PArr<TF, A, V> f{c};
     const size_t cslot = (size_t)G * P, rslot = (size_t)R * RW;
     const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
-    typename PArr<TF, A, V>::Raw fr;
-    RawRow<TF, V> braw, bnext;
+    typename PArr<TF, A, V>::Raw fr, fq[DP];
+    RawRow<TF, V> braw, bq[DP];
     A cm[V], cc[V], cp[V], dummy[V];
     A acc[VC];
 #pragma unroll
@@ -1086,8 +1088,12 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
         for (int i = 0; i < V; ++i) t[i] = store_as<TF>(cc[i]);
         store_row<TF, V>(cs + (size_t)gi * P + x0, t);
     }
-    f.fetch(g, x0, y, zf0 + 1, fr);
-    if (res_row) fetch_row<TF, V>(b + g.at(x0, y, zf0), bnext);
+    // queues: fq[d] holds c plane zf + 1 + d, bq[d] holds b plane zf + d
+#pragma unroll
+    for (int d = 0; d < DP; ++d) {
+        if (zf0 + 1 + d <= zf1 + 1) f.fetch(g, x0, y, zf0 + 1 + d, fq[d]);
+        if (res_row && zf0 + d <= zf1) fetch_row<TF, V>(b + g.at(x0, y, zf0 + d), bq[d]);
+    }
 
     // coarse step: fold the residual rows of fine plane zf (in slot s) into acc
     auto coarse_step = [&](int zf, int s) {
@@ -1137,10 +1143,15 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
         const int it = zf - zf0;
 #pragma unroll
         for (int i = 0; i < V; ++i) rkeep[i] = A(0);
-        f.value(fr, x0, y, zf + 1, cp, dummy);
-        if (zf + 2 <= zf1 + 1) f.fetch(g, x0, y, zf + 2, fr);
-        braw = bnext;
-        if (res_row && zf + 1 <= zf1) fetch_row<TF, V>(b + g.at(x0, y, zf + 1), bnext);
+        f.value(fq[0], x0, y, zf + 1, cp, dummy);
+        braw = bq[0];
+#pragma unroll
+        for (int d = 0; d + 1 < DP; ++d) {
+            fq[d] = fq[d + 1];
+            bq[d] = bq[d + 1];
+        }
+        if (zf + 1 + DP <= zf1 + 1) f.fetch(g, x0, y, zf + 1 + DP, fq[DP - 1]);
+        if (res_row && zf + DP <= zf1) fetch_row<TF, V>(b + g.at(x0, y, zf + DP), bq[DP - 1]);
         __syncthreads();
         if (coarse && it > 0) coarse_step(zf - 1, (it - 1) & 1);
         if (res_row) {
@@ -1364,7 +1375,7 @@ size_t restrict_lds_bytes(int D, int P, int pf, const RShape &s) {
     const size_t acc = pf == P_F64 ? 8 : 4;
     if (D == 3 && s.pipe)
         return 2 * (size_t)(2 * s.tyc + 3) * P * prec_bytes(pf) +
-               2 * (size_t)(2 * s.tyc + 1) * (s.pipe == 2 ? P / 2 : P) * acc;
+               2 * (size_t)(2 * s.tyc + 1) * (s.pipe >= 2 ? P / 2 : P) * acc;
     const int G = D == 3 ? 2 * s.tyc + 1 : 1;
     return 2 * (size_t)G * P * acc;
 }
@@ -1580,7 +1591,15 @@ static hipError_t restrict_run(int P, const void *b, const void *c, void *bc, co
         const int blocks = ytiles * ceil_div(Pc - 1, s.zcc);
         const int threads = (2 * s.tyc + 3) * (P / V);
         const size_t lds = restrict_lds_bytes(D, P, prec_of<TF>(), s);
-        if (s.pipe == 2)
+        if (s.pipe == 4)
+            hipLaunchKernelGGL((k_restrict2<V, TF, TC, true, 3>), dim3(blocks), dim3(threads), lds, st,
+                               static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P,
+                               s.tyc, s.zcc, ytiles, 1);
+        else if (s.pipe == 3)
+            hipLaunchKernelGGL((k_restrict2<V, TF, TC, true, 2>), dim3(blocks), dim3(threads), lds, st,
+                               static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P,
+                               s.tyc, s.zcc, ytiles, 1);
+        else if (s.pipe == 2)
             hipLaunchKernelGGL((k_restrict2<V, TF, TC, true>), dim3(blocks), dim3(threads), lds, st,
                                static_cast<const TF *>(b), static_cast<const TF *>(c), static_cast<TC *>(bc), P,
                                s.tyc, s.zcc, ytiles, 1);

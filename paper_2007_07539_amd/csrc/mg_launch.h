@@ -80,6 +80,14 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, unsigned *sink,
                         hipStream_t st);
 
+// Fused coarse end of a 3-D V-cycle in one workgroup (LDS-resident levels):
+// nlev grids of format prec with pitches P0 = 4 * 2^(nlev-1), ..., 4, then the
+// one-point base of format pb.  b: right-hand side of the first (padded, pitch
+// P0); c: receives its corrected, post-smoothed correction.
+size_t tail_lds_bytes(int prec, int pb, int P0, int nlev);  // 0 if unsupported
+hipError_t launch_tail(int prec, int pb, int P0, int nlev, const void *b, void *c, int nu1, int nu2, double omega,
+                       hipStream_t st);
+
 // ---- batched instances -------------------------------------------------------
 // Per-(instance, level) arguments of one batched launch.
 struct BDesc {

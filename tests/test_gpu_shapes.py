@@ -24,7 +24,8 @@ STENCIL = [[V, zc, bs, xcd, ty] for V, zc, bs, xcd, ty in
            [(8, 1, 256, 0, 0), (4, 3, 64, 1, 0), (8, 7, 128, 1, 0), (8, 64, 256, 1, 0),
             (8, 1, 256, 0, 1), (4, 5, 256, 1, 2), (8, 8, 256, 1, 6), (8, 3, 256, 0, 14), (4, 16, 256, 1, 3)]]
 RESTRICT = [[4, 1, 1, 0], [8, 2, 3, 0], [8, 7, 5, 0], [4, 3, 64, 0], [8, 1, 1, 1], [4, 2, 7, 1], [8, 4, 16, 1],
-            [8, 6, 3, 1], [8, 1, 2, 2], [4, 3, 5, 2], [8, 5, 9, 2], [8, 6, 1, 2]]
+            [8, 6, 3, 1], [8, 1, 2, 2], [4, 3, 5, 2], [8, 5, 9, 2], [8, 6, 1, 2], [8, 2, 7, 3], [4, 1, 3, 3],
+            [8, 3, 16, 4], [8, 1, 1, 4]]
 
 
 def _apply(s, kind, shape):
@@ -46,6 +47,7 @@ def test_shapes_bitwise(dev, name, n):
     b64 = torch.from_numpy(W.uniform_rhs(3, n, seed=5)).to(dev)
     bl = b64.to(mgir.TORCH_DTYPE[prec[0]])
     s = mgir.Solver(3, n, prec)
+    s.set_shape(0, mgir.SHAPE_TAIL, [0])  # every level through its own kernels
     defaults = {k: [s.get_shape(l, k) for l in range(s.nlevels - 1) if k != mgir.SHAPE_UPDATE or l == 0]
                 for k in (mgir.SHAPE_STENCIL, mgir.SHAPE_RESTRICT, mgir.SHAPE_UPDATE)}
     c_ref = s.vcycle(bl).clone()
@@ -75,3 +77,24 @@ def test_autotuned_solver_matches_default(dev):
     st = mgir.Solver(3, n, prec, autotune=True)
     u1, r1 = st.solve(b)
     assert r0.iterations == r1.iterations and torch.equal(u0, u1)
+
+
+@pytest.mark.parametrize("name,n", [("f16", 7), ("f16", 63), ("f64", 31), ("f32", 15), ("bf16", 127), ("hsd", 255),
+                                    ("h_mg", 63), ("f64", 127)])
+def test_fused_tail_bitwise(dev, name, n):
+    """The single-workgroup coarse end computes exactly the per-level kernels."""
+    print(f"tail {name} n={n}", flush=True)
+    prec = W.precision_map(name, W.levels_for(n))
+    b64 = torch.from_numpy(W.uniform_rhs(3, n, seed=7)).to(dev)
+    bl = b64.to(mgir.TORCH_DTYPE[prec[0]])
+    s = mgir.Solver(3, n, prec)
+    assert s.get_shape(0, mgir.SHAPE_TAIL) == [1]
+    c_on = s.vcycle(bl).clone()
+    u_on, r_on = s.solve(b64)
+    u_on = u_on.clone()
+    s.set_shape(0, mgir.SHAPE_TAIL, [0])
+    c_off = s.vcycle(bl)
+    u_off, r_off = s.solve(b64)
+    assert torch.equal(c_on, c_off)
+    assert r_on.iterations == r_off.iterations and torch.equal(u_on, u_off)
+    assert r_on.history == r_off.history
