@@ -77,6 +77,58 @@ def kernel_table(prof, level=0):
     return agg
 
 
+def extra_workloads(torch, mgir, W, dev, steps):
+    """Throughput of the batched and many-right-hand-side solves (FP16 V-cycles
+    and the FP64 solve of the same problems), each with inputs resident in HBM."""
+    res = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, r
+
+    ns, rhs = W.batched_instances()
+    dof = float(sum(n**3 for n in ns))
+    bs = [torch.from_numpy(r).to(dev) for r in rhs]
+    us = [torch.zeros_like(b) for b in bs]
+    entry = {"instances": len(ns), "sizes": {str(n): ns.count(n) for n in sorted(set(ns))}, "dof": dof}
+    for name, scaling in (("f16", True), ("f64", False)):
+        log(f"[bench] batched 64 instances, map {name}")
+        s = mgir.BatchedSolver(ns, W.precision_map(name, 8), residual_scaling=scaling, device=dev)
+        sec, (_, r, st) = timed(lambda: s.solve(bs, us))
+        entry[name] = {"ms": sec * 1e3, "dof_per_s": dof / sec, "status": st,
+                       "max_iterations": max(x.iterations for x in r),
+                       "max_rel_residual": max(x.rel_residual for x in r)}
+        del s
+        torch.cuda.empty_cache()
+    entry["speedup_f16_vs_f64"] = entry["f64"]["ms"] / entry["f16"]["ms"]
+    res["batched_64_instances"] = entry
+    del bs, us
+    torch.cuda.empty_cache()
+
+    n, k = 127, 32
+    b = torch.from_numpy(W.multi_rhs(n, k, seed=5)).to(dev)
+    u = torch.zeros_like(b)
+    dof = float(n**3 * k)
+    entry = {"n": n, "nrhs": k, "dof_x_rhs": dof}
+    for name, scaling in (("f16", True), ("f64", False)):
+        log(f"[bench] {k} right-hand sides at {n}^3, map {name}")
+        s = mgir.MultiSolver(n, k, W.precision_map(name, W.levels_for(n)), residual_scaling=scaling, device=dev)
+        sec, (_, r, st) = timed(lambda: s.solve(b, u))
+        entry[name] = {"ms": sec * 1e3, "dof_rhs_per_s": dof / sec, "status": st,
+                       "max_iterations": max(x.iterations for x in r),
+                       "max_rel_residual": max(x.rel_residual for x in r)}
+        del s
+        torch.cuda.empty_cache()
+    entry["speedup_f16_vs_f64"] = entry["f64"]["ms"] / entry["f16"]["ms"]
+    res["many_rhs_127x32"] = entry
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +140,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only run the mixed solve (for rocprofv3)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched-instances and many-right-hand-sides measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
@@ -178,6 +232,8 @@ def main():
         out["speedup_mixed_vs_fp64"] = ms64 / ms_mixed
         out["kernels_finest_fp64"] = {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1)}
                                       for k, v in kt64.items()}
+    if not args.no_extra and not args.profile_only:
+        out["extra"] = extra_workloads(torch, mgir, W, dev, args.steps)
     if not args.no_cpu_baseline and not args.profile_only:
         import oracle
         oracle.build()

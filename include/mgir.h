@@ -265,7 +265,8 @@ typedef enum {
                                thread), bs (threads per block, 64..256, register-queue
                                kernel), xcd (0|1: keep neighbouring tiles on one XCD),
                                ty (3-D: 0 = register-queue kernel, > 0 = LDS-plane
-                               kernel with ty output rows per block)} */
+                               kernel with ty output rows per block)[, dp (LDS-plane
+                               kernel: 1 or 2 planes loaded ahead; default 1)]} */
     MG_SHAPE_RESTRICT = 1,  /* residual + restriction: {V (4|8), tyc (coarse rows per
                                block, 3-D), zcc (coarse planes per block), pipe (3-D:
                                1 = correction plane staged in LDS, next plane

@@ -112,7 +112,7 @@ struct mg_ctx {
     std::vector<unsigned char> bmeta_img_tmp;
     // many right-hand sides (interleaved); nrhs == 0 for other handles
     int nrhs = 0;
-    size_t off_act = 0, off_mask = 0, off_zmask = 0;
+    size_t off_act = 0, off_mask = 0, off_zmask = 0, off_mres = 0;
     int m_upd_blocks = 0;
     int *host_mask = nullptr;
     double *host_scal_m = nullptr;
@@ -458,6 +458,7 @@ int level_prec_code(int p) { return p; }
 // choice changes speed only.  Workspace contents are scratch at this point.
 bool stencil_ok(const mg_ctx *h, const LevelPlan &L, const Shape &s) {
     if ((s.V != 4 && s.V != 8) || s.V > L.P || s.zc < 1 || s.zc > L.P - 1) return false;
+    if (s.dp < 1 || s.dp > 2 || (s.dp == 2 && s.ty == 0)) return false;
     if (s.ty > 0) {
         if (h->dim != 3) return false;
         if ((L.P / s.V) * (s.ty + 2) > 1024 || march_lds_bytes(L.P, s.ty, prec_bytes(L.prec)) > 65536) return false;
@@ -506,11 +507,13 @@ std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool 
     for (int V : {4, 8})
         for (int ty : tys)
             for (int zc : zcs) {
-                Shape s{V, zc, 256, 1, ty};
-                if (ty == 0 && h->dim == 3 && zc < 8) continue;
-                if (update && V == 8 && ty > 0) continue;  // FP64 rows spill at V = 8
-                if (L.prec == P_F64 && V == 8 && ty > 0) continue;
-                if (stencil_ok(h, L, s)) out.push_back(s);
+                for (int dp = 1; dp <= (ty > 0 ? 2 : 1); ++dp) {
+                    Shape s{V, zc, 256, 1, ty, dp};
+                    if (ty == 0 && h->dim == 3 && zc < 8) continue;
+                    if (update && V == 8 && ty > 0) continue;  // FP64 rows spill at V = 8
+                    if (L.prec == P_F64 && V == 8 && ty > 0) continue;
+                    if (stencil_ok(h, L, s)) out.push_back(s);
+                }
             }
     return out;
 }
@@ -1012,8 +1015,10 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
                               kind == MG_SHAPE_SWEEP || kind == MG_SHAPE_PROLONG;
     if (stencil_kind) {
         if (kind == MG_SHAPE_UPDATE && level != 0) return fail(MG_ERR_ARG, "the update shape exists on level 0 only");
-        if (np != 5) return fail(MG_ERR_ARG, "stencil shape takes 5 values {V, zc, bs, xcd, ty}");
-        Shape s{p[0], p[1], p[2], p[3], p[4]};
+        if (np != 5 && np != 6) return fail(MG_ERR_ARG, "stencil shape takes 5 or 6 values {V, zc, bs, xcd, ty[, dp]}");
+        Shape s{p[0], p[1], p[2], p[3], p[4], np == 6 ? p[5] : 1};
+        if (s.dp < 1 || s.dp > 2 || (s.dp == 2 && s.ty == 0))
+            return fail(MG_ERR_ARG, "dp must be 1, or 2 with ty > 0");
         if ((s.V != 4 && s.V != 8) || s.V > L.P) return fail(MG_ERR_ARG, "V must be 4 or 8 and <= P = %d", L.P);
         if (s.zc < 1 || s.zc > L.P) return fail(MG_ERR_ARG, "zc out of range");
         if (s.bs < 64 || s.bs > 256 || s.bs % 64) return fail(MG_ERR_ARG, "bs must be 64, 128, 192 or 256");
@@ -1062,6 +1067,7 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
                          : kind == MG_SHAPE_PROLONG ? L.shs[SH_PROLONG]
                                                     : L.shs[SH_SWEEP];
         p[0] = S.V, p[1] = S.zc, p[2] = S.bs, p[3] = S.xcd, p[4] = S.ty;
+        if (np >= 6) p[5] = S.dp;
     } else if (kind == MG_SHAPE_RESTRICT && np >= 4) {
         p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc, p[3] = L.rsh.pipe;
     } else {
@@ -1669,10 +1675,10 @@ hipError_t enq_multi_step(mg_ctx *h, hipStream_t st) {
         }
         h->cur[l] = cur;
         MArgs r;
-        r.prec = L.prec, r.pc = h->lv[l + 1].prec, r.P = L.P, r.K = K, r.zc = L.rsh.zcc;
+        r.prec = L.prec, r.pc = h->lv[l + 1].prec, r.P = L.P, r.K = K, r.zc = L.shs[SH_SWEEP].zc;
         r.b = rhs(l), r.cin = cbuf(h, l, cur), r.cout = bbuf(h, l + 1);
         RUN(h, st, "resid_restrict", l, N * 2 * s + (double)points(3, h->lv[l + 1].n) * K * sb(r.pc),
-            launch_m_stage(MS_RESTRICT, r, st));
+            launch_m_restrict2(r, h->ws + h->off_mres, L.rsh.zcc, st));
     }
     RUN(h, st, "coarse_solve", nl - 1, 2.0 * K * sb(h->lv[nl - 1].prec),
         launch_m_coarse(h->lv[nl - 1].prec, K, bbuf(h, nl - 1), cbuf(h, nl - 1, 0), st));
@@ -1686,8 +1692,9 @@ hipError_t enq_multi_step(mg_ctx *h, hipStream_t st) {
         a.prec = L.prec, a.pc = h->lv[l + 1].prec, a.P = L.P, a.K = K, a.zc = L.shs[SH_PROLONG].zc;
         a.omega = h->opt.omega;
         a.b = rhs(l), a.cin = cbuf(h, l, cur), a.ec = cbuf(h, l + 1, h->cur[l + 1]), a.cout = cbuf(h, l, cur ^ 1);
-        RUN(h, st, "prolong_sweep", l, N * 3 * s + (double)points(3, h->lv[l + 1].n) * K * sb(a.pc),
-            launch_m_stage(MS_PROLONG, a, st));
+        RUN(h, st, "prolong", l, N * 2 * s + (double)points(3, h->lv[l + 1].n) * K * sb(a.pc),
+            launch_m_prolong_field(a, st));
+        RUN(h, st, "prolong_sweep", l, N * 3 * s, launch_m_stage(MS_SWEEP, a, st));
         cur ^= 1;
         for (int k = 1; k < h->opt.nu2; ++k) {
             MArgs w;
@@ -1770,6 +1777,9 @@ mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_pr
     h->off_act = off, off += 256;
     h->off_mask = off, off += 256;
     h->off_zmask = off, off += 256;
+    size_t mres = 0;
+    for (int l = 0; l + 1 < m; ++l) mres = std::max(mres, m_resid_bytes(h->lv[l].prec, h->lv[l].elems));
+    h->off_mres = off, off += align_up(mres, 256);
     h->ws_need = off;
     *out = h;
     return MG_OK;

@@ -781,7 +781,9 @@ template <class F> struct StageOf<F, typename std::enable_if<F::kStaged>::type> 
     typedef typename F::Stage type;
 };
 
-template <int V, class F, class E>
+// DP: field and emit rows of DP planes ahead are in flight while a plane is
+// computed (the loads for plane z + 1 + DP are issued in iteration z).
+template <int V, class F, class E, int DP = 1>
 __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int zc, int ytiles, int xcd) {
     typedef typename F::acc A;
     typedef typename F::lds_t LT;
@@ -807,8 +809,8 @@ __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int 
     const size_t slot = (size_t)G * P;
     typename E::State st;
     e.init(st);
-    typename F::Raw fr;
-    typename E::Raw er;
+    typename F::Raw fr, fq[DP];
+    typename E::Raw eq[DP];
     A cm[V], cc[V], cp[V], ac[V], ap[V];
     F f = f_in;
     const int nthr = blockDim.x;
@@ -831,19 +833,28 @@ __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int 
         for (int i = 0; i < V; ++i) t[i] = store_as<LT>(cc[i]);
         store_row<LT, V>(lds + (size_t)gi * P + x0, t);
     }
-    f.fetch(g, x0, y, z0 + 1, fr);
-    if (out_row) e.fetch(g, x0, y, z0, er);
+    // queues: fq[d] holds field plane z + 1 + d, eq[d] the emit rows of plane z + d
+#pragma unroll
+    for (int d = 0; d < DP; ++d) {
+        if (z0 + 1 + d <= z1) f.fetch(g, x0, y, z0 + 1 + d, fq[d]);
+        if (out_row && z0 + d < z1) e.fetch(g, x0, y, z0 + d, eq[d]);
+    }
     if constexpr (F::kStaged) __syncthreads();  // prologue reads of the staged slots are done
     for (int z = z0; z < z1; ++z) {
         const int it = z - z0;
-        f.value(fr, x0, y, z + 1, cp, ap);
+        f.value(fq[0], x0, y, z + 1, cp, ap);
         if constexpr (F::kStaged) {
             f.stage_store(z + 2, threadIdx.x, nthr, S);
             if (z + 3 <= z1) f.stage_fetch(z + 3, threadIdx.x, nthr, S);
         }
-        if (z + 2 <= z1) f.fetch(g, x0, y, z + 2, fr);
-        const typename E::Raw ecur = er;
-        if (out_row && z + 1 < z1) e.fetch(g, x0, y, z + 1, er);
+        const typename E::Raw ecur = eq[0];
+#pragma unroll
+        for (int d = 0; d + 1 < DP; ++d) {
+            fq[d] = fq[d + 1];
+            eq[d] = eq[d + 1];
+        }
+        if (z + 1 + DP <= z1) f.fetch(g, x0, y, z + 1 + DP, fq[DP - 1]);
+        if (out_row && z + DP < z1) e.fetch(g, x0, y, z + DP, eq[DP - 1]);
         __syncthreads();
         if (out_row) {
             const LT *S = lds + (size_t)(it & 1) * slot;
@@ -1410,8 +1421,12 @@ static hipError_t run_march(const F &f, const E &e, int P, const Shape &s, hipSt
     const int nch = stencil_chunks(P, s.zc);
     const int threads = (P / V) * (s.ty + 2);
     const size_t lds = march_lds_bytes(P, s.ty, sizeof(typename F::lds_t)) + StagedBytes<F>::get(P, s.ty);
-    hipLaunchKernelGGL((k_march<V, F, E>), dim3(ytiles * nch), dim3(threads), lds, st, f, e, P, s.ty, s.zc, ytiles,
-                       s.xcd);
+    if (s.dp == 2 && !F::kStaged)
+        hipLaunchKernelGGL((k_march<V, F, E, 2>), dim3(ytiles * nch), dim3(threads), lds, st, f, e, P, s.ty, s.zc,
+                           ytiles, s.xcd);
+    else
+        hipLaunchKernelGGL((k_march<V, F, E, 1>), dim3(ytiles * nch), dim3(threads), lds, st, f, e, P, s.ty, s.zc,
+                           ytiles, s.xcd);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ struct Shape {
     int bs;   // threads per block (multiple of 64, <= 256), register-queue kernel only
     int xcd;  // 1: remap block ids so consecutive tiles share an XCD
     int ty;   // 3-D only: > 0 selects the LDS-plane kernel with ty output rows per block
+    int dp = 1;  // LDS-plane kernel: planes loaded ahead of the one being computed (1 or 2)
 };
 
 // LDS bytes of the LDS-plane kernel for a level of storage size sb bytes.
@@ -138,7 +139,7 @@ struct MArgs {
     void *cout = nullptr;          // output correction, or coarse right-hand side (restriction)
     double omega = 0.8;
 };
-enum { MS_SMOOTH2 = 0, MS_SWEEP = 1, MS_PROLONG = 2, MS_RESTRICT = 3 };
+enum { MS_SMOOTH2 = 0, MS_SWEEP = 1 };
 
 int m_vec(int prec);
 bool m_supported(int prec, int K);
@@ -153,5 +154,12 @@ hipError_t launch_m_resid(int n, int P, int K, const double *b, const double *U,
 hipError_t launch_m_pack(int n, int P, int K, const double *src, double *dst, const int *keep, hipStream_t st);
 hipError_t launch_m_finalize(const double *part, int nparts, int K, double *scal, const int *mask, int scaling,
                              hipStream_t st);
+// Two-pass restriction: the fine residual (accumulator type, m_resid_bytes
+// for a level of `elems` values) into rbuf, then full weighting into a.cout.
+size_t m_resid_bytes(int prec, size_t elems);
+hipError_t launch_m_restrict2(const MArgs &a, void *rbuf, int zcc, hipStream_t st);
+// c = round(c + 4 P e) in place on a.cin (then a plain sweep completes the
+// prolongation stage).
+hipError_t launch_m_prolong_field(const MArgs &a, hipStream_t st);
 
 }  // namespace mg

@@ -308,7 +308,7 @@ __device__ __forceinline__ void mstencil_body(const F &f, E &e, const MGrid &g, 
     }
 }
 
-enum { MK_SMOOTH2 = 0, MK_SMOOTH2_SCALED = 1, MK_SWEEP = 2, MK_PROLONG = 3 };
+enum { MK_SMOOTH2 = 0, MK_SMOOTH2_SCALED = 1, MK_SWEEP = 2 };
 
 template <int V, int KIND, class T, class TC>
 __global__ __launch_bounds__(256) void k_mstencil(const void *b, const double *r, const double *inv, const int *act,
@@ -336,14 +336,9 @@ __global__ __launch_bounds__(256) void k_mstencil(const void *b, const double *r
         const MJac0<T, R> f{rh, kw};
         MSweep<T, R, true> e{rh, static_cast<T *>(cout), static_cast<T *>(bout), kw};
         mstencil_body<V>(f, e, g, m);
-    } else if constexpr (KIND == MK_SWEEP) {
-        typedef MArr<T, A> R;
-        const R f{static_cast<const T *>(cin)};
-        MSweep<T, R, false> e{R{static_cast<const T *>(b)}, static_cast<T *>(cout), nullptr, kw};
-        mstencil_body<V>(f, e, g, m);
     } else {
         typedef MArr<T, A> R;
-        const MProl<T, TC> f{static_cast<const T *>(cin), static_cast<const TC *>(ec), P / 2};
+        const R f{static_cast<const T *>(cin)};
         MSweep<T, R, false> e{R{static_cast<const T *>(b)}, static_cast<T *>(cout), nullptr, kw};
         mstencil_body<V>(f, e, g, m);
     }
@@ -368,40 +363,42 @@ __global__ __launch_bounds__(256) void k_mupdate(const T *c, double *R, double *
     e.finish(lds, K, m.kc, blockIdx.x);
 }
 
-// ---- residual + full-weighting restriction ------------------------------------
-// Thread: coarse point (X, Y) and V columns, marching over a chunk of coarse
-// planes.  For each fine plane it forms the fine residuals b - (6 c - nb) of
-// the 3 x 3 fine points under (X, Y) and combines them in the order of the
-// single-grid kernel: x weights per fine row, then y weights, then z weights.
-template <class TF, int V>
-__device__ __forceinline__ void mresid_point(const MGrid &g, const TF *c, const TF *b, int x, int y, int z, int k0,
-                                             acc_t<TF> (&r)[V]) {
-    typedef acc_t<TF> A;
-    const MArr<TF, A> cf{c}, bf{b};
-    A cc[V], xl[V], xr[V], ym[V], yp[V], zm[V], zp[V], bb[V];
-    cf.template get<V>(g, x, y, z, k0, cc);
-    cf.template get<V>(g, x - 1, y, z, k0, xl);
-    cf.template get<V>(g, x + 1, y, z, k0, xr);
-    cf.template get<V>(g, x, y - 1, z, k0, ym);
-    cf.template get<V>(g, x, y + 1, z, k0, yp);
-    cf.template get<V>(g, x, y, z - 1, k0, zm);
-    cf.template get<V>(g, x, y, z + 1, k0, zp);
-    bf.template get<V>(g, x, y, z, k0, bb);
+// ---- two-pass residual + restriction and prolongation -------------------------
+// Pass 1 stores the fine residual b - (6 c - nb) in the fine accumulator type
+// (the exact value the fused form keeps in registers); pass 2 applies the
+// full-weighting weights in the fused form's order.  The prolongation first
+// replaces c by round(c + 4 P e) in place (every point reads only its own c),
+// then a plain sweep runs on it.  Same results as the fused kernels, with
+// every pass a streaming one.
+template <class TF, class A> struct MResidOut {
+    const TF *__restrict__ b;
+    A *__restrict__ r;
+    template <int V>
+    __device__ __forceinline__ void emit(const MGrid &g, int x, int y, int z, int k0, const A (&c)[V],
+                                         const A (&nb)[V]) {
+        A bb[V], rv[V];
+        load_row<TF, V>(b + g.at(x, y, z) + k0, bb);
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-        A nb = xl[i] + xr[i];
-        nb += ym[i];
-        nb += yp[i];
-        nb += zm[i];
-        nb += zp[i];
-        r[i] = bb[i] - fmaT<A>(A(6), cc[i], -nb);
+        for (int i = 0; i < V; ++i) rv[i] = bb[i] - fmaT<A>(A(6), c[i], -nb[i]);
+        store_row<A, V>(r + g.at(x, y, z) + k0, rv);
     }
+};
+
+template <int V, class TF>
+__global__ __launch_bounds__(256) void k_mresid_store(const TF *b, const TF *c, acc_t<TF> *r, int P, int K, int zc,
+                                                      int nchunks) {
+    typedef acc_t<TF> A;
+    const MGrid g{P, K};
+    const MMap m = mmap<V>(P, K, zc, nchunks);
+    const MArr<TF, A> f{c};
+    MResidOut<TF, A> e{b, r};
+    mstencil_body<V>(f, e, g, m);
 }
 
-template <int V, class TF, class TC>
-__global__ __launch_bounds__(256) void k_mrestrict(const TF *b, const TF *c, TC *bc, int P, int K, int zcc,
-                                                   int nzch) {
-    typedef acc_t<TF> A;
+// Coarse point (X, Y) and V columns, marching over coarse planes; reads the
+// stored fine residuals of the 3 x 3 fine points under (X, Y) per fine plane.
+template <int V, class A, class TC>
+__global__ __launch_bounds__(256) void k_mfw(const A *r, TC *bc, int P, int K, int zcc, int nzch) {
     const int Pc = P >> 1, KC = K / V;
     const MGrid g{P, K}, gc{Pc, K};
     const long TXC = (long)(Pc - 1) * KC;
@@ -415,17 +412,18 @@ __global__ __launch_bounds__(256) void k_mrestrict(const TF *b, const TF *c, TC 
     const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
     A acc[V];
     for (int zf = zf0; zf <= zf1; ++zf) {
-        A q[V], rs[3][V];
+        A rs[3][V];
 #pragma unroll
         for (int oy = 0; oy < 3; ++oy) {
             A r0[V], r1[V], r2[V];
-            const int fy = 2 * Y - 1 + oy;
-            mresid_point<TF, V>(g, c, b, 2 * X - 1, fy, zf, k0, r0);
-            mresid_point<TF, V>(g, c, b, 2 * X, fy, zf, k0, r1);
-            mresid_point<TF, V>(g, c, b, 2 * X + 1, fy, zf, k0, r2);
+            const size_t base = g.at(2 * X - 1, 2 * Y - 1 + oy, zf) + k0;
+            load_row<A, V>(r + base, r0);
+            load_row<A, V>(r + base + K, r1);
+            load_row<A, V>(r + base + 2 * (size_t)K, r2);
 #pragma unroll
             for (int i = 0; i < V; ++i) rs[oy][i] = A(0.25) * (r0[i] + r2[i]) + A(0.5) * r1[i];
         }
+        A q[V];
 #pragma unroll
         for (int i = 0; i < V; ++i) q[i] = A(0.25) * (rs[0][i] + rs[2][i]) + A(0.5) * rs[1][i];
         if (zf == zf0) {
@@ -443,6 +441,23 @@ __global__ __launch_bounds__(256) void k_mrestrict(const TF *b, const TF *c, TC 
             }
             store_row<TC, V>(bc + gc.at(X, Y, (zf - 1) >> 1) + k0, out);
         }
+    }
+}
+
+// c = round_TF(c + 4 P e_c) in place at every interior point.
+template <int V, class TF, class TC>
+__global__ __launch_bounds__(256) void k_mprol_field(TF *c, const TC *ec, int P, int K, int zc, int nchunks) {
+    const MGrid g{P, K};
+    const MMap m = mmap<V>(P, K, zc, nchunks);
+    if (!m.active) return;
+    const MProl<TF, TC> f{c, ec, P / 2};
+    for (int z = m.z0; z < m.z1; ++z) {
+        acc_t<TF> v[V];
+        f.template get<V>(g, m.x, m.y, z, m.k0, v);
+        TF o[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = Store<TF>::from_acc(v[i]);
+        store_row<TF, V>(c + g.at(m.x, m.y, z) + m.k0, o);
     }
 }
 
@@ -562,9 +577,7 @@ hipError_t mstencil_run(const MArgs &a, hipStream_t st) {
 }
 
 template <int KIND, class T> hipError_t mstencil_tc(const MArgs &a, hipStream_t st) {
-    if (KIND != MK_PROLONG) return mstencil_run<KIND, T, double>(a, st);
-    MG_MT(a.pc, return mstencil_run<KIND, T, TT>(a, st));
-    return hipErrorInvalidValue;
+    return mstencil_run<KIND, T, double>(a, st);
 }
 
 template <int KIND> hipError_t mstencil_kind(const MArgs &a, hipStream_t st) {
@@ -572,20 +585,33 @@ template <int KIND> hipError_t mstencil_kind(const MArgs &a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
-template <class TF, class TC> hipError_t mrestrict_run(const MArgs &a, hipStream_t st) {
+template <class TF> hipError_t mresid_store_run(const MArgs &a, void *rbuf, hipStream_t st) {
     constexpr int V = std::is_same<TF, double>::value ? 4 : 8;
-    const int Pc = a.P / 2;
-    const int nz = cdiv(Pc - 1, a.zc);
-    const long threads = (long)(Pc - 1) * (a.K / V) * (Pc - 1) * nz;
-    hipLaunchKernelGGL((k_mrestrict<V, TF, TC>), dim3(cdiv(threads, 256)), dim3(256), 0, st,
-                       static_cast<const TF *>(a.b), static_cast<const TF *>(a.cin), static_cast<TC *>(a.cout), a.P,
-                       a.K, a.zc, nz);
+    const int nch = cdiv(a.P - 1, a.zc);
+    const int blocks = m_stencil_blocks(a.prec, a.P, a.K, a.zc);
+    hipLaunchKernelGGL((k_mresid_store<V, TF>), dim3(blocks), dim3(256), 0, st, static_cast<const TF *>(a.b),
+                       static_cast<const TF *>(a.cin), static_cast<acc_t<TF> *>(rbuf), a.P, a.K, a.zc, nch);
     return hipGetLastError();
 }
 
-template <class TF> hipError_t mrestrict_tc(const MArgs &a, hipStream_t st) {
-    MG_MT(a.pc, return mrestrict_run<TF, TT>(a, st));
-    return hipErrorInvalidValue;
+template <class TF, class TC> hipError_t mfw_run(const MArgs &a, const void *rbuf, int zcc, hipStream_t st) {
+    constexpr int V = std::is_same<TF, double>::value ? 4 : 8;
+    const int Pc = a.P / 2;
+    const int nz = cdiv(Pc - 1, zcc);
+    const long threads = (long)(Pc - 1) * (a.K / V) * (Pc - 1) * nz;
+    hipLaunchKernelGGL((k_mfw<V, acc_t<TF>, TC>), dim3(cdiv(threads, 256)), dim3(256), 0, st,
+                       static_cast<const acc_t<TF> *>(rbuf), static_cast<TC *>(a.cout), a.P, a.K, zcc, nz);
+    return hipGetLastError();
+}
+
+template <class TF, class TC> hipError_t mprol_field_run(const MArgs &a, hipStream_t st) {
+    constexpr int V = std::is_same<TF, double>::value ? 4 : 8;
+    const int nch = cdiv(a.P - 1, a.zc);
+    const int blocks = m_stencil_blocks(a.prec, a.P, a.K, a.zc);
+    hipLaunchKernelGGL((k_mprol_field<V, TF, TC>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<TF *>(const_cast<void *>(a.cin)), static_cast<const TC *>(a.ec), a.P, a.K, a.zc,
+                       nch);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -609,8 +635,6 @@ hipError_t launch_m_stage(int kind, const MArgs &a, hipStream_t st) {
     switch (kind) {
     case MS_SMOOTH2: return a.r ? mstencil_kind<MK_SMOOTH2_SCALED>(a, st) : mstencil_kind<MK_SMOOTH2>(a, st);
     case MS_SWEEP: return mstencil_kind<MK_SWEEP>(a, st);
-    case MS_PROLONG: return mstencil_kind<MK_PROLONG>(a, st);
-    case MS_RESTRICT: MG_MT(a.prec, return mrestrict_tc<TT>(a, st)); return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
@@ -652,6 +676,33 @@ hipError_t launch_m_finalize(const double *part, int nparts, int K, double *scal
                              hipStream_t st) {
     hipLaunchKernelGGL(k_mfinalize, dim3(K), dim3(256), 0, st, part, nparts, K, scal, mask, scaling);
     return hipGetLastError();
+}
+
+size_t m_resid_bytes(int prec, size_t elems) { return elems * (prec == P_F64 ? 8 : 4); }
+
+hipError_t launch_m_restrict2(const MArgs &a, void *rbuf, int zcc, hipStream_t st) {
+    if (!m_supported(a.prec, a.K) || a.P < 4 || a.zc < 1 || zcc < 1) return hipErrorInvalidValue;
+    hipError_t e = hipErrorInvalidValue;
+    MG_MT(a.prec, e = mresid_store_run<TT>(a, rbuf, st));
+    if (e != hipSuccess) return e;
+    switch (a.prec) {
+    case P_F64: MG_MT(a.pc, return (mfw_run<double, TT>(a, rbuf, zcc, st))); break;
+    case P_F32: MG_MT(a.pc, return (mfw_run<float, TT>(a, rbuf, zcc, st))); break;
+    case P_F16: MG_MT(a.pc, return (mfw_run<f16, TT>(a, rbuf, zcc, st))); break;
+    case P_BF16: MG_MT(a.pc, return (mfw_run<bf16, TT>(a, rbuf, zcc, st))); break;
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_m_prolong_field(const MArgs &a, hipStream_t st) {
+    if (!m_supported(a.prec, a.K) || a.P < 4 || a.zc < 1) return hipErrorInvalidValue;
+    switch (a.prec) {
+    case P_F64: MG_MT(a.pc, return (mprol_field_run<double, TT>(a, st))); break;
+    case P_F32: MG_MT(a.pc, return (mprol_field_run<float, TT>(a, st))); break;
+    case P_F16: MG_MT(a.pc, return (mprol_field_run<f16, TT>(a, st))); break;
+    case P_BF16: MG_MT(a.pc, return (mprol_field_run<bf16, TT>(a, st))); break;
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace mg

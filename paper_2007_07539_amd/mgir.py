@@ -236,9 +236,9 @@ class Solver:
         _check(self.lib.mg_set_shape(self._h, level, kind, arr, len(params)), "mg_set_shape")
 
     def get_shape(self, level: int, kind: int):
-        arr = (ctypes.c_int * 5)()
-        _check(self.lib.mg_get_shape(self._h, level, kind, arr, 5), "mg_get_shape")
-        return list(arr[: 4 if kind == SHAPE_RESTRICT else 1 if kind == SHAPE_TAIL else 5])
+        arr = (ctypes.c_int * 6)()
+        _check(self.lib.mg_get_shape(self._h, level, kind, arr, 6), "mg_get_shape")
+        return list(arr[: 4 if kind == SHAPE_RESTRICT else 1 if kind == SHAPE_TAIL else 6])
 
     def profile_step(self, stream=None, cap: int = 512):
         names = (ctypes.c_char_p * cap)()

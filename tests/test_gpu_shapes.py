@@ -22,7 +22,8 @@ def dev():
 
 STENCIL = [[V, zc, bs, xcd, ty] for V, zc, bs, xcd, ty in
            [(8, 1, 256, 0, 0), (4, 3, 64, 1, 0), (8, 7, 128, 1, 0), (8, 64, 256, 1, 0),
-            (8, 1, 256, 0, 1), (4, 5, 256, 1, 2), (8, 8, 256, 1, 6), (8, 3, 256, 0, 14), (4, 16, 256, 1, 3)]]
+            (8, 1, 256, 0, 1), (4, 5, 256, 1, 2), (8, 8, 256, 1, 6), (8, 3, 256, 0, 14), (4, 16, 256, 1, 3)]] + \
+    [[8, 2, 256, 1, 2, 2], [4, 7, 256, 0, 5, 2], [8, 16, 256, 1, 14, 2]]
 RESTRICT = [[4, 1, 1, 0], [8, 2, 3, 0], [8, 7, 5, 0], [4, 3, 64, 0], [8, 1, 1, 1], [4, 2, 7, 1], [8, 4, 16, 1],
             [8, 6, 3, 1], [8, 1, 2, 2], [4, 3, 5, 2], [8, 5, 9, 2], [8, 6, 1, 2], [8, 2, 7, 3], [4, 1, 3, 3],
             [8, 3, 16, 4], [8, 1, 1, 4]]
