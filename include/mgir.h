@@ -279,7 +279,7 @@ typedef enum {
     MG_SHAPE_SWEEP = 4,     /* the single sweeps only (five values); MG_SHAPE_STENCIL
                                sets SMOOTH, SWEEP and PROLONG together and reads SWEEP */
     MG_SHAPE_PROLONG = 5,   /* prolongation + correction + sweep only (five values) */
-    MG_SHAPE_TAIL = 6       /* 3-D, level argument 0: {on (0|1)}.  When on (the
+    MG_SHAPE_TAIL = 6,      /* 3-D, level argument 0: {on (0|1)}.  When on (the
                                default), the coarse end of the V-cycle -- from the
                                first level of pitch <= 16 (<= 8 for FP64 levels)
                                whose levels share one format, down to the base and
@@ -287,6 +287,14 @@ typedef enum {
                                levels in LDS; bitwise the same result.  The
                                workspace copies of those levels are then not
                                updated. */
+    MG_SHAPE_FUSE = 7       /* 3-D, level argument 0: {on (0|1)[, V (4), zc, xcd,
+                               ty]}.  When on (the default; the autotuner keeps it
+                               only where it is faster), the last post-smoothing
+                               sweep of the finest level and the refinement update
+                               run as one kernel inside ir_solve (same result).  Not
+                               used when the finest level is FP64 without residual
+                               scaling (its right-hand side is r itself) or nu2 < 2.
+                               Reading returns whether it is in use and its shape. */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);

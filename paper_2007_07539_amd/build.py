@@ -32,7 +32,8 @@ def _stale(obj, srcs):
     return any(os.path.getmtime(s) > t for s in srcs)
 
 
-SOURCES = (("mg_kernels.hip", True), ("mg_multi.hip", True), ("mg_tail.hip", True), ("mg_api.cpp", False))
+SOURCES = (("mg_kernels.hip", True), ("mg_multi.hip", True), ("mg_tail.hip", True), ("mg_sweep_update.hip", True),
+           ("mg_api.cpp", False))
 
 
 def build(force: bool = True) -> str:

@@ -80,6 +80,9 @@ struct mg_ctx {
     hipEvent_t ev_norm = nullptr;     // single grid: the norm readback of a step is done
     int outer_parts = 0;
     bool tail_on = true;
+    bool fuse_on = true;   // allow the fused last sweep + update on the finest level
+    bool fused = false;    // ... and it is in use
+    Shape fsh{4, 16, 256, 1, 4};
     // profiling
     bool prof = false;
     std::vector<ProfRec> recs;
@@ -285,10 +288,10 @@ hipError_t enq_prolong(mg_ctx *h, hipStream_t st, int l, const void *b) {
     return hipSuccess;
 }
 
-hipError_t enq_post(mg_ctx *h, hipStream_t st, int l, const void *b) {
+hipError_t enq_post(mg_ctx *h, hipStream_t st, int l, const void *b, bool skip_last = false) {
     LevelPlan &L = h->lv[l];
     const double N = (double)points(h->dim, L.n);
-    for (int k = 1; k < h->opt.nu2; ++k) {
+    for (int k = 1; k < h->opt.nu2 - (skip_last ? 1 : 0); ++k) {
         const int cur = h->cur[l];
         RUN(h, st, "sweep", l, N * 3 * sb(L.prec),
             launch_sweep(h->dim, L.prec, L.P, b, cbuf(h, l, cur), cbuf(h, l, cur ^ 1), h->opt.omega,
@@ -346,6 +349,8 @@ int tail_level(const mg_ctx *h) {
 
 hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
     const int nl = h->nl;
+    // inside a refinement step the last finest-level sweep runs fused with the update
+    const bool skip0 = mode == RHS_SCALED_R && h->fused;
     std::vector<const void *> rhs(nl);
     for (int l = 0; l < nl; ++l) rhs[l] = bbuf(h, l);
     if (mode == RHS_ALIAS_R) rhs[0] = Rbuf(h);
@@ -363,7 +368,7 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
         h->cur[lt] = 0;
         for (int l = lt - 1; l >= 0; --l) {
             if ((e = enq_prolong(h, st, l, rhs[l])) != hipSuccess) return e;
-            if ((e = enq_post(h, st, l, rhs[l])) != hipSuccess) return e;
+            if ((e = enq_post(h, st, l, rhs[l], l == 0 && skip0)) != hipSuccess) return e;
         }
         return hipSuccess;
     }
@@ -373,12 +378,26 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
     if ((e = enq_coarse(h, st, nl - 1)) != hipSuccess) return e;
     for (int l = nl - 2; l >= 0; --l) {
         if ((e = enq_prolong(h, st, l, rhs[l])) != hipSuccess) return e;
-        if ((e = enq_post(h, st, l, rhs[l])) != hipSuccess) return e;
+        if ((e = enq_post(h, st, l, rhs[l], l == 0 && skip0)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 bool finest_alias(mg_ctx *h) { return h->lv[0].prec == P_F64 && !h->opt.residual_scaling; }
+
+// The fused last sweep + update needs the scaled right-hand side stored apart
+// from r (with the FP64 map and no scaling, r itself is the right-hand side
+// and the update overwrites it) and at least two post-sweeps.
+bool fusion_possible(mg_ctx *h) {
+    return h->fuse_on && !h->batched && !h->nrhs && h->dim == 3 && h->nl >= 2 && h->opt.nu2 >= 2 &&
+           !finest_alias(h) && sweep_update_ok(h->lv[0].P, h->lv[0].prec, h->fsh);
+}
+
+void set_fused(mg_ctx *h, bool on) {
+    h->fused = on && fusion_possible(h);
+    const LevelPlan &L = h->lv[0];
+    h->outer_parts = h->fused ? sweep_update_blocks(L.P, h->fsh) : stencil_blocks(h->dim, L.P, L.osh);
+}
 
 // One refinement step of Algorithm 2 (scale and cast, V-cycle, update) plus
 // the norm readback.
@@ -387,14 +406,21 @@ hipError_t enq_cycle(mg_ctx *h, hipStream_t st) {
     return enq_vcycle(h, st, finest_alias(h) ? RHS_ALIAS_R : RHS_SCALED_R);
 }
 
-// The update part: u, r, norms, alpha, and the norm readback.
+// The update part: u, r, norms, alpha, and the norm readback (with the fused
+// form, also the last post-smoothing sweep of the finest level).
 hipError_t enq_update(mg_ctx *h, hipStream_t st) {
     LevelPlan &L = h->lv[0];
     const double hh = 1.0 / (double)(L.n + 1);
     const double N = (double)points(h->dim, L.n);
-    RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
-        launch_outer_update(h->dim, L.prec, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h), hh * hh, part(h),
-                            L.osh, st));
+    if (h->fused) {
+        RUN(h, st, "sweep_update", 0, N * (32 + 2 * sb(L.prec)),
+            launch_sweep_update(L.prec, L.P, cbuf(h, 0, h->cur[0]), bbuf(h, 0), Rbuf(h), Ubuf(h), scal(h), hh * hh,
+                                h->opt.omega, part(h), h->fsh, st));
+    } else {
+        RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
+            launch_outer_update(h->dim, L.prec, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h), hh * hh,
+                                part(h), L.osh, st));
+    }
     RUN(h, st, "norm_finalize", 0, 16.0 * h->outer_parts,
         launch_finalize(part(h), h->outer_parts, scal(h), h->opt.residual_scaling, st));
     return hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -527,6 +553,7 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
         // first pre-smoothing is timed in the form the refinement loop uses
         const bool scaled0 = l == 0 && !finest_alias(h);
         const void *b0 = (l == 0 && finest_alias(h)) ? (const void *)Rbuf(h) : bbuf(h, l);
+        float fam_best[3] = {0.f, 0.f, 0.f};
         for (int fam = 0; fam < 3; ++fam) {
             float best = 1e30f;
             Shape bs = L.shs[fam];
@@ -545,6 +572,7 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                 if (t < best) best = t, bs = s;
             }
             L.shs[fam] = bs;
+            fam_best[fam] = best;
         }
         // residual + restriction
         float best = 1e30f;
@@ -576,6 +604,23 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
             }
             L.osh = bo;
             h->outer_parts = stencil_blocks(D, L.P, bo);
+            // the fused last sweep + update against the two kernels it replaces
+            if (fusion_possible(h)) {
+                float bf = 1e30f;
+                Shape bsu = h->fsh;
+                for (int ty : {1, 2, 3, 4})
+                    for (int zc : {4, 8, 16, 32, 64}) {
+                        const Shape s{4, zc, 256, 1, ty};
+                        if (!sweep_update_ok(L.P, L.prec, s)) continue;
+                        const float t = time_ms(st, [&]() {
+                            return launch_sweep_update(L.prec, L.P, cbuf(h, 0, 0), bbuf(h, 0), Rbuf(h), Ubuf(h),
+                                                       scal(h), hh * hh, h->opt.omega, part(h), s, st);
+                        }, 3);
+                        if (t < bf) bf = t, bsu = s;
+                    }
+                h->fsh = bsu;
+                set_fused(h, bf < best + fam_best[SH_SWEEP]);
+            }
         }
     }
     HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
@@ -681,10 +726,13 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     off += fin;
     if (m > 1) {
         h->outer_parts = stencil_blocks(dim, h->lv[0].P, h->lv[0].osh);
-        // room for the partials of any legal shape: V = 4, zc = 1, 64-thread blocks
+        // room for the partials of any legal shape: V = 4, zc = 1, 64-thread
+        // blocks (more than the fused kernel's one row per block, zc = 1)
         const int P0 = h->lv[0].P;
         const long worst = ((long)(P0 / 4) * (dim == 3 ? P0 : 1) * (P0 - 1) + 63) / 64;
-        maxp = (int)std::max<long>(h->outer_parts, worst);
+        const long worst_fused = (long)(P0 - 1) * (P0 - 1);
+        maxp = (int)std::max<long>(std::max<long>(h->outer_parts, worst), worst_fused);
+        h->fsh = Shape{4, std::max(1, std::min(16, P0 - 1)), 256, 1, std::max(1, std::min(4, P0 - 1))};
     }
     maxp = std::max(maxp, flat_blocks(points(dim, n)));
     h->max_parts = maxp;
@@ -693,6 +741,7 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     h->off_scal = off;
     off += 256;
     h->ws_need = off;
+    if (m > 1) set_fused(h, true);
     *out = h;
     return MG_OK;
 }
@@ -1008,6 +1057,20 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
         drop_graph(h);
         return MG_OK;
     }
+    if (kind == MG_SHAPE_FUSE) {
+        if ((np != 1 && np != 5) || (p[0] != 0 && p[0] != 1))
+            return fail(MG_ERR_ARG, "the fused-update shape is {on (0|1)[, V, zc, xcd, ty]}");
+        if (np == 5) {
+            const Shape f{p[1], p[2], 256, p[3], p[4]};
+            if (h->nl < 2 || !sweep_update_ok(h->lv[0].P, h->lv[0].prec, f) || (f.xcd != 0 && f.xcd != 1))
+                return fail(MG_ERR_ARG, "fused-update shape {V=4, zc, xcd, ty} not valid here");
+            h->fsh = f;
+        }
+        h->fuse_on = p[0] != 0;
+        set_fused(h, h->fuse_on);
+        drop_graph(h);
+        return MG_OK;
+    }
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
     LevelPlan &L = h->lv[level];
     const int D = h->dim;
@@ -1029,7 +1092,7 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
         if (kind == MG_SHAPE_UPDATE) {
             if (stencil_blocks(D, L.P, s) > h->max_parts) return fail(MG_ERR_ARG, "too many blocks");
             L.osh = s;
-            h->outer_parts = stencil_blocks(D, L.P, s);
+            set_fused(h, h->fused);
         } else if (kind == MG_SHAPE_STENCIL) {
             L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = s;
         } else {
@@ -1055,6 +1118,12 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
     if (kind == MG_SHAPE_TAIL) {
         if (np < 1) return fail(MG_ERR_ARG, "too few values");
         p[0] = h->tail_on ? 1 : 0;
+        return MG_OK;
+    }
+    if (kind == MG_SHAPE_FUSE) {
+        if (np < 1) return fail(MG_ERR_ARG, "too few values");
+        p[0] = h->fused ? 1 : 0;
+        if (np >= 5) p[1] = h->fsh.V, p[2] = h->fsh.zc, p[3] = h->fsh.xcd, p[4] = h->fsh.ty;
         return MG_OK;
     }
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);

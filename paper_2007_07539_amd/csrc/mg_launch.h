@@ -81,6 +81,15 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, unsigned *sink,
                         hipStream_t st);
 
+// Last post-smoothing sweep of the finest 3-D level fused with the refinement
+// update (LDS-plane kernel; s.ty rows per block, s.V values per thread).
+size_t sweep_update_lds_bytes(int P, int ty, size_t sb);
+bool sweep_update_ok(int P, int prec, const Shape &s);
+int sweep_update_blocks(int P, const Shape &s);
+hipError_t launch_sweep_update(int prec, int P, const void *c, const void *b, double *R, double *U,
+                               const double *scal, double h2, double omega, double *part, const Shape &s,
+                               hipStream_t st);
+
 // Fused coarse end of a 3-D V-cycle in one workgroup (LDS-resident levels):
 // nlev grids of format prec with pitches P0 = 4 * 2^(nlev-1), ..., 4, then the
 // one-point base of format pb.  b: right-hand side of the first (padded, pitch

@@ -1,0 +1,243 @@
+// The last post-smoothing sweep of the finest level fused with the
+// refinement update of Algorithm 2 (3-D):
+//   c' = round_T(c + k (b - (6 c - nb(c))))          (damped Jacobi)
+//   u += alpha h^2 c',  r -= alpha (6 c' - nb(c'))     (FP64)
+// plus the (sum r^2, max |r|) partials of the block.  c' never goes to HBM:
+// the kernel reads c, b, r, u and writes r, u (2 s + 32 bytes per point
+// instead of 3 s for the sweep and s + 32 for the update).
+//
+// A block owns TY output rows of full width and a chunk of planes.  The
+// update at plane z needs c' on rows y0-1 .. y0+TY and planes z-1 .. z+1, so
+// the sweep runs one plane ahead on TY + 2 rows, which needs c on TY + 4
+// rows.  Thread row groups gi = 0 .. TY+3 hold fine rows y0-2+gi.  Per
+// iteration w the sweep produces c' of plane w+1 and the update consumes
+// plane w; c (plane w+1) and c' (plane w) sit in double-buffered LDS slots,
+// one barrier per iteration: every LDS slot written in an iteration is written
+// after its barrier and is not read again before the next one.  The arithmetic
+// is that of the separate sweep and update kernels, operation for operation.
+#include "mg_device.h"
+#include "mg_launch.h"
+
+namespace mg {
+namespace {
+
+template <int V, class T>
+__global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, const T *__restrict__ b,
+                                                       double *__restrict__ R, double *__restrict__ U,
+                                                       const double *__restrict__ scal, double h2, double omega,
+                                                       double *__restrict__ part, int P, int TY, int zc, int ytiles,
+                                                       int xcd) {
+    typedef acc_t<T> A;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[32];
+    const int G = TY + 4;
+    const size_t slot = (size_t)G * P;
+    T *cs = reinterpret_cast<T *>(smem_raw);  // [2][G][P]: c of the plane being swept
+    T *fs = cs + 2 * slot;                    // [2][G][P]: c' of the plane being updated
+    const Grid<3> g{P};
+    int blk = blockIdx.x;
+    if (xcd) {
+        const int nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    const int yt = blk % ytiles, zch = blk / ytiles;
+    const int y0 = 1 + yt * TY;
+    const int z0 = 1 + zch * zc;
+    const int z1 = min(z0 + zc, P);
+    const int TXR = P / V;
+    const int xc = threadIdx.x % TXR, gi = threadIdx.x / TXR;
+    const int y = y0 - 2 + gi;
+    const int x0 = xc * V;
+    const bool row_in = y >= 1 && y <= P - 1;
+    const bool sweep_row = gi >= 1 && gi <= TY + 2;
+    const bool out_row = gi >= 2 && gi <= TY + 1 && y <= P - 1;
+    const A k = (A)(omega / 6.0);
+    const double a = scal[0];
+    const double ah2 = a * h2;
+
+    auto fetch_c = [&](int z, RawRow<T, V> &r) {
+        if (!row_in || z <= 0 || z >= P) {
+            zero_row(r);
+            return;
+        }
+        fetch_row<T, V>(c + g.at(x0, y, z), r);
+    };
+    // c of the own row: planes s-1, s, s+1 around the plane s being swept
+    A pm[V], pc[V], pp[V];
+    // c' of the own row: planes w-1, w, w+1 around the plane w being updated
+    A fm[V], fc[V], fp[V];
+    RawRow<T, V> cnext;       // c, plane s + 2
+    RawRow<T, V> bcur, bnext; // b, planes s and s + 1
+    RawRow<double, V> rcur, ucur, rnext, unext;
+    double ss = 0.0, mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < V; ++i) fm[i] = fc[i] = A(0);
+
+    const int wb = z0 - 2;  // first iteration: sweep plane z0 - 1
+    {
+        RawRow<T, V> t;
+        fetch_c(wb, t);  // plane s - 1 of the first sweep
+        widen_row<T, V>(t, pm);
+        fetch_c(wb + 1, t);
+        widen_row<T, V>(t, pc);
+        T st[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) st[i] = Store<T>::from_acc(pc[i]);
+        store_row<T, V>(cs + (size_t)((wb + 1) & 1) * slot + (size_t)gi * P + x0, st);
+        fetch_c(wb + 2, t);
+        widen_row<T, V>(t, pp);
+        fetch_c(wb + 3, cnext);
+        const int s0 = wb + 1;
+        if (sweep_row && row_in && s0 >= 1 && s0 <= P - 1) fetch_row<T, V>(b + g.at(x0, y, s0), bnext);
+        if (out_row && z0 < z1) {
+            fetch_row<double, V>(R + g.at(x0, y, z0), rnext);
+            fetch_row<double, V>(U + g.at(x0, y, z0), unext);
+        }
+    }
+    for (int w = wb; w < z1; ++w) {
+        const int s = w + 1;  // plane swept in this iteration
+        bcur = bnext;
+        if (sweep_row && row_in && s + 1 >= 1 && s + 1 <= P - 1 && s + 1 <= z1)
+            fetch_row<T, V>(b + g.at(x0, y, s + 1), bnext);
+        if (w >= z0) {
+            rcur = rnext;
+            ucur = unext;
+            if (out_row && w + 1 < z1) {
+                fetch_row<double, V>(R + g.at(x0, y, w + 1), rnext);
+                fetch_row<double, V>(U + g.at(x0, y, w + 1), unext);
+            }
+        }
+        __syncthreads();
+        // sweep of plane s on rows gi = 1 .. TY+2
+        if (sweep_row) {
+            T o[V];
+            if (row_in && s >= 1 && s <= P - 1) {
+                const T *row = cs + (size_t)(s & 1) * slot + (size_t)gi * P;
+                A nb[V];
+                const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
+                const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+#pragma unroll
+                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? pc[i - 1] : xl) + (i < V - 1 ? pc[i + 1] : xr);
+                A ym[V], yp[V], bv[V];
+                load_row<T, V>(row - P + x0, ym);
+                load_row<T, V>(row + P + x0, yp);
+                widen_row<T, V>(bcur, bv);
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    nb[i] += ym[i];
+                    nb[i] += yp[i];
+                    nb[i] += pm[i];
+                    nb[i] += pp[i];
+                    const A lc = fmaT<A>(A(6), pc[i], -nb[i]);
+                    o[i] = Store<T>::from_acc(fmaT<A>(k, bv[i] - lc, pc[i]));
+                }
+                if (x0 == 0) o[0] = zero_of<T>();
+            } else {
+#pragma unroll
+                for (int i = 0; i < V; ++i) o[i] = zero_of<T>();
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i) fp[i] = (A)widen(o[i]);
+            store_row<T, V>(fs + (size_t)(s & 1) * slot + (size_t)gi * P + x0, o);
+        }
+        // update of plane w = s - 1 on rows gi = 2 .. TY+1, c' of plane w in LDS
+        if (w >= z0 && out_row) {
+            const T *row = fs + (size_t)(w & 1) * slot + (size_t)gi * P;
+            double cv[V], nb[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) cv[i] = (double)fc[i];
+            const double xl = x0 > 0 ? (double)widen(row[x0 - 1]) : 0.0;
+            const double xr = x0 + V < P ? (double)widen(row[x0 + V]) : 0.0;
+#pragma unroll
+            for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cv[i - 1] : xl) + (i < V - 1 ? cv[i + 1] : xr);
+            double ym[V], yp[V];
+            load_row<T, V>(row - P + x0, ym);
+            load_row<T, V>(row + P + x0, yp);
+            double r[V], u[V];
+            widen_row<double, V>(rcur, r);
+            widen_row<double, V>(ucur, u);
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                nb[i] += ym[i];
+                nb[i] += yp[i];
+                nb[i] += (double)fm[i];
+                nb[i] += (double)fp[i];
+                const double lc = fmaT<double>(6.0, cv[i], -nb[i]);
+                r[i] = fmaT<double>(-a, lc, r[i]);
+                u[i] = fmaT<double>(ah2, cv[i], u[i]);
+            }
+            if (x0 == 0) r[0] = 0.0, u[0] = 0.0;
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                ss += r[i] * r[i];
+                mx = nanmax(mx, fabs(r[i]));
+            }
+            const size_t at = g.at(x0, y, w);
+            store_row<double, V>(R + at, r);
+            store_row<double, V>(U + at, u);
+        }
+        // c of plane s + 1 for the next iteration's y neighbours (that slot was
+        // last read before this iteration's barrier)
+        {
+            T st[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) st[i] = Store<T>::from_acc(pp[i]);
+            store_row<T, V>(cs + (size_t)((s + 1) & 1) * slot + (size_t)gi * P + x0, st);
+        }
+        // advance the queues
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            pm[i] = pc[i];
+            pc[i] = pp[i];
+            fm[i] = fc[i];
+            fc[i] = fp[i];
+        }
+        widen_row<T, V>(cnext, pp);
+        fetch_c(s + 3, cnext);
+    }
+    block_reduce(ss, mx, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss;
+        part[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+template <class T>
+hipError_t sweep_update_t(int P, const void *c, const void *b, double *R, double *U, const double *scal, double h2,
+                          double omega, double *part, const Shape &s, hipStream_t st) {
+    const int ytiles = (P - 1 + s.ty - 1) / s.ty;
+    const int nch = (P - 1 + s.zc - 1) / s.zc;
+    const int threads = (P / s.V) * (s.ty + 4);
+    const size_t lds = sweep_update_lds_bytes(P, s.ty, sizeof(T));
+    hipLaunchKernelGGL((k_sweep_update<4, T>), dim3(ytiles * nch), dim3(threads), lds, st, static_cast<const T *>(c),
+                       static_cast<const T *>(b), R, U, scal, h2, omega, part, P, s.ty, s.zc, ytiles, s.xcd);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t sweep_update_lds_bytes(int P, int ty, size_t sb) { return 4 * (size_t)(ty + 4) * P * sb; }
+
+bool sweep_update_ok(int P, int prec, const Shape &s) {
+    // V = 4 only: at V = 8 the FP64 rows of the update spill registers
+    if (s.V != 4 || s.V > P || s.ty < 1 || s.ty > P - 1 || s.zc < 1 || s.zc > P - 1) return false;
+    if ((P / s.V) * (s.ty + 4) > 1024) return false;
+    return sweep_update_lds_bytes(P, s.ty, prec_bytes(prec)) <= 65536;
+}
+
+int sweep_update_blocks(int P, const Shape &s) { return ((P - 1 + s.ty - 1) / s.ty) * ((P - 1 + s.zc - 1) / s.zc); }
+
+hipError_t launch_sweep_update(int prec, int P, const void *c, const void *b, double *R, double *U,
+                               const double *scal, double h2, double omega, double *part, const Shape &s,
+                               hipStream_t st) {
+    if (!sweep_update_ok(P, prec, s)) return hipErrorInvalidValue;
+    switch (prec) {
+    case P_F64: return sweep_update_t<double>(P, c, b, R, U, scal, h2, omega, part, s, st);
+    case P_F32: return sweep_update_t<float>(P, c, b, R, U, scal, h2, omega, part, s, st);
+    case P_F16: return sweep_update_t<f16>(P, c, b, R, U, scal, h2, omega, part, s, st);
+    case P_BF16: return sweep_update_t<bf16>(P, c, b, R, U, scal, h2, omega, part, s, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mg

@@ -99,3 +99,37 @@ def test_fused_tail_bitwise(dev, name, n):
     assert torch.equal(c_on, c_off)
     assert r_on.iterations == r_off.iterations and torch.equal(u_on, u_off)
     assert r_on.history == r_off.history
+
+
+@pytest.mark.parametrize("name,n,scaling", [("f16", 63, True), ("bf16", 31, True), ("f32", 127, True),
+                                            ("hsd", 63, True), ("h_mg", 31, True), ("f64", 31, True),
+                                            ("f16", 7, True)])
+def test_fused_sweep_update_bitwise(dev, name, n, scaling):
+    """The last finest-level sweep fused into the refinement update changes no
+    result, for every launch shape of the fused kernel."""
+    print(f"fused update {name} n={n}", flush=True)
+    prec = W.precision_map(name, W.levels_for(n))
+    b64 = torch.from_numpy(W.uniform_rhs(3, n, seed=8)).to(dev)
+    s = mgir.Solver(3, n, prec, residual_scaling=scaling)
+    s.set_shape(0, mgir.SHAPE_FUSE, [0])
+    assert s.get_shape(0, mgir.SHAPE_FUSE)[0] == 0
+    u_ref, r_ref = s.solve(b64)
+    u_ref = u_ref.clone()
+    for shape in ([1, 4, 16, 1, 4], [1, 4, 3, 0, 1], [1, 4, 64, 1, 2], [1, 4, 5, 1, 3]):
+        try:
+            s.set_shape(0, mgir.SHAPE_FUSE, shape)
+        except mgir.MgError:
+            continue
+        assert s.get_shape(0, mgir.SHAPE_FUSE) == shape
+        u, r = s.solve(b64)
+        # the norms are summed over the kernel's blocks, so the history may
+        # differ in the last bits between shapes; the iterates may not
+        assert r.iterations == r_ref.iterations, shape
+        assert np.allclose(r.history, r_ref.history, rtol=1e-13, atol=0), shape
+        assert torch.equal(u, u_ref), shape
+
+
+def test_fused_update_not_used_without_scaling_in_fp64(dev):
+    n = 31
+    s = mgir.Solver(3, n, W.precision_map("f64", W.levels_for(n)), residual_scaling=False)
+    assert s.get_shape(0, mgir.SHAPE_FUSE)[0] == 0
