@@ -1202,10 +1202,20 @@ mg_status_t mg_profile_step(mg_handle h, void *stream, int cap, int *count, cons
 // ============================================================================
 namespace {
 
-Shape batched_shape(int P, int prec) {
+// Batched launch shapes: the LDS-plane kernels wherever the single-grid
+// default uses them (pitch >= 16), else the register-queue kernel with a
+// fixed block size of 256.
+// `copies`: instances of this size in the batch, which share each launch.
+// Longer z marches amortise a tile's pipeline prologue; the plane chunk is
+// chosen so that a launch still has about 4096 tiles.
+Shape batched_shape(int P, int prec, int copies) {
     Shape s = pick_shape(3, P, prec);
-    // the batched path uses the register-queue kernel (block size fixed at 256)
-    s.ty = 0;
+    if (s.ty > 0) {
+        const long ytiles = (P - 1 + s.ty - 1) / s.ty;
+        const long nch = std::max(1L, (4096 + ytiles * copies - 1) / (ytiles * copies));
+        s.zc = std::max(1, std::min(32, (int)((P - 1 + nch - 1) / nch)));
+        return s;
+    }
     s.V = (P >= 8 && prec != P_F64) ? 8 : 4;
     s.bs = 256;
     const long per_chunk = (long)(P / s.V) * P;
@@ -1214,7 +1224,16 @@ Shape batched_shape(int P, int prec) {
     return s;
 }
 
-RShape batched_rshape(int P, int pf) {
+RShape batched_rshape(int P, int pf, int copies) {
+    if (P >= 16) {
+        RShape r = pick_rshape(3, P, pf);
+        if (r.pipe >= 1) {
+            const long ytiles = (P / 2 - 1 + r.tyc - 1) / r.tyc;
+            const long nzc = std::max(1L, (4096 + ytiles * copies - 1) / (ytiles * copies));
+            r.zcc = std::max(1, std::min(16, (int)((P / 2 - 1 + nzc - 1) / nzc)));
+            return r;
+        }
+    }
     RShape r;
     r.V = (P >= 8 && pf != P_F64) ? 8 : 4;
     r.pipe = 0;
@@ -1227,6 +1246,12 @@ RShape batched_rshape(int P, int pf) {
     const int nzc = std::max(1, (256 + ytiles - 1) / ytiles);
     r.zcc = std::max(1, (Pc - 1 + nzc - 1) / nzc);
     return r;
+}
+
+// Work items of one instance's stencil launch with shape s.
+int batched_stencil_blocks(int P, const Shape &s) {
+    if (s.ty > 0) return ((P - 1 + s.ty - 1) / s.ty) * ((P - 1 + s.zc - 1) / s.zc);
+    return stencil_blocks(3, P, s);
 }
 
 int bprec_of(const mg_ctx *h, int i, int l) {
@@ -1251,49 +1276,99 @@ void build_batched_plan(mg_ctx *h, char *base) {
     auto Up = [&](int i) { return reinterpret_cast<double *>(at(h->inst[i].off_U)); };
     auto Sp = [&](int i) { return reinterpret_cast<double *>(at(h->off_scal_all + 32 * (size_t)i)); };
     auto rhs = [&](int i, int l) -> const void * { return (l == 0 && alias) ? (const void *)Rp(i) : B(i, l); };
-    // group descriptors by (V, pc) into launches
+    // Launches group descriptors of one kernel form: register-queue stencil
+    // (what 0), register restriction (1), LDS-plane stencil (4, one pitch
+    // per launch) and pipelined restriction (5, one pitch per launch).
     struct Pend {
         BDesc d;
-        int V, pc, nblk;
+        int what, V, pc, nblk, threads;
+        size_t lds;
+        bool xsh;
     };
-    auto flush = [&](int what, int kind, int pf, const char *name, int level, std::vector<Pend> &pend,
+    auto flush = [&](int kind, int pf, const char *name, int level, std::vector<Pend> &pend,
                      double bytes_per_point) {
-        std::vector<std::pair<int, int>> keys;
+        // the LDS forms need one block size per launch: same pitch and rows
+        struct Key {
+            int what, V, pc, P, rows;
+            bool xsh;
+            bool operator==(const Key &o) const {
+                return what == o.what && V == o.V && pc == o.pc && P == o.P && rows == o.rows && xsh == o.xsh;
+            }
+        };
+        auto key_of = [](const Pend &p) {
+            if (p.what == 4) return Key{p.what, p.V, p.pc, p.d.P, p.d.ty, false};
+            if (p.what == 5) return Key{p.what, p.V, p.pc, p.d.P, p.d.tyc, p.xsh};
+            return Key{p.what, p.V, p.pc, 0, 0, false};
+        };
+        std::vector<Key> keys;
         for (auto &p : pend)
-            if (std::find(keys.begin(), keys.end(), std::make_pair(p.V, p.pc)) == keys.end())
-                keys.push_back({p.V, p.pc});
+            if (std::find(keys.begin(), keys.end(), key_of(p)) == keys.end()) keys.push_back(key_of(p));
         for (auto &k : keys) {
             mg_ctx::BLaunch L{};
-            L.what = what, L.kind = kind, L.V = k.first, L.pf = pf, L.pc = k.second;
+            L.what = k.what, L.kind = k.what == 5 ? (k.xsh ? 1 : 0) : kind, L.V = k.V, L.pf = pf, L.pc = k.pc;
             L.off_desc = descs.size(), L.off_items = items.size();
             L.name = name, L.level = level;
             int maxthreads = 0;
             size_t maxlds = 0;
             double pts = 0;
             for (auto &p : pend) {
-                if (p.V != k.first || p.pc != k.second) continue;
+                if (!(key_of(p) == k)) continue;
                 const int di = (int)(descs.size() - L.off_desc);
                 descs.push_back(p.d);
                 for (int b = 0; b < p.nblk; ++b) items.push_back(BItem{di, b});
                 pts += (double)(p.d.P - 1) * (p.d.P - 1) * (p.d.P - 1);
-                if (what == 1) {
-                    maxthreads = std::max(maxthreads, (2 * p.d.tyc + 1) * (p.d.P / p.V));
-                    maxlds = std::max(maxlds, 2 * (size_t)(2 * p.d.tyc + 1) * p.d.P * (pf == P_F64 ? 8 : 4));
-                }
+                maxthreads = std::max(maxthreads, p.threads);
+                maxlds = std::max(maxlds, p.lds);
             }
             L.ndesc = (int)(descs.size() - L.off_desc);
             L.nitems = (int)(items.size() - L.off_items);
-            L.grid = std::max(1, std::min(L.nitems, what == 1 ? 1024 : 4096));
-            L.threads = what == 1 ? ((maxthreads + 63) / 64) * 64 : 256;
+            L.grid = std::max(1, std::min(L.nitems, k.what == 0 ? 4096 : 2048));
+            // the register restriction tolerates extra threads; the LDS forms
+            // take exactly their row groups
+            L.threads = k.what == 0 ? 256 : k.what == 1 ? ((maxthreads + 63) / 64) * 64 : maxthreads;
             L.lds = maxlds;
             L.bytes = pts * bytes_per_point;
             h->bl.push_back(L);
         }
         pend.clear();
     };
+    // a stencil-stage descriptor with the form that shape sh selects
+    auto stencil_pend = [&](BDesc x, const Shape &sh, int P, int prec, int pc) {
+        x.P = P, x.zc = sh.zc, x.nchunks = (P - 1 + sh.zc - 1) / sh.zc;
+        Pend p{};
+        p.V = sh.V, p.pc = pc;
+        if (sh.ty > 0) {
+            x.ty = sh.ty, x.ytiles = (P - 1 + sh.ty - 1) / sh.ty;
+            p.what = 4;
+            p.threads = (sh.ty + 2) * (P / sh.V);
+            p.lds = march_lds_bytes(P, sh.ty, prec_bytes(prec));
+        } else {
+            p.what = 0;
+            p.threads = 256;
+        }
+        p.nblk = batched_stencil_blocks(P, sh);
+        p.d = x;
+        return p;
+    };
+    auto restrict_pend = [&](BDesc x, const RShape &r, int P, int pf, int pc) {
+        x.P = P, x.tyc = r.tyc, x.zcc = r.zcc, x.ytiles = (P / 2 - 1 + r.tyc - 1) / r.tyc;
+        Pend p{};
+        p.V = r.V, p.pc = pc, p.xsh = r.pipe >= 2;
+        p.nblk = restrict_blocks(3, P, r);
+        if (r.pipe >= 1) {
+            const RShape rr{r.V, r.tyc, r.zcc, p.xsh ? 3 : 1};
+            p.what = 5;
+            p.threads = (2 * r.tyc + 3) * (P / r.V);
+            p.lds = restrict_lds_bytes(3, P, pf, rr);
+        } else {
+            p.what = 1;
+            p.threads = (2 * r.tyc + 1) * (P / r.V);
+            p.lds = 2 * (size_t)(2 * r.tyc + 1) * P * (pf == P_F64 ? 8 : 4);
+        }
+        p.d = x;
+        return p;
+    };
     std::vector<Pend> pend;
-    const double omega = h->opt.omega;
-    (void)omega;
     for (int d = 0; d + 1 < h->Lmax; ++d) {
         const int pf = h->bprec[d];
         const double s = (double)prec_bytes(pf);
@@ -1306,35 +1381,32 @@ void build_batched_plan(mg_ctx *h, char *base) {
             x.cout = C(i, d, 0);
             x.bout = B(i, d);
             x.scal = Sp(i);
-            x.P = L.P, x.zc = L.shs[SH_SMOOTH].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
-            pend.push_back({x, L.shs[SH_SMOOTH].V, P_F64, stencil_blocks(3, L.P, L.shs[SH_SMOOTH])});
+            x.inst = i;
+            pend.push_back(stencil_pend(x, L.shs[SH_SMOOTH], L.P, pf, P_F64));
             cur[i][d] = 0;
         }
         const bool scaled = d == 0 && !alias;
-        flush(0, scaled ? BK_SMOOTH2_SCALED : BK_SMOOTH2, pf, scaled ? "smooth2_scaled" : "smooth2", d, pend,
+        flush(scaled ? BK_SMOOTH2_SCALED : BK_SMOOTH2, pf, scaled ? "smooth2_scaled" : "smooth2", d, pend,
               scaled ? 8 + 2 * s : 2 * s);
         for (int k = 2; k < h->opt.nu1; ++k) {
             for (int i = 0; i < ni; ++i) {
                 if (d > h->inst[i].nl - 2) continue;
                 const LevelPlan &L = h->inst[i].lv[d];
                 BDesc x{};
-                x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = C(i, d, cur[i][d] ^ 1);
-                x.P = L.P, x.zc = L.shs[SH_SWEEP].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
-                pend.push_back({x, L.shs[SH_SWEEP].V, P_F64, stencil_blocks(3, L.P, L.shs[SH_SWEEP])});
+                x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = C(i, d, cur[i][d] ^ 1), x.inst = i;
+                pend.push_back(stencil_pend(x, L.shs[SH_SWEEP], L.P, pf, P_F64));
                 cur[i][d] ^= 1;
             }
-            flush(0, BK_SWEEP, pf, "sweep", d, pend, 3 * s);
+            flush(BK_SWEEP, pf, "sweep", d, pend, 3 * s);
         }
         for (int i = 0; i < ni; ++i) {
             if (d > h->inst[i].nl - 2) continue;
             const LevelPlan &L = h->inst[i].lv[d];
             BDesc x{};
-            x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = B(i, d + 1);
-            x.P = L.P, x.tyc = L.rsh.tyc, x.zcc = L.rsh.zcc;
-            x.ytiles = (L.P / 2 - 1 + x.tyc - 1) / x.tyc, x.inst = i;
-            pend.push_back({x, L.rsh.V, bprec_of(h, i, d + 1), restrict_blocks(3, L.P, L.rsh)});
+            x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = B(i, d + 1), x.inst = i;
+            pend.push_back(restrict_pend(x, L.rsh, L.P, pf, bprec_of(h, i, d + 1)));
         }
-        flush(1, 0, pf, "resid_restrict", d, pend, 2 * s);
+        flush(0, pf, "resid_restrict", d, pend, 2 * s);
     }
     for (int i = 0; i < ni; ++i) {
         const int lb = h->inst[i].nl - 1;
@@ -1357,23 +1429,21 @@ void build_batched_plan(mg_ctx *h, char *base) {
             const LevelPlan &L = h->inst[i].lv[d];
             BDesc x{};
             x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.ec = C(i, d + 1, cur[i][d + 1]);
-            x.cout = C(i, d, cur[i][d] ^ 1);
-            x.P = L.P, x.zc = L.shs[SH_PROLONG].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
-            pend.push_back({x, L.shs[SH_PROLONG].V, bprec_of(h, i, d + 1), stencil_blocks(3, L.P, L.shs[SH_PROLONG])});
+            x.cout = C(i, d, cur[i][d] ^ 1), x.inst = i;
+            pend.push_back(stencil_pend(x, L.shs[SH_PROLONG], L.P, pf, bprec_of(h, i, d + 1)));
             cur[i][d] ^= 1;
         }
-        flush(0, BK_PROLONG, pf, "prolong_sweep", d, pend, 3 * s);
+        flush(BK_PROLONG, pf, "prolong_sweep", d, pend, 3 * s);
         for (int k = 1; k < h->opt.nu2; ++k) {
             for (int i = 0; i < ni; ++i) {
                 if (d > h->inst[i].nl - 2) continue;
                 const LevelPlan &L = h->inst[i].lv[d];
                 BDesc x{};
-                x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = C(i, d, cur[i][d] ^ 1);
-                x.P = L.P, x.zc = L.shs[SH_SWEEP].zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc, x.inst = i;
-                pend.push_back({x, L.shs[SH_SWEEP].V, P_F64, stencil_blocks(3, L.P, L.shs[SH_SWEEP])});
+                x.b = rhs(i, d), x.cin = C(i, d, cur[i][d]), x.cout = C(i, d, cur[i][d] ^ 1), x.inst = i;
+                pend.push_back(stencil_pend(x, L.shs[SH_SWEEP], L.P, pf, P_F64));
                 cur[i][d] ^= 1;
             }
-            flush(0, BK_SWEEP, pf, "sweep", d, pend, 3 * s);
+            flush(BK_SWEEP, pf, "sweep", d, pend, 3 * s);
         }
     }
     double *part_base = reinterpret_cast<double *>(at(h->off_part));
@@ -1382,13 +1452,12 @@ void build_batched_plan(mg_ctx *h, char *base) {
         const double hh = 1.0 / (double)(L.n + 1);
         BDesc x{};
         x.cin = C(i, 0, cur[i][0]), x.R = Rp(i), x.U = Up(i), x.scal = Sp(i), x.h2 = hh * hh;
-        x.P = L.P, x.zc = h->inst[i].osh.zc, x.nchunks = (L.P - 1 + x.zc - 1) / x.zc;
         x.part_off = h->inst[i].part_off, x.inst = i;
-        pend.push_back({x, h->inst[i].osh.V, P_F64, stencil_blocks(3, L.P, h->inst[i].osh)});
+        pend.push_back(stencil_pend(x, h->inst[i].osh, L.P, h->bprec[0], P_F64));
         fins.push_back(
-            BFin{part_base + 2 * (size_t)h->inst[i].part_off, stencil_blocks(3, L.P, h->inst[i].osh), Sp(i)});
+            BFin{part_base + 2 * (size_t)h->inst[i].part_off, batched_stencil_blocks(L.P, h->inst[i].osh), Sp(i)});
     }
-    flush(0, BK_OUTER, h->bprec[0], "ir_update", 0, pend, 32 + (double)prec_bytes(h->bprec[0]));
+    flush(BK_OUTER, h->bprec[0], "ir_update", 0, pend, 32 + (double)prec_bytes(h->bprec[0]));
     {
         mg_ctx::BLaunch L{};
         L.what = 3, L.name = "norm_finalize", L.level = 0;
@@ -1425,6 +1494,14 @@ hipError_t enq_batched_step(mg_ctx *h, hipStream_t st) {
             RUN(h, st, L.name, L.level, L.bytes,
                 launch_batched_stencil(L.kind, L.V, L.pf, L.pc, d, it, L.nitems, act, h->opt.omega, part_base,
                                        L.grid, st));
+        } else if (L.what == 4) {
+            RUN(h, st, L.name, L.level, L.bytes,
+                launch_batched_march(L.kind, L.V, L.pf, L.pc, d, it, L.nitems, act, h->opt.omega, part_base, L.grid,
+                                     L.threads, L.lds, st));
+        } else if (L.what == 5) {
+            RUN(h, st, L.name, L.level, L.bytes,
+                launch_batched_restrict2(L.V, L.pf, L.pc, L.kind == 1, d, it, L.nitems, act, L.grid, L.threads, L.lds,
+                                         st));
         } else if (L.what == 1) {
             RUN(h, st, L.name, L.level, L.bytes,
                 launch_batched_restrict(L.V, L.pf, L.pc, d, it, L.nitems, act, L.grid, L.threads, L.lds, st));
@@ -1481,6 +1558,7 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
     for (int i = 0; i < ninst; ++i) {
         auto &I = h->inst[i];
         I.n = n[i];
+        const int copies = (int)std::count(n, n + ninst, n[i]);
         int m = 0;
         while ((1 << m) < n[i] + 1) ++m;
         I.nl = m;
@@ -1496,16 +1574,15 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
             L.off_c[0] = off, off += bytes;
             L.off_c[1] = off, off += bytes;
             if (nn > 1) {
-                L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = batched_shape(L.P, L.prec);
-                L.rsh = batched_rshape(L.P, L.prec);
+                L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = batched_shape(L.P, L.prec, copies);
+                L.rsh = batched_rshape(L.P, L.prec, copies);
             }
             nn = (nn - 1) / 2;
         }
         const size_t fin = align_up(I.lv[0].elems * sizeof(double), 256);
         I.off_R = off, off += fin;
         I.off_U = off, off += fin;
-        I.osh = batched_shape(I.lv[0].P, P_F64);
-        I.osh.V = 4;
+        I.osh = batched_shape(I.lv[0].P, P_F64, copies);  // V = 4: FP64 rows
         I.part_off = parts;
         I.parts = std::max(stencil_blocks(3, I.lv[0].P, I.osh), flat_blocks(points(3, n[i])));
         parts += I.parts;

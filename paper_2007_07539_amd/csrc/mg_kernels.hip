@@ -740,7 +740,7 @@ template <class T, int V, bool RHS_AUX, bool WRITE_B> struct PSweep {
     T *__restrict__ bout;
     A k;
     __device__ __forceinline__ void init(State &) const {}
-    __device__ __forceinline__ void finish(State &, double *) const {}
+    __device__ __forceinline__ void finish(State &, double *, long) const {}
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
         if constexpr (!RHS_AUX) fetch_row<T, V>(b + g.at(x0, y, z), r);
     }
@@ -811,11 +811,11 @@ template <int V> struct POuter {
         store_row<double, V>(R + at, r);
         store_row<double, V>(U + at, u);
     }
-    __device__ __forceinline__ void finish(State &s, double *lds) const {
+    __device__ __forceinline__ void finish(State &s, double *lds, long pidx) const {
         block_reduce(s.ss, s.mx, lds);
         if (threadIdx.x == 0) {
-            part[2 * blockIdx.x] = s.ss;
-            part[2 * blockIdx.x + 1] = s.mx;
+            part[2 * pidx] = s.ss;
+            part[2 * pidx + 1] = s.mx;
         }
     }
 };
@@ -829,21 +829,17 @@ template <class F> struct StageOf<F, typename std::enable_if<F::kStaged>::type> 
 
 // DP: field and emit rows of DP planes ahead are in flight while a plane is
 // computed (the loads for plane z + 1 + DP are issued in iteration z).
-template <int V, class F, class E, int DP = 1>
-__global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int zc, int ytiles, int xcd) {
+// One tile (blk = y tile + ytiles * z chunk) of the LDS-plane march; pidx is
+// the index of the block's norm partial.  Called by every thread of the block.
+template <int V, class F, class E, int DP>
+__device__ __forceinline__ void march_body(const F &f_in, const E &e, int P, int TY, int zc, int ytiles, int blk,
+                                           long pidx, unsigned char *smem_raw, double *red) {
     typedef typename F::acc A;
     typedef typename F::lds_t LT;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     LT *lds = reinterpret_cast<LT *>(smem_raw);
-    __shared__ double red[32];
     const Grid<3> g{P};
     const int TXR = P / V;
     const int G = TY + 2;
-    int blk = blockIdx.x;
-    if (xcd) {
-        const int nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
-    }
     const int yt = blk % ytiles, zch = blk / ytiles;
     const int y0 = 1 + yt * TY;
     const int z0 = 1 + zch * zc;
@@ -935,7 +931,21 @@ __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int 
             ac[i] = ap[i];
         }
     }
-    e.finish(st, red);
+    e.finish(st, red, pidx);
+}
+
+template <int V, class F, class E, int DP = 1>
+__global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int zc, int ytiles, int xcd) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[32];
+    int blk = blockIdx.x;
+    if (xcd) {
+        // blocks are dealt round-robin to the 8 XCDs: give each XCD a
+        // contiguous range of tiles so neighbouring rows share an L2
+        const int nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    march_body<V, F, E, DP>(f_in, e, P, TY, zc, ytiles, blk, (long)blockIdx.x, smem_raw, red);
 }
 
 // ===========================================================================
@@ -1094,13 +1104,12 @@ __global__ __launch_bounds__(1024) void k_restrict(const TF *__restrict__ b, con
 // per row as one vector.
 // DP: planes of c and b in flight ahead of the plane being processed (the
 // loads for plane zf + 1 + DP are issued while plane zf is computed).
-template <int V, class TF, class TC, bool XSH, int DP = 1>
-__global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, const TF *__restrict__ c,
-                                                    TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles,
-                                                    int xcd) {
+template <int V, class TF, class TC, bool XSH, int DP>
+__device__ __forceinline__ void restrict2_body(const TF *__restrict__ b, const TF *__restrict__ c,
+                                               TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles, int blk,
+                                               unsigned char *smem_raw) {
     typedef acc_t<TF> A;
     constexpr int VC = V / 2;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = 2 * tyc + 3, R = 2 * tyc + 1;
     const int RW = XSH ? P / 2 : P;                                             // r row width
     TF *cs = reinterpret_cast<TF *>(smem_raw);                                  // [2][G][P]
@@ -1109,11 +1118,6 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
     const int TXR = P / V;
     const Grid<3> g{P};
     const Grid<3> gc{Pc};
-    int blk = blockIdx.x;
-    if (xcd) {
-        const int nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
-    }
     const int ytile = blk % ytiles, zch = blk / ytiles;
     const int Y0 = 1 + ytile * tyc;
     const int Z0 = 1 + zch * zcc;
@@ -1274,6 +1278,19 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
     }
     __syncthreads();
     if (coarse) coarse_step(zf1, (zf1 - zf0) & 1);
+}
+
+template <int V, class TF, class TC, bool XSH, int DP = 1>
+__global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, const TF *__restrict__ c,
+                                                    TC *__restrict__ bc, int P, int tyc, int zcc, int ytiles,
+                                                    int xcd) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int blk = blockIdx.x;
+    if (xcd) {
+        const int nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    restrict2_body<V, TF, TC, XSH, DP>(b, c, bc, P, tyc, zcc, ytiles, blk, smem_raw);
 }
 
 // Base level: the single interior point of an n = 1 grid (P = 2) at (1,1[,1]).
@@ -1927,6 +1944,69 @@ __global__ __launch_bounds__(256) void k_batched_finalize(const BFin *__restrict
     }
 }
 
+// LDS-plane forms: the same per-tile bodies as k_march and k_restrict2.
+template <int V, int KIND, class T, class TC>
+__global__ __launch_bounds__(1024) void k_batched_march(const BDesc *__restrict__ descs,
+                                                        const BItem *__restrict__ items, int nitems,
+                                                        const int *__restrict__ active, double omega,
+                                                        double *__restrict__ part) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[32];
+    typedef acc_t<T> A;
+    const A k = (A)(omega / 6.0);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem item = items[it];
+        const BDesc &d = descs[item.d];
+        if (!active[d.inst]) continue;
+        if constexpr (KIND == BK_SMOOTH2) {
+            typedef PJac0Arr<T, V> F;
+            typedef PSweep<T, V, true, false> E;
+            march_body<V, F, E, 1>(F{static_cast<const T *>(d.b), k}, E{nullptr, static_cast<T *>(d.cout), nullptr, k},
+                                   d.P, d.ty, d.zc, d.ytiles, item.blk, 0, smem_raw, red);
+        } else if constexpr (KIND == BK_SMOOTH2_SCALED) {
+            typedef PJac0Scaled<T, V> F;
+            typedef PSweep<T, V, true, true> E;
+            march_body<V, F, E, 1>(F{static_cast<const double *>(d.b), d.scal, k},
+                                   E{nullptr, static_cast<T *>(d.cout), static_cast<T *>(d.bout), k}, d.P, d.ty,
+                                   d.zc, d.ytiles, item.blk, 0, smem_raw, red);
+        } else if constexpr (KIND == BK_SWEEP) {
+            typedef PArr<T, A, V> F;
+            typedef PSweep<T, V, false, false> E;
+            march_body<V, F, E, 1>(F{static_cast<const T *>(d.cin)},
+                                   E{static_cast<const T *>(d.b), static_cast<T *>(d.cout), nullptr, k}, d.P, d.ty,
+                                   d.zc, d.ytiles, item.blk, 0, smem_raw, red);
+        } else if constexpr (KIND == BK_PROLONG) {
+            typedef PProl<T, TC, V> F;
+            typedef PSweep<T, V, false, false> E;
+            march_body<V, F, E, 1>(F{static_cast<const T *>(d.cin), static_cast<const TC *>(d.ec), d.P / 2},
+                                   E{static_cast<const T *>(d.b), static_cast<T *>(d.cout), nullptr, k}, d.P, d.ty,
+                                   d.zc, d.ytiles, item.blk, 0, smem_raw, red);
+        } else {
+            typedef PArr<T, double, V> F;
+            typedef POuter<V> E;
+            march_body<V, F, E, 1>(F{static_cast<const T *>(d.cin)}, E{d.R, d.U, d.scal, d.h2, part}, d.P, d.ty, d.zc,
+                                   d.ytiles, item.blk, (long)d.part_off + item.blk, smem_raw, red);
+        }
+        __syncthreads();  // the next item reuses the LDS slots
+    }
+}
+
+template <int V, class TF, class TC, bool XSH>
+__global__ __launch_bounds__(1024) void k_batched_restrict2(const BDesc *__restrict__ descs,
+                                                            const BItem *__restrict__ items, int nitems,
+                                                            const int *__restrict__ active) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem item = items[it];
+        const BDesc &d = descs[item.d];
+        if (!active[d.inst]) continue;
+        restrict2_body<V, TF, TC, XSH, XSH ? 2 : 1>(static_cast<const TF *>(d.b), static_cast<const TF *>(d.cin),
+                                                    static_cast<TC *>(d.cout), d.P, d.tyc, d.zcc, d.ytiles, item.blk,
+                                                    smem_raw);
+        __syncthreads();
+    }
+}
+
 #define MG_BT(prec, ...)                                   \
     switch (prec) {                                        \
     case P_F64: { typedef double TB; __VA_ARGS__; break; } \
@@ -2021,6 +2101,101 @@ hipError_t launch_batched_coarse(int prec, const BDesc *d, int n, const int *act
         hipLaunchKernelGGL((k_batched_coarse<TB>), dim3(grid), dim3(64), 0, st, d, n, active);
         return hipGetLastError();
     });
+    return hipErrorInvalidValue;
+}
+
+template <int KIND, class T, int V>
+static hipError_t bmarch_tc(int pc, const BDesc *d, const BItem *it, int n, const int *act, double omega,
+                            double *part, int grid, int threads, size_t lds, hipStream_t st) {
+    if constexpr (KIND == BK_PROLONG) {
+        MG_BT(pc, hipLaunchKernelGGL((k_batched_march<V, KIND, T, TB>), dim3(grid), dim3(threads), lds, st, d, it, n,
+                                     act, omega, part));
+    } else {
+        hipLaunchKernelGGL((k_batched_march<V, KIND, T, double>), dim3(grid), dim3(threads), lds, st, d, it, n, act,
+                           omega, part);
+    }
+    return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t bmarch_kind(int V, int pf, int pc, const BDesc *d, const BItem *it, int n, const int *act,
+                              double omega, double *part, int grid, int threads, size_t lds, hipStream_t st) {
+    // FP64 rows and the FP64 update use V = 4 (V = 8 spills registers)
+    if (V != 4 && V != 8) return hipErrorInvalidValue;
+    if constexpr (KIND == BK_OUTER) {
+        if (V != 4) return hipErrorInvalidValue;
+        MG_BT(pf, return (bmarch_tc<KIND, TB, 4>(pc, d, it, n, act, omega, part, grid, threads, lds, st)));
+    } else {
+        if (pf == P_F64) {
+            if (V != 4) return hipErrorInvalidValue;
+            return bmarch_tc<KIND, double, 4>(pc, d, it, n, act, omega, part, grid, threads, lds, st);
+        }
+        switch (pf) {
+        case P_F32:
+            return V == 8 ? bmarch_tc<KIND, float, 8>(pc, d, it, n, act, omega, part, grid, threads, lds, st)
+                          : bmarch_tc<KIND, float, 4>(pc, d, it, n, act, omega, part, grid, threads, lds, st);
+        case P_F16:
+            return V == 8 ? bmarch_tc<KIND, f16, 8>(pc, d, it, n, act, omega, part, grid, threads, lds, st)
+                          : bmarch_tc<KIND, f16, 4>(pc, d, it, n, act, omega, part, grid, threads, lds, st);
+        case P_BF16:
+            return V == 8 ? bmarch_tc<KIND, bf16, 8>(pc, d, it, n, act, omega, part, grid, threads, lds, st)
+                          : bmarch_tc<KIND, bf16, 4>(pc, d, it, n, act, omega, part, grid, threads, lds, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_march(int kind, int V, int pf, int pc, const BDesc *d, const BItem *items, int nitems,
+                                const int *active, double omega, double *part, int grid, int threads, size_t lds,
+                                hipStream_t st) {
+    switch (kind) {
+    case BK_SMOOTH2:
+        return bmarch_kind<BK_SMOOTH2>(V, pf, pc, d, items, nitems, active, omega, part, grid, threads, lds, st);
+    case BK_SMOOTH2_SCALED:
+        return bmarch_kind<BK_SMOOTH2_SCALED>(V, pf, pc, d, items, nitems, active, omega, part, grid, threads, lds,
+                                              st);
+    case BK_SWEEP:
+        return bmarch_kind<BK_SWEEP>(V, pf, pc, d, items, nitems, active, omega, part, grid, threads, lds, st);
+    case BK_PROLONG:
+        return bmarch_kind<BK_PROLONG>(V, pf, pc, d, items, nitems, active, omega, part, grid, threads, lds, st);
+    case BK_OUTER:
+        return bmarch_kind<BK_OUTER>(V, pf, pc, d, items, nitems, active, omega, part, grid, threads, lds, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int V, class TF, bool XSH>
+static hipError_t brs2_tc(int pc, const BDesc *d, const BItem *it, int n, const int *act, int grid, int threads,
+                          size_t lds, hipStream_t st) {
+    MG_BT(pc, hipLaunchKernelGGL((k_batched_restrict2<V, TF, TB, XSH>), dim3(grid), dim3(threads), lds, st, d, it, n,
+                                 act));
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_restrict2(int V, int pf, int pc, bool xsh, const BDesc *d, const BItem *items, int nitems,
+                                    const int *active, int grid, int threads, size_t lds, hipStream_t st) {
+    if (pf == P_F64) {
+        if (V != 4) return hipErrorInvalidValue;
+        return xsh ? brs2_tc<4, double, true>(pc, d, items, nitems, active, grid, threads, lds, st)
+                   : brs2_tc<4, double, false>(pc, d, items, nitems, active, grid, threads, lds, st);
+    }
+    switch (pf) {
+    case P_F32:
+        if (V == 8) return xsh ? brs2_tc<8, float, true>(pc, d, items, nitems, active, grid, threads, lds, st)
+                               : brs2_tc<8, float, false>(pc, d, items, nitems, active, grid, threads, lds, st);
+        return xsh ? brs2_tc<4, float, true>(pc, d, items, nitems, active, grid, threads, lds, st)
+                   : brs2_tc<4, float, false>(pc, d, items, nitems, active, grid, threads, lds, st);
+    case P_F16:
+        if (V == 8) return xsh ? brs2_tc<8, f16, true>(pc, d, items, nitems, active, grid, threads, lds, st)
+                               : brs2_tc<8, f16, false>(pc, d, items, nitems, active, grid, threads, lds, st);
+        return xsh ? brs2_tc<4, f16, true>(pc, d, items, nitems, active, grid, threads, lds, st)
+                   : brs2_tc<4, f16, false>(pc, d, items, nitems, active, grid, threads, lds, st);
+    case P_BF16:
+        if (V == 8) return xsh ? brs2_tc<8, bf16, true>(pc, d, items, nitems, active, grid, threads, lds, st)
+                               : brs2_tc<8, bf16, false>(pc, d, items, nitems, active, grid, threads, lds, st);
+        return xsh ? brs2_tc<4, bf16, true>(pc, d, items, nitems, active, grid, threads, lds, st)
+                   : brs2_tc<4, bf16, false>(pc, d, items, nitems, active, grid, threads, lds, st);
+    }
     return hipErrorInvalidValue;
 }
 

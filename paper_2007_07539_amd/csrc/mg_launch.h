@@ -113,6 +113,7 @@ struct BDesc {
     int tyc, zcc, ytiles;
     int part_off;        // first reduction partial of the instance (update)
     int inst;
+    int ty;              // LDS-plane kernels: rows per block (ytiles = its y tiles)
 };
 struct BItem {
     int d, blk;  // descriptor, tile
@@ -129,6 +130,13 @@ hipError_t launch_batched_stencil(int kind, int V, int pf, int pc, const BDesc *
 hipError_t launch_batched_restrict(int V, int pf, int pc, const BDesc *d, const BItem *items, int nitems,
                                    const int *active, int grid, int threads, size_t lds, hipStream_t st);
 hipError_t launch_batched_coarse(int prec, const BDesc *d, int n, const int *active, hipStream_t st);
+// LDS-plane forms (grids of pitch >= 16; one pitch per launch, block size
+// (ty + 2) P / V for the stencil kinds, (2 tyc + 3) P / V for the restriction).
+hipError_t launch_batched_march(int kind, int V, int pf, int pc, const BDesc *d, const BItem *items, int nitems,
+                                const int *active, double omega, double *part, int grid, int threads, size_t lds,
+                                hipStream_t st);
+hipError_t launch_batched_restrict2(int V, int pf, int pc, bool xsh, const BDesc *d, const BItem *items, int nitems,
+                                    const int *active, int grid, int threads, size_t lds, hipStream_t st);
 hipError_t launch_batched_finalize(const BFin *fin, int ninst, const int *active, int scaling, hipStream_t st);
 
 // ---- many right-hand sides, interleaved [z][y][x][k] -------------------------
