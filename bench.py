@@ -41,11 +41,24 @@ def timed_solves(solver, bt, u, steps, warmup, torch):
     return start.elapsed_time(end) / steps, results
 
 
+KERNEL_SOURCES = {"ir_update": ("mg_kernels.hip", "mg_device.h"),
+                  "sweep_update": ("mg_sweep_update.hip", "mg_device.h")}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2007_07539_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when that summary covers another kernel or older kernel sources."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "ir_update_poisson3d_511_f16_traffic.md")
+    if kernel not in KERNEL_SOURCES:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{kernel}_poisson3d_511_f16_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -53,10 +66,7 @@ def measured_traffic(kernel):
         if ":" in line and not line.startswith(("|", " ", "#", "`")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in ("mg_kernels.hip", "mg_device.h"):
-        h.update(open(os.path.join(ROOT, "paper_2007_07539_amd", "csrc", f), "rb").read())
-    if fields.get("traffic_kernel") != kernel or fields.get("source_sha256_16") != h.hexdigest()[:16]:
+    if fields.get("traffic_kernel") != kernel or fields.get("source_sha256_16") != kernel_source_hash(kernel):
         return None
     return float(fields["traffic_bytes_per_launch"])
 

@@ -317,51 +317,6 @@ struct EOuter {
     }
 };
 
-// True residual r = b - A U in FP64 (the operator (2D u - nb) / h^2, formed
-// in the same order as the row-wise pass), stored to the padded R; U is also
-// copied out to the dense uout (when given).  b and uout are dense n^D, x
-// fastest.  Per-block (sum r^2, max |r|) partials.
-struct EResid {
-    typedef double A;
-    struct State {
-        double ss, mx;
-    };
-    const double *__restrict__ b;
-    double *__restrict__ R;
-    double *__restrict__ uout;
-    double inv_h2;
-    int n;
-    double *__restrict__ part;
-    __device__ __forceinline__ void init(State &s) const { s.ss = 0.0, s.mx = 0.0; }
-    template <int D, int V>
-    __device__ __forceinline__ void emit(const Grid<D> &g, State &st, int x0, int y, int z, const A (&c)[V],
-                                         const A (&nb)[V]) const {
-        const size_t row = D == 3 ? ((size_t)(z - 1) * n + (size_t)(y - 1)) * n : (size_t)(z - 1) * n;
-        double r[V];
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            const int x = x0 + i;
-            if (x < 1) {
-                r[i] = 0.0;
-                continue;
-            }
-            const size_t d = row + (size_t)(x - 1);
-            r[i] = b[d] - (double(2 * D) * c[i] - nb[i]) * inv_h2;
-            if (uout) uout[d] = c[i];
-            st.ss += r[i] * r[i];
-            st.mx = nanmax(st.mx, fabs(r[i]));
-        }
-        store_row<double, V>(R + g.at(x0, y, z), r);
-    }
-    __device__ __forceinline__ void finish(State &s, double *lds, long pidx) const {
-        block_reduce(s.ss, s.mx, lds);
-        if (threadIdx.x == 0) {
-            part[2 * pidx] = s.ss;
-            part[2 * pidx + 1] = s.mx;
-        }
-    }
-};
-
 // ===========================================================================
 // The z-marching stencil kernel.  Thread t of the grid owns x chunk
 // (t mod P/V) of line (t div P/V); a line is a row y (3-D) of one z chunk, or
@@ -1761,21 +1716,6 @@ hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double 
                              double inv_h2, double *part, hipStream_t st) {
     const long N = D == 3 ? (long)n * n * n : (long)n * n;
     const int blocks = flat_blocks(N);
-    if (D == 3 && U && R && P >= 4) {
-        // z-marching form: each plane of U is read once per thread column
-        // (the row-wise pass re-reads the z neighbours); no more blocks than
-        // the row-wise pass, the rest of its partials zeroed
-        const long per_chunk = (long)(P / 4) * P;
-        const int nmax = (int)std::max(1L, (long)blocks * 256 / per_chunk);
-        const Shape s{4, (P - 1 + nmax - 1) / nmax, 256, 0, 0};
-        const int used = stencil_blocks(3, P, s);
-        const FArr<double, double> f{U};
-        const EResid e{b, R, uout, inv_h2, n, part};
-        hipError_t err = run_stencil<3, 4>(f, e, P, s, st);
-        if (err == hipSuccess && used < blocks)
-            err = launch_fill_zero(part + 2 * (size_t)used, (size_t)(blocks - used) * 2 * sizeof(double), st);
-        return err;
-    }
     if (D == 3)
         hipLaunchKernelGGL(k_resid_rows<3>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, part);
     else
