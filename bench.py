@@ -180,6 +180,7 @@ def main():
                     "restrict": mixed.get_shape(0, mgir.SHAPE_RESTRICT),
                     "update": mixed.get_shape(0, mgir.SHAPE_UPDATE),
                     "fused_sweep_update": mixed.get_shape(0, mgir.SHAPE_FUSE),
+                    "fused_smooth_restrict": mixed.get_shape(0, mgir.SHAPE_FUSE_SR),
                     "fused_coarse_end": mixed.get_shape(0, mgir.SHAPE_TAIL)}
     ms_mixed, res_mixed = timed_solves(mixed, bt, u, args.steps, args.warmup, torch)
     log(f"[bench] mixed: {ms_mixed:.2f} ms/solve, {res_mixed[-1].iterations} it, rel {res_mixed[-1].rel_residual:.2e}")

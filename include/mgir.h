@@ -287,7 +287,7 @@ typedef enum {
                                levels in LDS; bitwise the same result.  The
                                workspace copies of those levels are then not
                                updated. */
-    MG_SHAPE_FUSE = 7       /* 3-D, level argument 0: {on (0|1)[, V (4), zc, xcd,
+    MG_SHAPE_FUSE = 7,      /* 3-D, level argument 0: {on (0|1)[, V (4), zc, xcd,
                                ty]}.  When on (the default; the autotuner keeps it
                                only where it is faster), the last post-smoothing
                                sweep of the finest level and the refinement update
@@ -295,6 +295,14 @@ typedef enum {
                                used when the finest level is FP64 without residual
                                scaling (its right-hand side is r itself) or nu2 < 2.
                                Reading returns whether it is in use and its shape. */
+    MG_SHAPE_FUSE_SR = 8    /* 3-D, level argument 0: {on (0|1)[, tyc, zcc]}.  When on
+                               (the default; the autotuner keeps it only where it is
+                               faster), the first pre-smoothing of the finest level
+                               (from the scaled residual) and the residual +
+                               restriction of its result run as one kernel inside
+                               ir_solve (same result).  Needs nu1 = 2, residual
+                               scaling, an FP32/FP16/BF16 finest level and P/8
+                               dividing 64.  Reading returns whether it is in use. */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);

@@ -83,6 +83,9 @@ struct mg_ctx {
     bool fuse_on = true;   // allow the fused last sweep + update on the finest level
     bool fused = false;    // ... and it is in use
     Shape fsh{4, 16, 256, 1, 4};
+    bool fuse_sr_on = true;  // allow the fused first smoothing + restriction on the finest level
+    bool fused_sr = false;   // ... and it is in use
+    RShape srsh{8, 2, 16, 3};
     // profiling
     bool prof = false;
     std::vector<ProfRec> recs;
@@ -307,6 +310,15 @@ enum RhsMode { RHS_B = 0, RHS_SCALED_R = 1, RHS_ALIAS_R = 2 };
 // Pre-smoothing of level l and restriction of its residual to level l + 1.
 hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const void *rhs) {
     hipError_t e;
+    if (l == 0 && mode == RHS_SCALED_R && h->fused_sr) {
+        LevelPlan &L = h->lv[0], &C = h->lv[1];
+        const double N = (double)points(h->dim, L.n);
+        RUN(h, st, "smooth_restrict", 0, N * (8 + 2 * sb(L.prec)) + (double)points(h->dim, C.n) * sb(C.prec),
+            launch_smooth_restrict(L.prec, C.prec, L.P, Rbuf(h), scal(h), bbuf(h, 0), cbuf(h, 0, 0), bbuf(h, 1),
+                                   h->opt.omega, h->srsh, st));
+        h->cur[0] = 0;
+        return hipSuccess;
+    }
     if (l == 0 && mode == RHS_ALIAS_R) {
         // FP64 baseline without scaling: the residual is the right-hand side
         LevelPlan &L = h->lv[0];
@@ -392,6 +404,15 @@ bool fusion_possible(mg_ctx *h) {
     return h->fuse_on && !h->batched && !h->nrhs && h->dim == 3 && h->nl >= 2 && h->opt.nu2 >= 2 &&
            !finest_alias(h) && sweep_update_ok(h->lv[0].P, h->lv[0].prec, h->fsh);
 }
+
+// The fused first smoothing + restriction replaces exactly two pre-sweeps
+// of the scaled residual and the restriction of their result.
+bool fusion_sr_possible(mg_ctx *h) {
+    return h->fuse_sr_on && !h->batched && !h->nrhs && h->dim == 3 && h->nl >= 2 && h->opt.nu1 == 2 &&
+           !finest_alias(h) && smooth_restrict_ok(h->lv[0].P, h->lv[0].prec, h->srsh);
+}
+
+void set_fused_sr(mg_ctx *h, bool on) { h->fused_sr = on && fusion_sr_possible(h); }
 
 void set_fused(mg_ctx *h, bool on) {
     h->fused = on && fusion_possible(h);
@@ -590,6 +611,23 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                     if (t < best) best = t, br = r;
                 }
         L.rsh = br;
+        if (l == 0 && fusion_sr_possible(h)) {
+            // the fused first smoothing + restriction against the two kernels
+            float bf = 1e30f;
+            RShape bsr = h->srsh;
+            for (int tyc : {1, 2, 3})
+                for (int zcc : {4, 8, 16, 32}) {
+                    const RShape r{8, tyc, zcc, 3};
+                    if (!smooth_restrict_ok(L.P, L.prec, r)) continue;
+                    const float t = time_ms(st, [&]() {
+                        return launch_smooth_restrict(L.prec, h->lv[1].prec, L.P, Rbuf(h), scal(h), bbuf(h, 0),
+                                                      cbuf(h, 0, 0), bbuf(h, 1), h->opt.omega, r, st);
+                    }, 3);
+                    if (t < bf) bf = t, bsr = r;
+                }
+            h->srsh = bsr;
+            set_fused_sr(h, bf < best + fam_best[SH_SMOOTH]);
+        }
         if (l == 0) {
             best = 1e30f;
             Shape bo = L.osh;
@@ -741,7 +779,18 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     h->off_scal = off;
     off += 256;
     h->ws_need = off;
-    if (m > 1) set_fused(h, true);
+    if (m > 1) {
+        set_fused(h, true);
+        const int P0 = h->lv[0].P;
+        for (int tyc = 3; tyc >= 1; --tyc) {
+            const RShape r{8, tyc, std::max(1, std::min(16, P0 / 2 - 1)), 3};
+            if (smooth_restrict_ok(P0, h->lv[0].prec, r)) {
+                h->srsh = r;
+                break;
+            }
+        }
+        set_fused_sr(h, true);
+    }
     *out = h;
     return MG_OK;
 }
@@ -1057,6 +1106,20 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
         drop_graph(h);
         return MG_OK;
     }
+    if (kind == MG_SHAPE_FUSE_SR) {
+        if ((np != 1 && np != 3) || (p[0] != 0 && p[0] != 1))
+            return fail(MG_ERR_ARG, "the fused smoothing + restriction shape is {on (0|1)[, tyc, zcc]}");
+        if (np == 3) {
+            const RShape r{8, p[1], p[2], 3};
+            if (h->nl < 2 || !smooth_restrict_ok(h->lv[0].P, h->lv[0].prec, r))
+                return fail(MG_ERR_ARG, "fused smoothing + restriction shape {tyc, zcc} not valid here");
+            h->srsh = r;
+        }
+        h->fuse_sr_on = p[0] != 0;
+        set_fused_sr(h, h->fuse_sr_on);
+        drop_graph(h);
+        return MG_OK;
+    }
     if (kind == MG_SHAPE_FUSE) {
         if ((np != 1 && np != 5) || (p[0] != 0 && p[0] != 1))
             return fail(MG_ERR_ARG, "the fused-update shape is {on (0|1)[, V, zc, xcd, ty]}");
@@ -1118,6 +1181,12 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
     if (kind == MG_SHAPE_TAIL) {
         if (np < 1) return fail(MG_ERR_ARG, "too few values");
         p[0] = h->tail_on ? 1 : 0;
+        return MG_OK;
+    }
+    if (kind == MG_SHAPE_FUSE_SR) {
+        if (np < 1) return fail(MG_ERR_ARG, "too few values");
+        p[0] = h->fused_sr ? 1 : 0;
+        if (np >= 3) p[1] = h->srsh.tyc, p[2] = h->srsh.zcc;
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE) {

@@ -90,6 +90,16 @@ hipError_t launch_sweep_update(int prec, int P, const void *c, const void *b, do
                                const double *scal, double h2, double omega, double *part, const Shape &s,
                                hipStream_t st);
 
+// First pre-smoothing of the finest 3-D level from the FP64 residual (scaled
+// and cast) fused with the residual + full-weighting restriction of its
+// result; writes b = round(r / alpha), c2 and the coarse right-hand side.
+// FP32/FP16/BF16 levels with P/8 dividing 64; s.tyc coarse rows and s.zcc
+// coarse planes per block.
+size_t smooth_restrict_lds_bytes(int P, size_t sb, int tyc);
+bool smooth_restrict_ok(int P, int prec, const RShape &s);
+hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
+                                  void *cout, void *bc, double omega, const RShape &s, hipStream_t st);
+
 // Fused coarse end of a 3-D V-cycle in one workgroup (LDS-resident levels):
 // nlev grids of format prec with pitches P0 = 4 * 2^(nlev-1), ..., 4, then the
 // one-point base of format pb.  b: right-hand side of the first (padded, pitch

@@ -1,0 +1,288 @@
+// The finest level's first pre-smoothing inside a refinement step fused with
+// the residual and full-weighting restriction of its result (3-D):
+//   b  = round_T(r / alpha)                     (residuum scaling and cast)
+//   c1 = round_T(k b),  c2 = round_T(c1 + k (b - (6 c1 - nb(c1))))
+//   b_c = round_TC(FW(b - (6 c2 - nb(c2))))
+// b and c2 are written for the later sweeps and the prolongation; c2 is
+// restricted from registers and LDS instead of being read back from HBM
+// (8 + 2 s + s_c/8 bytes per point instead of 8 + 2 s, then 2 s + s_c/8).
+//
+// A block owns tyc coarse rows and zcc coarse planes, like the pipelined
+// restriction kernel.  Its thread row groups gi = 0 .. 2 tyc + 4 hold fine
+// rows 2 Y0 - 3 + gi: the residual rows 2 Y0 - 1 .. 2 Y0 + 2 tyc - 1 need c2
+// one row further out, which needs c1 one more row out.  Per iteration t the
+// block forms c2 of plane t+1 (from c1 of planes t .. t+2), the residual of
+// plane t (from c2 of planes t-1 .. t+1), and folds the residual rows of
+// plane t-1 into the coarse plane; c1, c2 and the residual rows sit in
+// double-buffered LDS slots, each written after the iteration's barrier and
+// not read again before the next one.  The arithmetic is that of the
+// separate kernels, operation for operation, so results are bitwise equal.
+#include "mg_device.h"
+#include "mg_launch.h"
+
+namespace mg {
+namespace {
+
+template <class T, class TC>
+__global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restrict__ R,
+                                                          const double *__restrict__ scal, T *__restrict__ bout,
+                                                          T *__restrict__ cout, TC *__restrict__ bc, int P, int tyc,
+                                                          int zcc, int ytiles, double omega, int xcd) {
+    constexpr int V = 8, VC = 4;
+    typedef acc_t<T> A;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int G = 2 * tyc + 5, RR = 2 * tyc + 1, RW = P / 2;
+    const size_t cslot = (size_t)G * P, rslot = (size_t)RR * RW;
+    T *c1s = reinterpret_cast<T *>(smem_raw);                                 // [2][G][P]
+    T *c2s = c1s + 2 * cslot;                                                 // [2][G][P]
+    A *rs = reinterpret_cast<A *>(smem_raw + 4 * cslot * sizeof(T));          // [2][RR][RW]
+    const int Pc = P >> 1, TXR = P / V;
+    const Grid<3> g{P};
+    const Grid<3> gc{Pc};
+    int blk = blockIdx.x;
+    if (xcd) {
+        const int nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    const int ytile = blk % ytiles, zch = blk / ytiles;
+    const int Y0 = 1 + ytile * tyc;
+    const int Z0 = 1 + zch * zcc, Z1 = min(Z0 + zcc, Pc);
+    const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
+    const int xc = threadIdx.x % TXR, gi = threadIdx.x / TXR;
+    const int y = 2 * Y0 - 3 + gi;
+    const int x0 = xc * V, X0 = xc * VC;
+    const bool row_in = y >= 1 && y <= P - 1;
+    const bool c2_row = gi >= 1 && gi <= G - 2;
+    const bool res_slot = gi >= 2 && gi <= G - 3;
+    const bool res_row = res_slot && row_in;
+    // fine rows 2 Y0 - 1 .. 2 Y0 + 2 tyc - 2 belong to this tile; the last
+    // tile also owns the last fine row P - 1
+    const bool own_row = row_in && y >= 2 * Y0 - 1 && (y <= 2 * Y0 + 2 * tyc - 2 || Y0 + tyc >= Pc);
+    const bool last_z = Z1 == Pc;
+    auto own_plane = [&](int z) { return z >= zf0 && (z <= zf1 - 1 || (last_z && z == P - 1)); };
+    const bool coarse = gi < tyc && Y0 + gi < Pc;
+    const int Yc = Y0 + gi;
+    const double inv = scal[1];
+    const A k = (A)(omega / 6.0);
+
+    auto fetch_r = [&](int z, RawRow<double, V> &rr) {
+        if (!row_in || z < 1 || z > P - 1) {
+            zero_row(rr);
+            return;
+        }
+        fetch_row<double, V>(R + g.at(x0, y, z), rr);
+    };
+    // b = round_T(r / alpha) of the own row (zero outside the interior)
+    auto scaled = [&](const RawRow<double, V> &rr, A (&o)[V]) {
+        double rv[V];
+        widen_row<double, V>(rr, rv);
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = widen(Store<T>::from_f64(rv[i] * inv));
+    };
+    auto store_t = [&](T *p, const A (&v)[V]) {
+        T o[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = Store<T>::from_acc(v[i]);
+        store_row<T, V>(p, o);
+    };
+
+    A bq0[V], bq1[V], bq2[V];   // b of the own row, planes t, t+1, t+2
+    A c2m[V], c2c[V], c2p[V];   // c2 of the own row, planes t-1, t, t+1
+    RawRow<double, V> rnext;    // r of the own row, plane t+2 (then t+3)
+    A acc[VC];
+#pragma unroll
+    for (int j = 0; j < VC; ++j) acc[j] = A(0);
+#pragma unroll
+    for (int i = 0; i < V; ++i) c2m[i] = c2c[i] = c2p[i] = A(0);
+
+    const int tb = zf0 - 2;
+    {
+        RawRow<double, V> t0;
+        fetch_r(tb, t0);
+        scaled(t0, bq0);
+        fetch_r(tb + 1, t0);
+        scaled(t0, bq1);
+        A c1[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) c1[i] = round_to<T>(k * bq1[i]);
+        store_t(c1s + (size_t)((tb + 1) & 1) * cslot + (size_t)gi * P + x0, c1);
+        fetch_r(tb + 2, rnext);
+    }
+
+    // fold the x-weighted residual rows of fine plane zf (slot s) into acc
+    auto coarse_step = [&](int zf, int s) {
+        const A *rb = rs + (size_t)s * rslot;
+        const int j = zf - zf0;
+        const bool last_of_z = j > 0 && (j & 1) == 0;  // zf = 2Z + 1
+        A xs[3][VC];
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) load_row<A, VC>(rb + (size_t)(2 * gi + oy) * RW + X0, xs[oy]);
+        TC out[VC];
+#pragma unroll
+        for (int jx = 0; jx < VC; ++jx) {
+            const int X = X0 + jx;
+            A q = A(0);
+            if (X >= 1) q = A(0.25) * (xs[0][jx] + xs[2][jx]) + A(0.5) * xs[1][jx];
+            if (j == 0) {
+                acc[jx] = A(0.25) * q;
+            } else if (!last_of_z) {
+                acc[jx] += A(0.5) * q;
+            } else {
+                out[jx] = store_as<TC>(acc[jx] + A(0.25) * q);
+                acc[jx] = A(0.25) * q;
+            }
+        }
+        if (last_of_z) {
+            if (X0 == 0) out[0] = store_as<TC>(A(0));
+            store_row<TC, VC>(bc + gc.at(X0, Yc, (zf - 1) >> 1), out);
+        }
+    };
+
+    for (int t = tb; t <= zf1; ++t) {
+        // b and c1 of plane t+2 (registers only before the barrier)
+        scaled(rnext, bq2);
+        fetch_r(t + 3, rnext);
+        A c1n[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) c1n[i] = round_to<T>(k * bq2[i]);
+        if (own_row && own_plane(t + 2)) {
+            T o[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) o[i] = Store<T>::from_acc(bq2[i]);
+            if (x0 == 0) o[0] = zero_of<T>();
+            store_row<T, V>(bout + g.at(x0, y, t + 2), o);
+        }
+        __syncthreads();
+        if (coarse && t - 1 >= zf0) coarse_step(t - 1, (t - 1) & 1);
+        // c2 of plane t+1 on rows gi = 1 .. G-2
+        if (c2_row) {
+            const int p = t + 1;
+            if (row_in && p >= 1 && p <= P - 1) {
+                const T *row = c1s + (size_t)(p & 1) * cslot + (size_t)gi * P;
+                A cc[V], nb[V];
+#pragma unroll
+                for (int i = 0; i < V; ++i) cc[i] = round_to<T>(k * bq1[i]);
+                const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
+                const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+#pragma unroll
+                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cc[i - 1] : xl) + (i < V - 1 ? cc[i + 1] : xr);
+                A ym[V], yp[V];
+                load_row<T, V>(row - P + x0, ym);
+                load_row<T, V>(row + P + x0, yp);
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    nb[i] += ym[i];
+                    nb[i] += yp[i];
+                    nb[i] += round_to<T>(k * bq0[i]);
+                    nb[i] += c1n[i];
+                    const A lc = fmaT<A>(A(6), cc[i], -nb[i]);
+                    c2p[i] = round_to<T>(fmaT<A>(k, bq1[i] - lc, cc[i]));
+                }
+                if (x0 == 0) c2p[0] = A(0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < V; ++i) c2p[i] = A(0);
+            }
+            store_t(c2s + (size_t)(p & 1) * cslot + (size_t)gi * P + x0, c2p);
+            if (own_row && own_plane(p)) store_t(cout + g.at(x0, y, p), c2p);
+        }
+        // residual of plane t on rows gi = 2 .. G-3, x weights in the thread
+        if (t >= zf0) {
+            A r[V];
+            if (res_row) {
+                const T *row = c2s + (size_t)(t & 1) * cslot + (size_t)gi * P;
+                A nb[V];
+                const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
+                const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+#pragma unroll
+                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? c2c[i - 1] : xl) + (i < V - 1 ? c2c[i + 1] : xr);
+                A ym[V], yp[V];
+                load_row<T, V>(row - P + x0, ym);
+                load_row<T, V>(row + P + x0, yp);
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    nb[i] += ym[i];
+                    nb[i] += yp[i];
+                    nb[i] += c2m[i];
+                    nb[i] += c2p[i];
+                    r[i] = bq0[i] - fmaT<A>(A(6), c2c[i], -nb[i]);
+                }
+                if (x0 == 0) r[0] = A(0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < V; ++i) r[i] = A(0);
+            }
+            // coarse X = x0/2 + j takes fine 2X-1, 2X, 2X+1; x0-1 from the previous lane
+            const A left_in = __shfl_up(r[V - 1], 1, 64);
+            const A left = x0 > 0 ? left_in : A(0);
+            A xq[VC];
+#pragma unroll
+            for (int j = 0; j < VC; ++j) {
+                const A lm = j > 0 ? r[2 * j - 1] : left;
+                xq[j] = A(0.25) * (lm + r[2 * j + 1]) + A(0.5) * r[2 * j];
+            }
+            if (x0 == 0) xq[0] = A(0);
+            if (res_slot) store_row<A, VC>(rs + (size_t)(t & 1) * rslot + (size_t)(gi - 2) * RW + (x0 >> 1), xq);
+        }
+        // c1 of plane t+2 for the next iteration's neighbours
+        store_t(c1s + (size_t)((t + 2) & 1) * cslot + (size_t)gi * P + x0, c1n);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            bq0[i] = bq1[i];
+            bq1[i] = bq2[i];
+            c2m[i] = c2c[i];
+            c2c[i] = c2p[i];
+        }
+    }
+    __syncthreads();
+    if (coarse) coarse_step(zf1, zf1 & 1);
+}
+
+template <class T>
+hipError_t smooth_restrict_t(int pc, int P, const double *R, const double *scal, void *bout, void *cout, void *bc,
+                             double omega, const RShape &s, hipStream_t st) {
+    const int Pc = P / 2;
+    const int ytiles = (Pc - 1 + s.tyc - 1) / s.tyc;
+    const int blocks = ytiles * ((Pc - 1 + s.zcc - 1) / s.zcc);
+    const int threads = (2 * s.tyc + 5) * (P / 8);
+    const size_t lds = smooth_restrict_lds_bytes(P, sizeof(T), s.tyc);
+#define MG_SR(TCT)                                                                                                     \
+    hipLaunchKernelGGL((k_smooth_restrict<T, TCT>), dim3(blocks), dim3(threads), lds, st, R, scal,                   \
+                       static_cast<T *>(bout), static_cast<T *>(cout), static_cast<TCT *>(bc), P, s.tyc, s.zcc,     \
+                       ytiles, omega, 1)
+    switch (pc) {
+    case P_F64: MG_SR(double); break;
+    case P_F32: MG_SR(float); break;
+    case P_F16: MG_SR(f16); break;
+    case P_BF16: MG_SR(bf16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MG_SR
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t smooth_restrict_lds_bytes(int P, size_t sb, int tyc) {
+    return 4 * (size_t)(2 * tyc + 5) * P * sb + 2 * (size_t)(2 * tyc + 1) * (P / 2) * 4;
+}
+
+bool smooth_restrict_ok(int P, int prec, const RShape &s) {
+    if (prec == P_F64 || P < 16 || P / 8 > 64 || 64 % (P / 8) != 0) return false;
+    if (s.tyc < 1 || s.tyc > P / 2 - 1 || s.zcc < 1 || s.zcc > P / 2 - 1) return false;
+    if ((2 * s.tyc + 5) * (P / 8) > 768) return false;  // the kernel's launch bound
+    return smooth_restrict_lds_bytes(P, prec_bytes(prec), s.tyc) <= 65536;
+}
+
+hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
+                                  void *cout, void *bc, double omega, const RShape &s, hipStream_t st) {
+    if (!smooth_restrict_ok(P, prec, s)) return hipErrorInvalidValue;
+    switch (prec) {
+    case P_F32: return smooth_restrict_t<float>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_F16: return smooth_restrict_t<f16>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_BF16: return smooth_restrict_t<bf16>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mg

@@ -27,8 +27,8 @@ EXPORTS = ("mg_default_options", "mg_setup", "mg_workspace_size", "mg_bind_works
            "mg_levels", "mg_level_n", "mg_profile_step", "mg_set_shape", "mg_get_shape", "mg_bandwidth_probe",
            "mg_setup_batched", "ir_solve_batched", "mg_instances", "mg_setup_multi", "ir_solve_multi",
            "mg_rhs_count")
-SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE, SHAPE_SMOOTH, SHAPE_SWEEP, SHAPE_PROLONG, SHAPE_TAIL, SHAPE_FUSE = \
-    0, 1, 2, 3, 4, 5, 6, 7
+SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE, SHAPE_SMOOTH, SHAPE_SWEEP, SHAPE_PROLONG, SHAPE_TAIL, SHAPE_FUSE, \
+    SHAPE_FUSE_SR = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
 
 class MgError(RuntimeError):
@@ -239,8 +239,8 @@ class Solver:
     def get_shape(self, level: int, kind: int):
         arr = (ctypes.c_int * 6)()
         _check(self.lib.mg_get_shape(self._h, level, kind, arr, 6), "mg_get_shape")
-        return list(arr[: 4 if kind == SHAPE_RESTRICT else 1 if kind == SHAPE_TAIL else 5 if kind == SHAPE_FUSE
-                        else 6])
+        n = {SHAPE_RESTRICT: 4, SHAPE_TAIL: 1, SHAPE_FUSE: 5, SHAPE_FUSE_SR: 3}.get(kind, 6)
+        return list(arr[:n])
 
     def profile_step(self, stream=None, cap: int = 512):
         names = (ctypes.c_char_p * cap)()

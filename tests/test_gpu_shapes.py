@@ -133,3 +133,34 @@ def test_fused_update_not_used_without_scaling_in_fp64(dev):
     n = 31
     s = mgir.Solver(3, n, W.precision_map("f64", W.levels_for(n)), residual_scaling=False)
     assert s.get_shape(0, mgir.SHAPE_FUSE)[0] == 0
+
+
+@pytest.mark.parametrize("name,n", [("f16", 63), ("bf16", 31), ("f32", 127), ("f16", 15), ("h_mg", 31),
+                                    ("hsd", 255)])
+def test_fused_smooth_restrict_bitwise(dev, name, n):
+    """The first finest-level smoothing fused with the residual + restriction
+    of its result changes no result, for every launch shape of the fused
+    kernel (several y tiles and plane chunks, ragged last ones)."""
+    print(f"fused smooth+restrict {name} n={n}", flush=True)
+    prec = W.precision_map(name, W.levels_for(n))
+    b64 = torch.from_numpy(W.uniform_rhs(3, n, seed=9)).to(dev)
+    s = mgir.Solver(3, n, prec)
+    assert s.get_shape(0, mgir.SHAPE_FUSE_SR)[0] == (0 if prec[0] == "f64" else 1)
+    s.set_shape(0, mgir.SHAPE_FUSE_SR, [0])
+    assert s.get_shape(0, mgir.SHAPE_FUSE_SR)[0] == 0
+    u_ref, r_ref = s.solve(b64)
+    u_ref = u_ref.clone()
+    tried = 0
+    for shape in ([1, 1, 1], [1, 2, 3], [1, 3, 16], [1, 1, 5], [1, 3, 7], [1, 2, 32]):
+        try:
+            s.set_shape(0, mgir.SHAPE_FUSE_SR, shape)
+        except mgir.MgError:
+            continue
+        tried += 1
+        assert s.get_shape(0, mgir.SHAPE_FUSE_SR) == shape
+        print(f"  shape {shape}", flush=True)
+        u, r = s.solve(b64)
+        assert r.iterations == r_ref.iterations, shape
+        assert r.history == r_ref.history, shape
+        assert torch.equal(u, u_ref), shape
+    assert tried >= (0 if prec[0] == "f64" else 3)
