@@ -615,8 +615,27 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
             // the fused first smoothing + restriction against the two kernels
             float bf = 1e30f;
             RShape bsr = h->srsh;
-            for (int tyc : {1, 2, 3})
-                for (int zcc : {4, 8, 16, 32}) {
+            int dev = 0, cus = 256;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            for (int tyc : {1, 2, 3}) {
+                // powers of two, and the shortest chunk for each chunk count
+                // whose block count nearly fills up to six whole rounds of one
+                // block per CU
+                std::vector<int> zs{4, 8, 16, 32};
+                const int Pc = L.P / 2, ytiles = (Pc - 1 + tyc - 1) / tyc;
+                int last_chunks = 0;
+                for (int zcc = 6; zcc <= 48 && zcc <= Pc - 1; ++zcc) {
+                    const int chunks = (Pc - 1 + zcc - 1) / zcc;
+                    if (chunks == last_chunks) continue;
+                    last_chunks = chunks;
+                    const long nb = (long)ytiles * chunks;
+                    const long rounds = (nb + cus - 1) / cus;
+                    if (rounds <= 6 && nb >= 0.97 * rounds * cus && std::find(zs.begin(), zs.end(), zcc) == zs.end())
+                        zs.push_back(zcc);
+                }
+                for (int zcc : zs) {
                     const RShape r{8, tyc, zcc, 3};
                     if (!smooth_restrict_ok(L.P, L.prec, r)) continue;
                     const float t = time_ms(st, [&]() {
@@ -625,6 +644,7 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                     }, 3);
                     if (t < bf) bf = t, bsr = r;
                 }
+            }
             h->srsh = bsr;
             set_fused_sr(h, bf < best + fam_best[SH_SMOOTH]);
         }
@@ -781,6 +801,9 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     h->ws_need = off;
     if (m > 1) {
         set_fused(h, true);
+        // the fused first smoothing + restriction needs more than 64 KB of LDS
+        // for its larger tiles; without that permission it stays off
+        if (h->dim != 3 || smooth_restrict_prepare() != hipSuccess) h->fuse_sr_on = false;
         const int P0 = h->lv[0].P;
         for (int tyc = 3; tyc >= 1; --tyc) {
             const RShape r{8, tyc, std::max(1, std::min(16, P0 / 2 - 1)), 3};

@@ -52,6 +52,18 @@ __device__ __forceinline__ float f64_to_f32_odd(double d) {
     return f;
 }
 
+// double -> float ahead of a rounding to FP16, by the bits of the double: the
+// 29 significand bits that float drops are cleared and OR-ed into its lowest
+// kept bit (round to odd), so that the conversion of the result is exact
+// wherever float is normal.  Below that range FP16 rounds to zero either way,
+// so the FP16 result equals that of f64_to_f32_odd.
+__device__ __forceinline__ float f64_to_f32_odd_for_f16(double d) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+    const uint32_t lo = (uint32_t)u;
+    const uint32_t kept = (lo & 0xE0000000u) | (min(lo & 0x1FFFFFFFu, 1u) << 29);
+    return (float)__longlong_as_double((long long)((u & 0xFFFFFFFF00000000ull) | kept));
+}
+
 // Round an accumulator value into storage format T (nearest even).
 template <class T> struct Store;
 template <> struct Store<double> {
@@ -71,7 +83,7 @@ template <> struct Store<f16> {
         asm volatile("" : "+v"(v));
         return (f16)v;
     }
-    __device__ static f16 from_f64(double v) { return (f16)f64_to_f32_odd(v); }
+    __device__ static f16 from_f64(double v) { return (f16)f64_to_f32_odd_for_f16(v); }
 };
 template <> struct Store<bf16> {
     __device__ static bf16 from_acc(float v) { return f32_to_bf16(v); }

@@ -95,7 +95,12 @@ hipError_t launch_sweep_update(int prec, int P, const void *c, const void *b, do
 // result; writes b = round(r / alpha), c2 and the coarse right-hand side.
 // FP32/FP16/BF16 levels with P/8 dividing 64; s.tyc coarse rows and s.zcc
 // coarse planes per block.
-size_t smooth_restrict_lds_bytes(int P, size_t sb, int tyc);
+// LDS one workgroup may allocate on gfx950.
+constexpr size_t kLdsMax = 160 * 1024;
+size_t smooth_restrict_lds_bytes(int P, int tyc);
+// Lets every instance of the fused kernel allocate up to kLdsMax of LDS; call
+// once per process before the first launch (not inside a stream capture).
+hipError_t smooth_restrict_prepare();
 bool smooth_restrict_ok(int P, int prec, const RShape &s);
 hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
                                   void *cout, void *bc, double omega, const RShape &s, hipStream_t st);

@@ -14,7 +14,8 @@
 // block forms c2 of plane t+1 (from c1 of planes t .. t+2), the residual of
 // plane t (from c2 of planes t-1 .. t+1), and folds the residual rows of
 // plane t-1 into the coarse plane; c1, c2 and the residual rows sit in
-// double-buffered LDS slots, each written after the iteration's barrier and
+// double-buffered LDS slots (in FP32, up to 104 KB at P = 512, which gfx950
+// allows one workgroup), each written after the iteration's barrier and
 // not read again before the next one.  The arithmetic is that of the
 // separate kernels, operation for operation, so results are bitwise equal.
 #include "mg_device.h"
@@ -33,11 +34,12 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = 2 * tyc + 5, RR = 2 * tyc + 1, RW = P / 2;
     const size_t cslot = (size_t)G * P, rslot = (size_t)RR * RW;
-    T *c1s = reinterpret_cast<T *>(smem_raw);                                 // [2][G][P]
-    T *c2s = c1s + 2 * cslot;                                                 // [2][G][P]
-    A *rs = reinterpret_cast<A *>(smem_raw + 4 * cslot * sizeof(T));          // [2][RR][RW]
+    // c1 and c2 sit in LDS widened to the accumulator type, so that neither
+    // their stores nor their loads convert
+    A *c1s = reinterpret_cast<A *>(smem_raw);  // [2][G][P]
+    A *c2s = c1s + 2 * cslot;                  // [2][G][P]
+    A *rs = c2s + 2 * cslot;                   // [2][RR][RW]
     const int Pc = P >> 1, TXR = P / V;
-    const Grid<3> g{P};
     const Grid<3> gc{Pc};
     int blk = blockIdx.x;
     if (xcd) {
@@ -64,48 +66,59 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
     const int Yc = Y0 + gi;
     const double inv = scal[1];
     const A k = (A)(omega / 6.0);
+    // offsets of the own row (plane 0) and of plane z, the latter uniform
+    const size_t roff = (size_t)(long)y * P + x0;
+    const size_t PP = (size_t)P * P;
+    auto at = [&](int z) { return (size_t)z * PP + roff; };
 
     auto fetch_r = [&](int z, RawRow<double, V> &rr) {
         if (!row_in || z < 1 || z > P - 1) {
             zero_row(rr);
             return;
         }
-        fetch_row<double, V>(R + g.at(x0, y, z), rr);
+        fetch_row<double, V>(R + at(z), rr);
     };
-    // b = round_T(r / alpha) of the own row (zero outside the interior)
-    auto scaled = [&](const RawRow<double, V> &rr, A (&o)[V]) {
+    // b = round_T(r / alpha) of the own row (zero outside the interior), as
+    // stored (braw) and widened (bw)
+    auto scaled = [&](const RawRow<double, V> &rr, T (&braw)[V], A (&bw)[V]) {
         double rv[V];
         widen_row<double, V>(rr, rv);
 #pragma unroll
-        for (int i = 0; i < V; ++i) o[i] = widen(Store<T>::from_f64(rv[i] * inv));
+        for (int i = 0; i < V; ++i) {
+            braw[i] = Store<T>::from_f64(rv[i] * inv);
+            bw[i] = widen(braw[i]);
+        }
     };
-    auto store_t = [&](T *p, const A (&v)[V]) {
-        T o[V];
+    // c1 = round_T(k b), widened
+    auto first = [&](const A (&bw)[V], A (&kw)[V]) {
 #pragma unroll
-        for (int i = 0; i < V; ++i) o[i] = Store<T>::from_acc(v[i]);
-        store_row<T, V>(p, o);
+        for (int i = 0; i < V; ++i) kw[i] = round_to<T>(k * bw[i]);
     };
 
-    A bq0[V], bq1[V], bq2[V];   // b of the own row, planes t, t+1, t+2
-    A c2m[V], c2c[V], c2p[V];   // c2 of the own row, planes t-1, t, t+1
-    RawRow<double, V> rnext;    // r of the own row, plane t+2 (then t+3)
+    // Per plane the block keeps b, c1 and c2 of the own row in registers,
+    // three planes each; the loop body is written out three times with the
+    // roles of the arrays rotated, so that no values are moved between planes.
+    A bA[V], bB[V], bC[V];   // b
+    A kA[V], kB[V], kC[V];   // c1
+    A cA[V], cB[V], cC[V];   // c2
+    RawRow<double, V> rnext; // r of the own row, plane t+2 (then t+3)
     A acc[VC];
 #pragma unroll
     for (int j = 0; j < VC; ++j) acc[j] = A(0);
 #pragma unroll
-    for (int i = 0; i < V; ++i) c2m[i] = c2c[i] = c2p[i] = A(0);
+    for (int i = 0; i < V; ++i) cA[i] = cB[i] = cC[i] = A(0);
 
     const int tb = zf0 - 2;
     {
         RawRow<double, V> t0;
+        T braw[V];
         fetch_r(tb, t0);
-        scaled(t0, bq0);
+        scaled(t0, braw, bA);
+        first(bA, kA);
         fetch_r(tb + 1, t0);
-        scaled(t0, bq1);
-        A c1[V];
-#pragma unroll
-        for (int i = 0; i < V; ++i) c1[i] = round_to<T>(k * bq1[i]);
-        store_t(c1s + (size_t)((tb + 1) & 1) * cslot + (size_t)gi * P + x0, c1);
+        scaled(t0, braw, bB);
+        first(bB, kB);
+        store_row<A, V>(c1s + (size_t)((tb + 1) & 1) * cslot + (size_t)gi * P + x0, kB);
         fetch_r(tb + 2, rnext);
     }
 
@@ -138,74 +151,74 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
         }
     };
 
-    for (int t = tb; t <= zf1; ++t) {
+    // One plane step: b0, b1 = b of planes t, t+1 and b2 <- b of plane t+2;
+    // k0, k1 = c1 of t, t+1 and k2 <- c1 of t+2; c0, c1 = c2 of t-1, t and
+    // c2 <- c2 of t+1.
+    auto body = [&](int t, const A (&b0)[V], const A (&b1)[V], A (&b2)[V], const A (&k0)[V], const A (&k1)[V],
+                    A (&k2)[V], const A (&c0)[V], const A (&c1)[V], A (&c2)[V]) __attribute__((always_inline)) {
         // b and c1 of plane t+2 (registers only before the barrier)
-        scaled(rnext, bq2);
+        T braw[V];
+        scaled(rnext, braw, b2);
         fetch_r(t + 3, rnext);
-        A c1n[V];
-#pragma unroll
-        for (int i = 0; i < V; ++i) c1n[i] = round_to<T>(k * bq2[i]);
+        first(b2, k2);
         if (own_row && own_plane(t + 2)) {
-            T o[V];
-#pragma unroll
-            for (int i = 0; i < V; ++i) o[i] = Store<T>::from_acc(bq2[i]);
-            if (x0 == 0) o[0] = zero_of<T>();
-            store_row<T, V>(bout + g.at(x0, y, t + 2), o);
+            if (x0 == 0) braw[0] = zero_of<T>();
+            store_row<T, V>(bout + at(t + 2), braw);
         }
         __syncthreads();
         if (coarse && t - 1 >= zf0) coarse_step(t - 1, (t - 1) & 1);
         // c2 of plane t+1 on rows gi = 1 .. G-2
         if (c2_row) {
             const int p = t + 1;
+            T craw[V];
             if (row_in && p >= 1 && p <= P - 1) {
-                const T *row = c1s + (size_t)(p & 1) * cslot + (size_t)gi * P;
-                A cc[V], nb[V];
+                const A *row = c1s + (size_t)(p & 1) * cslot + (size_t)gi * P;
+                A nb[V];
+                const A xl = x0 > 0 ? row[x0 - 1] : A(0);
+                const A xr = x0 + V < P ? row[x0 + V] : A(0);
 #pragma unroll
-                for (int i = 0; i < V; ++i) cc[i] = round_to<T>(k * bq1[i]);
-                const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
-                const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
-#pragma unroll
-                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cc[i - 1] : xl) + (i < V - 1 ? cc[i + 1] : xr);
+                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? k1[i - 1] : xl) + (i < V - 1 ? k1[i + 1] : xr);
                 A ym[V], yp[V];
-                load_row<T, V>(row - P + x0, ym);
-                load_row<T, V>(row + P + x0, yp);
+                load_row<A, V>(row - P + x0, ym);
+                load_row<A, V>(row + P + x0, yp);
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
                     nb[i] += ym[i];
                     nb[i] += yp[i];
-                    nb[i] += round_to<T>(k * bq0[i]);
-                    nb[i] += c1n[i];
-                    const A lc = fmaT<A>(A(6), cc[i], -nb[i]);
-                    c2p[i] = round_to<T>(fmaT<A>(k, bq1[i] - lc, cc[i]));
+                    nb[i] += k0[i];
+                    nb[i] += k2[i];
+                    const A lc = fmaT<A>(A(6), k1[i], -nb[i]);
+                    craw[i] = Store<T>::from_acc(fmaT<A>(k, b1[i] - lc, k1[i]));
+                    c2[i] = widen(craw[i]);
                 }
-                if (x0 == 0) c2p[0] = A(0);
+                if (x0 == 0) craw[0] = zero_of<T>(), c2[0] = A(0);
             } else {
 #pragma unroll
-                for (int i = 0; i < V; ++i) c2p[i] = A(0);
+                for (int i = 0; i < V; ++i) craw[i] = zero_of<T>(), c2[i] = A(0);
             }
-            store_t(c2s + (size_t)(p & 1) * cslot + (size_t)gi * P + x0, c2p);
-            if (own_row && own_plane(p)) store_t(cout + g.at(x0, y, p), c2p);
+            store_row<A, V>(c2s + (size_t)(p & 1) * cslot + (size_t)gi * P + x0, c2);
+            if (own_row && own_plane(p)) store_row<T, V>(cout + at(p), craw);
         }
         // residual of plane t on rows gi = 2 .. G-3, x weights in the thread
         if (t >= zf0) {
             A r[V];
             if (res_row) {
-                const T *row = c2s + (size_t)(t & 1) * cslot + (size_t)gi * P;
+                const A *row = c2s + (size_t)(t & 1) * cslot + (size_t)gi * P;
                 A nb[V];
-                const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
-                const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+                const A xl = x0 > 0 ? row[x0 - 1] : A(0);
+                const A xr = x0 + V < P ? row[x0 + V] : A(0);
 #pragma unroll
-                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? c2c[i - 1] : xl) + (i < V - 1 ? c2c[i + 1] : xr);
+                for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? c1[i - 1] : xl) + (i < V - 1 ? c1[i + 1] : xr);
                 A ym[V], yp[V];
-                load_row<T, V>(row - P + x0, ym);
-                load_row<T, V>(row + P + x0, yp);
+                load_row<A, V>(row - P + x0, ym);
+                load_row<A, V>(row + P + x0, yp);
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
                     nb[i] += ym[i];
                     nb[i] += yp[i];
-                    nb[i] += c2m[i];
-                    nb[i] += c2p[i];
-                    r[i] = bq0[i] - fmaT<A>(A(6), c2c[i], -nb[i]);
+                    nb[i] += c0[i];
+                    nb[i] += c2[i];
+                    r[i] = b0[i] - fmaT<A>(A(6), c1[i], -nb[i]);
                 }
                 if (x0 == 0) r[0] = A(0);
             } else {
@@ -224,15 +237,17 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
             if (x0 == 0) xq[0] = A(0);
             if (res_slot) store_row<A, VC>(rs + (size_t)(t & 1) * rslot + (size_t)(gi - 2) * RW + (x0 >> 1), xq);
         }
-        // c1 of plane t+2 for the next iteration's neighbours
-        store_t(c1s + (size_t)((t + 2) & 1) * cslot + (size_t)gi * P + x0, c1n);
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            bq0[i] = bq1[i];
-            bq1[i] = bq2[i];
-            c2m[i] = c2c[i];
-            c2c[i] = c2p[i];
-        }
+        // c1 of plane t+2 for the next step's neighbours
+        store_row<A, V>(c1s + (size_t)((t + 2) & 1) * cslot + (size_t)gi * P + x0, k2);
+    };
+
+    for (int t = tb;;) {
+        body(t, bA, bB, bC, kA, kB, kC, cA, cB, cC);
+        if (++t > zf1) break;
+        body(t, bB, bC, bA, kB, kC, kA, cB, cC, cA);
+        if (++t > zf1) break;
+        body(t, bC, bA, bB, kC, kA, kB, cC, cA, cB);
+        if (++t > zf1) break;
     }
     __syncthreads();
     if (coarse) coarse_step(zf1, zf1 & 1);
@@ -245,7 +260,7 @@ hipError_t smooth_restrict_t(int pc, int P, const double *R, const double *scal,
     const int ytiles = (Pc - 1 + s.tyc - 1) / s.tyc;
     const int blocks = ytiles * ((Pc - 1 + s.zcc - 1) / s.zcc);
     const int threads = (2 * s.tyc + 5) * (P / 8);
-    const size_t lds = smooth_restrict_lds_bytes(P, sizeof(T), s.tyc);
+    const size_t lds = smooth_restrict_lds_bytes(P, s.tyc);
 #define MG_SR(TCT)                                                                                                     \
     hipLaunchKernelGGL((k_smooth_restrict<T, TCT>), dim3(blocks), dim3(threads), lds, st, R, scal,                   \
                        static_cast<T *>(bout), static_cast<T *>(cout), static_cast<TCT *>(bc), P, s.tyc, s.zcc,     \
@@ -263,15 +278,32 @@ hipError_t smooth_restrict_t(int pc, int P, const double *R, const double *scal,
 
 }  // namespace
 
-size_t smooth_restrict_lds_bytes(int P, size_t sb, int tyc) {
-    return 4 * (size_t)(2 * tyc + 5) * P * sb + 2 * (size_t)(2 * tyc + 1) * (P / 2) * 4;
+size_t smooth_restrict_lds_bytes(int P, int tyc) {
+    return (4 * (size_t)(2 * tyc + 5) * P + 2 * (size_t)(2 * tyc + 1) * (P / 2)) * sizeof(float);
+}
+
+hipError_t smooth_restrict_prepare() {
+    static hipError_t done = [] {
+        const void *fns[] = {
+#define MG_SR_FN(T) (const void *)k_smooth_restrict<T, double>, (const void *)k_smooth_restrict<T, float>, \
+                    (const void *)k_smooth_restrict<T, f16>, (const void *)k_smooth_restrict<T, bf16>
+            MG_SR_FN(float), MG_SR_FN(f16), MG_SR_FN(bf16)
+#undef MG_SR_FN
+        };
+        for (const void *f : fns) {
+            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }();
+    return done;
 }
 
 bool smooth_restrict_ok(int P, int prec, const RShape &s) {
     if (prec == P_F64 || P < 16 || P / 8 > 64 || 64 % (P / 8) != 0) return false;
     if (s.tyc < 1 || s.tyc > P / 2 - 1 || s.zcc < 1 || s.zcc > P / 2 - 1) return false;
     if ((2 * s.tyc + 5) * (P / 8) > 768) return false;  // the kernel's launch bound
-    return smooth_restrict_lds_bytes(P, prec_bytes(prec), s.tyc) <= 65536;
+    return smooth_restrict_lds_bytes(P, s.tyc) <= kLdsMax;
 }
 
 hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
