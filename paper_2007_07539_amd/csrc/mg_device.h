@@ -64,6 +64,15 @@ __device__ __forceinline__ float f64_to_f32_odd_for_f16(double d) {
     return (float)__longlong_as_double((long long)((u & 0xFFFFFFFF00000000ull) | kept));
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (workgroup b to XCD b mod 8).
+// Renumber them so that each XCD takes a contiguous range of tiles and
+// neighbouring tiles share that XCD's L2: the k-th workgroup of XCD j gets
+// j q + min(j, r) + k, where nb = 8 q + r (a bijection of 0 .. nb-1).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, j = b & 7;
+    return j * q + min(j, r) + (b >> 3);
+}
+
 // Round an accumulator value into storage format T (nearest even).
 template <class T> struct Store;
 template <> struct Store<double> {

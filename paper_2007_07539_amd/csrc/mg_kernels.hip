@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void k_stencil(F f, E e, int P, int zc, int nc
         // blocks are dealt round-robin to the 8 XCDs: give each XCD a
         // contiguous range of tiles so neighbouring rows share an L2
         const long nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+        blk = xcd_block(blk, nb);
     }
     stencil_body<D, V>(f, e, P, zc, nchunks, blk, red, (long)blockIdx.x);
 }
@@ -898,7 +898,7 @@ __global__ __launch_bounds__(1024) void k_march(F f_in, E e, int P, int TY, int 
         // blocks are dealt round-robin to the 8 XCDs: give each XCD a
         // contiguous range of tiles so neighbouring rows share an L2
         const int nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+        blk = xcd_block(blk, nb);
     }
     march_body<V, F, E, DP>(f_in, e, P, TY, zc, ytiles, blk, (long)blockIdx.x, smem_raw, red);
 }
@@ -1243,7 +1243,7 @@ __global__ __launch_bounds__(1024) void k_restrict2(const TF *__restrict__ b, co
     int blk = blockIdx.x;
     if (xcd) {
         const int nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+        blk = xcd_block(blk, nb);
     }
     restrict2_body<V, TF, TC, XSH, DP>(b, c, bc, P, tyc, zcc, ytiles, blk, smem_raw);
 }

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
     int blk = blockIdx.x;
     if (xcd) {
         const int nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+        blk = xcd_block(blk, nb);
     }
     const int ytile = blk % ytiles, zch = blk / ytiles;
     const int Y0 = 1 + ytile * tyc;

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, 
     int blk = blockIdx.x;
     if (xcd) {
         const int nb = gridDim.x;
-        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+        blk = xcd_block(blk, nb);
     }
     const int yt = blk % ytiles, zch = blk / ytiles;
     const int y0 = 1 + yt * TY;
