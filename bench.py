@@ -87,10 +87,35 @@ def kernel_table(prof, level=0):
     return agg
 
 
-def extra_workloads(torch, mgir, W, dev, steps):
+def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=True):
     """Throughput of the batched and many-right-hand-side solves (FP16 V-cycles
-    and the FP64 solve of the same problems), each with inputs resident in HBM."""
+    and the FP64 solve of the same problems), and the paper's other precision
+    variants on the main problem, each with inputs resident in HBM."""
     res = {}
+    if bt is not None:
+        # Table 2's variants beside the main FP16 map: all-FP16 including the
+        # base (H_MG), FP16 -> FP32 -> FP64 (HSD) and FP64 -> FP32 -> FP16 with
+        # the residual rescaled into the FP16 levels (DSH)
+        L = W.levels_for(n)
+        entry = {}
+        for name, kw in (("h_mg", {}), ("hsd", {}), ("dsh", {"rescale_half": True})):
+            log(f"[bench] variant {name} at {n}^3")
+            s = mgir.Solver(3, n, W.precision_map(name, L), device=dev, autotune=tune, **kw)
+            u0 = torch.zeros_like(bt)
+            s.solve(bt, u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, r = s.solve(bt, u0)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            entry[name] = {"ms": ms, "iterations": r.iterations, "rel_residual": r.rel_residual,
+                           "status": r.status, "rescale_half": bool(kw), "map": W.precision_map(name, L)}
+            if ms64:
+                entry[name]["speedup_vs_f64"] = ms64 / ms
+            del s
+            torch.cuda.empty_cache()
+        res[f"variants_{n}"] = entry
 
     def timed(fn):
         fn()
@@ -246,7 +271,7 @@ def main():
         out["kernels_finest_fp64"] = {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1)}
                                       for k, v in kt64.items()}
     if not args.no_extra and not args.profile_only:
-        out["extra"] = extra_workloads(torch, mgir, W, dev, args.steps)
+        out["extra"] = extra_workloads(torch, mgir, W, dev, args.steps, bt=bt, n=n, ms64=ms64, tune=tune)
     if not args.no_cpu_baseline and not args.profile_only:
         import oracle
         oracle.build()

@@ -68,6 +68,13 @@ typedef struct {
     int use_initial_guess;   /* 0: ir_solve starts from u = 0 (default); 1: from the given u */
     int use_graph;           /* 1: replay one captured HIP graph per refinement step (default) */
     int autotune;            /* 1: time launch shapes at mg_bind_workspace (synchronises) */
+    int rescale_half;        /* 1: every restriction into an FP16 or BF16 level keeps the
+                                restricted residual t in the finer level's accumulator
+                                format, takes s = max|t| and stores round(t / s); the
+                                coarse correction is multiplied by s before it is
+                                prolongated (the DSH_MG residuum scaling, Section 6).
+                                Default 0.  Single-grid handles only: mg_setup_batched
+                                and mg_setup_multi reject it with MG_ERR_ARG. */
 } mg_options_t;
 
 typedef struct {

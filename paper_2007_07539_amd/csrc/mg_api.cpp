@@ -47,6 +47,8 @@ struct LevelPlan {
     int n = 0, P = 0, prec = 0;
     size_t elems = 0;
     size_t off_b = 0, off_c[2] = {0, 0};
+    bool rescale = false;  // restrictions into this level rescale (half-precision level, rescale_half)
+    size_t off_t = 0;      // its restricted residual / scaled correction in the finer accumulator format
     Shape shs[3];   // kernel families: SH_SMOOTH (first pre-smoothing), SH_SWEEP, SH_PROLONG
     Shape osh;      // refinement update (finest level only)
     RShape rsh;     // residual + restriction onto the next level
@@ -67,6 +69,7 @@ struct mg_ctx {
     mg_options_t opt{};
     std::vector<LevelPlan> lv;
     size_t off_R = 0, off_U = 0, off_part = 0, off_scal = 0, ws_need = 0;
+    size_t off_rs = 0, off_rpart = 0;  // per-level {s, 1/s} and the partial maxima of the rescaling
     int max_parts = 0;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -134,6 +137,11 @@ double *Rbuf(mg_ctx *h) { return at_ws<double>(h, h->off_R); }
 double *Ubuf(mg_ctx *h) { return at_ws<double>(h, h->off_U); }
 double *part(mg_ctx *h) { return at_ws<double>(h, h->off_part); }
 double *scal(mg_ctx *h) { return at_ws<double>(h, h->off_scal); }
+double *rscal(mg_ctx *h, int l) { return at_ws<double>(h, h->off_rs) + 2 * l; }
+// accumulator format of level l's arithmetic (the format a rescaled
+// restriction out of level l keeps before the cast)
+int acc_prec(int prec) { return prec == P_F64 ? P_F64 : P_F32; }
+bool half_prec(int prec) { return prec == P_F16 || prec == P_BF16; }
 
 long points(int D, int n) { return D == 3 ? (long)n * n * n : (long)n * n; }
 
@@ -267,6 +275,20 @@ hipError_t enq_restrict(mg_ctx *h, hipStream_t st, int l, const void *b) {
     LevelPlan &L = h->lv[l], &C = h->lv[l + 1];
     const double N = (double)points(h->dim, L.n);
     const double bytes = N * 2 * sb(L.prec) + (double)points(h->dim, C.n) * sb(C.prec);
+    if (C.rescale) {
+        // restrict in the fine accumulator format, then s = max |t| and the
+        // cast of t / s into the half-precision level
+        const int pa = acc_prec(L.prec);
+        const double Nc = (double)points(h->dim, C.n);
+        void *t = h->ws + C.off_t;
+        RUN(h, st, "resid_restrict", l, N * 2 * sb(L.prec) + Nc * sb(pa),
+            launch_restrict(h->dim, L.prec, pa, L.P, b, cbuf(h, l, h->cur[l]), t, L.rsh, st));
+        RUN(h, st, "rescale_max", l + 1, Nc * sb(pa),
+            launch_absmax(pa, t, (long)C.elems, at_ws<double>(h, h->off_rpart), rscal(h, l + 1), st));
+        RUN(h, st, "rescale_cast", l + 1, Nc * (sb(pa) + sb(C.prec)),
+            launch_scale_cast(pa, C.prec, t, rscal(h, l + 1), bbuf(h, l + 1), (long)C.elems, st));
+        return hipSuccess;
+    }
     RUN(h, st, "resid_restrict", l, bytes,
         launch_restrict(h->dim, L.prec, C.prec, L.P, b, cbuf(h, l, h->cur[l]), bbuf(h, l + 1), L.rsh, st));
     return hipSuccess;
@@ -284,6 +306,19 @@ hipError_t enq_prolong(mg_ctx *h, hipStream_t st, int l, const void *b) {
     const double N = (double)points(h->dim, L.n);
     const double bytes = N * 3 * sb(L.prec) + (double)points(h->dim, C.n) * sb(C.prec);
     const int cur = h->cur[l];
+    if (C.rescale) {
+        // the coarse correction times s, in the fine accumulator format
+        const int pa = acc_prec(L.prec);
+        const double Nc = (double)points(h->dim, C.n);
+        void *t = h->ws + C.off_t;
+        RUN(h, st, "rescale_widen", l + 1, Nc * (sb(C.prec) + sb(pa)),
+            launch_scale_widen(C.prec, pa, cbuf(h, l + 1, h->cur[l + 1]), rscal(h, l + 1), t, (long)C.elems, st));
+        RUN(h, st, "prolong_sweep", l, N * 3 * sb(L.prec) + Nc * sb(pa),
+            launch_prolong(h->dim, L.prec, pa, L.P, cbuf(h, l, cur), t, b, cbuf(h, l, cur ^ 1), h->opt.omega, true,
+                           L.shs[SH_PROLONG], st));
+        h->cur[l] = cur ^ 1;
+        return hipSuccess;
+    }
     RUN(h, st, "prolong_sweep", l, bytes,
         launch_prolong(h->dim, L.prec, C.prec, L.P, cbuf(h, l, cur), cbuf(h, l + 1, h->cur[l + 1]), b,
                        cbuf(h, l, cur ^ 1), h->opt.omega, true, L.shs[SH_PROLONG], st));
@@ -352,6 +387,8 @@ int tail_level(const mg_ctx *h) {
         if (P > (prec == P_F64 ? 8 : 16)) continue;
         bool same = true;
         for (int j = l; j < nl - 1; ++j) same = same && h->lv[j].prec == prec;
+        // the fused coarse end has no rescaled restriction inside it
+        for (int j = l + 1; j < nl; ++j) same = same && !h->lv[j].rescale;
         if (!same) continue;
         const size_t lds = tail_lds_bytes(prec, h->lv[nl - 1].prec, P, nl - 1 - l);
         if (lds > 0 && lds <= 65536) return l;
@@ -409,6 +446,7 @@ bool fusion_possible(mg_ctx *h) {
 // of the scaled residual and the restriction of their result.
 bool fusion_sr_possible(mg_ctx *h) {
     return h->fuse_sr_on && !h->batched && !h->nrhs && h->dim == 3 && h->nl >= 2 && h->opt.nu1 == 2 &&
+           !h->lv[1].rescale &&
            !finest_alias(h) && smooth_restrict_ok(h->lv[0].P, h->lv[0].prec, h->srsh);
 }
 
@@ -703,6 +741,7 @@ void mg_default_options(mg_options_t *o) {
     o->use_initial_guess = 0;
     o->use_graph = 1;
     o->autotune = 0;
+    o->rescale_half = 0;
 }
 
 const char *mg_status_string(mg_status_t s) {
@@ -798,6 +837,19 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     off += align_up((size_t)maxp * 2 * sizeof(double), 256);
     h->off_scal = off;
     off += 256;
+    if (o.rescale_half) {
+        for (int l = 1; l < m; ++l) {
+            LevelPlan &C = h->lv[l];
+            if (!half_prec(C.prec)) continue;
+            C.rescale = true;
+            C.off_t = off;
+            off += align_up(C.elems * prec_bytes(acc_prec(h->lv[l - 1].prec)), 256);
+        }
+        h->off_rs = off;
+        off += align_up((size_t)2 * m * sizeof(double), 256);
+        h->off_rpart = off;
+        off += align_up(rescale_part_count() * sizeof(double), 256);
+    }
     h->ws_need = off;
     if (m > 1) {
         set_fused(h, true);
@@ -1621,6 +1673,7 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
     mg_options_t o;
     mg_default_options(&o);
     if (opt) o = *opt;
+    if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
     if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
         return fail(MG_ERR_ARG, "batched solves need 2 <= nu1 <= 16 and 1 <= nu2 <= 16");
     if (!(o.omega > 0.0 && o.omega < 2.0) || o.max_iter < 0 || !(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "bad options");
@@ -1968,6 +2021,7 @@ mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_pr
     mg_options_t o;
     mg_default_options(&o);
     if (opt) o = *opt;
+    if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
     if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
         return fail(MG_ERR_ARG, "many right-hand sides need 2 <= nu1 <= 16 and 1 <= nu2 <= 16");
     if (!(o.omega > 0.0 && o.omega < 2.0) || o.max_iter < 0 || !(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "bad options");

@@ -105,6 +105,15 @@ bool smooth_restrict_ok(int P, int prec, const RShape &s);
 hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
                                   void *cout, void *bc, double omega, const RShape &s, hipStream_t st);
 
+// Residual rescaling on restriction into a half-precision level.  pa is the
+// fine level's accumulator format (P_F64 or P_F32), prec the coarse level's
+// (P_F16 or P_BF16); n counts padded elements.  part needs
+// rescale_part_count() doubles; rs receives {s, 1/s}.
+size_t rescale_part_count();
+hipError_t launch_absmax(int pa, const void *t, long n, double *part, double *rs, hipStream_t st);
+hipError_t launch_scale_cast(int pa, int prec, const void *t, const double *rs, void *out, long n, hipStream_t st);
+hipError_t launch_scale_widen(int prec, int pa, const void *c, const double *rs, void *out, long n, hipStream_t st);
+
 // Fused coarse end of a 3-D V-cycle in one workgroup (LDS-resident levels):
 // nlev grids of format prec with pitches P0 = 4 * 2^(nlev-1), ..., 4, then the
 // one-point base of format pb.  b: right-hand side of the first (padded, pitch

@@ -40,7 +40,8 @@ class MgError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("residual_scaling", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("use_initial_guess", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("use_initial_guess", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("rescale_half", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -138,7 +139,7 @@ class Solver:
 
     def __init__(self, dim: int, n: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
                  max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False,
-                 device=None, stream=None):
+                 rescale_half=False, device=None, stream=None):
         self.lib = load()
         self.dim, self.n = dim, n
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -147,6 +148,7 @@ class Solver:
         o.residual_scaling, o.max_iter, o.rtol = int(bool(residual_scaling)), max_iter, rtol
         o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), \
             int(bool(autotune))
+        o.rescale_half = int(bool(rescale_half))
         self.options = o
         self._h = ctypes.c_void_p()
         m = int(n + 1).bit_length() - 1

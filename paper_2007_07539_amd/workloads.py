@@ -91,12 +91,22 @@ def precision_map(name: str, nlevels: int) -> list[str]:
     level, which is solved in FP64.  h_mg: FP16 on every level including the
     base (the paper's all-half variant, Table 2).  hsd: FP16 on the finest two
     levels, FP32 on the next three, FP64 below (fine-to-coarse FP16 -> FP32 ->
-    FP64, Table 2).
+    FP64, Table 2).  dsh: FP64 down to the third-coarsest level, FP32 on that
+    one and FP16 on the last two (fine-to-coarse FP64 -> FP32 -> FP16, Table 2,
+    with the level split the paper's Section 6 gives); run it with
+    rescale_half.
     """
     if name in (F64, F32, F16, BF16):
         return [name] * (nlevels - 1) + [F64]
     if name == "h_mg":
         return [F16] * nlevels
+    if name == "dsh":
+        # FP64 fine levels, one FP32 level, FP16 on the last two (the paper's
+        # DSH_MG: FP16 base and level 1, FP32 level 2, FP64 above)
+        out = [F64] * nlevels
+        for i, p in zip(range(nlevels - 1, max(nlevels - 4, -1), -1), (F16, F16, F32)):
+            out[i] = p
+        return out
     if name == "hsd":
         out = []
         for i in range(nlevels):

@@ -175,3 +175,30 @@ def test_multi_setup_validation_and_workspace(lib):
         assert lib.ir_solve_multi(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == mgir.MG_ERR_STATE
     finally:
         lib.mg_destroy(h)
+
+
+def test_rescale_half_option(lib):
+    """Per-level rescaling: off by default, adds the scaled-residual buffers of
+    the half-precision levels to the workspace, single-grid handles only."""
+    assert mgir.default_options().rescale_half == 0
+    dsh = (ctypes.c_int * 5)(0, 0, 1, 2, 2)  # 31^3: FP64, FP64, FP32, FP16, FP16
+    sizes = []
+    for flag in (0, 1):
+        o = mgir.default_options()
+        o.rescale_half = flag
+        h = ctypes.c_void_p()
+        assert lib.mg_setup(ctypes.byref(h), 3, 31, 0, dsh, ctypes.byref(o)) == mgir.MG_OK
+        nb = ctypes.c_size_t()
+        assert lib.mg_workspace_size(h, ctypes.byref(nb)) == mgir.MG_OK
+        sizes.append(nb.value)
+        assert lib.mg_destroy(h) == mgir.MG_OK
+    # levels 3^3 and 1 in FP16: their FP32 / FP16 accumulator copies (padded,
+    # 256-byte aligned) plus {s, 1/s} per level and the partial maxima
+    assert sizes[1] > sizes[0]
+    o = mgir.default_options()
+    o.rescale_half = 1
+    h = ctypes.c_void_p()
+    ns = (ctypes.c_int * 2)(15, 31)
+    assert lib.mg_setup_batched(ctypes.byref(h), 3, 2, ns, dsh, ctypes.byref(o)) == mgir.MG_ERR_ARG
+    assert b"rescale_half" in lib.mg_last_error()
+    assert lib.mg_setup_multi(ctypes.byref(h), 3, 31, 8, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
