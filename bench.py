@@ -117,6 +117,36 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
             torch.cuda.empty_cache()
         res[f"variants_{n}"] = entry
 
+        # the paper's test axes: manufactured solutions k = 1, 20, 400 from a
+        # random initial guess in [0, 1] (Section 6), FP16 map against FP64
+        u0 = torch.from_numpy(W.random_initial_guess(3, n, seed=11)).to(dev)
+        solvers = {"f16": mgir.Solver(3, n, W.precision_map("f16", L), device=dev, autotune=tune,
+                                      use_initial_guess=True),
+                   "f64": mgir.Solver(3, n, W.precision_map("f64", L), residual_scaling=False, device=dev,
+                                      autotune=tune, use_initial_guess=True)}
+        entry = {}
+        for k in (1, 20, 400):
+            bk = torch.from_numpy(W.manufactured_rhs(3, n, k)).to(dev)
+            e = {}
+            for name, s in solvers.items():
+                log(f"[bench] axis k={k}, map {name}")
+                u = u0.clone()
+                s.solve(bk, u)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    u.copy_(u0)
+                    _, r = s.solve(bk, u)
+                torch.cuda.synchronize()
+                e[name] = {"ms": (time.perf_counter() - t0) / steps * 1e3, "iterations": r.iterations,
+                           "rel_residual": r.rel_residual, "status": r.status}
+            e["speedup_f16_vs_f64"] = e["f64"]["ms"] / e["f16"]["ms"]
+            entry[f"k{k}"] = e
+            del bk
+        del solvers, u0
+        torch.cuda.empty_cache()
+        res[f"axes_{n}_random_u0"] = entry
+
     def timed(fn):
         fn()
         torch.cuda.synchronize()

@@ -63,6 +63,20 @@ def poisson3d_sine_noise_rhs(n: int = 511, seed: int = 3, noise: float = 1e-3) -
     return f
 
 
+def manufactured_rhs(dim: int, n: int, k: int) -> np.ndarray:
+    """f = dim (k pi)^2 prod_d sin(k pi x_d): the right-hand side whose
+    continuous solution is the paper's test function prod_d sin(k pi x_d)
+    (Section 5; the measurements use k = 1, 20 and 400)."""
+    return dim * (k * np.pi) ** 2 * sine_mode(dim, n, (k, k, k))
+
+
+def random_initial_guess(dim: int, n: int, seed: int) -> np.ndarray:
+    """u0 i.i.d. uniform[0, 1], the initial guess of the paper's measurements
+    (Section 6): one rng.uniform(0, 1, n^dim) draw, x fastest."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, n**dim).reshape((n,) * dim)
+
+
 def batched_instances(count: int = 64, sizes=(63, 127, 255), seed: int = 4):
     """Independent 3-D instances: first ``rng.choice(sizes, count)`` draws the
     sizes, then one ``rng.uniform(-1, 1, n_i^3)`` per instance in order."""
