@@ -147,6 +147,29 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
         torch.cuda.empty_cache()
         res[f"axes_{n}_random_u0"] = entry
 
+        # several V-cycles per refinement step (the inner iteration the paper's
+        # conclusion points to): fewer FP64 updates per solve
+        entry = {}
+        for name, m in (("f16", 2), ("f16", 3), ("f64", 2)):
+            log(f"[bench] {m} V-cycles per step, map {name}")
+            s = mgir.Solver(3, n, W.precision_map(name, L), residual_scaling=name != "f64", device=dev,
+                            autotune=tune, cycles_per_step=m)
+            u0 = torch.zeros_like(bt)
+            s.solve(bt, u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, r = s.solve(bt, u0)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            entry[f"{name}_m{m}"] = {"ms": ms, "steps": r.iterations, "v_cycles": r.iterations * m,
+                                     "rel_residual": r.rel_residual, "status": r.status}
+            if ms64:
+                entry[f"{name}_m{m}"]["speedup_vs_f64_m1"] = ms64 / ms
+            del s
+            torch.cuda.empty_cache()
+        res[f"cycles_per_step_{n}"] = entry
+
     def timed(fn):
         fn()
         torch.cuda.synchronize()

@@ -63,7 +63,7 @@ typedef struct {
     double omega;            /* damped-Jacobi weight, default 0.8 */
     int residual_scaling;    /* 1: alpha = ||r||_inf before the cast (Algorithm 2);
                                 0: alpha = 1 (the FP64 baseline omits scaling, Section 6) */
-    int max_iter;            /* V-cycles at most, default 100 */
+    int max_iter;            /* refinement steps at most, default 100 */
     double rtol;             /* stop when ||r||_2 <= rtol * ||b||_2 (FP64), default 1e-10 */
     int use_initial_guess;   /* 0: ir_solve starts from u = 0 (default); 1: from the given u */
     int use_graph;           /* 1: replay one captured HIP graph per refinement step (default) */
@@ -75,10 +75,17 @@ typedef struct {
                                 prolongated (the DSH_MG residuum scaling, Section 6).
                                 Default 0.  Single-grid handles only: mg_setup_batched
                                 and mg_setup_multi reject it with MG_ERR_ARG. */
+    int cycles_per_step;     /* V-cycles per refinement step, 1..16 (default 1, Algorithm 2).
+                                Each further cycle continues from the correction so far
+                                (nu1 sweeps from it, then the usual cycle) on the same
+                                scaled residual, before u and r are updated once (the
+                                inner iteration the paper's conclusion points to).
+                                ir_solve then counts steps in max_iter and iterations.
+                                Single-grid handles only, as rescale_half. */
 } mg_options_t;
 
 typedef struct {
-    int iterations;          /* V-cycles applied */
+    int iterations;          /* refinement steps applied (V-cycles when cycles_per_step = 1) */
     double rel_residual;     /* ||b - A u||_2 / ||b||_2 of the returned u, recomputed in FP64 */
     double seconds;          /* host wall time of the call, to the final synchronisation */
     double *history;         /* optional caller-owned host array: ||r_k||_2/||b||_2, k = 0.. */

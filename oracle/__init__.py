@@ -40,6 +40,7 @@ class _IrOpts(ctypes.Structure):
         ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
         ("residual_scaling", ctypes.c_int), ("recursive_residual", ctypes.c_int),
         ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("use_initial_guess", ctypes.c_int),
+        ("cycles", ctypes.c_int),
     ]
 
 
@@ -171,14 +172,16 @@ class IrResult:
 
 
 def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
-             recursive_residual=False, max_iter=100, rtol=1e-10) -> IrResult:
+             recursive_residual=False, max_iter=100, rtol=1e-10, cycles=1) -> IrResult:
     """Iterative refinement with residuum scaling and one V-cycle per step
-    (Algorithm 2), all in FP64.  Stops when ||r||_2 <= rtol ||b||_2."""
+    (Algorithm 2), all in FP64.  Stops when ||r||_2 <= rtol ||b||_2.  With
+    cycles > 1 each step applies that many V-cycles to the scaled residual
+    equation, each continuing from the correction so far."""
     b = _f64(b)
     dim, n = _shape(b)
     u = np.zeros_like(b) if u0 is None else _f64(u0).copy()
     opts = _IrOpts(int(nu1), int(nu2), float(omega), int(bool(residual_scaling)),
-                   int(bool(recursive_residual)), int(max_iter), float(rtol), int(u0 is not None))
+                   int(bool(recursive_residual)), int(max_iter), float(rtol), int(u0 is not None), int(cycles))
     res = _IrResult()
     hist = np.zeros(max_iter + 2)
     st = _load().ref_ir_solve(dim, n, _ptr(b), _ptr(u), ctypes.byref(opts), ctypes.byref(res),

@@ -247,6 +247,9 @@ typedef struct {
     int max_iter;
     double rtol;               /* stop when ||r||_2 <= rtol ||b||_2 */
     int use_initial_guess;     /* 0: u starts at zero */
+    int cycles;                /* V-cycles per refinement step (<= 1: one, as in Algorithm 2);
+                                  each further cycle continues from the correction so far:
+                                  c <- c + V(r/alpha - A c) */
 } ref_ir_opts;
 
 typedef struct {
@@ -271,11 +274,17 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         if (history && hist_cap > 0) history[0] = 0.0;
         return REF_OK;
     }
+    const int cycles = o->cycles > 1 ? o->cycles : 1;
     double *r = (double *)malloc(sizeof(double) * N);
     double *rl = (double *)malloc(sizeof(double) * N);
     double *c = (double *)malloc(sizeof(double) * N);
     double *ac = (double *)malloc(sizeof(double) * N);
-    if (!r || !rl || !c || !ac) { free(r); free(rl); free(c); free(ac); return REF_ERR_NOMEM; }
+    double *t = cycles > 1 ? (double *)malloc(sizeof(double) * N) : NULL;
+    double *e = cycles > 1 ? (double *)malloc(sizeof(double) * N) : NULL;
+    if (!r || !rl || !c || !ac || (cycles > 1 && (!t || !e))) {
+        free(r); free(rl); free(c); free(ac); free(t); free(e);
+        return REF_ERR_NOMEM;
+    }
 
     if (!o->use_initial_guess) memset(u, 0, sizeof(double) * N);
     ref_residual(dim, n, b, u, r);        /* r_high := b_high - A_high u_high */
@@ -292,6 +301,11 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         double inv_alpha = 1.0 / alpha;
         for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];        /* scale */
         int vs = ref_vcycle(dim, n, o->nu1, o->nu2, o->omega, rl, c);  /* one V-cycle */
+        for (int j = 1; j < cycles && vs == REF_OK; j++) {              /* further cycles */
+            ref_residual(dim, n, rl, c, t);                             /* t = r/alpha - A c */
+            vs = ref_vcycle(dim, n, o->nu1, o->nu2, o->omega, t, e);
+            for (long p = 0; p < N; p++) c[p] += e[p];
+        }
         if (vs != REF_OK) { st = vs; break; }
         for (long p = 0; p < N; p++) u[p] += alpha * c[p];             /* update u */
         if (o->recursive_residual) {                                   /* update r */
@@ -305,6 +319,6 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
     res->iterations = k;
     ref_residual(dim, n, b, u, ac);
     res->true_rel_residual = ref_norm2(ac, N) / nb;
-    free(r); free(rl); free(c); free(ac);
+    free(r); free(rl); free(c); free(ac); free(t); free(e);
     return st;
 }

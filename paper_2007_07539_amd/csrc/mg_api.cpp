@@ -343,8 +343,22 @@ hipError_t enq_post(mg_ctx *h, hipStream_t st, int l, const void *b, bool skip_l
 enum RhsMode { RHS_B = 0, RHS_SCALED_R = 1, RHS_ALIAS_R = 2 };
 
 // Pre-smoothing of level l and restriction of its residual to level l + 1.
-hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const void *rhs) {
+// warm: the finest level continues from its current correction (a further
+// V-cycle of the same refinement step) with nu1 plain sweeps.
+hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const void *rhs, bool warm = false) {
     hipError_t e;
+    if (l == 0 && warm) {
+        LevelPlan &L = h->lv[0];
+        const double N = (double)points(h->dim, L.n);
+        for (int k = 0; k < h->opt.nu1; ++k) {
+            const int cur = h->cur[0];
+            RUN(h, st, "sweep", 0, N * 3 * sb(L.prec),
+                launch_sweep(h->dim, L.prec, L.P, rhs, cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), h->opt.omega,
+                             L.shs[SH_SWEEP], st));
+            h->cur[0] = cur ^ 1;
+        }
+        return enq_restrict(h, st, 0, rhs);
+    }
     if (l == 0 && mode == RHS_SCALED_R && h->fused_sr) {
         LevelPlan &L = h->lv[0], &C = h->lv[1];
         const double N = (double)points(h->dim, L.n);
@@ -396,10 +410,10 @@ int tail_level(const mg_ctx *h) {
     return nl - 1;
 }
 
-hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
+// One V-cycle.  warm: the finest level starts from its current correction;
+// skip0: its last post-sweep is left to the fused sweep + update.
+hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode, bool warm = false, bool skip0 = false) {
     const int nl = h->nl;
-    // inside a refinement step the last finest-level sweep runs fused with the update
-    const bool skip0 = mode == RHS_SCALED_R && h->fused;
     std::vector<const void *> rhs(nl);
     for (int l = 0; l < nl; ++l) rhs[l] = bbuf(h, l);
     if (mode == RHS_ALIAS_R) rhs[0] = Rbuf(h);
@@ -408,7 +422,7 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
     if (lt < nl - 1) {
         // levels 0 .. lt-1 as separate launches, lt .. base fused
         for (int l = 0; l < lt; ++l) {
-            if ((e = enq_vcycle_down(h, st, mode, l, rhs[l])) != hipSuccess) return e;
+            if ((e = enq_vcycle_down(h, st, mode, l, rhs[l], warm)) != hipSuccess) return e;
         }
         const LevelPlan &T = h->lv[lt];
         RUN(h, st, "coarse_tail", lt, 0.0,
@@ -422,7 +436,7 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode) {
         return hipSuccess;
     }
     for (int l = 0; l < nl - 1; ++l) {
-        if ((e = enq_vcycle_down(h, st, mode, l, rhs[l])) != hipSuccess) return e;
+        if ((e = enq_vcycle_down(h, st, mode, l, rhs[l], warm)) != hipSuccess) return e;
     }
     if ((e = enq_coarse(h, st, nl - 1)) != hipSuccess) return e;
     for (int l = nl - 2; l >= 0; --l) {
@@ -461,8 +475,19 @@ void set_fused(mg_ctx *h, bool on) {
 // One refinement step of Algorithm 2 (scale and cast, V-cycle, update) plus
 // the norm readback.
 // The V-cycle part of a refinement step (writes only level vectors).
+// The V-cycles of one refinement step: the first from the scaled residual
+// (or, for the FP64 baseline, the residual itself) and zero, each further one
+// from the correction so far on the same right-hand side.  Inside a step the
+// last finest-level sweep of the last cycle runs fused with the update.
 hipError_t enq_cycle(mg_ctx *h, hipStream_t st) {
-    return enq_vcycle(h, st, finest_alias(h) ? RHS_ALIAS_R : RHS_SCALED_R);
+    const bool alias = finest_alias(h);
+    const int m = std::max(1, h->opt.cycles_per_step);
+    for (int j = 0; j < m; ++j) {
+        const RhsMode mode = alias ? RHS_ALIAS_R : j == 0 ? RHS_SCALED_R : RHS_B;
+        const hipError_t e = enq_vcycle(h, st, mode, j > 0, j == m - 1 && !alias && h->fused);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // The update part: u, r, norms, alpha, and the norm readback (with the fused
@@ -742,6 +767,7 @@ void mg_default_options(mg_options_t *o) {
     o->use_graph = 1;
     o->autotune = 0;
     o->rescale_half = 0;
+    o->cycles_per_step = 1;
 }
 
 const char *mg_status_string(mg_status_t s) {
@@ -781,6 +807,8 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(MG_ERR_ARG, "omega must be in (0, 2)");
     if (o.max_iter < 0) return fail(MG_ERR_ARG, "max_iter must be >= 0");
     if (!(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "rtol must be >= 0");
+    if (o.cycles_per_step < 1 || o.cycles_per_step > 16)
+        return fail(MG_ERR_ARG, "cycles_per_step must be in 1..16 (got %d)", o.cycles_per_step);
     std::vector<int> prec(m, P_F64);
     if (level_prec)
         for (int i = 0; i < m; ++i) {
@@ -1674,6 +1702,8 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
     mg_default_options(&o);
     if (opt) o = *opt;
     if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
+    if (o.cycles_per_step != 1)
+        return fail(MG_ERR_ARG, "cycles_per_step other than 1 is only available on single-grid handles");
     if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
         return fail(MG_ERR_ARG, "batched solves need 2 <= nu1 <= 16 and 1 <= nu2 <= 16");
     if (!(o.omega > 0.0 && o.omega < 2.0) || o.max_iter < 0 || !(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "bad options");
@@ -2022,6 +2052,8 @@ mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_pr
     mg_default_options(&o);
     if (opt) o = *opt;
     if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
+    if (o.cycles_per_step != 1)
+        return fail(MG_ERR_ARG, "cycles_per_step other than 1 is only available on single-grid handles");
     if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
         return fail(MG_ERR_ARG, "many right-hand sides need 2 <= nu1 <= 16 and 1 <= nu2 <= 16");
     if (!(o.omega > 0.0 && o.omega < 2.0) || o.max_iter < 0 || !(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "bad options");

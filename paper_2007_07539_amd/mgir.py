@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("residual_scaling", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("use_initial_guess", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("rescale_half", ctypes.c_int)]
+                ("rescale_half", ctypes.c_int), ("cycles_per_step", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -139,7 +139,7 @@ class Solver:
 
     def __init__(self, dim: int, n: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
                  max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False,
-                 rescale_half=False, device=None, stream=None):
+                 rescale_half=False, cycles_per_step=1, device=None, stream=None):
         self.lib = load()
         self.dim, self.n = dim, n
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -149,6 +149,7 @@ class Solver:
         o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), \
             int(bool(autotune))
         o.rescale_half = int(bool(rescale_half))
+        o.cycles_per_step = int(cycles_per_step)
         self.options = o
         self._h = ctypes.c_void_p()
         m = int(n + 1).bit_length() - 1

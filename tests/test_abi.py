@@ -202,3 +202,20 @@ def test_rescale_half_option(lib):
     assert lib.mg_setup_batched(ctypes.byref(h), 3, 2, ns, dsh, ctypes.byref(o)) == mgir.MG_ERR_ARG
     assert b"rescale_half" in lib.mg_last_error()
     assert lib.mg_setup_multi(ctypes.byref(h), 3, 31, 8, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
+
+
+def test_cycles_per_step_option(lib):
+    assert mgir.default_options().cycles_per_step == 1
+    h = ctypes.c_void_p()
+    for bad in (0, 17, -1):
+        o = mgir.default_options()
+        o.cycles_per_step = bad
+        assert lib.mg_setup(ctypes.byref(h), 3, 31, 0, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
+        assert b"cycles_per_step" in lib.mg_last_error()
+    o = mgir.default_options()
+    o.cycles_per_step = 3
+    assert lib.mg_setup(ctypes.byref(h), 3, 31, 0, None, ctypes.byref(o)) == mgir.MG_OK
+    assert lib.mg_destroy(h) == mgir.MG_OK
+    ns = (ctypes.c_int * 2)(15, 31)
+    assert lib.mg_setup_batched(ctypes.byref(h), 3, 2, ns, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
+    assert lib.mg_setup_multi(ctypes.byref(h), 3, 31, 8, None, ctypes.byref(o)) == mgir.MG_ERR_ARG

@@ -304,3 +304,20 @@ def test_fp16_flush_without_scaling():
     q = (r * (1 / a)).astype(np.float16)
     assert np.abs(q).max() == 1.0
     assert np.count_nonzero(q) > 0.999 * r.size
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_cycles_per_step_equal_repeated_steps(ref, m):
+    """A step of m V-cycles, each continuing from the correction so far on the
+    same scaled residual, equals m one-cycle steps: the damped-Jacobi V-cycle is
+    affine, V(c; f) = c + V(0; f - A c), and linear in f, so the scaling by
+    alpha cancels (up to rounding)."""
+    b = W.uniform_rhs(3, 15, seed=14)
+    one = ref.ir_solve(b, max_iter=1, cycles=m)
+    rep = ref.ir_solve(b, max_iter=m)
+    assert one.status == -6 and rep.status == -6 and one.iterations == 1 and rep.iterations == m
+    assert np.abs(one.u - rep.u).max() <= 1e-13 * np.abs(rep.u).max()
+    full1 = ref.ir_solve(b)
+    fullm = ref.ir_solve(b, cycles=m)
+    assert fullm.status == 0 and fullm.true_rel_residual <= 1e-10
+    assert fullm.iterations == -(-full1.iterations // m)
