@@ -40,7 +40,8 @@ class _IrOpts(ctypes.Structure):
         ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
         ("residual_scaling", ctypes.c_int), ("recursive_residual", ctypes.c_int),
         ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("use_initial_guess", ctypes.c_int),
-        ("cycles", ctypes.c_int),
+        ("cycles", ctypes.c_int), ("base_n", ctypes.c_int), ("base_tol", ctypes.c_double),
+        ("base_max_iter", ctypes.c_int),
     ]
 
 
@@ -66,6 +67,9 @@ def _load():
         lib.ref_restrict.argtypes = [i, i, dp, dp]
         lib.ref_prolong.argtypes = [i, i, dp, dp]
         lib.ref_vcycle.argtypes, lib.ref_vcycle.restype = [i, i, i, i, ctypes.c_double, dp, dp], i
+        lib.ref_vcycle_base.argtypes = [i, i, i, i, i, ctypes.c_double, ctypes.c_double, i, dp, dp]
+        lib.ref_vcycle_base.restype = i
+        lib.ref_cg.argtypes, lib.ref_cg.restype = [i, i, dp, dp, ctypes.c_double, i], i
         lib.ref_norm2.argtypes, lib.ref_norm2.restype = [dp, ctypes.c_long], ctypes.c_double
         lib.ref_norminf.argtypes, lib.ref_norminf.restype = [dp, ctypes.c_long], ctypes.c_double
         lib.ref_ir_solve.argtypes = [i, i, dp, dp, ctypes.POINTER(_IrOpts), ctypes.POINTER(_IrResult), dp, i]
@@ -136,12 +140,35 @@ def prolong(e):
     return out
 
 
-def vcycle(b, nu1=2, nu2=2, omega=0.8):
-    """One V-cycle from a zero initial guess (Algorithm 1, recursive), physical units."""
+def base_max_iter_default(dim: int, n_base: int) -> int:
+    """CG steps allowed on the base level when none are given: its unknowns
+    (where exact-arithmetic CG terminates), at most 10000."""
+    return min(10000, n_base**dim)
+
+
+def cg(b, tol, max_iter=None):
+    """Conjugate gradients for A x = b from x = 0 (the base solver of Section
+    4.2), until ||r||_2 <= tol; returns (x, steps)."""
+    b = _f64(b)
+    dim, n = _shape(b)
+    x = np.empty_like(b)
+    k = _load().ref_cg(dim, n, _ptr(b), _ptr(x), float(tol),
+                       int(base_max_iter_default(dim, n) if max_iter is None else max_iter))
+    if k < 0:
+        raise ValueError(f"ref_cg failed with status {k}")
+    return x, k
+
+
+def vcycle(b, nu1=2, nu2=2, omega=0.8, base_n=1, base_tol=1e-4, base_max_iter=None):
+    """One V-cycle from a zero initial guess (Algorithm 1, recursive), physical
+    units, down to the base level of base_n points per dimension (one point:
+    exact; more: CG to base_tol)."""
     b = _f64(b)
     dim, n = _shape(b)
     c = np.empty_like(b)
-    st = _load().ref_vcycle(dim, n, int(nu1), int(nu2), float(omega), _ptr(b), _ptr(c))
+    mi = base_max_iter_default(dim, base_n) if base_max_iter is None else base_max_iter
+    st = _load().ref_vcycle_base(dim, n, int(base_n), int(nu1), int(nu2), float(omega), float(base_tol), int(mi),
+                                 _ptr(b), _ptr(c))
     if st != OK:
         raise ValueError(f"ref_vcycle failed with status {st}")
     return c
@@ -172,7 +199,8 @@ class IrResult:
 
 
 def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
-             recursive_residual=False, max_iter=100, rtol=1e-10, cycles=1) -> IrResult:
+             recursive_residual=False, max_iter=100, rtol=1e-10, cycles=1, base_n=1, base_tol=1e-4,
+             base_max_iter=None) -> IrResult:
     """Iterative refinement with residuum scaling and one V-cycle per step
     (Algorithm 2), all in FP64.  Stops when ||r||_2 <= rtol ||b||_2.  With
     cycles > 1 each step applies that many V-cycles to the scaled residual
@@ -181,7 +209,9 @@ def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
     dim, n = _shape(b)
     u = np.zeros_like(b) if u0 is None else _f64(u0).copy()
     opts = _IrOpts(int(nu1), int(nu2), float(omega), int(bool(residual_scaling)),
-                   int(bool(recursive_residual)), int(max_iter), float(rtol), int(u0 is not None), int(cycles))
+                   int(bool(recursive_residual)), int(max_iter), float(rtol), int(u0 is not None), int(cycles),
+                   int(base_n), float(base_tol),
+                   int(base_max_iter_default(dim, base_n) if base_max_iter is None else base_max_iter))
     res = _IrResult()
     hist = np.zeros(max_iter + 2)
     st = _load().ref_ir_solve(dim, n, _ptr(b), _ptr(u), ctypes.byref(opts), ctypes.byref(res),

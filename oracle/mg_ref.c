@@ -177,18 +177,66 @@ static void ref_base_solve(int dim, int n, const double *b, double *c) {
     c[0] = b[0] / (2.0 * dim / (h * h));
 }
 
+/* Conjugate gradients for A x = b on the level with n points per dimension
+ * (the paper's base solver, Section 4.2), from x = 0: with r = b, p = r,
+ *   q = A p,  a = (r.r)/(p.q),  x += a p,  r -= a q,
+ *   p = r + ((r.r)_new/(r.r)) p,
+ * until ||r||_2 <= tol (absolute, as the paper states it) or max_iter steps.
+ * Returns the steps taken. */
+int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter) {
+    long N = ref_points(dim, n);
+    double *r = (double *)malloc(sizeof(double) * N);
+    double *p = (double *)malloc(sizeof(double) * N);
+    double *q = (double *)malloc(sizeof(double) * N);
+    if (!r || !p || !q) { free(r); free(p); free(q); return REF_ERR_NOMEM; }
+    memset(x, 0, sizeof(double) * N);
+    memcpy(r, b, sizeof(double) * N);
+    memcpy(p, b, sizeof(double) * N);
+    double rr = 0.0;
+    for (long i = 0; i < N; i++) rr += r[i] * r[i];
+    int k = 0;
+    while (k < max_iter && sqrt(rr) > tol) {
+        ref_apply_A(dim, n, p, q);
+        double pq = 0.0;
+        for (long i = 0; i < N; i++) pq += p[i] * q[i];
+        if (!(pq > 0.0)) break;                      /* p = 0 (or breakdown) */
+        double a = rr / pq;
+        for (long i = 0; i < N; i++) { x[i] += a * p[i]; r[i] -= a * q[i]; }
+        double rr_new = 0.0;
+        for (long i = 0; i < N; i++) rr_new += r[i] * r[i];
+        double beta = rr_new / rr;
+        for (long i = 0; i < N; i++) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        k++;
+    }
+    free(r); free(p); free(q);
+    return k;
+}
+
 /* One V-cycle for A_l c = b on the level with n points per dimension
- * (Algorithm 1 applied recursively, Section 4.2), starting from c = 0:
+ * (Algorithm 1 applied recursively, Section 4.2), starting from c = 0, down
+ * to the base level of n_base points per dimension (n_base = 1: the exact
+ * one-point solve; otherwise CG to base_tol, at most base_max_iter steps):
  *   1. pre-smooth nu1 times,
  *   2. residual, restrict to the coarse grid,
  *   3. coarse correction by the same cycle one level down (exact on 1 point),
  *   4. prolongate and add,
  *   5. post-smooth nu2 times.
  * Returns REF_OK or an error code. */
-int ref_vcycle(int dim, int n, int nu1, int nu2, double omega, const double *b, double *c) {
-    if ((dim != 2 && dim != 3) || !ref_valid_n(n) || nu1 < 0 || nu2 < 0) return REF_ERR_ARG;
+int ref_vcycle_base(int dim, int n, int n_base, int nu1, int nu2, double omega, double base_tol,
+                    int base_max_iter, const double *b, double *c) {
+    if ((dim != 2 && dim != 3) || !ref_valid_n(n) || !ref_valid_n(n_base) || n_base > n || nu1 < 0 || nu2 < 0)
+        return REF_ERR_ARG;
     long N = ref_points(dim, n);
-    if (n == 1) { ref_base_solve(dim, n, b, c); return REF_OK; }
+    if (n == n_base) {
+        if (n == 1) {
+            ref_base_solve(dim, n, b, c);
+        } else {
+            int k = ref_cg(dim, n, b, c, base_tol, base_max_iter);
+            if (k < 0) return k;
+        }
+        return REF_OK;
+    }
     int n_c = (n - 1) / 2;
     long Nc = ref_points(dim, n_c);
     double *tmp = (double *)malloc(sizeof(double) * N);
@@ -203,7 +251,7 @@ int ref_vcycle(int dim, int n, int nu1, int nu2, double omega, const double *b, 
     }
     ref_residual(dim, n, b, c, tmp);                /* residual, restrict */
     ref_restrict(dim, n, tmp, bc);
-    int st = ref_vcycle(dim, n_c, nu1, nu2, omega, bc, ec);   /* coarse correction */
+    int st = ref_vcycle_base(dim, n_c, n_base, nu1, nu2, omega, base_tol, base_max_iter, bc, ec);
     if (st == REF_OK) {
         ref_prolong(dim, n_c, ec, tmp);             /* prolongate, add */
         for (long p = 0; p < N; p++) c[p] += tmp[p];
@@ -214,6 +262,10 @@ int ref_vcycle(int dim, int n, int nu1, int nu2, double omega, const double *b, 
     }
     free(tmp); free(bc); free(ec);
     return st;
+}
+
+int ref_vcycle(int dim, int n, int nu1, int nu2, double omega, const double *b, double *c) {
+    return ref_vcycle_base(dim, n, 1, nu1, nu2, omega, 0.0, 0, b, c);
 }
 
 /* Pairwise sum of squares (accurate Euclidean norm). */
@@ -250,6 +302,9 @@ typedef struct {
     int cycles;                /* V-cycles per refinement step (<= 1: one, as in Algorithm 2);
                                   each further cycle continues from the correction so far:
                                   c <- c + V(r/alpha - A c) */
+    int base_n;                /* points per dimension of the base level (<= 1: one point) */
+    double base_tol;           /* CG on a base of more than one point: ||r||_2 <= base_tol */
+    int base_max_iter;         /* ... at most this many steps */
 } ref_ir_opts;
 
 typedef struct {
@@ -275,6 +330,8 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         return REF_OK;
     }
     const int cycles = o->cycles > 1 ? o->cycles : 1;
+    const int nbase = o->base_n > 1 ? o->base_n : 1;
+    if (!ref_valid_n(nbase) || nbase > n) return REF_ERR_ARG;
     double *r = (double *)malloc(sizeof(double) * N);
     double *rl = (double *)malloc(sizeof(double) * N);
     double *c = (double *)malloc(sizeof(double) * N);
@@ -300,10 +357,11 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         double alpha = o->residual_scaling ? ref_norminf(r, N) : 1.0;
         double inv_alpha = 1.0 / alpha;
         for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];        /* scale */
-        int vs = ref_vcycle(dim, n, o->nu1, o->nu2, o->omega, rl, c);  /* one V-cycle */
+        int vs = ref_vcycle_base(dim, n, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter, rl,
+                                 c);                                    /* one V-cycle */
         for (int j = 1; j < cycles && vs == REF_OK; j++) {              /* further cycles */
             ref_residual(dim, n, rl, c, t);                             /* t = r/alpha - A c */
-            vs = ref_vcycle(dim, n, o->nu1, o->nu2, o->omega, t, e);
+            vs = ref_vcycle_base(dim, n, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter, t, e);
             for (long p = 0; p < N; p++) c[p] += e[p];
         }
         if (vs != REF_OK) { st = vs; break; }

@@ -63,15 +63,15 @@ def jacobi_iteration_matrix(dim, n, omega):
     return np.eye(A.shape[0]) - omega * A / np.diag(A)[:, None]
 
 
-def vcycle_matrix(dim, n, nu1=2, nu2=2, omega=0.8):
+def vcycle_matrix(dim, n, nu1=2, nu2=2, omega=0.8, base_n=1):
     """Dense V-cycle operator M with c = M b, from the two-grid error propagation
     E = S^nu2 (I - P M_c R A) S^nu1 and M = (I - E) A^-1, recursively down to
-    the exact one-point solve M_0 = A_0^-1."""
+    the exact solve on the base level of base_n points per dimension."""
     A = lap(dim, n)
-    if n == 1:
+    if n == base_n:
         return np.linalg.inv(A)
     nc = (n - 1) // 2
-    Mc = vcycle_matrix(dim, nc, nu1, nu2, omega)
+    Mc = vcycle_matrix(dim, nc, nu1, nu2, omega, base_n)
     S = jacobi_iteration_matrix(dim, n, omega)
     R, P = restrict(dim, n), prolong(dim, nc)
     I = np.eye(A.shape[0])

@@ -321,3 +321,46 @@ def test_cycles_per_step_equal_repeated_steps(ref, m):
     fullm = ref.ir_solve(b, cycles=m)
     assert fullm.status == 0 and fullm.true_rel_residual <= 1e-10
     assert fullm.iterations == -(-full1.iterations // m)
+
+
+# --- base solver on a multi-point base level ------------------------------------
+
+@pytest.mark.parametrize("dim,n", [(2, 7), (2, 15), (3, 3), (3, 7)])
+def test_cg_matches_dense_solve(ref, dim, n):
+    b = W.uniform_rhs(dim, n, seed=30 + n)
+    x, k = ref.cg(b, 1e-13 * np.linalg.norm(b))
+    exact = np.linalg.solve(dense_ref.lap(dim, n), b.ravel())
+    assert np.abs(x.ravel() - exact).max() <= 1e-11 * np.abs(exact).max()
+    assert k <= n**dim
+
+
+def test_cg_stops_at_the_absolute_tolerance(ref):
+    """The paper's base solver stops once ||b - A x||_2 < 1e-4 (absolute)."""
+    b = W.uniform_rhs(3, 7, seed=33)
+    A = dense_ref.lap(3, 7)
+    x, k = ref.cg(b, 1e-4)
+    assert k > 1 and np.linalg.norm(b.ravel() - A @ x.ravel()) <= 1e-4 * (1 + 1e-9)
+    x1, k1 = ref.cg(b, 1e-4, max_iter=k - 1)
+    assert k1 == k - 1 and np.linalg.norm(b.ravel() - A @ x1.ravel()) > 1e-4
+
+
+@pytest.mark.parametrize("dim,n,base", [(2, 15, 3), (2, 15, 7), (3, 7, 3)])
+def test_vcycle_with_base_level_matches_dense(ref, dim, n, base):
+    """A V-cycle stopping at a multi-point base level whose CG is run to a tight
+    tolerance is the two-grid recursion with an exact base solve."""
+    N = n**dim
+    M = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1
+        M[:, j] = ref.vcycle(e.reshape((n,) * dim), base_n=base, base_tol=1e-15).ravel()
+    Md = dense_ref.vcycle_matrix(dim, n, base_n=base)
+    np.testing.assert_allclose(M, Md, rtol=0, atol=1e-12 * np.abs(Md).max())
+
+
+def test_ir_with_cg_base_reaches_tolerance(ref):
+    b = W.uniform_rhs(3, 31, seed=34)
+    full = ref.ir_solve(b)
+    part = ref.ir_solve(b, base_n=7)
+    assert part.status == 0 and part.true_rel_residual <= 1e-10
+    assert abs(part.iterations - full.iterations) <= 2
