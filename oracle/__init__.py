@@ -148,7 +148,7 @@ def base_max_iter_default(dim: int, n_base: int) -> int:
 
 def cg(b, tol, max_iter=None):
     """Conjugate gradients for A x = b from x = 0 (the base solver of Section
-    4.2), until ||r||_2 <= tol; returns (x, steps)."""
+    4.2), until ||r||_2 <= tol ||b||_2; returns (x, steps)."""
     b = _f64(b)
     dim, n = _shape(b)
     x = np.empty_like(b)

@@ -181,7 +181,10 @@ static void ref_base_solve(int dim, int n, const double *b, double *c) {
  * (the paper's base solver, Section 4.2), from x = 0: with r = b, p = r,
  *   q = A p,  a = (r.r)/(p.q),  x += a p,  r -= a q,
  *   p = r + ((r.r)_new/(r.r)) p,
- * until ||r||_2 <= tol (absolute, as the paper states it) or max_iter steps.
+ * until ||r||_2 <= tol ||b||_2 or max_iter steps (the paper's 1e-4 is an
+ * absolute bound on residuals that the scaling has brought to norm one; taken
+ * relative to the base right-hand side, the test means the same there and does
+ * not switch the base solve off once an unscaled residual is small).
  * Returns the steps taken. */
 int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter) {
     long N = ref_points(dim, n);
@@ -194,8 +197,9 @@ int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter)
     memcpy(p, b, sizeof(double) * N);
     double rr = 0.0;
     for (long i = 0; i < N; i++) rr += r[i] * r[i];
+    const double stop = tol * sqrt(rr);
     int k = 0;
-    while (k < max_iter && sqrt(rr) > tol) {
+    while (k < max_iter && sqrt(rr) > stop) {
         ref_apply_A(dim, n, p, q);
         double pq = 0.0;
         for (long i = 0; i < N; i++) pq += p[i] * q[i];

@@ -328,20 +328,23 @@ def test_cycles_per_step_equal_repeated_steps(ref, m):
 @pytest.mark.parametrize("dim,n", [(2, 7), (2, 15), (3, 3), (3, 7)])
 def test_cg_matches_dense_solve(ref, dim, n):
     b = W.uniform_rhs(dim, n, seed=30 + n)
-    x, k = ref.cg(b, 1e-13 * np.linalg.norm(b))
+    x, k = ref.cg(b, 1e-13)
     exact = np.linalg.solve(dense_ref.lap(dim, n), b.ravel())
     assert np.abs(x.ravel() - exact).max() <= 1e-11 * np.abs(exact).max()
     assert k <= n**dim
 
 
-def test_cg_stops_at_the_absolute_tolerance(ref):
-    """The paper's base solver stops once ||b - A x||_2 < 1e-4 (absolute)."""
-    b = W.uniform_rhs(3, 7, seed=33)
+@pytest.mark.parametrize("scale", [1.0, 1e-9])
+def test_cg_stops_at_the_tolerance(ref, scale):
+    """The base solver stops at the first step with ||b - A x||_2 <= 1e-4 ||b||_2,
+    whatever the size of b."""
+    b = scale * W.uniform_rhs(3, 7, seed=33)
     A = dense_ref.lap(3, 7)
+    nb = np.linalg.norm(b)
     x, k = ref.cg(b, 1e-4)
-    assert k > 1 and np.linalg.norm(b.ravel() - A @ x.ravel()) <= 1e-4 * (1 + 1e-9)
+    assert k > 1 and np.linalg.norm(b.ravel() - A @ x.ravel()) <= 1e-4 * nb * (1 + 1e-6)
     x1, k1 = ref.cg(b, 1e-4, max_iter=k - 1)
-    assert k1 == k - 1 and np.linalg.norm(b.ravel() - A @ x1.ravel()) > 1e-4
+    assert k1 == k - 1 and np.linalg.norm(b.ravel() - A @ x1.ravel()) > 1e-4 * nb
 
 
 @pytest.mark.parametrize("dim,n,base", [(2, 15, 3), (2, 15, 7), (3, 7, 3)])
@@ -360,7 +363,8 @@ def test_vcycle_with_base_level_matches_dense(ref, dim, n, base):
 
 def test_ir_with_cg_base_reaches_tolerance(ref):
     b = W.uniform_rhs(3, 31, seed=34)
-    full = ref.ir_solve(b)
-    part = ref.ir_solve(b, base_n=7)
-    assert part.status == 0 and part.true_rel_residual <= 1e-10
-    assert abs(part.iterations - full.iterations) <= 2
+    for scaling in (True, False):
+        full = ref.ir_solve(b, residual_scaling=scaling)
+        part = ref.ir_solve(b, residual_scaling=scaling, base_n=7)
+        assert part.status == 0 and part.true_rel_residual <= 1e-10
+        assert abs(part.iterations - full.iterations) <= 2
