@@ -82,6 +82,11 @@ typedef struct {
                                 inner iteration the paper's conclusion points to).
                                 ir_solve then counts steps in max_iter and iterations.
                                 Single-grid handles only, as rescale_half. */
+    double base_tol;         /* base level of more than one point (nlevels < m): CG until
+                                ||b - L x||_2 <= base_tol ||b||_2 (default 1e-4, the
+                                paper's bound for residuals scaled to norm one,
+                                Section 4.2) */
+    int base_max_iter;       /* ... at most this many CG steps; 0: min(10000, base points) */
 } mg_options_t;
 
 typedef struct {
@@ -102,11 +107,13 @@ void mg_default_options(mg_options_t *opt);
  *   n          interior points per dimension, 2^m - 1 with 2 <= m <= 12 in
  *              2-D and 2 <= m <= 10 in 3-D (n >= 3: the finest level is
  *              smoothed and restricted at least once).
- *   nlevels    0 for the full hierarchy n, (n-1)/2, ..., 1 (m levels);
- *              otherwise it must equal m (a partial hierarchy would need a
- *              base solver other than the exact one-point solve).
- *   level_prec m entries, FINEST FIRST: level_prec[0] is the finest grid
- *              (the paper's level L), level_prec[m-1] the one-point base
+ *   nlevels    0 for the full hierarchy n, (n-1)/2, ..., 1 (m levels, the
+ *              one-point base solved exactly); 2..m for the first nlevels of
+ *              it, whose last level (2^(m-nlevels+1) - 1 points per
+ *              dimension) is solved by CG (Section 4.2; opt.base_tol,
+ *              opt.base_max_iter).
+ *   level_prec one entry per level used, FINEST FIRST: level_prec[0] is the
+ *              finest grid (the paper's level L), the last entry the base
  *              level (the paper's level 0).  NULL means all MG_F64.
  *   opt        NULL for defaults.
  * No device memory is allocated: query mg_workspace_size, allocate, then

@@ -35,6 +35,7 @@ def _stale(obj, srcs):
 SOURCES = (("mg_kernels.hip", True), ("mg_multi.hip", True), ("mg_tail.hip", True), ("mg_sweep_update.hip", True),
            ("mg_smooth_restrict.hip", True),
            ("mg_rescale.hip", True),
+           ("mg_cg.hip", True),
            ("mg_api.cpp", False))
 
 

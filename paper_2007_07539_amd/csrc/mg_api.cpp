@@ -47,6 +47,7 @@ struct LevelPlan {
     int n = 0, P = 0, prec = 0;
     size_t elems = 0;
     size_t off_b = 0, off_c[2] = {0, 0};
+    size_t off_cg = 0;     // CG vectors of a multi-point base level
     bool rescale = false;  // restrictions into this level rescale (half-precision level, rescale_half)
     size_t off_t = 0;      // its restricted residual / scaled correction in the finer accumulator format
     Shape shs[3];   // kernel families: SH_SMOOTH (first pre-smoothing), SH_SWEEP, SH_PROLONG
@@ -296,6 +297,16 @@ hipError_t enq_restrict(mg_ctx *h, hipStream_t st, int l, const void *b) {
 
 hipError_t enq_coarse(mg_ctx *h, hipStream_t st, int l) {
     LevelPlan &L = h->lv[l];
+    if (L.n > 1) {
+        // CG on a base level of more than one point (Section 4.2)
+        const long N = (long)points(h->dim, L.n);
+        const int maxit = h->opt.base_max_iter > 0 ? h->opt.base_max_iter : (int)std::min<long>(10000, N);
+        RUN(h, st, "cg_base", l, (double)N * 2 * sb(L.prec),
+            launch_cg_base(h->dim, L.prec, L.n, L.P, bbuf(h, l), cbuf(h, l, 0), h->ws + L.off_cg,
+                           cg_scratch_stride(L.prec, L.elems), h->opt.base_tol, maxit, st));
+        h->cur[l] = 0;
+        return hipSuccess;
+    }
     RUN(h, st, "coarse_solve", l, 2 * sb(L.prec), launch_coarse(h->dim, L.prec, bbuf(h, l), cbuf(h, l, 0), st));
     h->cur[l] = 0;
     return hipSuccess;
@@ -395,7 +406,7 @@ hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const
 // from which all levels above the base share one format and fit in LDS.
 int tail_level(const mg_ctx *h) {
     const int nl = h->nl;
-    if (!h->tail_on || h->dim != 3 || nl < 3) return nl - 1;
+    if (!h->tail_on || h->dim != 3 || nl < 3 || h->lv[nl - 1].n > 1) return nl - 1;
     for (int l = 1; l < nl - 1; ++l) {
         const int P = h->lv[l].P, prec = h->lv[l].prec;
         if (P > (prec == P_F64 ? 8 : 16)) continue;
@@ -768,6 +779,8 @@ void mg_default_options(mg_options_t *o) {
     o->autotune = 0;
     o->rescale_half = 0;
     o->cycles_per_step = 1;
+    o->base_tol = 1e-4;
+    o->base_max_iter = 0;
 }
 
 const char *mg_status_string(mg_status_t s) {
@@ -797,11 +810,14 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         return fail(MG_ERR_SHAPE, "3-D grids are limited to n <= 1023 (one block must hold three fine rows)");
     int m = 0;
     while ((1 << m) < n + 1) ++m;
-    if (nlevels != 0 && nlevels != m)
-        return fail(MG_ERR_ARG, "nlevels must be 0 or %d (the full hierarchy down to one point), got %d", m, nlevels);
+    if (nlevels != 0 && (nlevels < 2 || nlevels > m))
+        return fail(MG_ERR_ARG, "nlevels must be 0 (the full hierarchy, %d levels) or 2..%d, got %d", m, m, nlevels);
+    if (nlevels) m = nlevels;  // from here on m counts the levels used
     mg_options_t o;
     mg_default_options(&o);
     if (opt) o = *opt;
+    if (!(o.base_tol >= 0.0) || o.base_max_iter < 0)
+        return fail(MG_ERR_ARG, "base_tol must be >= 0 and base_max_iter >= 0");
     if (o.nu1 < 1 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
         return fail(MG_ERR_ARG, "nu1 and nu2 must be in 1..16 (got %d, %d)", o.nu1, o.nu2);
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(MG_ERR_ARG, "omega must be in (0, 2)");
@@ -843,6 +859,11 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
             L.rsh = pick_rshape(dim, L.P, L.prec);
         }
         nn = (nn - 1) / 2;
+    }
+    if (h->lv[m - 1].n > 1) {
+        LevelPlan &B = h->lv[m - 1];
+        B.off_cg = off;
+        off += 4 * cg_scratch_stride(B.prec, B.elems);
     }
     const size_t fin = align_up(h->lv[0].elems * sizeof(double), 256);
     h->off_R = off;

@@ -110,6 +110,11 @@ hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, cons
 // (P_F16 or P_BF16); n counts padded elements.  part needs
 // rescale_part_count() doubles; rs receives {s, 1/s}.
 size_t rescale_part_count();
+// CG base solve (base of n >= 3 points per dimension, level format prec);
+// scratch holds x, r, p, q at cg_scratch_stride(prec, elems) bytes apart.
+size_t cg_scratch_stride(int prec, size_t elems);
+hipError_t launch_cg_base(int D, int prec, int n, int P, const void *b, void *c, void *scratch, size_t stride,
+                          double tol, int max_iter, hipStream_t st);
 hipError_t launch_absmax(int pa, const void *t, long n, double *part, double *rs, hipStream_t st);
 hipError_t launch_scale_cast(int pa, int prec, const void *t, const double *rs, void *out, long n, hipStream_t st);
 hipError_t launch_scale_widen(int prec, int pa, const void *c, const double *rs, void *out, long n, hipStream_t st);

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("residual_scaling", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("use_initial_guess", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("rescale_half", ctypes.c_int), ("cycles_per_step", ctypes.c_int)]
+                ("rescale_half", ctypes.c_int), ("cycles_per_step", ctypes.c_int), ("base_tol", ctypes.c_double),
+                ("base_max_iter", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -139,7 +140,8 @@ class Solver:
 
     def __init__(self, dim: int, n: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
                  max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False,
-                 rescale_half=False, cycles_per_step=1, device=None, stream=None):
+                 rescale_half=False, cycles_per_step=1, nlevels=0, base_tol=1e-4, base_max_iter=0,
+                 device=None, stream=None):
         self.lib = load()
         self.dim, self.n = dim, n
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -150,16 +152,19 @@ class Solver:
             int(bool(autotune))
         o.rescale_half = int(bool(rescale_half))
         o.cycles_per_step = int(cycles_per_step)
+        o.base_tol, o.base_max_iter = float(base_tol), int(base_max_iter)
         self.options = o
         self._h = ctypes.c_void_p()
         m = int(n + 1).bit_length() - 1
+        if nlevels:
+            m = int(nlevels)
         if level_prec is None:
             level_prec = ["f64"] * m
         self.level_prec = list(level_prec)
         if len(self.level_prec) != m:
             raise ValueError(f"level_prec needs {m} entries (finest first), got {len(self.level_prec)}")
         arr = (ctypes.c_int * m)(*[PREC[p] for p in self.level_prec])
-        _check(self.lib.mg_setup(ctypes.byref(self._h), dim, n, 0, arr, ctypes.byref(o)), "mg_setup")
+        _check(self.lib.mg_setup(ctypes.byref(self._h), dim, n, int(nlevels), arr, ctypes.byref(o)), "mg_setup")
         nb = ctypes.c_size_t()
         _check(self.lib.mg_workspace_size(self._h, ctypes.byref(nb)), "mg_workspace_size")
         self.workspace_bytes = nb.value

@@ -55,7 +55,8 @@ def test_setup_rejects_bad_options_and_maps(lib):
     o = mgir.default_options()
     o.omega = 2.5
     assert lib.mg_setup(ctypes.byref(h), 3, 31, 0, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
-    assert lib.mg_setup(ctypes.byref(h), 3, 31, 3, None, None) == mgir.MG_ERR_ARG   # partial hierarchy
+    assert lib.mg_setup(ctypes.byref(h), 3, 31, 1, None, None) == mgir.MG_ERR_ARG   # no coarse level
+    assert lib.mg_setup(ctypes.byref(h), 3, 31, 6, None, None) == mgir.MG_ERR_ARG   # deeper than 31 -> 1
     bad = (ctypes.c_int * 5)(0, 2, 7, 1, 0)
     assert lib.mg_setup(ctypes.byref(h), 3, 31, 0, bad, None) == mgir.MG_ERR_PREC
     assert lib.mg_setup(None, 3, 31, 0, None, None) == mgir.MG_ERR_ARG
@@ -219,3 +220,24 @@ def test_cycles_per_step_option(lib):
     ns = (ctypes.c_int * 2)(15, 31)
     assert lib.mg_setup_batched(ctypes.byref(h), 3, 2, ns, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
     assert lib.mg_setup_multi(ctypes.byref(h), 3, 31, 8, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
+
+
+def test_partial_hierarchy_setup(lib):
+    """nlevels < m stops at a multi-point base level solved by CG; the level map
+    then has nlevels entries and the workspace holds the CG vectors."""
+    o = mgir.default_options()
+    assert (o.base_tol, o.base_max_iter) == (1e-4, 0)
+    h = ctypes.c_void_p()
+    prec = (ctypes.c_int * 3)(2, 2, 0)  # 31^3 FP16, 15^3 FP16, 7^3 FP64 base
+    assert lib.mg_setup(ctypes.byref(h), 3, 31, 3, prec, None) == mgir.MG_OK
+    try:
+        nl, nb = ctypes.c_int(), ctypes.c_int()
+        assert lib.mg_levels(h, ctypes.byref(nl)) == 0 and nl.value == 3
+        assert lib.mg_level_n(h, 2, ctypes.byref(nb)) == 0 and nb.value == 7
+        ws = ctypes.c_size_t()
+        assert lib.mg_workspace_size(h, ctypes.byref(ws)) == mgir.MG_OK
+        assert ws.value >= 4 * 10 * 8 * 8 * 8  # x, r, p, q of the padded 7^3 base in FP64
+    finally:
+        assert lib.mg_destroy(h) == mgir.MG_OK
+    o.base_tol = -1.0
+    assert lib.mg_setup(ctypes.byref(h), 3, 31, 3, prec, ctypes.byref(o)) == mgir.MG_ERR_ARG
