@@ -2115,7 +2115,7 @@ mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_pr
     const size_t fin = align_up(h->lv[0].elems * sizeof(double), 256);
     h->off_R = off, off += fin;
     h->off_U = off, off += fin;
-    h->m_upd_blocks = m_stencil_blocks(h->lv[0].prec, h->lv[0].P, K, h->lv[0].osh.zc);
+    h->m_upd_blocks = m_update_blocks(h->lv[0].prec, h->lv[0].P, K, h->lv[0].osh.zc);
     h->max_parts = std::max(h->m_upd_blocks, m_resid_blocks(n));
     h->off_part = off, off += align_up((size_t)h->max_parts * K * 2 * sizeof(double), 256);
     h->off_scal = off, off += align_up(4 * sizeof(double) * K, 256);

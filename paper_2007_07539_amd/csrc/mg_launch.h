@@ -190,6 +190,7 @@ enum { MS_SMOOTH2 = 0, MS_SWEEP = 1 };
 int m_vec(int prec);
 bool m_supported(int prec, int K);
 int m_stencil_blocks(int prec, int P, int K, int zc);
+int m_update_blocks(int prec, int P, int K, int zc);  // workgroups (and partials) of the update
 int m_resid_blocks(int n);
 hipError_t launch_m_stage(int kind, const MArgs &a, hipStream_t st);
 hipError_t launch_m_update(const MArgs &a, double *R, double *U, const double *alpha, double h2, double *part,

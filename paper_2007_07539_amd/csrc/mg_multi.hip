@@ -277,6 +277,98 @@ template <int V> __device__ __forceinline__ MMap mmap(int P, int K, int zc, int 
     return m;
 }
 
+// Row-segment decomposition of the stencil kernels: a workgroup owns up to
+// segx consecutive interior points of one row (all K columns) and a chunk of
+// planes; thread t holds columns (t mod KC) V .. of point xs + t div KC.  The
+// plane being swept passes through LDS (two slots), so the x neighbours come
+// from the neighbouring threads (from memory only at the segment ends): three
+// field reads per point and plane instead of five.  The thread count is
+// rounded up to whole waves (the spare threads compute nothing that is kept).
+struct MSeg {
+    int segx, nseg, threads;
+};
+__host__ __device__ inline MSeg mseg_shape(int V, int P, int K, int maxthr = 1024) {
+    const int KC = K / V;
+    MSeg s;
+    s.segx = (P - 1) < maxthr / KC ? (P - 1) : maxthr / KC;
+    s.nseg = (P - 1 + s.segx - 1) / s.segx;
+    s.threads = (s.segx * KC + 63) / 64 * 64;
+    return s;
+}
+
+struct MSegMap {
+    int x, y, kc, k0, z0, z1, xs, xe;
+    bool run;  // the workgroup has planes to do (uniform)
+    bool own;  // the thread's point is one of the segment's
+};
+
+template <int V> __device__ __forceinline__ MSegMap msegmap(int P, int K, int zc, int nchunks, int maxthr = 1024) {
+    const int KC = K / V;
+    const MSeg s = mseg_shape(V, P, K, maxthr);
+    const int seg = (int)(blockIdx.x % s.nseg);
+    const long rest = blockIdx.x / s.nseg;
+    MSegMap m;
+    m.xs = 1 + seg * s.segx;
+    m.xe = min(P - 1, m.xs + s.segx - 1);
+    m.x = m.xs + (int)threadIdx.x / KC;
+    m.kc = (int)threadIdx.x % KC;
+    m.k0 = m.kc * V;
+    m.y = 1 + (int)(rest % (P - 1));
+    const int chunk = (int)(rest / (P - 1));
+    m.run = chunk < nchunks;
+    m.own = m.x <= m.xe;
+    m.z0 = 1 + chunk * zc;
+    m.z1 = min(m.z0 + zc, P);
+    return m;
+}
+
+template <int V, class F, class E>
+__device__ __forceinline__ void mstencil_seg_body(const F &f, E &e, const MGrid &g, const MSegMap &m,
+                                                  typename F::acc *lds) {
+    typedef typename F::acc A;
+    const int KC = g.K / V;
+    const int t = threadIdx.x;
+    const size_t slot = (size_t)blockDim.x * V;
+    A cm[V], cc[V], cp[V];
+    f.template get<V>(g, m.x, m.y, m.z0 - 1, m.k0, cm);
+    f.template get<V>(g, m.x, m.y, m.z0, m.k0, cc);
+    store_row<A, V>(lds + (size_t)t * V, cc);
+    __syncthreads();
+    for (int z = m.z0; z < m.z1; ++z) {
+        const int it = z - m.z0;
+        f.template get<V>(g, m.x, m.y, z + 1, m.k0, cp);
+        const A *row = lds + (size_t)(it & 1) * slot;
+        A xl[V], xr[V], ym[V], yp[V], nb[V];
+        if (m.x > m.xs)
+            load_row<A, V>(row + (size_t)(t - KC) * V, xl);
+        else
+            f.template get<V>(g, m.x - 1, m.y, z, m.k0, xl);
+        if (m.x < m.xe)
+            load_row<A, V>(row + (size_t)(t + KC) * V, xr);
+        else
+            f.template get<V>(g, m.x + 1, m.y, z, m.k0, xr);
+        f.template get<V>(g, m.x, m.y - 1, z, m.k0, ym);
+        f.template get<V>(g, m.x, m.y + 1, z, m.k0, yp);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            nb[i] = xl[i] + xr[i];
+            nb[i] += ym[i];
+            nb[i] += yp[i];
+            nb[i] += cm[i];
+            nb[i] += cp[i];
+        }
+        if (m.own) e.template emit<V>(g, m.x, m.y, z, m.k0, cc, nb);
+        // plane z+1 into the other slot: it was last read before the previous barrier
+        store_row<A, V>(lds + (size_t)((it + 1) & 1) * slot + (size_t)t * V, cp);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            cm[i] = cc[i];
+            cc[i] = cp[i];
+        }
+    }
+}
+
 template <int V, class F, class E>
 __device__ __forceinline__ void mstencil_body(const F &f, E &e, const MGrid &g, const MMap &m) {
     typedef typename F::acc A;
@@ -311,19 +403,22 @@ __device__ __forceinline__ void mstencil_body(const F &f, E &e, const MGrid &g, 
 enum { MK_SMOOTH2 = 0, MK_SMOOTH2_SCALED = 1, MK_SWEEP = 2 };
 
 template <int V, int KIND, class T, class TC>
-__global__ __launch_bounds__(256) void k_mstencil(const void *b, const double *r, const double *inv, const int *act,
-                                                  void *bout, const void *cin, const void *ec, void *cout, int P,
-                                                  int K, int zc, int nchunks, double omega) {
+__global__ __launch_bounds__(1024) void k_mstencil(const void *b, const double *r, const double *inv, const int *act,
+                                                   void *bout, const void *cin, const void *ec, void *cout, int P,
+                                                   int K, int zc, int nchunks, double omega) {
     typedef acc_t<T> A;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *lds = reinterpret_cast<A *>(smem_raw);
     const MGrid g{P, K};
-    const MMap m = mmap<V>(P, K, zc, nchunks);
+    const MSegMap m = msegmap<V>(P, K, zc, nchunks);
+    if (!m.run) return;
     const A kw = (A)(omega / 6.0);
     if constexpr (KIND == MK_SMOOTH2) {
         typedef MArr<T, A> R;
         const R rh{static_cast<const T *>(b)};
         const MJac0<T, R> f{rh, kw};
         MSweep<T, R, false> e{rh, static_cast<T *>(cout), nullptr, kw};
-        mstencil_body<V>(f, e, g, m);
+        mstencil_seg_body<V>(f, e, g, m, lds);
     } else if constexpr (KIND == MK_SMOOTH2_SCALED) {
         typedef MScaled<T, V> R;
         R rh;
@@ -335,22 +430,28 @@ __global__ __launch_bounds__(256) void k_mstencil(const void *b, const double *r
         }
         const MJac0<T, R> f{rh, kw};
         MSweep<T, R, true> e{rh, static_cast<T *>(cout), static_cast<T *>(bout), kw};
-        mstencil_body<V>(f, e, g, m);
+        mstencil_seg_body<V>(f, e, g, m, lds);
     } else {
         typedef MArr<T, A> R;
         const R f{static_cast<const T *>(cin)};
         MSweep<T, R, false> e{R{static_cast<const T *>(b)}, static_cast<T *>(cout), nullptr, kw};
-        mstencil_body<V>(f, e, g, m);
+        mstencil_seg_body<V>(f, e, g, m, lds);
     }
 }
 
+// The update holds its field and R, U in FP64: 4 columns per thread in every
+// format, at most 512 threads, so that its registers need not spill.
+constexpr int kUpdThreads = 512;
+constexpr int kUpdVec = 4;
+
 template <int V, class T>
-__global__ __launch_bounds__(256) void k_mupdate(const T *c, double *R, double *U, const double *alpha,
-                                                 const int *act, double h2, double *part, int P, int K, int zc,
-                                                 int nchunks) {
-    __shared__ double lds[8 * 64];
+__global__ __launch_bounds__(kUpdThreads) void k_mupdate(const T *c, double *R, double *U, const double *alpha,
+                                                         const int *act, double h2, double *part, int P, int K,
+                                                         int zc, int nchunks) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *lds = reinterpret_cast<double *>(smem_raw);  // the plane slots, then the column reduction
     const MGrid g{P, K};
-    const MMap m = mmap<V>(P, K, zc, nchunks);
+    const MSegMap m = msegmap<V>(P, K, zc, nchunks, kUpdThreads);
     const MArr<T, double> f{c};
     MOuter<V> e;
     e.R = R, e.U = U, e.h2 = h2, e.part = part;
@@ -359,7 +460,7 @@ __global__ __launch_bounds__(256) void k_mupdate(const T *c, double *R, double *
         e.a[i] = act[m.k0 + i] ? alpha[m.k0 + i] : 0.0;
         e.ss[i] = 0.0, e.mx[i] = 0.0;
     }
-    mstencil_body<V>(f, e, g, m);
+    if (m.run) mstencil_seg_body<V>(f, e, g, m, lds);
     e.finish(lds, K, m.kc, blockIdx.x);
 }
 
@@ -385,14 +486,16 @@ template <class TF, class A> struct MResidOut {
 };
 
 template <int V, class TF>
-__global__ __launch_bounds__(256) void k_mresid_store(const TF *b, const TF *c, acc_t<TF> *r, int P, int K, int zc,
-                                                      int nchunks) {
+__global__ __launch_bounds__(1024) void k_mresid_store(const TF *b, const TF *c, acc_t<TF> *r, int P, int K, int zc,
+                                                       int nchunks) {
     typedef acc_t<TF> A;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const MGrid g{P, K};
-    const MMap m = mmap<V>(P, K, zc, nchunks);
+    const MSegMap m = msegmap<V>(P, K, zc, nchunks);
+    if (!m.run) return;
     const MArr<TF, A> f{c};
     MResidOut<TF, A> e{b, r};
-    mstencil_body<V>(f, e, g, m);
+    mstencil_seg_body<V>(f, e, g, m, reinterpret_cast<A *>(smem_raw));
 }
 
 // Coarse point (X, Y) and V columns, marching over coarse planes; reads the
@@ -566,13 +669,27 @@ int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
     default: return hipErrorInvalidValue;                  \
     }
 
+// LDS of a row-segment kernel: two plane slots of V accumulator values per
+// thread (and room for the update's per-column reduction).
+size_t mseg_lds(int V, size_t acc, const MSeg &s, int K) {
+    return std::max((size_t)2 * s.threads * V * acc, (size_t)2 * (s.threads / 64) * K * sizeof(double));
+}
+
+// Workgroups of the pointwise prolongation (256 threads, thread t as in mmap).
+int m_flat_blocks(int prec, int P, int K, int zc) {
+    const long threads = (long)(P - 1) * (K / m_vec(prec)) * (P - 1) * cdiv(P - 1, zc);
+    return cdiv(threads, 256);
+}
+
 template <int KIND, class T, class TC>
 hipError_t mstencil_run(const MArgs &a, hipStream_t st) {
     constexpr int V = std::is_same<T, double>::value ? 4 : 8;
     const int nch = cdiv(a.P - 1, a.zc);
     const int blocks = m_stencil_blocks(a.prec, a.P, a.K, a.zc);
-    hipLaunchKernelGGL((k_mstencil<V, KIND, T, TC>), dim3(blocks), dim3(256), 0, st, a.b, a.r, a.inv, a.act, a.bout,
-                       a.cin, a.ec, a.cout, a.P, a.K, a.zc, nch, a.omega);
+    const MSeg sg = mseg_shape(V, a.P, a.K);
+    hipLaunchKernelGGL((k_mstencil<V, KIND, T, TC>), dim3(blocks), dim3(sg.threads),
+                       mseg_lds(V, sizeof(acc_t<T>), sg, a.K), st, a.b, a.r, a.inv, a.act, a.bout, a.cin, a.ec,
+                       a.cout, a.P, a.K, a.zc, nch, a.omega);
     return hipGetLastError();
 }
 
@@ -589,7 +706,9 @@ template <class TF> hipError_t mresid_store_run(const MArgs &a, void *rbuf, hipS
     constexpr int V = std::is_same<TF, double>::value ? 4 : 8;
     const int nch = cdiv(a.P - 1, a.zc);
     const int blocks = m_stencil_blocks(a.prec, a.P, a.K, a.zc);
-    hipLaunchKernelGGL((k_mresid_store<V, TF>), dim3(blocks), dim3(256), 0, st, static_cast<const TF *>(a.b),
+    const MSeg sg = mseg_shape(V, a.P, a.K);
+    hipLaunchKernelGGL((k_mresid_store<V, TF>), dim3(blocks), dim3(sg.threads),
+                       mseg_lds(V, sizeof(acc_t<TF>), sg, a.K), st, static_cast<const TF *>(a.b),
                        static_cast<const TF *>(a.cin), static_cast<acc_t<TF> *>(rbuf), a.P, a.K, a.zc, nch);
     return hipGetLastError();
 }
@@ -607,7 +726,7 @@ template <class TF, class TC> hipError_t mfw_run(const MArgs &a, const void *rbu
 template <class TF, class TC> hipError_t mprol_field_run(const MArgs &a, hipStream_t st) {
     constexpr int V = std::is_same<TF, double>::value ? 4 : 8;
     const int nch = cdiv(a.P - 1, a.zc);
-    const int blocks = m_stencil_blocks(a.prec, a.P, a.K, a.zc);
+    const int blocks = m_flat_blocks(a.prec, a.P, a.K, a.zc);
     hipLaunchKernelGGL((k_mprol_field<V, TF, TC>), dim3(blocks), dim3(256), 0, st,
                        static_cast<TF *>(const_cast<void *>(a.cin)), static_cast<const TC *>(a.ec), a.P, a.K, a.zc,
                        nch);
@@ -624,8 +743,11 @@ bool m_supported(int prec, int K) {
 }
 
 int m_stencil_blocks(int prec, int P, int K, int zc) {
-    const long threads = (long)(P - 1) * (K / m_vec(prec)) * (P - 1) * cdiv(P - 1, zc);
-    return cdiv(threads, 256);
+    return mseg_shape(m_vec(prec), P, K).nseg * (P - 1) * cdiv(P - 1, zc);
+}
+
+int m_update_blocks(int, int P, int K, int zc) {
+    return mseg_shape(kUpdVec, P, K, kUpdThreads).nseg * (P - 1) * cdiv(P - 1, zc);
 }
 
 int m_resid_blocks(int n) { return std::max(1, std::min(cdiv((long)n * n, 4), 4096)); }
@@ -643,11 +765,12 @@ hipError_t launch_m_update(const MArgs &a, double *R, double *U, const double *a
                            hipStream_t st) {
     if (!m_supported(a.prec, a.K)) return hipErrorInvalidValue;
     const int nch = cdiv(a.P - 1, a.zc);
-    const int blocks = m_stencil_blocks(a.prec, a.P, a.K, a.zc);
+    const int blocks = m_update_blocks(a.prec, a.P, a.K, a.zc);
     MG_MT(a.prec, {
-        constexpr int V = std::is_same<TT, double>::value ? 4 : 8;
-        hipLaunchKernelGGL((k_mupdate<V, TT>), dim3(blocks), dim3(256), 0, st, static_cast<const TT *>(a.cin), R, U,
-                           alpha, a.act, h2, part, a.P, a.K, a.zc, nch);
+        constexpr int V = kUpdVec;
+        const MSeg sg = mseg_shape(V, a.P, a.K, kUpdThreads);
+        hipLaunchKernelGGL((k_mupdate<V, TT>), dim3(blocks), dim3(sg.threads), mseg_lds(V, sizeof(double), sg, a.K),
+                           st, static_cast<const TT *>(a.cin), R, U, alpha, a.act, h2, part, a.P, a.K, a.zc, nch);
     });
     return hipGetLastError();
 }
