@@ -550,16 +550,89 @@ __global__ __launch_bounds__(256) void k_mfw(const A *r, TC *bc, int P, int K, i
 // c = round_TF(c + 4 P e_c) in place at every interior point.
 template <int V, class TF, class TC>
 __global__ __launch_bounds__(256) void k_mprol_field(TF *c, const TC *ec, int P, int K, int zc, int nchunks) {
+    typedef MProl<TF, TC> F;
+    typedef typename F::PA PA;
     const MGrid g{P, K};
     const MMap m = mmap<V>(P, K, zc, nchunks);
     if (!m.active) return;
-    const MProl<TF, TC> f{c, ec, P / 2};
+    // The coarse values of the (up to) 2 x 2 coarse columns around (x, y) are
+    // loaded once per coarse plane and kept for the two or three fine planes
+    // that use it (slot Z & 1), instead of once per fine plane; the sums are
+    // those of MProl::get, in its order.
+    const int Pc = P / 2;
+    const MGrid gc{Pc, K};
+    int Xs[2] = {0, 0}, Ys[2] = {0, 0};
+    const int nx = F::split(m.x, Xs), ny = F::split(m.y, Ys);
+    const PA wy = ny == 1 ? PA(1) : PA(0.5);
+    PA ce[2][2][V], co[2][2][V];  // coarse planes of even and of odd index
+    int tag_e = -1, tag_o = -1;
+    auto load_plane = [&](int Z, PA (&dst)[2][2][V]) {
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx)
+#pragma unroll
+            for (int by = 0; by < 2; ++by)
+                if (bx < nx && by < ny && Xs[bx] >= 1 && Xs[bx] < Pc && Ys[by] >= 1 && Ys[by] < Pc)
+                    load_row<TC, V>(ec + gc.at(Xs[bx], Ys[by], Z) + m.k0, dst[bx][by]);
+    };
     for (int z = m.z0; z < m.z1; ++z) {
-        acc_t<TF> v[V];
-        f.template get<V>(g, m.x, m.y, z, m.k0, v);
+        int Zs[2] = {0, 0};
+        const int nz = F::split(z, Zs);
+        const PA wz = nz == 1 ? PA(1) : PA(0.5);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (a >= nz) break;
+            const int Z = Zs[a];
+            if (Z < 1 || Z >= Pc) continue;
+            if (Z & 1) {
+                if (tag_o != Z) load_plane(Z, co), tag_o = Z;
+            } else {
+                if (tag_e != Z) load_plane(Z, ce), tag_e = Z;
+            }
+        }
+        PA p[V];
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx) {
+            if (bx >= nx) break;
+            PA s[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) s[i] = PA(0);
+#pragma unroll
+            for (int by = 0; by < 2; ++by) {
+                if (by >= ny) break;
+                PA t[V];
+#pragma unroll
+                for (int i = 0; i < V; ++i) t[i] = PA(0);
+                if (Xs[bx] >= 1 && Xs[bx] < Pc && Ys[by] >= 1 && Ys[by] < Pc) {
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        if (a >= nz) break;
+                        const int Z = Zs[a];
+                        if (Z < 1 || Z >= Pc) continue;
+                        if (Z & 1) {
+#pragma unroll
+                            for (int i = 0; i < V; ++i) t[i] += wz * co[bx][by][i];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < V; ++i) t[i] += wz * ce[bx][by][i];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < V; ++i) s[i] += wy * t[i];
+            }
+            if (bx == 0) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) p[i] = s[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < V; ++i) p[i] = PA(0.5) * (p[i] + s[i]);
+            }
+        }
+        acc_t<TF> cv[V];
+        load_row<TF, V>(c + g.at(m.x, m.y, z) + m.k0, cv);
         TF o[V];
 #pragma unroll
-        for (int i = 0; i < V; ++i) o[i] = Store<TF>::from_acc(v[i]);
+        for (int i = 0; i < V; ++i) o[i] = Store<TF>::from_acc(round_to<TF>((PA)cv[i] + PA(4) * p[i]));
         store_row<TF, V>(c + g.at(m.x, m.y, z) + m.k0, o);
     }
 }
