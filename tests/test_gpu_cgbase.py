@@ -65,3 +65,19 @@ def test_solves_with_cg_base_reach_tolerance(dev, ref, name):
     assert res.status == 0
     assert ref.norm2(ref.residual(b, u.cpu().numpy())) / ref.norm2(b) <= 1e-10
     assert res.iterations <= r64.iterations + 2
+
+
+@pytest.mark.parametrize("dim,n,nl", [(3, 63, 4), (2, 255, 5)])
+def test_options_compose(dev, ref, dim, n, nl):
+    """A CG base in FP16 reached through rescaled restrictions (DSH-type map),
+    with two V-cycles per step: every option on at once still solves to the
+    tolerance, within two steps of the FP64 solve of the same hierarchy."""
+    print(f"composed options dim={dim} n={n} nl={nl}", flush=True)
+    b = W.uniform_rhs(dim, n, seed=160)
+    bt = torch.from_numpy(b).to(dev)
+    _, r64 = mgir.Solver(dim, n, ["f64"] * nl, nlevels=nl, residual_scaling=False, cycles_per_step=2).solve(bt)
+    s = mgir.Solver(dim, n, W.precision_map("dsh", nl), nlevels=nl, rescale_half=True, cycles_per_step=2)
+    u, res = s.solve(bt)
+    assert res.status == 0
+    assert ref.norm2(ref.residual(b, u.cpu().numpy())) / ref.norm2(b) <= 1e-10
+    assert res.iterations <= r64.iterations + 2
