@@ -87,6 +87,37 @@ def kernel_table(prof, level=0):
     return agg
 
 
+def bandwidth_ceiling(torch, mgir, reps=5):
+    """Best HBM rate (GB/s, event-timed) of one streaming launch per access
+    mix over a range of grid sizes: copy, read and write of 1 GiB, and the
+    refinement update's mix (two FP64 arrays read and written, two FP16 arrays
+    read; 36 bytes per element over 2^27 elements)."""
+    dev = torch.device("cuda:0")
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    ru = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+    cb = torch.ones(2 * n, dtype=torch.float16, device=dev)
+    out = {"metric": "streaming HBM bandwidth ceiling", "unit": "GB/s", "peak": 8000.0}
+    for name, kind, bytes_moved in (("copy", 0, 2 * 8 * n), ("read", 1, 8 * n), ("write", 2, 8 * n),
+                                    ("update_mix", 3, 36 * n)):
+        best = 0.0
+        for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
+            a, b = (ru, cb) if kind == 3 else (dst, src)
+            mgir.bandwidth_probe(a, b, kind, blocks)
+            torch.cuda.synchronize()
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                mgir.bandwidth_probe(a, b, kind, blocks)
+                e1.record()
+                torch.cuda.synchronize()
+                best = max(best, bytes_moved / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        out[name] = round(best, 1)
+        log(f"[ceiling] {name}: {best:.0f} GB/s")
+    return out
+
+
 def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=True):
     """Throughput of the batched and many-right-hand-side solves (FP16 V-cycles
     and the FP64 solve of the same problems), and the paper's other precision
@@ -250,6 +281,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only run the mixed solve (for rocprofv3)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="only measure the streaming bandwidth ceilings (copy, read, write, update mix)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-instances and many-right-hand-sides measurements")
     args = ap.parse_args()
@@ -262,6 +295,10 @@ def main():
 
     from paper_2007_07539_amd import mgir
     from paper_2007_07539_amd import workloads as W
+
+    if args.ceiling:
+        print(json.dumps(bandwidth_ceiling(torch, mgir)), flush=True)
+        return
 
     n = args.n
     L = W.levels_for(n)

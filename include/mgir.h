@@ -331,9 +331,12 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int npar
 /* ---- Measurement --------------------------------------------------------
  * Bandwidth probe: one kernel launch that copies (kind 0), reads (1) or
  * writes (2) `bytes` (a multiple of 16) of device memory with 16-byte lanes,
- * `blocks` blocks of 256 threads in a grid-stride loop.  Used to measure the
- * achievable HBM bandwidth and to calibrate traffic counters.  For kind 1 the
- * first 4 bytes of dst may be written.  Async. */
+ * `blocks` blocks of 256 threads in a grid-stride loop.  Kind 3 streams the
+ * access mix of the refinement update: dst holds two FP64 arrays of `bytes`
+ * each (read and written), src two FP16 arrays of bytes/4 each (read), 36
+ * bytes per element; bytes a multiple of 32.  Used to measure the achievable
+ * HBM bandwidth and to calibrate traffic counters.  For kind 1 the first 4
+ * bytes of dst may be written.  Async. */
 mg_status_t mg_bandwidth_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, void *stream);
 
 /* Run one refinement step eagerly with a HIP event pair around every kernel

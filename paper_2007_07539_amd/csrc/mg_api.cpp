@@ -1339,8 +1339,8 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
 }
 
 mg_status_t mg_bandwidth_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, void *stream) {
-    if (!dst || !src || kind < 0 || kind > 2 || blocks < 1) return fail(MG_ERR_ARG, "bad argument");
-    if (bytes % 16) return fail(MG_ERR_ARG, "bytes must be a multiple of 16");
+    if (!dst || !src || kind < 0 || kind > 3 || blocks < 1) return fail(MG_ERR_ARG, "bad argument");
+    if (bytes % (kind == 3 ? 32 : 16)) return fail(MG_ERR_ARG, "bytes must be a multiple of 16 (32 for kind 3)");
     HIPCHK(launch_probe(dst, src, bytes, kind, blocks, static_cast<unsigned *>(dst), static_cast<hipStream_t>(stream)));
     return MG_OK;
 }

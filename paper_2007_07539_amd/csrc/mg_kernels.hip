@@ -1375,6 +1375,36 @@ __global__ __launch_bounds__(256) void k_probe(uint4 *__restrict__ dst, const ui
     if (kind == 1 && acc == 0x9e3779b9u) sink[0] = acc;  // keeps the loads live
 }
 
+// The access mix of the fused last sweep + update without its stencil: per
+// point, read two FP16 values (c, b) and read and write two FP64 values (R, U),
+// 36 bytes; four points per thread, as the update's rows.
+__global__ __launch_bounds__(256) void k_probe_update(double *__restrict__ R, double *__restrict__ U,
+                                                      const f16 *__restrict__ c, const f16 *__restrict__ b,
+                                                      size_t n4) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        RawRow<double, 4> r, u;
+        RawRow<f16, 4> cr, br;
+        fetch_row<double, 4>(R + 4 * i, r);
+        fetch_row<double, 4>(U + 4 * i, u);
+        fetch_row<f16, 4>(c + 4 * i, cr);
+        fetch_row<f16, 4>(b + 4 * i, br);
+        double rv[4], uv[4];
+        float cv[4], bv[4];
+        widen_row<double, 4>(r, rv);
+        widen_row<double, 4>(u, uv);
+        widen_row<f16, 4>(cr, cv);
+        widen_row<f16, 4>(br, bv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            rv[j] = fmaT<double>(-(double)cv[j], (double)bv[j], rv[j]);
+            uv[j] += (double)cv[j];
+        }
+        store_row<double, 4>(R + 4 * i, rv);
+        store_row<double, 4>(U + 4 * i, uv);
+    }
+}
+
 // ===========================================================================
 // Host launchers.
 // ===========================================================================
@@ -1769,6 +1799,14 @@ hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int 
                         hipStream_t st) {
     if (bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
         return hipErrorInvalidValue;
+    if (kind == 3) {
+        // dst: R and U, bytes each; src: c and b, bytes / 4 each (FP16)
+        double *R = static_cast<double *>(dst);
+        const f16 *c = static_cast<const f16 *>(src);
+        hipLaunchKernelGGL(k_probe_update, dim3((unsigned)blocks), dim3(256), 0, st, R, R + bytes / 8, c,
+                           c + bytes / 8, bytes / 32);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_probe, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint4 *>(dst),
                        static_cast<const uint4 *>(src), bytes / 16, kind, sink);
     return hipGetLastError();
