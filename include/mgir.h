@@ -316,14 +316,17 @@ typedef enum {
                                used when the finest level is FP64 without residual
                                scaling (its right-hand side is r itself) or nu2 < 2.
                                Reading returns whether it is in use and its shape. */
-    MG_SHAPE_FUSE_SR = 8    /* 3-D, level argument 0: {on (0|1)[, tyc, zcc]}.  When on
-                               (the default; the autotuner keeps it only where it is
-                               faster), the first pre-smoothing of the finest level
-                               (from the scaled residual) and the residual +
-                               restriction of its result run as one kernel inside
-                               ir_solve (same result).  Needs nu1 = 2, residual
-                               scaling, an FP32/FP16/BF16 finest level and P/8
-                               dividing 64.  Reading returns whether it is in use. */
+    MG_SHAPE_FUSE_SR = 8    /* 3-D, level l below the base: {on (0|1)[, tyc, zcc]}.  When
+                               on, the level's first pre-smoothing (two sweeps from zero)
+                               and the residual + restriction of its result run as one
+                               kernel (same result).  Level 0: the finest level inside
+                               ir_solve, from the scaled residual (on by default).  Level
+                               l >= 1: that level, from its stored right-hand side (off by
+                               default).  The autotuner keeps it only where it is faster.
+                               Needs nu1 = 2, an FP32/FP16/BF16 level, P/8 dividing 64,
+                               and (level 0) residual scaling; not used into a rescaled
+                               level.  Reading returns whether it is in use and its
+                               shape. */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);

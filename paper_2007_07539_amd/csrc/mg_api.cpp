@@ -48,6 +48,9 @@ struct LevelPlan {
     size_t elems = 0;
     size_t off_b = 0, off_c[2] = {0, 0};
     size_t off_cg = 0;     // CG vectors of a multi-point base level
+    // fused first smoothing + restriction from the stored b (levels >= 1)
+    bool fsr_on = true, fsr = false;
+    RShape fsrsh{8, 2, 16, 3};
     bool rescale = false;  // restrictions into this level rescale (half-precision level, rescale_half)
     size_t off_t = 0;      // its restricted residual / scaled correction in the finer accumulator format
     Shape shs[3];   // kernel families: SH_SMOOTH (first pre-smoothing), SH_SWEEP, SH_PROLONG
@@ -370,6 +373,15 @@ hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const
         }
         return enq_restrict(h, st, 0, rhs);
     }
+    if (l >= 1 && h->lv[l].fsr) {
+        LevelPlan &L = h->lv[l], &C = h->lv[l + 1];
+        const double N = (double)points(h->dim, L.n);
+        RUN(h, st, "smooth_restrict", l, N * 2 * sb(L.prec) + (double)points(h->dim, C.n) * sb(C.prec),
+            launch_smooth_restrict_b(L.prec, C.prec, L.P, rhs, cbuf(h, l, 0), bbuf(h, l + 1), h->opt.omega, L.fsrsh,
+                                     st));
+        h->cur[l] = 0;
+        return hipSuccess;
+    }
     if (l == 0 && mode == RHS_SCALED_R && h->fused_sr) {
         LevelPlan &L = h->lv[0], &C = h->lv[1];
         const double N = (double)points(h->dim, L.n);
@@ -476,6 +488,26 @@ bool fusion_sr_possible(mg_ctx *h) {
 }
 
 void set_fused_sr(mg_ctx *h, bool on) { h->fused_sr = on && fusion_sr_possible(h); }
+
+// The same fusion on a coarser level l (right-hand side b_l from memory).
+bool fusion_srb_possible(mg_ctx *h, int l) {
+    if (l < 1 || l + 1 >= h->nl) return false;
+    const LevelPlan &L = h->lv[l];
+    return L.fsr_on && !h->batched && !h->nrhs && h->dim == 3 && h->opt.nu1 == 2 &&
+           !h->lv[l + 1].rescale && smooth_restrict_ok(L.P, L.prec, L.fsrsh);
+}
+
+void set_fused_srb(mg_ctx *h, int l, bool on) { h->lv[l].fsr = on && fusion_srb_possible(h, l); }
+
+// A fused-kernel shape that fits level l: the most coarse rows per tile that
+// the kernel allows, 16 coarse planes per chunk (fewer on small levels).
+RShape default_srshape(const LevelPlan &L) {
+    for (int tyc = 3; tyc >= 1; --tyc) {
+        const RShape r{8, tyc, std::max(1, std::min(16, L.P / 2 - 1)), 3};
+        if (smooth_restrict_ok(L.P, L.prec, r)) return r;
+    }
+    return RShape{8, 1, 1, 3};
+}
 
 void set_fused(mg_ctx *h, bool on) {
     h->fused = on && fusion_possible(h);
@@ -685,10 +717,10 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                     if (t < best) best = t, br = r;
                 }
         L.rsh = br;
-        if (l == 0 && fusion_sr_possible(h)) {
+        if (l == 0 ? fusion_sr_possible(h) : fusion_srb_possible(h, l)) {
             // the fused first smoothing + restriction against the two kernels
             float bf = 1e30f;
-            RShape bsr = h->srsh;
+            RShape bsr = l == 0 ? h->srsh : L.fsrsh;
             int dev = 0, cus = 256;
             if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -713,14 +745,23 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                     const RShape r{8, tyc, zcc, 3};
                     if (!smooth_restrict_ok(L.P, L.prec, r)) continue;
                     const float t = time_ms(st, [&]() {
-                        return launch_smooth_restrict(L.prec, h->lv[1].prec, L.P, Rbuf(h), scal(h), bbuf(h, 0),
-                                                      cbuf(h, 0, 0), bbuf(h, 1), h->opt.omega, r, st);
+                        if (l == 0)
+                            return launch_smooth_restrict(L.prec, h->lv[1].prec, L.P, Rbuf(h), scal(h), bbuf(h, 0),
+                                                          cbuf(h, 0, 0), bbuf(h, 1), h->opt.omega, r, st);
+                        return launch_smooth_restrict_b(L.prec, h->lv[l + 1].prec, L.P, bbuf(h, l), cbuf(h, l, 0),
+                                                        bbuf(h, l + 1), h->opt.omega, r, st);
                     }, 3);
                     if (t < bf) bf = t, bsr = r;
                 }
             }
-            h->srsh = bsr;
-            set_fused_sr(h, bf < best + fam_best[SH_SMOOTH]);
+            const bool win = bf < best + fam_best[SH_SMOOTH];
+            if (l == 0) {
+                h->srsh = bsr;
+                set_fused_sr(h, win);
+            } else {
+                L.fsrsh = bsr;
+                set_fused_srb(h, l, win);
+            }
         }
         if (l == 0) {
             best = 1e30f;
@@ -905,15 +946,15 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         // the fused first smoothing + restriction needs more than 64 KB of LDS
         // for its larger tiles; without that permission it stays off
         if (h->dim != 3 || smooth_restrict_prepare() != hipSuccess) h->fuse_sr_on = false;
-        const int P0 = h->lv[0].P;
-        for (int tyc = 3; tyc >= 1; --tyc) {
-            const RShape r{8, tyc, std::max(1, std::min(16, P0 / 2 - 1)), 3};
-            if (smooth_restrict_ok(P0, h->lv[0].prec, r)) {
-                h->srsh = r;
-                break;
-            }
-        }
+        h->srsh = default_srshape(h->lv[0]);
         set_fused_sr(h, true);
+        // on the coarser levels (fewer tiles than CUs, often) the fused form
+        // is usually slower than the two kernels: off unless the autotuner
+        // finds it faster
+        for (int l = 1; l + 1 < m; ++l) {
+            h->lv[l].fsrsh = default_srshape(h->lv[l]);
+            set_fused_srb(h, l, false);
+        }
     }
     *out = h;
     return MG_OK;
@@ -1231,16 +1272,22 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE_SR) {
+        if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no restriction", level);
         if ((np != 1 && np != 3) || (p[0] != 0 && p[0] != 1))
             return fail(MG_ERR_ARG, "the fused smoothing + restriction shape is {on (0|1)[, tyc, zcc]}");
         if (np == 3) {
             const RShape r{8, p[1], p[2], 3};
-            if (h->nl < 2 || !smooth_restrict_ok(h->lv[0].P, h->lv[0].prec, r))
+            if (!smooth_restrict_ok(h->lv[level].P, h->lv[level].prec, r))
                 return fail(MG_ERR_ARG, "fused smoothing + restriction shape {tyc, zcc} not valid here");
-            h->srsh = r;
+            (level == 0 ? h->srsh : h->lv[level].fsrsh) = r;
         }
-        h->fuse_sr_on = p[0] != 0;
-        set_fused_sr(h, h->fuse_sr_on);
+        if (level == 0) {
+            h->fuse_sr_on = p[0] != 0;
+            set_fused_sr(h, h->fuse_sr_on);
+        } else {
+            h->lv[level].fsr_on = p[0] != 0;
+            set_fused_srb(h, level, h->lv[level].fsr_on);
+        }
         drop_graph(h);
         return MG_OK;
     }
@@ -1308,9 +1355,11 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE_SR) {
+        if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no restriction", level);
         if (np < 1) return fail(MG_ERR_ARG, "too few values");
-        p[0] = h->fused_sr ? 1 : 0;
-        if (np >= 3) p[1] = h->srsh.tyc, p[2] = h->srsh.zcc;
+        const RShape &r = level == 0 ? h->srsh : h->lv[level].fsrsh;
+        p[0] = (level == 0 ? h->fused_sr : h->lv[level].fsr) ? 1 : 0;
+        if (np >= 3) p[1] = r.tyc, p[2] = r.zcc;
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE) {

@@ -104,6 +104,9 @@ hipError_t smooth_restrict_prepare();
 bool smooth_restrict_ok(int P, int prec, const RShape &s);
 hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
                                   void *cout, void *bc, double omega, const RShape &s, hipStream_t st);
+// The same from the level's stored right-hand side b (no b output).
+hipError_t launch_smooth_restrict_b(int prec, int pc, int P, const void *b, void *cout, void *bc, double omega,
+                                    const RShape &s, hipStream_t st);
 
 // Residual rescaling on restriction into a half-precision level.  pa is the
 // fine level's accumulator format (P_F64 or P_F32), prec the coarse level's

@@ -1,11 +1,14 @@
-// The finest level's first pre-smoothing inside a refinement step fused with
-// the residual and full-weighting restriction of its result (3-D):
+// A level's first pre-smoothing (two sweeps from zero) fused with the residual
+// and full-weighting restriction of its result (3-D).  On the finest level
+// inside a refinement step the right-hand side is the scaled residual:
 //   b  = round_T(r / alpha)                     (residuum scaling and cast)
 //   c1 = round_T(k b),  c2 = round_T(c1 + k (b - (6 c1 - nb(c1))))
 //   b_c = round_TC(FW(b - (6 c2 - nb(c2))))
 // b and c2 are written for the later sweeps and the prolongation; c2 is
 // restricted from registers and LDS instead of being read back from HBM
-// (8 + 2 s + s_c/8 bytes per point instead of 8 + 2 s, then 2 s + s_c/8).
+// (8 + 2 s + s_c/8 bytes per point instead of 8 + 2 s, then 2 s + s_c/8).  On
+// a coarser level b is the stored right-hand side and only c2 and b_c are
+// written (2 s + s_c/8 instead of 2 s, then 2 s + s_c/8).
 //
 // A block owns tyc coarse rows and zcc coarse planes, like the pipelined
 // restriction kernel.  Its thread row groups gi = 0 .. 2 tyc + 4 hold fine
@@ -21,16 +24,22 @@
 #include "mg_device.h"
 #include "mg_launch.h"
 
+#include <type_traits>
+
 namespace mg {
 namespace {
 
-template <class T, class TC>
-__global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restrict__ R,
+// SCALED: the right-hand side is the scaled-and-cast FP64 residual (the
+// finest level inside a refinement step; b is also written out); otherwise
+// it is the level's stored b (a coarser level, or a V-cycle on its own).
+template <class T, class TC, bool SCALED>
+__global__ __launch_bounds__(768) void k_smooth_restrict(const void *__restrict__ src,
                                                           const double *__restrict__ scal, T *__restrict__ bout,
                                                           T *__restrict__ cout, TC *__restrict__ bc, int P, int tyc,
                                                           int zcc, int ytiles, double omega, int xcd) {
     constexpr int V = 8, VC = 4;
     typedef acc_t<T> A;
+    typedef typename std::conditional<SCALED, double, T>::type S;  // source format
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = 2 * tyc + 5, RR = 2 * tyc + 1, RW = P / 2;
     const size_t cslot = (size_t)G * P, rslot = (size_t)RR * RW;
@@ -64,29 +73,33 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
     auto own_plane = [&](int z) { return z >= zf0 && (z <= zf1 - 1 || (last_z && z == P - 1)); };
     const bool coarse = gi < tyc && Y0 + gi < Pc;
     const int Yc = Y0 + gi;
-    const double inv = scal[1];
+    const double inv = SCALED ? scal[1] : 1.0;
     const A k = (A)(omega / 6.0);
     // offsets of the own row (plane 0) and of plane z, the latter uniform
     const size_t roff = (size_t)(long)y * P + x0;
     const size_t PP = (size_t)P * P;
     auto at = [&](int z) { return (size_t)z * PP + roff; };
 
-    auto fetch_r = [&](int z, RawRow<double, V> &rr) {
+    auto fetch_r = [&](int z, RawRow<S, V> &rr) {
         if (!row_in || z < 1 || z > P - 1) {
             zero_row(rr);
             return;
         }
-        fetch_row<double, V>(R + at(z), rr);
+        fetch_row<S, V>(static_cast<const S *>(src) + at(z), rr);
     };
-    // b = round_T(r / alpha) of the own row (zero outside the interior), as
-    // stored (braw) and widened (bw)
-    auto scaled = [&](const RawRow<double, V> &rr, T (&braw)[V], A (&bw)[V]) {
-        double rv[V];
-        widen_row<double, V>(rr, rv);
+    // b of the own row (zero outside the interior), as stored (braw) and
+    // widened (bw): round_T(r / alpha), or the stored b itself
+    auto scaled = [&](const RawRow<S, V> &rr, T (&braw)[V], A (&bw)[V]) {
+        if constexpr (SCALED) {
+            double rv[V];
+            widen_row<double, V>(rr, rv);
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-            braw[i] = Store<T>::from_f64(rv[i] * inv);
-            bw[i] = widen(braw[i]);
+            for (int i = 0; i < V; ++i) {
+                braw[i] = Store<T>::from_f64(rv[i] * inv);
+                bw[i] = widen(braw[i]);
+            }
+        } else {
+            widen_row<T, V>(rr, bw);
         }
     };
     // c1 = round_T(k b), widened
@@ -101,7 +114,7 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
     A bA[V], bB[V], bC[V];   // b
     A kA[V], kB[V], kC[V];   // c1
     A cA[V], cB[V], cC[V];   // c2
-    RawRow<double, V> rnext; // r of the own row, plane t+2 (then t+3)
+    RawRow<S, V> rnext;      // source row of the own row, plane t+2 (then t+3)
     A acc[VC];
 #pragma unroll
     for (int j = 0; j < VC; ++j) acc[j] = A(0);
@@ -110,7 +123,7 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
 
     const int tb = zf0 - 2;
     {
-        RawRow<double, V> t0;
+        RawRow<S, V> t0;
         T braw[V];
         fetch_r(tb, t0);
         scaled(t0, braw, bA);
@@ -161,9 +174,11 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
         scaled(rnext, braw, b2);
         fetch_r(t + 3, rnext);
         first(b2, k2);
-        if (own_row && own_plane(t + 2)) {
-            if (x0 == 0) braw[0] = zero_of<T>();
-            store_row<T, V>(bout + at(t + 2), braw);
+        if constexpr (SCALED) {
+            if (own_row && own_plane(t + 2)) {
+                if (x0 == 0) braw[0] = zero_of<T>();
+                store_row<T, V>(bout + at(t + 2), braw);
+            }
         }
         __syncthreads();
         if (coarse && t - 1 >= zf0) coarse_step(t - 1, (t - 1) & 1);
@@ -253,8 +268,8 @@ __global__ __launch_bounds__(768) void k_smooth_restrict(const double *__restric
     if (coarse) coarse_step(zf1, zf1 & 1);
 }
 
-template <class T>
-hipError_t smooth_restrict_t(int pc, int P, const double *R, const double *scal, void *bout, void *cout, void *bc,
+template <class T, bool SCALED>
+hipError_t smooth_restrict_t(int pc, int P, const void *src, const double *scal, void *bout, void *cout, void *bc,
                              double omega, const RShape &s, hipStream_t st) {
     const int Pc = P / 2;
     const int ytiles = (Pc - 1 + s.tyc - 1) / s.tyc;
@@ -262,7 +277,7 @@ hipError_t smooth_restrict_t(int pc, int P, const double *R, const double *scal,
     const int threads = (2 * s.tyc + 5) * (P / 8);
     const size_t lds = smooth_restrict_lds_bytes(P, s.tyc);
 #define MG_SR(TCT)                                                                                                     \
-    hipLaunchKernelGGL((k_smooth_restrict<T, TCT>), dim3(blocks), dim3(threads), lds, st, R, scal,                   \
+    hipLaunchKernelGGL((k_smooth_restrict<T, TCT, SCALED>), dim3(blocks), dim3(threads), lds, st, src, scal,       \
                        static_cast<T *>(bout), static_cast<T *>(cout), static_cast<TCT *>(bc), P, s.tyc, s.zcc,     \
                        ytiles, omega, 1)
     switch (pc) {
@@ -285,9 +300,11 @@ size_t smooth_restrict_lds_bytes(int P, int tyc) {
 hipError_t smooth_restrict_prepare() {
     static hipError_t done = [] {
         const void *fns[] = {
-#define MG_SR_FN(T) (const void *)k_smooth_restrict<T, double>, (const void *)k_smooth_restrict<T, float>, \
-                    (const void *)k_smooth_restrict<T, f16>, (const void *)k_smooth_restrict<T, bf16>
-            MG_SR_FN(float), MG_SR_FN(f16), MG_SR_FN(bf16)
+#define MG_SR_FN(T, S)                                                                                        \
+    (const void *)k_smooth_restrict<T, double, S>, (const void *)k_smooth_restrict<T, float, S>,              \
+        (const void *)k_smooth_restrict<T, f16, S>, (const void *)k_smooth_restrict<T, bf16, S>
+            MG_SR_FN(float, true), MG_SR_FN(f16, true), MG_SR_FN(bf16, true),
+            MG_SR_FN(float, false), MG_SR_FN(f16, false), MG_SR_FN(bf16, false)
 #undef MG_SR_FN
         };
         for (const void *f : fns) {
@@ -310,9 +327,20 @@ hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, cons
                                   void *cout, void *bc, double omega, const RShape &s, hipStream_t st) {
     if (!smooth_restrict_ok(P, prec, s)) return hipErrorInvalidValue;
     switch (prec) {
-    case P_F32: return smooth_restrict_t<float>(pc, P, R, scal, bout, cout, bc, omega, s, st);
-    case P_F16: return smooth_restrict_t<f16>(pc, P, R, scal, bout, cout, bc, omega, s, st);
-    case P_BF16: return smooth_restrict_t<bf16>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_F32: return smooth_restrict_t<float, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_F16: return smooth_restrict_t<f16, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_BF16: return smooth_restrict_t<bf16, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_smooth_restrict_b(int prec, int pc, int P, const void *b, void *cout, void *bc, double omega,
+                                    const RShape &s, hipStream_t st) {
+    if (!smooth_restrict_ok(P, prec, s)) return hipErrorInvalidValue;
+    switch (prec) {
+    case P_F32: return smooth_restrict_t<float, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
+    case P_F16: return smooth_restrict_t<f16, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
+    case P_BF16: return smooth_restrict_t<bf16, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
     }
     return hipErrorInvalidValue;
 }

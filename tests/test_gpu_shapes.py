@@ -164,3 +164,43 @@ def test_fused_smooth_restrict_bitwise(dev, name, n):
         assert r.history == r_ref.history, shape
         assert torch.equal(u, u_ref), shape
     assert tried >= (0 if prec[0] == "f64" else 3)
+
+
+@pytest.mark.parametrize("name,n", [("f16", 127), ("bf16", 63), ("f32", 63), ("hsd", 255), ("h_mg", 127)])
+def test_fused_smooth_restrict_coarse_levels_bitwise(dev, name, n):
+    """On the coarser levels the fused first smoothing + restriction reads the
+    stored right-hand side; turning it off level by level, or changing its
+    shape, changes neither the V-cycle nor the solve."""
+    print(f"fused smooth+restrict, coarse levels, {name} n={n}", flush=True)
+    prec = W.precision_map(name, W.levels_for(n))
+    b64 = torch.from_numpy(W.uniform_rhs(3, n, seed=10)).to(dev)
+    bl = b64.to(mgir.TORCH_DTYPE[prec[0]])
+    s = mgir.Solver(3, n, prec)
+    s.set_shape(0, mgir.SHAPE_TAIL, [0])  # every level through its own kernels
+    levels = []
+    for l in range(1, s.nlevels - 1):
+        assert s.get_shape(l, mgir.SHAPE_FUSE_SR)[0] == 0  # off by default on coarser levels
+        try:
+            s.set_shape(l, mgir.SHAPE_FUSE_SR, [1])
+        except mgir.MgError:
+            continue
+        if s.get_shape(l, mgir.SHAPE_FUSE_SR)[0] == 1:
+            levels.append(l)
+    assert levels
+    c_on = s.vcycle(bl).clone()
+    u_on, r_on = s.solve(b64)
+    u_on = u_on.clone()
+    for shape in ([1, 1, 3], [1, 2, 5], [1, 3, 2]):
+        for l in levels:
+            try:
+                s.set_shape(l, mgir.SHAPE_FUSE_SR, shape)
+            except mgir.MgError:
+                pass
+        assert torch.equal(s.vcycle(bl), c_on), shape
+    for l in levels:
+        s.set_shape(l, mgir.SHAPE_FUSE_SR, [0])
+        assert s.get_shape(l, mgir.SHAPE_FUSE_SR)[0] == 0
+    assert torch.equal(s.vcycle(bl), c_on)
+    u_off, r_off = s.solve(b64)
+    assert r_off.iterations == r_on.iterations and torch.equal(u_off, u_on)
+    assert r_off.history == r_on.history
