@@ -732,7 +732,7 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                 std::vector<int> zs{4, 8, 16, 32};
                 const int Pc = L.P / 2, ytiles = (Pc - 1 + tyc - 1) / tyc;
                 int last_chunks = 0;
-                for (int zcc = 6; zcc <= 48 && zcc <= Pc - 1; ++zcc) {
+                for (int zcc = 6; zcc <= Pc - 1; ++zcc) {
                     const int chunks = (Pc - 1 + zcc - 1) / zcc;
                     if (chunks == last_chunks) continue;
                     last_chunks = chunks;
