@@ -25,6 +25,16 @@ _LIB = os.path.join(_HERE, "libmgref.so")
 
 OK, ERR_ARG, ERR_SHAPE, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_NOMEM = 0, -1, -2, -6, -7, -9
 
+# Discretisations of Section 5: the finite-difference stencil, and the
+# bilinear / trilinear Q1 finite elements the paper's measurements use.
+DISCS = {"fd": 0, "q1": 1}
+
+
+def _disc(d) -> int:
+    if d not in DISCS:
+        raise ValueError(f"unknown discretisation {d!r}")
+    return DISCS[d]
+
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (serial, -O2, no fast-math)."""
@@ -41,7 +51,7 @@ class _IrOpts(ctypes.Structure):
         ("residual_scaling", ctypes.c_int), ("recursive_residual", ctypes.c_int),
         ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("use_initial_guess", ctypes.c_int),
         ("cycles", ctypes.c_int), ("base_n", ctypes.c_int), ("base_tol", ctypes.c_double),
-        ("base_max_iter", ctypes.c_int),
+        ("base_max_iter", ctypes.c_int), ("disc", ctypes.c_int),
     ]
 
 
@@ -61,20 +71,22 @@ def _load():
         i = ctypes.c_int
         lib.ref_points.argtypes, lib.ref_points.restype = [i, i], ctypes.c_long
         lib.ref_levels.argtypes, lib.ref_levels.restype = [i], i
-        lib.ref_apply_A.argtypes = [i, i, dp, dp]
-        lib.ref_residual.argtypes = [i, i, dp, dp, dp]
-        lib.ref_jacobi.argtypes = [i, i, ctypes.c_double, dp, dp, dp]
-        lib.ref_restrict.argtypes = [i, i, dp, dp]
+        lib.ref_apply_A_disc.argtypes = [i, i, i, dp, dp]
+        lib.ref_residual_disc.argtypes = [i, i, i, dp, dp, dp]
+        lib.ref_jacobi_disc.argtypes = [i, i, i, ctypes.c_double, dp, dp, dp]
+        lib.ref_restrict_disc.argtypes = [i, i, i, dp, dp]
         lib.ref_prolong.argtypes = [i, i, dp, dp]
         lib.ref_vcycle.argtypes, lib.ref_vcycle.restype = [i, i, i, i, ctypes.c_double, dp, dp], i
         lib.ref_vcycle_base.argtypes = [i, i, i, i, i, ctypes.c_double, ctypes.c_double, i, dp, dp]
         lib.ref_vcycle_base.restype = i
-        lib.ref_cg.argtypes, lib.ref_cg.restype = [i, i, dp, dp, ctypes.c_double, i], i
+        lib.ref_vcycle_disc.argtypes = [i, i, i, i, i, i, ctypes.c_double, ctypes.c_double, i, dp, dp]
+        lib.ref_vcycle_disc.restype = i
+        lib.ref_cg_disc.argtypes, lib.ref_cg_disc.restype = [i, i, i, dp, dp, ctypes.c_double, i], i
         lib.ref_norm2.argtypes, lib.ref_norm2.restype = [dp, ctypes.c_long], ctypes.c_double
         lib.ref_norminf.argtypes, lib.ref_norminf.restype = [dp, ctypes.c_long], ctypes.c_double
         lib.ref_ir_solve.argtypes = [i, i, dp, dp, ctypes.POINTER(_IrOpts), ctypes.POINTER(_IrResult), dp, i]
         lib.ref_ir_solve.restype = i
-        for f in ("ref_apply_A", "ref_residual", "ref_jacobi", "ref_restrict", "ref_prolong"):
+        for f in ("ref_apply_A_disc", "ref_residual_disc", "ref_jacobi_disc", "ref_restrict_disc", "ref_prolong"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -94,40 +106,42 @@ def _shape(a: np.ndarray):
     return a.ndim, a.shape[0]
 
 
-def apply_A(v):
-    """A v for the finite-difference Laplacian with zero Dirichlet boundary (Section 5)."""
+def apply_A(v, disc="fd"):
+    """A v with zero Dirichlet boundary (Section 5): the finite-difference
+    Laplacian (disc "fd") or the Q1 finite-element stiffness matrix ("q1")."""
     v = _f64(v)
     dim, n = _shape(v)
     out = np.empty_like(v)
-    _load().ref_apply_A(dim, n, _ptr(v), _ptr(out))
+    _load().ref_apply_A_disc(dim, n, _disc(disc), _ptr(v), _ptr(out))
     return out
 
 
-def residual(b, c):
+def residual(b, c, disc="fd"):
     """b - A c."""
     b, c = _f64(b), _f64(c)
     dim, n = _shape(b)
     out = np.empty_like(b)
-    _load().ref_residual(dim, n, _ptr(b), _ptr(c), _ptr(out))
+    _load().ref_residual_disc(dim, n, _disc(disc), _ptr(b), _ptr(c), _ptr(out))
     return out
 
 
-def jacobi(b, c, omega=0.8):
+def jacobi(b, c, omega=0.8, disc="fd"):
     """One damped-Jacobi sweep c + omega (b - A c) / diag(A) (Section 4.2)."""
     b, c = _f64(b), _f64(c)
     dim, n = _shape(b)
     out = np.empty_like(b)
-    _load().ref_jacobi(dim, n, float(omega), _ptr(b), _ptr(c), _ptr(out))
+    _load().ref_jacobi_disc(dim, n, _disc(disc), float(omega), _ptr(b), _ptr(c), _ptr(out))
     return out
 
 
-def restrict(r):
-    """Full-weighting restriction to the next coarser grid."""
+def restrict(r, disc="fd"):
+    """Restriction to the next coarser grid: full weighting (fd), or the
+    transpose of linear interpolation (q1)."""
     r = _f64(r)
     dim, n = _shape(r)
     nc = (n - 1) // 2
     out = np.empty((nc,) * dim)
-    _load().ref_restrict(dim, n, _ptr(r), _ptr(out))
+    _load().ref_restrict_disc(dim, n, _disc(disc), _ptr(r), _ptr(out))
     return out
 
 
@@ -146,20 +160,30 @@ def base_max_iter_default(dim: int, n_base: int) -> int:
     return min(10000, n_base**dim)
 
 
-def cg(b, tol, max_iter=None):
+def cg(b, tol, max_iter=None, disc="fd"):
     """Conjugate gradients for A x = b from x = 0 (the base solver of Section
     4.2), until ||r||_2 <= tol ||b||_2; returns (x, steps)."""
     b = _f64(b)
     dim, n = _shape(b)
     x = np.empty_like(b)
-    k = _load().ref_cg(dim, n, _ptr(b), _ptr(x), float(tol),
-                       int(base_max_iter_default(dim, n) if max_iter is None else max_iter))
+    k = _load().ref_cg_disc(dim, n, _disc(disc), _ptr(b), _ptr(x), float(tol),
+                            int(base_max_iter_default(dim, n) if max_iter is None else max_iter))
     if k < 0:
         raise ValueError(f"ref_cg failed with status {k}")
     return x, k
 
 
-def vcycle(b, nu1=2, nu2=2, omega=0.8, base_n=1, base_tol=1e-4, base_max_iter=None):
+def hierarchy(n: int, nlevels: int = 0) -> list:
+    """Level sizes n, (n-1)/2, ...: down to one point for n = 2^m - 1, else to
+    the first even size (the paper's grids c 2^k - 1 end on c - 1); nlevels > 0
+    keeps the finest nlevels of them."""
+    out = [n]
+    while out[-1] > 1 and out[-1] % 2 == 1:
+        out.append((out[-1] - 1) // 2)
+    return out[:nlevels] if nlevels else out
+
+
+def vcycle(b, nu1=2, nu2=2, omega=0.8, base_n=1, base_tol=1e-4, base_max_iter=None, disc="fd"):
     """One V-cycle from a zero initial guess (Algorithm 1, recursive), physical
     units, down to the base level of base_n points per dimension (one point:
     exact; more: CG to base_tol)."""
@@ -167,8 +191,8 @@ def vcycle(b, nu1=2, nu2=2, omega=0.8, base_n=1, base_tol=1e-4, base_max_iter=No
     dim, n = _shape(b)
     c = np.empty_like(b)
     mi = base_max_iter_default(dim, base_n) if base_max_iter is None else base_max_iter
-    st = _load().ref_vcycle_base(dim, n, int(base_n), int(nu1), int(nu2), float(omega), float(base_tol), int(mi),
-                                 _ptr(b), _ptr(c))
+    st = _load().ref_vcycle_disc(dim, n, _disc(disc), int(base_n), int(nu1), int(nu2), float(omega),
+                                 float(base_tol), int(mi), _ptr(b), _ptr(c))
     if st != OK:
         raise ValueError(f"ref_vcycle failed with status {st}")
     return c
@@ -200,7 +224,7 @@ class IrResult:
 
 def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
              recursive_residual=False, max_iter=100, rtol=1e-10, cycles=1, base_n=1, base_tol=1e-4,
-             base_max_iter=None) -> IrResult:
+             base_max_iter=None, disc="fd") -> IrResult:
     """Iterative refinement with residuum scaling and one V-cycle per step
     (Algorithm 2), all in FP64.  Stops when ||r||_2 <= rtol ||b||_2.  With
     cycles > 1 each step applies that many V-cycles to the scaled residual
@@ -211,7 +235,8 @@ def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
     opts = _IrOpts(int(nu1), int(nu2), float(omega), int(bool(residual_scaling)),
                    int(bool(recursive_residual)), int(max_iter), float(rtol), int(u0 is not None), int(cycles),
                    int(base_n), float(base_tol),
-                   int(base_max_iter_default(dim, base_n) if base_max_iter is None else base_max_iter))
+                   int(base_max_iter_default(dim, base_n) if base_max_iter is None else base_max_iter),
+                   _disc(disc))
     res = _IrResult()
     hist = np.zeros(max_iter + 2)
     st = _load().ref_ir_solve(dim, n, _ptr(b), _ptr(u), ctypes.byref(opts), ctypes.byref(res),

@@ -12,25 +12,33 @@
  * the plainest loops that state the definitions:
  *
  *   Model problem (Section 5): -Laplace(u) = f on the unit square (D = 2) or
- *   unit cube (D = 3), u = 0 on the boundary.  Discretised with the standard
- *   (2D+1)-point finite-difference stencil on n^D interior points, n = 2^m - 1,
- *   mesh width h = 1/(n+1):
+ *   unit cube (D = 3), u = 0 on the boundary, on n^D interior points of a
+ *   uniform mesh of width h = 1/(n+1), in one of two discretisations:
+ *
+ *   FD (disc 0): the standard (2D+1)-point finite-difference stencil,
  *       (A v)_i = (2D v_i - sum_{j face neighbour of i} v_j) / h^2,
  *   with v_j = 0 for neighbours on the boundary (homogeneous Dirichlet).
  *
- *   Grid hierarchy (Section 4.2): level l has n_l = 2^(l+1) - 1 points per
- *   dimension; level 0 (the base level) has a single interior point.  Coarse
- *   operators are the same stencil rediscretised with h_l = 1/(n_l + 1).
+ *   Q1 (disc 1): the bilinear (2-D) / trilinear (3-D) finite elements that
+ *   the paper uses (Section 5): A_ij = integral of grad(phi_i) . grad(phi_j)
+ *   over the domain, phi_i the nodal basis, assembled cell by cell.
+ *
+ *   Grid hierarchy (Section 4.2): level sizes n, (n-1)/2, ... down to the
+ *   base level; with n = 2^m - 1 the base can be a single point.  Coarse
+ *   operators are the same discretisation on the coarser mesh (for Q1 this is
+ *   also the Galerkin product R A P, which the tests check).
  *
  *   Smoother (Section 4.2): damped Jacobi,  c <- c + omega * D^-1 (b - A c),
- *   with D = diag(A) = 2D/h^2.
+ *   with D = diag(A) (2D/h^2 for FD).
  *
- *   Transfers: full-weighting restriction (tensor product of the 1-D weights
- *   1/4, 1/2, 1/4 centred on the coarse point's fine twin) and linear
- *   (bi-/tri-linear) interpolation for prolongation.
+ *   Transfers: linear (bi-/tri-linear) interpolation P for prolongation.
+ *   Restriction: FD uses full weighting (tensor product of the 1-D weights
+ *   1/4, 1/2, 1/4 centred on the coarse point's fine twin), Q1 the transpose
+ *   R = P^T of the interpolation (2^D times full weighting), so that
+ *   R A_h P = A_2h.
  *
  *   V-cycle: the two-grid method of Algorithm 1 applied recursively, with an
- *   exact solve on the one-point base level.
+ *   exact solve on a one-point base level or CG on a larger one.
  *
  *   Outer solver: mixed-precision iterative refinement with residuum scaling,
  *   Algorithm 2 (Section 4.3), run here entirely in FP64.
@@ -49,17 +57,32 @@
 #define REF_ERR_NONFINITE -7
 #define REF_ERR_NOMEM -9
 
+#define REF_DISC_FD 0
+#define REF_DISC_Q1 1
+
 /* n must be 2^m - 1 with m >= 1 so that coarsening by two ends on one point. */
 static int ref_valid_n(int n) { return n >= 1 && (((long)n + 1) & (long)n) == 0; }
+
+/* The hierarchy n, (n-1)/2, ... reaches n_base through odd sizes only
+ * (every coarse point has a fine twin and two fine neighbours). */
+static int ref_chain_ok(int n, int n_base) {
+    if (n_base < 1 || n < n_base) return 0;
+    while (n > n_base) {
+        if (n % 2 == 0) return 0;
+        n = (n - 1) / 2;
+    }
+    return n == n_base;
+}
 
 long ref_points(int dim, int n) {
     return dim == 2 ? (long)n * n : (long)n * n * n;
 }
 
-/* Number of levels of the full hierarchy, finest n down to the 1-point base. */
+/* Number of levels of the full hierarchy n, (n-1)/2, ...: down to the
+ * 1-point base for n = 2^m - 1, otherwise down to the first even size. */
 int ref_levels(int n) {
     int L = 0;
-    while (n > 1) { n = (n - 1) / 2; L++; }
+    while (n > 1 && n % 2 == 1) { n = (n - 1) / 2; L++; }
     return L + 1;
 }
 
@@ -91,31 +114,107 @@ void ref_apply_A(int dim, int n, const double *v, double *out) {
             }
 }
 
-/* r = b - A c  (the residual of Algorithms 1 and 2). */
-void ref_residual(int dim, int n, const double *b, const double *c, double *r) {
+/* The Q1 element matrix of one cell of side h (Section 5): with the 1-D
+ * element stiffness k = [1 -1; -1 1] / h and mass m = h [1/3 1/6; 1/6 1/3]
+ * of the linear hat functions, the tensor-product basis gives
+ *   K_e[a][b] = sum_d k[a_d][b_d] * prod_{d' != d} m[a_d'][b_d'],
+ * a, b in {0,1}^D the local vertex numbers (bit d of a = offset along axis d). */
+static void ref_q1_element(int dim, double h, double Ke[8][8]) {
+    const double k1[2][2] = {{1.0 / h, -1.0 / h}, {-1.0 / h, 1.0 / h}};
+    const double m1[2][2] = {{h / 3.0, h / 6.0}, {h / 6.0, h / 3.0}};
+    int nv = 1 << dim;
+    for (int a = 0; a < nv; a++)
+        for (int b = 0; b < nv; b++) {
+            double s = 0.0;
+            for (int d = 0; d < dim; d++) {
+                double t = k1[(a >> d) & 1][(b >> d) & 1];
+                for (int e = 0; e < dim; e++)
+                    if (e != d) t *= m1[(a >> e) & 1][(b >> e) & 1];
+                s += t;
+            }
+            Ke[a][b] = s;
+        }
+}
+
+/* out = A v for Q1: the sum of the element matrices over the (n+1)^D cells,
+ * cell (cx, cy, cz) spanning interior indices cx-1 .. cx (0-based, -1 and n on
+ * the boundary).  Boundary vertices hold v = 0 and have no row. */
+static void ref_apply_q1(int dim, int n, const double *v, double *out) {
+    double Ke[8][8];
+    ref_q1_element(dim, ref_h(n), Ke);
+    int nv = 1 << dim;
     long N = ref_points(dim, n);
-    ref_apply_A(dim, n, c, r);
+    for (long p = 0; p < N; p++) out[p] = 0.0;
+    int ncz = dim == 3 ? n + 1 : 1;
+    for (int cz = 0; cz < ncz; cz++)
+        for (int cy = 0; cy <= n; cy++)
+            for (int cx = 0; cx <= n; cx++)
+                for (int a = 0; a < nv; a++) {
+                    int i = cx - 1 + (a & 1), j = cy - 1 + ((a >> 1) & 1);
+                    int k = dim == 3 ? cz - 1 + ((a >> 2) & 1) : 0;
+                    if (i < 0 || i >= n || j < 0 || j >= n || k < 0 || (dim == 3 && k >= n)) continue;
+                    double s = 0.0;
+                    for (int b = 0; b < nv; b++) {
+                        int bi = cx - 1 + (b & 1), bj = cy - 1 + ((b >> 1) & 1);
+                        int bk = dim == 3 ? cz - 1 + ((b >> 2) & 1) : 0;
+                        s += Ke[a][b] * ref_get(dim, n, v, bi, bj, bk);
+                    }
+                    long idx = dim == 2 ? (long)j * n + i : ((long)k * n + j) * n + i;
+                    out[idx] += s;
+                }
+}
+
+/* diag(A): 2D/h^2 for FD; for Q1 the 2^D cells around a vertex each add
+ * K_e[0][0] = D h^(D-2) / 3^(D-1). */
+static double ref_diag(int dim, int n, int disc) {
+    double h = ref_h(n);
+    if (disc == REF_DISC_Q1) return (double)(1 << dim) * dim * pow(h, dim - 2) / pow(3.0, dim - 1);
+    return 2.0 * dim / (h * h);
+}
+
+void ref_apply_A_disc(int dim, int n, int disc, const double *v, double *out) {
+    if (disc == REF_DISC_Q1) ref_apply_q1(dim, n, v, out);
+    else ref_apply_A(dim, n, v, out);
+}
+
+/* r = b - A c  (the residual of Algorithms 1 and 2). */
+static void ref_residual_d(int dim, int n, int disc, const double *b, const double *c, double *r) {
+    long N = ref_points(dim, n);
+    ref_apply_A_disc(dim, n, disc, c, r);
     for (long p = 0; p < N; p++) r[p] = b[p] - r[p];
+}
+
+void ref_residual(int dim, int n, const double *b, const double *c, double *r) {
+    ref_residual_d(dim, n, REF_DISC_FD, b, c, r);
+}
+
+void ref_residual_disc(int dim, int n, int disc, const double *b, const double *c, double *r) {
+    ref_residual_d(dim, n, disc, b, c, r);
 }
 
 /* One damped-Jacobi sweep (Section 4.2): out = c + omega * (b - A c) / diag(A).
  * The update is simultaneous, so out must not alias c. */
-void ref_jacobi(int dim, int n, double omega, const double *b, const double *c, double *out) {
+void ref_jacobi_disc(int dim, int n, int disc, double omega, const double *b, const double *c, double *out) {
     long N = ref_points(dim, n);
-    double h = ref_h(n);
-    double diag = 2.0 * dim / (h * h);
+    double diag = ref_diag(dim, n, disc);
     double *r = (double *)malloc(sizeof(double) * N);
-    ref_residual(dim, n, b, c, r);
+    ref_residual_d(dim, n, disc, b, c, r);
     for (long p = 0; p < N; p++) out[p] = c[p] + omega * r[p] / diag;
     free(r);
 }
 
-/* Full-weighting restriction from a fine grid of n_f points per dimension to
- * the coarse grid of n_c = (n_f - 1)/2 points.  Coarse point I sits on fine
- * point 2I+1 (0-based); the 1-D weights are 1/4, 1/2, 1/4. */
-void ref_restrict(int dim, int n_f, const double *r_f, double *b_c) {
+void ref_jacobi(int dim, int n, double omega, const double *b, const double *c, double *out) {
+    ref_jacobi_disc(dim, n, REF_DISC_FD, omega, b, c, out);
+}
+
+/* Restriction from a fine grid of n_f points per dimension to the coarse grid
+ * of n_c = (n_f - 1)/2 points.  Coarse point I sits on fine point 2I+1
+ * (0-based).  FD: full weighting, 1-D weights 1/4, 1/2, 1/4.  Q1: the
+ * transpose of linear interpolation, 1-D weights 1/2, 1, 1/2. */
+void ref_restrict_disc(int dim, int n_f, int disc, const double *r_f, double *b_c) {
     int n_c = (n_f - 1) / 2;
-    static const double w[3] = {0.25, 0.5, 0.25};
+    const double g = disc == REF_DISC_Q1 ? 2.0 : 1.0;
+    const double w[3] = {0.25 * g, 0.5 * g, 0.25 * g};
     int nK = dim == 2 ? 1 : n_c;
     for (int K = 0; K < nK; K++)
         for (int J = 0; J < n_c; J++)
@@ -132,6 +231,10 @@ void ref_restrict(int dim, int n_f, const double *r_f, double *b_c) {
                 long idx = dim == 2 ? (long)J * n_c + I : ((long)K * n_c + J) * n_c + I;
                 b_c[idx] = s;
             }
+}
+
+void ref_restrict(int dim, int n_f, const double *r_f, double *b_c) {
+    ref_restrict_disc(dim, n_f, REF_DISC_FD, r_f, b_c);
 }
 
 /* Linear interpolation weight of coarse point I for fine point i (0-based):
@@ -169,12 +272,11 @@ void ref_prolong(int dim, int n_c, const double *e_c, double *e_f) {
             }
 }
 
-/* Exact solve on the one-point base level: A_0 = 2D/h_0^2 is 1x1. */
-static void ref_base_solve(int dim, int n, const double *b, double *c) {
-    double h = ref_h(n);
+/* Exact solve on the one-point base level: A_0 = diag(A_0) is 1x1. */
+static void ref_base_solve(int dim, int n, int disc, const double *b, double *c) {
     long N = ref_points(dim, n);
     if (N != 1) return;
-    c[0] = b[0] / (2.0 * dim / (h * h));
+    c[0] = b[0] / ref_diag(dim, n, disc);
 }
 
 /* Conjugate gradients for A x = b on the level with n points per dimension
@@ -186,7 +288,7 @@ static void ref_base_solve(int dim, int n, const double *b, double *c) {
  * relative to the base right-hand side, the test means the same there and does
  * not switch the base solve off once an unscaled residual is small).
  * Returns the steps taken. */
-int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter) {
+int ref_cg_disc(int dim, int n, int disc, const double *b, double *x, double tol, int max_iter) {
     long N = ref_points(dim, n);
     double *r = (double *)malloc(sizeof(double) * N);
     double *p = (double *)malloc(sizeof(double) * N);
@@ -200,7 +302,7 @@ int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter)
     const double stop = tol * sqrt(rr);
     int k = 0;
     while (k < max_iter && sqrt(rr) > stop) {
-        ref_apply_A(dim, n, p, q);
+        ref_apply_A_disc(dim, n, disc, p, q);
         double pq = 0.0;
         for (long i = 0; i < N; i++) pq += p[i] * q[i];
         if (!(pq > 0.0)) break;                      /* p = 0 (or breakdown) */
@@ -217,6 +319,10 @@ int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter)
     return k;
 }
 
+int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter) {
+    return ref_cg_disc(dim, n, REF_DISC_FD, b, x, tol, max_iter);
+}
+
 /* One V-cycle for A_l c = b on the level with n points per dimension
  * (Algorithm 1 applied recursively, Section 4.2), starting from c = 0, down
  * to the base level of n_base points per dimension (n_base = 1: the exact
@@ -227,16 +333,17 @@ int ref_cg(int dim, int n, const double *b, double *x, double tol, int max_iter)
  *   4. prolongate and add,
  *   5. post-smooth nu2 times.
  * Returns REF_OK or an error code. */
-int ref_vcycle_base(int dim, int n, int n_base, int nu1, int nu2, double omega, double base_tol,
+int ref_vcycle_disc(int dim, int n, int disc, int n_base, int nu1, int nu2, double omega, double base_tol,
                     int base_max_iter, const double *b, double *c) {
-    if ((dim != 2 && dim != 3) || !ref_valid_n(n) || !ref_valid_n(n_base) || n_base > n || nu1 < 0 || nu2 < 0)
+    if ((dim != 2 && dim != 3) || (disc != REF_DISC_FD && disc != REF_DISC_Q1) || !ref_chain_ok(n, n_base) ||
+        nu1 < 0 || nu2 < 0)
         return REF_ERR_ARG;
     long N = ref_points(dim, n);
     if (n == n_base) {
         if (n == 1) {
-            ref_base_solve(dim, n, b, c);
+            ref_base_solve(dim, n, disc, b, c);
         } else {
-            int k = ref_cg(dim, n, b, c, base_tol, base_max_iter);
+            int k = ref_cg_disc(dim, n, disc, b, c, base_tol, base_max_iter);
             if (k < 0) return k;
         }
         return REF_OK;
@@ -250,22 +357,28 @@ int ref_vcycle_base(int dim, int n, int n_base, int nu1, int nu2, double omega, 
 
     memset(c, 0, sizeof(double) * N);
     for (int s = 0; s < nu1; s++) {                 /* pre-smooth */
-        ref_jacobi(dim, n, omega, b, c, tmp);
+        ref_jacobi_disc(dim, n, disc, omega, b, c, tmp);
         memcpy(c, tmp, sizeof(double) * N);
     }
-    ref_residual(dim, n, b, c, tmp);                /* residual, restrict */
-    ref_restrict(dim, n, tmp, bc);
-    int st = ref_vcycle_base(dim, n_c, n_base, nu1, nu2, omega, base_tol, base_max_iter, bc, ec);
+    ref_residual_d(dim, n, disc, b, c, tmp);        /* residual, restrict */
+    ref_restrict_disc(dim, n, disc, tmp, bc);
+    int st = ref_vcycle_disc(dim, n_c, disc, n_base, nu1, nu2, omega, base_tol, base_max_iter, bc, ec);
     if (st == REF_OK) {
         ref_prolong(dim, n_c, ec, tmp);             /* prolongate, add */
         for (long p = 0; p < N; p++) c[p] += tmp[p];
         for (int s = 0; s < nu2; s++) {             /* post-smooth */
-            ref_jacobi(dim, n, omega, b, c, tmp);
+            ref_jacobi_disc(dim, n, disc, omega, b, c, tmp);
             memcpy(c, tmp, sizeof(double) * N);
         }
     }
     free(tmp); free(bc); free(ec);
     return st;
+}
+
+int ref_vcycle_base(int dim, int n, int n_base, int nu1, int nu2, double omega, double base_tol,
+                    int base_max_iter, const double *b, double *c) {
+    if (!ref_valid_n(n) || !ref_valid_n(n_base)) return REF_ERR_ARG;
+    return ref_vcycle_disc(dim, n, REF_DISC_FD, n_base, nu1, nu2, omega, base_tol, base_max_iter, b, c);
 }
 
 int ref_vcycle(int dim, int n, int nu1, int nu2, double omega, const double *b, double *c) {
@@ -309,6 +422,7 @@ typedef struct {
     int base_n;                /* points per dimension of the base level (<= 1: one point) */
     double base_tol;           /* CG on a base of more than one point: ||r||_2 <= base_tol */
     int base_max_iter;         /* ... at most this many steps */
+    int disc;                  /* REF_DISC_FD or REF_DISC_Q1 */
 } ref_ir_opts;
 
 typedef struct {
@@ -323,7 +437,11 @@ typedef struct {
 int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *o,
                  ref_ir_result *res, double *history, int hist_cap) {
     if ((dim != 2 && dim != 3) || !o || !res) return REF_ERR_ARG;
-    if (!ref_valid_n(n)) return REF_ERR_SHAPE;
+    const int disc = o->disc;
+    if (disc != REF_DISC_FD && disc != REF_DISC_Q1) return REF_ERR_ARG;
+    const int nbase = o->base_n > 1 ? o->base_n : 1;
+    if (n < 1) return REF_ERR_SHAPE;
+    if (!ref_chain_ok(n, nbase)) return nbase == 1 ? REF_ERR_SHAPE : REF_ERR_ARG;
     long N = ref_points(dim, n);
     memset(res, 0, sizeof(*res));
     double nb = ref_norm2(b, N);
@@ -334,8 +452,6 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         return REF_OK;
     }
     const int cycles = o->cycles > 1 ? o->cycles : 1;
-    const int nbase = o->base_n > 1 ? o->base_n : 1;
-    if (!ref_valid_n(nbase) || nbase > n) return REF_ERR_ARG;
     double *r = (double *)malloc(sizeof(double) * N);
     double *rl = (double *)malloc(sizeof(double) * N);
     double *c = (double *)malloc(sizeof(double) * N);
@@ -348,7 +464,7 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
     }
 
     if (!o->use_initial_guess) memset(u, 0, sizeof(double) * N);
-    ref_residual(dim, n, b, u, r);        /* r_high := b_high - A_high u_high */
+    ref_residual_d(dim, n, disc, b, u, r); /* r_high := b_high - A_high u_high */
     int st = REF_OK;
     int k = 0;
     for (;;) {
@@ -361,25 +477,26 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         double alpha = o->residual_scaling ? ref_norminf(r, N) : 1.0;
         double inv_alpha = 1.0 / alpha;
         for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];        /* scale */
-        int vs = ref_vcycle_base(dim, n, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter, rl,
-                                 c);                                    /* one V-cycle */
+        int vs = ref_vcycle_disc(dim, n, disc, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter,
+                                 rl, c);                                /* one V-cycle */
         for (int j = 1; j < cycles && vs == REF_OK; j++) {              /* further cycles */
-            ref_residual(dim, n, rl, c, t);                             /* t = r/alpha - A c */
-            vs = ref_vcycle_base(dim, n, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter, t, e);
+            ref_residual_d(dim, n, disc, rl, c, t);                     /* t = r/alpha - A c */
+            vs = ref_vcycle_disc(dim, n, disc, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter,
+                                 t, e);
             for (long p = 0; p < N; p++) c[p] += e[p];
         }
         if (vs != REF_OK) { st = vs; break; }
         for (long p = 0; p < N; p++) u[p] += alpha * c[p];             /* update u */
         if (o->recursive_residual) {                                   /* update r */
-            ref_apply_A(dim, n, c, ac);
+            ref_apply_A_disc(dim, n, disc, c, ac);
             for (long p = 0; p < N; p++) r[p] -= alpha * ac[p];
         } else {
-            ref_residual(dim, n, b, u, r);
+            ref_residual_d(dim, n, disc, b, u, r);
         }
         k++;
     }
     res->iterations = k;
-    ref_residual(dim, n, b, u, ac);
+    ref_residual_d(dim, n, disc, b, u, ac);
     res->true_rel_residual = ref_norm2(ac, N) / nb;
     free(r); free(rl); free(c); free(ac); free(t); free(e);
     return st;

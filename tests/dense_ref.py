@@ -14,6 +14,18 @@ def lap1d(n):
     return (2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)) / h**2
 
 
+def stiff1d(n):
+    """1-D linear-element stiffness matrix tridiag(-1, 2, -1) / h."""
+    h = 1.0 / (n + 1)
+    return (2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)) / h
+
+
+def mass1d(n):
+    """1-D linear-element mass matrix h tridiag(1/6, 2/3, 1/6)."""
+    h = 1.0 / (n + 1)
+    return h * (4 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)) / 6
+
+
 def kron_all(mats):
     out = mats[0]
     for m in mats[1:]:
@@ -25,6 +37,18 @@ def lap(dim, n):
     """Finite-difference -Laplace with zero Dirichlet boundary: sum over axes."""
     I, T = np.eye(n), lap1d(n)
     return sum(kron_all([T if a == b else I for b in range(dim)]) for a in range(dim))
+
+
+def q1(dim, n):
+    """Bilinear / trilinear finite-element stiffness matrix: the tensor-product
+    basis makes it sum over axes a of (stiffness along a) x (mass along the
+    others)."""
+    I, K, M = np.eye(n), stiff1d(n), mass1d(n)
+    return sum(kron_all([K if a == b else M for b in range(dim)]) for a in range(dim))
+
+
+def operator(dim, n, disc="fd"):
+    return q1(dim, n) if disc == "q1" else lap(dim, n)
 
 
 def restrict1d(nf):
@@ -57,23 +81,25 @@ def prolong(dim, nc):
     return kron_all([prolong1d(nc)] * dim)
 
 
-def jacobi_iteration_matrix(dim, n, omega):
+def jacobi_iteration_matrix(dim, n, omega, disc="fd"):
     """Error propagation of one damped-Jacobi sweep: S = I - omega D^-1 A."""
-    A = lap(dim, n)
+    A = operator(dim, n, disc)
     return np.eye(A.shape[0]) - omega * A / np.diag(A)[:, None]
 
 
-def vcycle_matrix(dim, n, nu1=2, nu2=2, omega=0.8, base_n=1):
+def vcycle_matrix(dim, n, nu1=2, nu2=2, omega=0.8, base_n=1, disc="fd"):
     """Dense V-cycle operator M with c = M b, from the two-grid error propagation
     E = S^nu2 (I - P M_c R A) S^nu1 and M = (I - E) A^-1, recursively down to
-    the exact solve on the base level of base_n points per dimension."""
-    A = lap(dim, n)
+    the exact solve on the base level of base_n points per dimension.  The
+    restriction R is full weighting (fd) or P^T (q1)."""
+    A = operator(dim, n, disc)
     if n == base_n:
         return np.linalg.inv(A)
     nc = (n - 1) // 2
-    Mc = vcycle_matrix(dim, nc, nu1, nu2, omega, base_n)
-    S = jacobi_iteration_matrix(dim, n, omega)
-    R, P = restrict(dim, n), prolong(dim, nc)
+    Mc = vcycle_matrix(dim, nc, nu1, nu2, omega, base_n, disc)
+    S = jacobi_iteration_matrix(dim, n, omega, disc)
+    P = prolong(dim, nc)
+    R = P.T if disc == "q1" else restrict(dim, n)
     I = np.eye(A.shape[0])
     E = np.linalg.matrix_power(S, nu2) @ (I - P @ Mc @ R @ A) @ np.linalg.matrix_power(S, nu1)
     return (I - E) @ np.linalg.inv(A)
