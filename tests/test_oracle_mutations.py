@@ -15,13 +15,21 @@ MUTATIONS = {
                           "out[idx] = (2.0 * dim * centre + nb) * inv_h2;"),
     "operator_h_scale": ("double inv_h2 = 1.0 / (h * h);", "double inv_h2 = 1.0 / h;"),
     "jacobi_damping": ("out[p] = c[p] + omega * r[p] / diag;", "out[p] = c[p] + r[p] / diag;"),
-    "restrict_weights": ("static const double w[3] = {0.25, 0.5, 0.25};",
-                         "static const double w[3] = {0.25, 0.25, 0.5};"),
+    "restrict_weights": ("const double w[3] = {0.25 * g, 0.5 * g, 0.25 * g};",
+                         "const double w[3] = {0.25 * g, 0.25 * g, 0.5 * g};"),
     "restrict_offset": ("int fi = 2 * I + ox, fj = 2 * J + oy", "int fi = 2 * I + ox + 1, fj = 2 * J + oy"),
     "prolong_weight": ("if (d == 1 || d == -1) return 0.5;", "if (d == 1 || d == -1) return 0.25;"),
     "coarse_correction_sign": ("for (long p = 0; p < N; p++) c[p] += tmp[p];",
                                "for (long p = 0; p < N; p++) c[p] -= tmp[p];"),
-    "base_solve": ("c[0] = b[0] / (2.0 * dim / (h * h));", "c[0] = b[0] / (2.0 * dim / h);"),
+    "base_solve": ("c[0] = b[0] / ref_diag(dim, n, disc);", "c[0] = b[0] / (2.0 * ref_diag(dim, n, disc));"),
+    "fd_diag": ("return 2.0 * dim / (h * h);", "return 2.0 * dim / h;"),
+    "q1_element_mass": ("const double m1[2][2] = {{h / 3.0, h / 6.0}, {h / 6.0, h / 3.0}};",
+                        "const double m1[2][2] = {{h / 3.0, h / 4.0}, {h / 4.0, h / 3.0}};"),
+    "q1_restrict_scale": ("const double g = disc == REF_DISC_Q1 ? 2.0 : 1.0;",
+                          "const double g = disc == REF_DISC_Q1 ? 1.0 : 1.0;"),
+    "q1_diag": ("* dim * pow(h, dim - 2) / pow(3.0, dim - 1);", "* dim * pow(h, dim - 2) / pow(3.0, dim);"),
+    "q1_cell_range": ("for (int cx = 0; cx <= n; cx++)", "for (int cx = 0; cx < n; cx++)"),
+    "chain_stops_early": ("while (n > n_base) {", "while (n > n_base + 1) {"),
     "no_post_smoothing": ("for (int s = 0; s < nu2; s++) {             /* post-smooth */",
                           "for (int s = 0; s < 0; s++) {             /* post-smooth */"),
     "scaling_not_compensated": ("u[p] += alpha * c[p];", "u[p] += c[p];"),
@@ -41,6 +49,7 @@ def test_pins_catch_planted_mistake(tmp_path, name):
     (dst / "mg_ref.c").write_text(src.replace(old, new))
     env = dict(os.environ, MGREF_ORACLE_DIR=str(dst))
     proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                           os.path.join(ROOT, "tests", "test_oracle_q1.py")],
                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert proc.returncode != 0, f"pins did not catch mutation {name}:\n{proc.stdout[-2000:]}"
