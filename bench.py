@@ -223,6 +223,35 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
             torch.cuda.empty_cache()
         res[f"cg_base_{n}"] = entry
 
+        # Q1 finite elements (the paper's discretisation, Section 5) on the
+        # main grid and on the paper's own meshes n = c 2^k - 1 (Section 6),
+        # whose hierarchies end on a (c-1)^D base solved by CG
+        entry = {}
+        for dim, nq in [(3, n)] + [(3, g) for g in W.paper_grid_sizes(3)] + [(2, W.paper_grid_sizes(2)[-1])]:
+            Lq = mgir.full_levels(nq)
+            bq = torch.from_numpy(W.q1_load_vector(dim, nq, seed=12)).to(dev)
+            e = {"dim": dim, "n": nq, "levels": Lq, "dof": float(nq**dim)}
+            for name in ("f16", "f64"):
+                log(f"[bench] Q1 {dim}-D n={nq}, map {name}")
+                s = mgir.Solver(dim, nq, W.precision_map(name, Lq), disc="q1", residual_scaling=name != "f64",
+                                device=dev)
+                u0 = torch.zeros_like(bq)
+                s.solve(bq, u0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    _, r = s.solve(bq, u0)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / steps * 1e3
+                e[name] = {"ms": ms, "dof_per_s": nq**dim / ms * 1e3, "iterations": r.iterations,
+                           "rel_residual": r.rel_residual, "status": r.status}
+                del s, u0
+                torch.cuda.empty_cache()
+            e["speedup_f16_vs_f64"] = e["f64"]["ms"] / e["f16"]["ms"]
+            entry[f"{dim}d_{nq}"] = e
+            del bq
+        res["q1_fem"] = entry
+
     def timed(fn):
         fn()
         torch.cuda.synchronize()

@@ -44,7 +44,7 @@ extern "C" {
 typedef enum {
     MG_OK = 0,
     MG_ERR_ARG = -1,            /* null pointer, out-of-range option or index */
-    MG_ERR_SHAPE = -2,          /* n is not 2^m - 1, or dim is not 2 or 3 */
+    MG_ERR_SHAPE = -2,          /* n not of an accepted form, dim not 2 or 3, base level too large */
     MG_ERR_PREC = -3,           /* unknown precision code in a level map */
     MG_ERR_WORKSPACE = -4,      /* no workspace bound, or bound one too small / misaligned */
     MG_ERR_HIP = -5,            /* a HIP runtime call failed (message in mg_last_error) */
@@ -56,6 +56,18 @@ typedef enum {
 /* Storage format of one level's vectors.  FP16/BF16/FP32 levels accumulate in
  * FP32 registers, FP64 levels in FP64; every store rounds to nearest even. */
 typedef enum { MG_F64 = 0, MG_F32 = 1, MG_F16 = 2, MG_BF16 = 3 } mg_prec_t;
+
+/* Discretisation of -Laplace(u) = f with zero boundary values (Section 5).
+ * MG_DISC_FD: the (2D+1)-point finite-difference stencil, A = L / h^2 with
+ *   L = [2D centre, -1 face neighbours]; b holds f at the interior nodes.
+ * MG_DISC_Q1: bilinear (2-D) / trilinear (3-D) finite elements, the
+ *   discretisation of the paper's measurements: A_ij = integral of
+ *   grad(phi_i) . grad(phi_j), the 9-point stencil [8, -1 (8x)] / 3 in 2-D
+ *   and h [32, 0 (faces), -2 (edges), -1 (corners)] / 12 in 3-D; b is the
+ *   load vector (integral of f phi_i; h^dim f_i when the mass is lumped).
+ *   Restriction is P^T and the coarse operators are the Q1 matrices of the
+ *   coarser meshes (= the Galerkin products P^T A P). */
+typedef enum { MG_DISC_FD = 0, MG_DISC_Q1 = 1 } mg_disc_t;
 
 typedef struct {
     int nu1;                 /* pre-smoothing sweeps (Algorithm 1), default 2 */
@@ -87,6 +99,10 @@ typedef struct {
                                 paper's bound for residuals scaled to norm one,
                                 Section 4.2) */
     int base_max_iter;       /* ... at most this many CG steps; 0: min(10000, base points) */
+    int discretization;      /* an mg_disc_t, default MG_DISC_FD.  MG_DISC_Q1 runs its own
+                                kernels (no fused forms, no launch-shape tuning:
+                                opt.autotune is ignored and mg_set_shape returns
+                                MG_ERR_STATE); single-grid handles only, as rescale_half. */
 } mg_options_t;
 
 typedef struct {
@@ -104,14 +120,19 @@ void mg_default_options(mg_options_t *opt);
 
 /* Create a solver for one grid.
  *   dim        2 or 3.
- *   n          interior points per dimension, 2^m - 1 with 2 <= m <= 12 in
- *              2-D and 2 <= m <= 10 in 3-D (n >= 3: the finest level is
- *              smoothed and restricted at least once).
- *   nlevels    0 for the full hierarchy n, (n-1)/2, ..., 1 (m levels, the
- *              one-point base solved exactly); 2..m for the first nlevels of
- *              it, whose last level (2^(m-nlevels+1) - 1 points per
- *              dimension) is solved by CG (Section 4.2; opt.base_tol,
- *              opt.base_max_iter).
+ *   n          interior points per dimension, n <= 1023 in 3-D.
+ *              MG_DISC_FD: n = 2^m - 1 with m >= 2 (n <= 4095 in 2-D).
+ *              MG_DISC_Q1: any odd n >= 3 (n <= 8191 in 2-D), in particular
+ *              the paper's c 2^k - 1 with odd c
+ *              (meshes of 193^3 .. 289^3 and 4097^2 .. 6145^2 vertices,
+ *              Section 6).
+ *   nlevels    0 for the full hierarchy n, (n-1)/2, ... while the size is odd
+ *              and above 1: m levels, ending on one point (solved exactly)
+ *              for n = 2^m - 1, otherwise on c - 1 points per dimension
+ *              (solved by CG); 2..m for the first nlevels of it, whose last
+ *              level is solved by CG (Section 4.2; opt.base_tol,
+ *              opt.base_max_iter).  A CG base level runs in one workgroup and
+ *              may hold at most 262144 points (MG_ERR_SHAPE beyond).
  *   level_prec one entry per level used, FINEST FIRST: level_prec[0] is the
  *              finest grid (the paper's level L), the last entry the base
  *              level (the paper's level 0).  NULL means all MG_F64.

@@ -36,6 +36,7 @@ SOURCES = (("mg_kernels.hip", True), ("mg_multi.hip", True), ("mg_tail.hip", Tru
            ("mg_smooth_restrict.hip", True),
            ("mg_rescale.hip", True),
            ("mg_cg.hip", True),
+           ("mg_q1.hip", True),
            ("mg_api.cpp", False))
 
 

@@ -87,6 +87,8 @@ struct mg_ctx {
     hipEvent_t ev_norm = nullptr;     // single grid: the norm readback of a step is done
     int outer_parts = 0;
     bool tail_on = true;
+    bool q1 = false;       // Q1 finite elements (mg_q1.hip kernels) instead of finite differences
+    size_t off_q1r = 0;    // Q1: fine residual ahead of its restriction (any level's, accumulator format)
     bool fuse_on = true;   // allow the fused last sweep + update on the finest level
     bool fused = false;    // ... and it is in use
     Shape fsh{4, 16, 256, 1, 4};
@@ -148,6 +150,8 @@ int acc_prec(int prec) { return prec == P_F64 ? P_F64 : P_F32; }
 bool half_prec(int prec) { return prec == P_F16 || prec == P_BF16; }
 
 long points(int D, int n) { return D == 3 ? (long)n * n * n : (long)n * n; }
+// Largest base level the one-workgroup CG solves (64^3 points).
+constexpr long kMaxBasePoints = 262144;
 
 bool valid_prec(int p) { return p >= 0 && p <= 3; }
 
@@ -246,6 +250,43 @@ double sb(int prec) { return (double)prec_bytes(prec); }
         if (e_ != hipSuccess) return e_;                  \
     } while (0)
 
+// Launches that differ between the discretisations.  The Q1 forms have no
+// launch shapes and no fused variants (mg_q1.hip).
+hipError_t level_sweep(mg_ctx *h, int l, int prec, const void *b, const void *c, void *c_out, hipStream_t st) {
+    const LevelPlan &L = h->lv[l];
+    if (h->q1) return launch_q1_sweep(h->dim, prec, L.n, L.P, b, c, c_out, h->opt.omega, st);
+    return launch_sweep(h->dim, prec, L.P, b, c, c_out, h->opt.omega, L.shs[SH_SWEEP], st);
+}
+
+hipError_t level_first(mg_ctx *h, int l, int prec, const void *b, const double *r, const double *sc, void *b_out,
+                       void *c_out, bool two, hipStream_t st) {
+    const LevelPlan &L = h->lv[l];
+    if (h->q1) return launch_q1_first(h->dim, prec, L.n, L.P, b, r, sc, b_out, c_out, h->opt.omega, st);
+    return launch_smooth_first(h->dim, prec, L.P, b, r, sc, b_out, c_out, h->opt.omega, two, L.shs[SH_SMOOTH], st);
+}
+
+hipError_t level_restrict(mg_ctx *h, int l, int pf, int pc, const void *b, const void *c, void *bc, hipStream_t st) {
+    const LevelPlan &L = h->lv[l];
+    if (h->q1) return launch_q1_restrict(h->dim, pf, pc, L.n, L.P, b, c, h->ws + h->off_q1r, bc, st);
+    return launch_restrict(h->dim, pf, pc, L.P, b, c, bc, L.rsh, st);
+}
+
+hipError_t level_prolong(mg_ctx *h, int l, int pf, int pc, const void *c, const void *ec, const void *b, void *c_out,
+                         hipStream_t st) {
+    const LevelPlan &L = h->lv[l];
+    if (h->q1) return launch_q1_prolong(h->dim, pf, pc, L.n, L.P, c, ec, b, c_out, h->opt.omega, st);
+    return launch_prolong(h->dim, pf, pc, L.P, c, ec, b, c_out, h->opt.omega, true, L.shs[SH_PROLONG], st);
+}
+
+// r = b - A U on the finest level from the dense b (see launch_resid_flat).
+hipError_t finest_resid(mg_ctx *h, const double *b, const double *U, double *R, double *uout, hipStream_t st) {
+    const LevelPlan &L = h->lv[0];
+    const double hh = 1.0 / (double)(L.n + 1);
+    if (h->q1)
+        return launch_q1_resid_flat(h->dim, L.n, L.P, b, U, R, uout, h->dim == 3 ? hh : 1.0, part(h), st);
+    return launch_resid_flat(h->dim, L.n, L.P, b, U, R, uout, 1.0 / (hh * hh), part(h), st);
+}
+
 // Pre-smoothing of level l from c = 0 into C[0] (plus extra sweeps), with the
 // right-hand side taken from B_l, or for the finest level of a refinement step
 // from the FP64 residual (scaled and cast on the fly, b-hat written to B_0).
@@ -254,21 +295,18 @@ hipError_t enq_presmooth(mg_ctx *h, hipStream_t st, int l, bool from_R) {
     const int D = h->dim;
     const double N = (double)points(D, L.n);
     const double s = sb(L.prec);
-    const bool two = h->opt.nu1 >= 2;
+    const bool two = h->opt.nu1 >= 2 && !h->q1;
+    (void)D;
     if (from_R) {
         RUN(h, st, two ? "smooth2_scaled" : "smooth1_scaled", l, N * (8 + 2 * s),
-            launch_smooth_first(D, L.prec, L.P, nullptr, Rbuf(h), scal(h), bbuf(h, l), cbuf(h, l, 0), h->opt.omega,
-                                two, L.shs[SH_SMOOTH], st));
+            level_first(h, l, L.prec, nullptr, Rbuf(h), scal(h), bbuf(h, l), cbuf(h, l, 0), two, st));
     } else {
         RUN(h, st, two ? "smooth2" : "smooth1", l, N * 2 * s,
-            launch_smooth_first(D, L.prec, L.P, bbuf(h, l), nullptr, nullptr, nullptr, cbuf(h, l, 0), h->opt.omega,
-                                two, L.shs[SH_SMOOTH], st));
+            level_first(h, l, L.prec, bbuf(h, l), nullptr, nullptr, nullptr, cbuf(h, l, 0), two, st));
     }
     int cur = 0;
     for (int k = two ? 2 : 1; k < h->opt.nu1; ++k) {
-        RUN(h, st, "sweep", l, N * 3 * s,
-            launch_sweep(D, L.prec, L.P, bbuf(h, l), cbuf(h, l, cur), cbuf(h, l, cur ^ 1), h->opt.omega,
-                         L.shs[SH_SWEEP], st));
+        RUN(h, st, "sweep", l, N * 3 * s, level_sweep(h, l, L.prec, bbuf(h, l), cbuf(h, l, cur), cbuf(h, l, cur ^ 1), st));
         cur ^= 1;
     }
     h->cur[l] = cur;
@@ -286,7 +324,7 @@ hipError_t enq_restrict(mg_ctx *h, hipStream_t st, int l, const void *b) {
         const double Nc = (double)points(h->dim, C.n);
         void *t = h->ws + C.off_t;
         RUN(h, st, "resid_restrict", l, N * 2 * sb(L.prec) + Nc * sb(pa),
-            launch_restrict(h->dim, L.prec, pa, L.P, b, cbuf(h, l, h->cur[l]), t, L.rsh, st));
+            level_restrict(h, l, L.prec, pa, b, cbuf(h, l, h->cur[l]), t, st));
         RUN(h, st, "rescale_max", l + 1, Nc * sb(pa),
             launch_absmax(pa, t, (long)C.elems, at_ws<double>(h, h->off_rpart), rscal(h, l + 1), st));
         RUN(h, st, "rescale_cast", l + 1, Nc * (sb(pa) + sb(C.prec)),
@@ -294,7 +332,7 @@ hipError_t enq_restrict(mg_ctx *h, hipStream_t st, int l, const void *b) {
         return hipSuccess;
     }
     RUN(h, st, "resid_restrict", l, bytes,
-        launch_restrict(h->dim, L.prec, C.prec, L.P, b, cbuf(h, l, h->cur[l]), bbuf(h, l + 1), L.rsh, st));
+        level_restrict(h, l, L.prec, C.prec, b, cbuf(h, l, h->cur[l]), bbuf(h, l + 1), st));
     return hipSuccess;
 }
 
@@ -306,11 +344,13 @@ hipError_t enq_coarse(mg_ctx *h, hipStream_t st, int l) {
         const int maxit = h->opt.base_max_iter > 0 ? h->opt.base_max_iter : (int)std::min<long>(10000, N);
         RUN(h, st, "cg_base", l, (double)N * 2 * sb(L.prec),
             launch_cg_base(h->dim, L.prec, L.n, L.P, bbuf(h, l), cbuf(h, l, 0), h->ws + L.off_cg,
-                           cg_scratch_stride(L.prec, L.elems), h->opt.base_tol, maxit, st));
+                           cg_scratch_stride(L.prec, L.elems), h->opt.base_tol, maxit, h->q1 ? 1 : 0, st));
         h->cur[l] = 0;
         return hipSuccess;
     }
-    RUN(h, st, "coarse_solve", l, 2 * sb(L.prec), launch_coarse(h->dim, L.prec, bbuf(h, l), cbuf(h, l, 0), st));
+    RUN(h, st, "coarse_solve", l, 2 * sb(L.prec),
+        h->q1 ? launch_q1_coarse(h->dim, L.prec, bbuf(h, l), cbuf(h, l, 0), st)
+              : launch_coarse(h->dim, L.prec, bbuf(h, l), cbuf(h, l, 0), st));
     h->cur[l] = 0;
     return hipSuccess;
 }
@@ -328,14 +368,13 @@ hipError_t enq_prolong(mg_ctx *h, hipStream_t st, int l, const void *b) {
         RUN(h, st, "rescale_widen", l + 1, Nc * (sb(C.prec) + sb(pa)),
             launch_scale_widen(C.prec, pa, cbuf(h, l + 1, h->cur[l + 1]), rscal(h, l + 1), t, (long)C.elems, st));
         RUN(h, st, "prolong_sweep", l, N * 3 * sb(L.prec) + Nc * sb(pa),
-            launch_prolong(h->dim, L.prec, pa, L.P, cbuf(h, l, cur), t, b, cbuf(h, l, cur ^ 1), h->opt.omega, true,
-                           L.shs[SH_PROLONG], st));
+            level_prolong(h, l, L.prec, pa, cbuf(h, l, cur), t, b, cbuf(h, l, cur ^ 1), st));
         h->cur[l] = cur ^ 1;
         return hipSuccess;
     }
     RUN(h, st, "prolong_sweep", l, bytes,
-        launch_prolong(h->dim, L.prec, C.prec, L.P, cbuf(h, l, cur), cbuf(h, l + 1, h->cur[l + 1]), b,
-                       cbuf(h, l, cur ^ 1), h->opt.omega, true, L.shs[SH_PROLONG], st));
+        level_prolong(h, l, L.prec, C.prec, cbuf(h, l, cur), cbuf(h, l + 1, h->cur[l + 1]), b, cbuf(h, l, cur ^ 1),
+                      st));
     h->cur[l] = cur ^ 1;
     return hipSuccess;
 }
@@ -345,9 +384,7 @@ hipError_t enq_post(mg_ctx *h, hipStream_t st, int l, const void *b, bool skip_l
     const double N = (double)points(h->dim, L.n);
     for (int k = 1; k < h->opt.nu2 - (skip_last ? 1 : 0); ++k) {
         const int cur = h->cur[l];
-        RUN(h, st, "sweep", l, N * 3 * sb(L.prec),
-            launch_sweep(h->dim, L.prec, L.P, b, cbuf(h, l, cur), cbuf(h, l, cur ^ 1), h->opt.omega,
-                         L.shs[SH_SWEEP], st));
+        RUN(h, st, "sweep", l, N * 3 * sb(L.prec), level_sweep(h, l, L.prec, b, cbuf(h, l, cur), cbuf(h, l, cur ^ 1), st));
         h->cur[l] = cur ^ 1;
     }
     return hipSuccess;
@@ -366,9 +403,7 @@ hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const
         const double N = (double)points(h->dim, L.n);
         for (int k = 0; k < h->opt.nu1; ++k) {
             const int cur = h->cur[0];
-            RUN(h, st, "sweep", 0, N * 3 * sb(L.prec),
-                launch_sweep(h->dim, L.prec, L.P, rhs, cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), h->opt.omega,
-                             L.shs[SH_SWEEP], st));
+            RUN(h, st, "sweep", 0, N * 3 * sb(L.prec), level_sweep(h, 0, L.prec, rhs, cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), st));
             h->cur[0] = cur ^ 1;
         }
         return enq_restrict(h, st, 0, rhs);
@@ -395,15 +430,12 @@ hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const
         // FP64 baseline without scaling: the residual is the right-hand side
         LevelPlan &L = h->lv[0];
         const double N = (double)points(h->dim, L.n);
-        const bool two = h->opt.nu1 >= 2;
+        const bool two = h->opt.nu1 >= 2 && !h->q1;
         RUN(h, st, two ? "smooth2" : "smooth1", 0, N * 16,
-            launch_smooth_first(h->dim, P_F64, L.P, Rbuf(h), nullptr, nullptr, nullptr, cbuf(h, 0, 0), h->opt.omega,
-                                two, L.shs[SH_SMOOTH], st));
+            level_first(h, 0, P_F64, Rbuf(h), nullptr, nullptr, nullptr, cbuf(h, 0, 0), two, st));
         int cur = 0;
         for (int k = two ? 2 : 1; k < h->opt.nu1; ++k) {
-            RUN(h, st, "sweep", 0, N * 24,
-                launch_sweep(h->dim, P_F64, L.P, Rbuf(h), cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), h->opt.omega,
-                             L.shs[SH_SWEEP], st));
+            RUN(h, st, "sweep", 0, N * 24, level_sweep(h, 0, P_F64, Rbuf(h), cbuf(h, 0, cur), cbuf(h, 0, cur ^ 1), st));
             cur ^= 1;
         }
         h->cur[0] = cur;
@@ -512,7 +544,9 @@ RShape default_srshape(const LevelPlan &L) {
 void set_fused(mg_ctx *h, bool on) {
     h->fused = on && fusion_possible(h);
     const LevelPlan &L = h->lv[0];
-    h->outer_parts = h->fused ? sweep_update_blocks(L.P, h->fsh) : stencil_blocks(h->dim, L.P, L.osh);
+    h->outer_parts = h->q1      ? q1_outer_blocks(h->dim, L.n)
+                     : h->fused ? sweep_update_blocks(L.P, h->fsh)
+                                : stencil_blocks(h->dim, L.P, L.osh);
 }
 
 // One refinement step of Algorithm 2 (scale and cast, V-cycle, update) plus
@@ -543,6 +577,11 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
         RUN(h, st, "sweep_update", 0, N * (32 + 2 * sb(L.prec)),
             launch_sweep_update(L.prec, L.P, cbuf(h, 0, h->cur[0]), bbuf(h, 0), Rbuf(h), Ubuf(h), scal(h), hh * hh,
                                 h->opt.omega, part(h), h->fsh, st));
+    } else if (h->q1) {
+        // U += alpha h^(2-D) c, R -= alpha S c
+        RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
+            launch_q1_outer(h->dim, L.prec, L.n, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h),
+                            h->dim == 3 ? 1.0 / hh : 1.0, part(h), st));
     } else {
         RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
             launch_outer_update(h->dim, L.prec, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h), hh * hh,
@@ -822,6 +861,7 @@ void mg_default_options(mg_options_t *o) {
     o->cycles_per_step = 1;
     o->base_tol = 1e-4;
     o->base_max_iter = 0;
+    o->discretization = MG_DISC_FD;
 }
 
 const char *mg_status_string(mg_status_t s) {
@@ -845,18 +885,33 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
                      const mg_options_t *opt) {
     if (!out) return fail(MG_ERR_ARG, "out is null");
     if (dim != 2 && dim != 3) return fail(MG_ERR_SHAPE, "dim must be 2 or 3, got %d", dim);
-    if (n < 3 || ((n + 1) & n) != 0 || n > 4095)
-        return fail(MG_ERR_SHAPE, "n must be 2^m - 1 with 2 <= m <= 12, got %d", n);
-    if (dim == 3 && n > 1023)
-        return fail(MG_ERR_SHAPE, "3-D grids are limited to n <= 1023 (one block must hold three fine rows)");
-    int m = 0;
-    while ((1 << m) < n + 1) ++m;
-    if (nlevels != 0 && (nlevels < 2 || nlevels > m))
-        return fail(MG_ERR_ARG, "nlevels must be 0 (the full hierarchy, %d levels) or 2..%d, got %d", m, m, nlevels);
-    if (nlevels) m = nlevels;  // from here on m counts the levels used
     mg_options_t o;
     mg_default_options(&o);
     if (opt) o = *opt;
+    if (o.discretization != MG_DISC_FD && o.discretization != MG_DISC_Q1)
+        return fail(MG_ERR_ARG, "discretization must be MG_DISC_FD or MG_DISC_Q1, got %d", o.discretization);
+    const bool q1 = o.discretization == MG_DISC_Q1;
+    if (q1) {
+        if (n < 3 || n % 2 == 0 || n > 8191)
+            return fail(MG_ERR_SHAPE, "Q1: n must be odd with 3 <= n <= 8191, got %d", n);
+    } else if (n < 3 || ((n + 1) & n) != 0 || n > 4095) {
+        return fail(MG_ERR_SHAPE, "n must be 2^m - 1 with 2 <= m <= 12, got %d", n);
+    }
+    if (dim == 3 && n > 1023)
+        return fail(MG_ERR_SHAPE, "3-D grids are limited to n <= 1023 (one block must hold three fine rows)");
+    // levels of the full hierarchy: halve while the size is odd and above one
+    int m = 1;
+    for (int t = n; t > 1 && t % 2 == 1; t = (t - 1) / 2) ++m;
+    if (nlevels != 0 && (nlevels < 2 || nlevels > m))
+        return fail(MG_ERR_ARG, "nlevels must be 0 (the full hierarchy, %d levels) or 2..%d, got %d", m, m, nlevels);
+    if (nlevels) m = nlevels;  // from here on m counts the levels used
+    {
+        int nb = n;
+        for (int l = 1; l < m; ++l) nb = (nb - 1) / 2;
+        if (points(dim, nb) > kMaxBasePoints)
+            return fail(MG_ERR_SHAPE, "base level of %d^%d points exceeds the %ld points of the one-workgroup CG; "
+                        "use more levels", nb, dim, (long)kMaxBasePoints);
+    }
     if (!(o.base_tol >= 0.0) || o.base_max_iter < 0)
         return fail(MG_ERR_ARG, "base_tol must be >= 0 and base_max_iter >= 0");
     if (o.nu1 < 1 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
@@ -877,6 +932,8 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     h->n = n;
     h->nl = m;
     h->opt = o;
+    h->q1 = q1;
+    if (q1) h->tail_on = h->fuse_on = h->fuse_sr_on = false;
     h->lv.resize(m);
     size_t off = 0;
     int nn = n;
@@ -894,7 +951,9 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         off += bytes;
         L.off_c[1] = off;
         off += bytes;
-        if (nn > 1) {
+        // (launch shapes of the finite-difference kernels; the Q1 kernels have
+        // none, but the finest level's sizes the reduction partials)
+        if (nn > 1 && (!q1 || l == 0)) {
             L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = pick_shape(dim, L.P, L.prec);
             L.osh = pick_shape(dim, L.P, P_F64);  // FP64 rows dominate the update's registers
             L.rsh = pick_rshape(dim, L.P, L.prec);
@@ -905,6 +964,12 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         LevelPlan &B = h->lv[m - 1];
         B.off_cg = off;
         off += 4 * cg_scratch_stride(B.prec, B.elems);
+    }
+    if (q1) {
+        size_t rb = 0;
+        for (int l = 0; l + 1 < m; ++l) rb = std::max(rb, q1_resid_bytes(dim, h->lv[l].prec, h->lv[l].P));
+        h->off_q1r = off;
+        off += align_up(rb, 256);
     }
     const size_t fin = align_up(h->lv[0].elems * sizeof(double), 256);
     h->off_R = off;
@@ -995,7 +1060,7 @@ mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *st
         h->bmeta_img_tmp.clear();
         return MG_OK;
     }
-    if (h->opt.autotune) {
+    if (h->opt.autotune && !h->q1) {
         mg_status_t s = autotune(h, st);
         if (s != MG_OK) return s;
     }
@@ -1091,8 +1156,7 @@ mg_status_t mg_stage(mg_handle h, mg_stage_t stage, int level, void *stream) {
         if (base) return fail(MG_ERR_ARG, "the base level is solved, not smoothed");
         LevelPlan &L = h->lv[level];
         const int cur = h->cur[level];
-        e = launch_sweep(h->dim, L.prec, L.P, bbuf(h, level), cbuf(h, level, cur), cbuf(h, level, cur ^ 1),
-                         h->opt.omega, L.shs[SH_SWEEP], st);
+        e = level_sweep(h, level, L.prec, bbuf(h, level), cbuf(h, level, cur), cbuf(h, level, cur ^ 1), st);
         if (e == hipSuccess) h->cur[level] = cur ^ 1;
         break;
     }
@@ -1154,9 +1218,9 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
 
     // ||b||_2 first (and the initial residual when u starts at zero)
     if (h->opt.use_initial_guess) {
-        HIPCHK(launch_resid_flat(D, L.n, L.P, b, nullptr, nullptr, nullptr, inv_h2, part(h), st));
+        HIPCHK(finest_resid(h, b, nullptr, nullptr, nullptr, st));
     } else {
-        HIPCHK(launch_resid_flat(D, L.n, L.P, b, nullptr, Rbuf(h), nullptr, inv_h2, part(h), st));
+        HIPCHK(finest_resid(h, b, nullptr, Rbuf(h), nullptr, st));
         HIPCHK(launch_fill_zero(Ubuf(h), align_up(L.elems * sizeof(double), 16), st));
     }
     const int fparts = flat_blocks(points(D, L.n));
@@ -1177,7 +1241,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     }
     if (h->opt.use_initial_guess) {
         HIPCHK(launch_pack(D, P_F64, P_F64, L.n, L.P, u, Ubuf(h), st));
-        HIPCHK(launch_resid_flat(D, L.n, L.P, b, Ubuf(h), Rbuf(h), nullptr, inv_h2, part(h), st));
+        HIPCHK(finest_resid(h, b, Ubuf(h), Rbuf(h), nullptr, st));
         HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
         HIPCHK(hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1211,7 +1275,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
             // confirm with the residual recomputed from u (a queued V-cycle
             // only wrote level vectors and is discarded)
             cycle_queued = false;
-            HIPCHK(launch_resid_flat(D, L.n, L.P, b, Ubuf(h), Rbuf(h), u, inv_h2, part(h), st));
+            HIPCHK(finest_resid(h, b, Ubuf(h), Rbuf(h), u, st));
             HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
             HIPCHK(hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -1253,7 +1317,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     }
     if (cycle_queued) HIPCHK(hipStreamSynchronize(st));
     // final: recompute the true residual and copy u out
-    HIPCHK(launch_resid_flat(D, L.n, L.P, b, Ubuf(h), Rbuf(h), u, inv_h2, part(h), st));
+    HIPCHK(finest_resid(h, b, Ubuf(h), Rbuf(h), u, st));
     HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
     HIPCHK(hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1265,6 +1329,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np) {
     if (!h || !p) return fail(MG_ERR_ARG, "null argument");
     if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
+    if (h->q1) return fail(MG_ERR_STATE, "the Q1 kernels have no launch shapes");
     if (kind == MG_SHAPE_TAIL) {
         if (np != 1 || (p[0] != 0 && p[0] != 1)) return fail(MG_ERR_ARG, "the tail shape is {0|1}");
         h->tail_on = p[0] != 0;
@@ -1772,6 +1837,8 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
     mg_default_options(&o);
     if (opt) o = *opt;
     if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
+    if (o.discretization != MG_DISC_FD)
+        return fail(MG_ERR_ARG, "the Q1 discretisation is only available on single-grid handles");
     if (o.cycles_per_step != 1)
         return fail(MG_ERR_ARG, "cycles_per_step other than 1 is only available on single-grid handles");
     if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)
@@ -2122,6 +2189,8 @@ mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_pr
     mg_default_options(&o);
     if (opt) o = *opt;
     if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
+    if (o.discretization != MG_DISC_FD)
+        return fail(MG_ERR_ARG, "the Q1 discretisation is only available on single-grid handles");
     if (o.cycles_per_step != 1)
         return fail(MG_ERR_ARG, "cycles_per_step other than 1 is only available on single-grid handles");
     if (o.nu1 < 2 || o.nu1 > 16 || o.nu2 < 1 || o.nu2 > 16)

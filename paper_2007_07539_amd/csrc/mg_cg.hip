@@ -1,6 +1,6 @@
 // Conjugate gradients on a base level of more than one point (the paper's
-// base solver, Section 4.2): L x = b with the level's integer stencil
-// [2D, -1], from x = 0, until ||r||_2 <= tol ||b||_2 or max_iter steps.  In
+// base solver, Section 4.2): L x = b with the level's grid-scaled operator
+// (the finite-difference stencil [2D, -1], or the Q1 stencil S), from x = 0, until ||r||_2 <= tol ||b||_2 or max_iter steps.  In
 // grid-scaled units the residual of L x = b is the residual of the physical
 // system, and CG is invariant under a scaling of the operator, so the steps
 // are those of CG on the physical base system.  The base level is small and
@@ -25,7 +25,7 @@ __device__ __forceinline__ double block_sum(double v, double *red, double *bc) {
     return bc[0];
 }
 
-template <int D, class T>
+template <int D, int OP, class T>
 __global__ __launch_bounds__(kThreads) void k_cg_base(const T *__restrict__ b, T *__restrict__ c,
                                                       acc_t<T> *__restrict__ x, acc_t<T> *__restrict__ r,
                                                       acc_t<T> *__restrict__ p, acc_t<T> *__restrict__ q, int n, int P,
@@ -58,14 +58,19 @@ __global__ __launch_bounds__(kThreads) void k_cg_base(const T *__restrict__ b, T
         loc = 0.0;
         for (long i = threadIdx.x; i < N; i += kThreads) {
             const long o = pos(i);
-            A nb = p[o - 1] + p[o + 1];
-            if (D == 3) {
-                nb += p[o - P];
-                nb += p[o + P];
+            A lp;
+            if (OP == 1) {
+                lp = q1_weighted<D, A>(p, (size_t)o, P) * q1_scale<D, A>();
+            } else {
+                A nb = p[o - 1] + p[o + 1];
+                if (D == 3) {
+                    nb += p[o - P];
+                    nb += p[o + P];
+                }
+                nb += p[o - plane];
+                nb += p[o + plane];
+                lp = fmaT<A>(A(2 * D), p[o], -nb);
             }
-            nb += p[o - plane];
-            nb += p[o + plane];
-            const A lp = fmaT<A>(A(2 * D), p[o], -nb);
             q[o] = lp;
             loc += (double)p[o] * (double)lp;
         }
@@ -95,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_base(const T *__restrict__ b, T
     }
 }
 
-template <class T>
+template <int OP, class T>
 hipError_t cg_t(int D, int n, int P, const void *b, void *c, void *scratch, size_t stride, double tol, int max_iter,
                 hipStream_t st) {
     typedef acc_t<T> A;
@@ -104,10 +109,10 @@ hipError_t cg_t(int D, int n, int P, const void *b, void *c, void *scratch, size
     A *p = reinterpret_cast<A *>(static_cast<char *>(scratch) + 2 * stride);
     A *q = reinterpret_cast<A *>(static_cast<char *>(scratch) + 3 * stride);
     if (D == 3)
-        hipLaunchKernelGGL((k_cg_base<3, T>), dim3(1), dim3(kThreads), 0, st, static_cast<const T *>(b),
+        hipLaunchKernelGGL((k_cg_base<3, OP, T>), dim3(1), dim3(kThreads), 0, st, static_cast<const T *>(b),
                            static_cast<T *>(c), x, r, p, q, n, P, tol, max_iter);
     else
-        hipLaunchKernelGGL((k_cg_base<2, T>), dim3(1), dim3(kThreads), 0, st, static_cast<const T *>(b),
+        hipLaunchKernelGGL((k_cg_base<2, OP, T>), dim3(1), dim3(kThreads), 0, st, static_cast<const T *>(b),
                            static_cast<T *>(c), x, r, p, q, n, P, tol, max_iter);
     return hipGetLastError();
 }
@@ -119,16 +124,23 @@ size_t cg_scratch_stride(int prec, size_t elems) {
     return (elems * acc + 255) / 256 * 256;
 }
 
-hipError_t launch_cg_base(int D, int prec, int n, int P, const void *b, void *c, void *scratch, size_t stride,
-                          double tol, int max_iter, hipStream_t st) {
-    if (n < 3 || (D != 2 && D != 3)) return hipErrorInvalidValue;
+template <int OP>
+hipError_t cg_op(int D, int prec, int n, int P, const void *b, void *c, void *scratch, size_t stride, double tol,
+                 int max_iter, hipStream_t st) {
     switch (prec) {
-    case P_F64: return cg_t<double>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
-    case P_F32: return cg_t<float>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
-    case P_F16: return cg_t<f16>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
-    case P_BF16: return cg_t<bf16>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
+    case P_F64: return cg_t<OP, double>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
+    case P_F32: return cg_t<OP, float>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
+    case P_F16: return cg_t<OP, f16>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
+    case P_BF16: return cg_t<OP, bf16>(D, n, P, b, c, scratch, stride, tol, max_iter, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_cg_base(int D, int prec, int n, int P, const void *b, void *c, void *scratch, size_t stride,
+                          double tol, int max_iter, int op, hipStream_t st) {
+    if (n < 2 || (D != 2 && D != 3)) return hipErrorInvalidValue;
+    return op == 1 ? cg_op<1>(D, prec, n, P, b, c, scratch, stride, tol, max_iter, st)
+                   : cg_op<0>(D, prec, n, P, b, c, scratch, stride, tol, max_iter, st);
 }
 
 }  // namespace mg

@@ -237,6 +237,32 @@ template <int D> struct Grid {
 };
 
 // ---------------------------------------------------------------------------
+// Q1 finite elements (bilinear in 2-D, trilinear in 3-D) in grid-scaled
+// units: on every level the stiffness operator is the constant stencil S with
+// 3 S = [8 centre, -1 on all 8 neighbours] (2-D) and 12 S = [32 centre, 0 on
+// faces, -2 on the 12 edge neighbours, -1 on the 8 corners] (3-D).  q1_weighted
+// returns 3 S v resp. 12 S v at padded offset o (integer weights, summed in A);
+// multiply by q1_scale to get S v.  All neighbours of an interior point lie
+// inside the padded array (ghosts hold zero).
+template <int D, class A, class T>
+__device__ __forceinline__ A q1_weighted(const T *__restrict__ v, size_t o, int P) {
+    const long b = (long)o;
+    auto L = [&](long d) -> A { return (A)widen(v[b + d]); };
+    const long Y = P;
+    if (D == 2) {
+        const A nb = ((L(-Y - 1) + L(-Y)) + (L(-Y + 1) + L(-1))) + ((L(1) + L(Y - 1)) + (L(Y) + L(Y + 1)));
+        return fmaT<A>(A(8), L(0), -nb);
+    }
+    const long Z = (long)P * P;
+    const A e = ((L(-Z - Y) + L(-Z - 1)) + (L(-Z + 1) + L(-Z + Y))) + ((L(-Y - 1) + L(-Y + 1)) + (L(Y - 1) + L(Y + 1))) +
+                ((L(Z - Y) + L(Z - 1)) + (L(Z + 1) + L(Z + Y)));
+    const A cn = ((L(-Z - Y - 1) + L(-Z - Y + 1)) + (L(-Z + Y - 1) + L(-Z + Y + 1))) +
+                 ((L(Z - Y - 1) + L(Z - Y + 1)) + (L(Z + Y - 1) + L(Z + Y + 1)));
+    return fmaT<A>(A(32), L(0), -fmaT<A>(A(2), e, cn));
+}
+template <int D, class A> __device__ __forceinline__ A q1_scale() { return D == 3 ? A(1.0 / 12.0) : A(1.0 / 3.0); }
+
+// ---------------------------------------------------------------------------
 // wave64 and block reductions with a fixed combination order.
 __device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
 

@@ -113,11 +113,31 @@ hipError_t launch_smooth_restrict_b(int prec, int pc, int P, const void *b, void
 // (P_F16 or P_BF16); n counts padded elements.  part needs
 // rescale_part_count() doubles; rs receives {s, 1/s}.
 size_t rescale_part_count();
-// CG base solve (base of n >= 3 points per dimension, level format prec);
+// CG base solve (base of n >= 2 points per dimension, level format prec,
+// op 0: finite-difference stencil, 1: Q1);
 // scratch holds x, r, p, q at cg_scratch_stride(prec, elems) bytes apart.
 size_t cg_scratch_stride(int prec, size_t elems);
 hipError_t launch_cg_base(int D, int prec, int n, int P, const void *b, void *c, void *scratch, size_t stride,
-                          double tol, int max_iter, hipStream_t st);
+                          double tol, int max_iter, int op, hipStream_t st);
+
+// Q1 finite elements (grid-scaled stencil S, see mg_q1.hip).  n is the level's
+// interior size (odd for levels with a coarser one), P = n + 1.
+// launch_q1_restrict writes the fine residual into rs (q1_resid_bytes) first.
+size_t q1_resid_bytes(int D, int prec, int P);
+int q1_outer_blocks(int D, int n);
+hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const double *R, const double *scal,
+                           void *b_out, void *c_out, double omega, hipStream_t st);
+hipError_t launch_q1_sweep(int D, int prec, int n, int P, const void *b, const void *c, void *c_out, double omega,
+                           hipStream_t st);
+hipError_t launch_q1_restrict(int D, int pf, int pc, int n, int P, const void *b, const void *c, void *rs, void *bc,
+                              hipStream_t st);
+hipError_t launch_q1_prolong(int D, int pf, int pc, int n, int P, const void *c, const void *ec, const void *b,
+                             void *c_out, double omega, hipStream_t st);
+hipError_t launch_q1_outer(int D, int prec, int n, int P, const void *c, double *R, double *U, const double *scal,
+                           double f, double *part, hipStream_t st);
+hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,
+                                double hd, double *part, hipStream_t st);
+hipError_t launch_q1_coarse(int D, int prec, const void *b, void *c, hipStream_t st);
 hipError_t launch_absmax(int pa, const void *t, long n, double *part, double *rs, hipStream_t st);
 hipError_t launch_scale_cast(int pa, int prec, const void *t, const double *rs, void *out, long n, hipStream_t st);
 hipError_t launch_scale_widen(int prec, int pa, const void *c, const double *rs, void *out, long n, hipStream_t st);

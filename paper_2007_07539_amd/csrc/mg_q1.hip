@@ -1,0 +1,390 @@
+// The V-cycle and refinement kernels for the Q1 finite-element discretisation
+// that the paper's measurements use (Section 5: bilinear elements on the unit
+// square, trilinear on the unit cube).
+//
+// Units.  With the grid-scaled correction c = h^(D-2) e on every level, the
+// level operator h^(D-2) S becomes the constant stencil S (q1_weighted), the
+// restriction is full weighting (weights (1/4, 1/2, 1/4) per axis, summing to
+// one: the finite-element restriction P^T divided by 2^D) and the
+// prolongation carries a factor 4, exactly as for the finite-difference
+// operator: P^T A_h P = A_2h for Q1, and (A_h = h^(D-2) S) the coarse
+// correction equation S c_2h = FW r_h then reproduces the physical two-grid
+// correction.  Magnitudes stay level-independent, which half precision needs.
+//
+// Damped Jacobi: c <- c + omega (b - S c) / diag(S), diag(S) = 8/3 in 2-D and
+// 3-D.  Arithmetic in the level's accumulator format (FP32 for FP32, FP16 and
+// BF16 storage, FP64 for FP64), one rounding into the storage format per
+// stored value.  The transfers and residuals read neighbours through the
+// caches: one thread per interior point, consecutive threads on consecutive x,
+// and work-group numbers remapped so that each XCD takes one contiguous range
+// of points (neighbouring rows and planes then meet in the same L2).
+#include "mg_device.h"
+#include "mg_launch.h"
+
+namespace mg {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Interior point number i (x fastest) -> padded offset.
+template <int D> __device__ __forceinline__ size_t q1_at(unsigned i, int n, int P, int &x, int &y, int &z) {
+    x = (int)(i % (unsigned)n) + 1;
+    const unsigned rest = i / (unsigned)n;
+    if (D == 3) {
+        y = (int)(rest % (unsigned)n) + 1;
+        z = (int)(rest / (unsigned)n) + 1;
+    } else {
+        y = 0;
+        z = (int)rest + 1;
+    }
+    return Grid<D>{P}.at(x, y, z);
+}
+
+__device__ __forceinline__ unsigned q1_index(int xcd) {
+    const int b = xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    return (unsigned)b * kThreads + threadIdx.x;
+}
+
+// First Jacobi iterate from c = 0: c = round(w b), w = omega / diag(S).
+// FROM_R: the right-hand side is the FP64 residual times 1/alpha (scal[1]),
+// rounded once into the level format and stored as b-hat as well.
+template <int D, class T, bool FROM_R>
+__global__ __launch_bounds__(kThreads) void k_q1_first(const T *__restrict__ b, const double *__restrict__ R,
+                                                       const double *__restrict__ scal, T *__restrict__ bout,
+                                                       T *__restrict__ cout, int n, int P, unsigned N, acc_t<T> w) {
+    typedef acc_t<T> A;
+    const unsigned i = q1_index(1);
+    if (i >= N) return;
+    int x, y, z;
+    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    A bv;
+    if (FROM_R) {
+        const T bh = Store<T>::from_f64(R[o] * scal[1]);
+        bout[o] = bh;
+        bv = (A)widen(bh);
+    } else {
+        bv = (A)widen(b[o]);
+    }
+    cout[o] = Store<T>::from_acc(w * bv);
+}
+
+// One Jacobi sweep: cout = c + w (b - S c).
+template <int D, class T>
+__global__ __launch_bounds__(kThreads) void k_q1_sweep(const T *__restrict__ b, const T *__restrict__ c,
+                                                       T *__restrict__ cout, int n, int P, unsigned N, acc_t<T> w) {
+    typedef acc_t<T> A;
+    const unsigned i = q1_index(1);
+    if (i >= N) return;
+    int x, y, z;
+    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    const A sc = q1_weighted<D, A>(c, o, P) * q1_scale<D, A>();
+    const A r = (A)widen(b[o]) - sc;
+    cout[o] = Store<T>::from_acc(fmaT<A>(w, r, (A)widen(c[o])));
+}
+
+// Fine residual r = b - S c in the accumulator format (the restriction's input).
+template <int D, class T>
+__global__ __launch_bounds__(kThreads) void k_q1_resid(const T *__restrict__ b, const T *__restrict__ c,
+                                                       acc_t<T> *__restrict__ r, int n, int P, unsigned N) {
+    typedef acc_t<T> A;
+    const unsigned i = q1_index(1);
+    if (i >= N) return;
+    int x, y, z;
+    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    r[o] = (A)widen(b[o]) - q1_weighted<D, A>(c, o, P) * q1_scale<D, A>();
+}
+
+// Full weighting of r at coarse point (X, Y, Z), whose fine twin is
+// (2X, 2Y, 2Z): 1-D weights 1, 2, 1 summed exactly and scaled by 4^-D.
+template <int D, class A, class TC>
+__global__ __launch_bounds__(kThreads) void k_q1_restrict(const A *__restrict__ r, TC *__restrict__ bc, int nc,
+                                                          int Pf, int Pc, unsigned Nc) {
+    const unsigned i = q1_index(1);
+    if (i >= Nc) return;
+    int X, Y, Z;
+    const size_t oc = q1_at<D>(i, nc, Pc, X, Y, Z);
+    const Grid<D> gf{Pf};
+    const long o = (long)(D == 3 ? gf.at(2 * X, 2 * Y, 2 * Z) : gf.at(2 * X, 0, 2 * Z));
+    const long Yf = Pf, Zf = (long)Pf * Pf;
+    auto row = [&](long c0) -> A { return (r[c0 - 1] + r[c0 + 1]) + A(2) * r[c0]; };
+    A s;
+    if (D == 2) {
+        s = (row(o - Yf) + row(o + Yf)) + A(2) * row(o);
+        s *= A(1.0 / 16.0);
+    } else {
+        auto plane = [&](long c0) -> A { return (row(c0 - Yf) + row(c0 + Yf)) + A(2) * row(c0); };
+        s = (plane(o - Zf) + plane(o + Zf)) + A(2) * plane(o);
+        s *= A(1.0 / 64.0);
+    }
+    bc[oc] = store_as<TC>(s);
+}
+
+// c += 4 P ec (linear interpolation of the coarse correction) in place, in W:
+// along each axis an even fine index 2X copies coarse X, an odd one averages
+// coarse (x-1)/2 and (x+1)/2 (ghosts hold zero).
+template <int D, class TF, class TC>
+__global__ __launch_bounds__(kThreads) void k_q1_prolong_add(TF *__restrict__ c, const TC *__restrict__ ec, int n,
+                                                             int P, int Pc, unsigned N) {
+    typedef typename std::conditional<sizeof(acc_t<TF>) >= sizeof(acc_t<TC>), acc_t<TF>, acc_t<TC>>::type W;
+    const unsigned i = q1_index(1);
+    if (i >= N) return;
+    int x, y, z;
+    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    const Grid<D> gc{Pc};
+    const int x0 = x >> 1, x1 = (x + 1) >> 1, z0 = z >> 1, z1 = (z + 1) >> 1;
+    auto xs = [&](int Yc, int Zc) -> W {
+        const size_t b = D == 3 ? gc.at(0, Yc, Zc) : gc.at(0, 0, Zc);
+        return (W)widen(ec[b + x0]) + (W)widen(ec[b + x1]);
+    };
+    W s;
+    if (D == 2) {
+        s = xs(0, z0) + xs(0, z1);
+    } else {
+        const int y0 = y >> 1, y1 = (y + 1) >> 1;
+        s = (xs(y0, z0) + xs(y1, z0)) + (xs(y0, z1) + xs(y1, z1));
+    }
+    // each axis adds the same coarse value twice where the fine index is even,
+    // so s is 2^D times the interpolant; 4 P ec = s * 4 / 2^D
+    s *= W(D == 3 ? 0.5 : 1.0);
+    c[o] = store_as<TF>((W)widen(c[o]) + s);
+}
+
+// Finest-level update of a refinement step in FP64: U += alpha f c and
+// R -= alpha S c (the recursively updated residual of Algorithm 2), f =
+// h^(2-D) undoing the grid scaling; partial sum of squares and max |R| per block.
+template <int D, class T>
+__global__ __launch_bounds__(kThreads) void k_q1_outer(const T *__restrict__ c, double *__restrict__ R,
+                                                       double *__restrict__ U, const double *__restrict__ scal,
+                                                       double f, int n, int P, unsigned N, double *__restrict__ part) {
+    __shared__ double red[8];
+    const double a = scal[0];
+    double ss = 0.0, mx = 0.0;
+    for (unsigned i = blockIdx.x * kThreads + threadIdx.x; i < N; i += gridDim.x * kThreads) {
+        int x, y, z;
+        const size_t o = q1_at<D>(i, n, P, x, y, z);
+        const double sc = q1_weighted<D, double>(c, o, P) * q1_scale<D, double>();
+        const double r = fmaT<double>(-a, sc, R[o]);
+        R[o] = r;
+        U[o] = fmaT<double>(a * f, (double)widen(c[o]), U[o]);
+        ss += r * r;
+        mx = nanmax(mx, fabs(r));
+    }
+    block_reduce(ss, mx, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss;
+        part[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+// r = b - hd S U (hd = h^(D-2)) from the dense right-hand side b; without U,
+// r = b.  Optionally writes r into the padded R and U into the dense uout;
+// partial sum of squares and max |r| per block.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_q1_resid_flat(const double *__restrict__ b, const double *__restrict__ U,
+                                                            double *__restrict__ R, double *__restrict__ uout, int n,
+                                                            int P, unsigned N, double hd, double *__restrict__ part) {
+    __shared__ double red[8];
+    double ss = 0.0, mx = 0.0;
+    for (unsigned i = blockIdx.x * kThreads + threadIdx.x; i < N; i += gridDim.x * kThreads) {
+        int x, y, z;
+        const size_t o = q1_at<D>(i, n, P, x, y, z);
+        double r = b[i];
+        if (U) {
+            r -= hd * (q1_weighted<D, double>(U, o, P) * q1_scale<D, double>());
+            if (uout) uout[i] = U[o];
+        }
+        if (R) R[o] = r;
+        ss += r * r;
+        mx = nanmax(mx, fabs(r));
+    }
+    block_reduce(ss, mx, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss;
+        part[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+// One-point base level: S c = b with S = 8/3.
+template <int D, class T> __global__ void k_q1_coarse(const T *__restrict__ b, T *__restrict__ c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        typedef acc_t<T> A;
+        const int i = D == 3 ? 7 : 3;
+        c[i] = Store<T>::from_acc((A)widen(b[i]) * A(0.375));
+    }
+}
+
+unsigned npoints(int D, int n) { return D == 3 ? (unsigned)n * n * n : (unsigned)n * n; }
+int nblocks(unsigned N) { return (int)((N + kThreads - 1) / kThreads); }
+
+template <class T>
+hipError_t first_t(int D, int n, int P, const void *b, const double *R, const double *scal, void *bout, void *cout,
+                   double omega, hipStream_t st) {
+    typedef acc_t<T> A;
+    const unsigned N = npoints(D, n);
+    const A w = (A)(omega * 0.375);
+    const T *bb = static_cast<const T *>(b);
+    T *bo = static_cast<T *>(bout), *co = static_cast<T *>(cout);
+    if (R) {
+        if (D == 3)
+            hipLaunchKernelGGL((k_q1_first<3, T, true>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo, co,
+                               n, P, N, w);
+        else
+            hipLaunchKernelGGL((k_q1_first<2, T, true>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo, co,
+                               n, P, N, w);
+    } else {
+        if (D == 3)
+            hipLaunchKernelGGL((k_q1_first<3, T, false>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo,
+                               co, n, P, N, w);
+        else
+            hipLaunchKernelGGL((k_q1_first<2, T, false>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo,
+                               co, n, P, N, w);
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout, double omega, hipStream_t st) {
+    typedef acc_t<T> A;
+    const unsigned N = npoints(D, n);
+    const A w = (A)(omega * 0.375);
+    if (D == 3)
+        hipLaunchKernelGGL((k_q1_sweep<3, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), static_cast<T *>(cout), n, P, N, w);
+    else
+        hipLaunchKernelGGL((k_q1_sweep<2, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), static_cast<T *>(cout), n, P, N, w);
+    return hipGetLastError();
+}
+
+template <class T, class TC>
+hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *rs, void *bc, hipStream_t st) {
+    typedef acc_t<T> A;
+    const unsigned N = npoints(D, n);
+    const int nc = (n - 1) / 2, Pc = nc + 1;
+    const unsigned Nc = npoints(D, nc);
+    A *r = static_cast<A *>(rs);
+    if (D == 3) {
+        hipLaunchKernelGGL((k_q1_resid<3, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), r, n, P, N);
+        hipLaunchKernelGGL((k_q1_restrict<3, A, TC>), dim3(nblocks(Nc)), dim3(kThreads), 0, st, r,
+                           static_cast<TC *>(bc), nc, P, Pc, Nc);
+    } else {
+        hipLaunchKernelGGL((k_q1_resid<2, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), r, n, P, N);
+        hipLaunchKernelGGL((k_q1_restrict<2, A, TC>), dim3(nblocks(Nc)), dim3(kThreads), 0, st, r,
+                           static_cast<TC *>(bc), nc, P, Pc, Nc);
+    }
+    return hipGetLastError();
+}
+
+template <class TF, class TC>
+hipError_t prolong_t(int D, int n, int P, void *c, const void *ec, hipStream_t st) {
+    const unsigned N = npoints(D, n);
+    const int Pc = (n - 1) / 2 + 1;
+    if (D == 3)
+        hipLaunchKernelGGL((k_q1_prolong_add<3, TF, TC>), dim3(nblocks(N)), dim3(kThreads), 0, st,
+                           static_cast<TF *>(c), static_cast<const TC *>(ec), n, P, Pc, N);
+    else
+        hipLaunchKernelGGL((k_q1_prolong_add<2, TF, TC>), dim3(nblocks(N)), dim3(kThreads), 0, st,
+                           static_cast<TF *>(c), static_cast<const TC *>(ec), n, P, Pc, N);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t outer_t(int D, int n, int P, const void *c, double *R, double *U, const double *scal, double f,
+                   double *part, int nparts, hipStream_t st) {
+    const unsigned N = npoints(D, n);
+    if (D == 3)
+        hipLaunchKernelGGL((k_q1_outer<3, T>), dim3(nparts), dim3(kThreads), 0, st, static_cast<const T *>(c), R, U,
+                           scal, f, n, P, N, part);
+    else
+        hipLaunchKernelGGL((k_q1_outer<2, T>), dim3(nparts), dim3(kThreads), 0, st, static_cast<const T *>(c), R, U,
+                           scal, f, n, P, N, part);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define Q1_DISPATCH(prec, TT, ...)                 \
+    switch (prec) {                                \
+    case P_F64: {                                  \
+        typedef double TT;                         \
+        __VA_ARGS__;                               \
+    }                                              \
+    case P_F32: {                                  \
+        typedef float TT;                          \
+        __VA_ARGS__;                               \
+    }                                              \
+    case P_F16: {                                  \
+        typedef f16 TT;                            \
+        __VA_ARGS__;                               \
+    }                                              \
+    case P_BF16: {                                 \
+        typedef bf16 TT;                           \
+        __VA_ARGS__;                               \
+    }                                              \
+    default: return hipErrorInvalidValue;          \
+    }
+
+size_t q1_resid_bytes(int D, int prec, int P) {
+    return level_elems(D, P) * (prec == P_F64 ? sizeof(double) : sizeof(float));
+}
+
+int q1_outer_blocks(int D, int n) { return flat_blocks((long)npoints(D, n)); }
+
+hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const double *R, const double *scal,
+                           void *b_out, void *c_out, double omega, hipStream_t st) {
+    Q1_DISPATCH(prec, TT, return first_t<TT>(D, n, P, b, R, scal, b_out, c_out, omega, st));
+}
+
+hipError_t launch_q1_sweep(int D, int prec, int n, int P, const void *b, const void *c, void *c_out, double omega,
+                           hipStream_t st) {
+    Q1_DISPATCH(prec, TT, return sweep_t<TT>(D, n, P, b, c, c_out, omega, st));
+}
+
+hipError_t launch_q1_restrict(int D, int pf, int pc, int n, int P, const void *b, const void *c, void *rs, void *bc,
+                              hipStream_t st) {
+    if (n < 3 || n % 2 == 0) return hipErrorInvalidValue;
+    Q1_DISPATCH(pf, TF, Q1_DISPATCH(pc, TC, return (restrict_t<TF, TC>(D, n, P, b, c, rs, bc, st))));
+}
+
+hipError_t launch_q1_prolong(int D, int pf, int pc, int n, int P, const void *c, const void *ec, const void *b,
+                             void *c_out, double omega, hipStream_t st) {
+    if (n < 3 || n % 2 == 0) return hipErrorInvalidValue;
+    hipError_t e = hipErrorInvalidValue;
+    Q1_DISPATCH(pf, TF, Q1_DISPATCH(pc, TC, e = (prolong_t<TF, TC>(D, n, P, const_cast<void *>(c), ec, st)); break);
+                break);
+    if (e != hipSuccess) return e;
+    return launch_q1_sweep(D, pf, n, P, b, c, c_out, omega, st);
+}
+
+hipError_t launch_q1_outer(int D, int prec, int n, int P, const void *c, double *R, double *U, const double *scal,
+                           double f, double *part, hipStream_t st) {
+    const int nparts = q1_outer_blocks(D, n);
+    Q1_DISPATCH(prec, TT, return outer_t<TT>(D, n, P, c, R, U, scal, f, part, nparts, st));
+}
+
+hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,
+                                double hd, double *part, hipStream_t st) {
+    const unsigned N = npoints(D, n);
+    const int blocks = flat_blocks((long)N);
+    if (D == 3)
+        hipLaunchKernelGGL(k_q1_resid_flat<3>, dim3(blocks), dim3(kThreads), 0, st, b, U, R, uout, n, P, N, hd, part);
+    else
+        hipLaunchKernelGGL(k_q1_resid_flat<2>, dim3(blocks), dim3(kThreads), 0, st, b, U, R, uout, n, P, N, hd, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_q1_coarse(int D, int prec, const void *b, void *c, hipStream_t st) {
+    Q1_DISPATCH(prec, TT, {
+        if (D == 3)
+            hipLaunchKernelGGL((k_q1_coarse<3, TT>), dim3(1), dim3(64), 0, st, static_cast<const TT *>(b),
+                               static_cast<TT *>(c));
+        else
+            hipLaunchKernelGGL((k_q1_coarse<2, TT>), dim3(1), dim3(64), 0, st, static_cast<const TT *>(b),
+                               static_cast<TT *>(c));
+        return hipGetLastError();
+    });
+}
+
+}  // namespace mg

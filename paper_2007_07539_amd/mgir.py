@@ -19,6 +19,19 @@ LIB_PATH = os.path.join(_HERE, "libmgir.so")
 MG_OK, MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_PREC, MG_ERR_WORKSPACE, MG_ERR_HIP, MG_ERR_NOT_CONVERGED, \
     MG_ERR_NONFINITE, MG_ERR_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+# Discretisations: finite differences (n = 2^m - 1) or Q1 finite elements
+# (n = c 2^k - 1 for odd c as well, the paper's grids).
+DISC = {"fd": 0, "q1": 1}
+
+
+def full_levels(n: int) -> int:
+    """Levels of the full hierarchy n, (n-1)/2, ... (down to one point, or to
+    the first even size)."""
+    m = 1
+    while n > 1 and n % 2 == 1:
+        n = (n - 1) // 2
+        m += 1
+    return m
 TORCH_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
 BUF_RHS, BUF_COR, BUF_RES, BUF_SOL = 0, 1, 2, 3
 STAGE_SMOOTH_FIRST, STAGE_SWEEP, STAGE_RESTRICT, STAGE_PROLONG_SWEEP, STAGE_COARSE = 0, 1, 2, 3, 4
@@ -42,7 +55,7 @@ class Options(ctypes.Structure):
                 ("residual_scaling", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("use_initial_guess", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("rescale_half", ctypes.c_int), ("cycles_per_step", ctypes.c_int), ("base_tol", ctypes.c_double),
-                ("base_max_iter", ctypes.c_int)]
+                ("base_max_iter", ctypes.c_int), ("discretization", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -141,7 +154,7 @@ class Solver:
     def __init__(self, dim: int, n: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
                  max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False,
                  rescale_half=False, cycles_per_step=1, nlevels=0, base_tol=1e-4, base_max_iter=0,
-                 device=None, stream=None):
+                 disc="fd", device=None, stream=None):
         self.lib = load()
         self.dim, self.n = dim, n
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -153,9 +166,13 @@ class Solver:
         o.rescale_half = int(bool(rescale_half))
         o.cycles_per_step = int(cycles_per_step)
         o.base_tol, o.base_max_iter = float(base_tol), int(base_max_iter)
+        if disc not in DISC:
+            raise ValueError(f"disc must be one of {sorted(DISC)}, got {disc!r}")
+        o.discretization = DISC[disc]
+        self.disc = disc
         self.options = o
         self._h = ctypes.c_void_p()
-        m = int(n + 1).bit_length() - 1
+        m = full_levels(n)
         if nlevels:
             m = int(nlevels)
         if level_prec is None:

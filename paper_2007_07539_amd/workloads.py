@@ -70,6 +70,20 @@ def manufactured_rhs(dim: int, n: int, k: int) -> np.ndarray:
     return dim * (k * np.pi) ** 2 * sine_mode(dim, n, (k, k, k))
 
 
+def q1_load_vector(dim: int, n: int, seed: int) -> np.ndarray:
+    """Right-hand side of the Q1 finite-element system (Section 5): the lumped
+    load vector h^dim f_i of f i.i.d. uniform[-1, 1] (one rng.uniform(-1, 1,
+    n^dim) draw, x fastest)."""
+    return uniform_rhs(dim, n, seed) / float(n + 1) ** dim
+
+
+def paper_grid_sizes(dim: int) -> list[int]:
+    """Interior points per dimension of the paper's meshes (Section 6): the
+    smallest and largest of its ranges, 193^3 .. 289^3 and 4097^2 .. 6145^2
+    vertices including the boundary."""
+    return [191, 287] if dim == 3 else [4095, 6143]
+
+
 def random_initial_guess(dim: int, n: int, seed: int) -> np.ndarray:
     """u0 i.i.d. uniform[0, 1], the initial guess of the paper's measurements
     (Section 6): one rng.uniform(0, 1, n^dim) draw, x fastest."""

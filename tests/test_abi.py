@@ -241,3 +241,44 @@ def test_partial_hierarchy_setup(lib):
         assert lib.mg_destroy(h) == mgir.MG_OK
     o.base_tol = -1.0
     assert lib.mg_setup(ctypes.byref(h), 3, 31, 3, prec, ctypes.byref(o)) == mgir.MG_ERR_ARG
+
+
+def test_q1_discretisation_option(lib):
+    """Q1 finite elements: any odd n (the paper's c 2^k - 1 grids), hierarchy to
+    the first even size, one-workgroup CG base bounded, single-grid only."""
+    assert mgir.default_options().discretization == mgir.DISC["fd"]
+    h = ctypes.c_void_p()
+    o = mgir.default_options()
+    o.discretization = 2
+    assert lib.mg_setup(ctypes.byref(h), 3, 31, 0, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
+    o.discretization = mgir.DISC["q1"]
+    for dim, n in [(3, 96), (3, 1), (2, 4096), (3, 1025), (2, 8193)]:
+        assert lib.mg_setup(ctypes.byref(h), dim, n, 0, None, ctypes.byref(o)) == mgir.MG_ERR_SHAPE
+    # finite differences keep n = 2^m - 1
+    assert lib.mg_setup(ctypes.byref(h), 3, 191, 0, None, None) == mgir.MG_ERR_SHAPE
+    # 191 -> 95 -> 47 -> 23 -> 11 -> 5 -> 2: seven levels, base of 2^3 points
+    assert lib.mg_setup(ctypes.byref(h), 3, 191, 0, None, ctypes.byref(o)) == mgir.MG_OK
+    nl, nb = ctypes.c_int(), ctypes.c_int()
+    assert lib.mg_levels(h, ctypes.byref(nl)) == mgir.MG_OK and nl.value == 7
+    assert lib.mg_level_n(h, 6, ctypes.byref(nb)) == mgir.MG_OK and nb.value == 2
+    q1_bytes = ctypes.c_size_t()
+    assert lib.mg_workspace_size(h, ctypes.byref(q1_bytes)) == mgir.MG_OK and q1_bytes.value > 0
+    one = (ctypes.c_int * 1)(1)
+    assert lib.mg_set_shape(h, 0, mgir.SHAPE_TAIL, one, 1) == mgir.MG_ERR_STATE
+    assert lib.mg_destroy(h) == mgir.MG_OK
+    assert mgir.full_levels(191) == 7 and mgir.full_levels(511) == 9 and mgir.full_levels(6143) == 12
+    # 2^m - 1 grids coarsen to one point as with finite differences
+    h = ctypes.c_void_p()
+    assert lib.mg_setup(ctypes.byref(h), 2, 255, 0, None, ctypes.byref(o)) == mgir.MG_OK
+    assert lib.mg_levels(h, ctypes.byref(nl)) == mgir.MG_OK and nl.value == 8
+    assert lib.mg_destroy(h) == mgir.MG_OK
+    # a base level above 64^3 points is refused (one workgroup runs the CG)
+    assert lib.mg_setup(ctypes.byref(h), 3, 1023, 2, None, None) == mgir.MG_ERR_SHAPE
+    assert lib.mg_setup(ctypes.byref(h), 3, 287, 2, None, ctypes.byref(o)) == mgir.MG_ERR_SHAPE
+    assert lib.mg_setup(ctypes.byref(h), 3, 287, 3, None, ctypes.byref(o)) == mgir.MG_ERR_SHAPE  # 71^3
+    assert lib.mg_setup(ctypes.byref(h), 3, 287, 4, None, ctypes.byref(o)) == mgir.MG_OK  # 35^3
+    assert lib.mg_destroy(h) == mgir.MG_OK
+    # single-grid handles only
+    assert _setup_batched(lib, [15, 7], opt=o)[0] == mgir.MG_ERR_ARG
+    h = ctypes.c_void_p()
+    assert lib.mg_setup_multi(ctypes.byref(h), 3, 15, 4, None, ctypes.byref(o)) == mgir.MG_ERR_ARG

@@ -1,0 +1,220 @@
+"""GPU parity of the Q1 finite-element path (the paper's discretisation,
+Section 5) and of the paper's grid family n = c 2^k - 1 (Section 6) against
+the oracle, whose Q1 operator, restriction and V-cycle are pinned to
+quadrature assembly, Kronecker definitions and dense solves.
+
+Units: on level l the GPU holds c_l = h_l^(D-2) e_l / 2^(D l) (the grid-scaled
+correction of the FE system, with full weighting in place of P^T); on the
+finest level c = g e with g = h^(D-2), and b is the physical load vector."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2007_07539_amd import mgir
+from paper_2007_07539_amd import workloads as W
+from tests.helpers import TOL, rel_err, round_to
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["f64", "f32", "f16", "bf16"]
+ACC_TOL = {"f64": 1e-12, "f32": 1e-6, "f16": 1e-6, "bf16": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _g(dim, n):
+    return (1.0 / (n + 1)) ** (dim - 2)
+
+
+def _solver(dim, n, fine, coarse=None, **kw):
+    m = mgir.full_levels(n)
+    prec = [fine] * m
+    if coarse is not None:
+        prec[1:] = [coarse] * (m - 1)
+    return mgir.Solver(dim, n, prec, disc="q1", **kw)
+
+
+def _put(s, level, buf, x, dev):
+    s.write(level, buf, torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev))
+    return s.read(level, buf).cpu().numpy()
+
+
+def _get(s, level, buf):
+    torch.cuda.synchronize()
+    return s.read(level, buf).cpu().numpy()
+
+
+def _true_rel(ref, b, u):
+    return ref.norm2(ref.residual(b, u, "q1")) / ref.norm2(b)
+
+
+CASES = [(3, 7), (3, 15), (3, 63), (3, 95), (2, 15), (2, 255), (2, 383)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,n", CASES)
+def test_q1_sweep(dev, ref, prec, dim, n):
+    print(f"q1 sweep prec={prec} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, prec)
+    rng = np.random.default_rng(10 * n + dim)
+    g = _g(dim, n)
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    cq = _put(s, 0, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (n,) * dim), dev)
+    s.stage(mgir.STAGE_SWEEP, 0)
+    out = _get(s, 0, mgir.BUF_COR)
+    expect = ref.jacobi(bq, cq / g, 0.8, "q1") * g
+    assert rel_err(out, expect) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,n", CASES)
+def test_q1_smooth_first(dev, ref, prec, dim, n):
+    print(f"q1 smooth_first prec={prec} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, prec)
+    rng = np.random.default_rng(20 * n + dim)
+    g = _g(dim, n)
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    s.stage(mgir.STAGE_SMOOTH_FIRST, 0)
+    out = _get(s, 0, mgir.BUF_COR)
+    c1 = round_to(ref.jacobi(bq, np.zeros_like(bq), 0.8, "q1") * g, prec)
+    c2 = ref.jacobi(bq, c1 / g, 0.8, "q1") * g
+    assert rel_err(out, c2) <= TOL[prec]
+
+
+@pytest.mark.parametrize("pf,pc", [(a, b) for a in PRECS for b in PRECS])
+@pytest.mark.parametrize("dim,n", [(3, 15), (3, 47), (2, 63), (2, 95)])
+def test_q1_resid_restrict(dev, ref, pf, pc, dim, n):
+    print(f"q1 restrict {pf}->{pc} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, pf, pc)
+    rng = np.random.default_rng(30 * n + dim)
+    g = _g(dim, n)
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    cq = _put(s, 0, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (n,) * dim), dev)
+    s.stage(mgir.STAGE_RESTRICT, 0)
+    out = _get(s, 1, mgir.BUF_RHS)
+    # full weighting = P^T / 2^D
+    expect = ref.restrict(ref.residual(bq, cq / g, "q1"), "q1") / 2**dim
+    assert rel_err(out, expect) <= max(TOL[pc], ACC_TOL[pf])
+
+
+@pytest.mark.parametrize("pf,pc", [(a, b) for a in PRECS for b in PRECS])
+@pytest.mark.parametrize("dim,n", [(3, 15), (3, 47), (2, 63), (2, 95)])
+def test_q1_prolong_sweep(dev, ref, pf, pc, dim, n):
+    print(f"q1 prolong {pc}->{pf} dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, pf, pc)
+    nc = (n - 1) // 2
+    rng = np.random.default_rng(40 * n + dim)
+    gf, gc = _g(dim, n), _g(dim, nc) / 2**dim
+    bq = _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * dim), dev)
+    cq = _put(s, 0, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (n,) * dim), dev)
+    ecq = _put(s, 1, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (nc,) * dim), dev)
+    s.stage(mgir.STAGE_PROLONG_SWEEP, 0)
+    out = _get(s, 0, mgir.BUF_COR)
+    corrected = round_to((cq / gf + ref.prolong(ecq / gc)) * gf, pf)
+    expect = ref.jacobi(bq, corrected / gf, 0.8, "q1") * gf
+    assert rel_err(out, expect) <= TOL[pf]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_q1_coarse_solve(dev, prec, dim):
+    s = _solver(dim, 7, "f64", prec)
+    base = s.nlevels - 1
+    bq = _put(s, base, mgir.BUF_RHS, np.full((1,) * dim, 0.7071), dev)
+    s.stage(mgir.STAGE_COARSE, base)
+    out = _get(s, base, mgir.BUF_COR)
+    # S = 8/3 on one point
+    assert rel_err(out, round_to(bq * 0.375, prec)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("dim,n", [(3, 7), (3, 31), (3, 63), (3, 47), (2, 63), (2, 255), (2, 191)])
+def test_q1_vcycle_fp64(dev, ref, dim, n):
+    print(f"q1 vcycle f64 dim={dim} n={n}", flush=True)
+    s = _solver(dim, n, "f64", base_tol=1e-14, base_max_iter=5000)
+    b = W.uniform_rhs(dim, n, seed=50 + n) / (n + 1) ** dim
+    c = s.vcycle(torch.from_numpy(b).to(dev)).cpu().numpy()
+    base = s.level_n(s.nlevels - 1)
+    e = ref.vcycle(b, disc="q1", base_n=base, base_tol=1e-14, base_max_iter=5000)
+    assert rel_err(c / _g(dim, n), e) <= 1e-11
+
+
+@pytest.mark.parametrize("name,tol", [("f32", 1e-5), ("f16", 2e-2), ("bf16", 1e-1), ("hsd", 2e-2)])
+@pytest.mark.parametrize("dim,n", [(3, 63), (2, 255)])
+def test_q1_vcycle_mixed(dev, ref, name, tol, dim, n):
+    print(f"q1 vcycle {name} dim={dim} n={n}", flush=True)
+    m = mgir.full_levels(n)
+    s = mgir.Solver(dim, n, W.precision_map(name, m), disc="q1")
+    prec = W.precision_map(name, m)
+    bq = round_to(W.uniform_rhs(dim, n, seed=60 + n), prec[0])
+    bt = torch.from_numpy(bq).to(dev).to(mgir.TORCH_DTYPE[prec[0]])
+    c = s.vcycle(bt).to(torch.float64).cpu().numpy()
+    e = ref.vcycle(bq, disc="q1")
+    assert rel_err(c / _g(dim, n), e) <= tol
+
+
+@pytest.mark.parametrize("dim,n", [(3, 63), (2, 255), (3, 95), (2, 383)])
+def test_q1_ir_fp64_matches_oracle(dev, ref, dim, n):
+    print(f"q1 ir f64 dim={dim} n={n}", flush=True)
+    m = mgir.full_levels(n)
+    base = ref.hierarchy(n)[-1]
+    b = W.uniform_rhs(dim, n, seed=70 + n) / (n + 1) ** dim
+    s = mgir.Solver(dim, n, ["f64"] * m, disc="q1", residual_scaling=False, base_tol=1e-12, base_max_iter=5000)
+    u, res = s.solve(torch.from_numpy(b).to(dev))
+    u = u.cpu().numpy()
+    o = ref.ir_solve(b, disc="q1", residual_scaling=False, recursive_residual=True, base_n=base, base_tol=1e-12,
+                     base_max_iter=5000)
+    assert res.status == 0 and o.status == 0
+    assert abs(res.iterations - o.iterations) <= 1
+    assert _true_rel(ref, b, u) <= 1e-10
+    assert rel_err(u, o.u) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["f32", "f16", "bf16", "h_mg", "hsd"])
+@pytest.mark.parametrize("dim,n", [(3, 63), (2, 255), (3, 95)])
+def test_q1_ir_mixed_reaches_tolerance(dev, ref, name, dim, n):
+    print(f"q1 ir {name} dim={dim} n={n}", flush=True)
+    m = mgir.full_levels(n)
+    b = W.uniform_rhs(dim, n, seed=80 + n) / (n + 1) ** dim
+    bt = torch.from_numpy(b).to(dev)
+    _, r64 = mgir.Solver(dim, n, ["f64"] * m, disc="q1", residual_scaling=False).solve(bt)
+    s = mgir.Solver(dim, n, W.precision_map(name, m), disc="q1")
+    u, res = s.solve(bt)
+    assert res.status == 0
+    assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
+    assert res.iterations <= r64.iterations + 2
+
+
+def test_q1_options_compose(dev, ref):
+    """Q1 with rescaled restrictions into half-precision levels, two V-cycles per
+    step and a partial hierarchy on a paper grid: still to the tolerance."""
+    dim, n, nl = 3, 95, 4  # base 11^3 by CG
+    print(f"q1 composed dim={dim} n={n} nl={nl}", flush=True)
+    b = W.uniform_rhs(dim, n, seed=90) / (n + 1) ** dim
+    s = mgir.Solver(dim, n, W.precision_map("dsh", nl), disc="q1", nlevels=nl, rescale_half=True,
+                    cycles_per_step=2)
+    u, res = s.solve(torch.from_numpy(b).to(dev))
+    assert res.status == 0
+    assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
+
+
+@pytest.mark.parametrize("dim,n", [(3, 191), (3, 287), (2, 6143)])
+def test_q1_paper_grids_full_size(dev, ref, dim, n):
+    """The paper's smallest and largest meshes (193^3 and 289^3 vertices, and
+    6145^2), FP16 cycle, base level c - 1 solved by CG: the FP64 residual
+    recomputed by the oracle meets the tolerance, in no more steps than the
+    FP64 cycle needs plus two."""
+    print(f"q1 paper grid dim={dim} n={n}", flush=True)
+    m = mgir.full_levels(n)
+    b = W.uniform_rhs(dim, n, seed=100 + n) / (n + 1) ** dim
+    bt = torch.from_numpy(b).to(dev)
+    _, r64 = mgir.Solver(dim, n, ["f64"] * m, disc="q1", residual_scaling=False).solve(bt)
+    s = mgir.Solver(dim, n, W.precision_map("f16", m), disc="q1")
+    u, res = s.solve(bt)
+    assert res.status == 0 and r64.status == 0
+    assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
+    assert res.iterations <= r64.iterations + 2
