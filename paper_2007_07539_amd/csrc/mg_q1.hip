@@ -14,8 +14,9 @@
 // Damped Jacobi: c <- c + omega (b - S c) / diag(S), diag(S) = 8/3 in 2-D and
 // 3-D.  Arithmetic in the level's accumulator format (FP32 for FP32, FP16 and
 // BF16 storage, FP64 for FP64), one rounding into the storage format per
-// stored value.  The transfers and residuals read neighbours through the
-// caches: one thread per interior point, consecutive threads on consecutive x,
+// stored value.  The kernels read neighbours through the caches: one thread
+// per interior point (four consecutive x points in the interpolation, which
+// then loads each coarse value once), consecutive threads on consecutive x,
 // and work-group numbers remapped so that each XCD takes one contiguous range
 // of points (neighbouring rows and planes then meet in the same L2).
 #include "mg_device.h"
@@ -43,6 +44,14 @@ template <int D> __device__ __forceinline__ size_t q1_at(unsigned i, int n, int 
 __device__ __forceinline__ unsigned q1_index(int xcd) {
     const int b = xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
     return (unsigned)b * kThreads + threadIdx.x;
+}
+
+// Row segments of kV points for the interpolation: segment t covers x0 ..
+// x0 + kV - 1 of one row (points beyond n are not stored).
+constexpr int kV = 4;
+__host__ __device__ __forceinline__ unsigned q1_segs_per_row(int n) { return (unsigned)(n + kV - 1) / kV; }
+__host__ __device__ __forceinline__ unsigned q1_segs(int D, int n) {
+    return q1_segs_per_row(n) * (D == 3 ? (unsigned)n * n : (unsigned)n);
 }
 
 // First Jacobi iterate from c = 0: c = round(w b), w = omega / diag(S).
@@ -121,32 +130,48 @@ __global__ __launch_bounds__(kThreads) void k_q1_restrict(const A *__restrict__ 
 
 // c += 4 P ec (linear interpolation of the coarse correction) in place, in W:
 // along each axis an even fine index 2X copies coarse X, an odd one averages
-// coarse (x-1)/2 and (x+1)/2 (ghosts hold zero).
+// coarse (x-1)/2 and (x+1)/2 (ghosts hold zero).  A segment's fine points
+// x0 .. x0+3 need coarse x from x0/2 to x0/2 + 2 (x0 odd).
 template <int D, class TF, class TC>
 __global__ __launch_bounds__(kThreads) void k_q1_prolong_add(TF *__restrict__ c, const TC *__restrict__ ec, int n,
-                                                             int P, int Pc, unsigned N) {
+                                                             int P, int Pc, unsigned NS) {
     typedef typename std::conditional<sizeof(acc_t<TF>) >= sizeof(acc_t<TC>), acc_t<TF>, acc_t<TC>>::type W;
-    const unsigned i = q1_index(1);
-    if (i >= N) return;
-    int x, y, z;
-    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    constexpr int K = kV / 2 + 1;
+    const unsigned t = q1_index(1);
+    if (t >= NS) return;
+    const unsigned ns = q1_segs_per_row(n);
+    const unsigned row = t / ns;
+    const int x0 = 1 + kV * (int)(t - row * ns);
+    const int y = D == 3 ? (int)(row % (unsigned)n) + 1 : 0;
+    const int z = D == 3 ? (int)(row / (unsigned)n) + 1 : (int)row + 1;
+    const long o = D == 3 ? (long)Grid<3>{P}.at(x0, y, z) : (long)Grid<2>{P}.at(x0, 0, z);
     const Grid<D> gc{Pc};
-    const int x0 = x >> 1, x1 = (x + 1) >> 1, z0 = z >> 1, z1 = (z + 1) >> 1;
-    auto xs = [&](int Yc, int Zc) -> W {
-        const size_t b = D == 3 ? gc.at(0, Yc, Zc) : gc.at(0, 0, Zc);
-        return (W)widen(ec[b + x0]) + (W)widen(ec[b + x1]);
-    };
-    W s;
+    const int cx = x0 >> 1;
+    // s2[k]: coarse value at x = cx + k summed over the (up to) 2 x 2 coarse
+    // rows around the fine row, each axis counting an aligned row twice
+    W s2[K];
+    const int z0 = z >> 1, z1 = (z + 1) >> 1;
     if (D == 2) {
-        s = xs(0, z0) + xs(0, z1);
+        const long b0 = (long)gc.at(cx, 0, z0), b1 = (long)gc.at(cx, 0, z1);
+#pragma unroll
+        for (int k = 0; k < K; ++k) s2[k] = (W)widen(ec[b0 + k]) + (W)widen(ec[b1 + k]);
     } else {
         const int y0 = y >> 1, y1 = (y + 1) >> 1;
-        s = (xs(y0, z0) + xs(y1, z0)) + (xs(y0, z1) + xs(y1, z1));
+        const long b00 = (long)gc.at(cx, y0, z0), b10 = (long)gc.at(cx, y1, z0);
+        const long b01 = (long)gc.at(cx, y0, z1), b11 = (long)gc.at(cx, y1, z1);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            s2[k] = ((W)widen(ec[b00 + k]) + (W)widen(ec[b10 + k])) + ((W)widen(ec[b01 + k]) + (W)widen(ec[b11 + k]));
     }
-    // each axis adds the same coarse value twice where the fine index is even,
-    // so s is 2^D times the interpolant; 4 P ec = s * 4 / 2^D
-    s *= W(D == 3 ? 0.5 : 1.0);
-    c[o] = store_as<TF>((W)widen(c[o]) + s);
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+        const int x = x0 + i;
+        if (x > n) break;
+        // 2^D times the interpolant; 4 P ec = that * 4 / 2^D
+        W s = s2[(x >> 1) - cx] + s2[((x + 1) >> 1) - cx];
+        s *= W(D == 3 ? 0.5 : 1.0);
+        c[o + i] = store_as<TF>((W)widen(c[o + i]) + s);
+    }
 }
 
 // Finest-level update of a refinement step in FP64: U += alpha f c and
@@ -279,7 +304,7 @@ hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *r
 
 template <class TF, class TC>
 hipError_t prolong_t(int D, int n, int P, void *c, const void *ec, hipStream_t st) {
-    const unsigned N = npoints(D, n);
+    const unsigned N = q1_segs(D, n);
     const int Pc = (n - 1) / 2 + 1;
     if (D == 3)
         hipLaunchKernelGGL((k_q1_prolong_add<3, TF, TC>), dim3(nblocks(N)), dim3(kThreads), 0, st,
