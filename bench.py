@@ -314,6 +314,8 @@ def main():
                     help="only measure the streaming bandwidth ceilings (copy, read, write, update mix)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-instances and many-right-hand-sides measurements")
+    ap.add_argument("--q1-profile-only", action="store_true",
+                    help="only run Q1 finite-element solves at --n (3-D, --map levels) for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
@@ -327,6 +329,22 @@ def main():
 
     if args.ceiling:
         print(json.dumps(bandwidth_ceiling(torch, mgir)), flush=True)
+        return
+
+    if args.q1_profile_only:
+        # warm-up plus --steps timed Q1 solves of the lumped load vector
+        n = args.n
+        dev = torch.device("cuda:0")
+        bq = torch.from_numpy(W.q1_load_vector(3, n, seed=12)).to(dev)
+        Lq = mgir.full_levels(n)
+        s = mgir.Solver(3, n, W.precision_map(args.map, Lq), disc="q1", residual_scaling=args.map != "f64",
+                        device=dev)
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = s.solve(bq)
+            torch.cuda.synchronize()
+            log(f"[bench] Q1 solve {k}: {(time.perf_counter() - t0) * 1e3:.2f} ms, {r.iterations} steps")
         return
 
     n = args.n

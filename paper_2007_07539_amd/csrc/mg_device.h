@@ -246,19 +246,22 @@ template <int D> struct Grid {
 // inside the padded array (ghosts hold zero).
 template <int D, class A, class T>
 __device__ __forceinline__ A q1_weighted(const T *__restrict__ v, size_t o, int P) {
-    const long b = (long)o;
-    auto L = [&](long d) -> A { return (A)widen(v[b + d]); };
+    // one pointer per neighbour row; the x-neighbours are then constant offsets
+    const T *c = v + o;
     const long Y = P;
+    auto L = [](const T *r, int d) -> A { return (A)widen(r[d]); };
     if (D == 2) {
-        const A nb = ((L(-Y - 1) + L(-Y)) + (L(-Y + 1) + L(-1))) + ((L(1) + L(Y - 1)) + (L(Y) + L(Y + 1)));
-        return fmaT<A>(A(8), L(0), -nb);
+        const T *s = c - Y, *t = c + Y;
+        const A nb = ((L(s, -1) + L(s, 0)) + (L(s, 1) + L(c, -1))) + ((L(c, 1) + L(t, -1)) + (L(t, 0) + L(t, 1)));
+        return fmaT<A>(A(8), L(c, 0), -nb);
     }
     const long Z = (long)P * P;
-    const A e = ((L(-Z - Y) + L(-Z - 1)) + (L(-Z + 1) + L(-Z + Y))) + ((L(-Y - 1) + L(-Y + 1)) + (L(Y - 1) + L(Y + 1))) +
-                ((L(Z - Y) + L(Z - 1)) + (L(Z + 1) + L(Z + Y)));
-    const A cn = ((L(-Z - Y - 1) + L(-Z - Y + 1)) + (L(-Z + Y - 1) + L(-Z + Y + 1))) +
-                 ((L(Z - Y - 1) + L(Z - Y + 1)) + (L(Z + Y - 1) + L(Z + Y + 1)));
-    return fmaT<A>(A(32), L(0), -fmaT<A>(A(2), e, cn));
+    const T *bs = c - Z - Y, *b0 = c - Z, *bn = c - Z + Y, *s = c - Y, *t = c + Y;
+    const T *ts = c + Z - Y, *t0 = c + Z, *tn = c + Z + Y;
+    const A e = ((L(bs, 0) + L(b0, -1)) + (L(b0, 1) + L(bn, 0))) + ((L(s, -1) + L(s, 1)) + (L(t, -1) + L(t, 1))) +
+                ((L(ts, 0) + L(t0, -1)) + (L(t0, 1) + L(tn, 0)));
+    const A cn = ((L(bs, -1) + L(bs, 1)) + (L(bn, -1) + L(bn, 1))) + ((L(ts, -1) + L(ts, 1)) + (L(tn, -1) + L(tn, 1)));
+    return fmaT<A>(A(32), L(c, 0), -fmaT<A>(A(2), e, cn));
 }
 template <int D, class A> __device__ __forceinline__ A q1_scale() { return D == 3 ? A(1.0 / 12.0) : A(1.0 / 3.0); }
 

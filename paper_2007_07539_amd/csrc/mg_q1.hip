@@ -41,6 +41,15 @@ template <int D> __device__ __forceinline__ size_t q1_at(unsigned i, int n, int 
     return Grid<D>{P}.at(x, y, z);
 }
 
+// Point of a (x blocks, n, n) grid (3-D) or (x blocks, n) grid (2-D): no
+// division; false beyond the row.
+template <int D> __device__ __forceinline__ bool q1_point(int n, int P, size_t &o) {
+    const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x) + 1;
+    if (x > n) return false;
+    o = D == 3 ? Grid<3>{P}.at(x, (int)blockIdx.y + 1, (int)blockIdx.z + 1) : Grid<2>{P}.at(x, 0, (int)blockIdx.y + 1);
+    return true;
+}
+
 __device__ __forceinline__ unsigned q1_index(int xcd) {
     const int b = xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
     return (unsigned)b * kThreads + threadIdx.x;
@@ -60,12 +69,10 @@ __host__ __device__ __forceinline__ unsigned q1_segs(int D, int n) {
 template <int D, class T, bool FROM_R>
 __global__ __launch_bounds__(kThreads) void k_q1_first(const T *__restrict__ b, const double *__restrict__ R,
                                                        const double *__restrict__ scal, T *__restrict__ bout,
-                                                       T *__restrict__ cout, int n, int P, unsigned N, acc_t<T> w) {
+                                                       T *__restrict__ cout, int n, int P, acc_t<T> w) {
     typedef acc_t<T> A;
-    const unsigned i = q1_index(1);
-    if (i >= N) return;
-    int x, y, z;
-    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    size_t o;
+    if (!q1_point<D>(n, P, o)) return;
     A bv;
     if (FROM_R) {
         const T bh = Store<T>::from_f64(R[o] * scal[1]);
@@ -80,12 +87,10 @@ __global__ __launch_bounds__(kThreads) void k_q1_first(const T *__restrict__ b, 
 // One Jacobi sweep: cout = c + w (b - S c).
 template <int D, class T>
 __global__ __launch_bounds__(kThreads) void k_q1_sweep(const T *__restrict__ b, const T *__restrict__ c,
-                                                       T *__restrict__ cout, int n, int P, unsigned N, acc_t<T> w) {
+                                                       T *__restrict__ cout, int n, int P, acc_t<T> w) {
     typedef acc_t<T> A;
-    const unsigned i = q1_index(1);
-    if (i >= N) return;
-    int x, y, z;
-    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    size_t o;
+    if (!q1_point<D>(n, P, o)) return;
     const A sc = q1_weighted<D, A>(c, o, P) * q1_scale<D, A>();
     const A r = (A)widen(b[o]) - sc;
     cout[o] = Store<T>::from_acc(fmaT<A>(w, r, (A)widen(c[o])));
@@ -94,12 +99,10 @@ __global__ __launch_bounds__(kThreads) void k_q1_sweep(const T *__restrict__ b, 
 // Fine residual r = b - S c in the accumulator format (the restriction's input).
 template <int D, class T>
 __global__ __launch_bounds__(kThreads) void k_q1_resid(const T *__restrict__ b, const T *__restrict__ c,
-                                                       acc_t<T> *__restrict__ r, int n, int P, unsigned N) {
+                                                       acc_t<T> *__restrict__ r, int n, int P) {
     typedef acc_t<T> A;
-    const unsigned i = q1_index(1);
-    if (i >= N) return;
-    int x, y, z;
-    const size_t o = q1_at<D>(i, n, P, x, y, z);
+    size_t o;
+    if (!q1_point<D>(n, P, o)) return;
     r[o] = (A)widen(b[o]) - q1_weighted<D, A>(c, o, P) * q1_scale<D, A>();
 }
 
@@ -180,24 +183,31 @@ __global__ __launch_bounds__(kThreads) void k_q1_prolong_add(TF *__restrict__ c,
 template <int D, class T>
 __global__ __launch_bounds__(kThreads) void k_q1_outer(const T *__restrict__ c, double *__restrict__ R,
                                                        double *__restrict__ U, const double *__restrict__ scal,
-                                                       double f, int n, int P, unsigned N, double *__restrict__ part) {
+                                                       double f, int n, int P, double *__restrict__ part) {
+    // grid (x blocks, gy): a thread keeps its x and walks the rows
+    // blockIdx.y, blockIdx.y + gy, ... (row = y + n z in 3-D)
     __shared__ double red[8];
     const double a = scal[0];
     double ss = 0.0, mx = 0.0;
-    for (unsigned i = blockIdx.x * kThreads + threadIdx.x; i < N; i += gridDim.x * kThreads) {
-        int x, y, z;
-        const size_t o = q1_at<D>(i, n, P, x, y, z);
-        const double sc = q1_weighted<D, double>(c, o, P) * q1_scale<D, double>();
-        const double r = fmaT<double>(-a, sc, R[o]);
-        R[o] = r;
-        U[o] = fmaT<double>(a * f, (double)widen(c[o]), U[o]);
-        ss += r * r;
-        mx = nanmax(mx, fabs(r));
+    const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x) + 1;
+    const unsigned rows = D == 3 ? (unsigned)n * n : (unsigned)n;
+    if (x <= n) {
+        for (unsigned row = blockIdx.y; row < rows; row += gridDim.y) {
+            const size_t o = D == 3 ? Grid<3>{P}.at(x, (int)(row % (unsigned)n) + 1, (int)(row / (unsigned)n) + 1)
+                                    : Grid<2>{P}.at(x, 0, (int)row + 1);
+            const double sc = q1_weighted<D, double>(c, o, P) * q1_scale<D, double>();
+            const double r = fmaT<double>(-a, sc, R[o]);
+            R[o] = r;
+            U[o] = fmaT<double>(a * f, (double)widen(c[o]), U[o]);
+            ss += r * r;
+            mx = nanmax(mx, fabs(r));
+        }
     }
     block_reduce(ss, mx, red);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = ss;
-        part[2 * blockIdx.x + 1] = mx;
+        const unsigned b = blockIdx.y * gridDim.x + blockIdx.x;
+        part[2 * b] = ss;
+        part[2 * b + 1] = mx;
     }
 }
 
@@ -239,30 +249,35 @@ template <int D, class T> __global__ void k_q1_coarse(const T *__restrict__ b, T
 }
 
 unsigned npoints(int D, int n) { return D == 3 ? (unsigned)n * n * n : (unsigned)n * n; }
+// Threads along x of the point-mapped kernels, and their grid.
+int q1_bx(int n) { return n > 128 ? 256 : n > 64 ? 128 : 64; }
+dim3 q1_grid(int D, int n) {
+    const unsigned bx = (unsigned)((n + q1_bx(n) - 1) / q1_bx(n));
+    return D == 3 ? dim3(bx, (unsigned)n, (unsigned)n) : dim3(bx, (unsigned)n, 1);
+}
 int nblocks(unsigned N) { return (int)((N + kThreads - 1) / kThreads); }
 
 template <class T>
 hipError_t first_t(int D, int n, int P, const void *b, const double *R, const double *scal, void *bout, void *cout,
                    double omega, hipStream_t st) {
     typedef acc_t<T> A;
-    const unsigned N = npoints(D, n);
     const A w = (A)(omega * 0.375);
     const T *bb = static_cast<const T *>(b);
     T *bo = static_cast<T *>(bout), *co = static_cast<T *>(cout);
     if (R) {
         if (D == 3)
-            hipLaunchKernelGGL((k_q1_first<3, T, true>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo, co,
-                               n, P, N, w);
+            hipLaunchKernelGGL((k_q1_first<3, T, true>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, bb, R, scal, bo, co,
+                               n, P, w);
         else
-            hipLaunchKernelGGL((k_q1_first<2, T, true>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo, co,
-                               n, P, N, w);
+            hipLaunchKernelGGL((k_q1_first<2, T, true>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, bb, R, scal, bo, co,
+                               n, P, w);
     } else {
         if (D == 3)
-            hipLaunchKernelGGL((k_q1_first<3, T, false>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo,
-                               co, n, P, N, w);
+            hipLaunchKernelGGL((k_q1_first<3, T, false>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, bb, R, scal, bo,
+                               co, n, P, w);
         else
-            hipLaunchKernelGGL((k_q1_first<2, T, false>), dim3(nblocks(N)), dim3(kThreads), 0, st, bb, R, scal, bo,
-                               co, n, P, N, w);
+            hipLaunchKernelGGL((k_q1_first<2, T, false>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, bb, R, scal, bo,
+                               co, n, P, w);
     }
     return hipGetLastError();
 }
@@ -270,32 +285,30 @@ hipError_t first_t(int D, int n, int P, const void *b, const double *R, const do
 template <class T>
 hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout, double omega, hipStream_t st) {
     typedef acc_t<T> A;
-    const unsigned N = npoints(D, n);
     const A w = (A)(omega * 0.375);
     if (D == 3)
-        hipLaunchKernelGGL((k_q1_sweep<3, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
-                           static_cast<const T *>(c), static_cast<T *>(cout), n, P, N, w);
+        hipLaunchKernelGGL((k_q1_sweep<3, T>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), static_cast<T *>(cout), n, P, w);
     else
-        hipLaunchKernelGGL((k_q1_sweep<2, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
-                           static_cast<const T *>(c), static_cast<T *>(cout), n, P, N, w);
+        hipLaunchKernelGGL((k_q1_sweep<2, T>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), static_cast<T *>(cout), n, P, w);
     return hipGetLastError();
 }
 
 template <class T, class TC>
 hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *rs, void *bc, hipStream_t st) {
     typedef acc_t<T> A;
-    const unsigned N = npoints(D, n);
     const int nc = (n - 1) / 2, Pc = nc + 1;
     const unsigned Nc = npoints(D, nc);
     A *r = static_cast<A *>(rs);
     if (D == 3) {
-        hipLaunchKernelGGL((k_q1_resid<3, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
-                           static_cast<const T *>(c), r, n, P, N);
+        hipLaunchKernelGGL((k_q1_resid<3, T>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), r, n, P);
         hipLaunchKernelGGL((k_q1_restrict<3, A, TC>), dim3(nblocks(Nc)), dim3(kThreads), 0, st, r,
                            static_cast<TC *>(bc), nc, P, Pc, Nc);
     } else {
-        hipLaunchKernelGGL((k_q1_resid<2, T>), dim3(nblocks(N)), dim3(kThreads), 0, st, static_cast<const T *>(b),
-                           static_cast<const T *>(c), r, n, P, N);
+        hipLaunchKernelGGL((k_q1_resid<2, T>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, static_cast<const T *>(b),
+                           static_cast<const T *>(c), r, n, P);
         hipLaunchKernelGGL((k_q1_restrict<2, A, TC>), dim3(nblocks(Nc)), dim3(kThreads), 0, st, r,
                            static_cast<TC *>(bc), nc, P, Pc, Nc);
     }
@@ -315,16 +328,24 @@ hipError_t prolong_t(int D, int n, int P, void *c, const void *ec, hipStream_t s
     return hipGetLastError();
 }
 
+// Grid of the update: q1_bx(n) threads along x, gy row groups, at most
+// flat_blocks(points) blocks (= reduction partials) in all.
+dim3 q1_outer_grid(int D, int n) {
+    const int xb = (n + q1_bx(n) - 1) / q1_bx(n);
+    const int cap = flat_blocks((long)npoints(D, n));
+    return dim3((unsigned)xb, (unsigned)std::max(1, cap / xb), 1);
+}
+
 template <class T>
 hipError_t outer_t(int D, int n, int P, const void *c, double *R, double *U, const double *scal, double f,
-                   double *part, int nparts, hipStream_t st) {
-    const unsigned N = npoints(D, n);
+                   double *part, hipStream_t st) {
+    const dim3 g = q1_outer_grid(D, n);
     if (D == 3)
-        hipLaunchKernelGGL((k_q1_outer<3, T>), dim3(nparts), dim3(kThreads), 0, st, static_cast<const T *>(c), R, U,
-                           scal, f, n, P, N, part);
+        hipLaunchKernelGGL((k_q1_outer<3, T>), g, dim3(q1_bx(n)), 0, st, static_cast<const T *>(c), R, U, scal, f, n,
+                           P, part);
     else
-        hipLaunchKernelGGL((k_q1_outer<2, T>), dim3(nparts), dim3(kThreads), 0, st, static_cast<const T *>(c), R, U,
-                           scal, f, n, P, N, part);
+        hipLaunchKernelGGL((k_q1_outer<2, T>), g, dim3(q1_bx(n)), 0, st, static_cast<const T *>(c), R, U, scal, f, n,
+                           P, part);
     return hipGetLastError();
 }
 
@@ -355,7 +376,10 @@ size_t q1_resid_bytes(int D, int prec, int P) {
     return level_elems(D, P) * (prec == P_F64 ? sizeof(double) : sizeof(float));
 }
 
-int q1_outer_blocks(int D, int n) { return flat_blocks((long)npoints(D, n)); }
+int q1_outer_blocks(int D, int n) {
+    const dim3 g = q1_outer_grid(D, n);
+    return (int)(g.x * g.y);
+}
 
 hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const double *R, const double *scal,
                            void *b_out, void *c_out, double omega, hipStream_t st) {
@@ -385,8 +409,7 @@ hipError_t launch_q1_prolong(int D, int pf, int pc, int n, int P, const void *c,
 
 hipError_t launch_q1_outer(int D, int prec, int n, int P, const void *c, double *R, double *U, const double *scal,
                            double f, double *part, hipStream_t st) {
-    const int nparts = q1_outer_blocks(D, n);
-    Q1_DISPATCH(prec, TT, return outer_t<TT>(D, n, P, c, R, U, scal, f, part, nparts, st));
+    Q1_DISPATCH(prec, TT, return outer_t<TT>(D, n, P, c, R, U, scal, f, part, st));
 }
 
 hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,
