@@ -106,6 +106,105 @@ __global__ __launch_bounds__(kThreads) void k_q1_resid(const T *__restrict__ b, 
     r[o] = (A)widen(b[o]) - q1_weighted<D, A>(c, o, P) * q1_scale<D, A>();
 }
 
+// Four-point forms for levels whose pitch P is a multiple of 4: a thread takes
+// x = 4j .. 4j+3 of one row (x = 0 is the ghost and is not stored), so every
+// row segment starts on a 4-element boundary and is read with one vector load;
+// x - 1 and x + 4 are single loads (for j = 0, x - 1 only serves the ghost and
+// the ghost itself is read in its place).  Grid (P/4 / threads, n, n) in 3-D, (.., n) in 2-D.
+template <class T, class A> __device__ __forceinline__ void q1_load4(const T *p, A (&o)[4]) {
+    T v[4];
+    __builtin_memcpy(v, __builtin_assume_aligned(p, 4 * sizeof(T)), sizeof(v));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = (A)widen(v[i]);
+}
+
+// w[k], k = 0..5: the row at x0 - 1 .. x0 + 4
+template <class T, class A> __device__ __forceinline__ void q1_row6(const T *r, bool first, A (&w)[6]) {
+    A m[4];
+    q1_load4<T, A>(r, m);
+    w[0] = (A)widen(r[first ? 0 : -1]);  // first: the ghost x = 0 itself (zero), never x = -1
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i + 1] = m[i];
+    w[5] = (A)widen(r[4]);
+}
+
+template <int D> __device__ __forceinline__ bool q1_seg4(int P, size_t &o, int &x0) {
+    x0 = 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (x0 >= P) return false;
+    o = D == 3 ? Grid<3>{P}.at(x0, (int)blockIdx.y + 1, (int)blockIdx.z + 1) : Grid<2>{P}.at(x0, 0, (int)blockIdx.y + 1);
+    return true;
+}
+
+// t[i] = 3 S v (2-D) or 12 S v (3-D) at x0 + i (same weights as q1_weighted)
+template <int D, class A, class T>
+__device__ __forceinline__ void q1_weighted4(const T *__restrict__ v, size_t o, int P, bool first, A (&t)[4]) {
+    const T *c = v + o;
+    const long Y = P;
+    A cc[6];
+    q1_row6<T, A>(c, first, cc);
+    if (D == 2) {
+        A s[6], n[6];
+        q1_row6<T, A>(c - Y, first, s);
+        q1_row6<T, A>(c + Y, first, n);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const A nb = ((s[i] + s[i + 1]) + (s[i + 2] + cc[i])) + ((cc[i + 2] + n[i]) + (n[i + 1] + n[i + 2]));
+            t[i] = fmaT<A>(A(8), cc[i + 1], -nb);
+        }
+        return;
+    }
+    const long Z = (long)P * P;
+    A bs[6], b0[6], bn[6], sy[6], ny[6], ts[6], t0[6], tn[6];
+    q1_row6<T, A>(c - Z - Y, first, bs);
+    q1_row6<T, A>(c - Z, first, b0);
+    q1_row6<T, A>(c - Z + Y, first, bn);
+    q1_row6<T, A>(c - Y, first, sy);
+    q1_row6<T, A>(c + Y, first, ny);
+    q1_row6<T, A>(c + Z - Y, first, ts);
+    q1_row6<T, A>(c + Z, first, t0);
+    q1_row6<T, A>(c + Z + Y, first, tn);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = i + 1;
+        const A e = ((bs[k] + b0[k - 1]) + (b0[k + 1] + bn[k])) + ((sy[k - 1] + sy[k + 1]) + (ny[k - 1] + ny[k + 1])) +
+                    ((ts[k] + t0[k - 1]) + (t0[k + 1] + tn[k]));
+        const A cn = ((bs[k - 1] + bs[k + 1]) + (bn[k - 1] + bn[k + 1])) + ((ts[k - 1] + ts[k + 1]) + (tn[k - 1] + tn[k + 1]));
+        t[i] = fmaT<A>(A(32), cc[k], -fmaT<A>(A(2), e, cn));
+    }
+}
+
+template <int D, class T>
+__global__ __launch_bounds__(kThreads) void k_q1_sweep4(const T *__restrict__ b, const T *__restrict__ c,
+                                                        T *__restrict__ cout, int P, acc_t<T> w) {
+    typedef acc_t<T> A;
+    size_t o;
+    int x0;
+    if (!q1_seg4<D>(P, o, x0)) return;
+    A s[4], bv[4], cv[4];
+    q1_weighted4<D, A>(c, o, P, x0 == 0, s);
+    q1_load4<T, A>(b + o, bv);
+    q1_load4<T, A>(c + o, cv);
+#pragma unroll
+    for (int i = x0 == 0 ? 1 : 0; i < 4; ++i) {
+        const A r = bv[i] - s[i] * q1_scale<D, A>();
+        cout[o + i] = Store<T>::from_acc(fmaT<A>(w, r, cv[i]));
+    }
+}
+
+template <int D, class T>
+__global__ __launch_bounds__(kThreads) void k_q1_resid4(const T *__restrict__ b, const T *__restrict__ c,
+                                                        acc_t<T> *__restrict__ r, int P) {
+    typedef acc_t<T> A;
+    size_t o;
+    int x0;
+    if (!q1_seg4<D>(P, o, x0)) return;
+    A s[4], bv[4];
+    q1_weighted4<D, A>(c, o, P, x0 == 0, s);
+    q1_load4<T, A>(b + o, bv);
+#pragma unroll
+    for (int i = x0 == 0 ? 1 : 0; i < 4; ++i) r[o + i] = bv[i] - s[i] * q1_scale<D, A>();
+}
+
 // Full weighting of r at coarse point (X, Y, Z), whose fine twin is
 // (2X, 2Y, 2Z): 1-D weights 1, 2, 1 summed exactly and scaled by 4^-D.
 template <int D, class A, class TC>
@@ -251,6 +350,12 @@ template <int D, class T> __global__ void k_q1_coarse(const T *__restrict__ b, T
 unsigned npoints(int D, int n) { return D == 3 ? (unsigned)n * n * n : (unsigned)n * n; }
 // Threads along x of the point-mapped kernels, and their grid.
 int q1_bx(int n) { return n > 128 ? 256 : n > 64 ? 128 : 64; }
+// Four-point forms: P/4 threads per row.
+int q1_bx4(int P) { return P / 4 > 128 ? 256 : P / 4 > 64 ? 128 : 64; }
+dim3 q1_grid4(int D, int n, int P) {
+    const unsigned bx = (unsigned)((P / 4 + q1_bx4(P) - 1) / q1_bx4(P));
+    return D == 3 ? dim3(bx, (unsigned)n, (unsigned)n) : dim3(bx, (unsigned)n, 1);
+}
 dim3 q1_grid(int D, int n) {
     const unsigned bx = (unsigned)((n + q1_bx(n) - 1) / q1_bx(n));
     return D == 3 ? dim3(bx, (unsigned)n, (unsigned)n) : dim3(bx, (unsigned)n, 1);
@@ -286,6 +391,16 @@ template <class T>
 hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout, double omega, hipStream_t st) {
     typedef acc_t<T> A;
     const A w = (A)(omega * 0.375);
+    if (P % 4 == 0) {
+        const dim3 g4 = q1_grid4(D, n, P);
+        if (D == 3)
+            hipLaunchKernelGGL((k_q1_sweep4<3, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
+                               static_cast<const T *>(c), static_cast<T *>(cout), P, w);
+        else
+            hipLaunchKernelGGL((k_q1_sweep4<2, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
+                               static_cast<const T *>(c), static_cast<T *>(cout), P, w);
+        return hipGetLastError();
+    }
     if (D == 3)
         hipLaunchKernelGGL((k_q1_sweep<3, T>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, static_cast<const T *>(b),
                            static_cast<const T *>(c), static_cast<T *>(cout), n, P, w);
@@ -301,6 +416,22 @@ hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *r
     const int nc = (n - 1) / 2, Pc = nc + 1;
     const unsigned Nc = npoints(D, nc);
     A *r = static_cast<A *>(rs);
+    if (P % 4 == 0) {
+        const dim3 g4 = q1_grid4(D, n, P);
+        if (D == 3)
+            hipLaunchKernelGGL((k_q1_resid4<3, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
+                               static_cast<const T *>(c), r, P);
+        else
+            hipLaunchKernelGGL((k_q1_resid4<2, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
+                               static_cast<const T *>(c), r, P);
+        if (D == 3)
+            hipLaunchKernelGGL((k_q1_restrict<3, A, TC>), dim3(nblocks(Nc)), dim3(kThreads), 0, st, r,
+                               static_cast<TC *>(bc), nc, P, Pc, Nc);
+        else
+            hipLaunchKernelGGL((k_q1_restrict<2, A, TC>), dim3(nblocks(Nc)), dim3(kThreads), 0, st, r,
+                               static_cast<TC *>(bc), nc, P, Pc, Nc);
+        return hipGetLastError();
+    }
     if (D == 3) {
         hipLaunchKernelGGL((k_q1_resid<3, T>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, static_cast<const T *>(b),
                            static_cast<const T *>(c), r, n, P);
