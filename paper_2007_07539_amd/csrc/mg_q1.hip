@@ -14,11 +14,14 @@
 // Damped Jacobi: c <- c + omega (b - S c) / diag(S), diag(S) = 8/3 in 2-D and
 // 3-D.  Arithmetic in the level's accumulator format (FP32 for FP32, FP16 and
 // BF16 storage, FP64 for FP64), one rounding into the storage format per
-// stored value.  The kernels read neighbours through the caches: one thread
-// per interior point (four consecutive x points in the interpolation, which
-// then loads each coarse value once), consecutive threads on consecutive x,
-// and work-group numbers remapped so that each XCD takes one contiguous range
-// of points (neighbouring rows and planes then meet in the same L2).
+// stored value.  The kernels read neighbours through the caches, consecutive
+// threads on consecutive x.  The sweep and the residual take four x points per
+// thread with one vector load per neighbour row where the pitch is a multiple
+// of 4, else one point per thread on a (x blocks, n, n) grid.  The
+// interpolation takes four fine points per thread (each coarse value loaded
+// once).  The restriction and interpolation remap work-group numbers so that
+// each XCD takes one contiguous range of points; neighbouring rows and planes
+// then meet in the same L2.
 #include "mg_device.h"
 #include "mg_launch.h"
 
