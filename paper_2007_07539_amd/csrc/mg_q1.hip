@@ -208,6 +208,131 @@ __global__ __launch_bounds__(kThreads) void k_q1_resid4(const T *__restrict__ b,
     for (int i = x0 == 0 ? 1 : 0; i < 4; ++i) r[o + i] = bv[i] - s[i] * q1_scale<D, A>();
 }
 
+// 3-D, pitch a multiple of 4: the sweep (RESID false: out = c + w (b - S c) in
+// T) or the residual (RESID true: out = b - S c in the accumulator format),
+// with each thread marching zc planes of its four-point row segment.  Per
+// plane it keeps the centre row C and the sum A of rows y - 1 and y + 1 (six
+// values each, x0 - 1 .. x0 + 4), so each new plane costs three row loads:
+//   edges   = A_z[x-1] + A_z[x+1] + C_{z-1}[x-1] + C_{z-1}[x+1]
+//             + C_{z+1}[x-1] + C_{z+1}[x+1] + A_{z-1}[x] + A_{z+1}[x],
+//   corners = A_{z-1}[x-1] + A_{z-1}[x+1] + A_{z+1}[x-1] + A_{z+1}[x+1],
+//   12 S c  = 32 C_z[x] - 2 edges - corners.
+// Grid (P/4 / threads, n, ceil(n / zc)).
+template <class T, bool RESID>
+__global__ __launch_bounds__(kThreads) void k_q1_march4(const T *__restrict__ b, const T *__restrict__ c,
+                                                        void *__restrict__ out, int n, int P, int zc, acc_t<T> w) {
+    typedef acc_t<T> A;
+    const int x0 = 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (x0 >= P) return;
+    const int y = (int)blockIdx.y + 1;
+    const int z0 = (int)blockIdx.z * zc + 1;
+    const int z1 = min(z0 + zc - 1, n);
+    const bool first = x0 == 0;
+    const long Y = P;
+    const Grid<3> g{P};
+    A Am[6], Cm[6], A0[6], C0[6], Ap[6], Cp[6];
+    auto plane = [&](int z, A(&Av)[6], A(&Cv)[6]) {
+        const T *r = c + g.at(x0, y, z);
+        A s[6], t[6];
+        q1_row6<T, A>(r, first, Cv);
+        q1_row6<T, A>(r - Y, first, s);
+        q1_row6<T, A>(r + Y, first, t);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Av[k] = s[k] + t[k];
+    };
+    plane(z0 - 1, Am, Cm);
+    plane(z0, A0, C0);
+    for (int z = z0; z <= z1; ++z) {
+        plane(z + 1, Ap, Cp);
+        const size_t o = g.at(x0, y, z);
+        A bv[4];
+        q1_load4<T, A>(b + o, bv);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = i + 1;
+            const A e = ((A0[k - 1] + A0[k + 1]) + ((Cm[k - 1] + Cm[k + 1]) + (Cp[k - 1] + Cp[k + 1]))) + (Am[k] + Ap[k]);
+            const A cn = (Am[k - 1] + Am[k + 1]) + (Ap[k - 1] + Ap[k + 1]);
+            const A sc = fmaT<A>(A(32), C0[k], -fmaT<A>(A(2), e, cn)) * q1_scale<3, A>();
+            if (i == 0 && first) continue;
+            if (RESID)
+                static_cast<A *>(out)[o + i] = bv[i] - sc;
+            else
+                static_cast<T *>(out)[o + i] = Store<T>::from_acc(fmaT<A>(w, bv[i] - sc, C0[k]));
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            Am[k] = A0[k], Cm[k] = C0[k];
+            A0[k] = Ap[k], C0[k] = Cp[k];
+        }
+    }
+}
+
+// The FP64 update (as k_q1_outer) in the marching form of k_q1_march4: grid
+// (P/4 / threads, n, zgroups), zc planes per thread; one partial per block.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict__ c, double *__restrict__ R,
+                                                             double *__restrict__ U, const double *__restrict__ scal,
+                                                             double f, int n, int P, int zc,
+                                                             double *__restrict__ part) {
+    typedef double A;
+    __shared__ double red[8];
+    const double a = scal[0];
+    double ss = 0.0, mx = 0.0;
+    const int x0 = 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int y = (int)blockIdx.y + 1;
+    const int z0 = (int)blockIdx.z * zc + 1;
+    const int z1 = min(z0 + zc - 1, n);
+    if (x0 < P && z0 <= n) {
+        const bool first = x0 == 0;
+        const long Y = P;
+        const Grid<3> g{P};
+        A Am[6], Cm[6], A0[6], C0[6], Ap[6], Cp[6];
+        auto plane = [&](int z, A(&Av)[6], A(&Cv)[6]) {
+            const T *r = c + g.at(x0, y, z);
+            A sv[6], tv[6];
+            q1_row6<T, A>(r, first, Cv);
+            q1_row6<T, A>(r - Y, first, sv);
+            q1_row6<T, A>(r + Y, first, tv);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Av[k] = sv[k] + tv[k];
+        };
+        plane(z0 - 1, Am, Cm);
+        plane(z0, A0, C0);
+        for (int z = z0; z <= z1; ++z) {
+            plane(z + 1, Ap, Cp);
+            const size_t o = g.at(x0, y, z);
+            A rv[4], uv[4];
+            q1_load4<double, A>(R + o, rv);
+            q1_load4<double, A>(U + o, uv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = i + 1;
+                const A e =
+                    ((A0[k - 1] + A0[k + 1]) + ((Cm[k - 1] + Cm[k + 1]) + (Cp[k - 1] + Cp[k + 1]))) + (Am[k] + Ap[k]);
+                const A cn = (Am[k - 1] + Am[k + 1]) + (Ap[k - 1] + Ap[k + 1]);
+                const A sc = fmaT<A>(A(32), C0[k], -fmaT<A>(A(2), e, cn)) * q1_scale<3, A>();
+                if (i == 0 && first) continue;
+                const double r = fmaT<double>(-a, sc, rv[i]);
+                R[o + i] = r;
+                U[o + i] = fmaT<double>(a * f, C0[k], uv[i]);
+                ss += r * r;
+                mx = nanmax(mx, fabs(r));
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                Am[k] = A0[k], Cm[k] = C0[k];
+                A0[k] = Ap[k], C0[k] = Cp[k];
+            }
+        }
+    }
+    block_reduce(ss, mx, red);
+    if (threadIdx.x == 0) {
+        const unsigned b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        part[2 * b] = ss;
+        part[2 * b + 1] = mx;
+    }
+}
+
 // Full weighting of r at coarse point (X, Y, Z), whose fine twin is
 // (2X, 2Y, 2Z): 1-D weights 1, 2, 1 summed exactly and scaled by 4^-D.
 template <int D, class A, class TC>
@@ -359,6 +484,12 @@ dim3 q1_grid4(int D, int n, int P) {
     const unsigned bx = (unsigned)((P / 4 + q1_bx4(P) - 1) / q1_bx4(P));
     return D == 3 ? dim3(bx, (unsigned)n, (unsigned)n) : dim3(bx, (unsigned)n, 1);
 }
+// Planes marched by one thread of k_q1_march4, and its grid.
+constexpr int kMarchZ = 16;
+dim3 q1_grid4z(int n, int P) {
+    const unsigned bx = (unsigned)((P / 4 + q1_bx4(P) - 1) / q1_bx4(P));
+    return dim3(bx, (unsigned)n, (unsigned)((n + kMarchZ - 1) / kMarchZ));
+}
 dim3 q1_grid(int D, int n) {
     const unsigned bx = (unsigned)((n + q1_bx(n) - 1) / q1_bx(n));
     return D == 3 ? dim3(bx, (unsigned)n, (unsigned)n) : dim3(bx, (unsigned)n, 1);
@@ -397,8 +528,8 @@ hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout
     if (P % 4 == 0) {
         const dim3 g4 = q1_grid4(D, n, P);
         if (D == 3)
-            hipLaunchKernelGGL((k_q1_sweep4<3, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
-                               static_cast<const T *>(c), static_cast<T *>(cout), P, w);
+            hipLaunchKernelGGL((k_q1_march4<T, false>), q1_grid4z(n, P), dim3(q1_bx4(P)), 0, st,
+                               static_cast<const T *>(b), static_cast<const T *>(c), cout, n, P, kMarchZ, w);
         else
             hipLaunchKernelGGL((k_q1_sweep4<2, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
                                static_cast<const T *>(c), static_cast<T *>(cout), P, w);
@@ -422,8 +553,9 @@ hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *r
     if (P % 4 == 0) {
         const dim3 g4 = q1_grid4(D, n, P);
         if (D == 3)
-            hipLaunchKernelGGL((k_q1_resid4<3, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
-                               static_cast<const T *>(c), r, P);
+            hipLaunchKernelGGL((k_q1_march4<T, true>), q1_grid4z(n, P), dim3(q1_bx4(P)), 0, st,
+                               static_cast<const T *>(b), static_cast<const T *>(c), static_cast<void *>(r), n, P,
+                               kMarchZ, A(0));
         else
             hipLaunchKernelGGL((k_q1_resid4<2, T>), g4, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(b),
                                static_cast<const T *>(c), r, P);
@@ -464,9 +596,23 @@ hipError_t prolong_t(int D, int n, int P, void *c, const void *ec, hipStream_t s
 
 // Grid of the update: q1_bx(n) threads along x, gy row groups, at most
 // flat_blocks(points) blocks (= reduction partials) in all.
+// The marching update (k_q1_outer_march) serves 3-D levels of pitch a
+// multiple of 4 whose (x blocks, n rows) fit the partial budget
+// flat_blocks(points); the rest take k_q1_outer.
+bool q1_outer_marches(int D, int n) {
+    const int P = n + 1;
+    if (D != 3 || P % 4 != 0) return false;
+    const int xb = (P / 4 + q1_bx4(P) - 1) / q1_bx4(P);
+    return xb * n <= flat_blocks((long)npoints(D, n));
+}
+
 dim3 q1_outer_grid(int D, int n) {
+    const int P = n + 1, cap = flat_blocks((long)npoints(D, n));
+    if (q1_outer_marches(D, n)) {
+        const int xb = (P / 4 + q1_bx4(P) - 1) / q1_bx4(P);
+        return dim3((unsigned)xb, (unsigned)n, (unsigned)std::min(n, cap / (xb * n)));
+    }
     const int xb = (n + q1_bx(n) - 1) / q1_bx(n);
-    const int cap = flat_blocks((long)npoints(D, n));
     return dim3((unsigned)xb, (unsigned)std::max(1, cap / xb), 1);
 }
 
@@ -474,6 +620,12 @@ template <class T>
 hipError_t outer_t(int D, int n, int P, const void *c, double *R, double *U, const double *scal, double f,
                    double *part, hipStream_t st) {
     const dim3 g = q1_outer_grid(D, n);
+    if (q1_outer_marches(D, n)) {
+        const int zc = (n + (int)g.z - 1) / (int)g.z;
+        hipLaunchKernelGGL((k_q1_outer_march<T>), g, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(c), R, U, scal, f,
+                           n, P, zc, part);
+        return hipGetLastError();
+    }
     if (D == 3)
         hipLaunchKernelGGL((k_q1_outer<3, T>), g, dim3(q1_bx(n)), 0, st, static_cast<const T *>(c), R, U, scal, f, n,
                            P, part);
@@ -512,7 +664,7 @@ size_t q1_resid_bytes(int D, int prec, int P) {
 
 int q1_outer_blocks(int D, int n) {
     const dim3 g = q1_outer_grid(D, n);
-    return (int)(g.x * g.y);
+    return (int)(g.x * g.y * g.z);
 }
 
 hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const double *R, const double *scal,
