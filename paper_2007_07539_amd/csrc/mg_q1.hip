@@ -15,13 +15,13 @@
 // 3-D.  Arithmetic in the level's accumulator format (FP32 for FP32, FP16 and
 // BF16 storage, FP64 for FP64), one rounding into the storage format per
 // stored value.  The kernels read neighbours through the caches, consecutive
-// threads on consecutive x.  The sweep and the residual take four x points per
-// thread with one vector load per neighbour row where the pitch is a multiple
-// of 4, else one point per thread on a (x blocks, n, n) grid.  The
-// interpolation takes four fine points per thread (each coarse value loaded
-// once).  The restriction and interpolation remap work-group numbers so that
-// each XCD takes one contiguous range of points; neighbouring rows and planes
-// then meet in the same L2.
+// threads on consecutive x.  Where the pitch is a multiple of 4 the sweep, the
+// residual and the FP64 update take four x points per thread with one vector
+// load per row: in 3-D marching z with three planes of row sums kept in
+// registers, in 2-D row by row.  Elsewhere they take one point per thread on
+// a (x blocks, n, n) grid.  The interpolation takes four fine points per thread
+// (each coarse value loaded once).  The restriction and interpolation remap
+// work-group numbers so that each XCD takes one contiguous range of points.
 #include "mg_device.h"
 #include "mg_launch.h"
 
