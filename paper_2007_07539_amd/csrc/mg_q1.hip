@@ -109,11 +109,12 @@ __global__ __launch_bounds__(kThreads) void k_q1_resid(const T *__restrict__ b, 
     r[o] = (A)widen(b[o]) - q1_weighted<D, A>(c, o, P) * q1_scale<D, A>();
 }
 
-// Four-point forms for levels whose pitch P is a multiple of 4: a thread takes
+// Four-point forms for levels whose pitch P is a multiple of 4 (2-D here; 3-D
+// below, marching z): a thread takes
 // x = 4j .. 4j+3 of one row (x = 0 is the ghost and is not stored), so every
 // row segment starts on a 4-element boundary and is read with one vector load;
 // x - 1 and x + 4 are single loads (for j = 0, x - 1 only serves the ghost and
-// the ghost itself is read in its place).  Grid (P/4 / threads, n, n) in 3-D, (.., n) in 2-D.
+// the ghost itself is read in its place).  Grid (P/4 / threads, n).
 template <class T, class A> __device__ __forceinline__ void q1_load4(const T *p, A (&o)[4]) {
     T v[4];
     __builtin_memcpy(v, __builtin_assume_aligned(p, 4 * sizeof(T)), sizeof(v));
@@ -138,41 +139,21 @@ template <int D> __device__ __forceinline__ bool q1_seg4(int P, size_t &o, int &
     return true;
 }
 
-// t[i] = 3 S v (2-D) or 12 S v (3-D) at x0 + i (same weights as q1_weighted)
+// t[i] = 3 S v at x0 + i, 2-D (same weights as q1_weighted; the 3-D levels
+// use the marching kernels below)
 template <int D, class A, class T>
 __device__ __forceinline__ void q1_weighted4(const T *__restrict__ v, size_t o, int P, bool first, A (&t)[4]) {
+    static_assert(D == 2, "the 3-D four-point forms march z (k_q1_march4)");
     const T *c = v + o;
     const long Y = P;
-    A cc[6];
+    A cc[6], s[6], n[6];
     q1_row6<T, A>(c, first, cc);
-    if (D == 2) {
-        A s[6], n[6];
-        q1_row6<T, A>(c - Y, first, s);
-        q1_row6<T, A>(c + Y, first, n);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const A nb = ((s[i] + s[i + 1]) + (s[i + 2] + cc[i])) + ((cc[i + 2] + n[i]) + (n[i + 1] + n[i + 2]));
-            t[i] = fmaT<A>(A(8), cc[i + 1], -nb);
-        }
-        return;
-    }
-    const long Z = (long)P * P;
-    A bs[6], b0[6], bn[6], sy[6], ny[6], ts[6], t0[6], tn[6];
-    q1_row6<T, A>(c - Z - Y, first, bs);
-    q1_row6<T, A>(c - Z, first, b0);
-    q1_row6<T, A>(c - Z + Y, first, bn);
-    q1_row6<T, A>(c - Y, first, sy);
-    q1_row6<T, A>(c + Y, first, ny);
-    q1_row6<T, A>(c + Z - Y, first, ts);
-    q1_row6<T, A>(c + Z, first, t0);
-    q1_row6<T, A>(c + Z + Y, first, tn);
+    q1_row6<T, A>(c - Y, first, s);
+    q1_row6<T, A>(c + Y, first, n);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int k = i + 1;
-        const A e = ((bs[k] + b0[k - 1]) + (b0[k + 1] + bn[k])) + ((sy[k - 1] + sy[k + 1]) + (ny[k - 1] + ny[k + 1])) +
-                    ((ts[k] + t0[k - 1]) + (t0[k + 1] + tn[k]));
-        const A cn = ((bs[k - 1] + bs[k + 1]) + (bn[k - 1] + bn[k + 1])) + ((ts[k - 1] + ts[k + 1]) + (tn[k - 1] + tn[k + 1]));
-        t[i] = fmaT<A>(A(32), cc[k], -fmaT<A>(A(2), e, cn));
+        const A nb = ((s[i] + s[i + 1]) + (s[i + 2] + cc[i])) + ((cc[i + 2] + n[i]) + (n[i + 1] + n[i + 2]));
+        t[i] = fmaT<A>(A(8), cc[i + 1], -nb);
     }
 }
 
