@@ -218,3 +218,25 @@ def test_q1_paper_grids_full_size(dev, ref, dim, n):
     assert res.status == 0 and r64.status == 0
     assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
     assert res.iterations <= r64.iterations + 2
+
+
+@pytest.mark.parametrize("dim,n,nl", [(3, 95, 0), (2, 383, 5)])
+def test_q1_initial_guess_and_partial_hierarchy(dev, ref, dim, n, nl):
+    """Q1 from the paper's random initial guess in [0, 1] (Section 6), on a full
+    hierarchy and on a 2-D partial one (base 23^2 by CG), without graphs in the
+    second case: the FP64 residual meets the tolerance, within two steps of the
+    FP64 cycle."""
+    print(f"q1 u0 dim={dim} n={n} nl={nl}", flush=True)
+    m = nl or mgir.full_levels(n)
+    b = W.q1_load_vector(dim, n, seed=110)
+    u0 = W.random_initial_guess(dim, n, seed=111)
+    bt = torch.from_numpy(b).to(dev)
+    kw = dict(disc="q1", nlevels=nl, use_initial_guess=True, use_graph=nl == 0)
+    u64 = torch.from_numpy(u0).to(dev)
+    _, r64 = mgir.Solver(dim, n, ["f64"] * m, residual_scaling=False, **kw).solve(bt, u64)
+    u = torch.from_numpy(u0).to(dev)
+    s = mgir.Solver(dim, n, W.precision_map("f16", m), **kw)
+    u, res = s.solve(bt, u)
+    assert res.status == 0 and r64.status == 0
+    assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
+    assert res.iterations <= r64.iterations + 2
