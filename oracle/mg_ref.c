@@ -431,8 +431,14 @@ typedef struct {
     double true_rel_residual;  /* ||b - A u||_2 / ||b||_2 recomputed at the end */
 } ref_ir_result;
 
-/* Mixed-precision iterative refinement with residuum scaling (Algorithm 2),
- * every step in FP64.  history (optional, length hist_cap) receives
+/* Iterative refinement with residuum scaling (Algorithm 2, Section 4.3), with
+ * every quantity in FP64.  The solution u is improved by corrections from the
+ * correction equation A c = r / alpha, whose right-hand side is the current
+ * residual divided by its largest entry (alpha = 1 without scaling); one
+ * V-cycle from zero (or several, each continuing from the correction so far)
+ * approximates c, u moves by alpha c, and r is brought up to date either by
+ * subtracting alpha A c or by recomputing b - A u.  The loop ends when
+ * ||r||_2 <= rtol ||b||_2.  history (optional, length hist_cap) receives
  * ||r||_2/||b||_2 before each V-cycle and after the last one. */
 int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *o,
                  ref_ir_result *res, double *history, int hist_cap) {
@@ -464,7 +470,7 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
     }
 
     if (!o->use_initial_guess) memset(u, 0, sizeof(double) * N);
-    ref_residual_d(dim, n, disc, b, u, r); /* r_high := b_high - A_high u_high */
+    ref_residual_d(dim, n, disc, b, u, r);
     int st = REF_OK;
     int k = 0;
     for (;;) {
@@ -476,18 +482,18 @@ int ref_ir_solve(int dim, int n, const double *b, double *u, const ref_ir_opts *
         if (k >= o->max_iter) { st = REF_ERR_NOT_CONVERGED; break; }
         double alpha = o->residual_scaling ? ref_norminf(r, N) : 1.0;
         double inv_alpha = 1.0 / alpha;
-        for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];        /* scale */
+        for (long p = 0; p < N; p++) rl[p] = inv_alpha * r[p];
         int vs = ref_vcycle_disc(dim, n, disc, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter,
-                                 rl, c);                                /* one V-cycle */
-        for (int j = 1; j < cycles && vs == REF_OK; j++) {              /* further cycles */
-            ref_residual_d(dim, n, disc, rl, c, t);                     /* t = r/alpha - A c */
+                                 rl, c);
+        for (int j = 1; j < cycles && vs == REF_OK; j++) {
+            ref_residual_d(dim, n, disc, rl, c, t);
             vs = ref_vcycle_disc(dim, n, disc, nbase, o->nu1, o->nu2, o->omega, o->base_tol, o->base_max_iter,
                                  t, e);
             for (long p = 0; p < N; p++) c[p] += e[p];
         }
         if (vs != REF_OK) { st = vs; break; }
-        for (long p = 0; p < N; p++) u[p] += alpha * c[p];             /* update u */
-        if (o->recursive_residual) {                                   /* update r */
+        for (long p = 0; p < N; p++) u[p] += alpha * c[p];
+        if (o->recursive_residual) {
             ref_apply_A_disc(dim, n, disc, c, ac);
             for (long p = 0; p < N; p++) r[p] -= alpha * ac[p];
         } else {

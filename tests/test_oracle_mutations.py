@@ -35,6 +35,13 @@ MUTATIONS = {
     "scaling_not_compensated": ("u[p] += alpha * c[p];", "u[p] += c[p];"),
     "recursive_residual_sign": ("r[p] -= alpha * ac[p];", "r[p] += alpha * ac[p];"),
     "norm_without_sqrt": ("return sqrt(ref_sumsq(v, N));", "return ref_sumsq(v, N);"),
+    "norm_pairwise_drops_entry": ("return ref_sumsq(v, m) + ref_sumsq(v + m, N - m);",
+                                  "return ref_sumsq(v, m) + ref_sumsq(v + m, N - m - 1);"),
+    "norminf_without_abs": ("double a = fabs(v[p]);", "double a = v[p];"),
+    "initial_guess_ignored": ("if (!o->use_initial_guess) memset(u, 0, sizeof(double) * N);",
+                              "memset(u, 0, sizeof(double) * N);"),
+    "initial_residual_from_b": ("    ref_residual_d(dim, n, disc, b, u, r);\n    int st = REF_OK;",
+                                "    memcpy(r, b, sizeof(double) * N);\n    int st = REF_OK;"),
 }
 
 

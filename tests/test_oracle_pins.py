@@ -368,3 +368,83 @@ def test_ir_with_cg_base_reaches_tolerance(ref):
         part = ref.ir_solve(b, residual_scaling=scaling, base_n=7)
         assert part.status == 0 and part.true_rel_residual <= 1e-10
         assert abs(part.iterations - full.iterations) <= 2
+
+
+# --- norms and the initial-guess path of the refinement loop ---------------------
+
+@pytest.mark.parametrize("N", [1, 2, 7, 9, 17, 1001, 100003])
+def test_norms_against_independent_definitions(ref, N):
+    """||v||_inf is max |v_i| and ||v||_2 the square root of the exactly rounded
+    sum of squares (math.fsum), on vectors of odd and even lengths whose entries
+    are all negative, all positive or mixed (Algorithm 2 uses both norms)."""
+    import math
+    rng = np.random.default_rng(40 + N)
+    for v in (-rng.uniform(0.5, 2.0, N), rng.uniform(0.5, 2.0, N), rng.standard_normal(N) * 10.0 ** rng.integers(-8, 8, N)):
+        assert ref.norminf(v) == np.abs(v).max()
+        exact = math.sqrt(math.fsum(float(x) * float(x) for x in v))
+        assert ref.norm2(v) == pytest.approx(exact, rel=4e-16 * max(1.0, math.log2(N)))
+        assert ref.norm2(v) == pytest.approx(float(np.linalg.norm(v)), rel=1e-14)
+
+
+def test_norminf_propagates_nan(ref):
+    """A NaN anywhere makes ||r||_inf NaN, so the loop's finiteness check sees it."""
+    v = -np.arange(1.0, 12.0)
+    for i in (0, 5, 10):
+        w = v.copy()
+        w[i] = np.nan
+        assert np.isnan(ref.norminf(w)) and np.isnan(np.abs(w).max())
+
+
+@pytest.mark.parametrize("dim,n", [(2, 31), (3, 15)])
+def test_ir_from_the_exact_solution_takes_no_step(ref, dim, n):
+    """Started from the exact discrete solution (the sine-transform solve, not
+    the oracle), the refinement loop finds r = b - A u below the tolerance
+    before any V-cycle and returns u unchanged."""
+    b = W.uniform_rhs(dim, n, seed=41)
+    x = _dst_solve(b)
+    res = ref.ir_solve(b, u0=x)
+    assert res.status == 0 and res.iterations == 0
+    np.testing.assert_array_equal(res.u, x)
+    assert res.true_rel_residual <= 1e-13
+
+
+@pytest.mark.parametrize("scaling", [True, False])
+def test_ir_resume_equals_uninterrupted_solve(ref, scaling):
+    """Stopping after k steps and restarting from that iterate gives what the
+    uninterrupted solve gives, bit for bit, when the residual is recomputed as
+    b - A u every step (the restart computes exactly that residual first)."""
+    b = W.uniform_rhs(3, 31, seed=42)
+    full = ref.ir_solve(b, residual_scaling=scaling)
+    assert full.status == 0 and full.iterations > 5
+    k = 4
+    head = ref.ir_solve(b, residual_scaling=scaling, max_iter=k)
+    assert head.status == -6 and head.iterations == k
+    tail = ref.ir_solve(b, u0=head.u, residual_scaling=scaling)
+    assert tail.status == 0 and head.iterations + tail.iterations == full.iterations
+    np.testing.assert_array_equal(tail.u, full.u)
+
+
+def test_ir_from_a_random_guess_reaches_the_exact_solution(ref):
+    """From a random u0 in [0, 1] (Section 6) the loop converges to the same
+    discrete solution as from zero (pinned by the sine transform)."""
+    b = W.uniform_rhs(3, 31, seed=43)
+    u0 = W.random_initial_guess(3, 31, seed=44)
+    res = ref.ir_solve(b, u0=u0, rtol=1e-12)
+    x = _dst_solve(b)
+    assert res.status == 0 and res.true_rel_residual <= 1e-12
+    assert np.abs(res.u - x).max() <= 1e-9 * np.abs(x).max()
+    r0 = b - _apply_np(u0)
+    assert res.history[0] == pytest.approx(np.linalg.norm(r0) / np.linalg.norm(b), rel=1e-12)
+
+
+def _apply_np(v):
+    """The (2D+1)-point Laplacian by array slicing, zero outside the grid."""
+    n, dim = v.shape[0], v.ndim
+    p = np.pad(v, 1)
+    out = 2 * dim * v
+    for ax in range(dim):
+        lo = [slice(1, -1)] * dim
+        hi = [slice(1, -1)] * dim
+        lo[ax], hi[ax] = slice(0, -2), slice(2, None)
+        out = out - p[tuple(lo)] - p[tuple(hi)]
+    return out * (n + 1) ** 2
