@@ -73,7 +73,15 @@ typedef struct {
     int nu1;                 /* pre-smoothing sweeps (Algorithm 1), default 2 */
     int nu2;                 /* post-smoothing sweeps (Algorithm 1), default 2 */
     double omega;            /* damped-Jacobi weight, default 0.8 */
-    int residual_scaling;    /* 1: alpha = ||r||_inf before the cast (Algorithm 2);
+    int residual_scaling;    /* 1: alpha = 2^j ||r||_inf before the cast (Algorithm 2; the
+                                scaled residual has max-norm 2^-j).  j = 0 unless an FP16
+                                level's correction could leave FP16's range: in grid-
+                                scaled units the correction of a right-hand side of
+                                max-norm one on a level of n points per dimension is
+                                below K (n+1)^2 (K = 0.074 in 2-D, 0.058 in 3-D, above
+                                the torsion-function maximum), and j is the least power that
+                                brings that bound under 2^14 on every FP16 level (see
+                                mg_alpha_shift; 2-D n >= 511, 3-D n = 1023).
                                 0: alpha = 1 (the FP64 baseline omits scaling, Section 6) */
     int max_iter;            /* refinement steps at most, default 100 */
     double rtol;             /* stop when ||r||_2 <= rtol * ||b||_2 (FP64), default 1e-10 */
@@ -255,6 +263,14 @@ mg_status_t ir_solve_multi(mg_handle h, const double *b, double *u, mg_stats_t *
 
 /* Number of right-hand sides of a handle (1 unless from mg_setup_multi). */
 mg_status_t mg_rhs_count(mg_handle h, int *nrhs);
+
+/* The exponent j of alpha = 2^j ||r||_inf (see residual_scaling) that instance
+ * `instance` of the handle uses (0 for single-grid and many-right-hand-side
+ * handles); *shift = -1 when residual scaling is off.  mg_setup fails with
+ * MG_ERR_PREC when opt.rescale_half would enter an FP16 level whose bound
+ * exceeds 2^14 (its right-hand side is rescaled to max-norm one on its own).
+ * Errors: MG_ERR_ARG. */
+mg_status_t mg_alpha_shift(mg_handle h, int instance, int *shift);
 
 /* Release the handle (never frees caller memory).  NULL is accepted. */
 mg_status_t mg_destroy(mg_handle h);

@@ -71,6 +71,9 @@ struct ProfRec {
 struct mg_ctx {
     int dim = 3, n = 0, nl = 0;
     mg_options_t opt{};
+    // finalize-kernel code of the residual scaling: 0 = off (alpha = 1),
+    // 1 + j = on with alpha = 2^j ||r||_inf (see alpha_shift)
+    int ascale = 0;
     std::vector<LevelPlan> lv;
     size_t off_R = 0, off_U = 0, off_part = 0, off_scal = 0, ws_need = 0;
     size_t off_rs = 0, off_rpart = 0;  // per-level {s, 1/s} and the partial maxima of the rescaling
@@ -106,6 +109,7 @@ struct mg_ctx {
         size_t off_R = 0, off_U = 0;
         int part_off = 0, parts = 0;
         Shape osh;
+        int ascale = 0;
     };
     std::vector<Inst> inst;
     int Lmax = 0;
@@ -154,6 +158,46 @@ long points(int D, int n) { return D == 3 ? (long)n * n * n : (long)n * n; }
 constexpr long kMaxBasePoints = 262144;
 
 bool valid_prec(int p) { return p >= 0 && p <= 3; }
+
+// Range of the FP16 levels.  Residual scaling divides r by alpha = ||r||_inf
+// so that the correction equation's right-hand side has max-norm one
+// (Algorithm 2).  Its solution in grid-scaled units on a level of n points per
+// dimension is then bounded by max(L^-1 1) (discrete maximum principle), which
+// is close to w_D (n + 1)^2 with w_D the centre value of the torsion function
+// of the unit square, 0.07367, or cube, 0.05621: the finite-difference values
+// approach it from below, the Q1 values (lumped unit load) from above, and
+// K_D = 0.074 (2-D), 0.058 (3-D) bounds both on every grid of 15 or more points
+// per dimension.  From about 2^14 on (2-D n >= 511, 3-D n = 1023) a V-cycle's
+// values would come within a factor four of FP16's largest value 65504, or
+// beyond it.  The scale is then alpha = 2^j ||r||_inf with the least j that
+// brings K_D (n + 1)^2 of every FP16 level under 2^14; a power of two, so
+// nothing else in the method changes.
+constexpr double kHalfCorrectionBound = 16384.0;
+double correction_bound(int D, int n) { return (D == 2 ? 0.074 : 0.058) * (double)(n + 1) * (double)(n + 1); }
+int shift_for_bound(double bound) {
+    int j = 0;
+    while (bound > kHalfCorrectionBound * std::ldexp(1.0, j)) ++j;
+    return j;
+}
+// Finalize code (0: alpha = 1; 1 + j: alpha = 2^j ||r||_inf) of a hierarchy
+// with sizes ns[l] and formats prec[l], finest first.  A level entered by a
+// rescaled restriction (rescaled[l]) has its own right-hand side of max-norm
+// one, which alpha does not change: its bound must hold as it is (false).
+bool alpha_code(int D, const std::vector<int> &ns, const std::vector<int> &prec, const std::vector<bool> &rescaled,
+                int scaling, int *code) {
+    int j = 0;
+    for (size_t l = 0; l < ns.size(); ++l) {
+        if (prec[l] != P_F16) continue;
+        const double bnd = correction_bound(D, ns[l]);
+        if (rescaled[l]) {
+            if (bnd > kHalfCorrectionBound) return false;
+        } else {
+            j = std::max(j, shift_for_bound(bnd));
+        }
+    }
+    *code = scaling ? 1 + j : 0;
+    return true;
+}
 
 Shape pick_shape(int D, int P, int prec) {
     Shape s;
@@ -588,7 +632,7 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
                                 part(h), L.osh, st));
     }
     RUN(h, st, "norm_finalize", 0, 16.0 * h->outer_parts,
-        launch_finalize(part(h), h->outer_parts, scal(h), h->opt.residual_scaling, st));
+        launch_finalize(part(h), h->outer_parts, scal(h), h->ascale, st));
     return hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st);
 }
 
@@ -927,11 +971,25 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
             if (!valid_prec((int)level_prec[i])) return fail(MG_ERR_PREC, "level_prec[%d] = %d is not a format", i, (int)level_prec[i]);
             prec[i] = (int)level_prec[i];
         }
+    int ascale = 0;
+    {
+        std::vector<int> ns(m);
+        std::vector<bool> resc(m, false);
+        for (int l = 0, nn = n; l < m; ++l, nn = (nn - 1) / 2) {
+            ns[l] = nn;
+            resc[l] = o.rescale_half && l >= 1 && half_prec(prec[l]);
+        }
+        if (!alpha_code(dim, ns, prec, resc, o.residual_scaling, &ascale))
+            return fail(MG_ERR_PREC, "an FP16 level entered by a rescaled restriction would exceed FP16's range "
+                        "(its correction bound %.0f > %.0f): store it in BF16, FP32 or FP64",
+                        correction_bound(dim, ns[1]), kHalfCorrectionBound);
+    }
     mg_ctx *h = new mg_ctx();
     h->dim = dim;
     h->n = n;
     h->nl = m;
     h->opt = o;
+    h->ascale = ascale;
     h->q1 = q1;
     if (q1) h->tail_on = h->fuse_on = h->fuse_sr_on = false;
     h->lv.resize(m);
@@ -1081,6 +1139,15 @@ mg_status_t mg_destroy(mg_handle h) {
     return MG_OK;
 }
 
+mg_status_t mg_alpha_shift(mg_handle h, int instance, int *shift) {
+    if (!h || !shift) return fail(MG_ERR_ARG, "null argument");
+    const int ni = h->batched ? (int)h->inst.size() : 1;
+    if (instance < 0 || instance >= ni) return fail(MG_ERR_ARG, "instance %d out of range 0..%d", instance, ni - 1);
+    const int code = h->batched ? h->inst[instance].ascale : h->ascale;
+    *shift = code - 1;
+    return MG_OK;
+}
+
 mg_status_t mg_levels(mg_handle h, int *nlevels) {
     if (!h || !nlevels) return fail(MG_ERR_ARG, "null argument");
     *nlevels = h->nl;
@@ -1204,7 +1271,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     const double hh = 1.0 / (double)(L.n + 1);
     const double inv_h2 = 1.0 / (hh * hh);
     const int D = h->dim;
-    const int scaling = h->opt.residual_scaling;
+    const int scaling = h->ascale;
     auto finish_stats = [&](int iters, double rel) {
         if (stats) {
             stats->iterations = iters;
@@ -1762,7 +1829,8 @@ void build_batched_plan(mg_ctx *h, char *base) {
         x.part_off = h->inst[i].part_off, x.inst = i;
         pend.push_back(stencil_pend(x, h->inst[i].osh, L.P, h->bprec[0], P_F64));
         fins.push_back(
-            BFin{part_base + 2 * (size_t)h->inst[i].part_off, batched_stencil_blocks(L.P, h->inst[i].osh), Sp(i)});
+            BFin{part_base + 2 * (size_t)h->inst[i].part_off, batched_stencil_blocks(L.P, h->inst[i].osh), Sp(i),
+                 h->inst[i].ascale});
     }
     flush(BK_OUTER, h->bprec[0], "ir_update", 0, pend, 32 + (double)prec_bytes(h->bprec[0]));
     {
@@ -1817,7 +1885,7 @@ hipError_t enq_batched_step(mg_ctx *h, hipStream_t st) {
         } else {
             RUN(h, st, L.name, 0, 0.0,
                 launch_batched_finalize(reinterpret_cast<const BFin *>(h->ws + h->off_fin), (int)h->inst.size(), act,
-                                        h->opt.residual_scaling, st));
+                                        st));
         }
     }
     return hipMemcpyAsync(h->host_scal_all, h->ws + h->off_scal_all, 4 * sizeof(double) * h->inst.size(),
@@ -1891,6 +1959,11 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
             }
             nn = (nn - 1) / 2;
         }
+        {
+            std::vector<int> ns(m), pr(m);
+            for (int l = 0; l < m; ++l) ns[l] = I.lv[l].n, pr[l] = I.lv[l].prec;
+            (void)alpha_code(3, ns, pr, std::vector<bool>(m, false), o.residual_scaling, &I.ascale);
+        }
         const size_t fin = align_up(I.lv[0].elems * sizeof(double), 256);
         I.off_R = off, off += fin;
         I.off_U = off, off += fin;
@@ -1925,7 +1998,6 @@ mg_status_t ir_solve_batched(mg_handle h, const double *const *b, double *const 
     for (int i = 0; i < ni; ++i)
         if (!b[i] || !u[i]) return fail(MG_ERR_ARG, "null pointer for instance %d", i);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int scaling = h->opt.residual_scaling;
     double *part_base = reinterpret_cast<double *>(h->ws + h->off_part);
     double *scal_all = reinterpret_cast<double *>(h->ws + h->off_scal_all);
     int *act_dev = reinterpret_cast<int *>(h->ws + h->off_active);
@@ -1954,7 +2026,7 @@ mg_status_t ir_solve_batched(mg_handle h, const double *const *b, double *const 
         double *part = part_base + 2 * (size_t)I.part_off;
         hipError_t e = launch_resid_flat(3, L.n, L.P, b[i], use_u ? (const double *)(h->ws + I.off_U) : nullptr,
                                          reinterpret_cast<double *>(h->ws + I.off_R), uout, 1.0 / (hh * hh), part, st);
-        if (e == hipSuccess) e = launch_finalize(part, flat_blocks(points(3, L.n)), scal_all + 4 * i, scaling, st);
+        if (e == hipSuccess) e = launch_finalize(part, flat_blocks(points(3, L.n)), scal_all + 4 * i, I.ascale, st);
         return e;
     };
     // ||b||_2 of every instance, and the initial residual
@@ -1964,7 +2036,7 @@ mg_status_t ir_solve_batched(mg_handle h, const double *const *b, double *const 
             HIPCHK(launch_resid_flat(3, I.n, I.lv[0].P, b[i], nullptr, nullptr, nullptr, 1.0,
                                      part_base + 2 * (size_t)I.part_off, st));
             HIPCHK(launch_finalize(part_base + 2 * (size_t)I.part_off, flat_blocks(points(3, I.n)), scal_all + 4 * i,
-                                   scaling, st));
+                                   I.ascale, st));
         } else {
             HIPCHK(resid(i, false, nullptr));
             HIPCHK(launch_fill_zero(h->ws + I.off_U, align_up(I.lv[0].elems * sizeof(double), 16), st));
@@ -2170,7 +2242,7 @@ hipError_t enq_multi_step(mg_ctx *h, hipStream_t st) {
     u.prec = L.prec, u.P = L.P, u.K = K, u.zc = L.osh.zc, u.cin = cbuf(h, 0, h->cur[0]), u.act = act;
     RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)), launch_m_update(u, Rbuf(h), Ubuf(h), sc, hh * hh, part(h), st));
     RUN(h, st, "norm_finalize", 0, 16.0 * h->m_upd_blocks * K,
-        launch_m_finalize(part(h), h->m_upd_blocks, K, sc, act, h->opt.residual_scaling, st));
+        launch_m_finalize(part(h), h->m_upd_blocks, K, sc, act, h->ascale, st));
     return hipMemcpyAsync(h->host_scal_m, sc, 4 * sizeof(double) * K, hipMemcpyDeviceToHost, st);
 }
 
@@ -2208,8 +2280,15 @@ mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_pr
         if (!m_supported(prec[l], nrhs))
             return fail(MG_ERR_ARG, "nrhs = %d is below the %d columns a thread of level %d handles", nrhs,
                         m_vec(prec[l]), l);
+    int ascale = 0;
+    {
+        std::vector<int> ns(m);
+        for (int l = 0, nn = n; l < m; ++l, nn = (nn - 1) / 2) ns[l] = nn;
+        (void)alpha_code(3, ns, prec, std::vector<bool>(m, false), o.residual_scaling, &ascale);
+    }
     mg_ctx *h = new mg_ctx();
     h->dim = 3, h->n = n, h->nl = m, h->opt = o, h->nrhs = nrhs;
+    h->ascale = ascale;
     h->lv.resize(m);
     const int K = nrhs;
     size_t off = 0;
@@ -2261,7 +2340,7 @@ mg_status_t ir_solve_multi(mg_handle h, const double *b, double *u, mg_stats_t *
     const int n = L.n, P = L.P;
     const double hh = 1.0 / (double)(n + 1);
     const double inv_h2 = 1.0 / (hh * hh);
-    const int scaling = h->opt.residual_scaling;
+    const int scaling = h->ascale;
     const int rparts = m_resid_blocks(n);
     double *sc = scal(h);
     const double *hs = h->host_scal_m;

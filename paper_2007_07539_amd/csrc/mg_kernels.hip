@@ -1318,7 +1318,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     }
     block_reduce(s, m, red);
     if (threadIdx.x == 0) {
-        double a = scaling ? m : 1.0;
+        double a = scaling ? ldexp(m, scaling - 1) : 1.0;
         if (!(a > 0.0) || a > 1.7e308) a = 1.0;
         scal[0] = a;
         scal[1] = 1.0 / a;
@@ -1902,7 +1902,7 @@ __global__ void k_batched_coarse(const BDesc *__restrict__ descs, int n, const i
 
 // One block per instance: reduce its partials into its scalars.
 __global__ __launch_bounds__(256) void k_batched_finalize(const BFin *__restrict__ fin,
-                                                          const int *__restrict__ active, int scaling) {
+                                                          const int *__restrict__ active) {
     __shared__ double red[8];
     if (!active[blockIdx.x]) return;
     const BFin f = fin[blockIdx.x];
@@ -1913,7 +1913,7 @@ __global__ __launch_bounds__(256) void k_batched_finalize(const BFin *__restrict
     }
     block_reduce(s, m, red);
     if (threadIdx.x == 0) {
-        double a = scaling ? m : 1.0;
+        double a = f.ascale ? ldexp(m, f.ascale - 1) : 1.0;
         if (!(a > 0.0) || a > 1.7e308) a = 1.0;
         f.scal[0] = a;
         f.scal[1] = 1.0 / a;
@@ -2177,8 +2177,8 @@ hipError_t launch_batched_restrict2(int V, int pf, int pc, bool xsh, const BDesc
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batched_finalize(const BFin *fin, int ninst, const int *active, int scaling, hipStream_t st) {
-    hipLaunchKernelGGL(k_batched_finalize, dim3(ninst), dim3(256), 0, st, fin, active, scaling);
+hipError_t launch_batched_finalize(const BFin *fin, int ninst, const int *active, hipStream_t st) {
+    hipLaunchKernelGGL(k_batched_finalize, dim3(ninst), dim3(256), 0, st, fin, active);
     return hipGetLastError();
 }
 

@@ -69,7 +69,8 @@ hipError_t launch_outer_update(int D, int prec, int P, const void *c, double *R,
 // partials per block.
 hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double *U, double *R,
                              double *uout, double inv_h2, double *part, hipStream_t st);
-// Reduce partials: scal = {alpha, 1/alpha, ||r||_2, ||r||_inf}.
+// Reduce partials: scal = {alpha, 1/alpha, ||r||_2, ||r||_inf}.  scaling 0:
+// alpha = 1; scaling 1 + j: alpha = 2^j ||r||_inf (also for launch_m_finalize).
 hipError_t launch_finalize(const double *part, int nparts, double *scal, int scaling, hipStream_t st);
 // Dense <-> padded copies with format conversion (round to nearest even).
 hipError_t launch_pack(int D, int src_prec, int dst_prec, int n, int P, const void *src, void *dst,
@@ -174,6 +175,7 @@ struct BFin {
     const double *part;
     int count;
     double *scal;
+    int ascale;  // 0: alpha = 1; 1 + j: alpha = 2^j ||r||_inf
 };
 enum { BK_SMOOTH2 = 0, BK_SMOOTH2_SCALED = 1, BK_SWEEP = 2, BK_PROLONG = 3, BK_OUTER = 4 };
 
@@ -189,7 +191,7 @@ hipError_t launch_batched_march(int kind, int V, int pf, int pc, const BDesc *d,
                                 hipStream_t st);
 hipError_t launch_batched_restrict2(int V, int pf, int pc, bool xsh, const BDesc *d, const BItem *items, int nitems,
                                     const int *active, int grid, int threads, size_t lds, hipStream_t st);
-hipError_t launch_batched_finalize(const BFin *fin, int ninst, const int *active, int scaling, hipStream_t st);
+hipError_t launch_batched_finalize(const BFin *fin, int ninst, const int *active, hipStream_t st);
 
 // ---- many right-hand sides, interleaved [z][y][x][k] -------------------------
 // Arguments of one interleaved stage launch (unused members may stay null).

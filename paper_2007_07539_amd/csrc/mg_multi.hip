@@ -722,7 +722,7 @@ __global__ __launch_bounds__(256) void k_mfinalize(const double *__restrict__ pa
     }
     block_reduce(s, m, red);
     if (threadIdx.x == 0) {
-        double a = scaling ? m : 1.0;
+        double a = scaling ? ldexp(m, scaling - 1) : 1.0;
         if (!(a > 0.0) || a > 1.7e308) a = 1.0;
         scal[k] = a;
         scal[K + k] = 1.0 / a;

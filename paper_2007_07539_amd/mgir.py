@@ -39,7 +39,7 @@ EXPORTS = ("mg_default_options", "mg_setup", "mg_workspace_size", "mg_bind_works
            "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_write", "mg_level_read", "mg_stage",
            "mg_levels", "mg_level_n", "mg_profile_step", "mg_set_shape", "mg_get_shape", "mg_bandwidth_probe",
            "mg_setup_batched", "ir_solve_batched", "mg_instances", "mg_setup_multi", "ir_solve_multi",
-           "mg_rhs_count")
+           "mg_rhs_count", "mg_alpha_shift")
 SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE, SHAPE_SMOOTH, SHAPE_SWEEP, SHAPE_PROLONG, SHAPE_TAIL, SHAPE_FUSE, \
     SHAPE_FUSE_SR = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
@@ -102,6 +102,7 @@ def load() -> ctypes.CDLL:
     lib.mg_setup_multi.argtypes = [ctypes.POINTER(H), i, i, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Options)]
     lib.ir_solve_multi.argtypes = [H, vp, vp, ctypes.POINTER(Stats), vp]
     lib.mg_rhs_count.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
+    lib.mg_alpha_shift.argtypes = [H, i, ctypes.POINTER(ctypes.c_int)]
     for f in EXPORTS:
         if f not in ("mg_default_options", "mg_status_string", "mg_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -196,6 +197,12 @@ class Solver:
         self.nlevels = nl.value
 
     # -- helpers ---------------------------------------------------------------
+    def alpha_shift(self, instance: int = 0) -> int:
+        """j of alpha = 2^j ||r||_inf (-1 with residual scaling off)."""
+        v = ctypes.c_int()
+        _check(self.lib.mg_alpha_shift(self._h, int(instance), ctypes.byref(v)), "mg_alpha_shift")
+        return v.value
+
     def level_n(self, level: int) -> int:
         v = ctypes.c_int()
         _check(self.lib.mg_level_n(self._h, level, ctypes.byref(v)), "mg_level_n")
