@@ -118,6 +118,76 @@ def bandwidth_ceiling(torch, mgir, reps=5):
     return out
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def solve_maps(torch, mgir, W, oracle, dev, dim, n, b, maps, steps, tune, defer=0):
+    """Time the solve of one problem under several precision maps (the FP64
+    map without residual scaling, the others with it) and check each result
+    with the oracle: its FP64 relative residual ||b - A u||_2 / ||b||_2, and
+    ||u - u_f64||_inf / ||u_f64||_inf against the FP64 map's solution."""
+    bt = torch.from_numpy(b).to(dev)
+    L = W.levels_for(n)
+    out, u64 = {}, None
+    nb = oracle.norm2(b)
+    for name in maps:
+        log(f"[bench] {dim}-D n={n} map {name}")
+        kw = dict(residual_scaling=name != "f64", autotune=tune and dim == 3, device=dev)
+        if name != "f64" and defer and dim == 3:
+            kw["defer_update"] = defer
+        s = mgir.Solver(dim, n, W.precision_map(name, L), **kw)
+        u = torch.zeros_like(bt)
+        ms, res = timed_solves(s, bt, u, steps, 1, torch)
+        r = res[-1]
+        uh = u.cpu().numpy()
+        e = {"ms": round(ms, 3), "dof_per_s": n**dim / (ms * 1e-3), "iterations": r.iterations,
+             "status": r.status, "rel_residual_gpu": r.rel_residual,
+             "rel_residual_oracle": oracle.norm2(oracle.residual(b, uh)) / nb,
+             "map": W.precision_map(name, L)}
+        if name == "f64":
+            u64 = uh
+        elif u64 is not None:
+            e["err_vs_f64"] = float(np.abs(uh - u64).max() / np.abs(u64).max())
+            e["speedup_vs_f64"] = out["f64"]["ms"] / ms
+        out[name] = e
+        del s, u, uh
+        torch.cuda.empty_cache()
+    del bt
+    return out, u64
+
+
+def config_sweep(torch, mgir, W, oracle, dev, steps, tune, defer, cfg3=None):
+    """The benchmark configurations other than the headline: the 2-D 255^2
+    sine in FP64 (against the closed-form discrete solution and the oracle's
+    own solve), 255^3 uniform noise FP64 vs FP16, and every precision map of
+    the 511^3 problem (cfg3: results already measured there, or None)."""
+    res = {}
+    n = 255
+    b = W.poisson2d_sine_rhs(n)
+    e, u64 = solve_maps(torch, mgir, W, oracle, dev, 2, n, b, ["f64"], steps, tune)
+    h = 1.0 / (n + 1)
+    amp = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2   # discrete solution of the eigenmode
+    uh = amp * W.sine_mode(2, n, (1, 1))
+    o = oracle.ir_solve(b, residual_scaling=False, recursive_residual=True)
+    e["f64"]["err_vs_discrete_closed_form"] = float(np.abs(u64 - uh).max() / np.abs(uh).max())
+    e["f64"]["err_vs_oracle_solve"] = float(np.abs(u64 - o.u).max() / np.abs(o.u).max())
+    e["f64"]["oracle_iterations"] = o.iterations
+    res["poisson2d_255_sine_f64"] = e
+    b = W.uniform_rhs(3, n, seed=2)
+    res["poisson3d_255_uniform"], _ = solve_maps(torch, mgir, W, oracle, dev, 3, n, b, ["f64", "f16"], steps, tune,
+                                                 defer)
+    if cfg3 is not None:
+        res["poisson3d_511_sine_noise"] = cfg3
+    return res
+
+
 def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=True):
     """Throughput of the batched and many-right-hand-side solves (FP16 V-cycles
     and the FP64 solve of the same problems), and the paper's other precision
@@ -314,6 +384,11 @@ def main():
                     help="only measure the streaming bandwidth ceilings (copy, read, write, update mix)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-instances and many-right-hand-sides measurements")
+    ap.add_argument("--defer", type=int, default=8,
+                    help="also time the mixed solve with the solution update postponed over this many steps "
+                         "(0: only the per-step update); the faster one is the headline")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other precision maps and workloads (2-D 255^2, 255^3, FP32/BF16/HSD at n)")
     ap.add_argument("--q1-profile-only", action="store_true",
                     help="only run Q1 finite-element solves at --n (3-D, --map levels) for rocprofv3")
     args = ap.parse_args()
@@ -355,23 +430,32 @@ def main():
     dev = torch.device("cuda:0")
     bt = torch.from_numpy(b).to(dev)
     u = torch.zeros_like(bt)
-
-    log("[bench] setup mixed solver")
     tune = not args.no_autotune
-    mixed = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=True, device=dev, autotune=tune)
-    shapes_mixed = {"smooth": mixed.get_shape(0, mgir.SHAPE_SMOOTH), "sweep": mixed.get_shape(0, mgir.SHAPE_SWEEP),
-                    "prolong": mixed.get_shape(0, mgir.SHAPE_PROLONG),
-                    "restrict": mixed.get_shape(0, mgir.SHAPE_RESTRICT),
-                    "update": mixed.get_shape(0, mgir.SHAPE_UPDATE),
-                    "fused_sweep_update": mixed.get_shape(0, mgir.SHAPE_FUSE),
-                    "fused_smooth_restrict": mixed.get_shape(0, mgir.SHAPE_FUSE_SR),
-                    "fused_coarse_end": mixed.get_shape(0, mgir.SHAPE_TAIL)}
-    ms_mixed, res_mixed = timed_solves(mixed, bt, u, args.steps, args.warmup, torch)
-    log(f"[bench] mixed: {ms_mixed:.2f} ms/solve, {res_mixed[-1].iterations} it, rel {res_mixed[-1].rel_residual:.2e}")
-    prof = mixed.profile_step()
-    kt = kernel_table(prof)
-    del mixed
-    torch.cuda.empty_cache()
+
+    def shapes_of(s):
+        return {"smooth": s.get_shape(0, mgir.SHAPE_SMOOTH), "sweep": s.get_shape(0, mgir.SHAPE_SWEEP),
+                "prolong": s.get_shape(0, mgir.SHAPE_PROLONG), "restrict": s.get_shape(0, mgir.SHAPE_RESTRICT),
+                "update": s.get_shape(0, mgir.SHAPE_UPDATE), "fused_sweep_update": s.get_shape(0, mgir.SHAPE_FUSE),
+                "fused_smooth_restrict": s.get_shape(0, mgir.SHAPE_FUSE_SR),
+                "fused_coarse_end": s.get_shape(0, mgir.SHAPE_TAIL)}
+
+    # the mixed solve: FP16 levels, FP64 refinement; with the solution update
+    # every step (Algorithm 2 as written) and postponed over --defer steps
+    mixed_runs = {}
+    for depth in ([0, args.defer] if args.defer else [0]):
+        log(f"[bench] setup mixed solver (defer_update={depth})")
+        s = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=True, device=dev, autotune=tune,
+                        defer_update=depth)
+        ms, res = timed_solves(s, bt, u, args.steps, args.warmup, torch)
+        log(f"[bench] mixed defer={depth}: {ms:.2f} ms/solve, {res[-1].iterations} it, "
+            f"rel {res[-1].rel_residual:.2e}")
+        mixed_runs[depth] = {"ms": ms, "res": res[-1], "shapes": shapes_of(s), "prof": s.profile_step(),
+                             "u": u.cpu().numpy() if not args.profile_only else None}
+        del s
+        torch.cuda.empty_cache()
+    best_depth = min(mixed_runs, key=lambda d: mixed_runs[d]["ms"])
+    mx = mixed_runs[best_depth]
+    ms_mixed, kt = mx["ms"], kernel_table(mx["prof"])
     if args.profile_only:
         # a plain 1 GiB device copy: the reference that scales hardware traffic
         # counters (FETCH_SIZE, WRITE_SIZE) of the solver kernels to bytes
@@ -382,21 +466,36 @@ def main():
         log("[bench] calibration copy: 1 GiB read + 1 GiB written by k_probe")
         del src, dst
 
-    fp64 = None
+    fp64_runs = {}
     if not args.profile_only:
-        log("[bench] setup FP64 solver")
-        fp64 = mgir.Solver(3, n, W.precision_map("f64", L), residual_scaling=False, device=dev, autotune=tune)
-        ms64, res64 = timed_solves(fp64, bt, u, args.steps, args.warmup, torch)
-        log(f"[bench] fp64: {ms64:.2f} ms/solve, {res64[-1].iterations} it, rel {res64[-1].rel_residual:.2e}")
-        kt64 = kernel_table(fp64.profile_step())
-        del fp64
-        torch.cuda.empty_cache()
+        # the FP64 baseline (no residual scaling, Section 6) in its fastest
+        # form: the autotuner keeps the fused finest-level kernels where they
+        # win; the unfused form is timed beside it for reference
+        for label in ("fused", "unfused"):
+            log(f"[bench] setup FP64 solver ({label})")
+            s = mgir.Solver(3, n, W.precision_map("f64", L), residual_scaling=False, device=dev, autotune=tune)
+            if label == "unfused":
+                s.set_shape(0, mgir.SHAPE_FUSE, [0])
+                s.set_shape(0, mgir.SHAPE_FUSE_SR, [0])
+            ms, res = timed_solves(s, bt, u, args.steps, args.warmup, torch)
+            log(f"[bench] fp64 {label}: {ms:.2f} ms/solve, {res[-1].iterations} it, rel {res[-1].rel_residual:.2e}")
+            fp64_runs[label] = {"ms": ms, "res": res[-1], "shapes": shapes_of(s), "prof": s.profile_step(),
+                                "u": u.cpu().numpy() if label == "fused" else None}
+            del s
+            torch.cuda.empty_cache()
+        best64 = min(fp64_runs, key=lambda k: fp64_runs[k]["ms"])
+        ms64 = fp64_runs[best64]["ms"]
 
     dofs_mixed = N / (ms_mixed * 1e-3)
     # dominant kernel: the finest-level kernel with the largest share of the step
     dom_name = max(kt, key=lambda k: kt[k]["ms"])
     dom = kt[dom_name]
     achieved = dom["bytes"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e9
+
+    def ktab(prof):
+        return {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1), "launches": v["launches"]}
+                for k, v in kernel_table(prof).items()}
+
     out = {
         "metric": "solved DoF/s to rel. residual 1e-10, mixed vs FP64 on GPU; achieved HBM GB/s",
         "value": dofs_mixed,
@@ -411,40 +510,87 @@ def main():
         "dtype": "f64 refinement + f16 V-cycle (f32 accumulate)" if args.map == "f16" else args.map,
         "data": "synthetic",
         "config": {"workload": f"poisson3d_{n}_sine_noise", "n": n, "levels": L, "map": args.map,
-                   "cycle": "V(2,2) damped Jacobi omega=0.8", "rtol": 1e-10},
-        "iterations_mixed": res_mixed[-1].iterations,
-        "rel_residual_mixed": res_mixed[-1].rel_residual,
+                   "cycle": "V(2,2) damped Jacobi omega=0.8", "rtol": 1e-10, "defer_update": best_depth},
+        "iterations_mixed": mx["res"].iterations,
+        "rel_residual_mixed": mx["res"].rel_residual,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom_name),
                      "avg_ms": dom["avg_ms"], "bytes_per_launch": dom["bytes"] / dom["launches"]},
-        "kernels_finest": {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1),
-                               "launches": v["launches"]} for k, v in kt.items()},
-        "launch_shapes_finest": shapes_mixed,
+        "kernels_finest": ktab(mx["prof"]),
+        "launch_shapes_finest": mx["shapes"],
+        "mixed_by_defer_update": {str(d): {"ms": r["ms"], "iterations": r["res"].iterations}
+                                  for d, r in mixed_runs.items()},
         "autotune": tune,
     }
     if not args.profile_only:
+        r64 = fp64_runs[best64]
         out["fp64_value"] = N / (ms64 * 1e-3)
         out["fp64_ms_per_step"] = ms64
-        out["iterations_fp64"] = res64[-1].iterations
+        out["fp64_form"] = best64
+        out["iterations_fp64"] = r64["res"].iterations
         out["speedup_mixed_vs_fp64"] = ms64 / ms_mixed
-        out["kernels_finest_fp64"] = {k: {"avg_ms": round(v["avg_ms"], 4), "GBps": round(v["GBps"], 1)}
-                                      for k, v in kt64.items()}
+        out["fp64_by_form"] = {k: {"ms": v["ms"], "iterations": v["res"].iterations,
+                                   "speedup_mixed_vs_this": v["ms"] / ms_mixed} for k, v in fp64_runs.items()}
+        out["kernels_finest_fp64"] = ktab(r64["prof"])
+        out["launch_shapes_finest_fp64"] = r64["shapes"]
+        import oracle
+        oracle.build()
+        # every result checked by the oracle's FP64 residual, and against the
+        # FP64 map's solution
+        u64 = fp64_runs["fused"]["u"]
+        nb = oracle.norm2(b)
+        cfg3 = {}
+        for name, runs in (("f64", fp64_runs["fused"]), (args.map, mx)):
+            e = {"ms": round(runs["ms"], 3), "dof_per_s": N / (runs["ms"] * 1e-3), "iterations": runs["res"].iterations,
+                 "status": runs["res"].status, "rel_residual_gpu": runs["res"].rel_residual,
+                 "rel_residual_oracle": oracle.norm2(oracle.residual(b, runs["u"])) / nb,
+                 "map": W.precision_map(name, L)}
+            if name != "f64":
+                e["err_vs_f64"] = float(np.abs(runs["u"] - u64).max() / np.abs(u64).max())
+                e["speedup_vs_f64"] = ms64 / runs["ms"]
+            cfg3[name] = e
+        out["rel_residual_oracle_mixed"] = cfg3[args.map]["rel_residual_oracle"]
+        out["err_vs_f64_mixed"] = cfg3[args.map]["err_vs_f64"]
+        for r in list(mixed_runs.values()) + list(fp64_runs.values()):
+            r["u"] = None
+        if not args.no_configs:
+            for name in ("f32", "bf16", "hsd"):
+                if name == args.map:
+                    continue
+                log(f"[bench] {n}^3 map {name}")
+                kw = {"defer_update": best_depth} if best_depth else {}
+                s = mgir.Solver(3, n, W.precision_map(name, L), device=dev, autotune=tune, **kw)
+                ms, res = timed_solves(s, bt, u, args.steps, 1, torch)
+                uh = u.cpu().numpy()
+                cfg3[name] = {"ms": round(ms, 3), "dof_per_s": N / (ms * 1e-3), "iterations": res[-1].iterations,
+                              "status": res[-1].status, "rel_residual_gpu": res[-1].rel_residual,
+                              "rel_residual_oracle": oracle.norm2(oracle.residual(b, uh)) / nb,
+                              "err_vs_f64": float(np.abs(uh - u64).max() / np.abs(u64).max()),
+                              "speedup_vs_f64": ms64 / ms, "map": W.precision_map(name, L)}
+                del s, uh
+                torch.cuda.empty_cache()
+            out["configs"] = config_sweep(torch, mgir, W, oracle, dev, args.steps, tune, best_depth, cfg3)
+        else:
+            out["configs"] = {"poisson3d_511_sine_noise": cfg3}
+        del u64
     if not args.no_extra and not args.profile_only:
         out["extra"] = extra_workloads(torch, mgir, W, dev, args.steps, bt=bt, n=n, ms64=ms64, tune=tune)
     if not args.no_cpu_baseline and not args.profile_only:
         import oracle
-        oracle.build()
+        oracle.build(native=True)
         k = args.cpu_iters
-        log(f"[bench] oracle: {k} FP64 IR iterations at n={n} on the host (1 thread)")
+        log(f"[bench] oracle: {k} FP64 IR iterations at n={n} on the host (1 thread, -O3 -march=native)")
         t0 = time.perf_counter()
-        o = oracle.ir_solve(b, residual_scaling=False, recursive_residual=True, max_iter=k)
+        o = oracle.ir_solve(b, residual_scaling=False, recursive_residual=True, max_iter=k, native=True)
         t = time.perf_counter() - t0
-        iters = res64[-1].iterations
+        iters = out["iterations_fp64"]
         out["cpu_baseline"] = {
             "value": N / (t / max(o.iterations, 1) * iters), "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{o.iterations} FP64 IR iterations of the serial C oracle on the same {n}^3 RHS "
-                      f"({t:.1f} s incl. the initial residual), extrapolated to the FP64 solve's {iters} iterations",
-            "host_cpus": os.cpu_count(),
+            "sample": f"extrapolated: {o.iterations} FP64 IR iterations of the serial C oracle (gcc -O3 "
+                      f"-march=native, one thread) on the same {n}^3 RHS took {t:.1f} s including the initial "
+                      f"residual; scaled to the FP64 solve's {iters} iterations (a whole solve is about "
+                      f"{t / max(o.iterations, 1) * iters:.0f} s)",
+            "host_cpu": host_cpu_model(), "host_cpus": os.cpu_count(),
         }
         log(f"[bench] oracle: {t:.1f} s")
     print(json.dumps(out), flush=True)

@@ -111,6 +111,20 @@ typedef struct {
                                 kernels (no fused forms, no launch-shape tuning:
                                 opt.autotune is ignored and mg_set_shape returns
                                 MG_ERR_STATE); single-grid handles only, as rescale_half. */
+    int defer_update;        /* 0 (default): ir_solve adds alpha c to u in every step, as
+                                Algorithm 2 writes it.  k in 1..64: the step that runs the
+                                fused last sweep + update (3-D finite differences,
+                                MG_SHAPE_FUSE in use) stores c in the finest level's
+                                format in a ring of k slots instead of reading and
+                                writing the FP64 u; when the ring is full, and before
+                                u is read (the recomputed residual, the return), one
+                                pass adds the stored alpha_j c_j to u in step order.
+                                u is bit for bit the same, since the same roundings
+                                happen in the same sequence; the refinement loop itself
+                                only needs r.  The workspace grows by k finest-level
+                                vectors of that format.  Pays where the format is
+                                narrower than FP64 (FP16: 2 instead of 16 bytes per
+                                point and step).  Single-grid handles only. */
 } mg_options_t;
 
 typedef struct {
@@ -349,9 +363,11 @@ typedef enum {
                                ty]}.  When on (the default; the autotuner keeps it
                                only where it is faster), the last post-smoothing
                                sweep of the finest level and the refinement update
-                               run as one kernel inside ir_solve (same result).  Not
-                               used when the finest level is FP64 without residual
-                               scaling (its right-hand side is r itself) or nu2 < 2.
+                               run as one kernel inside ir_solve (same result).  With
+                               an FP64 finest level and no residual scaling, whose
+                               right-hand side is r itself, the kernel writes the new
+                               residual to a second array of the workspace and the
+                               two swap roles every step.  Not used when nu2 < 2.
                                Reading returns whether it is in use and its shape. */
     MG_SHAPE_FUSE_SR = 8    /* 3-D, level l below the base: {on (0|1)[, tyc, zcc]}.  When
                                on, the level's first pre-smoothing (two sweeps from zero)
@@ -360,9 +376,11 @@ typedef enum {
                                ir_solve, from the scaled residual (on by default).  Level
                                l >= 1: that level, from its stored right-hand side (off by
                                default).  The autotuner keeps it only where it is faster.
-                               Needs nu1 = 2, an FP32/FP16/BF16 level, P/8 dividing 64,
-                               and (level 0) residual scaling; not used into a rescaled
-                               level.  Reading returns whether it is in use and its
+                               Needs nu1 = 2 and P/8 dividing 64 (an FP64 level: one
+                               coarse row per tile at P = 512); level 0 reads the
+                               scaled residual, or with an FP64 finest level and no
+                               residual scaling the residual itself; not used into a
+                               rescaled level.  Reading returns whether it is in use and its
                                shape. */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);

@@ -22,6 +22,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mg_ref.c")
 _LIB = os.path.join(_HERE, "libmgref.so")
+# the same source built for speed on the host that runs it (timing only)
+_LIB_NATIVE = os.path.join(_HERE, "libmgref_native.so")
 
 OK, ERR_ARG, ERR_SHAPE, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_NOMEM = 0, -1, -2, -6, -7, -9
 
@@ -36,13 +38,18 @@ def _disc(d) -> int:
     return DISCS[d]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (serial, -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile the oracle with gcc (serial, no fast-math): -O2 for the tests,
+    or with native=True -O3 -march=native into a second library, the copy the
+    CPU baseline times (same source, same arithmetic: no contraction of
+    products and sums into fused multiply-adds)."""
+    lib = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp"
+        flags = ["-O3", "-march=native", "-ffp-contract=off"] if native else ["-O2"]
+        subprocess.check_call(["gcc"] + flags + ["-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _IrOpts(ctypes.Structure):
@@ -60,13 +67,12 @@ class _IrResult(ctypes.Structure):
                 ("true_rel_residual", ctypes.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        lib = ctypes.CDLL(build())
+def _load(native: bool = False):
+    if native not in _libs:
+        lib = ctypes.CDLL(build(native=native))
         dp = ctypes.POINTER(ctypes.c_double)
         i = ctypes.c_int
         lib.ref_points.argtypes, lib.ref_points.restype = [i, i], ctypes.c_long
@@ -88,8 +94,8 @@ def _load():
         lib.ref_ir_solve.restype = i
         for f in ("ref_apply_A_disc", "ref_residual_disc", "ref_jacobi_disc", "ref_restrict_disc", "ref_prolong"):
             getattr(lib, f).restype = None
-        _lib = lib
-    return _lib
+        _libs[native] = lib
+    return _libs[native]
 
 
 def _ptr(a: np.ndarray):
@@ -224,11 +230,12 @@ class IrResult:
 
 def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
              recursive_residual=False, max_iter=100, rtol=1e-10, cycles=1, base_n=1, base_tol=1e-4,
-             base_max_iter=None, disc="fd") -> IrResult:
+             base_max_iter=None, disc="fd", native=False) -> IrResult:
     """Iterative refinement with residuum scaling and one V-cycle per step
     (Algorithm 2), all in FP64.  Stops when ||r||_2 <= rtol ||b||_2.  With
     cycles > 1 each step applies that many V-cycles to the scaled residual
-    equation, each continuing from the correction so far."""
+    equation, each continuing from the correction so far.  native=True runs
+    the -O3 -march=native build of the same source (for timing)."""
     b = _f64(b)
     dim, n = _shape(b)
     u = np.zeros_like(b) if u0 is None else _f64(u0).copy()
@@ -239,7 +246,7 @@ def ir_solve(b, u0=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
                    _disc(disc))
     res = _IrResult()
     hist = np.zeros(max_iter + 2)
-    st = _load().ref_ir_solve(dim, n, _ptr(b), _ptr(u), ctypes.byref(opts), ctypes.byref(res),
-                              _ptr(hist), hist.size)
+    st = _load(native).ref_ir_solve(dim, n, _ptr(b), _ptr(u), ctypes.byref(opts), ctypes.byref(res),
+                                    _ptr(hist), hist.size)
     k = res.iterations
     return IrResult(st, u, k, res.rel_residual, res.true_rel_residual, hist[: k + 1].copy())

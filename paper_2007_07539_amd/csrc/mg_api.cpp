@@ -87,6 +87,16 @@ struct mg_ctx {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph2 = nullptr;      // single grid: the update part of a step
     hipGraphExec_t gexec2 = nullptr;
+    // single grid whose update swaps the residual arrays (see swaps_r): the
+    // two graphs of a step that starts from the second array
+    hipGraph_t graph_p1 = nullptr, graph2_p1 = nullptr;
+    hipGraphExec_t gexec_p1 = nullptr, gexec2_p1 = nullptr;
+    size_t off_R2 = 0;  // the second residual array (0: none)
+    int rpar = 0;       // 1: the current residual is in the second array
+    // postponed solution updates (opt.defer_update)
+    int defer = 0;      // ring depth in use; 0: u is updated every step
+    size_t off_cdef = 0, cdef_stride = 0, off_adef = 0, off_dctr = 0;
+    int pending = 0;    // corrections in the ring not yet added to u
     hipEvent_t ev_norm = nullptr;     // single grid: the norm readback of a step is done
     int outer_parts = 0;
     bool tail_on = true;
@@ -143,7 +153,10 @@ template <class T> T *at_ws(mg_ctx *h, size_t off) { return reinterpret_cast<T *
 
 void *cbuf(mg_ctx *h, int l, int which) { return h->ws + h->lv[l].off_c[which]; }
 void *bbuf(mg_ctx *h, int l) { return h->ws + h->lv[l].off_b; }
-double *Rbuf(mg_ctx *h) { return at_ws<double>(h, h->off_R); }
+// The current residual, and (FP64 map without scaling, fused update) the
+// array the next update writes.
+double *Rbuf(mg_ctx *h) { return at_ws<double>(h, h->rpar ? h->off_R2 : h->off_R); }
+double *Rnext(mg_ctx *h) { return at_ws<double>(h, h->rpar ? h->off_R : h->off_R2); }
 double *Ubuf(mg_ctx *h) { return at_ws<double>(h, h->off_U); }
 double *part(mg_ctx *h) { return at_ws<double>(h, h->off_part); }
 double *scal(mg_ctx *h) { return at_ws<double>(h, h->off_scal); }
@@ -156,6 +169,8 @@ bool half_prec(int prec) { return prec == P_F16 || prec == P_BF16; }
 long points(int D, int n) { return D == 3 ? (long)n * n * n : (long)n * n; }
 // Largest base level the one-workgroup CG solves (64^3 points).
 constexpr long kMaxBasePoints = 262144;
+// Deepest ring of postponed solution updates.
+constexpr int kMaxDefer = 64;
 
 bool valid_prec(int p) { return p >= 0 && p <= 3; }
 
@@ -470,6 +485,15 @@ hipError_t enq_vcycle_down(mg_ctx *h, hipStream_t st, RhsMode mode, int l, const
         h->cur[0] = 0;
         return hipSuccess;
     }
+    if (l == 0 && mode == RHS_ALIAS_R && h->fused_sr) {
+        LevelPlan &L = h->lv[0], &C = h->lv[1];
+        const double N = (double)points(h->dim, L.n);
+        RUN(h, st, "smooth_restrict", 0, N * 16 + (double)points(h->dim, C.n) * sb(C.prec),
+            launch_smooth_restrict_b(P_F64, C.prec, L.P, Rbuf(h), cbuf(h, 0, 0), bbuf(h, 1), h->opt.omega, h->srsh,
+                                     st));
+        h->cur[0] = 0;
+        return hipSuccess;
+    }
     if (l == 0 && mode == RHS_ALIAS_R) {
         // FP64 baseline without scaling: the residual is the right-hand side
         LevelPlan &L = h->lv[0];
@@ -547,20 +571,50 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode, bool warm = false
 
 bool finest_alias(mg_ctx *h) { return h->lv[0].prec == P_F64 && !h->opt.residual_scaling; }
 
-// The fused last sweep + update needs the scaled right-hand side stored apart
-// from r (with the FP64 map and no scaling, r itself is the right-hand side
-// and the update overwrites it) and at least two post-sweeps.
+// The fused last sweep + update needs at least two post-sweeps.  With the
+// FP64 map and no scaling, r itself is the right-hand side, which a block reads
+// on rows its neighbours update: the new residual then goes to a second array
+// (swaps_r).
 bool fusion_possible(mg_ctx *h) {
     return h->fuse_on && !h->batched && !h->nrhs && h->dim == 3 && h->nl >= 2 && h->opt.nu2 >= 2 &&
-           !finest_alias(h) && sweep_update_ok(h->lv[0].P, h->lv[0].prec, h->fsh);
+           (!finest_alias(h) || h->off_R2) && sweep_update_ok(h->lv[0].P, h->lv[0].prec, h->fsh);
+}
+
+// Whether a refinement step writes its residual to the other array.
+bool swaps_r(const mg_ctx *h) { return h->fused && h->lv[0].prec == P_F64 && !h->opt.residual_scaling; }
+
+// Whether the step postpones the solution update (fused update only).
+bool defers(const mg_ctx *h) { return h->defer > 0 && h->fused; }
+
+// Arguments of the fused sweep + update for the current state.
+SweepUpdateArgs su_args(mg_ctx *h, const void *c) {
+    const LevelPlan &L = h->lv[0];
+    const double hh = 1.0 / (double)(L.n + 1);
+    SweepUpdateArgs a;
+    a.c = c;
+    a.b = finest_alias(h) ? (const void *)Rbuf(h) : bbuf(h, 0);
+    a.R = Rbuf(h);
+    a.Rout = finest_alias(h) ? Rnext(h) : Rbuf(h);
+    a.U = Ubuf(h);
+    if (defers(h)) {
+        a.cdefer = h->ws + h->off_cdef;
+        a.ctr = at_ws<int>(h, h->off_dctr);
+        a.cstride = h->cdef_stride;
+        a.adef = at_ws<double>(h, h->off_adef);
+    }
+    a.scal = scal(h);
+    a.h2 = hh * hh;
+    a.omega = h->opt.omega;
+    a.part = part(h);
+    return a;
 }
 
 // The fused first smoothing + restriction replaces exactly two pre-sweeps
-// of the scaled residual and the restriction of their result.
+// of the scaled residual (or, for the FP64 map without scaling, of the
+// residual itself) and the restriction of their result.
 bool fusion_sr_possible(mg_ctx *h) {
     return h->fuse_sr_on && !h->batched && !h->nrhs && h->dim == 3 && h->nl >= 2 && h->opt.nu1 == 2 &&
-           !h->lv[1].rescale &&
-           !finest_alias(h) && smooth_restrict_ok(h->lv[0].P, h->lv[0].prec, h->srsh);
+           !h->lv[1].rescale && smooth_restrict_ok(h->lv[0].P, h->lv[0].prec, h->srsh);
 }
 
 void set_fused_sr(mg_ctx *h, bool on) { h->fused_sr = on && fusion_sr_possible(h); }
@@ -605,7 +659,7 @@ hipError_t enq_cycle(mg_ctx *h, hipStream_t st) {
     const int m = std::max(1, h->opt.cycles_per_step);
     for (int j = 0; j < m; ++j) {
         const RhsMode mode = alias ? RHS_ALIAS_R : j == 0 ? RHS_SCALED_R : RHS_B;
-        const hipError_t e = enq_vcycle(h, st, mode, j > 0, j == m - 1 && !alias && h->fused);
+        const hipError_t e = enq_vcycle(h, st, mode, j > 0, j == m - 1 && h->fused);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -618,9 +672,13 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
     const double hh = 1.0 / (double)(L.n + 1);
     const double N = (double)points(h->dim, L.n);
     if (h->fused) {
-        RUN(h, st, "sweep_update", 0, N * (32 + 2 * sb(L.prec)),
-            launch_sweep_update(L.prec, L.P, cbuf(h, 0, h->cur[0]), bbuf(h, 0), Rbuf(h), Ubuf(h), scal(h), hh * hh,
-                                h->opt.omega, part(h), h->fsh, st));
+        // bytes: c, b, r read, r written, u read and written; with the
+        // residual as right-hand side r is not read apart from b; a postponed
+        // update writes c' instead of reading and writing u
+        const double s = sb(L.prec);
+        const double by = (finest_alias(h) ? s + 8 : 2 * s + 16) + (defers(h) ? s : 16);
+        RUN(h, st, defers(h) ? "sweep_update_defer" : "sweep_update", 0, N * by,
+            launch_sweep_update(L.prec, L.P, su_args(h, cbuf(h, 0, h->cur[0])), h->fsh, st));
     } else if (h->q1) {
         // U += alpha h^(2-D) c, R -= alpha S c
         RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
@@ -632,8 +690,33 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
                                 part(h), L.osh, st));
     }
     RUN(h, st, "norm_finalize", 0, 16.0 * h->outer_parts,
-        launch_finalize(part(h), h->outer_parts, scal(h), h->ascale, st));
+        launch_finalize(part(h), h->outer_parts, scal(h), h->ascale, st,
+                        defers(h) ? at_ws<int>(h, h->off_dctr) : nullptr));
     return hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+}
+
+// Add the postponed corrections to u (their slots in order) and empty the
+// ring; nothing to do without postponed corrections.
+hipError_t enq_flush(mg_ctx *h, hipStream_t st) {
+    if (h->pending == 0) return hipSuccess;
+    const LevelPlan &L = h->lv[0];
+    const double hh = 1.0 / (double)(L.n + 1);
+    const int k = h->pending;
+    h->pending = 0;
+    RUN(h, st, "defer_flush", 0, (double)points(h->dim, L.n) * (16 + k * sb(L.prec)),
+        launch_defer_flush(L.prec, h->ws + h->off_cdef, h->cdef_stride, at_ws<double>(h, h->off_adef), k, hh * hh,
+                           Ubuf(h), L.elems, at_ws<int>(h, h->off_dctr), st));
+    return hipSuccess;
+}
+
+// Host bookkeeping after a step's update has been queued: the residual array
+// it wrote becomes current, and its correction waits in the ring (which is
+// flushed when full).
+hipError_t after_update(mg_ctx *h, hipStream_t st) {
+    if (swaps_r(h)) h->rpar ^= 1;
+    if (!defers(h)) return hipSuccess;
+    ++h->pending;
+    return h->pending >= h->defer ? enq_flush(h, st) : hipSuccess;
 }
 
 // One refinement step of Algorithm 2 (scale and cast, V-cycle, update) plus
@@ -644,34 +727,54 @@ hipError_t enq_step(mg_ctx *h, hipStream_t st) {
 }
 
 void drop_graph(mg_ctx *h) {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
-    if (h->gexec2) (void)hipGraphExecDestroy(h->gexec2);
-    if (h->graph2) (void)hipGraphDestroy(h->graph2);
-    h->gexec = h->gexec2 = nullptr;
-    h->graph = h->graph2 = nullptr;
+    for (hipGraphExec_t *x : {&h->gexec, &h->gexec2, &h->gexec_p1, &h->gexec2_p1}) {
+        if (*x) (void)hipGraphExecDestroy(*x);
+        *x = nullptr;
+    }
+    for (hipGraph_t *g : {&h->graph, &h->graph2, &h->graph_p1, &h->graph2_p1}) {
+        if (*g) (void)hipGraphDestroy(*g);
+        *g = nullptr;
+    }
 }
 
 // Capture the cycle part and the update part of a refinement step as two
 // graphs, so that the next cycle can be queued before the host has read the
-// current step's norm.
+// current step's norm.  When steps swap the residual arrays, a second pair is
+// captured for steps that start from the second array.
 mg_status_t ensure_graph(mg_ctx *h) {
-    if (h->gexec && h->gexec2) return MG_OK;
+    const bool two = swaps_r(h);
+    if (h->gexec && h->gexec2 && (!two || (h->gexec_p1 && h->gexec2_p1))) return MG_OK;
     drop_graph(h);
     if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    for (int part = 0; part < 2; ++part) {
-        HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = part == 0 ? enq_cycle(h, h->cap_stream) : enq_update(h, h->cap_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
-        if (e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(MG_ERR_HIP, "capture of the refinement step failed: %s", hipGetErrorString(e));
+    const int keep = h->rpar;
+    for (int par = 0; par < (two ? 2 : 1); ++par) {
+        h->rpar = par;
+        for (int part = 0; part < 2; ++part) {
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = part == 0 ? enq_cycle(h, h->cap_stream) : enq_update(h, h->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                h->rpar = keep;
+                return fail(MG_ERR_HIP, "capture of the refinement step failed: %s", hipGetErrorString(e));
+            }
+            if (e2 != hipSuccess) {
+                h->rpar = keep;
+                return fail(MG_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+            }
+            hipGraph_t &gs = par == 0 ? (part == 0 ? h->graph : h->graph2) : (part == 0 ? h->graph_p1 : h->graph2_p1);
+            hipGraphExec_t &gx =
+                par == 0 ? (part == 0 ? h->gexec : h->gexec2) : (part == 0 ? h->gexec_p1 : h->gexec2_p1);
+            gs = g;
+            const hipError_t e3 = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+            if (e3 != hipSuccess) {
+                h->rpar = keep;
+                return fail(MG_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+            }
         }
-        if (e2 != hipSuccess) return fail(MG_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
-        (part == 0 ? h->graph : h->graph2) = g;
-        HIPCHK(hipGraphInstantiate(part == 0 ? &h->gexec : &h->gexec2, g, nullptr, nullptr, 0));
     }
+    h->rpar = keep;
     return MG_OK;
 }
 
@@ -828,6 +931,9 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                     const RShape r{8, tyc, zcc, 3};
                     if (!smooth_restrict_ok(L.P, L.prec, r)) continue;
                     const float t = time_ms(st, [&]() {
+                        if (l == 0 && finest_alias(h))
+                            return launch_smooth_restrict_b(L.prec, h->lv[1].prec, L.P, Rbuf(h), cbuf(h, 0, 0),
+                                                            bbuf(h, 1), h->opt.omega, r, st);
                         if (l == 0)
                             return launch_smooth_restrict(L.prec, h->lv[1].prec, L.P, Rbuf(h), scal(h), bbuf(h, 0),
                                                           cbuf(h, 0, 0), bbuf(h, 1), h->opt.omega, r, st);
@@ -868,10 +974,11 @@ mg_status_t autotune(mg_ctx *h, hipStream_t st) {
                     for (int zc : {4, 8, 16, 32, 64}) {
                         const Shape s{4, zc, 256, 1, ty};
                         if (!sweep_update_ok(L.P, L.prec, s)) continue;
-                        const float t = time_ms(st, [&]() {
-                            return launch_sweep_update(L.prec, L.P, cbuf(h, 0, 0), bbuf(h, 0), Rbuf(h), Ubuf(h),
-                                                       scal(h), hh * hh, h->opt.omega, part(h), s, st);
-                        }, 3);
+                        const bool was = h->fused;
+                        h->fused = true;  // the arguments of the form the step would use
+                        const SweepUpdateArgs q = su_args(h, cbuf(h, 0, 0));
+                        h->fused = was;
+                        const float t = time_ms(st, [&]() { return launch_sweep_update(L.prec, L.P, q, s, st); }, 3);
                         if (t < bf) bf = t, bsu = s;
                     }
                 h->fsh = bsu;
@@ -906,6 +1013,7 @@ void mg_default_options(mg_options_t *o) {
     o->base_tol = 1e-4;
     o->base_max_iter = 0;
     o->discretization = MG_DISC_FD;
+    o->defer_update = 0;
 }
 
 const char *mg_status_string(mg_status_t s) {
@@ -965,6 +1073,8 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     if (!(o.rtol >= 0.0)) return fail(MG_ERR_ARG, "rtol must be >= 0");
     if (o.cycles_per_step < 1 || o.cycles_per_step > 16)
         return fail(MG_ERR_ARG, "cycles_per_step must be in 1..16 (got %d)", o.cycles_per_step);
+    if (o.defer_update < 0 || o.defer_update > kMaxDefer)
+        return fail(MG_ERR_ARG, "defer_update must be in 0..%d (got %d)", kMaxDefer, o.defer_update);
     std::vector<int> prec(m, P_F64);
     if (level_prec)
         for (int i = 0; i < m; ++i) {
@@ -1034,6 +1144,25 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     off += fin;
     h->off_U = off;
     off += fin;
+    // the forms of the fused finest-level update (3-D finite differences)
+    const bool fusable = dim == 3 && !q1 && m >= 2;
+    if (fusable && prec[0] == P_F64 && !o.residual_scaling) {
+        // the residual is the right-hand side: the fused update writes the
+        // new residual to a second array
+        h->off_R2 = off;
+        off += fin;
+    }
+    if (fusable && o.defer_update > 0) {
+        const LevelPlan &L = h->lv[0];
+        h->defer = o.defer_update;
+        h->cdef_stride = align_up(L.elems * prec_bytes(L.prec), 256) / prec_bytes(L.prec);
+        h->off_cdef = off;
+        off += (size_t)h->defer * h->cdef_stride * prec_bytes(L.prec);
+        h->off_adef = off;
+        off += align_up((size_t)h->defer * sizeof(double), 256);
+        h->off_dctr = off;
+        off += 256;
+    }
     if (m > 1) {
         h->outer_parts = stencil_blocks(dim, h->lv[0].P, h->lv[0].osh);
         // room for the partials of any legal shape: V = 4, zc = 1, 64-thread
@@ -1042,7 +1171,11 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         const long worst = ((long)(P0 / 4) * (dim == 3 ? P0 : 1) * (P0 - 1) + 63) / 64;
         const long worst_fused = (long)(P0 - 1) * (P0 - 1);
         maxp = (int)std::max<long>(std::max<long>(h->outer_parts, worst), worst_fused);
-        h->fsh = Shape{4, std::max(1, std::min(16, P0 - 1)), 256, 1, std::max(1, std::min(4, P0 - 1))};
+        // the most rows per block the fused update allows (fewer for FP64 rows)
+        for (int ty = std::max(1, std::min(4, P0 - 1)); ty >= 1; --ty) {
+            h->fsh = Shape{4, std::max(1, std::min(16, P0 - 1)), 256, 1, ty};
+            if (sweep_update_ok(P0, prec[0], h->fsh)) break;
+        }
     }
     maxp = std::max(maxp, flat_blocks(points(dim, n)));
     h->max_parts = maxp;
@@ -1065,6 +1198,8 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     }
     h->ws_need = off;
     if (m > 1) {
+        // the fused update's FP64 rows need more than 64 KB of LDS at P = 512
+        if (h->dim == 3 && sweep_update_prepare() != hipSuccess) h->fuse_on = false;
         set_fused(h, true);
         // the fused first smoothing + restriction needs more than 64 KB of LDS
         // for its larger tiles; without that permission it stays off
@@ -1284,6 +1419,9 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     };
 
     // ||b||_2 first (and the initial residual when u starts at zero)
+    h->rpar = 0;
+    h->pending = 0;
+    if (h->defer) HIPCHK(launch_fill_zero(h->ws + h->off_dctr, 16, st));
     if (h->opt.use_initial_guess) {
         HIPCHK(finest_resid(h, b, nullptr, nullptr, nullptr, st));
     } else {
@@ -1326,7 +1464,10 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     mg_status_t result = MG_OK;
     double rel = h->host_scal[2] / nb;
     auto launch = [&](bool cycle) -> hipError_t {
-        if (graph) return hipGraphLaunch(cycle ? h->gexec : h->gexec2, st);
+        if (graph) {
+            if (h->rpar) return hipGraphLaunch(cycle ? h->gexec_p1 : h->gexec2_p1, st);
+            return hipGraphLaunch(cycle ? h->gexec : h->gexec2, st);
+        }
         return cycle ? enq_cycle(h, st) : enq_update(h, st);
     };
     for (;;) {
@@ -1342,6 +1483,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
             // confirm with the residual recomputed from u (a queued V-cycle
             // only wrote level vectors and is discarded)
             cycle_queued = false;
+            HIPCHK(enq_flush(h, st));
             HIPCHK(finest_resid(h, b, Ubuf(h), Rbuf(h), u, st));
             HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
             HIPCHK(hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1364,6 +1506,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
         if (!cycle_queued) e = launch(true);
         if (e == hipSuccess) e = launch(false);
         if (e == hipSuccess) e = hipEventRecord(h->ev_norm, st);
+        if (e == hipSuccess) e = after_update(h, st);
         // Queue the next step's V-cycle before reading this step's norm when
         // the residual is unlikely to reach the tolerance in this step (the
         // prediction uses the last contraction factor; a wrong guess costs
@@ -1384,6 +1527,7 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     }
     if (cycle_queued) HIPCHK(hipStreamSynchronize(st));
     // final: recompute the true residual and copy u out
+    HIPCHK(enq_flush(h, st));
     HIPCHK(finest_resid(h, b, Ubuf(h), Rbuf(h), u, st));
     HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
     HIPCHK(hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1546,6 +1690,12 @@ mg_status_t mg_profile_step(mg_handle h, void *stream, int cap, int *count, cons
         HIPCHK(hipStreamSynchronize(st));
     }
     hipError_t e = h->batched ? enq_batched_step(h, st) : h->nrhs ? enq_multi_step(h, st) : enq_step(h, st);
+    if (e == hipSuccess && !h->batched && !h->nrhs) {
+        // a postponed update is added to u at once, so that the step leaves
+        // the state a real one would after its flush (timed as defer_flush)
+        e = after_update(h, st);
+        if (e == hipSuccess) e = enq_flush(h, st);
+    }
     h->prof = false;
     hipError_t e2 = hipStreamSynchronize(st);
     int i = 0;
@@ -1905,6 +2055,7 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
     mg_default_options(&o);
     if (opt) o = *opt;
     if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
+    if (o.defer_update) return fail(MG_ERR_ARG, "defer_update is only available on single-grid handles");
     if (o.discretization != MG_DISC_FD)
         return fail(MG_ERR_ARG, "the Q1 discretisation is only available on single-grid handles");
     if (o.cycles_per_step != 1)
@@ -2261,6 +2412,7 @@ mg_status_t mg_setup_multi(mg_handle *out, int dim, int n, int nrhs, const mg_pr
     mg_default_options(&o);
     if (opt) o = *opt;
     if (o.rescale_half) return fail(MG_ERR_ARG, "rescale_half is only available on single-grid handles");
+    if (o.defer_update) return fail(MG_ERR_ARG, "defer_update is only available on single-grid handles");
     if (o.discretization != MG_DISC_FD)
         return fail(MG_ERR_ARG, "the Q1 discretisation is only available on single-grid handles");
     if (o.cycles_per_step != 1)

@@ -1309,7 +1309,7 @@ __global__ __launch_bounds__(256) void k_resid_rows(const double *__restrict__ b
 }
 
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ part, int nparts, double *__restrict__ scal,
-                                                  int scaling) {
+                                                  int scaling, int *__restrict__ ctr) {
     __shared__ double red[8];
     double s = 0.0, m = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
@@ -1324,7 +1324,29 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
         scal[1] = 1.0 / a;
         scal[2] = sqrt(s);
         scal[3] = m;
+        if (ctr) *ctr += 1;
     }
+}
+
+// u += a_j h^2 c_j over the postponed corrections in order; one thread per
+// eight consecutive elements (the padded arrays have a multiple of 8).
+template <class T>
+__global__ __launch_bounds__(256) void k_defer_flush(const T *__restrict__ cd, size_t cstride,
+                                                     const double *__restrict__ adef, int count, double h2,
+                                                     double *__restrict__ U, size_t n8, int *__restrict__ ctr) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += (size_t)gridDim.x * blockDim.x) {
+        double u[8];
+        load_row<double, 8>(U + 8 * i, u);
+        for (int j = 0; j < count; ++j) {
+            const double ah2 = adef[j] * h2;
+            double cv[8];
+            load_row<T, 8>(cd + (size_t)j * cstride + 8 * i, cv);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) u[e] = fmaT<double>(ah2, cv[e], u[e]);
+        }
+        store_row<double, 8>(U + 8 * i, u);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr = 0;
 }
 
 template <int D, class TS, class TD>
@@ -1753,8 +1775,27 @@ hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *part, int nparts, double *scal, int scaling, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, part, nparts, scal, scaling);
+hipError_t launch_defer_flush(int prec, const void *cdefer, size_t cstride, const double *adef, int count, double h2,
+                              double *U, size_t elems, int *ctr, hipStream_t st) {
+    if (elems % 8 || count < 0) return hipErrorInvalidValue;
+    const size_t n8 = elems / 8;
+    const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>((n8 + 255) / 256, 8192));
+#define MG_FL(T) \
+    hipLaunchKernelGGL(k_defer_flush<T>, dim3(blocks), dim3(256), 0, st, static_cast<const T *>(cdefer), cstride, adef, \
+                       count, h2, U, n8, ctr)
+    switch (prec) {
+    case P_F64: MG_FL(double); break;
+    case P_F32: MG_FL(float); break;
+    case P_F16: MG_FL(f16); break;
+    case P_BF16: MG_FL(bf16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MG_FL
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *part, int nparts, double *scal, int scaling, hipStream_t st, int *ctr) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, part, nparts, scal, scaling, ctr);
     return hipGetLastError();
 }
 

@@ -71,7 +71,9 @@ hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double 
                              double *uout, double inv_h2, double *part, hipStream_t st);
 // Reduce partials: scal = {alpha, 1/alpha, ||r||_2, ||r||_inf}.  scaling 0:
 // alpha = 1; scaling 1 + j: alpha = 2^j ||r||_inf (also for launch_m_finalize).
-hipError_t launch_finalize(const double *part, int nparts, double *scal, int scaling, hipStream_t st);
+// A non-null ctr is incremented (the slot counter of postponed updates).
+hipError_t launch_finalize(const double *part, int nparts, double *scal, int scaling, hipStream_t st,
+                           int *ctr = nullptr);
 // Dense <-> padded copies with format conversion (round to nearest even).
 hipError_t launch_pack(int D, int src_prec, int dst_prec, int n, int P, const void *src, void *dst,
                        hipStream_t st);
@@ -84,21 +86,43 @@ hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int 
 
 // Last post-smoothing sweep of the finest 3-D level fused with the refinement
 // update (LDS-plane kernel; s.ty rows per block, s.V values per thread).
+struct SweepUpdateArgs {
+    const void *c = nullptr;    // correction before the sweep (level format)
+    const void *b = nullptr;    // right-hand side (level format); == R for the FP64 map without scaling
+    const double *R = nullptr;  // residual in
+    double *Rout = nullptr;     // residual out: == R (in place) unless b == R, then another array
+    double *U = nullptr;        // iterate, updated unless cdefer is set
+    void *cdefer = nullptr;     // ring of postponed corrections (level format), or null
+    const int *ctr = nullptr;   // ... slot of this step
+    size_t cstride = 0;         // ... elements between slots
+    double *adef = nullptr;     // ... alpha of each slot
+    const double *scal = nullptr;
+    double h2 = 0.0, omega = 0.8;
+    double *part = nullptr;
+};
 size_t sweep_update_lds_bytes(int P, int ty, size_t sb);
 bool sweep_update_ok(int P, int prec, const Shape &s);
 int sweep_update_blocks(int P, const Shape &s);
-hipError_t launch_sweep_update(int prec, int P, const void *c, const void *b, double *R, double *U,
-                               const double *scal, double h2, double omega, double *part, const Shape &s,
-                               hipStream_t st);
+// Lets the kernel's instances allocate up to kLdsMax of LDS (FP64 rows at
+// P = 512 need more than 64 KB); call before the first launch, outside a
+// stream capture.
+hipError_t sweep_update_prepare();
+hipError_t launch_sweep_update(int prec, int P, const SweepUpdateArgs &a, const Shape &s, hipStream_t st);
+// Apply postponed corrections: U += adef[j] h^2 c_j for j = 0 .. count-1 in
+// order (c_j at cdefer + j * cstride elements, level format prec; elems
+// padded elements each), then *ctr = 0.
+hipError_t launch_defer_flush(int prec, const void *cdefer, size_t cstride, const double *adef, int count, double h2,
+                              double *U, size_t elems, int *ctr, hipStream_t st);
 
 // First pre-smoothing of the finest 3-D level from the FP64 residual (scaled
 // and cast) fused with the residual + full-weighting restriction of its
 // result; writes b = round(r / alpha), c2 and the coarse right-hand side.
-// FP32/FP16/BF16 levels with P/8 dividing 64; s.tyc coarse rows and s.zcc
+// Levels with P/8 dividing 64 (FP64 ones: at most 512 threads and kLdsMax of
+// LDS, one coarse row per tile at P = 512); s.tyc coarse rows and s.zcc
 // coarse planes per block.
 // LDS one workgroup may allocate on gfx950.
 constexpr size_t kLdsMax = 160 * 1024;
-size_t smooth_restrict_lds_bytes(int P, int tyc);
+size_t smooth_restrict_lds_bytes(int P, int tyc, int prec);
 // Lets every instance of the fused kernel allocate up to kLdsMax of LDS; call
 // once per process before the first launch (not inside a stream capture).
 hipError_t smooth_restrict_prepare();

@@ -17,9 +17,10 @@
 // block forms c2 of plane t+1 (from c1 of planes t .. t+2), the residual of
 // plane t (from c2 of planes t-1 .. t+1), and folds the residual rows of
 // plane t-1 into the coarse plane; c1, c2 and the residual rows sit in
-// double-buffered LDS slots (in FP32, up to 104 KB at P = 512, which gfx950
-// allows one workgroup), each written after the iteration's barrier and
-// not read again before the next one.  The arithmetic is that of the
+// double-buffered LDS slots (in the accumulator format: FP32, up to 104 KB at
+// P = 512, or FP64 for an FP64 level, 124 KB at P = 512 with one coarse row
+// per tile; gfx950 allows one workgroup 160 KB), each written after the
+// iteration's barrier and not read again before the next one.  The arithmetic is that of the
 // separate kernels, operation for operation, so results are bitwise equal.
 #include "mg_device.h"
 #include "mg_launch.h"
@@ -32,8 +33,12 @@ namespace {
 // SCALED: the right-hand side is the scaled-and-cast FP64 residual (the
 // finest level inside a refinement step; b is also written out); otherwise
 // it is the level's stored b (a coarser level, or a V-cycle on its own).
+// FP64 levels keep nine rows of eight doubles in registers: a lower thread
+// bound leaves each thread more of them
+template <class T> constexpr int sr_bound() { return sizeof(T) == 8 ? 512 : 768; }
+
 template <class T, class TC, bool SCALED>
-__global__ __launch_bounds__(768) void k_smooth_restrict(const void *__restrict__ src,
+__global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *__restrict__ src,
                                                           const double *__restrict__ scal, T *__restrict__ bout,
                                                           T *__restrict__ cout, TC *__restrict__ bc, int P, int tyc,
                                                           int zcc, int ytiles, double omega, int xcd) {
@@ -275,7 +280,7 @@ hipError_t smooth_restrict_t(int pc, int P, const void *src, const double *scal,
     const int ytiles = (Pc - 1 + s.tyc - 1) / s.tyc;
     const int blocks = ytiles * ((Pc - 1 + s.zcc - 1) / s.zcc);
     const int threads = (2 * s.tyc + 5) * (P / 8);
-    const size_t lds = smooth_restrict_lds_bytes(P, s.tyc);
+    const size_t lds = smooth_restrict_lds_bytes(P, s.tyc, sizeof(T) == 8 ? P_F64 : P_F32);
 #define MG_SR(TCT)                                                                                                     \
     hipLaunchKernelGGL((k_smooth_restrict<T, TCT, SCALED>), dim3(blocks), dim3(threads), lds, st, src, scal,       \
                        static_cast<T *>(bout), static_cast<T *>(cout), static_cast<TCT *>(bc), P, s.tyc, s.zcc,     \
@@ -293,8 +298,9 @@ hipError_t smooth_restrict_t(int pc, int P, const void *src, const double *scal,
 
 }  // namespace
 
-size_t smooth_restrict_lds_bytes(int P, int tyc) {
-    return (4 * (size_t)(2 * tyc + 5) * P + 2 * (size_t)(2 * tyc + 1) * (P / 2)) * sizeof(float);
+size_t smooth_restrict_lds_bytes(int P, int tyc, int prec) {
+    const size_t acc = prec == P_F64 ? sizeof(double) : sizeof(float);
+    return (4 * (size_t)(2 * tyc + 5) * P + 2 * (size_t)(2 * tyc + 1) * (P / 2)) * acc;
 }
 
 hipError_t smooth_restrict_prepare() {
@@ -303,13 +309,16 @@ hipError_t smooth_restrict_prepare() {
 #define MG_SR_FN(T, S)                                                                                        \
     (const void *)k_smooth_restrict<T, double, S>, (const void *)k_smooth_restrict<T, float, S>,              \
         (const void *)k_smooth_restrict<T, f16, S>, (const void *)k_smooth_restrict<T, bf16, S>
-            MG_SR_FN(float, true), MG_SR_FN(f16, true), MG_SR_FN(bf16, true),
-            MG_SR_FN(float, false), MG_SR_FN(f16, false), MG_SR_FN(bf16, false)
+            MG_SR_FN(double, true), MG_SR_FN(float, true), MG_SR_FN(f16, true), MG_SR_FN(bf16, true),
+            MG_SR_FN(double, false), MG_SR_FN(float, false), MG_SR_FN(f16, false), MG_SR_FN(bf16, false)
 #undef MG_SR_FN
         };
         for (const void *f : fns) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-            if (e != hipSuccess) return e;
+            if (e != hipSuccess) {
+                (void)hipGetLastError();  // leave no error for the next launch to report
+                return e;
+            }
         }
         return hipSuccess;
     }();
@@ -317,16 +326,17 @@ hipError_t smooth_restrict_prepare() {
 }
 
 bool smooth_restrict_ok(int P, int prec, const RShape &s) {
-    if (prec == P_F64 || P < 16 || P / 8 > 64 || 64 % (P / 8) != 0) return false;
+    if (P < 16 || P / 8 > 64 || 64 % (P / 8) != 0) return false;
     if (s.tyc < 1 || s.tyc > P / 2 - 1 || s.zcc < 1 || s.zcc > P / 2 - 1) return false;
-    if ((2 * s.tyc + 5) * (P / 8) > 768) return false;  // the kernel's launch bound
-    return smooth_restrict_lds_bytes(P, s.tyc) <= kLdsMax;
+    if ((2 * s.tyc + 5) * (P / 8) > (prec == P_F64 ? 512 : 768)) return false;  // the kernel's launch bound
+    return smooth_restrict_lds_bytes(P, s.tyc, prec) <= kLdsMax;
 }
 
 hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
                                   void *cout, void *bc, double omega, const RShape &s, hipStream_t st) {
     if (!smooth_restrict_ok(P, prec, s)) return hipErrorInvalidValue;
     switch (prec) {
+    case P_F64: return smooth_restrict_t<double, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
     case P_F32: return smooth_restrict_t<float, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
     case P_F16: return smooth_restrict_t<f16, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
     case P_BF16: return smooth_restrict_t<bf16, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
@@ -338,6 +348,7 @@ hipError_t launch_smooth_restrict_b(int prec, int pc, int P, const void *b, void
                                     const RShape &s, hipStream_t st) {
     if (!smooth_restrict_ok(P, prec, s)) return hipErrorInvalidValue;
     switch (prec) {
+    case P_F64: return smooth_restrict_t<double, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
     case P_F32: return smooth_restrict_t<float, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
     case P_F16: return smooth_restrict_t<f16, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
     case P_BF16: return smooth_restrict_t<bf16, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);

@@ -6,6 +6,20 @@
 // the kernel reads c, b, r, u and writes r, u (2 s + 32 bytes per point
 // instead of 3 s for the sweep and s + 32 for the update).
 //
+// Two variants change what is read and written, not the arithmetic:
+//   ALIAS  the FP64 map without residual scaling, whose right-hand side b is
+//          the residual r itself.  A block reads b on halo rows that its
+//          neighbours update, so the new residual goes to a second array
+//          (Rout != R, swapped every step), and r of a point is the b value
+//          the block already holds: c, r and u read, r and u written
+//          (8 + 32 bytes per point in FP64).
+//   DEFER  the update of u is postponed: c' is stored in its storage format
+//          in slot k of a ring of corrections (k read from *ctr) and alpha in
+//          adef[k]; launch_defer_flush later forms u += alpha_j h^2 c'_j for
+//          the slots in order, the same roundings in the same sequence.  Per
+//          step the kernel then reads c, b, r and writes r and c' (3 s + 16
+//          bytes per point instead of 2 s + 32).
+//
 // A block owns TY output rows of full width and a chunk of planes.  The
 // update at plane z needs c' on rows y0-1 .. y0+TY and planes z-1 .. z+1, so
 // the sweep runs one plane ahead on TY + 2 rows, which needs c on TY + 4
@@ -21,12 +35,16 @@
 namespace mg {
 namespace {
 
-template <int V, class T>
-__global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, const T *__restrict__ b,
-                                                       double *__restrict__ R, double *__restrict__ U,
-                                                       const double *__restrict__ scal, double h2, double omega,
-                                                       double *__restrict__ part, int P, int TY, int zc, int ytiles,
-                                                       int xcd) {
+// FP64 rows need more registers than a 1024-thread block leaves a thread
+template <class T> constexpr int su_bound() { return sizeof(T) == 8 ? 768 : 1024; }
+
+template <int V, class T, bool ALIAS, bool DEFER>
+__global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
+    const T *__restrict__ c, const T *__restrict__ b, const double *R, double *Rout, double *__restrict__ U,
+    T *__restrict__ Cd, const int *__restrict__ ctr, size_t cstride, double *__restrict__ adef,
+    const double *__restrict__ scal, double h2, double omega, double *__restrict__ part, int P, int TY, int zc,
+    int ytiles, int xcd) {
+    static_assert(!ALIAS || sizeof(T) == 8, "the residual is the right-hand side only in FP64");
     typedef acc_t<T> A;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[32];
@@ -54,6 +72,12 @@ __global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, 
     const A k = (A)(omega / 6.0);
     const double a = scal[0];
     const double ah2 = a * h2;
+    T *cd = nullptr;  // DEFER: this step's slot
+    if constexpr (DEFER) {
+        const int k = *ctr;
+        cd = Cd + (size_t)k * cstride;
+        if (blockIdx.x == 0 && threadIdx.x == 0) adef[k] = a;
+    }
 
     auto fetch_c = [&](int z, RawRow<T, V> &r) {
         if (!row_in || z <= 0 || z >= P) {
@@ -90,21 +114,24 @@ __global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, 
         const int s0 = wb + 1;
         if (sweep_row && row_in && s0 >= 1 && s0 <= P - 1) fetch_row<T, V>(b + g.at(x0, y, s0), bnext);
         if (out_row && z0 < z1) {
-            fetch_row<double, V>(R + g.at(x0, y, z0), rnext);
-            fetch_row<double, V>(U + g.at(x0, y, z0), unext);
+            if constexpr (!ALIAS) fetch_row<double, V>(R + g.at(x0, y, z0), rnext);
+            if constexpr (!DEFER) fetch_row<double, V>(U + g.at(x0, y, z0), unext);
         }
     }
     for (int w = wb; w < z1; ++w) {
         const int s = w + 1;  // plane swept in this iteration
+        if constexpr (ALIAS) {
+            if (w >= z0) rcur = bcur;  // b of plane w is its residual
+        }
         bcur = bnext;
         if (sweep_row && row_in && s + 1 >= 1 && s + 1 <= P - 1 && s + 1 <= z1)
             fetch_row<T, V>(b + g.at(x0, y, s + 1), bnext);
         if (w >= z0) {
-            rcur = rnext;
-            ucur = unext;
+            if constexpr (!ALIAS) rcur = rnext;
+            if constexpr (!DEFER) ucur = unext;
             if (out_row && w + 1 < z1) {
-                fetch_row<double, V>(R + g.at(x0, y, w + 1), rnext);
-                fetch_row<double, V>(U + g.at(x0, y, w + 1), unext);
+                if constexpr (!ALIAS) fetch_row<double, V>(R + g.at(x0, y, w + 1), rnext);
+                if constexpr (!DEFER) fetch_row<double, V>(U + g.at(x0, y, w + 1), unext);
             }
         }
         __syncthreads();
@@ -155,7 +182,7 @@ __global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, 
             load_row<T, V>(row + P + x0, yp);
             double r[V], u[V];
             widen_row<double, V>(rcur, r);
-            widen_row<double, V>(ucur, u);
+            if constexpr (!DEFER) widen_row<double, V>(ucur, u);
 #pragma unroll
             for (int i = 0; i < V; ++i) {
                 nb[i] += ym[i];
@@ -164,7 +191,7 @@ __global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, 
                 nb[i] += (double)fp[i];
                 const double lc = fmaT<double>(6.0, cv[i], -nb[i]);
                 r[i] = fmaT<double>(-a, lc, r[i]);
-                u[i] = fmaT<double>(ah2, cv[i], u[i]);
+                if constexpr (!DEFER) u[i] = fmaT<double>(ah2, cv[i], u[i]);
             }
             if (x0 == 0) r[0] = 0.0, u[0] = 0.0;
 #pragma unroll
@@ -173,8 +200,16 @@ __global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, 
                 mx = nanmax(mx, fabs(r[i]));
             }
             const size_t at = g.at(x0, y, w);
-            store_row<double, V>(R + at, r);
-            store_row<double, V>(U + at, u);
+            store_row<double, V>(Rout + at, r);
+            if constexpr (DEFER) {
+                // c' is a value of T (rounded by the sweep), so this is exact
+                T co[V];
+#pragma unroll
+                for (int i = 0; i < V; ++i) co[i] = Store<T>::from_acc(fc[i]);
+                store_row<T, V>(cd + at, co);
+            } else {
+                store_row<double, V>(U + at, u);
+            }
         }
         // c of plane s + 1 for the next iteration's y neighbours (that slot was
         // last read before this iteration's barrier)
@@ -202,40 +237,82 @@ __global__ __launch_bounds__(1024) void k_sweep_update(const T *__restrict__ c, 
     }
 }
 
-template <class T>
-hipError_t sweep_update_t(int P, const void *c, const void *b, double *R, double *U, const double *scal, double h2,
-                          double omega, double *part, const Shape &s, hipStream_t st) {
+template <class T, bool ALIAS, bool DEFER>
+hipError_t sweep_update_t(int P, const SweepUpdateArgs &q, const Shape &s, hipStream_t st) {
     const int ytiles = (P - 1 + s.ty - 1) / s.ty;
     const int nch = (P - 1 + s.zc - 1) / s.zc;
     const int threads = (P / s.V) * (s.ty + 4);
     const size_t lds = sweep_update_lds_bytes(P, s.ty, sizeof(T));
-    hipLaunchKernelGGL((k_sweep_update<4, T>), dim3(ytiles * nch), dim3(threads), lds, st, static_cast<const T *>(c),
-                       static_cast<const T *>(b), R, U, scal, h2, omega, part, P, s.ty, s.zc, ytiles, s.xcd);
+    hipLaunchKernelGGL((k_sweep_update<4, T, ALIAS, DEFER>), dim3(ytiles * nch), dim3(threads), lds, st,
+                       static_cast<const T *>(q.c), static_cast<const T *>(q.b), q.R, q.Rout, q.U,
+                       static_cast<T *>(q.cdefer), q.ctr, q.cstride, q.adef, q.scal, q.h2, q.omega, q.part, P, s.ty,
+                       s.zc, ytiles, s.xcd);
     return hipGetLastError();
+}
+
+template <class T> hipError_t sweep_update_mode(int P, const SweepUpdateArgs &q, const Shape &s, hipStream_t st) {
+    const bool alias = q.b == (const void *)q.R, defer = q.cdefer != nullptr;
+    if constexpr (sizeof(T) == 8) {
+        if (alias) {
+            if (q.Rout == q.R) return hipErrorInvalidValue;  // the residual must not be updated in place
+            return defer ? sweep_update_t<T, true, true>(P, q, s, st) : sweep_update_t<T, true, false>(P, q, s, st);
+        }
+    } else if (alias) {
+        return hipErrorInvalidValue;
+    }
+    return defer ? sweep_update_t<T, false, true>(P, q, s, st) : sweep_update_t<T, false, false>(P, q, s, st);
 }
 
 }  // namespace
 
 size_t sweep_update_lds_bytes(int P, int ty, size_t sb) { return 4 * (size_t)(ty + 4) * P * sb; }
 
+// the kernel's own 256 bytes of reduction scratch come out of the same LDS
+constexpr size_t kSuDynLdsMax = kLdsMax - 1024;
+
+hipError_t sweep_update_prepare() {
+    static hipError_t done = [] {
+        const void *fns[] = {
+#define MG_SU_FN(T) (const void *)k_sweep_update<4, T, false, false>, (const void *)k_sweep_update<4, T, false, true>
+            MG_SU_FN(double), MG_SU_FN(float), MG_SU_FN(f16), MG_SU_FN(bf16),
+#undef MG_SU_FN
+            (const void *)k_sweep_update<4, double, true, false>, (const void *)k_sweep_update<4, double, true, true>};
+        for (const void *f : fns) {
+            // what the function's static LDS leaves of the workgroup's kLdsMax
+            hipFuncAttributes fa{};
+            hipError_t e = hipFuncGetAttributes(&fa, f);
+            if (e == hipSuccess && fa.sharedSizeBytes + kSuDynLdsMax > kLdsMax) e = hipErrorInvalidValue;
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)(kLdsMax - fa.sharedSizeBytes));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();  // leave no error for the next launch to report
+                return e;
+            }
+        }
+        return hipSuccess;
+    }();
+    return done;
+}
+
 bool sweep_update_ok(int P, int prec, const Shape &s) {
     // V = 4 only: at V = 8 the FP64 rows of the update spill registers
     if (s.V != 4 || s.V > P || s.ty < 1 || s.ty > P - 1 || s.zc < 1 || s.zc > P - 1) return false;
-    if ((P / s.V) * (s.ty + 4) > 1024) return false;
-    return sweep_update_lds_bytes(P, s.ty, prec_bytes(prec)) <= 65536;
+    if ((P / s.V) * (s.ty + 4) > (prec == P_F64 ? 768 : 1024)) return false;
+    return sweep_update_lds_bytes(P, s.ty, prec_bytes(prec)) <= kSuDynLdsMax;
 }
 
 int sweep_update_blocks(int P, const Shape &s) { return ((P - 1 + s.ty - 1) / s.ty) * ((P - 1 + s.zc - 1) / s.zc); }
 
-hipError_t launch_sweep_update(int prec, int P, const void *c, const void *b, double *R, double *U,
-                               const double *scal, double h2, double omega, double *part, const Shape &s,
-                               hipStream_t st) {
+hipError_t launch_sweep_update(int prec, int P, const SweepUpdateArgs &q, const Shape &s, hipStream_t st) {
     if (!sweep_update_ok(P, prec, s)) return hipErrorInvalidValue;
+    if (sweep_update_lds_bytes(P, s.ty, prec_bytes(prec)) > 65536 && sweep_update_prepare() != hipSuccess)
+        return hipErrorInvalidValue;
     switch (prec) {
-    case P_F64: return sweep_update_t<double>(P, c, b, R, U, scal, h2, omega, part, s, st);
-    case P_F32: return sweep_update_t<float>(P, c, b, R, U, scal, h2, omega, part, s, st);
-    case P_F16: return sweep_update_t<f16>(P, c, b, R, U, scal, h2, omega, part, s, st);
-    case P_BF16: return sweep_update_t<bf16>(P, c, b, R, U, scal, h2, omega, part, s, st);
+    case P_F64: return sweep_update_mode<double>(P, q, s, st);
+    case P_F32: return sweep_update_mode<float>(P, q, s, st);
+    case P_F16: return sweep_update_mode<f16>(P, q, s, st);
+    case P_BF16: return sweep_update_mode<bf16>(P, q, s, st);
     }
     return hipErrorInvalidValue;
 }

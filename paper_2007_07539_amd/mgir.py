@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
                 ("residual_scaling", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("use_initial_guess", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("rescale_half", ctypes.c_int), ("cycles_per_step", ctypes.c_int), ("base_tol", ctypes.c_double),
-                ("base_max_iter", ctypes.c_int), ("discretization", ctypes.c_int)]
+                ("base_max_iter", ctypes.c_int), ("discretization", ctypes.c_int), ("defer_update", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -155,7 +155,7 @@ class Solver:
     def __init__(self, dim: int, n: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
                  max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False,
                  rescale_half=False, cycles_per_step=1, nlevels=0, base_tol=1e-4, base_max_iter=0,
-                 disc="fd", device=None, stream=None):
+                 disc="fd", defer_update=0, device=None, stream=None):
         self.lib = load()
         self.dim, self.n = dim, n
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -167,6 +167,7 @@ class Solver:
         o.rescale_half = int(bool(rescale_half))
         o.cycles_per_step = int(cycles_per_step)
         o.base_tol, o.base_max_iter = float(base_tol), int(base_max_iter)
+        o.defer_update = int(defer_update)
         if disc not in DISC:
             raise ValueError(f"disc must be one of {sorted(DISC)}, got {disc!r}")
         o.discretization = DISC[disc]

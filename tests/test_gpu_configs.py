@@ -78,23 +78,28 @@ def test_poisson3d_511_maps(dev, ref, name):
 
 
 @pytest.mark.slow
-def test_fused_kernels_in_their_511_shapes_bitwise(dev):
-    """At 511^3 the fused first smoothing + restriction runs with 3 coarse rows
-    per tile (102 KB of LDS) and the fused last sweep + update with 1024-thread
-    blocks: shapes no smaller grid reaches.  One refinement step and a whole
-    solve with these shapes equal the unfused kernels' bit for bit."""
+@pytest.mark.parametrize("name,scaling,sr,fuse", [("f16", True, [1, 3, 85], [1, 4, 64, 1, 4]),
+                                                  ("f64", False, [1, 1, 16], [1, 4, 32, 1, 2])])
+def test_fused_kernels_in_their_511_shapes_bitwise(dev, name, scaling, sr, fuse):
+    """At 511^3 the fused first smoothing + restriction runs with its largest
+    tiles (FP16: 3 coarse rows, 102 KB of LDS; FP64: 1 coarse row, 124 KB) and
+    the fused last sweep + update with its largest blocks (FP16: 1024 threads;
+    FP64: 768 threads, 96 KB, the new residual in the second array): shapes no
+    smaller grid reaches.  One refinement step and a whole solve with these
+    shapes equal the unfused kernels' bit for bit."""
     n = 511
-    print("511^3 fused shapes vs unfused", flush=True)
-    prec = W.precision_map("f16", W.levels_for(n))
+    print(f"511^3 fused shapes vs unfused, {name}", flush=True)
+    prec = W.precision_map(name, W.levels_for(n))
+    dt = mgir.TORCH_DTYPE[prec[0]]
     bt = torch.from_numpy(W.poisson3d_sine_noise_rhs(n, seed=3)).to(dev)
 
     def run(fused, max_iter):
-        s = mgir.Solver(3, n, prec, max_iter=max_iter)
+        s = mgir.Solver(3, n, prec, max_iter=max_iter, residual_scaling=scaling)
         if fused:
-            s.set_shape(0, mgir.SHAPE_FUSE_SR, [1, 3, 85])
-            s.set_shape(0, mgir.SHAPE_FUSE, [1, 4, 64, 1, 4])
-            assert s.get_shape(0, mgir.SHAPE_FUSE_SR) == [1, 3, 85]
-            assert s.get_shape(0, mgir.SHAPE_FUSE) == [1, 4, 64, 1, 4]
+            s.set_shape(0, mgir.SHAPE_FUSE_SR, sr)
+            s.set_shape(0, mgir.SHAPE_FUSE, fuse)
+            assert s.get_shape(0, mgir.SHAPE_FUSE_SR) == sr
+            assert s.get_shape(0, mgir.SHAPE_FUSE) == fuse
         else:
             s.set_shape(0, mgir.SHAPE_FUSE_SR, [0])
             s.set_shape(0, mgir.SHAPE_FUSE, [0])
@@ -102,8 +107,9 @@ def test_fused_kernels_in_their_511_shapes_bitwise(dev):
         out = {"u": u}
         if max_iter == 1:
             assert r.status == mgir.MG_ERR_NOT_CONVERGED and r.iterations == 1
-            out.update(bhat=s.read(0, mgir.BUF_RHS, torch.float16), bc=s.read(1, mgir.BUF_RHS, torch.float16),
-                       r=s.read(0, mgir.BUF_RES))
+            out.update(bc=s.read(1, mgir.BUF_RHS, mgir.TORCH_DTYPE[prec[1]]), r=s.read(0, mgir.BUF_RES))
+            if scaling:
+                out.update(bhat=s.read(0, mgir.BUF_RHS, dt))
         del s
         torch.cuda.empty_cache()
         return out, r
@@ -139,23 +145,74 @@ def test_fp16_without_residual_scaling_stalls(dev, scale):
     assert off.rel_residual > 1e3 * on.rel_residual
 
 
+def _kappa_2d(disc, n):
+    """Condition number of the 2-D grid operator: FD [4, -1] has eigenvalues
+    8 sin^2(t/2) .. 8 cos^2(t/2), t = pi h; Q1 [8, -1 (8x)] / 3 has
+    (8 - 2 cx - 2 cy - 4 cx cy) / 3 over the modes, smallest at cx = cy = cos t,
+    largest (4) at one cosine -1 and the other 1."""
+    t = np.pi / (n + 1)
+    if disc == "fd":
+        return (np.cos(t / 2) / np.sin(t / 2)) ** 2
+    c = np.cos(t)
+    return 4.0 / ((8 - 4 * c - 4 * c * c) / 3.0)
+
+
 @pytest.mark.parametrize("disc,n", [("fd", 2047), ("q1", 6143)])
 def test_fp16_on_large_2d_grids_stays_in_range(dev, ref, disc, n):
     """2-D grids whose correction bound exceeds FP16's range for a right-hand
-    side of max-norm one (the paper's k = 1 sine from u0 = 0; 6143^2 is its
-    largest Q1 mesh): the range-safe alpha keeps the FP16 levels finite and the
-    solve reaches 1e-10 within two iterations of FP64."""
+    side of max-norm one (the paper's k = 1 sine; 6143^2 is its largest Q1
+    mesh): the range-safe alpha keeps the FP16 levels finite and the solve
+    reaches 1e-10.
+
+    From u0 = 0 the first correction is the smoothest mode at its largest
+    gain, and rounding it to FP16 (relative u = 2^-11) leaves a residual of up
+    to about u kappa(L) (1 + rho) relative to the scaled one: the first step
+    may raise the residual (kappa u ~ 830 at 2047^2 FD), after which every
+    step contracts it again at a multigrid rate.  The paper measures from a random guess in [0, 1]
+    (Section 6), whose first residual is rough; from there the FP16 solve stays
+    within two iterations of FP64.
+
+    Tolerance: 1e-10 relative on the FD grid.  On the paper's 6143^2 Q1 mesh
+    the smooth solution makes FP64's own rounding of A u about
+    u_64 lambda_max / lambda_min ~ 1e-9 of ||b||, so a relative 1e-10 lies
+    below what any FP64 residual can confirm there; that case stops at the
+    paper's own test, ||r||_2 < 1e-9 absolute (Section 6; 6e-7 relative for
+    this lumped load vector)."""
     print(f"2-D {disc} n={n}, k=1 sine, FP16 levels", flush=True)
     b = W.manufactured_rhs(2, n, 1)
     if disc == "q1":
         b = b / float(n + 1) ** 2   # lumped load vector h^2 f
     bt = torch.from_numpy(b).to(dev)
     L = mgir.full_levels(n)
-    s16 = mgir.Solver(2, n, W.precision_map("f16", L), disc=disc)
+    rtol = 1e-10 if disc == "fd" else 1e-9 / ref.norm2(b)
+    s16 = mgir.Solver(2, n, W.precision_map("f16", L), disc=disc, rtol=rtol)
+    s64 = mgir.Solver(2, n, W.precision_map("f64", L), disc=disc, residual_scaling=False, rtol=rtol)
     assert s16.alpha_shift() >= 1
     u16, r16 = s16.solve(bt)
-    _, r64 = mgir.Solver(2, n, W.precision_map("f64", L), disc=disc, residual_scaling=False).solve(bt)
+    _, r64 = s64.solve(bt)
     rel = _oracle_rel(ref, b, u16.cpu().numpy(), disc)
-    print(f"  shift {s16.alpha_shift()}: f16 {r16.iterations} it rel {rel:.3e}; f64 {r64.iterations} it", flush=True)
-    assert r16.status == mgir.MG_OK and rel <= 1e-10
-    assert r16.iterations <= r64.iterations + 2
+    h16, h64 = np.asarray(r16.history), np.asarray(r64.history)
+    rho64 = (h64[-1] / h64[0]) ** (1.0 / r64.iterations)
+    spike = h16[1] / h16[0]
+    bound = rho64 + (1 + rho64) * 2.0 ** -11 * _kappa_2d(disc, n)
+    print(f"  shift {s16.alpha_shift()}: f16 {r16.iterations} it rel {rel:.3e} first step x{spike:.3g} "
+          f"(bound {bound:.3g}); f64 {r64.iterations} it rate {rho64:.3f}", flush=True)
+    assert r16.status == mgir.MG_OK and rel <= rtol
+    assert np.all(np.isfinite(h16)) and spike <= bound
+    # after the first step every FP16 step reduces the residual, at a multigrid
+    # rate (FD: as fast as FP64's; Q1, whose kappa is 4.5 times larger: 0.11
+    # per step against FP64's 0.07, measured)
+    rho16 = (h16[-1] / h16[1]) ** (1.0 / (r16.iterations - 1))
+    print(f"  rate after the first step: f16 {rho16:.3f}, f64 {rho64:.3f}", flush=True)
+    assert np.all(np.diff(h16[1:]) < 0) and rho16 < 0.5, (h16, rho16)
+    # the paper's protocol: random initial guess in [0, 1]
+    u0 = torch.from_numpy(W.random_initial_guess(2, n, seed=7)).to(dev)
+    s16g = mgir.Solver(2, n, W.precision_map("f16", L), disc=disc, use_initial_guess=True, rtol=rtol)
+    s64g = mgir.Solver(2, n, W.precision_map("f64", L), disc=disc, residual_scaling=False, use_initial_guess=True,
+                       rtol=rtol)
+    ug16, g16 = s16g.solve(bt, u0.clone())
+    _, g64 = s64g.solve(bt, u0.clone())
+    relg = _oracle_rel(ref, b, ug16.cpu().numpy(), disc)
+    print(f"  random u0: f16 {g16.iterations} it rel {relg:.3e}; f64 {g64.iterations} it", flush=True)
+    assert g16.status == mgir.MG_OK and relg <= rtol
+    assert g16.iterations <= g64.iterations + 2
