@@ -184,6 +184,21 @@ mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *st
  * Asynchronous on stream.  Errors: MG_ERR_ARG, MG_ERR_WORKSPACE, MG_ERR_HIP. */
 mg_status_t mg_vcycle(mg_handle h, const void *b, void *c, void *stream);
 
+/* mg_vcycle for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same V-cycle, with the level vectors in a 128 MiB array the library holds on
+ * each GPU (a file-scope device array, held until the process ends) instead of
+ * the bound workspace, which this call neither needs nor touches.  128 MiB
+ * holds the V-cycle of a 255^3 FP16 or a 127^3 FP64 hierarchy.  The handle
+ * comes from mg_setup (which allocates no device memory); nothing is
+ * allocated and nothing synchronises.  Every call on a GPU shares that GPU's
+ * array and clears the part it uses first, so calls that overlap on one GPU
+ * (other streams, other threads) race; serialise them.
+ *   b, c  as for mg_vcycle; the result is bit for bit mg_vcycle's.
+ * Errors: MG_ERR_ARG, MG_ERR_STATE (batched or many-right-hand-side handle),
+ * MG_ERR_WORKSPACE (the handle's V-cycle needs more than 128 MiB), MG_ERR_HIP. */
+mg_status_t mg_vcycle_noalloc(mg_handle h, const void *b, void *c, void *stream);
+
 /* Solve A u = b by iterative refinement with residuum scaling (Algorithm 2):
  * r = b - A u;  while ||r||_2 > rtol ||b||_2:  alpha = ||r||_inf (or 1);
  * c = V-cycle(r / alpha) in the level formats;  u += alpha c;  r -= alpha A c.

@@ -37,6 +37,7 @@ SOURCES = (("mg_kernels.hip", True), ("mg_multi.hip", True), ("mg_tail.hip", Tru
            ("mg_rescale.hip", True),
            ("mg_cg.hip", True),
            ("mg_q1.hip", True),
+           ("mg_noalloc.hip", True),
            ("mg_api.cpp", False))
 
 

@@ -76,6 +76,7 @@ struct mg_ctx {
     int ascale = 0;
     std::vector<LevelPlan> lv;
     size_t off_R = 0, off_U = 0, off_part = 0, off_scal = 0, ws_need = 0;
+    size_t vc_bytes = 0;  // the leading part of the workspace a lone V-cycle uses
     size_t off_rs = 0, off_rpart = 0;  // per-level {s, 1/s} and the partial maxima of the rescaling
     int max_parts = 0;
     char *ws = nullptr;
@@ -537,7 +538,7 @@ int tail_level(const mg_ctx *h) {
 // skip0: its last post-sweep is left to the fused sweep + update.
 hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode, bool warm = false, bool skip0 = false) {
     const int nl = h->nl;
-    std::vector<const void *> rhs(nl);
+    const void *rhs[32];  // (levels are at most 13; no heap use on this path)
     for (int l = 0; l < nl; ++l) rhs[l] = bbuf(h, l);
     if (mode == RHS_ALIAS_R) rhs[0] = Rbuf(h);
     hipError_t e;
@@ -1139,6 +1140,21 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         h->off_q1r = off;
         off += align_up(rb, 256);
     }
+    if (o.rescale_half) {
+        for (int l = 1; l < m; ++l) {
+            LevelPlan &C = h->lv[l];
+            if (!half_prec(C.prec)) continue;
+            C.rescale = true;
+            C.off_t = off;
+            off += align_up(C.elems * prec_bytes(acc_prec(h->lv[l - 1].prec)), 256);
+        }
+        h->off_rs = off;
+        off += align_up((size_t)2 * m * sizeof(double), 256);
+        h->off_rpart = off;
+        off += align_up(rescale_part_count() * sizeof(double), 256);
+    }
+    // everything a V-cycle on its own touches lies below this offset
+    h->vc_bytes = off;
     const size_t fin = align_up(h->lv[0].elems * sizeof(double), 256);
     h->off_R = off;
     off += fin;
@@ -1183,19 +1199,6 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     off += align_up((size_t)maxp * 2 * sizeof(double), 256);
     h->off_scal = off;
     off += 256;
-    if (o.rescale_half) {
-        for (int l = 1; l < m; ++l) {
-            LevelPlan &C = h->lv[l];
-            if (!half_prec(C.prec)) continue;
-            C.rescale = true;
-            C.off_t = off;
-            off += align_up(C.elems * prec_bytes(acc_prec(h->lv[l - 1].prec)), 256);
-        }
-        h->off_rs = off;
-        off += align_up((size_t)2 * m * sizeof(double), 256);
-        h->off_rpart = off;
-        off += align_up(rescale_part_count() * sizeof(double), 256);
-    }
     h->ws_need = off;
     if (m > 1) {
         // the fused update's FP64 rows need more than 64 KB of LDS at P = 512
@@ -1393,6 +1396,48 @@ mg_status_t mg_vcycle(mg_handle h, const void *b, void *c, void *stream) {
     HIPCHK(launch_unpack(h->dim, L.prec, L.prec, L.n, L.P, cbuf(h, 0, h->cur[0]), c, st));
     return MG_OK;
 }
+
+}  // extern "C"
+
+// ---- the V-cycle on a library-owned scratch array (mg_noalloc.hip) ----------
+namespace mg {
+
+mg_status_t set_error(mg_status_t s, const char *msg) { return fail(s, "%s", msg); }
+
+mg_status_t vcycle_scratch_need(mg_handle h, size_t *bytes) {
+    if (!h || !bytes) return fail(MG_ERR_ARG, "null argument");
+    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
+    *bytes = h->vc_bytes;
+    return MG_OK;
+}
+
+mg_status_t vcycle_in(mg_handle h, void *ws, size_t cap, const void *b, void *c, void *stream) {
+    size_t need = 0;
+    mg_status_t s = vcycle_scratch_need(h, &need);
+    if (s != MG_OK) return s;
+    if (!ws || !b || !c) return fail(MG_ERR_ARG, "null argument");
+    if (need > cap) return fail(MG_ERR_WORKSPACE, "a V-cycle of this handle needs %zu bytes, more than %zu", need, cap);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the handle's own workspace and level roles stay as they were
+    char *keep_ws = h->ws;
+    int keep_cur[32];
+    std::memcpy(keep_cur, h->cur, sizeof keep_cur);
+    h->ws = static_cast<char *>(ws);
+    const LevelPlan &L = h->lv[0];
+    // ghost cells must read zero, and the array keeps the last call's values
+    hipError_t e = launch_fill_zero(ws, align_up(need, 16), st);
+    if (e == hipSuccess) e = launch_pack(h->dim, L.prec, L.prec, L.n, L.P, b, bbuf(h, 0), st);
+    if (e == hipSuccess) e = enq_vcycle(h, st, RHS_B);
+    if (e == hipSuccess) e = launch_unpack(h->dim, L.prec, L.prec, L.n, L.P, cbuf(h, 0, h->cur[0]), c, st);
+    h->ws = keep_ws;
+    std::memcpy(h->cur, keep_cur, sizeof keep_cur);
+    if (e != hipSuccess) return fail(MG_ERR_HIP, "V-cycle launch failed: %s", hipGetErrorString(e));
+    return MG_OK;
+}
+
+}  // namespace mg
+
+extern "C" {
 
 mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats, void *stream) {
     auto t0 = std::chrono::steady_clock::now();

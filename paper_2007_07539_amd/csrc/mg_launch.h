@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include "mgir.h"
+
 namespace mg {
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
@@ -257,5 +259,16 @@ hipError_t launch_m_restrict2(const MArgs &a, void *rbuf, int zcc, hipStream_t s
 // c = round(c + 4 P e) in place on a.cin (then a plain sweep completes the
 // prolongation stage).
 hipError_t launch_m_prolong_field(const MArgs &a, hipStream_t st);
+
+// ---- the V-cycle on a caller-given scratch array (host side, mg_api.cpp) -----
+// Bytes the V-cycle of a single-grid handle touches (its level vectors and
+// base-level scratch; the leading part of the workspace layout).
+mg_status_t vcycle_scratch_need(mg_handle h, size_t *bytes);
+// mg_vcycle with ws (cap bytes, 256-byte aligned) in place of the bound
+// workspace: clears the first vcycle_scratch_need bytes with a kernel, runs
+// pack, V-cycle and unpack on stream; nothing is allocated.
+mg_status_t vcycle_in(mg_handle h, void *ws, size_t cap, const void *b, void *c, void *stream);
+// Set the thread's mg_last_error text and return s.
+mg_status_t set_error(mg_status_t s, const char *msg);
 
 }  // namespace mg

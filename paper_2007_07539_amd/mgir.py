@@ -39,7 +39,7 @@ EXPORTS = ("mg_default_options", "mg_setup", "mg_workspace_size", "mg_bind_works
            "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_write", "mg_level_read", "mg_stage",
            "mg_levels", "mg_level_n", "mg_profile_step", "mg_set_shape", "mg_get_shape", "mg_bandwidth_probe",
            "mg_setup_batched", "ir_solve_batched", "mg_instances", "mg_setup_multi", "ir_solve_multi",
-           "mg_rhs_count", "mg_alpha_shift")
+           "mg_rhs_count", "mg_alpha_shift", "mg_vcycle_noalloc")
 SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE, SHAPE_SMOOTH, SHAPE_SWEEP, SHAPE_PROLONG, SHAPE_TAIL, SHAPE_FUSE, \
     SHAPE_FUSE_SR = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
@@ -81,6 +81,7 @@ def load() -> ctypes.CDLL:
     lib.mg_workspace_size.argtypes = [H, ctypes.POINTER(ctypes.c_size_t)]
     lib.mg_bind_workspace.argtypes = [H, vp, ctypes.c_size_t, vp]
     lib.mg_vcycle.argtypes = [H, vp, vp, vp]
+    lib.mg_vcycle_noalloc.argtypes = [H, vp, vp, vp]
     lib.ir_solve.argtypes = [H, vp, vp, ctypes.POINTER(Stats), vp]
     lib.mg_destroy.argtypes = [H]
     lib.mg_status_string.argtypes, lib.mg_status_string.restype = [i], ctypes.c_char_p
@@ -231,6 +232,16 @@ class Solver:
             raise ValueError(f"b must be {dt} of shape {(self.n,) * self.dim}")
         c = torch.empty_like(b) if out is None else out
         _check(self.lib.mg_vcycle(self._h, _dptr(b), _dptr(c), _stream_ptr(stream)), "mg_vcycle")
+        return c
+
+    def vcycle_noalloc(self, b: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """The same V-cycle through mg_vcycle_noalloc (the library's own
+        device array, no workspace, no allocation inside the call)."""
+        dt = TORCH_DTYPE[self.level_prec[0]]
+        if b.dtype != dt or tuple(b.shape) != (self.n,) * self.dim:
+            raise ValueError(f"b must be {dt} of shape {(self.n,) * self.dim}")
+        c = torch.empty_like(b) if out is None else out
+        _check(self.lib.mg_vcycle_noalloc(self._h, _dptr(b), _dptr(c), _stream_ptr(stream)), "mg_vcycle_noalloc")
         return c
 
     def solve(self, b: torch.Tensor, u: torch.Tensor | None = None, stream=None, history_cap: int = 256,

@@ -282,3 +282,16 @@ def test_q1_discretisation_option(lib):
     assert _setup_batched(lib, [15, 7], opt=o)[0] == mgir.MG_ERR_ARG
     h = ctypes.c_void_p()
     assert lib.mg_setup_multi(ctypes.byref(h), 3, 15, 4, None, ctypes.byref(o)) == mgir.MG_ERR_ARG
+
+
+def test_noalloc_vcycle_refusals_without_a_gpu(lib):
+    """mg_vcycle_noalloc checks the handle and the scratch size before any
+    device work: a 511^3 hierarchy needs more than the library's array."""
+    h = ctypes.c_void_p()
+    prec = (ctypes.c_int * 9)(*([mgir.PREC["f16"]] * 8 + [mgir.PREC["f64"]]))
+    assert lib.mg_setup(ctypes.byref(h), 3, 511, 0, prec, None) == mgir.MG_OK
+    dummy = ctypes.c_void_p(256)
+    assert lib.mg_vcycle_noalloc(h, dummy, dummy, None) == mgir.MG_ERR_WORKSPACE
+    assert b"mg_vcycle_noalloc holds" in lib.mg_last_error()
+    lib.mg_destroy(h)
+    assert lib.mg_vcycle_noalloc(None, dummy, dummy, None) == mgir.MG_ERR_ARG
