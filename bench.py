@@ -378,7 +378,8 @@ def main():
     ap.add_argument("--map", default="f16")
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle IR iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-only", action="store_true", help="only run the mixed solve (for rocprofv3)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only run the solve of --map with --defer (for rocprofv3)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--ceiling", action="store_true",
                     help="only measure the streaming bandwidth ceilings (copy, read, write, update mix)")
@@ -442,10 +443,13 @@ def main():
     # the mixed solve: FP16 levels, FP64 refinement; with the solution update
     # every step (Algorithm 2 as written) and postponed over --defer steps
     mixed_runs = {}
-    for depth in ([0, args.defer] if args.defer else [0]):
-        log(f"[bench] setup mixed solver (defer_update={depth})")
-        s = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=True, device=dev, autotune=tune,
-                        defer_update=depth)
+    # (profiling: one configuration, --map with --defer; the FP64 map runs
+    # without residual scaling, as the baseline does)
+    depths = [args.defer] if args.profile_only else [0, args.defer] if args.defer else [0]
+    for depth in depths:
+        log(f"[bench] setup {args.map} solver (defer_update={depth})")
+        s = mgir.Solver(3, n, W.precision_map(args.map, L), residual_scaling=args.map != "f64", device=dev,
+                        autotune=tune, defer_update=depth)
         ms, res = timed_solves(s, bt, u, args.steps, args.warmup, torch)
         log(f"[bench] mixed defer={depth}: {ms:.2f} ms/solve, {res[-1].iterations} it, "
             f"rel {res[-1].rel_residual:.2e}")
