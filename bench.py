@@ -41,8 +41,10 @@ def timed_solves(solver, bt, u, steps, warmup, torch):
     return start.elapsed_time(end) / steps, results
 
 
+# the sources a kernel is built from: a traffic summary holds for them as hashed
 KERNEL_SOURCES = {"ir_update": ("mg_kernels.hip", "mg_device.h"),
-                  "sweep_update": ("mg_sweep_update.hip", "mg_device.h")}
+                  "sweep_update": ("mg_sweep_update.hip", "mg_device.h"),
+                  "sweep_update_defer": ("mg_sweep_update.hip", "mg_device.h")}
 
 
 def kernel_source_hash(kernel):
@@ -100,10 +102,11 @@ def bandwidth_ceiling(torch, mgir, reps=5):
     cb = torch.ones(2 * n, dtype=torch.float16, device=dev)
     out = {"metric": "streaming HBM bandwidth ceiling", "unit": "GB/s", "peak": 8000.0}
     for name, kind, bytes_moved in (("copy", 0, 2 * 8 * n), ("read", 1, 8 * n), ("write", 2, 8 * n),
-                                    ("update_mix", 3, 36 * n)):
+                                    ("update_mix", 3, 36 * n), ("copy_nt", 4, 2 * 8 * n), ("read_nt", 5, 8 * n),
+                                    ("update_mix_nt", 6, 36 * n), ("update_mix_nt_store", 7, 36 * n)):
         best = 0.0
         for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
-            a, b = (ru, cb) if kind == 3 else (dst, src)
+            a, b = (ru, cb) if kind in (3, 6, 7) else (dst, src)
             mgir.bandwidth_probe(a, b, kind, blocks)
             torch.cuda.synchronize()
             for _ in range(reps):
@@ -115,7 +118,46 @@ def bandwidth_ceiling(torch, mgir, reps=5):
                 best = max(best, bytes_moved / (e0.elapsed_time(e1) * 1e-3) / 1e9)
         out[name] = round(best, 1)
         log(f"[ceiling] {name}: {best:.0f} GB/s")
+    del src, dst, ru, cb
+    torch.cuda.empty_cache()
+    out["size_sweep"] = bandwidth_size_sweep(torch, mgir, reps)
     return out
+
+
+def bandwidth_size_sweep(torch, mgir, reps=5):
+    """Copy and read rates (GB/s, best launch shape, event-timed) of one
+    streaming launch over vectors of 1 MiB to 4 GiB: the analogue of the
+    paper's vector-length sweep of AXPY-like kernels (Section 8.2).  Small
+    vectors expose launch latency and the caches (the 256 MB Infinity Cache
+    holds the vectors up to about 128 MiB), large ones the HBM rate."""
+    dev = torch.device("cuda:0")
+    rows = []
+    for lg in range(20, 33):
+        nbytes = 1 << lg
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        row = {"bytes": nbytes}
+        for name, kind, moved in (("copy", 0, 2 * nbytes), ("read", 1, nbytes)):
+            best_ms = 1e30
+            for blocks in (256, 1024, 4096, 16384):
+                if blocks * 256 * 16 > 4 * nbytes and blocks > 256:
+                    continue
+                mgir.bandwidth_probe(dst, src, kind, blocks)
+                torch.cuda.synchronize()
+                for _ in range(reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    mgir.bandwidth_probe(dst, src, kind, blocks)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    best_ms = min(best_ms, e0.elapsed_time(e1))
+            row[name] = round(moved / (best_ms * 1e-3) / 1e9, 1)
+            row[name + "_us"] = round(best_ms * 1e3, 2)
+        log(f"[ceiling] {nbytes >> 20} MiB: copy {row['copy']:.0f} GB/s, read {row['read']:.0f} GB/s")
+        rows.append(row)
+        del src, dst
+        torch.cuda.empty_cache()
+    return rows
 
 
 def host_cpu_model():
@@ -188,10 +230,12 @@ def config_sweep(torch, mgir, W, oracle, dev, steps, tune, defer, cfg3=None):
     return res
 
 
-def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=True):
+def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=True, defer=0):
     """Throughput of the batched and many-right-hand-side solves (FP16 V-cycles
     and the FP64 solve of the same problems), and the paper's other precision
-    variants on the main problem, each with inputs resident in HBM."""
+    variants on the main problem, each with inputs resident in HBM.  Maps with
+    a narrow finest level postpone the solution update over `defer` steps, as
+    the headline solve does."""
     res = {}
     if bt is not None:
         # Table 2's variants beside the main FP16 map: all-FP16 including the
@@ -199,7 +243,8 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
         # the residual rescaled into the FP16 levels (DSH)
         L = W.levels_for(n)
         entry = {}
-        for name, kw in (("h_mg", {}), ("hsd", {}), ("dsh", {"rescale_half": True})):
+        dk = {"defer_update": defer} if defer else {}
+        for name, kw in (("h_mg", dk), ("hsd", dk), ("dsh", {"rescale_half": True})):
             log(f"[bench] variant {name} at {n}^3")
             s = mgir.Solver(3, n, W.precision_map(name, L), device=dev, autotune=tune, **kw)
             u0 = torch.zeros_like(bt)
@@ -211,7 +256,8 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) / steps * 1e3
             entry[name] = {"ms": ms, "iterations": r.iterations, "rel_residual": r.rel_residual,
-                           "status": r.status, "rescale_half": bool(kw), "map": W.precision_map(name, L)}
+                           "status": r.status, "rescale_half": name == "dsh", "defer_update": kw.get("defer_update", 0),
+                           "map": W.precision_map(name, L)}
             if ms64:
                 entry[name]["speedup_vs_f64"] = ms64 / ms
             del s
@@ -222,7 +268,7 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
         # random initial guess in [0, 1] (Section 6), FP16 map against FP64
         u0 = torch.from_numpy(W.random_initial_guess(3, n, seed=11)).to(dev)
         solvers = {"f16": mgir.Solver(3, n, W.precision_map("f16", L), device=dev, autotune=tune,
-                                      use_initial_guess=True),
+                                      use_initial_guess=True, **dk),
                    "f64": mgir.Solver(3, n, W.precision_map("f64", L), residual_scaling=False, device=dev,
                                       autotune=tune, use_initial_guess=True)}
         entry = {}
@@ -254,7 +300,7 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
         for name, m in (("f16", 2), ("f16", 3), ("f64", 2)):
             log(f"[bench] {m} V-cycles per step, map {name}")
             s = mgir.Solver(3, n, W.precision_map(name, L), residual_scaling=name != "f64", device=dev,
-                            autotune=tune, cycles_per_step=m)
+                            autotune=tune, cycles_per_step=m, **(dk if name != "f64" else {}))
             u0 = torch.zeros_like(bt)
             s.solve(bt, u0)
             torch.cuda.synchronize()
@@ -272,13 +318,14 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
         res[f"cycles_per_step_{n}"] = entry
 
         # partial hierarchies ending on a multi-point base level solved by CG
-        # to the paper's absolute 1e-4 (its grids coarsen to such a base)
+        # to 1e-4 relative to the base right-hand side (the paper's 1e-4 holds
+        # for residuals scaled to norm one; its grids coarsen to such a base)
         entry = {}
         for name, nl in (("f16", L - 3), ("f64", L - 3), ("f16", L - 2)):
             nb = (n + 1) // 2 ** (nl - 1) - 1
             log(f"[bench] {nl} levels, CG on {nb}^3, map {name}")
             s = mgir.Solver(3, n, W.precision_map(name, nl), residual_scaling=name != "f64", device=dev,
-                            autotune=tune, nlevels=nl)
+                            autotune=tune, nlevels=nl, **(dk if name != "f64" else {}))
             u0 = torch.zeros_like(bt)
             s.solve(bt, u0)
             torch.cuda.synchronize()
@@ -385,7 +432,7 @@ def main():
                     help="only measure the streaming bandwidth ceilings (copy, read, write, update mix)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-instances and many-right-hand-sides measurements")
-    ap.add_argument("--defer", type=int, default=8,
+    ap.add_argument("--defer", type=int, default=32,
                     help="also time the mixed solve with the solution update postponed over this many steps "
                          "(0: only the per-step update); the faster one is the headline")
     ap.add_argument("--no-configs", action="store_true",
@@ -578,7 +625,8 @@ def main():
             out["configs"] = {"poisson3d_511_sine_noise": cfg3}
         del u64
     if not args.no_extra and not args.profile_only:
-        out["extra"] = extra_workloads(torch, mgir, W, dev, args.steps, bt=bt, n=n, ms64=ms64, tune=tune)
+        out["extra"] = extra_workloads(torch, mgir, W, dev, args.steps, bt=bt, n=n, ms64=ms64, tune=tune,
+                                       defer=best_depth)
     if not args.no_cpu_baseline and not args.profile_only:
         import oracle
         oracle.build(native=True)

@@ -87,7 +87,12 @@ typedef struct {
     double rtol;             /* stop when ||r||_2 <= rtol * ||b||_2 (FP64), default 1e-10 */
     int use_initial_guess;   /* 0: ir_solve starts from u = 0 (default); 1: from the given u */
     int use_graph;           /* 1: replay one captured HIP graph per refinement step (default) */
-    int autotune;            /* 1: time launch shapes at mg_bind_workspace (synchronises) */
+    int autotune;            /* 1: time launch shapes at mg_bind_workspace (synchronises).
+                                When the environment variable MGIR_TUNE_CACHE names a
+                                file, the chosen shapes are appended to it under a key
+                                of device architecture, CU count, grid, level formats
+                                and the kernel-changing options, and a later handle of
+                                the same key reads them back instead of timing. */
     int rescale_half;        /* 1: every restriction into an FP16 or BF16 level keeps the
                                 restricted residual t in the finer level's accumulator
                                 format, takes s = max|t| and stores round(t / s); the
@@ -407,9 +412,11 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int npar
  * `blocks` blocks of 256 threads in a grid-stride loop.  Kind 3 streams the
  * access mix of the refinement update: dst holds two FP64 arrays of `bytes`
  * each (read and written), src two FP16 arrays of bytes/4 each (read), 36
- * bytes per element; bytes a multiple of 32.  Used to measure the achievable
- * HBM bandwidth and to calibrate traffic counters.  For kind 1 the first 4
- * bytes of dst may be written.  Async. */
+ * bytes per element; bytes a multiple of 32.  Kinds 4, 5 are kinds 0, 1 with
+ * non-temporal loads and stores; kind 6 is kind 3 with non-temporal loads and
+ * stores, kind 7 with non-temporal stores only.  Used to measure the
+ * achievable HBM bandwidth and to calibrate traffic counters.  For kinds 1 and
+ * 5 the first 4 bytes of dst may be written.  Async. */
 mg_status_t mg_bandwidth_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, void *stream);
 
 /* Run one refinement step eagerly with a HIP event pair around every kernel

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -858,7 +859,132 @@ std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool 
     return out;
 }
 
+// ---- persisted tuning -------------------------------------------------------
+// With MGIR_TUNE_CACHE naming a file, the shapes the autotuner picked are
+// appended to it as one line per configuration, and a later mg_bind_workspace
+// with the same configuration on the same kind of device reads them back
+// instead of timing again.  The key holds everything the choice depends on:
+// device architecture and CU count, the library's tuning version, dimension,
+// grid, level formats and the options that change the kernels.
+constexpr int kTuneVersion = 3;
+
+std::string tune_key(const mg_ctx *h) {
+    int dev = 0, cus = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    char buf[512];
+    int k = std::snprintf(buf, sizeof buf, "v%d|%s|cu%d|d%d|n%d|L%d|nu%d,%d|sc%d|df%d|rh%d|cy%d|p", kTuneVersion,
+                          prop.gcnArchName, cus, h->dim, h->n, h->nl, h->opt.nu1, h->opt.nu2,
+                          h->opt.residual_scaling, h->opt.defer_update, h->opt.rescale_half, h->opt.cycles_per_step);
+    for (int l = 0; l < h->nl && k < (int)sizeof buf - 4; ++l) k += std::snprintf(buf + k, sizeof buf - k, "%d", h->lv[l].prec);
+    return std::string(buf);
+}
+
+// The tuned state as integers: per level the three stencil shapes, the
+// update shape, the restriction shape and the coarse fused form; then the
+// finest-level fused forms.
+void tune_state(const mg_ctx *h, std::vector<int> &v) {
+    auto sh = [&](const Shape &s) { v.insert(v.end(), {s.V, s.zc, s.bs, s.xcd, s.ty, s.dp}); };
+    auto rs = [&](const RShape &r) { v.insert(v.end(), {r.V, r.tyc, r.zcc, r.pipe}); };
+    for (int l = 0; l + 1 < h->nl; ++l) {
+        const LevelPlan &L = h->lv[l];
+        for (int f = 0; f < 3; ++f) sh(L.shs[f]);
+        sh(L.osh);
+        rs(L.rsh);
+        rs(L.fsrsh);
+        v.push_back(L.fsr ? 1 : 0);
+    }
+    rs(h->srsh);
+    v.push_back(h->fused_sr ? 1 : 0);
+    sh(h->fsh);
+    v.push_back(h->fused ? 1 : 0);
+}
+
+// Apply a state read from the cache; false (and nothing changed) when any
+// shape is not valid for this handle.
+bool apply_tune_state(mg_ctx *h, const std::vector<int> &v) {
+    const size_t per = 4 * 6 + 4 + 4 + 1, need = per * (h->nl - 1) + 4 + 1 + 6 + 1;
+    if (v.size() != need) return false;
+    size_t i = 0;
+    auto sh = [&]() { Shape s{v[i], v[i + 1], v[i + 2], v[i + 3], v[i + 4], v[i + 5]}; i += 6; return s; };
+    auto rs = [&]() { RShape r{v[i], v[i + 1], v[i + 2], v[i + 3]}; i += 4; return r; };
+    std::vector<LevelPlan> lv = h->lv;
+    std::vector<bool> fsr(h->nl, false);
+    for (int l = 0; l + 1 < h->nl; ++l) {
+        LevelPlan &L = lv[l];
+        for (int f = 0; f < 3; ++f) {
+            L.shs[f] = sh();
+            if (!stencil_ok(h, L, L.shs[f])) return false;
+        }
+        L.osh = sh();
+        if (l == 0 && (!stencil_ok(h, L, L.osh) || stencil_blocks(h->dim, L.P, L.osh) > h->max_parts)) return false;
+        L.rsh = rs();
+        if (!restrict_ok(h, L, L.rsh)) return false;
+        L.fsrsh = rs();
+        fsr[l] = v[i++] != 0;
+    }
+    const RShape srsh = rs();
+    const bool fused_sr = v[i++] != 0;
+    const Shape fsh = sh();
+    const bool fused = v[i++] != 0;
+    h->lv = lv;
+    for (int l = 1; l + 1 < h->nl; ++l) set_fused_srb(h, l, fsr[l]);
+    h->srsh = srsh;
+    set_fused_sr(h, fused_sr);
+    h->fsh = fsh;
+    set_fused(h, fused);
+    return true;
+}
+
+bool tune_cache_load(mg_ctx *h, const std::string &key) {
+    const char *path = std::getenv("MGIR_TUNE_CACHE");
+    if (!path || !*path || key.empty()) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[8192];
+    bool ok = false;
+    while (!ok && std::fgets(line, sizeof line, f)) {
+        char *tab = std::strchr(line, '\t');
+        if (!tab || std::string(line, tab - line) != key) continue;
+        std::vector<int> v;
+        for (char *p = tab + 1; *p && *p != '\n';) {
+            char *end = nullptr;
+            const long x = std::strtol(p, &end, 10);
+            if (end == p) break;
+            v.push_back((int)x);
+            p = end;
+        }
+        ok = apply_tune_state(h, v);
+    }
+    std::fclose(f);
+    return ok;
+}
+
+void tune_cache_store(const mg_ctx *h, const std::string &key) {
+    const char *path = std::getenv("MGIR_TUNE_CACHE");
+    if (!path || !*path || key.empty()) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::vector<int> v;
+    tune_state(h, v);
+    std::fprintf(f, "%s\t", key.c_str());
+    for (size_t i = 0; i < v.size(); ++i) std::fprintf(f, i ? " %d" : "%d", v[i]);
+    std::fprintf(f, "\n");
+    std::fclose(f);
+}
+
+mg_status_t autotune_timed(mg_ctx *h, hipStream_t st);
+
 mg_status_t autotune(mg_ctx *h, hipStream_t st) {
+    const std::string key = tune_key(h);
+    if (tune_cache_load(h, key)) return MG_OK;
+    const mg_status_t s = autotune_timed(h, st);
+    if (s == MG_OK) tune_cache_store(h, key);
+    return s;
+}
+
+mg_status_t autotune_timed(mg_ctx *h, hipStream_t st) {
     const int D = h->dim;
     for (int l = 0; l + 1 < h->nl; ++l) {
         LevelPlan &L = h->lv[l];
@@ -1709,8 +1835,9 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
 }
 
 mg_status_t mg_bandwidth_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, void *stream) {
-    if (!dst || !src || kind < 0 || kind > 3 || blocks < 1) return fail(MG_ERR_ARG, "bad argument");
-    if (bytes % (kind == 3 ? 32 : 16)) return fail(MG_ERR_ARG, "bytes must be a multiple of 16 (32 for kind 3)");
+    if (!dst || !src || kind < 0 || kind > 7 || blocks < 1) return fail(MG_ERR_ARG, "bad argument");
+    const bool mix = kind == 3 || kind == 6 || kind == 7;
+    if (bytes % (mix ? 32 : 16)) return fail(MG_ERR_ARG, "bytes must be a multiple of 16 (32 for the update mix)");
     HIPCHK(launch_probe(dst, src, bytes, kind, blocks, static_cast<unsigned *>(dst), static_cast<hipStream_t>(stream)));
     return MG_OK;
 }

@@ -178,6 +178,47 @@ template <class T, int V> __device__ __forceinline__ void load_raw(const T *__re
 
 template <class T> __device__ __forceinline__ T zero_of() { return Store<T>::from_acc(acc_t<T>(0)); }
 
+// ---------------------------------------------------------------------------
+// Rows of values staged in LDS where thread t of a row holds the V values
+// t V .. t V + V - 1.  Stored chunk-major: chunk j (C values, 16 bytes) of
+// thread t sits at (j TXR + t) C, TXR the threads of a row, so the 16-byte
+// accesses of a wave's lanes land on consecutive banks.  (Stored thread-major,
+// lanes V sizeof(A) bytes apart, a 16-byte access of a wave touches each bank
+// V sizeof(A) / 16 times.)  The arithmetic that uses the values is unchanged.
+template <class A, int V> struct LdsRun {
+    static constexpr int C = (16 / (int)sizeof(A)) < V ? 16 / (int)sizeof(A) : V;
+    static constexpr int NC = V / C;
+    static_assert(V % C == 0, "whole chunks per thread");
+    // position of element x of the row
+    __device__ __forceinline__ static int at(int x, int TXR) {
+        const int t = x / V, i = x - t * V;
+        return ((i / C) * TXR + t) * C + (i % C);
+    }
+    template <class S> __device__ __forceinline__ static void store(A *row, int t, int TXR, const S (&v)[V]) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            A c[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) c[i] = (A)v[j * C + i];
+            store_row<A, C>(row + (size_t)(j * TXR + t) * C, c);
+        }
+    }
+    template <class O> __device__ __forceinline__ static void load(const A *row, int t, int TXR, O (&v)[V]) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            O c[C];
+            load_row<A, C>(row + (size_t)(j * TXR + t) * C, c);
+#pragma unroll
+            for (int i = 0; i < C; ++i) v[j * C + i] = c[i];
+        }
+    }
+    // the last value of thread t - 1 and the first of thread t + 1
+    __device__ __forceinline__ static A left_of(const A *row, int t, int TXR) {
+        return row[((NC - 1) * TXR + t - 1) * C + C - 1];
+    }
+    __device__ __forceinline__ static A right_of(const A *row, int t, int TXR) { return row[(size_t)(t + 1) * C]; }
+};
+
 // A prefetched row kept packed in its storage format (e.g. eight FP16 values
 // in four 32-bit registers) until it is widened.
 template <class T, int V> struct RawRow {

@@ -791,6 +791,7 @@ __device__ __forceinline__ void march_body(const F &f_in, const E &e, int P, int
                                            long pidx, unsigned char *smem_raw, double *red) {
     typedef typename F::acc A;
     typedef typename F::lds_t LT;
+    typedef LdsRun<LT, V> LR;  // LDS rows, chunk-major
     LT *lds = reinterpret_cast<LT *>(smem_raw);
     const Grid<3> g{P};
     const int TXR = P / V;
@@ -828,7 +829,7 @@ __device__ __forceinline__ void march_body(const F &f_in, const E &e, int P, int
         LT t[V];
 #pragma unroll
         for (int i = 0; i < V; ++i) t[i] = store_as<LT>(cc[i]);
-        store_row<LT, V>(lds + (size_t)gi * P + x0, t);
+        LR::store(lds + (size_t)gi * P, xc, TXR, t);
     }
     // queues: fq[d] holds field plane z + 1 + d, eq[d] the emit rows of plane z + d
 #pragma unroll
@@ -857,13 +858,13 @@ __device__ __forceinline__ void march_body(const F &f_in, const E &e, int P, int
             const LT *S = lds + (size_t)(it & 1) * slot;
             const LT *row = S + (size_t)gi * P;
             A nb[V];
-            const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
-            const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+            const A xl = x0 > 0 ? (A)widen(LR::left_of(row, xc, TXR)) : A(0);
+            const A xr = x0 + V < P ? (A)widen(LR::right_of(row, xc, TXR)) : A(0);
 #pragma unroll
             for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cc[i - 1] : xl) + (i < V - 1 ? cc[i + 1] : xr);
             A ym[V], yp[V];
-            load_row<LT, V>(row - P + x0, ym);
-            load_row<LT, V>(row + P + x0, yp);
+            LR::load(row - P, xc, TXR, ym);
+            LR::load(row + P, xc, TXR, yp);
 #pragma unroll
             for (int i = 0; i < V; ++i) {
                 nb[i] += ym[i];
@@ -877,7 +878,7 @@ __device__ __forceinline__ void march_body(const F &f_in, const E &e, int P, int
             LT t[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) t[i] = store_as<LT>(cp[i]);
-            store_row<LT, V>(lds + (size_t)((it + 1) & 1) * slot + (size_t)gi * P + x0, t);
+            LR::store(lds + (size_t)((it + 1) & 1) * slot + (size_t)gi * P, xc, TXR, t);
         }
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -1308,6 +1309,76 @@ __global__ __launch_bounds__(256) void k_resid_rows(const double *__restrict__ b
     }
 }
 
+// The same residual in 3-D, marching z: a tile is four consecutive rows y (one
+// wave each, lane l on x = l + 64 k) and a chunk of zc planes.  Each lane keeps
+// U of its points on planes z-1, z, z+1 in registers, so a plane of U is read
+// from HBM once, when it becomes plane z+1; the y neighbours are the rows the
+// waves beside it read at the same plane (cache hits), the x neighbours lie in
+// the row the wave has just read.  Tiles are dealt to the XCDs in contiguous
+// ranges (neighbouring y bands share an L2).  Blocks loop over tiles
+// (gridDim.x may be below the tile count); one partial per block.
+template <int KX>
+__global__ __launch_bounds__(256) void k_resid_march(const double *__restrict__ b, const double *__restrict__ U,
+                                                     double *__restrict__ R, double *__restrict__ uout, int n, int P,
+                                                     double inv_h2, double *__restrict__ part, int ytiles, int zc,
+                                                     int ntiles) {
+    __shared__ double red[8];
+    const Grid<3> g{P};
+    const size_t plane = (size_t)P * P;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double ss = 0.0, mx = 0.0;
+    for (int t = xcd_block(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
+        const int y = 1 + (t % ytiles) * 4 + w;
+        const int z0 = 1 + (t / ytiles) * zc, z1 = min(z0 + zc, n + 1);
+        if (y > n) continue;
+        double um[KX], uc[KX], up[KX];
+        // planes z0 - 1 and z0 (plane 0 is a zero ghost)
+#pragma unroll
+        for (int k = 0; k < KX; ++k) {
+            const int x = lane + 64 * k;
+            const bool in = x < n;
+            um[k] = in ? U[g.at(1 + x, y, z0 - 1)] : 0.0;
+            uc[k] = in ? U[g.at(1 + x, y, z0)] : 0.0;
+        }
+        for (int z = z0; z < z1; ++z) {
+            const size_t dbase = ((size_t)(z - 1) * n + (y - 1)) * n;
+            const size_t pbase = g.at(1, y, z);
+#pragma unroll
+            for (int k = 0; k < KX; ++k) {
+                const int x = lane + 64 * k;
+                if (x < n) up[k] = U[pbase + plane + x];  // plane z+1 (plane n+1 is a zero ghost)
+            }
+#pragma unroll
+            for (int k = 0; k < KX; ++k) {
+                const int x = lane + 64 * k;
+                if (x < n) {
+                    const size_t p = pbase + x;
+                    double nb = U[p - 1] + U[p + 1];
+                    nb += U[p - P];
+                    nb += U[p + P];
+                    nb += um[k];
+                    nb += up[k];
+                    const double r = b[dbase + x] - (6.0 * uc[k] - nb) * inv_h2;
+                    if (uout) uout[dbase + x] = uc[k];
+                    if (R) R[p] = r;
+                    ss += r * r;
+                    mx = nanmax(mx, fabs(r));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < KX; ++k) {
+                um[k] = uc[k];
+                uc[k] = up[k];
+            }
+        }
+    }
+    block_reduce(ss, mx, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss;
+        part[2 * blockIdx.x + 1] = mx;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ part, int nparts, double *__restrict__ scal,
                                                   int scaling, int *__restrict__ ctr) {
     __shared__ double red[8];
@@ -1380,56 +1451,70 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4 *__restrict__ p, size_t
 
 // Bandwidth probe: copy, read-only (sum kept live) or write-only passes over
 // 16-byte lanes; each thread handles `per` consecutive lanes per grid sweep.
-__global__ __launch_bounds__(256) void k_probe(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16,
+// 16-byte vector types for the probes' non-temporal accesses
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT, class V> __device__ __forceinline__ V ld_nt(const V *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, class V> __device__ __forceinline__ void st_nt(V *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Bandwidth probe: copy, read-only (sum kept live) or write-only passes over
+// 16-byte lanes in a grid-stride loop; NT: non-temporal loads and stores.
+template <bool NT>
+__global__ __launch_bounds__(256) void k_probe(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src, size_t n16,
                                               int kind, unsigned *__restrict__ sink) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     uint32_t acc = 0;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
         if (kind == 0) {
-            dst[i] = src[i];
+            st_nt<NT>(dst + i, ld_nt<NT>(src + i));
         } else if (kind == 1) {
-            const uint4 v = src[i];
+            const u32x4 v = ld_nt<NT>(src + i);
             acc ^= v.x ^ v.y ^ v.z ^ v.w;
         } else {
-            dst[i] = make_uint4((uint32_t)i, 0u, 0u, 0u);
+            u32x4 v = {(uint32_t)i, 0u, 0u, 0u};
+            st_nt<NT>(dst + i, v);
         }
     }
     if (kind == 1 && acc == 0x9e3779b9u) sink[0] = acc;  // keeps the loads live
 }
 
-// The access mix of the fused last sweep + update without its stencil: per
-// point, read two FP16 values (c, b) and read and write two FP64 values (R, U),
-// 36 bytes; four points per thread, as the update's rows.
+// The refinement update's access mix: two FP64 arrays read and written, two
+// FP16 arrays read, four elements per thread and step.  NTL / NTS:
+// non-temporal loads / stores.
+template <bool NTL, bool NTS>
 __global__ __launch_bounds__(256) void k_probe_update(double *__restrict__ R, double *__restrict__ U,
                                                       const f16 *__restrict__ c, const f16 *__restrict__ b,
                                                       size_t n4) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-        RawRow<double, 4> r, u;
-        RawRow<f16, 4> cr, br;
-        fetch_row<double, 4>(R + 4 * i, r);
-        fetch_row<double, 4>(U + 4 * i, u);
-        fetch_row<f16, 4>(c + 4 * i, cr);
-        fetch_row<f16, 4>(b + 4 * i, br);
-        double rv[4], uv[4];
-        float cv[4], bv[4];
-        widen_row<double, 4>(r, rv);
-        widen_row<double, 4>(u, uv);
-        widen_row<f16, 4>(cr, cv);
-        widen_row<f16, 4>(br, bv);
+        f64x2 *r2 = reinterpret_cast<f64x2 *>(R + 4 * i);
+        f64x2 *u2 = reinterpret_cast<f64x2 *>(U + 4 * i);
+        const f64x2 r0 = ld_nt<NTL>(r2), r1 = ld_nt<NTL>(r2 + 1);
+        const f64x2 u0 = ld_nt<NTL>(u2), u1 = ld_nt<NTL>(u2 + 1);
+        const f16x4 cv = ld_nt<NTL>(reinterpret_cast<const f16x4 *>(c + 4 * i));
+        const f16x4 bv = ld_nt<NTL>(reinterpret_cast<const f16x4 *>(b + 4 * i));
+        double rv[4] = {r0.x, r0.y, r1.x, r1.y}, uv[4] = {u0.x, u0.y, u1.x, u1.y};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            rv[j] = fmaT<double>(-(double)cv[j], (double)bv[j], rv[j]);
-            uv[j] += (double)cv[j];
+            const double cj = (double)(float)cv[j], bj = (double)(float)bv[j];
+            rv[j] = fmaT<double>(-cj, bj, rv[j]);
+            uv[j] += cj;
         }
-        store_row<double, 4>(R + 4 * i, rv);
-        store_row<double, 4>(U + 4 * i, uv);
+        st_nt<NTS>(r2, f64x2{rv[0], rv[1]});
+        st_nt<NTS>(r2 + 1, f64x2{rv[2], rv[3]});
+        st_nt<NTS>(u2, f64x2{uv[0], uv[1]});
+        st_nt<NTS>(u2 + 1, f64x2{uv[2], uv[3]});
     }
 }
 
-// ===========================================================================
-// Host launchers.
-// ===========================================================================
 static int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 static int stencil_chunks(int P, int zc) { return ceil_div(P - 1, zc); }
@@ -1768,9 +1853,28 @@ hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double 
                              double inv_h2, double *part, hipStream_t st) {
     const long N = D == 3 ? (long)n * n * n : (long)n * n;
     const int blocks = flat_blocks(N);
-    if (D == 3)
-        hipLaunchKernelGGL(k_resid_rows<3>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, part);
-    else
+    if (D == 3) {
+        // y bands of four rows; z chunks so that the tiles about fill the blocks
+        const int ytiles = (n + 3) / 4;
+        const int nzparts = std::max(1, (blocks + ytiles - 1) / ytiles);
+        const int zc = std::max(1, (n + nzparts - 1) / nzparts);
+        const int ntiles = ytiles * ((n + zc - 1) / zc);
+        if (U) {
+            // lane l holds x = l + 64 k, k < KX
+            const int kx = (n + 63) / 64;
+#define MG_RM(KX)                                                                                                  \
+    hipLaunchKernelGGL(k_resid_march<KX>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, part, ytiles, \
+                       zc, ntiles)
+            if (kx <= 1) MG_RM(1);
+            else if (kx <= 2) MG_RM(2);
+            else if (kx <= 4) MG_RM(4);
+            else if (kx <= 8) MG_RM(8);
+            else MG_RM(16);
+#undef MG_RM
+        } else {
+            hipLaunchKernelGGL(k_resid_rows<3>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, part);
+        }
+    } else
         hipLaunchKernelGGL(k_resid_rows<2>, dim3(blocks), dim3(256), 0, st, b, U, R, uout, n, P, inv_h2, part);
     return hipGetLastError();
 }
@@ -1840,16 +1944,29 @@ hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int 
                         hipStream_t st) {
     if (bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
         return hipErrorInvalidValue;
-    if (kind == 3) {
+    if (kind == 3 || kind == 6 || kind == 7) {
         // dst: R and U, bytes each; src: c and b, bytes / 4 each (FP16)
+        if (bytes % 32) return hipErrorInvalidValue;
         double *R = static_cast<double *>(dst);
         const f16 *c = static_cast<const f16 *>(src);
-        hipLaunchKernelGGL(k_probe_update, dim3((unsigned)blocks), dim3(256), 0, st, R, R + bytes / 8, c,
-                           c + bytes / 8, bytes / 32);
+        if (kind == 3)
+            hipLaunchKernelGGL((k_probe_update<false, false>), dim3((unsigned)blocks), dim3(256), 0, st, R,
+                               R + bytes / 8, c, c + bytes / 8, bytes / 32);
+        else if (kind == 6)
+            hipLaunchKernelGGL((k_probe_update<true, true>), dim3((unsigned)blocks), dim3(256), 0, st, R,
+                               R + bytes / 8, c, c + bytes / 8, bytes / 32);
+        else
+            hipLaunchKernelGGL((k_probe_update<false, true>), dim3((unsigned)blocks), dim3(256), 0, st, R,
+                               R + bytes / 8, c, c + bytes / 8, bytes / 32);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_probe, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint4 *>(dst),
-                       static_cast<const uint4 *>(src), bytes / 16, kind, sink);
+    if (kind < 0 || kind > 5) return hipErrorInvalidValue;
+    if (kind >= 3)
+        hipLaunchKernelGGL(k_probe<true>, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<u32x4 *>(dst),
+                           static_cast<const u32x4 *>(src), bytes / 16, kind - 3, sink);
+    else
+        hipLaunchKernelGGL(k_probe<false>, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<u32x4 *>(dst),
+                           static_cast<const u32x4 *>(src), bytes / 16, kind, sink);
     return hipGetLastError();
 }
 

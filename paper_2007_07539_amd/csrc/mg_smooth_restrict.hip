@@ -20,7 +20,9 @@
 // double-buffered LDS slots (in the accumulator format: FP32, up to 104 KB at
 // P = 512, or FP64 for an FP64 level, 124 KB at P = 512 with one coarse row
 // per tile; gfx950 allows one workgroup 160 KB), each written after the
-// iteration's barrier and not read again before the next one.  The arithmetic is that of the
+// iteration's barrier and not read again before the next one.  LDS rows are
+// stored chunk-major (LdsRun) so that the wave's 16-byte accesses do not
+// conflict.  The arithmetic is that of the
 // separate kernels, operation for operation, so results are bitwise equal.
 #include "mg_device.h"
 #include "mg_launch.h"
@@ -44,6 +46,8 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
                                                           int zcc, int ytiles, double omega, int xcd) {
     constexpr int V = 8, VC = 4;
     typedef acc_t<T> A;
+    typedef LdsRun<A, V> LR;    // fine rows in LDS, chunk-major
+    typedef LdsRun<A, VC> LRC;  // x-weighted residual rows
     typedef typename std::conditional<SCALED, double, T>::type S;  // source format
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = 2 * tyc + 5, RR = 2 * tyc + 1, RW = P / 2;
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
         fetch_r(tb + 1, t0);
         scaled(t0, braw, bB);
         first(bB, kB);
-        store_row<A, V>(c1s + (size_t)((tb + 1) & 1) * cslot + (size_t)gi * P + x0, kB);
+        LR::store(c1s + (size_t)((tb + 1) & 1) * cslot + (size_t)gi * P, xc, TXR, kB);
         fetch_r(tb + 2, rnext);
     }
 
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
         const bool last_of_z = j > 0 && (j & 1) == 0;  // zf = 2Z + 1
         A xs[3][VC];
 #pragma unroll
-        for (int oy = 0; oy < 3; ++oy) load_row<A, VC>(rb + (size_t)(2 * gi + oy) * RW + X0, xs[oy]);
+        for (int oy = 0; oy < 3; ++oy) LRC::load(rb + (size_t)(2 * gi + oy) * RW, xc, TXR, xs[oy]);
         TC out[VC];
 #pragma unroll
         for (int jx = 0; jx < VC; ++jx) {
@@ -194,13 +198,13 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
             if (row_in && p >= 1 && p <= P - 1) {
                 const A *row = c1s + (size_t)(p & 1) * cslot + (size_t)gi * P;
                 A nb[V];
-                const A xl = x0 > 0 ? row[x0 - 1] : A(0);
-                const A xr = x0 + V < P ? row[x0 + V] : A(0);
+                const A xl = x0 > 0 ? LR::left_of(row, xc, TXR) : A(0);
+                const A xr = x0 + V < P ? LR::right_of(row, xc, TXR) : A(0);
 #pragma unroll
                 for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? k1[i - 1] : xl) + (i < V - 1 ? k1[i + 1] : xr);
                 A ym[V], yp[V];
-                load_row<A, V>(row - P + x0, ym);
-                load_row<A, V>(row + P + x0, yp);
+                LR::load(row - P, xc, TXR, ym);
+                LR::load(row + P, xc, TXR, yp);
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
                     nb[i] += ym[i];
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
 #pragma unroll
                 for (int i = 0; i < V; ++i) craw[i] = zero_of<T>(), c2[i] = A(0);
             }
-            store_row<A, V>(c2s + (size_t)(p & 1) * cslot + (size_t)gi * P + x0, c2);
+            LR::store(c2s + (size_t)(p & 1) * cslot + (size_t)gi * P, xc, TXR, c2);
             if (own_row && own_plane(p)) store_row<T, V>(cout + at(p), craw);
         }
         // residual of plane t on rows gi = 2 .. G-3, x weights in the thread
@@ -225,13 +229,13 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
             if (res_row) {
                 const A *row = c2s + (size_t)(t & 1) * cslot + (size_t)gi * P;
                 A nb[V];
-                const A xl = x0 > 0 ? row[x0 - 1] : A(0);
-                const A xr = x0 + V < P ? row[x0 + V] : A(0);
+                const A xl = x0 > 0 ? LR::left_of(row, xc, TXR) : A(0);
+                const A xr = x0 + V < P ? LR::right_of(row, xc, TXR) : A(0);
 #pragma unroll
                 for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? c1[i - 1] : xl) + (i < V - 1 ? c1[i + 1] : xr);
                 A ym[V], yp[V];
-                load_row<A, V>(row - P + x0, ym);
-                load_row<A, V>(row + P + x0, yp);
+                LR::load(row - P, xc, TXR, ym);
+                LR::load(row + P, xc, TXR, yp);
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
                     nb[i] += ym[i];
@@ -255,10 +259,10 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
                 xq[j] = A(0.25) * (lm + r[2 * j + 1]) + A(0.5) * r[2 * j];
             }
             if (x0 == 0) xq[0] = A(0);
-            if (res_slot) store_row<A, VC>(rs + (size_t)(t & 1) * rslot + (size_t)(gi - 2) * RW + (x0 >> 1), xq);
+            if (res_slot) LRC::store(rs + (size_t)(t & 1) * rslot + (size_t)(gi - 2) * RW, xc, TXR, xq);
         }
         // c1 of plane t+2 for the next step's neighbours
-        store_row<A, V>(c1s + (size_t)((t + 2) & 1) * cslot + (size_t)gi * P + x0, k2);
+        LR::store(c1s + (size_t)((t + 2) & 1) * cslot + (size_t)gi * P, xc, TXR, k2);
     };
 
     for (int t = tb;;) {

@@ -25,7 +25,8 @@
 // the sweep runs one plane ahead on TY + 2 rows, which needs c on TY + 4
 // rows.  Thread row groups gi = 0 .. TY+3 hold fine rows y0-2+gi.  Per
 // iteration w the sweep produces c' of plane w+1 and the update consumes
-// plane w; c (plane w+1) and c' (plane w) sit in double-buffered LDS slots,
+// plane w; c (plane w+1) and c' (plane w) sit in double-buffered LDS slots
+// (rows chunk-major, LdsRun),
 // one barrier per iteration: every LDS slot written in an iteration is written
 // after its barrier and is not read again before the next one.  The arithmetic
 // is that of the separate sweep and update kernels, operation for operation.
@@ -46,6 +47,7 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
     int ytiles, int xcd) {
     static_assert(!ALIAS || sizeof(T) == 8, "the residual is the right-hand side only in FP64");
     typedef acc_t<T> A;
+    typedef LdsRun<T, V> LR;  // LDS rows, chunk-major
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[32];
     const int G = TY + 4;
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
         T st[V];
 #pragma unroll
         for (int i = 0; i < V; ++i) st[i] = Store<T>::from_acc(pc[i]);
-        store_row<T, V>(cs + (size_t)((wb + 1) & 1) * slot + (size_t)gi * P + x0, st);
+        LR::store(cs + (size_t)((wb + 1) & 1) * slot + (size_t)gi * P, xc, TXR, st);
         fetch_c(wb + 2, t);
         widen_row<T, V>(t, pp);
         fetch_c(wb + 3, cnext);
@@ -141,13 +143,13 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
             if (row_in && s >= 1 && s <= P - 1) {
                 const T *row = cs + (size_t)(s & 1) * slot + (size_t)gi * P;
                 A nb[V];
-                const A xl = x0 > 0 ? (A)widen(row[x0 - 1]) : A(0);
-                const A xr = x0 + V < P ? (A)widen(row[x0 + V]) : A(0);
+                const A xl = x0 > 0 ? (A)widen(LR::left_of(row, xc, TXR)) : A(0);
+                const A xr = x0 + V < P ? (A)widen(LR::right_of(row, xc, TXR)) : A(0);
 #pragma unroll
                 for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? pc[i - 1] : xl) + (i < V - 1 ? pc[i + 1] : xr);
                 A ym[V], yp[V], bv[V];
-                load_row<T, V>(row - P + x0, ym);
-                load_row<T, V>(row + P + x0, yp);
+                LR::load(row - P, xc, TXR, ym);
+                LR::load(row + P, xc, TXR, yp);
                 widen_row<T, V>(bcur, bv);
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
             }
 #pragma unroll
             for (int i = 0; i < V; ++i) fp[i] = (A)widen(o[i]);
-            store_row<T, V>(fs + (size_t)(s & 1) * slot + (size_t)gi * P + x0, o);
+            LR::store(fs + (size_t)(s & 1) * slot + (size_t)gi * P, xc, TXR, o);
         }
         // update of plane w = s - 1 on rows gi = 2 .. TY+1, c' of plane w in LDS
         if (w >= z0 && out_row) {
@@ -173,13 +175,13 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
             double cv[V], nb[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) cv[i] = (double)fc[i];
-            const double xl = x0 > 0 ? (double)widen(row[x0 - 1]) : 0.0;
-            const double xr = x0 + V < P ? (double)widen(row[x0 + V]) : 0.0;
+            const double xl = x0 > 0 ? (double)widen(LR::left_of(row, xc, TXR)) : 0.0;
+            const double xr = x0 + V < P ? (double)widen(LR::right_of(row, xc, TXR)) : 0.0;
 #pragma unroll
             for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? cv[i - 1] : xl) + (i < V - 1 ? cv[i + 1] : xr);
             double ym[V], yp[V];
-            load_row<T, V>(row - P + x0, ym);
-            load_row<T, V>(row + P + x0, yp);
+            LR::load(row - P, xc, TXR, ym);
+            LR::load(row + P, xc, TXR, yp);
             double r[V], u[V];
             widen_row<double, V>(rcur, r);
             if constexpr (!DEFER) widen_row<double, V>(ucur, u);
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
             T st[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) st[i] = Store<T>::from_acc(pp[i]);
-            store_row<T, V>(cs + (size_t)((s + 1) & 1) * slot + (size_t)gi * P + x0, st);
+            LR::store(cs + (size_t)((s + 1) & 1) * slot + (size_t)gi * P, xc, TXR, st);
         }
         // advance the queues
 #pragma unroll

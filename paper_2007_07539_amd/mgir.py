@@ -455,7 +455,7 @@ def bandwidth_probe(dst: torch.Tensor, src: torch.Tensor, kind: int, blocks: int
     16-byte lanes; kind 3: the update's access mix, dst = two FP64 arrays of N
     elements back to back, src = two FP16 arrays of N elements."""
     nbytes = src.numel() * src.element_size()
-    if kind == 3:
+    if kind in (3, 6, 7):
         nbytes = dst.numel() * dst.element_size() // 2
     _check(load().mg_bandwidth_probe(_dptr(dst), _dptr(src), nbytes, kind, blocks, _stream_ptr(stream)),
            "mg_bandwidth_probe")

@@ -80,6 +80,37 @@ def test_autotuned_solver_matches_default(dev):
     assert r0.iterations == r1.iterations and torch.equal(u0, u1)
 
 
+@pytest.mark.parametrize("name,scaling,defer", [("f16", True, 0), ("f64", False, 0), ("f16", True, 4)])
+def test_tuning_cache_round_trip(dev, tmp_path, monkeypatch, name, scaling, defer):
+    """With MGIR_TUNE_CACHE set, the first autotuned handle records its shapes
+    and a second one of the same configuration reads them back instead of
+    timing: same shapes, same fused forms, bitwise the same solve; a handle
+    of another configuration gets a line of its own."""
+    n = 63
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MGIR_TUNE_CACHE", str(path))
+    prec = W.precision_map(name, W.levels_for(n))
+    b64 = torch.from_numpy(W.uniform_rhs(3, n, seed=15)).to(dev)
+    kinds = (mgir.SHAPE_SMOOTH, mgir.SHAPE_SWEEP, mgir.SHAPE_PROLONG, mgir.SHAPE_RESTRICT, mgir.SHAPE_FUSE,
+             mgir.SHAPE_FUSE_SR)
+
+    def shapes(s):
+        return [s.get_shape(l, k) for l in range(s.nlevels - 1) for k in kinds if k in kinds[:4] or l == 0] + \
+            [s.get_shape(0, mgir.SHAPE_UPDATE)]
+
+    a = mgir.Solver(3, n, prec, residual_scaling=scaling, autotune=True, defer_update=defer)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    b = mgir.Solver(3, n, prec, residual_scaling=scaling, autotune=True, defer_update=defer)
+    assert path.read_text().splitlines() == lines  # read back, not tuned again
+    assert shapes(a) == shapes(b)
+    ua, ra = a.solve(b64)
+    ub, rb = b.solve(b64)
+    assert ra.iterations == rb.iterations and torch.equal(ua, ub)
+    mgir.Solver(3, 31, W.precision_map(name, W.levels_for(31)), residual_scaling=scaling, autotune=True)
+    assert len(path.read_text().splitlines()) == 2
+
+
 @pytest.mark.parametrize("name,n", [("f16", 7), ("f16", 63), ("f64", 31), ("f32", 15), ("bf16", 127), ("hsd", 255),
                                     ("h_mg", 63), ("f64", 127)])
 def test_fused_tail_bitwise(dev, name, n):

@@ -448,3 +448,17 @@ def _apply_np(v):
         lo[ax], hi[ax] = slice(0, -2), slice(2, None)
         out = out - p[tuple(lo)] - p[tuple(hi)]
     return out * (n + 1) ** 2
+
+
+def test_timing_build_matches_test_build(ref):
+    """The CPU baseline times the oracle built with -O3 -march=native; with
+    contraction off it computes the same iterates as the -O2 build the pins
+    check, bit for bit."""
+    from paper_2007_07539_amd import workloads as W
+    if not hasattr(ref, "build") or "native" not in ref.build.__code__.co_varnames:
+        pytest.skip("oracle copy without a timing build")
+    b = W.uniform_rhs(3, 31, seed=2)
+    a = ref.ir_solve(b, residual_scaling=False, recursive_residual=True)
+    n = ref.ir_solve(b, residual_scaling=False, recursive_residual=True, native=True)
+    assert a.iterations == n.iterations
+    np.testing.assert_array_equal(a.u, n.u)
