@@ -358,7 +358,10 @@ typedef enum {
                                kernel), xcd (0|1: keep neighbouring tiles on one XCD),
                                ty (3-D: 0 = register-queue kernel, > 0 = LDS-plane
                                kernel with ty output rows per block)[, dp (LDS-plane
-                               kernel: 1 or 2 planes loaded ahead; default 1)]} */
+                               kernel: 1 or 2 planes loaded ahead; default 1)[, sg
+                               (LDS-plane prolongation: 1 = stage the z-interpolated
+                               coarse plane in LDS where it fits, default; 0 = each row
+                               reads its coarse rows from memory)]]} */
     MG_SHAPE_RESTRICT = 1,  /* residual + restriction: {V (4|8), tyc (coarse rows per
                                block, 3-D), zcc (coarse planes per block), pipe (3-D:
                                1 = correction plane staged in LDS, next plane
@@ -389,7 +392,7 @@ typedef enum {
                                residual to a second array of the workspace and the
                                two swap roles every step.  Not used when nu2 < 2.
                                Reading returns whether it is in use and its shape. */
-    MG_SHAPE_FUSE_SR = 8    /* 3-D, level l below the base: {on (0|1)[, tyc, zcc]}.  When
+    MG_SHAPE_FUSE_SR = 8    /* 3-D, level l below the base: {on (0|1)[, tyc, zcc[, lds16]]}.  When
                                on, the level's first pre-smoothing (two sweeps from zero)
                                and the residual + restriction of its result run as one
                                kernel (same result).  Level 0: the finest level inside
@@ -400,8 +403,12 @@ typedef enum {
                                coarse row per tile at P = 512); level 0 reads the
                                scaled residual, or with an FP64 finest level and no
                                residual scaling the residual itself; not used into a
-                               rescaled level.  Reading returns whether it is in use and its
-                               shape. */
+                               rescaled level.  lds16 = 1 (FP16/BF16 levels) keeps the
+                               two sweeps' results in LDS in that 2-byte format instead of
+                               FP32 (exact: they are values of it), so that two workgroups
+                               fit a CU; three values set lds16 = 0.  Reading returns
+                               whether it is in use and its shape (lds16 as a fourth value
+                               when nparams >= 4). */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);

@@ -799,7 +799,7 @@ int level_prec_code(int p) { return p; }
 // choice changes speed only.  Workspace contents are scratch at this point.
 bool stencil_ok(const mg_ctx *h, const LevelPlan &L, const Shape &s) {
     if ((s.V != 4 && s.V != 8) || s.V > L.P || s.zc < 1 || s.zc > L.P - 1) return false;
-    if (s.dp < 1 || s.dp > 2 || (s.dp == 2 && s.ty == 0)) return false;
+    if (s.dp < 1 || s.dp > 2 || (s.dp == 2 && s.ty == 0) || (s.sg != 0 && s.sg != 1)) return false;
     if (s.ty > 0) {
         if (h->dim != 3) return false;
         if ((L.P / s.V) * (s.ty + 2) > 1024 || march_lds_bytes(L.P, s.ty, prec_bytes(L.prec)) > 65536) return false;
@@ -841,7 +841,9 @@ template <class F> float time_ms(hipStream_t st, F &&fn, int reps) {
     return best;
 }
 
-std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool update) {
+// prolong: the prolongation family, which also tries reading its coarse rows
+// from memory on the LDS-plane kernel (sg = 0)
+std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool update, bool prolong = false) {
     std::vector<Shape> out;
     const int tys[] = {0, 2, 4, 6, 10, 14};
     const int zcs[] = {2, 4, 8, 16, 32, 64};
@@ -849,11 +851,13 @@ std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool 
         for (int ty : tys)
             for (int zc : zcs) {
                 for (int dp = 1; dp <= (ty > 0 ? 2 : 1); ++dp) {
-                    Shape s{V, zc, 256, 1, ty, dp};
+                    for (int sg = 1; sg >= (prolong && ty > 0 ? 0 : 1); --sg) {
+                    Shape s{V, zc, 256, 1, ty, dp, sg};
                     if (ty == 0 && h->dim == 3 && zc < 8) continue;
                     if (update && V == 8 && ty > 0) continue;  // FP64 rows spill at V = 8
                     if (L.prec == P_F64 && V == 8 && ty > 0) continue;
                     if (stencil_ok(h, L, s)) out.push_back(s);
+                    }
                 }
             }
     return out;
@@ -866,7 +870,7 @@ std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool 
 // instead of timing again.  The key holds everything the choice depends on:
 // device architecture and CU count, the library's tuning version, dimension,
 // grid, level formats and the options that change the kernels.
-constexpr int kTuneVersion = 3;
+constexpr int kTuneVersion = 4;
 
 std::string tune_key(const mg_ctx *h) {
     int dev = 0, cus = 0;
@@ -885,7 +889,7 @@ std::string tune_key(const mg_ctx *h) {
 // update shape, the restriction shape and the coarse fused form; then the
 // finest-level fused forms.
 void tune_state(const mg_ctx *h, std::vector<int> &v) {
-    auto sh = [&](const Shape &s) { v.insert(v.end(), {s.V, s.zc, s.bs, s.xcd, s.ty, s.dp}); };
+    auto sh = [&](const Shape &s) { v.insert(v.end(), {s.V, s.zc, s.bs, s.xcd, s.ty, s.dp, s.sg}); };
     auto rs = [&](const RShape &r) { v.insert(v.end(), {r.V, r.tyc, r.zcc, r.pipe}); };
     for (int l = 0; l + 1 < h->nl; ++l) {
         const LevelPlan &L = h->lv[l];
@@ -904,10 +908,14 @@ void tune_state(const mg_ctx *h, std::vector<int> &v) {
 // Apply a state read from the cache; false (and nothing changed) when any
 // shape is not valid for this handle.
 bool apply_tune_state(mg_ctx *h, const std::vector<int> &v) {
-    const size_t per = 4 * 6 + 4 + 4 + 1, need = per * (h->nl - 1) + 4 + 1 + 6 + 1;
+    const size_t per = 4 * 7 + 4 + 4 + 1, need = per * (h->nl - 1) + 4 + 1 + 7 + 1;
     if (v.size() != need) return false;
     size_t i = 0;
-    auto sh = [&]() { Shape s{v[i], v[i + 1], v[i + 2], v[i + 3], v[i + 4], v[i + 5]}; i += 6; return s; };
+    auto sh = [&]() {
+        Shape s{v[i], v[i + 1], v[i + 2], v[i + 3], v[i + 4], v[i + 5], v[i + 6]};
+        i += 7;
+        return s;
+    };
     auto rs = [&]() { RShape r{v[i], v[i + 1], v[i + 2], v[i + 3]}; i += 4; return r; };
     std::vector<LevelPlan> lv = h->lv;
     std::vector<bool> fsr(h->nl, false);
@@ -997,7 +1005,7 @@ mg_status_t autotune_timed(mg_ctx *h, hipStream_t st) {
         for (int fam = 0; fam < 3; ++fam) {
             float best = 1e30f;
             Shape bs = L.shs[fam];
-            for (const Shape &s : stencil_candidates(h, L, false)) {
+            for (const Shape &s : stencil_candidates(h, L, false, fam == SH_PROLONG)) {
                 const float t = time_ms(st, [&]() -> hipError_t {
                     if (fam == SH_SMOOTH)
                         return scaled0 ? launch_smooth_first(D, L.prec, L.P, nullptr, Rbuf(h), scal(h), bbuf(h, l),
@@ -1054,8 +1062,9 @@ mg_status_t autotune_timed(mg_ctx *h, hipStream_t st) {
                     if (rounds <= 6 && nb >= 0.97 * rounds * cus && std::find(zs.begin(), zs.end(), zcc) == zs.end())
                         zs.push_back(zcc);
                 }
-                for (int zcc : zs) {
-                    const RShape r{8, tyc, zcc, 3};
+                for (int zcc : zs)
+                    for (int lw : {3, 4}) {  // c1, c2 in LDS in FP32/FP64, or in the 2-byte format
+                    const RShape r{8, tyc, zcc, lw};
                     if (!smooth_restrict_ok(L.P, L.prec, r)) continue;
                     const float t = time_ms(st, [&]() {
                         if (l == 0 && finest_alias(h))
@@ -1720,10 +1729,10 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
     }
     if (kind == MG_SHAPE_FUSE_SR) {
         if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no restriction", level);
-        if ((np != 1 && np != 3) || (p[0] != 0 && p[0] != 1))
-            return fail(MG_ERR_ARG, "the fused smoothing + restriction shape is {on (0|1)[, tyc, zcc]}");
-        if (np == 3) {
-            const RShape r{8, p[1], p[2], 3};
+        if ((np != 1 && np != 3 && np != 4) || (p[0] != 0 && p[0] != 1) || (np == 4 && p[3] != 0 && p[3] != 1))
+            return fail(MG_ERR_ARG, "the fused smoothing + restriction shape is {on (0|1)[, tyc, zcc[, lds16 (0|1)]]}");
+        if (np >= 3) {
+            const RShape r{8, p[1], p[2], np == 4 && p[3] ? 4 : 3};
             if (!smooth_restrict_ok(h->lv[level].P, h->lv[level].prec, r))
                 return fail(MG_ERR_ARG, "fused smoothing + restriction shape {tyc, zcc} not valid here");
             (level == 0 ? h->srsh : h->lv[level].fsrsh) = r;
@@ -1759,10 +1768,12 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
                               kind == MG_SHAPE_SWEEP || kind == MG_SHAPE_PROLONG;
     if (stencil_kind) {
         if (kind == MG_SHAPE_UPDATE && level != 0) return fail(MG_ERR_ARG, "the update shape exists on level 0 only");
-        if (np != 5 && np != 6) return fail(MG_ERR_ARG, "stencil shape takes 5 or 6 values {V, zc, bs, xcd, ty[, dp]}");
-        Shape s{p[0], p[1], p[2], p[3], p[4], np == 6 ? p[5] : 1};
+        if (np < 5 || np > 7)
+            return fail(MG_ERR_ARG, "stencil shape takes 5 to 7 values {V, zc, bs, xcd, ty[, dp[, sg]]}");
+        Shape s{p[0], p[1], p[2], p[3], p[4], np >= 6 ? p[5] : 1, np == 7 ? p[6] : 1};
         if (s.dp < 1 || s.dp > 2 || (s.dp == 2 && s.ty == 0))
             return fail(MG_ERR_ARG, "dp must be 1, or 2 with ty > 0");
+        if (s.sg != 0 && s.sg != 1) return fail(MG_ERR_ARG, "sg must be 0 or 1");
         if ((s.V != 4 && s.V != 8) || s.V > L.P) return fail(MG_ERR_ARG, "V must be 4 or 8 and <= P = %d", L.P);
         if (s.zc < 1 || s.zc > L.P) return fail(MG_ERR_ARG, "zc out of range");
         if (s.bs < 64 || s.bs > 256 || s.bs % 64) return fail(MG_ERR_ARG, "bs must be 64, 128, 192 or 256");
@@ -1807,6 +1818,7 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
         const RShape &r = level == 0 ? h->srsh : h->lv[level].fsrsh;
         p[0] = (level == 0 ? h->fused_sr : h->lv[level].fsr) ? 1 : 0;
         if (np >= 3) p[1] = r.tyc, p[2] = r.zcc;
+        if (np >= 4) p[3] = r.pipe == 4 ? 1 : 0;
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE) {
@@ -1826,6 +1838,7 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
                                                     : L.shs[SH_SWEEP];
         p[0] = S.V, p[1] = S.zc, p[2] = S.bs, p[3] = S.xcd, p[4] = S.ty;
         if (np >= 6) p[5] = S.dp;
+        if (np >= 7) p[6] = S.sg;
     } else if (kind == MG_SHAPE_RESTRICT && np >= 4) {
         p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc, p[3] = L.rsh.pipe;
     } else {

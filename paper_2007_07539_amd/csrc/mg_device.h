@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mg {
 
 // ---------------------------------------------------------------------------
@@ -199,7 +201,11 @@ template <class A, int V> struct LdsRun {
         for (int j = 0; j < NC; ++j) {
             A c[C];
 #pragma unroll
-            for (int i = 0; i < C; ++i) c[i] = (A)v[j * C + i];
+            for (int i = 0; i < C; ++i) {
+                // (narrowing stores only values the format holds exactly)
+                if constexpr (std::is_same<A, S>::value) c[i] = v[j * C + i];
+                else c[i] = store_as<A>(v[j * C + i]);
+            }
             store_row<A, C>(row + (size_t)(j * TXR + t) * C, c);
         }
     }

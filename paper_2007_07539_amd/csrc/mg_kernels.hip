@@ -1704,7 +1704,7 @@ static hipError_t prolong_t(int D, int P, const void *c, const void *ec, const v
     if (D == 3 && s.ty > 0 && sweep) {
         typedef typename FProl<TF, TC>::PA PA;
         const int nthr = (P / s.V) * (s.ty + 2);
-        const bool staged = P / 2 >= 8 &&
+        const bool staged = s.sg && P / 2 >= 8 &&
                             march_lds_bytes(P, s.ty, sizeof(TF)) + staged_ez_bytes(P, s.ty, sizeof(PA)) <= 65536 &&
                             (s.ty / 2 + 3) * (P / 2 + 4) <= 4 * nthr;
         if (staged) {

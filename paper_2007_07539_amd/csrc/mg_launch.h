@@ -20,6 +20,8 @@ struct Shape {
     int xcd;  // 1: remap block ids so consecutive tiles share an XCD
     int ty;   // 3-D only: > 0 selects the LDS-plane kernel with ty output rows per block
     int dp = 1;  // LDS-plane kernel: planes loaded ahead of the one being computed (1 or 2)
+    int sg = 1;  // LDS-plane prolongation: 1 = stage the z-interpolated coarse plane in LDS
+                 // where it fits, 0 = every row reads its coarse rows from memory
 };
 
 // LDS bytes of the LDS-plane kernel for a level of storage size sb bytes.
@@ -124,7 +126,8 @@ hipError_t launch_defer_flush(int prec, const void *cdefer, size_t cstride, cons
 // coarse planes per block.
 // LDS one workgroup may allocate on gfx950.
 constexpr size_t kLdsMax = 160 * 1024;
-size_t smooth_restrict_lds_bytes(int P, int tyc, int prec);
+// narrow: c1 and c2 in LDS in the level's 2-byte format (RShape pipe 4)
+size_t smooth_restrict_lds_bytes(int P, int tyc, int prec, bool narrow);
 // Lets every instance of the fused kernel allocate up to kLdsMax of LDS; call
 // once per process before the first launch (not inside a stream capture).
 hipError_t smooth_restrict_prepare();

@@ -32,6 +32,10 @@
 namespace mg {
 namespace {
 
+template <class T> constexpr int prec_of_t() {
+    return sizeof(T) == 8 ? P_F64 : sizeof(T) == 4 ? P_F32 : std::is_same<T, f16>::value ? P_F16 : P_BF16;
+}
+
 // SCALED: the right-hand side is the scaled-and-cast FP64 residual (the
 // finest level inside a refinement step; b is also written out); otherwise
 // it is the level's stored b (a coarser level, or a V-cycle on its own).
@@ -39,14 +43,18 @@ namespace {
 // bound leaves each thread more of them
 template <class T> constexpr int sr_bound() { return sizeof(T) == 8 ? 512 : 768; }
 
-template <class T, class TC, bool SCALED>
+// NARROW: c1 and c2 sit in LDS in the storage format T instead of the
+// accumulator format (exact: both are values of T), which halves that part of
+// the LDS so that two workgroups fit a CU; they are widened when read.
+template <class T, class TC, bool SCALED, bool NARROW>
 __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *__restrict__ src,
                                                           const double *__restrict__ scal, T *__restrict__ bout,
                                                           T *__restrict__ cout, TC *__restrict__ bc, int P, int tyc,
                                                           int zcc, int ytiles, double omega, int xcd) {
     constexpr int V = 8, VC = 4;
     typedef acc_t<T> A;
-    typedef LdsRun<A, V> LR;    // fine rows in LDS, chunk-major
+    typedef typename std::conditional<NARROW, T, A>::type LC;  // LDS format of c1 and c2
+    typedef LdsRun<LC, V> LR;   // fine rows in LDS, chunk-major
     typedef LdsRun<A, VC> LRC;  // x-weighted residual rows
     typedef typename std::conditional<SCALED, double, T>::type S;  // source format
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -54,9 +62,9 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
     const size_t cslot = (size_t)G * P, rslot = (size_t)RR * RW;
     // c1 and c2 sit in LDS widened to the accumulator type, so that neither
     // their stores nor their loads convert
-    A *c1s = reinterpret_cast<A *>(smem_raw);  // [2][G][P]
-    A *c2s = c1s + 2 * cslot;                  // [2][G][P]
-    A *rs = c2s + 2 * cslot;                   // [2][RR][RW]
+    LC *c1s = reinterpret_cast<LC *>(smem_raw);  // [2][G][P]
+    LC *c2s = c1s + 2 * cslot;                   // [2][G][P]
+    A *rs = reinterpret_cast<A *>(c2s + 2 * cslot);  // [2][RR][RW]
     const int Pc = P >> 1, TXR = P / V;
     const Grid<3> gc{Pc};
     int blk = blockIdx.x;
@@ -196,10 +204,10 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
             const int p = t + 1;
             T craw[V];
             if (row_in && p >= 1 && p <= P - 1) {
-                const A *row = c1s + (size_t)(p & 1) * cslot + (size_t)gi * P;
+                const LC *row = c1s + (size_t)(p & 1) * cslot + (size_t)gi * P;
                 A nb[V];
-                const A xl = x0 > 0 ? LR::left_of(row, xc, TXR) : A(0);
-                const A xr = x0 + V < P ? LR::right_of(row, xc, TXR) : A(0);
+                const A xl = x0 > 0 ? (A)widen(LR::left_of(row, xc, TXR)) : A(0);
+                const A xr = x0 + V < P ? (A)widen(LR::right_of(row, xc, TXR)) : A(0);
 #pragma unroll
                 for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? k1[i - 1] : xl) + (i < V - 1 ? k1[i + 1] : xr);
                 A ym[V], yp[V];
@@ -227,10 +235,10 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
         if (t >= zf0) {
             A r[V];
             if (res_row) {
-                const A *row = c2s + (size_t)(t & 1) * cslot + (size_t)gi * P;
+                const LC *row = c2s + (size_t)(t & 1) * cslot + (size_t)gi * P;
                 A nb[V];
-                const A xl = x0 > 0 ? LR::left_of(row, xc, TXR) : A(0);
-                const A xr = x0 + V < P ? LR::right_of(row, xc, TXR) : A(0);
+                const A xl = x0 > 0 ? (A)widen(LR::left_of(row, xc, TXR)) : A(0);
+                const A xr = x0 + V < P ? (A)widen(LR::right_of(row, xc, TXR)) : A(0);
 #pragma unroll
                 for (int i = 0; i < V; ++i) nb[i] = (i > 0 ? c1[i - 1] : xl) + (i < V - 1 ? c1[i + 1] : xr);
                 A ym[V], yp[V];
@@ -277,18 +285,18 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
     if (coarse) coarse_step(zf1, zf1 & 1);
 }
 
-template <class T, bool SCALED>
+template <class T, bool SCALED, bool NARROW>
 hipError_t smooth_restrict_t(int pc, int P, const void *src, const double *scal, void *bout, void *cout, void *bc,
                              double omega, const RShape &s, hipStream_t st) {
     const int Pc = P / 2;
     const int ytiles = (Pc - 1 + s.tyc - 1) / s.tyc;
     const int blocks = ytiles * ((Pc - 1 + s.zcc - 1) / s.zcc);
     const int threads = (2 * s.tyc + 5) * (P / 8);
-    const size_t lds = smooth_restrict_lds_bytes(P, s.tyc, sizeof(T) == 8 ? P_F64 : P_F32);
+    const size_t lds = smooth_restrict_lds_bytes(P, s.tyc, prec_of_t<T>(), NARROW);
 #define MG_SR(TCT)                                                                                                     \
-    hipLaunchKernelGGL((k_smooth_restrict<T, TCT, SCALED>), dim3(blocks), dim3(threads), lds, st, src, scal,       \
-                       static_cast<T *>(bout), static_cast<T *>(cout), static_cast<TCT *>(bc), P, s.tyc, s.zcc,     \
-                       ytiles, omega, 1)
+    hipLaunchKernelGGL((k_smooth_restrict<T, TCT, SCALED, NARROW>), dim3(blocks), dim3(threads), lds, st, src,     \
+                       scal, static_cast<T *>(bout), static_cast<T *>(cout), static_cast<TCT *>(bc), P, s.tyc,     \
+                       s.zcc, ytiles, omega, 1)
     switch (pc) {
     case P_F64: MG_SR(double); break;
     case P_F32: MG_SR(float); break;
@@ -302,19 +310,22 @@ hipError_t smooth_restrict_t(int pc, int P, const void *src, const double *scal,
 
 }  // namespace
 
-size_t smooth_restrict_lds_bytes(int P, int tyc, int prec) {
+size_t smooth_restrict_lds_bytes(int P, int tyc, int prec, bool narrow) {
     const size_t acc = prec == P_F64 ? sizeof(double) : sizeof(float);
-    return (4 * (size_t)(2 * tyc + 5) * P + 2 * (size_t)(2 * tyc + 1) * (P / 2)) * acc;
+    const size_t lc = narrow ? prec_bytes(prec) : acc;
+    return 4 * (size_t)(2 * tyc + 5) * P * lc + 2 * (size_t)(2 * tyc + 1) * (P / 2) * acc;
 }
 
 hipError_t smooth_restrict_prepare() {
     static hipError_t done = [] {
         const void *fns[] = {
-#define MG_SR_FN(T, S)                                                                                        \
-    (const void *)k_smooth_restrict<T, double, S>, (const void *)k_smooth_restrict<T, float, S>,              \
-        (const void *)k_smooth_restrict<T, f16, S>, (const void *)k_smooth_restrict<T, bf16, S>
-            MG_SR_FN(double, true), MG_SR_FN(float, true), MG_SR_FN(f16, true), MG_SR_FN(bf16, true),
-            MG_SR_FN(double, false), MG_SR_FN(float, false), MG_SR_FN(f16, false), MG_SR_FN(bf16, false)
+#define MG_SR_FN(T, S, N)                                                                                     \
+    (const void *)k_smooth_restrict<T, double, S, N>, (const void *)k_smooth_restrict<T, float, S, N>,        \
+        (const void *)k_smooth_restrict<T, f16, S, N>, (const void *)k_smooth_restrict<T, bf16, S, N>
+            MG_SR_FN(double, true, false), MG_SR_FN(float, true, false), MG_SR_FN(f16, true, false),
+            MG_SR_FN(bf16, true, false), MG_SR_FN(double, false, false), MG_SR_FN(float, false, false),
+            MG_SR_FN(f16, false, false), MG_SR_FN(bf16, false, false), MG_SR_FN(f16, true, true),
+            MG_SR_FN(bf16, true, true), MG_SR_FN(f16, false, true), MG_SR_FN(bf16, false, true)
 #undef MG_SR_FN
         };
         for (const void *f : fns) {
@@ -332,18 +343,25 @@ hipError_t smooth_restrict_prepare() {
 bool smooth_restrict_ok(int P, int prec, const RShape &s) {
     if (P < 16 || P / 8 > 64 || 64 % (P / 8) != 0) return false;
     if (s.tyc < 1 || s.tyc > P / 2 - 1 || s.zcc < 1 || s.zcc > P / 2 - 1) return false;
+    // pipe 3: c1, c2 in LDS in FP32/FP64; 4: in the 2-byte storage format
+    if (s.pipe != 3 && !(s.pipe == 4 && prec_bytes(prec) == 2)) return false;
     if ((2 * s.tyc + 5) * (P / 8) > (prec == P_F64 ? 512 : 768)) return false;  // the kernel's launch bound
-    return smooth_restrict_lds_bytes(P, s.tyc, prec) <= kLdsMax;
+    return smooth_restrict_lds_bytes(P, s.tyc, prec, s.pipe == 4) <= kLdsMax;
 }
 
 hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, const double *scal, void *bout,
                                   void *cout, void *bc, double omega, const RShape &s, hipStream_t st) {
     if (!smooth_restrict_ok(P, prec, s)) return hipErrorInvalidValue;
+    const bool nw = s.pipe == 4;
     switch (prec) {
-    case P_F64: return smooth_restrict_t<double, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
-    case P_F32: return smooth_restrict_t<float, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
-    case P_F16: return smooth_restrict_t<f16, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
-    case P_BF16: return smooth_restrict_t<bf16, true>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_F64: return smooth_restrict_t<double, true, false>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_F32: return smooth_restrict_t<float, true, false>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_F16:
+        return nw ? smooth_restrict_t<f16, true, true>(pc, P, R, scal, bout, cout, bc, omega, s, st)
+                  : smooth_restrict_t<f16, true, false>(pc, P, R, scal, bout, cout, bc, omega, s, st);
+    case P_BF16:
+        return nw ? smooth_restrict_t<bf16, true, true>(pc, P, R, scal, bout, cout, bc, omega, s, st)
+                  : smooth_restrict_t<bf16, true, false>(pc, P, R, scal, bout, cout, bc, omega, s, st);
     }
     return hipErrorInvalidValue;
 }
@@ -351,11 +369,16 @@ hipError_t launch_smooth_restrict(int prec, int pc, int P, const double *R, cons
 hipError_t launch_smooth_restrict_b(int prec, int pc, int P, const void *b, void *cout, void *bc, double omega,
                                     const RShape &s, hipStream_t st) {
     if (!smooth_restrict_ok(P, prec, s)) return hipErrorInvalidValue;
+    const bool nw = s.pipe == 4;
     switch (prec) {
-    case P_F64: return smooth_restrict_t<double, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
-    case P_F32: return smooth_restrict_t<float, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
-    case P_F16: return smooth_restrict_t<f16, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
-    case P_BF16: return smooth_restrict_t<bf16, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
+    case P_F64: return smooth_restrict_t<double, false, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
+    case P_F32: return smooth_restrict_t<float, false, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
+    case P_F16:
+        return nw ? smooth_restrict_t<f16, false, true>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st)
+                  : smooth_restrict_t<f16, false, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
+    case P_BF16:
+        return nw ? smooth_restrict_t<bf16, false, true>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st)
+                  : smooth_restrict_t<bf16, false, false>(pc, P, b, nullptr, nullptr, cout, bc, omega, s, st);
     }
     return hipErrorInvalidValue;
 }

@@ -280,10 +280,12 @@ class Solver:
         arr = (ctypes.c_int * len(params))(*params)
         _check(self.lib.mg_set_shape(self._h, level, kind, arr, len(params)), "mg_set_shape")
 
-    def get_shape(self, level: int, kind: int):
-        arr = (ctypes.c_int * 6)()
-        _check(self.lib.mg_get_shape(self._h, level, kind, arr, 6), "mg_get_shape")
-        n = {SHAPE_RESTRICT: 4, SHAPE_TAIL: 1, SHAPE_FUSE: 5, SHAPE_FUSE_SR: 3}.get(kind, 6)
+    def get_shape(self, level: int, kind: int, count: int | None = None):
+        """The shape's values (count of them; default: the set a caller passes
+        to set_shape, e.g. three for SHAPE_FUSE_SR, four to include lds16)."""
+        arr = (ctypes.c_int * 7)()
+        _check(self.lib.mg_get_shape(self._h, level, kind, arr, 7), "mg_get_shape")
+        n = {SHAPE_RESTRICT: 4, SHAPE_TAIL: 1, SHAPE_FUSE: 5, SHAPE_FUSE_SR: 3}.get(kind, 6) if count is None else count
         return list(arr[:n])
 
     def profile_step(self, stream=None, cap: int = 512):

@@ -261,20 +261,25 @@ def test_fused_smooth_restrict_bitwise(dev, name, n):
     assert s.get_shape(0, mgir.SHAPE_FUSE_SR)[0] == 0
     u_ref, r_ref = s.solve(b64)
     u_ref = u_ref.clone()
-    tried = 0
-    for shape in ([1, 1, 1], [1, 2, 3], [1, 3, 16], [1, 1, 5], [1, 3, 7], [1, 2, 32]):
+    tried = narrow_tried = 0
+    # three values: c1, c2 in FP32 (FP64) LDS; a fourth 1: in the level's 2-byte format
+    for shape in ([1, 1, 1], [1, 2, 3], [1, 3, 16], [1, 1, 5], [1, 3, 7], [1, 2, 32], [1, 1, 1, 1], [1, 3, 16, 1],
+                  [1, 2, 32, 1], [1, 3, 7, 1]):
         try:
             s.set_shape(0, mgir.SHAPE_FUSE_SR, shape)
         except mgir.MgError:
             continue
         tried += 1
-        assert s.get_shape(0, mgir.SHAPE_FUSE_SR) == shape
+        narrow_tried += len(shape) == 4
+        assert s.get_shape(0, mgir.SHAPE_FUSE_SR, len(shape)) == shape
         print(f"  shape {shape}", flush=True)
         u, r = s.solve(b64)
         assert r.iterations == r_ref.iterations, shape
         assert r.history == r_ref.history, shape
         assert torch.equal(u, u_ref), shape
     assert tried >= (2 if prec[0] == "f64" else 3)
+    if prec[0] in ("f16", "bf16") and n >= 15:
+        assert narrow_tried >= 1
 
 
 @pytest.mark.parametrize("name,n", [("f16", 127), ("bf16", 63), ("f32", 63), ("hsd", 255), ("h_mg", 127)])
@@ -301,7 +306,7 @@ def test_fused_smooth_restrict_coarse_levels_bitwise(dev, name, n):
     c_on = s.vcycle(bl).clone()
     u_on, r_on = s.solve(b64)
     u_on = u_on.clone()
-    for shape in ([1, 1, 3], [1, 2, 5], [1, 3, 2]):
+    for shape in ([1, 1, 3], [1, 2, 5], [1, 3, 2], [1, 2, 5, 1], [1, 1, 3, 1]):
         for l in levels:
             try:
                 s.set_shape(l, mgir.SHAPE_FUSE_SR, shape)
