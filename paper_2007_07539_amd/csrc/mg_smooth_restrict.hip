@@ -39,9 +39,12 @@ template <class T> constexpr int prec_of_t() {
 // SCALED: the right-hand side is the scaled-and-cast FP64 residual (the
 // finest level inside a refinement step; b is also written out); otherwise
 // it is the level's stored b (a coarser level, or a V-cycle on its own).
-// FP64 levels keep nine rows of eight doubles in registers: a lower thread
-// bound leaves each thread more of them
-template <class T> constexpr int sr_bound() { return sizeof(T) == 8 ? 512 : 768; }
+// FP64 levels: four values per thread (two waves per fine row of P = 512, twice
+// the waves of eight per thread); the fine residual rows then go to LDS as
+// they are and the coarse threads apply the x weights (XW), since a row's
+// left neighbour value may sit in the other wave.  Same operations, same order.
+template <class T> constexpr int sr_vec() { return sizeof(T) == 8 ? 4 : 8; }
+template <class T> constexpr int sr_bound() { return sizeof(T) == 8 ? 1024 : 768; }
 
 // NARROW: c1 and c2 sit in LDS in the storage format T instead of the
 // accumulator format (exact: both are values of T), which halves that part of
@@ -51,14 +54,15 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
                                                           const double *__restrict__ scal, T *__restrict__ bout,
                                                           T *__restrict__ cout, TC *__restrict__ bc, int P, int tyc,
                                                           int zcc, int ytiles, double omega, int xcd) {
-    constexpr int V = 8, VC = 4;
+    constexpr int V = sr_vec<T>(), VC = V / 2;
+    constexpr bool XW = V == 4;  // x weights in the coarse threads, from raw residual rows
     typedef acc_t<T> A;
     typedef typename std::conditional<NARROW, T, A>::type LC;  // LDS format of c1 and c2
     typedef LdsRun<LC, V> LR;   // fine rows in LDS, chunk-major
-    typedef LdsRun<A, VC> LRC;  // x-weighted residual rows
+    typedef LdsRun<A, XW ? V : VC> LRC;  // residual rows: raw (XW) or x-weighted
     typedef typename std::conditional<SCALED, double, T>::type S;  // source format
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int G = 2 * tyc + 5, RR = 2 * tyc + 1, RW = P / 2;
+    const int G = 2 * tyc + 5, RR = 2 * tyc + 1, RW = XW ? P : P / 2;
     const size_t cslot = (size_t)G * P, rslot = (size_t)RR * RW;
     // c1 and c2 sit in LDS widened to the accumulator type, so that neither
     // their stores nor their loads convert
@@ -158,8 +162,26 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
         const int j = zf - zf0;
         const bool last_of_z = j > 0 && (j & 1) == 0;  // zf = 2Z + 1
         A xs[3][VC];
+        if constexpr (XW) {
+            // fine residuals x0 - 1 .. x0 + 3 of each of the three rows, then
+            // the x weights exactly as a fine thread forms them
 #pragma unroll
-        for (int oy = 0; oy < 3; ++oy) LRC::load(rb + (size_t)(2 * gi + oy) * RW, xc, TXR, xs[oy]);
+            for (int oy = 0; oy < 3; ++oy) {
+                const A *row = rb + (size_t)(2 * gi + oy) * RW;
+                A r[V];
+                LRC::load(row, xc, TXR, r);
+                const A left = xc > 0 ? LRC::left_of(row, xc, TXR) : A(0);
+#pragma unroll
+                for (int jj = 0; jj < VC; ++jj) {
+                    const A lm = jj > 0 ? r[2 * jj - 1] : left;
+                    xs[oy][jj] = A(0.25) * (lm + r[2 * jj + 1]) + A(0.5) * r[2 * jj];
+                }
+                if (xc == 0) xs[oy][0] = A(0);
+            }
+        } else {
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) LRC::load(rb + (size_t)(2 * gi + oy) * RW, xc, TXR, xs[oy]);
+        }
         TC out[VC];
 #pragma unroll
         for (int jx = 0; jx < VC; ++jx) {
@@ -257,17 +279,22 @@ __global__ __launch_bounds__(sr_bound<T>()) void k_smooth_restrict(const void *_
 #pragma unroll
                 for (int i = 0; i < V; ++i) r[i] = A(0);
             }
-            // coarse X = x0/2 + j takes fine 2X-1, 2X, 2X+1; x0-1 from the previous lane
-            const A left_in = __shfl_up(r[V - 1], 1, 64);
-            const A left = x0 > 0 ? left_in : A(0);
-            A xq[VC];
+            if constexpr (XW) {
+                // the raw residual row; the coarse threads weight it
+                if (res_slot) LRC::store(rs + (size_t)(t & 1) * rslot + (size_t)(gi - 2) * RW, xc, TXR, r);
+            } else {
+                // coarse X = x0/2 + j takes fine 2X-1, 2X, 2X+1; x0-1 from the previous lane
+                const A left_in = __shfl_up(r[V - 1], 1, 64);
+                const A left = x0 > 0 ? left_in : A(0);
+                A xq[VC];
 #pragma unroll
-            for (int j = 0; j < VC; ++j) {
-                const A lm = j > 0 ? r[2 * j - 1] : left;
-                xq[j] = A(0.25) * (lm + r[2 * j + 1]) + A(0.5) * r[2 * j];
+                for (int j = 0; j < VC; ++j) {
+                    const A lm = j > 0 ? r[2 * j - 1] : left;
+                    xq[j] = A(0.25) * (lm + r[2 * j + 1]) + A(0.5) * r[2 * j];
+                }
+                if (x0 == 0) xq[0] = A(0);
+                if (res_slot) LRC::store(rs + (size_t)(t & 1) * rslot + (size_t)(gi - 2) * RW, xc, TXR, xq);
             }
-            if (x0 == 0) xq[0] = A(0);
-            if (res_slot) LRC::store(rs + (size_t)(t & 1) * rslot + (size_t)(gi - 2) * RW, xc, TXR, xq);
         }
         // c1 of plane t+2 for the next step's neighbours
         LR::store(c1s + (size_t)((t + 2) & 1) * cslot + (size_t)gi * P, xc, TXR, k2);
@@ -291,7 +318,7 @@ hipError_t smooth_restrict_t(int pc, int P, const void *src, const double *scal,
     const int Pc = P / 2;
     const int ytiles = (Pc - 1 + s.tyc - 1) / s.tyc;
     const int blocks = ytiles * ((Pc - 1 + s.zcc - 1) / s.zcc);
-    const int threads = (2 * s.tyc + 5) * (P / 8);
+    const int threads = (2 * s.tyc + 5) * (P / sr_vec<T>());
     const size_t lds = smooth_restrict_lds_bytes(P, s.tyc, prec_of_t<T>(), NARROW);
 #define MG_SR(TCT)                                                                                                     \
     hipLaunchKernelGGL((k_smooth_restrict<T, TCT, SCALED, NARROW>), dim3(blocks), dim3(threads), lds, st, src,     \
@@ -313,7 +340,8 @@ hipError_t smooth_restrict_t(int pc, int P, const void *src, const double *scal,
 size_t smooth_restrict_lds_bytes(int P, int tyc, int prec, bool narrow) {
     const size_t acc = prec == P_F64 ? sizeof(double) : sizeof(float);
     const size_t lc = narrow ? prec_bytes(prec) : acc;
-    return 4 * (size_t)(2 * tyc + 5) * P * lc + 2 * (size_t)(2 * tyc + 1) * (P / 2) * acc;
+    const size_t rw = prec == P_F64 ? P : P / 2;  // raw residual rows for FP64 (XW)
+    return 4 * (size_t)(2 * tyc + 5) * P * lc + 2 * (size_t)(2 * tyc + 1) * rw * acc;
 }
 
 hipError_t smooth_restrict_prepare() {
@@ -341,11 +369,14 @@ hipError_t smooth_restrict_prepare() {
 }
 
 bool smooth_restrict_ok(int P, int prec, const RShape &s) {
-    if (P < 16 || P / 8 > 64 || 64 % (P / 8) != 0) return false;
+    // FP32/FP16/BF16: rows of P/8 threads within one wave (the x weights use a
+    // lane shuffle); FP64: P/4 threads per row, no shuffle
+    if (P < 16 || (prec != P_F64 && (P / 8 > 64 || 64 % (P / 8) != 0))) return false;
     if (s.tyc < 1 || s.tyc > P / 2 - 1 || s.zcc < 1 || s.zcc > P / 2 - 1) return false;
     // pipe 3: c1, c2 in LDS in FP32/FP64; 4: in the 2-byte storage format
     if (s.pipe != 3 && !(s.pipe == 4 && prec_bytes(prec) == 2)) return false;
-    if ((2 * s.tyc + 5) * (P / 8) > (prec == P_F64 ? 512 : 768)) return false;  // the kernel's launch bound
+    const int threads = (2 * s.tyc + 5) * (P / (prec == P_F64 ? 4 : 8));
+    if (threads > (prec == P_F64 ? 1024 : 768)) return false;  // the kernel's launch bound
     return smooth_restrict_lds_bytes(P, s.tyc, prec, s.pipe == 4) <= kLdsMax;
 }
 
