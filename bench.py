@@ -230,6 +230,21 @@ def config_sweep(torch, mgir, W, oracle, dev, steps, tune, defer, cfg3=None):
     return res
 
 
+def batched_shapes(mgir, s, ns):
+    """The launch shapes of a batched handle per level pitch (every level of one
+    pitch and format shares them once tuned): stencil {V, zc, bs, xcd, ty},
+    restriction {V, tyc, zcc, pipe}."""
+    out = {}
+    for i, n in enumerate(ns):
+        m = int(n + 1).bit_length() - 1
+        for l in range(m - 1):
+            key = f"P{(n + 1) >> l}"
+            if key not in out:
+                out[key] = {"stencil": s.get_shape(i, l, mgir.SHAPE_SWEEP, 5),
+                            "restrict": s.get_shape(i, l, mgir.SHAPE_RESTRICT)}
+    return out
+
+
 def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=True, defer=0):
     """Throughput of the batched and many-right-hand-side solves (FP16 V-cycles
     and the FP64 solve of the same problems), and the paper's other precision
@@ -382,16 +397,23 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
     dof = float(sum(n**3 for n in ns))
     bs = [torch.from_numpy(r).to(dev) for r in rhs]
     us = [torch.zeros_like(b) for b in bs]
-    entry = {"instances": len(ns), "sizes": {str(n): ns.count(n) for n in sorted(set(ns))}, "dof": dof}
+    entry = {"instances": len(ns), "sizes": {str(n): ns.count(n) for n in sorted(set(ns))}, "dof": dof,
+             "autotune": bool(tune)}
     for name, scaling in (("f16", True), ("f64", False)):
-        log(f"[bench] batched 64 instances, map {name}")
-        s = mgir.BatchedSolver(ns, W.precision_map(name, 8), residual_scaling=scaling, device=dev)
-        sec, (_, r, st) = timed(lambda: s.solve(bs, us))
-        entry[name] = {"ms": sec * 1e3, "dof_per_s": dof / sec, "status": st,
-                       "max_iterations": max(x.iterations for x in r),
-                       "max_rel_residual": max(x.rel_residual for x in r)}
-        del s
-        torch.cuda.empty_cache()
+        for tuned in ((False, True) if tune else (False,)):
+            log(f"[bench] batched 64 instances, map {name}{', autotuned' if tuned else ''}")
+            s = mgir.BatchedSolver(ns, W.precision_map(name, 8), residual_scaling=scaling, device=dev,
+                                   autotune=tuned)
+            sec, (_, r, st) = timed(lambda: s.solve(bs, us))
+            e = {"ms": sec * 1e3, "dof_per_s": dof / sec, "status": st,
+                 "max_iterations": max(x.iterations for x in r),
+                 "max_rel_residual": max(x.rel_residual for x in r)}
+            if tuned:
+                e["untuned_ms"] = entry[name]["ms"]
+                e["shapes"] = batched_shapes(mgir, s, ns)
+            entry[name] = e
+            del s
+            torch.cuda.empty_cache()
     entry["speedup_f16_vs_f64"] = entry["f64"]["ms"] / entry["f16"]["ms"]
     res["batched_64_instances"] = entry
     del bs, us
@@ -401,16 +423,27 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
     b = torch.from_numpy(W.multi_rhs(n, k, seed=5)).to(dev)
     u = torch.zeros_like(b)
     dof = float(n**3 * k)
-    entry = {"n": n, "nrhs": k, "dof_x_rhs": dof}
+    entry = {"n": n, "nrhs": k, "dof_x_rhs": dof, "autotune": bool(tune)}
     for name, scaling in (("f16", True), ("f64", False)):
-        log(f"[bench] {k} right-hand sides at {n}^3, map {name}")
-        s = mgir.MultiSolver(n, k, W.precision_map(name, W.levels_for(n)), residual_scaling=scaling, device=dev)
-        sec, (_, r, st) = timed(lambda: s.solve(b, u))
-        entry[name] = {"ms": sec * 1e3, "dof_rhs_per_s": dof / sec, "status": st,
-                       "max_iterations": max(x.iterations for x in r),
-                       "max_rel_residual": max(x.rel_residual for x in r)}
-        del s
-        torch.cuda.empty_cache()
+        for tuned in ((False, True) if tune else (False,)):
+            log(f"[bench] {k} right-hand sides at {n}^3, map {name}{', autotuned' if tuned else ''}")
+            s = mgir.MultiSolver(n, k, W.precision_map(name, W.levels_for(n)), residual_scaling=scaling, device=dev,
+                                 autotune=tuned)
+            sec, (_, r, st) = timed(lambda: s.solve(b, u))
+            e = {"ms": sec * 1e3, "dof_rhs_per_s": dof / sec, "status": st,
+                 "max_iterations": max(x.iterations for x in r),
+                 "max_rel_residual": max(x.rel_residual for x in r)}
+            if tuned:
+                e["untuned_ms"] = entry[name]["ms"]
+                # planes per thread of the smoothing, sweeps, prolongation; coarse
+                # planes per block of the restriction
+                e["shapes"] = {f"level{l}": [s.get_shape(l, kk)[1] for kk in (mgir.SHAPE_SMOOTH, mgir.SHAPE_SWEEP,
+                                                                               mgir.SHAPE_PROLONG)]
+                               + [s.get_shape(l, mgir.SHAPE_RESTRICT)[2]]
+                               for l in range(W.levels_for(n) - 1)}
+            entry[name] = e
+            del s
+            torch.cuda.empty_cache()
     entry["speedup_f16_vs_f64"] = entry["f64"]["ms"] / entry["f16"]["ms"]
     res["many_rhs_127x32"] = entry
     return res

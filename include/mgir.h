@@ -237,7 +237,10 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
  *              same map a single-grid solver gets from level_prec[0..m_i-2]
  *              followed by level_prec[Lmax-1].  NULL means all MG_F64.
  *   opt        NULL for defaults; needs nu1 >= 2.  use_graph captures one
- *              refinement step of the whole batch; autotune is ignored.
+ *              refinement step of the whole batch; autotune times launch
+ *              shapes per class of levels (pitch and format) at
+ *              mg_bind_workspace, whole batched steps at a time (cached as
+ *              for mg_setup under MGIR_TUNE_CACHE).
  * Each instance computes bit for bit what a single-grid solver with its size
  * and map computes.  Workspace as for mg_setup (mg_workspace_size,
  * mg_bind_workspace).  The single-grid calls (mg_vcycle, ir_solve, stage and
@@ -278,7 +281,9 @@ mg_status_t mg_instances(mg_handle h, int *ninst);
  *   nrhs       4, 8, 16, 32 or 64, and at least 8 when any level is stored
  *              in FP32, FP16 or BF16 (a thread handles 8 such columns).
  *   level_prec m formats, finest first, as for mg_setup.
- *   opt        NULL for defaults; needs nu1 >= 2; autotune is ignored.
+ *   opt        NULL for defaults; needs nu1 >= 2; autotune times the planes
+ *              per thread of each level's stages at mg_bind_workspace, whole
+ *              steps at a time (cached under MGIR_TUNE_CACHE).
  * Errors: MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_PREC.  Workspace as for mg_setup;
  * single-grid calls other than mg_levels / mg_level_n refuse the handle with
  * MG_ERR_STATE. */
@@ -411,7 +416,18 @@ typedef enum {
                                when nparams >= 4). */
 } mg_shape_kind_t;
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
+/* Reading a shape: the values mg_set_shape takes (up to nparams).  On a
+ * many-right-hand-side handle, the stencil kinds and MG_SHAPE_RESTRICT of
+ * levels below the base (only zc, and zcc of the restriction, shape those
+ * kernels).  A batched handle's shapes are read per instance with
+ * mg_get_instance_shape. */
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *params, int nparams);
+
+/* A batched handle: the launch shape of level `level` (below the base) of
+ * instance `inst` -- the stencil kinds, MG_SHAPE_RESTRICT, and MG_SHAPE_UPDATE on
+ * level 0 -- as mg_get_shape returns them.  MG_ERR_STATE on other handles,
+ * MG_ERR_ARG for an instance, level or kind out of range. */
+mg_status_t mg_get_instance_shape(mg_handle h, int inst, int level, int kind, int *params, int nparams);
 
 /* ---- Measurement --------------------------------------------------------
  * Bandwidth probe: one kernel launch that copies (kind 0), reads (1) or

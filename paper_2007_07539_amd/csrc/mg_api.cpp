@@ -138,6 +138,7 @@ struct mg_ctx {
     };
     std::vector<BLaunch> bl;
     size_t off_bmeta = 0, bmeta_bytes = 0, off_active = 0, off_scal_all = 0, off_fin = 0;
+    size_t bmeta_cap = 0;  // workspace bytes reserved for the descriptor image
     int *host_active = nullptr;
     double *host_scal_all = nullptr;
     std::vector<unsigned char> bmeta_img_tmp;
@@ -783,6 +784,9 @@ mg_status_t ensure_graph(mg_ctx *h) {
 void build_batched_plan(mg_ctx *h, char *base);
 hipError_t enq_batched_step(mg_ctx *h, hipStream_t st);
 hipError_t enq_multi_step(mg_ctx *h, hipStream_t st);
+mg_status_t autotune_batched(mg_ctx *h, hipStream_t st);
+mg_status_t autotune_multi(mg_ctx *h, hipStream_t st);
+mg_status_t batched_upload(mg_ctx *h);
 
 mg_status_t need_ws(mg_ctx *h) {
     if (!h) return fail(MG_ERR_ARG, "null handle");
@@ -872,17 +876,69 @@ std::vector<Shape> stencil_candidates(const mg_ctx *h, const LevelPlan &L, bool 
 // grid, level formats and the options that change the kernels.
 constexpr int kTuneVersion = 4;
 
-std::string tune_key(const mg_ctx *h) {
+// The device part of a key: tuning version, architecture, CU count ("" when
+// no device is current).
+std::string device_key() {
     int dev = 0, cus = 0;
     hipDeviceProp_t prop{};
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "v%d|%s|cu%d", kTuneVersion, prop.gcnArchName, cus);
+    return std::string(buf);
+}
+
+std::string tune_key(const mg_ctx *h) {
+    const std::string dk = device_key();
+    if (dk.empty()) return dk;
     char buf[512];
-    int k = std::snprintf(buf, sizeof buf, "v%d|%s|cu%d|d%d|n%d|L%d|nu%d,%d|sc%d|df%d|rh%d|cy%d|p", kTuneVersion,
-                          prop.gcnArchName, cus, h->dim, h->n, h->nl, h->opt.nu1, h->opt.nu2,
-                          h->opt.residual_scaling, h->opt.defer_update, h->opt.rescale_half, h->opt.cycles_per_step);
+    int k = std::snprintf(buf, sizeof buf, "%s|d%d|n%d|L%d|nu%d,%d|sc%d|df%d|rh%d|cy%d|p", dk.c_str(), h->dim, h->n,
+                          h->nl, h->opt.nu1, h->opt.nu2, h->opt.residual_scaling, h->opt.defer_update,
+                          h->opt.rescale_half, h->opt.cycles_per_step);
     for (int l = 0; l < h->nl && k < (int)sizeof buf - 4; ++l) k += std::snprintf(buf + k, sizeof buf - k, "%d", h->lv[l].prec);
     return std::string(buf);
+}
+
+// The integers stored under key in the MGIR_TUNE_CACHE file (false: none).
+bool cache_read(const std::string &key, std::vector<int> &v) {
+    const char *path = std::getenv("MGIR_TUNE_CACHE");
+    if (!path || !*path || key.empty()) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    char chunk[4096];
+    while (!found && std::fgets(chunk, sizeof chunk, f)) {
+        line += chunk;
+        if (line.empty() || line.back() != '\n') continue;  // a line longer than the chunk
+        const size_t tab = line.find('\t');
+        if (tab != std::string::npos && line.compare(0, tab, key) == 0 && tab == key.size()) {
+            v.clear();
+            const char *p = line.c_str() + tab + 1;
+            for (;;) {
+                char *end = nullptr;
+                const long x = std::strtol(p, &end, 10);
+                if (end == p) break;
+                v.push_back((int)x);
+                p = end;
+            }
+            found = true;
+        }
+        line.clear();
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_write(const std::string &key, const std::vector<int> &v) {
+    const char *path = std::getenv("MGIR_TUNE_CACHE");
+    if (!path || !*path || key.empty()) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t", key.c_str());
+    for (size_t i = 0; i < v.size(); ++i) std::fprintf(f, i ? " %d" : "%d", v[i]);
+    std::fprintf(f, "\n");
+    std::fclose(f);
 }
 
 // The tuned state as integers: per level the three stencil shapes, the
@@ -946,40 +1002,14 @@ bool apply_tune_state(mg_ctx *h, const std::vector<int> &v) {
 }
 
 bool tune_cache_load(mg_ctx *h, const std::string &key) {
-    const char *path = std::getenv("MGIR_TUNE_CACHE");
-    if (!path || !*path || key.empty()) return false;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return false;
-    char line[8192];
-    bool ok = false;
-    while (!ok && std::fgets(line, sizeof line, f)) {
-        char *tab = std::strchr(line, '\t');
-        if (!tab || std::string(line, tab - line) != key) continue;
-        std::vector<int> v;
-        for (char *p = tab + 1; *p && *p != '\n';) {
-            char *end = nullptr;
-            const long x = std::strtol(p, &end, 10);
-            if (end == p) break;
-            v.push_back((int)x);
-            p = end;
-        }
-        ok = apply_tune_state(h, v);
-    }
-    std::fclose(f);
-    return ok;
+    std::vector<int> v;
+    return cache_read(key, v) && apply_tune_state(h, v);
 }
 
 void tune_cache_store(const mg_ctx *h, const std::string &key) {
-    const char *path = std::getenv("MGIR_TUNE_CACHE");
-    if (!path || !*path || key.empty()) return;
-    FILE *f = std::fopen(path, "a");
-    if (!f) return;
     std::vector<int> v;
     tune_state(h, v);
-    std::fprintf(f, "%s\t", key.c_str());
-    for (size_t i = 0; i < v.size(); ++i) std::fprintf(f, i ? " %d" : "%d", v[i]);
-    std::fprintf(f, "\n");
-    std::fclose(f);
+    cache_write(key, v);
 }
 
 mg_status_t autotune_timed(mg_ctx *h, hipStream_t st);
@@ -1124,6 +1154,28 @@ mg_status_t autotune_timed(mg_ctx *h, hipStream_t st) {
     }
     HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
     HIPCHK(hipStreamSynchronize(st));
+    return MG_OK;
+}
+}  // namespace
+
+namespace {
+// The stencil-family or restriction shape of one level, as mg_get_shape returns it.
+mg_status_t level_shape(const LevelPlan &L, int level, int kind, int *p, int np) {
+    const bool stencil_kind = kind == MG_SHAPE_STENCIL || kind == MG_SHAPE_SMOOTH || kind == MG_SHAPE_SWEEP ||
+                              kind == MG_SHAPE_PROLONG || (kind == MG_SHAPE_UPDATE && level == 0);
+    if (stencil_kind && np >= 5) {
+        const Shape &S = kind == MG_SHAPE_UPDATE   ? L.osh
+                         : kind == MG_SHAPE_SMOOTH  ? L.shs[SH_SMOOTH]
+                         : kind == MG_SHAPE_PROLONG ? L.shs[SH_PROLONG]
+                                                    : L.shs[SH_SWEEP];
+        p[0] = S.V, p[1] = S.zc, p[2] = S.bs, p[3] = S.xcd, p[4] = S.ty;
+        if (np >= 6) p[5] = S.dp;
+        if (np >= 7) p[6] = S.sg;
+    } else if (kind == MG_SHAPE_RESTRICT && np >= 4) {
+        p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc, p[3] = L.rsh.pipe;
+    } else {
+        return fail(MG_ERR_ARG, "bad kind or too few values");
+    }
     return MG_OK;
 }
 }  // namespace
@@ -1378,6 +1430,7 @@ mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *st
         const int K = h->nrhs;
         if (!h->host_mask) HIPCHK(hipHostMalloc((void **)&h->host_mask, 2 * sizeof(int) * K, hipHostMallocDefault));
         if (!h->host_scal_m) HIPCHK(hipHostMalloc((void **)&h->host_scal_m, 4 * sizeof(double) * K, hipHostMallocDefault));
+        if (h->opt.autotune) return autotune_multi(h, st);
         return MG_OK;
     }
     if (h->batched) {
@@ -1385,11 +1438,8 @@ mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *st
         if (!h->host_active) HIPCHK(hipHostMalloc((void **)&h->host_active, sizeof(int) * ni, hipHostMallocDefault));
         if (!h->host_scal_all)
             HIPCHK(hipHostMalloc((void **)&h->host_scal_all, 4 * sizeof(double) * ni, hipHostMallocDefault));
-        build_batched_plan(h, h->ws);
-        HIPCHK(hipMemcpy(h->ws + h->off_bmeta, h->bmeta_img_tmp.data(), h->bmeta_img_tmp.size(),
-                         hipMemcpyHostToDevice));
-        h->bmeta_img_tmp.clear();
-        return MG_OK;
+        if (h->opt.autotune) return autotune_batched(h, st);
+        return batched_upload(h);
     }
     if (h->opt.autotune && !h->q1) {
         mg_status_t s = autotune(h, st);
@@ -1806,7 +1856,11 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
 
 mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
     if (!h || !p) return fail(MG_ERR_ARG, "null argument");
-    if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
+    if (h->batched) return fail(MG_ERR_STATE, "a batched handle's shapes are read with mg_get_instance_shape");
+    if (h->nrhs) {
+        if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
+        return level_shape(h->lv[level], level, kind, p, np);
+    }
     if (kind == MG_SHAPE_TAIL) {
         if (np < 1) return fail(MG_ERR_ARG, "too few values");
         p[0] = h->tail_on ? 1 : 0;
@@ -1828,23 +1882,22 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
         return MG_OK;
     }
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
-    const LevelPlan &L = h->lv[level];
-    const bool stencil_kind = kind == MG_SHAPE_STENCIL || kind == MG_SHAPE_SMOOTH || kind == MG_SHAPE_SWEEP ||
-                              kind == MG_SHAPE_PROLONG || (kind == MG_SHAPE_UPDATE && level == 0);
-    if (stencil_kind && np >= 5) {
-        const Shape &S = kind == MG_SHAPE_UPDATE   ? L.osh
-                         : kind == MG_SHAPE_SMOOTH  ? L.shs[SH_SMOOTH]
-                         : kind == MG_SHAPE_PROLONG ? L.shs[SH_PROLONG]
-                                                    : L.shs[SH_SWEEP];
-        p[0] = S.V, p[1] = S.zc, p[2] = S.bs, p[3] = S.xcd, p[4] = S.ty;
-        if (np >= 6) p[5] = S.dp;
-        if (np >= 7) p[6] = S.sg;
-    } else if (kind == MG_SHAPE_RESTRICT && np >= 4) {
-        p[0] = L.rsh.V, p[1] = L.rsh.tyc, p[2] = L.rsh.zcc, p[3] = L.rsh.pipe;
-    } else {
-        return fail(MG_ERR_ARG, "bad kind or too few values");
+    return level_shape(h->lv[level], level, kind, p, np);
+}
+
+mg_status_t mg_get_instance_shape(mg_handle h, int inst, int level, int kind, int *p, int np) {
+    if (!h || !p) return fail(MG_ERR_ARG, "null argument");
+    if (!h->batched) return fail(MG_ERR_STATE, "not a batched handle");
+    if (inst < 0 || inst >= (int)h->inst.size()) return fail(MG_ERR_ARG, "no instance %d", inst);
+    const auto &I = h->inst[inst];
+    if (level < 0 || level >= I.nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);
+    if (kind == MG_SHAPE_UPDATE) {
+        if (level != 0) return fail(MG_ERR_ARG, "the update runs on level 0 only");
+        LevelPlan L = I.lv[0];
+        L.osh = I.osh;
+        return level_shape(L, 0, kind, p, np);
     }
-    return MG_OK;
+    return level_shape(I.lv[level], level, kind, p, np);
 }
 
 mg_status_t mg_bandwidth_probe(void *dst, const void *src, size_t bytes, int kind, int blocks, void *stream) {
@@ -2227,6 +2280,148 @@ hipError_t enq_batched_step(mg_ctx *h, hipStream_t st) {
                           hipMemcpyDeviceToHost, st);
 }
 
+// ---- batched autotuner ---------------------------------------------------------
+// Launch shapes are chosen per class of levels (pitch and format): every level
+// of the class, in every instance, takes the class's shape, and the choice
+// only changes how the work is cut (every shape forms the same roundings).  A
+// candidate is timed as a whole batched refinement step with every instance
+// active, class by class from the largest pitch, stencil shape first, then the
+// restriction shape.
+struct BClass {
+    int P, prec;
+};
+
+std::vector<BClass> batched_classes(const mg_ctx *h) {
+    std::vector<BClass> cl;
+    for (const auto &I : h->inst)
+        for (int l = 0; l + 1 < I.nl; ++l) {
+            const LevelPlan &L = I.lv[l];
+            if (L.P < 16) continue;
+            bool seen = false;
+            for (const auto &c : cl) seen = seen || (c.P == L.P && c.prec == L.prec);
+            if (!seen) cl.push_back(BClass{L.P, L.prec});
+        }
+    std::sort(cl.begin(), cl.end(), [](const BClass &a, const BClass &b) { return a.P > b.P || (a.P == b.P && a.prec < b.prec); });
+    return cl;
+}
+
+template <class F> void for_class(mg_ctx *h, const BClass &c, F &&f) {
+    for (auto &I : h->inst)
+        for (int l = 0; l + 1 < I.nl; ++l)
+            if (I.lv[l].P == c.P && I.lv[l].prec == c.prec) f(I.lv[l]);
+}
+
+std::string batched_tune_key(const mg_ctx *h) {
+    const std::string dk = device_key();
+    if (dk.empty()) return dk;
+    std::string k = dk + "|batched|nu" + std::to_string(h->opt.nu1) + "," + std::to_string(h->opt.nu2) + "|sc" +
+                    std::to_string(h->opt.residual_scaling) + "|p";
+    for (int p : h->bprec) k += std::to_string(p);
+    std::vector<int> ns;
+    for (const auto &I : h->inst) ns.push_back(I.n);
+    std::sort(ns.begin(), ns.end());
+    for (size_t i = 0; i < ns.size();) {
+        size_t j = i;
+        while (j < ns.size() && ns[j] == ns[i]) ++j;
+        k += "|" + std::to_string(ns[i]) + "x" + std::to_string(j - i);
+        i = j;
+    }
+    return k;
+}
+
+// Build the plan for the current shapes and copy its descriptors into the
+// workspace; MG_ERR_WORKSPACE (nothing copied) when they exceed the room
+// reserved for them.
+mg_status_t batched_upload(mg_ctx *h) {
+    build_batched_plan(h, nullptr);
+    if (h->bmeta_bytes > h->bmeta_cap)
+        return fail(MG_ERR_WORKSPACE, "batched plan of %zu bytes exceeds its %zu", h->bmeta_bytes, h->bmeta_cap);
+    build_batched_plan(h, h->ws);
+    HIPCHK(hipMemcpy(h->ws + h->off_bmeta, h->bmeta_img_tmp.data(), h->bmeta_img_tmp.size(), hipMemcpyHostToDevice));
+    h->bmeta_img_tmp.clear();
+    return MG_OK;
+}
+
+// state: per class {P, prec, stencil V, zc, ty, restriction V, tyc, zcc, pipe}
+constexpr int kBClassInts = 9;
+
+bool apply_batched_state(mg_ctx *h, const std::vector<int> &v) {
+    const std::vector<BClass> cl = batched_classes(h);
+    if (v.size() != cl.size() * kBClassInts) return false;
+    for (size_t c = 0; c < cl.size(); ++c) {
+        const int *q = v.data() + c * kBClassInts;
+        if (q[0] != cl[c].P || q[1] != cl[c].prec) return false;
+        LevelPlan probe;
+        probe.P = cl[c].P, probe.prec = cl[c].prec;
+        const Shape sh{q[2], q[3], 256, 1, q[4]};
+        const RShape rs{q[5], q[6], q[7], q[8]};
+        if (!stencil_ok(h, probe, sh) || !restrict_ok(h, probe, rs)) return false;
+    }
+    for (size_t c = 0; c < cl.size(); ++c) {
+        const int *q = v.data() + c * kBClassInts;
+        const Shape sh{q[2], q[3], 256, 1, q[4]};
+        const RShape rs{q[5], q[6], q[7], q[8]};
+        for_class(h, cl[c], [&](LevelPlan &L) {
+            L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = sh;
+            L.rsh = rs;
+        });
+    }
+    return true;
+}
+
+mg_status_t autotune_batched(mg_ctx *h, hipStream_t st) {
+    const std::string key = batched_tune_key(h);
+    std::vector<int> v;
+    if (cache_read(key, v) && apply_batched_state(h, v)) return batched_upload(h);
+    const int ni = (int)h->inst.size();
+    for (int i = 0; i < ni; ++i) h->host_active[i] = 1;
+    HIPCHK(hipMemcpy(h->ws + h->off_active, h->host_active, sizeof(int) * ni, hipMemcpyHostToDevice));
+    auto step_ms = [&]() -> float {
+        if (batched_upload(h) != MG_OK) return 1e30f;
+        return time_ms(st, [&]() { return enq_batched_step(h, st); }, 2);
+    };
+    const std::vector<BClass> cl = batched_classes(h);
+    v.clear();
+    for (const BClass &c : cl) {
+        LevelPlan probe;
+        probe.P = c.P, probe.prec = c.prec;
+        Shape bs;
+        RShape br;
+        for_class(h, c, [&](LevelPlan &L) { bs = L.shs[SH_SWEEP], br = L.rsh; });
+        float best = step_ms();
+        for (int V : {4, 8})
+            for (int ty : {0, 2, 4, 6, 10, 14})
+                for (int zc : {2, 4, 8, 16, 32}) {
+                    const Shape s{V, zc, 256, 1, ty};
+                    if ((ty == 0 && zc < 8) || !stencil_ok(h, probe, s)) continue;
+                    if (c.prec == P_F64 && V == 8 && ty > 0) continue;  // FP64 rows spill at V = 8
+                    for_class(h, c, [&](LevelPlan &L) { L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = s; });
+                    const float t = step_ms();
+                    if (t < best) best = t, bs = s;
+                }
+        for_class(h, c, [&](LevelPlan &L) { L.shs[SH_SMOOTH] = L.shs[SH_SWEEP] = L.shs[SH_PROLONG] = bs; });
+        for (int V : {4, 8})
+            for (int tyc : {1, 2, 3, 5, 7})
+                for (int zcc : {2, 4, 8, 16})
+                    for (int pipe : {0, 1, 2}) {
+                        const RShape r{V, tyc, zcc, pipe};
+                        if (!restrict_ok(h, probe, r)) continue;
+                        for_class(h, c, [&](LevelPlan &L) { L.rsh = r; });
+                        const float t = step_ms();
+                        if (t < best) best = t, br = r;
+                    }
+        for_class(h, c, [&](LevelPlan &L) { L.rsh = br; });
+        v.insert(v.end(), {c.P, c.prec, bs.V, bs.zc, bs.ty, br.V, br.tyc, br.zcc, br.pipe});
+    }
+    mg_status_t s = batched_upload(h);
+    if (s != MG_OK) return s;
+    HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s = batched_upload(h);  // (the descriptors lie in the workspace just cleared)
+    if (s == MG_OK) cache_write(key, v);
+    return s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2314,7 +2509,10 @@ mg_status_t mg_setup_batched(mg_handle *out, int dim, int ninst, const int *n, c
     h->off_active = off, off += align_up((size_t)ninst * sizeof(int), 256);
     h->off_bmeta = off;
     build_batched_plan(h, nullptr);
-    off += h->bmeta_bytes;
+    // room for the plans of other launch shapes (the autotuner's candidates
+    // with shorter plane chunks have more work items)
+    h->bmeta_cap = align_up(4 * h->bmeta_bytes, 256);
+    off += h->bmeta_cap;
     h->ws_need = off;
     h->nl = Lmax;
     h->n = n[0];
@@ -2580,6 +2778,73 @@ hipError_t enq_multi_step(mg_ctx *h, hipStream_t st) {
     RUN(h, st, "norm_finalize", 0, 16.0 * h->m_upd_blocks * K,
         launch_m_finalize(part(h), h->m_upd_blocks, K, sc, act, h->ascale, st));
     return hipMemcpyAsync(h->host_scal_m, sc, 4 * sizeof(double) * K, hipMemcpyDeviceToHost, st);
+}
+
+// ---- many-right-hand-side autotuner --------------------------------------------
+// Per level, the planes per thread of the first smoothing, the sweeps (and the
+// residual pass of the restriction), the prolongation and the coarse planes
+// per block of the restriction, each timed as a whole refinement step with
+// every column active (the update keeps its shape: its block count sizes the
+// reduction partials).  Every choice forms the same roundings.
+std::string multi_tune_key(const mg_ctx *h) {
+    const std::string dk = device_key();
+    if (dk.empty()) return dk;
+    std::string k = dk + "|multi|n" + std::to_string(h->n) + "|K" + std::to_string(h->nrhs) + "|nu" +
+                    std::to_string(h->opt.nu1) + "," + std::to_string(h->opt.nu2) + "|sc" +
+                    std::to_string(h->opt.residual_scaling) + "|p";
+    for (int l = 0; l < h->nl; ++l) k += std::to_string(h->lv[l].prec);
+    return k;
+}
+
+constexpr int kMLevelInts = 4;  // zc of smoothing, sweeps, prolongation; zcc of the restriction
+
+bool apply_multi_state(mg_ctx *h, const std::vector<int> &v) {
+    if (v.size() != (size_t)(h->nl - 1) * kMLevelInts) return false;
+    for (int l = 0; l + 1 < h->nl; ++l) {
+        const int *q = v.data() + l * kMLevelInts, P = h->lv[l].P;
+        for (int j = 0; j < 3; ++j)
+            if (q[j] < 1 || q[j] > std::max(1, P - 1)) return false;
+        if (q[3] < 1 || q[3] > std::max(1, P / 2 - 1)) return false;
+    }
+    for (int l = 0; l + 1 < h->nl; ++l) {
+        const int *q = v.data() + l * kMLevelInts;
+        LevelPlan &L = h->lv[l];
+        L.shs[SH_SMOOTH].zc = q[0], L.shs[SH_SWEEP].zc = q[1], L.shs[SH_PROLONG].zc = q[2], L.rsh.zcc = q[3];
+    }
+    return true;
+}
+
+mg_status_t autotune_multi(mg_ctx *h, hipStream_t st) {
+    const std::string key = multi_tune_key(h);
+    std::vector<int> v;
+    if (cache_read(key, v) && apply_multi_state(h, v)) return MG_OK;
+    const int K = h->nrhs;
+    for (int k = 0; k < K; ++k) h->host_mask[k] = 1;
+    HIPCHK(hipMemcpy(h->ws + h->off_act, h->host_mask, sizeof(int) * K, hipMemcpyHostToDevice));
+    auto step_ms = [&]() { return time_ms(st, [&]() { return enq_multi_step(h, st); }, 2); };
+    v.clear();
+    for (int l = 0; l + 1 < h->nl; ++l) {
+        LevelPlan &L = h->lv[l];
+        int *knobs[4] = {&L.shs[SH_SMOOTH].zc, &L.shs[SH_SWEEP].zc, &L.shs[SH_PROLONG].zc, &L.rsh.zcc};
+        const int lim[4] = {L.P - 1, L.P - 1, L.P - 1, L.P / 2 - 1};
+        for (int j = 0; j < 4; ++j) {
+            if (lim[j] < 2) continue;
+            int bestv = *knobs[j];
+            float best = step_ms();
+            for (int zc : {1, 2, 4, 8, 16, 32, 64}) {
+                if (zc > lim[j] || zc == bestv) continue;
+                *knobs[j] = zc;
+                const float t = step_ms();
+                if (t < best) best = t, bestv = zc;
+            }
+            *knobs[j] = bestv;
+        }
+        v.insert(v.end(), {L.shs[SH_SMOOTH].zc, L.shs[SH_SWEEP].zc, L.shs[SH_PROLONG].zc, L.rsh.zcc});
+    }
+    HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
+    HIPCHK(hipStreamSynchronize(st));
+    cache_write(key, v);
+    return MG_OK;
 }
 
 }  // namespace

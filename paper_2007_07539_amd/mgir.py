@@ -39,7 +39,7 @@ EXPORTS = ("mg_default_options", "mg_setup", "mg_workspace_size", "mg_bind_works
            "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_write", "mg_level_read", "mg_stage",
            "mg_levels", "mg_level_n", "mg_profile_step", "mg_set_shape", "mg_get_shape", "mg_bandwidth_probe",
            "mg_setup_batched", "ir_solve_batched", "mg_instances", "mg_setup_multi", "ir_solve_multi",
-           "mg_rhs_count", "mg_alpha_shift", "mg_vcycle_noalloc")
+           "mg_rhs_count", "mg_alpha_shift", "mg_vcycle_noalloc", "mg_get_instance_shape")
 SHAPE_STENCIL, SHAPE_RESTRICT, SHAPE_UPDATE, SHAPE_SMOOTH, SHAPE_SWEEP, SHAPE_PROLONG, SHAPE_TAIL, SHAPE_FUSE, \
     SHAPE_FUSE_SR = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int)]
     lib.mg_set_shape.argtypes = [H, i, i, ctypes.POINTER(ctypes.c_int), i]
     lib.mg_get_shape.argtypes = [H, i, i, ctypes.POINTER(ctypes.c_int), i]
+    lib.mg_get_instance_shape.argtypes = [H, i, i, i, ctypes.POINTER(ctypes.c_int), i]
     lib.mg_bandwidth_probe.argtypes = [vp, vp, ctypes.c_size_t, i, i, vp]
     lib.mg_setup_batched.argtypes = [ctypes.POINTER(H), i, i, ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Options)]
@@ -319,14 +320,15 @@ class BatchedSolver:
     """
 
     def __init__(self, sizes, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True, max_iter=100,
-                 rtol=1e-10, use_initial_guess=False, use_graph=True, device=None, stream=None):
+                 rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False, device=None, stream=None):
         self.lib = load()
         self.sizes = [int(n) for n in sizes]
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         o = default_options()
         o.nu1, o.nu2, o.omega = nu1, nu2, omega
         o.residual_scaling, o.max_iter, o.rtol = int(bool(residual_scaling)), max_iter, rtol
-        o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), 0
+        o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), \
+            int(bool(autotune))
         self.options = o
         lmax = max(int(n + 1).bit_length() - 1 for n in self.sizes)
         if level_prec is None:
@@ -385,6 +387,13 @@ class BatchedSolver:
     def profile_step(self, stream=None, cap: int = 1024):
         return Solver.profile_step(self, stream, cap)
 
+    def get_shape(self, inst: int, level: int, kind: int, count: int | None = None):
+        """Instance inst's shape of level and kind (see Solver.get_shape)."""
+        arr = (ctypes.c_int * 7)()
+        _check(self.lib.mg_get_instance_shape(self._h, inst, level, kind, arr, 7), "mg_get_instance_shape")
+        n = (4 if kind == SHAPE_RESTRICT else 6) if count is None else count
+        return list(arr[:n])
+
 
 class MultiSolver:
     """Many right-hand sides on one 3-D grid: ``mg_setup_multi`` + ``ir_solve_multi``.
@@ -394,14 +403,16 @@ class MultiSolver:
     """
 
     def __init__(self, n: int, nrhs: int, level_prec=None, *, nu1=2, nu2=2, omega=0.8, residual_scaling=True,
-                 max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, device=None, stream=None):
+                 max_iter=100, rtol=1e-10, use_initial_guess=False, use_graph=True, autotune=False, device=None,
+                 stream=None):
         self.lib = load()
         self.n, self.nrhs = int(n), int(nrhs)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         o = default_options()
         o.nu1, o.nu2, o.omega = nu1, nu2, omega
         o.residual_scaling, o.max_iter, o.rtol = int(bool(residual_scaling)), max_iter, rtol
-        o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), 0
+        o.use_initial_guess, o.use_graph, o.autotune = int(bool(use_initial_guess)), int(bool(use_graph)), \
+            int(bool(autotune))
         self.options = o
         m = int(n + 1).bit_length() - 1
         if level_prec is None:
@@ -450,6 +461,11 @@ class MultiSolver:
 
     def profile_step(self, stream=None, cap: int = 1024):
         return Solver.profile_step(self, stream, cap)
+
+    def get_shape(self, level: int, kind: int, count: int | None = None):
+        """Level's shape (see Solver.get_shape; zc, and zcc of the restriction,
+        are the values that shape these kernels)."""
+        return Solver.get_shape(self, level, kind, count)
 
 
 def bandwidth_probe(dst: torch.Tensor, src: torch.Tensor, kind: int, blocks: int = 4096, stream=None):

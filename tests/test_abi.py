@@ -133,6 +133,20 @@ def test_batched_workspace_and_refusals(lib):
         assert lib.ir_solve_batched(h, ptrs, ptrs, None, None) == mgir.MG_ERR_WORKSPACE
         assert lib.mg_level_n(h, 0, ctypes.byref(k)) == mgir.MG_ERR_STATE
         assert lib.mg_get_shape(h, 0, 0, (ctypes.c_int * 5)(), 5) == mgir.MG_ERR_STATE
+        # shapes are read per instance: instance 2 (n = 127) has six levels below its base
+        arr = (ctypes.c_int * 7)()
+        for kind in (mgir.SHAPE_STENCIL, mgir.SHAPE_SMOOTH, mgir.SHAPE_SWEEP, mgir.SHAPE_PROLONG):
+            assert lib.mg_get_instance_shape(h, 2, 5, kind, arr, 7) == mgir.MG_OK
+            assert arr[0] in (4, 8) and 1 <= arr[1] <= 127
+        assert lib.mg_get_instance_shape(h, 2, 0, mgir.SHAPE_UPDATE, arr, 7) == mgir.MG_OK and arr[0] == 4
+        assert lib.mg_get_instance_shape(h, 2, 0, mgir.SHAPE_RESTRICT, arr, 4) == mgir.MG_OK
+        assert arr[0] in (4, 8) and arr[1] >= 1 and arr[2] >= 1
+        assert lib.mg_get_instance_shape(h, 2, 6, mgir.SHAPE_STENCIL, arr, 7) == mgir.MG_ERR_ARG  # the base
+        assert lib.mg_get_instance_shape(h, 1, 2, mgir.SHAPE_STENCIL, arr, 7) == mgir.MG_ERR_ARG  # n = 7: 2 levels
+        assert lib.mg_get_instance_shape(h, 4, 0, mgir.SHAPE_STENCIL, arr, 7) == mgir.MG_ERR_ARG
+        assert lib.mg_get_instance_shape(h, -1, 0, mgir.SHAPE_STENCIL, arr, 7) == mgir.MG_ERR_ARG
+        assert lib.mg_get_instance_shape(h, 2, 1, mgir.SHAPE_UPDATE, arr, 7) == mgir.MG_ERR_ARG
+        assert lib.mg_get_instance_shape(h, 2, 0, mgir.SHAPE_TAIL, arr, 7) == mgir.MG_ERR_ARG
     finally:
         assert lib.mg_destroy(h) == mgir.MG_OK
     # a single-grid handle refuses the batched solve
@@ -169,6 +183,14 @@ def test_multi_setup_validation_and_workspace(lib):
         assert lib.mg_level_n(h, 1, ctypes.byref(k)) == 0 and k.value == 63
         assert lib.ir_solve_multi(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == mgir.MG_ERR_WORKSPACE
         assert lib.mg_vcycle(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == mgir.MG_ERR_WORKSPACE
+        # the stencil and restriction shapes of the levels below the base can be read
+        arr = (ctypes.c_int * 7)()
+        for lvl in range(6):
+            assert lib.mg_get_shape(h, lvl, mgir.SHAPE_SWEEP, arr, 7) == mgir.MG_OK and arr[1] >= 1
+            assert lib.mg_get_shape(h, lvl, mgir.SHAPE_RESTRICT, arr, 4) == mgir.MG_OK and arr[2] >= 1
+        assert lib.mg_get_shape(h, 6, mgir.SHAPE_SWEEP, arr, 7) == mgir.MG_ERR_ARG
+        assert lib.mg_get_shape(h, 0, mgir.SHAPE_TAIL, arr, 1) == mgir.MG_ERR_ARG
+        assert lib.mg_get_instance_shape(h, 0, 0, mgir.SHAPE_SWEEP, arr, 7) == mgir.MG_ERR_STATE
     finally:
         lib.mg_destroy(h)
     assert lib.mg_setup(ctypes.byref(h), 3, 15, 0, None, None) == mgir.MG_OK

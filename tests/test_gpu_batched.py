@@ -146,3 +146,53 @@ def test_batched_workload_64_instances(dev, ref):
             assert _true_rel(ref, rhs[i], us[i].cpu().numpy()) <= 1e-10
     del us, bsv
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["f16", "f64"])
+def test_batched_autotuned_bitwise_and_cached(dev, tmp_path, monkeypatch, name):
+    """The batched autotuner picks launch shapes per class of levels (pitch and
+    format) by timing whole batched steps; every shape forms the same
+    roundings, so the tuned handle's solutions equal the untuned handle's and
+    each instance's single-grid solve bit for bit.  With MGIR_TUNE_CACHE set the
+    choice is stored once and a second handle reads it back."""
+    sizes = [63, 7, 127, 15, 63]
+    print(f"batched autotune {name} sizes={sizes}", flush=True)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MGIR_TUNE_CACHE", str(path))
+    lmax = max(W.levels_for(n) for n in sizes)
+    prec = W.precision_map(name, lmax)
+    scaling = name != "f64"
+    rng = np.random.default_rng(205)
+    bs = [torch.from_numpy(rng.uniform(-1, 1, (n,) * 3)).to(dev) for n in sizes]
+    tuned = mgir.BatchedSolver(sizes, prec, residual_scaling=scaling, autotune=True)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and "|batched|" in lines[0]
+    kinds = (mgir.SHAPE_SMOOTH, mgir.SHAPE_SWEEP, mgir.SHAPE_PROLONG, mgir.SHAPE_RESTRICT)
+
+    def shapes(s):
+        return [s.get_shape(i, l, k) for i, n in enumerate(sizes) for l in range(W.levels_for(n) - 1) for k in kinds]
+
+    # one shape per tuned class (pitch >= 16): every level of the class takes it
+    sh = shapes(tuned)
+    per = {}
+    for i, n in enumerate(sizes):
+        for l in range(W.levels_for(n) - 1):
+            if (n + 1) >> l < 16:
+                continue
+            key = ((n + 1) >> l, tuned.instance_prec(i)[l])
+            val = [tuned.get_shape(i, l, k) for k in kinds]
+            assert per.setdefault(key, val) == val, (i, l)
+    again = mgir.BatchedSolver(sizes, prec, residual_scaling=scaling, autotune=True)
+    assert path.read_text().splitlines() == lines  # read back, not tuned again
+    assert shapes(again) == sh
+    plain = mgir.BatchedSolver(sizes, prec, residual_scaling=scaling)
+    ut, rt, st = tuned.solve(bs)
+    up, rp, sp = plain.solve(bs)
+    ua, ra, sa = again.solve(bs)
+    assert st == sp == sa == 0
+    for i, n in enumerate(sizes):
+        assert rt[i].history == rp[i].history == ra[i].history, (i, n)
+        assert torch.equal(ut[i], up[i]) and torch.equal(ut[i], ua[i]), (i, n)
+        u1, r1 = _single(n, tuned.instance_prec(i), bs[i], residual_scaling=scaling)
+        assert r1.iterations == rt[i].iterations and torch.equal(ut[i], u1), (i, n)
+        assert rt[i].rel_residual <= 1e-10

@@ -150,3 +150,37 @@ def test_multi_workload_127_32(dev, ref):
     _compare_columns(dev, n, prec, b, u, res, [0, 13, 31])
     uj = u[..., 0].contiguous().cpu().numpy()
     assert _true_rel(ref, np.ascontiguousarray(b[..., 0]), uj) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["f16", "f64"])
+def test_multi_autotuned_bitwise_and_cached(dev, tmp_path, monkeypatch, name):
+    """The many-right-hand-side autotuner times each level's planes per thread
+    over whole steps; the choice only cuts the work differently, so the tuned
+    handle's solution equals the untuned one bit for bit.  With MGIR_TUNE_CACHE
+    set the choice is stored once and read back by a second handle."""
+    n, k = 31, 16
+    print(f"multi autotune {name} n={n} k={k}", flush=True)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MGIR_TUNE_CACHE", str(path))
+    prec = W.precision_map(name, W.levels_for(n))
+    scaling = name != "f64"
+    b = torch.from_numpy(_rhs(n, k, 320, emax=2.0)).to(dev)
+    tuned = mgir.MultiSolver(n, k, prec, residual_scaling=scaling, autotune=True)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and "|multi|" in lines[0]
+    kinds = (mgir.SHAPE_SMOOTH, mgir.SHAPE_SWEEP, mgir.SHAPE_PROLONG, mgir.SHAPE_RESTRICT)
+
+    def shapes(s):
+        return [s.get_shape(l, kk) for l in range(W.levels_for(n) - 1) for kk in kinds]
+
+    again = mgir.MultiSolver(n, k, prec, residual_scaling=scaling, autotune=True)
+    assert path.read_text().splitlines() == lines
+    assert shapes(again) == shapes(tuned)
+    ut, rt, st = tuned.solve(b)
+    up, rp, sp = mgir.MultiSolver(n, k, prec, residual_scaling=scaling).solve(b)
+    ua, ra, sa = again.solve(b)
+    assert st == sp == sa == 0
+    for j in range(k):
+        assert rt[j].history == rp[j].history == ra[j].history, j
+    assert torch.equal(ut, up) and torch.equal(ut, ua)
+    assert max(r.rel_residual for r in rt) <= 1e-10
