@@ -111,7 +111,10 @@ template <class TF, class TC> struct FProl {
     // Canonical order of the interpolation sums (every kernel uses it, so all
     // of them round alike): for each contributing coarse row Y_b, first the z
     // sum t_b(X) = sum_a w_Z e_c(X, Y_b, Z_a) over the interior planes Z_a,
-    // then s(X) = sum_b w_Y t_b(X), then the x weights.
+    // then s(X) = sum_b w_Y t_b(X), then the x weights.  The weights are
+    // powers of two, and scaling by a power of two commutes with rounding
+    // (away from the underflow range), so a kernel may also form the plain
+    // sums in this order and apply the product of the weights once.
     // rowsum: s(X) for X = x0/2 .. x0/2 + V/2 (the last may be the ghost Pc).
     template <int D, int V> __device__ __forceinline__ void rowsum(int x0, int y, int z, PA (&s)[V / 2 + 1]) const {
         constexpr int H = V / 2;
@@ -491,17 +494,19 @@ template <class TF, class TC, int V> struct PProl {
     static constexpr int H = V / 2;
     struct Raw {
         RawRow<TF, V> c;
-        RawRow<TC, H> seg[4];
+        RawRow<TC, H> seg[4];  // coarse row (Z_a, Y_b) at a * 2 + b
         TC last[4];
-        int ok;  // bit a*2+b: coarse row (Z_a, Y_b) present
     };
     const TF *__restrict__ c;
     const TC *__restrict__ ec;
     int Pc;
+    // Coarse rows (Z_a, Y_b) for a < nz, b < ny; a row on a ghost plane or
+    // ghost row is fetched as zeros (it adds nothing to the sums).
     __device__ __forceinline__ void fetch(const Grid<3> &g, int x0, int y, int z, Raw &r) const {
-        r.ok = 0;
-        if (g.ghost_row(y, z)) {
+        if (g.ghost_row(y, z)) {  // all zeros: the row's value is zero
             zero_row(r.c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) zero_row(r.seg[k]), r.last[k] = zero_of<TC>();
             return;
         }
         fetch_row<TF, V>(c + g.at(x0, y, z), r.c);
@@ -515,50 +520,55 @@ template <class TF, class TC, int V> struct PProl {
 #pragma unroll
             for (int bb = 0; bb < 2; ++bb) {
                 const int idx = a * 2 + bb;
-                const bool use = a < nz && bb < ny && Zs[a] >= 1 && Zs[a] < Pc && Ys[bb] >= 1 && Ys[bb] < Pc;
-                if (use) {
-                    const TC *base = ec + gc.at(X0, Ys[bb], Zs[a]);
-                    fetch_row<TC, H>(base, r.seg[idx]);
-                    r.last[idx] = (X0 + H < Pc) ? base[H] : zero_of<TC>();
-                    r.ok |= 1 << idx;
+                if (a < nz && bb < ny) {
+                    if (Zs[a] >= 1 && Zs[a] < Pc && Ys[bb] >= 1 && Ys[bb] < Pc) {
+                        const TC *base = ec + gc.at(X0, Ys[bb], Zs[a]);
+                        fetch_row<TC, H>(base, r.seg[idx]);
+                        r.last[idx] = (X0 + H < Pc) ? base[H] : zero_of<TC>();
+                    } else {
+                        zero_row(r.seg[idx]);
+                        r.last[idx] = zero_of<TC>();
+                    }
                 }
             }
         }
     }
+    // The canonical sums with the weights applied once: S(X) = (e(Z_0, Y_0) +
+    // e(Z_1, Y_0)) + (e(Z_0, Y_1) + e(Z_1, Y_1)) over the present terms, then
+    // c + 4 w_Z w_Y S at even x and c + 4 w_Z w_Y (S(X) + S(X+1)) / 2 at odd x.
+    // nz is the same for the whole block (one plane), ny for a whole row.
     __device__ __forceinline__ void value(const Raw &r, int x0, int y, int z, acc (&o)[V], acc (&)[V]) const {
-        int Zs[2], Ys[2];
-        const int nz = FProl<TF, TC>::split(z, Zs);
-        const int ny = FProl<TF, TC>::split(y, Ys);
-        const PA wz = nz == 1 ? PA(1) : PA(0.5), wy = ny == 1 ? PA(1) : PA(0.5);
-        PA s[H + 1];
-#pragma unroll
-        for (int j = 0; j <= H; ++j) s[j] = PA(0);
+        const int nz = (z & 1) ? 2 : 1;
+        const int ny = (y & 1) ? 2 : 1;
+        PA t[2][H + 1];
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb) {
             if (bb < ny) {
-                PA t[H + 1];
+                PA u[H];
+                widen_row<TC, H>(r.seg[bb], u);
 #pragma unroll
-                for (int j = 0; j <= H; ++j) t[j] = PA(0);
+                for (int j = 0; j < H; ++j) t[bb][j] = u[j];
+                t[bb][H] = (PA)widen(r.last[bb]);
+                if (nz == 2) {
+                    PA v[H];
+                    widen_row<TC, H>(r.seg[2 + bb], v);
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    if (r.ok & (1 << (a * 2 + bb))) {
-                        PA v[H];
-                        widen_row<TC, H>(r.seg[a * 2 + bb], v);
-#pragma unroll
-                        for (int j = 0; j < H; ++j) t[j] += wz * v[j];
-                        t[H] += wz * (PA)widen(r.last[a * 2 + bb]);
-                    }
+                    for (int j = 0; j < H; ++j) t[bb][j] += v[j];
+                    t[bb][H] += (PA)widen(r.last[2 + bb]);
                 }
-#pragma unroll
-                for (int j = 0; j <= H; ++j) s[j] += wy * t[j];
             }
         }
+        PA S[H + 1];
+#pragma unroll
+        for (int j = 0; j <= H; ++j) S[j] = ny == 2 ? t[0][j] + t[1][j] : t[0][j];
+        const PA k0 = PA(4) * (nz == 2 ? PA(0.5) : PA(1)) * (ny == 2 ? PA(0.5) : PA(1));
+        const PA k1 = PA(0.5) * k0;
         acc cv[V];
         widen_row<TF, V>(r.c, cv);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-            const PA p = (i & 1) ? PA(0.5) * (s[i >> 1] + s[(i >> 1) + 1]) : s[i >> 1];
-            o[i] = round_to<TF>((PA)cv[i] + PA(4) * p);
+            const PA q = (i & 1) ? S[i >> 1] + S[(i >> 1) + 1] : S[i >> 1];
+            o[i] = round_to<TF>((PA)cv[i] + ((i & 1) ? k1 : k0) * q);
         }
         if (x0 == 0) o[0] = acc(0);
     }

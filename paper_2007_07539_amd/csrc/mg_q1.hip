@@ -168,11 +168,13 @@ __global__ __launch_bounds__(kThreads) void k_q1_sweep4(const T *__restrict__ b,
     q1_weighted4<D, A>(c, o, P, x0 == 0, s);
     q1_load4<T, A>(b + o, bv);
     q1_load4<T, A>(c + o, cv);
+    T ov[4];  // x = 0 (first segment) is the ghost and receives zero
 #pragma unroll
-    for (int i = x0 == 0 ? 1 : 0; i < 4; ++i) {
+    for (int i = 0; i < 4; ++i) {
         const A r = bv[i] - s[i] * q1_scale<D, A>();
-        cout[o + i] = Store<T>::from_acc(fmaT<A>(w, r, cv[i]));
+        ov[i] = (i == 0 && x0 == 0) ? zero_of<T>() : Store<T>::from_acc(fmaT<A>(w, r, cv[i]));
     }
+    store_row<T, 4>(cout + o, ov);
 }
 
 template <int D, class T>
@@ -185,8 +187,10 @@ __global__ __launch_bounds__(kThreads) void k_q1_resid4(const T *__restrict__ b,
     A s[4], bv[4];
     q1_weighted4<D, A>(c, o, P, x0 == 0, s);
     q1_load4<T, A>(b + o, bv);
+    A ov[4];  // x = 0 (first segment) is the ghost and receives zero
 #pragma unroll
-    for (int i = x0 == 0 ? 1 : 0; i < 4; ++i) r[o + i] = bv[i] - s[i] * q1_scale<D, A>();
+    for (int i = 0; i < 4; ++i) ov[i] = (i == 0 && x0 == 0) ? A(0) : bv[i] - s[i] * q1_scale<D, A>();
+    store_row<A, 4>(r + o, ov);
 }
 
 // 3-D, pitch a multiple of 4: the sweep (RESID false: out = c + w (b - S c) in
@@ -228,18 +232,25 @@ __global__ __launch_bounds__(kThreads) void k_q1_march4(const T *__restrict__ b,
         const size_t o = g.at(x0, y, z);
         A bv[4];
         q1_load4<T, A>(b + o, bv);
+        // the four results are stored with one vector store; x = 0 (first
+        // segment) is the ghost and receives zero
+        A ra[4];
+        T rt[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = i + 1;
             const A e = ((A0[k - 1] + A0[k + 1]) + ((Cm[k - 1] + Cm[k + 1]) + (Cp[k - 1] + Cp[k + 1]))) + (Am[k] + Ap[k]);
             const A cn = (Am[k - 1] + Am[k + 1]) + (Ap[k - 1] + Ap[k + 1]);
             const A sc = fmaT<A>(A(32), C0[k], -fmaT<A>(A(2), e, cn)) * q1_scale<3, A>();
-            if (i == 0 && first) continue;
             if (RESID)
-                static_cast<A *>(out)[o + i] = bv[i] - sc;
+                ra[i] = (i == 0 && first) ? A(0) : bv[i] - sc;
             else
-                static_cast<T *>(out)[o + i] = Store<T>::from_acc(fmaT<A>(w, bv[i] - sc, C0[k]));
+                rt[i] = (i == 0 && first) ? zero_of<T>() : Store<T>::from_acc(fmaT<A>(w, bv[i] - sc, C0[k]));
         }
+        if (RESID)
+            store_row<A, 4>(static_cast<A *>(out) + o, ra);
+        else
+            store_row<T, 4>(static_cast<T *>(out) + o, rt);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             Am[k] = A0[k], Cm[k] = C0[k];
@@ -285,6 +296,8 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
             A rv[4], uv[4];
             q1_load4<double, A>(R + o, rv);
             q1_load4<double, A>(U + o, uv);
+            // one vector store each for R and U; x = 0 (first segment) is the
+            // ghost: zero, which adds nothing to the norms
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int k = i + 1;
@@ -292,13 +305,15 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
                     ((A0[k - 1] + A0[k + 1]) + ((Cm[k - 1] + Cm[k + 1]) + (Cp[k - 1] + Cp[k + 1]))) + (Am[k] + Ap[k]);
                 const A cn = (Am[k - 1] + Am[k + 1]) + (Ap[k - 1] + Ap[k + 1]);
                 const A sc = fmaT<A>(A(32), C0[k], -fmaT<A>(A(2), e, cn)) * q1_scale<3, A>();
-                if (i == 0 && first) continue;
-                const double r = fmaT<double>(-a, sc, rv[i]);
-                R[o + i] = r;
-                U[o + i] = fmaT<double>(a * f, C0[k], uv[i]);
+                const bool ghost = i == 0 && first;
+                const double r = ghost ? 0.0 : fmaT<double>(-a, sc, rv[i]);
+                uv[i] = ghost ? 0.0 : fmaT<double>(a * f, C0[k], uv[i]);
+                rv[i] = r;
                 ss += r * r;
                 mx = nanmax(mx, fabs(r));
             }
+            store_row<double, 4>(R + o, rv);
+            store_row<double, 4>(U + o, uv);
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 Am[k] = A0[k], Cm[k] = C0[k];
@@ -383,6 +398,62 @@ __global__ __launch_bounds__(kThreads) void k_q1_prolong_add(TF *__restrict__ c,
         s *= W(D == 3 ? 0.5 : 1.0);
         c[o + i] = store_as<TF>((W)widen(c[o + i]) + s);
     }
+}
+
+// The same on a level whose pitch P is a multiple of 4: segment t covers x0
+// = 4j .. 4j + 3 of one row (x = 0, the ghost, keeps its value), so c is read
+// and written with one vector access; coarse x from 2j to 2j + 2.  Same sums
+// per point as k_q1_prolong_add.
+template <int D, class TF, class TC>
+__global__ __launch_bounds__(kThreads) void k_q1_prolong_add4(TF *__restrict__ c, const TC *__restrict__ ec, int n,
+                                                              int P, int Pc, unsigned NS) {
+    typedef typename std::conditional<sizeof(acc_t<TF>) >= sizeof(acc_t<TC>), acc_t<TF>, acc_t<TC>>::type W;
+    const unsigned t = q1_index(1);
+    if (t >= NS) return;
+    const unsigned ns = (unsigned)P / 4;
+    const unsigned row = t / ns;
+    const int x0 = 4 * (int)(t - row * ns);
+    const int y = D == 3 ? (int)(row % (unsigned)n) + 1 : 0;
+    const int z = D == 3 ? (int)(row / (unsigned)n) + 1 : (int)row + 1;
+    const size_t o = D == 3 ? Grid<3>{P}.at(x0, y, z) : Grid<2>{P}.at(x0, 0, z);
+    const Grid<D> gc{Pc};
+    const int cx = x0 >> 1;
+    auto coarse3 = [&](size_t b, W (&v)[3]) {
+        TC two[2];
+        load_raw<TC, 2>(ec + b, two);  // cx is even: an aligned pair
+        v[0] = (W)widen(two[0]);
+        v[1] = (W)widen(two[1]);
+        v[2] = (W)widen(ec[b + 2]);
+    };
+    W s2[3];
+    const int z0 = z >> 1, z1 = (z + 1) >> 1;
+    if (D == 2) {
+        W a[3], bb[3];
+        coarse3(gc.at(cx, 0, z0), a);
+        coarse3(gc.at(cx, 0, z1), bb);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s2[k] = a[k] + bb[k];
+    } else {
+        const int y0 = y >> 1, y1 = (y + 1) >> 1;
+        W v00[3], v10[3], v01[3], v11[3];
+        coarse3(gc.at(cx, y0, z0), v00);
+        coarse3(gc.at(cx, y1, z0), v10);
+        coarse3(gc.at(cx, y0, z1), v01);
+        coarse3(gc.at(cx, y1, z1), v11);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s2[k] = (v00[k] + v10[k]) + (v01[k] + v11[k]);
+    }
+    TF cv[4];
+    load_raw<TF, 4>(c + o, cv);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int x = x0 + i;
+        if (x == 0) continue;  // the ghost
+        W sx = s2[(x >> 1) - cx] + s2[((x + 1) >> 1) - cx];
+        sx *= W(D == 3 ? 0.5 : 1.0);
+        cv[i] = store_as<TF>((W)widen(cv[i]) + sx);
+    }
+    store_row<TF, 4>(c + o, cv);
 }
 
 // Finest-level update of a refinement step in FP64: U += alpha f c and
@@ -564,8 +635,18 @@ hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *r
 
 template <class TF, class TC>
 hipError_t prolong_t(int D, int n, int P, void *c, const void *ec, hipStream_t st) {
-    const unsigned N = q1_segs(D, n);
     const int Pc = (n - 1) / 2 + 1;
+    if (P % 4 == 0) {
+        const unsigned N = (unsigned)(P / 4) * (D == 3 ? (unsigned)n * n : (unsigned)n);
+        if (D == 3)
+            hipLaunchKernelGGL((k_q1_prolong_add4<3, TF, TC>), dim3(nblocks(N)), dim3(kThreads), 0, st,
+                               static_cast<TF *>(c), static_cast<const TC *>(ec), n, P, Pc, N);
+        else
+            hipLaunchKernelGGL((k_q1_prolong_add4<2, TF, TC>), dim3(nblocks(N)), dim3(kThreads), 0, st,
+                               static_cast<TF *>(c), static_cast<const TC *>(ec), n, P, Pc, N);
+        return hipGetLastError();
+    }
+    const unsigned N = q1_segs(D, n);
     if (D == 3)
         hipLaunchKernelGGL((k_q1_prolong_add<3, TF, TC>), dim3(nblocks(N)), dim3(kThreads), 0, st,
                            static_cast<TF *>(c), static_cast<const TC *>(ec), n, P, Pc, N);
