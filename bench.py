@@ -494,7 +494,7 @@ def main():
         bq = torch.from_numpy(W.q1_load_vector(3, n, seed=12)).to(dev)
         Lq = mgir.full_levels(n)
         s = mgir.Solver(3, n, W.precision_map(args.map, Lq), disc="q1", residual_scaling=args.map != "f64",
-                        device=dev)
+                        device=dev, defer_update=args.defer if args.map != "f64" else 0)
         for k in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -117,9 +117,10 @@ typedef struct {
                                 opt.autotune is ignored and mg_set_shape returns
                                 MG_ERR_STATE); single-grid handles only, as rescale_half. */
     int defer_update;        /* 0 (default): ir_solve adds alpha c to u in every step, as
-                                Algorithm 2 writes it.  k in 1..64: the step that runs the
-                                fused last sweep + update (3-D finite differences,
-                                MG_SHAPE_FUSE in use) stores c in the finest level's
+                                Algorithm 2 writes it.  k in 1..64: the step's update
+                                kernel (3-D finite differences with the fused last
+                                sweep + update, MG_SHAPE_FUSE in use; or the Q1 update,
+                                2-D and 3-D) stores c in the finest level's
                                 format in a ring of k slots instead of reading and
                                 writing the FP64 u; when the ring is full, and before
                                 u is read (the recomputed residual, the return), one

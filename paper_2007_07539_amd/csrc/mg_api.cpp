@@ -586,8 +586,17 @@ bool fusion_possible(mg_ctx *h) {
 // Whether a refinement step writes its residual to the other array.
 bool swaps_r(const mg_ctx *h) { return h->fused && h->lv[0].prec == P_F64 && !h->opt.residual_scaling; }
 
-// Whether the step postpones the solution update (fused update only).
-bool defers(const mg_ctx *h) { return h->defer > 0 && h->fused; }
+// Whether the step postpones the solution update (the fused finite-difference
+// update, or the Q1 update).
+bool defers(const mg_ctx *h) { return h->defer > 0 && (h->fused || h->q1); }
+
+// The factor of the update u += alpha f c: h^2 for finite differences in
+// grid-scaled units, h^(2-D) for the Q1 elements.
+double update_factor(const mg_ctx *h) {
+    const double hh = 1.0 / (double)(h->lv[0].n + 1);
+    if (h->q1) return h->dim == 3 ? 1.0 / hh : 1.0;
+    return hh * hh;
+}
 
 // Arguments of the fused sweep + update for the current state.
 SweepUpdateArgs su_args(mg_ctx *h, const void *c) {
@@ -683,10 +692,13 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
         RUN(h, st, defers(h) ? "sweep_update_defer" : "sweep_update", 0, N * by,
             launch_sweep_update(L.prec, L.P, su_args(h, cbuf(h, 0, h->cur[0])), h->fsh, st));
     } else if (h->q1) {
-        // U += alpha h^(2-D) c, R -= alpha S c
-        RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
+        // U += alpha h^(2-D) c, R -= alpha S c; postponed: c copied to the ring
+        const bool d = defers(h);
+        RUN(h, st, d ? "ir_update_defer" : "ir_update", 0, N * (d ? 16 + 2 * sb(L.prec) : 32 + sb(L.prec)),
             launch_q1_outer(h->dim, L.prec, L.n, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h),
-                            h->dim == 3 ? 1.0 / hh : 1.0, part(h), st));
+                            update_factor(h), part(h), st, d ? (void *)(h->ws + h->off_cdef) : nullptr,
+                            h->cdef_stride, d ? at_ws<double>(h, h->off_adef) : nullptr,
+                            d ? at_ws<int>(h, h->off_dctr) : nullptr));
     } else {
         RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
             launch_outer_update(h->dim, L.prec, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h), hh * hh,
@@ -703,12 +715,11 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
 hipError_t enq_flush(mg_ctx *h, hipStream_t st) {
     if (h->pending == 0) return hipSuccess;
     const LevelPlan &L = h->lv[0];
-    const double hh = 1.0 / (double)(L.n + 1);
     const int k = h->pending;
     h->pending = 0;
     RUN(h, st, "defer_flush", 0, (double)points(h->dim, L.n) * (16 + k * sb(L.prec)),
-        launch_defer_flush(L.prec, h->ws + h->off_cdef, h->cdef_stride, at_ws<double>(h, h->off_adef), k, hh * hh,
-                           Ubuf(h), L.elems, at_ws<int>(h, h->off_dctr), st));
+        launch_defer_flush(L.prec, h->ws + h->off_cdef, h->cdef_stride, at_ws<double>(h, h->off_adef), k,
+                           update_factor(h), Ubuf(h), L.elems, at_ws<int>(h, h->off_dctr), st));
     return hipSuccess;
 }
 
@@ -1355,7 +1366,7 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
         h->off_R2 = off;
         off += fin;
     }
-    if (fusable && o.defer_update > 0) {
+    if ((fusable || q1) && o.defer_update > 0) {
         const LevelPlan &L = h->lv[0];
         h->defer = o.defer_update;
         h->cdef_stride = align_up(L.elems * prec_bytes(L.prec), 256) / prec_bytes(L.prec);

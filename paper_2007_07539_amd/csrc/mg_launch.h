@@ -163,8 +163,11 @@ hipError_t launch_q1_restrict(int D, int pf, int pc, int n, int P, const void *b
                               hipStream_t st);
 hipError_t launch_q1_prolong(int D, int pf, int pc, int n, int P, const void *c, const void *ec, const void *b,
                              void *c_out, double omega, hipStream_t st);
+// cdefer != nullptr: postponed update (the correction goes to ring slot *ctr
+// of cstride elements, alpha to adef[*ctr]; U untouched).
 hipError_t launch_q1_outer(int D, int prec, int n, int P, const void *c, double *R, double *U, const double *scal,
-                           double f, double *part, hipStream_t st);
+                           double f, double *part, hipStream_t st, void *cdefer = nullptr, size_t cstride = 0,
+                           double *adef = nullptr, const int *ctr = nullptr);
 hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,
                                 double hd, double *part, hipStream_t st);
 hipError_t launch_q1_coarse(int D, int prec, const void *b, void *c, hipStream_t st);

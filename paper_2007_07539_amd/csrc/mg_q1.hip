@@ -261,14 +261,29 @@ __global__ __launch_bounds__(kThreads) void k_q1_march4(const T *__restrict__ b,
 
 // The FP64 update (as k_q1_outer) in the marching form of k_q1_march4: grid
 // (P/4 / threads, n, zgroups), zc planes per thread; one partial per block.
-template <class T>
+// With a ring (DEFER), the update of U is postponed: the correction is
+// copied into ring slot *ctr and alpha into adef[*ctr] (U is not touched).
+struct Q1Ring {
+    void *cd;            // slots of cstride elements in the level format
+    size_t cstride;
+    double *adef;
+    const int *ctr;
+};
+
+template <class T, bool DEFER>
 __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict__ c, double *__restrict__ R,
                                                              double *__restrict__ U, const double *__restrict__ scal,
                                                              double f, int n, int P, int zc,
-                                                             double *__restrict__ part) {
+                                                             double *__restrict__ part, Q1Ring ring) {
     typedef double A;
     __shared__ double red[8];
     const double a = scal[0];
+    T *cd = nullptr;
+    if constexpr (DEFER) {
+        const int slot = *ring.ctr;
+        cd = static_cast<T *>(ring.cd) + (size_t)slot * ring.cstride;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) ring.adef[slot] = a;
+    }
     double ss = 0.0, mx = 0.0;
     const int x0 = 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const int y = (int)blockIdx.y + 1;
@@ -293,9 +308,9 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
         for (int z = z0; z <= z1; ++z) {
             plane(z + 1, Ap, Cp);
             const size_t o = g.at(x0, y, z);
-            A rv[4], uv[4];
+            A rv[4], uv[4] = {};
             q1_load4<double, A>(R + o, rv);
-            q1_load4<double, A>(U + o, uv);
+            if constexpr (!DEFER) q1_load4<double, A>(U + o, uv);
             // one vector store each for R and U; x = 0 (first segment) is the
             // ghost: zero, which adds nothing to the norms
 #pragma unroll
@@ -313,7 +328,14 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
                 mx = nanmax(mx, fabs(r));
             }
             store_row<double, 4>(R + o, rv);
-            store_row<double, 4>(U + o, uv);
+            if constexpr (DEFER) {
+                T cv[4];  // the correction itself (values of T: exact)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) cv[i] = (i == 0 && first) ? zero_of<T>() : store_as<T>(C0[i + 1]);
+                store_row<T, 4>(cd + o, cv);
+            } else {
+                store_row<double, 4>(U + o, uv);
+            }
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 Am[k] = A0[k], Cm[k] = C0[k];
@@ -459,14 +481,20 @@ __global__ __launch_bounds__(kThreads) void k_q1_prolong_add4(TF *__restrict__ c
 // Finest-level update of a refinement step in FP64: U += alpha f c and
 // R -= alpha S c (the recursively updated residual of Algorithm 2), f =
 // h^(2-D) undoing the grid scaling; partial sum of squares and max |R| per block.
-template <int D, class T>
+template <int D, class T, bool DEFER>
 __global__ __launch_bounds__(kThreads) void k_q1_outer(const T *__restrict__ c, double *__restrict__ R,
                                                        double *__restrict__ U, const double *__restrict__ scal,
-                                                       double f, int n, int P, double *__restrict__ part) {
+                                                       double f, int n, int P, double *__restrict__ part, Q1Ring ring) {
     // grid (x blocks, gy): a thread keeps its x and walks the rows
     // blockIdx.y, blockIdx.y + gy, ... (row = y + n z in 3-D)
     __shared__ double red[8];
     const double a = scal[0];
+    T *cd = nullptr;
+    if constexpr (DEFER) {
+        const int slot = *ring.ctr;
+        cd = static_cast<T *>(ring.cd) + (size_t)slot * ring.cstride;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ring.adef[slot] = a;
+    }
     double ss = 0.0, mx = 0.0;
     const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x) + 1;
     const unsigned rows = D == 3 ? (unsigned)n * n : (unsigned)n;
@@ -477,7 +505,10 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer(const T *__restrict__ c, 
             const double sc = q1_weighted<D, double>(c, o, P) * q1_scale<D, double>();
             const double r = fmaT<double>(-a, sc, R[o]);
             R[o] = r;
-            U[o] = fmaT<double>(a * f, (double)widen(c[o]), U[o]);
+            if constexpr (DEFER)
+                cd[o] = c[o];
+            else
+                U[o] = fmaT<double>(a * f, (double)widen(c[o]), U[o]);
             ss += r * r;
             mx = nanmax(mx, fabs(r));
         }
@@ -678,22 +709,22 @@ dim3 q1_outer_grid(int D, int n) {
     return dim3((unsigned)xb, (unsigned)std::max(1, cap / xb), 1);
 }
 
-template <class T>
+template <class T, bool DEFER>
 hipError_t outer_t(int D, int n, int P, const void *c, double *R, double *U, const double *scal, double f,
-                   double *part, hipStream_t st) {
+                   double *part, const Q1Ring &ring, hipStream_t st) {
     const dim3 g = q1_outer_grid(D, n);
     if (q1_outer_marches(D, n)) {
         const int zc = (n + (int)g.z - 1) / (int)g.z;
-        hipLaunchKernelGGL((k_q1_outer_march<T>), g, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(c), R, U, scal, f,
-                           n, P, zc, part);
+        hipLaunchKernelGGL((k_q1_outer_march<T, DEFER>), g, dim3(q1_bx4(P)), 0, st, static_cast<const T *>(c), R, U,
+                           scal, f, n, P, zc, part, ring);
         return hipGetLastError();
     }
     if (D == 3)
-        hipLaunchKernelGGL((k_q1_outer<3, T>), g, dim3(q1_bx(n)), 0, st, static_cast<const T *>(c), R, U, scal, f, n,
-                           P, part);
+        hipLaunchKernelGGL((k_q1_outer<3, T, DEFER>), g, dim3(q1_bx(n)), 0, st, static_cast<const T *>(c), R, U, scal,
+                           f, n, P, part, ring);
     else
-        hipLaunchKernelGGL((k_q1_outer<2, T>), g, dim3(q1_bx(n)), 0, st, static_cast<const T *>(c), R, U, scal, f, n,
-                           P, part);
+        hipLaunchKernelGGL((k_q1_outer<2, T, DEFER>), g, dim3(q1_bx(n)), 0, st, static_cast<const T *>(c), R, U, scal,
+                           f, n, P, part, ring);
     return hipGetLastError();
 }
 
@@ -756,8 +787,14 @@ hipError_t launch_q1_prolong(int D, int pf, int pc, int n, int P, const void *c,
 }
 
 hipError_t launch_q1_outer(int D, int prec, int n, int P, const void *c, double *R, double *U, const double *scal,
-                           double f, double *part, hipStream_t st) {
-    Q1_DISPATCH(prec, TT, return outer_t<TT>(D, n, P, c, R, U, scal, f, part, st));
+                           double f, double *part, hipStream_t st, void *cdefer, size_t cstride, double *adef,
+                           const int *ctr) {
+    const Q1Ring ring{cdefer, cstride, adef, ctr};
+    if (cdefer) {
+        if (!adef || !ctr) return hipErrorInvalidValue;
+        Q1_DISPATCH(prec, TT, return (outer_t<TT, true>(D, n, P, c, R, U, scal, f, part, ring, st)));
+    }
+    Q1_DISPATCH(prec, TT, return (outer_t<TT, false>(D, n, P, c, R, U, scal, f, part, ring, st)));
 }
 
 hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,

@@ -53,7 +53,9 @@ def _true_rel(ref, b, u):
     return ref.norm2(ref.residual(b, u, "q1")) / ref.norm2(b)
 
 
-CASES = [(3, 7), (3, 15), (3, 63), (3, 95), (2, 15), (2, 255), (2, 383)]
+# pitches that are multiples of 4 take the four-point and marching kernels,
+# the others (n = 9, 21) the one-point-per-thread kernels
+CASES = [(3, 7), (3, 15), (3, 63), (3, 95), (2, 15), (2, 255), (2, 383), (3, 9), (3, 21), (2, 9)]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -87,7 +89,7 @@ def test_q1_smooth_first(dev, ref, prec, dim, n):
 
 
 @pytest.mark.parametrize("pf,pc", [(a, b) for a in PRECS for b in PRECS])
-@pytest.mark.parametrize("dim,n", [(3, 15), (3, 47), (2, 63), (2, 95)])
+@pytest.mark.parametrize("dim,n", [(3, 15), (3, 47), (2, 63), (2, 95), (3, 9), (3, 21), (2, 9)])
 def test_q1_resid_restrict(dev, ref, pf, pc, dim, n):
     print(f"q1 restrict {pf}->{pc} dim={dim} n={n}", flush=True)
     s = _solver(dim, n, pf, pc)
@@ -103,7 +105,7 @@ def test_q1_resid_restrict(dev, ref, pf, pc, dim, n):
 
 
 @pytest.mark.parametrize("pf,pc", [(a, b) for a in PRECS for b in PRECS])
-@pytest.mark.parametrize("dim,n", [(3, 15), (3, 47), (2, 63), (2, 95)])
+@pytest.mark.parametrize("dim,n", [(3, 15), (3, 47), (2, 63), (2, 95), (3, 9), (3, 21), (2, 9)])
 def test_q1_prolong_sweep(dev, ref, pf, pc, dim, n):
     print(f"q1 prolong {pc}->{pf} dim={dim} n={n}", flush=True)
     s = _solver(dim, n, pf, pc)
@@ -240,3 +242,21 @@ def test_q1_initial_guess_and_partial_hierarchy(dev, ref, dim, n, nl):
     assert res.status == 0 and r64.status == 0
     assert _true_rel(ref, b, u.cpu().numpy()) <= 1e-10
     assert res.iterations <= r64.iterations + 2
+
+
+@pytest.mark.parametrize("name,dim,n", [("f16", 3, 95), ("f16", 3, 21), ("f16", 2, 255), ("f64", 3, 63)])
+def test_q1_deferred_update_bitwise(dev, name, dim, n):
+    """Postponed solution updates on the Q1 path (the marching update at n = 95
+    and 63, the one-point update at n = 21 and in 2-D): the stored corrections,
+    added to u in step order when the ring is full and before u is read, give u
+    bit for bit and the same residual history as the update in every step."""
+    print(f"q1 defer {name} dim={dim} n={n}", flush=True)
+    m = mgir.full_levels(n)
+    b = torch.from_numpy(W.q1_load_vector(dim, n, seed=120)).to(dev)
+    kw = dict(disc="q1", residual_scaling=name != "f64")
+    u0, r0 = mgir.Solver(dim, n, W.precision_map(name, m), **kw).solve(b)
+    for k in (3, 64):
+        u1, r1 = mgir.Solver(dim, n, W.precision_map(name, m), defer_update=k, **kw).solve(b)
+        assert r1.status == 0 and r1.iterations == r0.iterations, k
+        assert r1.history == r0.history, k
+        assert torch.equal(u1, u0), k
