@@ -366,7 +366,7 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
             for name in ("f16", "f64"):
                 log(f"[bench] Q1 {dim}-D n={nq}, map {name}")
                 s = mgir.Solver(dim, nq, W.precision_map(name, Lq), disc="q1", residual_scaling=name != "f64",
-                                device=dev)
+                                device=dev, **(dk if name != "f64" else {}))
                 u0 = torch.zeros_like(bq)
                 s.solve(bq, u0)
                 torch.cuda.synchronize()
@@ -376,7 +376,8 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
                 torch.cuda.synchronize()
                 ms = (time.perf_counter() - t0) / steps * 1e3
                 e[name] = {"ms": ms, "dof_per_s": nq**dim / ms * 1e3, "iterations": r.iterations,
-                           "rel_residual": r.rel_residual, "status": r.status}
+                           "rel_residual": r.rel_residual, "status": r.status,
+                           "defer_update": dk.get("defer_update", 0) if name != "f64" else 0}
                 del s, u0
                 torch.cuda.empty_cache()
             e["speedup_f16_vs_f64"] = e["f64"]["ms"] / e["f16"]["ms"]

@@ -193,6 +193,43 @@ __global__ __launch_bounds__(kThreads) void k_q1_resid4(const T *__restrict__ b,
     store_row<A, 4>(r + o, ov);
 }
 
+// The three rows y, y - 1, y + 1 of one plane that a four-point segment needs
+// (x0 - 1 .. x0 + 4), still in the storage format: loaded one plane ahead of
+// their use by the marching kernels.
+template <class T> struct Q1Plane {
+    RawRow<T, 4> m[3];  // x0 .. x0 + 3 of rows y, y - 1, y + 1
+    T l[3], r[3];       // x0 - 1 (the ghost x = 0 itself for the first segment) and x0 + 4
+};
+template <class T>
+__device__ __forceinline__ void q1_fetch_plane(const T *row, long Y, bool first, Q1Plane<T> &p) {
+    const T *rows[3] = {row, row - Y, row + Y};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        fetch_row<T, 4>(rows[k], p.m[k]);
+        p.l[k] = rows[k][first ? 0 : -1];
+        p.r[k] = rows[k][4];
+    }
+}
+// C = row y and A = row (y - 1) + row (y + 1), as q1_row6 forms them
+template <class T, class A>
+__device__ __forceinline__ void q1_widen_plane(const Q1Plane<T> &p, A (&Av)[6], A (&Cv)[6]) {
+    A w[3][6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        A m[4];
+        widen_row<T, 4>(p.m[k], m);
+        w[k][0] = (A)widen(p.l[k]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[k][i + 1] = m[i];
+        w[k][5] = (A)widen(p.r[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        Cv[k] = w[0][k];
+        Av[k] = w[1][k] + w[2][k];
+    }
+}
+
 // 3-D, pitch a multiple of 4: the sweep (RESID false: out = c + w (b - S c) in
 // T) or the residual (RESID true: out = b - S c in the accumulator format),
 // with each thread marching zc planes of its four-point row segment.  Per
@@ -216,22 +253,35 @@ __global__ __launch_bounds__(kThreads) void k_q1_march4(const T *__restrict__ b,
     const long Y = P;
     const Grid<3> g{P};
     A Am[6], Cm[6], A0[6], C0[6], Ap[6], Cp[6];
-    auto plane = [&](int z, A(&Av)[6], A(&Cv)[6]) {
-        const T *r = c + g.at(x0, y, z);
-        A s[6], t[6];
-        q1_row6<T, A>(r, first, Cv);
-        q1_row6<T, A>(r - Y, first, s);
-        q1_row6<T, A>(r + Y, first, t);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Av[k] = s[k] + t[k];
-    };
-    plane(z0 - 1, Am, Cm);
-    plane(z0, A0, C0);
+    Q1Plane<T> pl;
+    q1_fetch_plane<T>(c + g.at(x0, y, z0 - 1), Y, first, pl);
+    q1_widen_plane<T, A>(pl, Am, Cm);
+    q1_fetch_plane<T>(c + g.at(x0, y, z0), Y, first, pl);
+    q1_widen_plane<T, A>(pl, A0, C0);
+    // 4- and 8-byte formats load one plane ahead (c rows of plane z + 1 and b
+    // of plane z); the 2-byte ones measured faster loading just in time
+    constexpr bool kAhead = sizeof(T) >= 4;
+    RawRow<T, 4> bq;
+    if constexpr (kAhead) {
+        q1_fetch_plane<T>(c + g.at(x0, y, z0 + 1), Y, first, pl);
+        fetch_row<T, 4>(b + g.at(x0, y, z0), bq);
+    }
     for (int z = z0; z <= z1; ++z) {
-        plane(z + 1, Ap, Cp);
+        Q1Plane<T> cur;
+        RawRow<T, 4> bcur;
+        if constexpr (kAhead) {
+            cur = pl;
+            bcur = bq;
+            if (z + 2 <= z1 + 1) q1_fetch_plane<T>(c + g.at(x0, y, z + 2), Y, first, pl);
+            if (z + 1 <= z1) fetch_row<T, 4>(b + g.at(x0, y, z + 1), bq);
+        } else {
+            q1_fetch_plane<T>(c + g.at(x0, y, z + 1), Y, first, cur);
+            fetch_row<T, 4>(b + g.at(x0, y, z), bcur);
+        }
+        q1_widen_plane<T, A>(cur, Ap, Cp);
         const size_t o = g.at(x0, y, z);
         A bv[4];
-        q1_load4<T, A>(b + o, bv);
+        widen_row<T, 4>(bcur, bv);
         // the four results are stored with one vector store; x = 0 (first
         // segment) is the ghost and receives zero
         A ra[4];
@@ -294,23 +344,42 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
         const long Y = P;
         const Grid<3> g{P};
         A Am[6], Cm[6], A0[6], C0[6], Ap[6], Cp[6];
-        auto plane = [&](int z, A(&Av)[6], A(&Cv)[6]) {
-            const T *r = c + g.at(x0, y, z);
-            A sv[6], tv[6];
-            q1_row6<T, A>(r, first, Cv);
-            q1_row6<T, A>(r - Y, first, sv);
-            q1_row6<T, A>(r + Y, first, tv);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Av[k] = sv[k] + tv[k];
-        };
-        plane(z0 - 1, Am, Cm);
-        plane(z0, A0, C0);
+        Q1Plane<T> pl;
+        q1_fetch_plane<T>(c + g.at(x0, y, z0 - 1), Y, first, pl);
+        q1_widen_plane<T, A>(pl, Am, Cm);
+        q1_fetch_plane<T>(c + g.at(x0, y, z0), Y, first, pl);
+        q1_widen_plane<T, A>(pl, A0, C0);
+        // 4- and 8-byte formats load one plane ahead (c rows of plane z + 1, R
+        // and U of plane z); the 2-byte ones measured faster loading just in time
+        constexpr bool kAhead = sizeof(T) >= 4;
+        RawRow<double, 4> rq, uq;
+        if constexpr (kAhead) {
+            q1_fetch_plane<T>(c + g.at(x0, y, z0 + 1), Y, first, pl);
+            fetch_row<double, 4>(R + g.at(x0, y, z0), rq);
+            if constexpr (!DEFER) fetch_row<double, 4>(U + g.at(x0, y, z0), uq);
+        }
         for (int z = z0; z <= z1; ++z) {
-            plane(z + 1, Ap, Cp);
+            Q1Plane<T> cur;
+            RawRow<double, 4> rcur, ucur;
+            if constexpr (kAhead) {
+                cur = pl;
+                rcur = rq;
+                if constexpr (!DEFER) ucur = uq;
+                if (z + 2 <= z1 + 1) q1_fetch_plane<T>(c + g.at(x0, y, z + 2), Y, first, pl);
+                if (z + 1 <= z1) {
+                    fetch_row<double, 4>(R + g.at(x0, y, z + 1), rq);
+                    if constexpr (!DEFER) fetch_row<double, 4>(U + g.at(x0, y, z + 1), uq);
+                }
+            } else {
+                q1_fetch_plane<T>(c + g.at(x0, y, z + 1), Y, first, cur);
+                fetch_row<double, 4>(R + g.at(x0, y, z), rcur);
+                if constexpr (!DEFER) fetch_row<double, 4>(U + g.at(x0, y, z), ucur);
+            }
+            q1_widen_plane<T, A>(cur, Ap, Cp);
             const size_t o = g.at(x0, y, z);
             A rv[4], uv[4] = {};
-            q1_load4<double, A>(R + o, rv);
-            if constexpr (!DEFER) q1_load4<double, A>(U + o, uv);
+            widen_row<double, 4>(rcur, rv);
+            if constexpr (!DEFER) widen_row<double, 4>(ucur, uv);
             // one vector store each for R and U; x = 0 (first segment) is the
             // ghost: zero, which adds nothing to the norms
 #pragma unroll
