@@ -654,7 +654,7 @@ RShape default_srshape(const LevelPlan &L) {
 void set_fused(mg_ctx *h, bool on) {
     h->fused = on && fusion_possible(h);
     const LevelPlan &L = h->lv[0];
-    h->outer_parts = h->q1      ? q1_outer_blocks(h->dim, L.n)
+    h->outer_parts = h->q1      ? q1_outer_blocks(h->dim, L.n, L.prec)
                      : h->fused ? sweep_update_blocks(L.P, h->fsh)
                                 : stencil_blocks(h->dim, L.P, L.osh);
 }

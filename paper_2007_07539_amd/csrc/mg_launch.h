@@ -154,7 +154,7 @@ hipError_t launch_cg_base(int D, int prec, int n, int P, const void *b, void *c,
 // interior size (odd for levels with a coarser one), P = n + 1.
 // launch_q1_restrict writes the fine residual into rs (q1_resid_bytes) first.
 size_t q1_resid_bytes(int D, int prec, int P);
-int q1_outer_blocks(int D, int n);
+int q1_outer_blocks(int D, int n, int prec);
 hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const double *R, const double *scal,
                            void *b_out, void *c_out, double omega, hipStream_t st);
 hipError_t launch_q1_sweep(int D, int prec, int n, int P, const void *b, const void *c, void *c_out, double omega,

@@ -420,6 +420,185 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
     }
 }
 
+// The marching Q1 kernels with each plane's rows staged in LDS (3-D, pitch a
+// multiple of 4).  A block owns TY consecutive rows (threads of row g: x0 = 4 t
+// for t < P/4) of zc planes; the rows above and below (g = 0, TY + 1) are
+// loaded by their own threads and only written to LDS.  Every plane is read
+// from memory once per block row and stored whole in LDS (x = 0 and the ghost
+// after a row's last point included), one plane ahead: the thread then forms
+// the centre row C and the row sum A = row (y - 1) + row (y + 1) of that plane
+// for x0 - 1 .. x0 + 4 from LDS, with the same sums as k_q1_march4, so the
+// results are identical.  MODE 0: the sweep (out = c + w (b - S c) in T),
+// 1: the residual (out = b - S c in the accumulator format), 2: the FP64
+// update (R -= alpha S c; U += alpha f c, or the correction into the ring).
+template <class T, int MODE, bool DEFER = false>
+__global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const T *__restrict__ c,
+                                                 void *__restrict__ out, int n, int P, int TY, int zc, int ytiles,
+                                                 acc_t<T> w, double *__restrict__ R, double *__restrict__ U,
+                                                 const double *__restrict__ scal, double f, double *__restrict__ part,
+                                                 Q1Ring ring) {
+    typedef typename std::conditional<MODE == 2, double, acc_t<T>>::type A;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[32];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int TX = P / 4, G = TY + 2;
+    const size_t slot = (size_t)G * P + 8;  // G rows and the ghost after the last one
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int yt = blk % ytiles, zch = blk / ytiles;
+    const int y0 = 1 + yt * TY;
+    const int z0 = 1 + zch * zc, z1 = min(z0 + zc - 1, n);
+    const int tx = (int)threadIdx.x % TX, gi = (int)threadIdx.x / TX;
+    const int x0 = 4 * tx;
+    const int y = y0 - 1 + gi;
+    const bool row_in = y >= 1 && y <= n;  // other rows are zero ghosts
+    const bool outr = gi >= 1 && gi <= TY && y <= n;
+    const bool first = x0 == 0;
+    const Grid<3> g{P};
+    double ss = 0.0, mx = 0.0;
+    T *cd = nullptr;
+    double a = 0.0;
+    if constexpr (MODE == 2) {
+        a = scal[0];
+        if constexpr (DEFER) {
+            const int s = *ring.ctr;
+            cd = static_cast<T *>(ring.cd) + (size_t)s * ring.cstride;
+            if (blockIdx.x == 0 && threadIdx.x == 0) ring.adef[s] = a;
+        }
+    }
+    for (int i = threadIdx.x; i < 2 * 8; i += blockDim.x) lds[(i / 8) * slot + (size_t)G * P + (i % 8)] = zero_of<T>();
+    auto fetch = [&](int z, RawRow<T, 4> &r) {
+        if (row_in) fetch_row<T, 4>(c + g.at(x0, y, z), r);
+        else zero_row(r);
+    };
+    auto publish = [&](int s, const RawRow<T, 4> &r) {
+        typedef typename RawRow<T, 4>::C C;
+        C *dst = reinterpret_cast<C *>(lds + (size_t)s * slot + (size_t)gi * P + x0);
+#pragma unroll
+        for (int j = 0; j < RawRow<T, 4>::B / RawRow<T, 4>::CB; ++j) dst[j] = r.c[j];
+    };
+    // C and A of the plane in slot s for this thread's segment (out rows only)
+    auto rows = [&](int s, A (&Av)[6], A (&Cv)[6]) {
+        const T *base = lds + (size_t)s * slot + (size_t)gi * P + x0;
+        auto row6 = [&](const T *r, A (&v)[6]) {
+            A m[4];
+            load_row<T, 4>(r, m);
+            v[0] = (A)widen(r[first ? 0 : -1]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i + 1] = m[i];
+            v[5] = (A)widen(r[4]);
+        };
+        A sv[6], tv[6];
+        row6(base, Cv);
+        row6(base - P, sv);
+        row6(base + P, tv);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Av[k] = sv[k] + tv[k];
+    };
+    A Am[6], Cm[6], A0[6], C0[6], Ap[6], Cp[6];
+    RawRow<T, 4> rr;
+    fetch(z0 - 1, rr);
+    publish(0, rr);
+    fetch(z0, rr);
+    __syncthreads();
+    if (outr) rows(0, Am, Cm);
+    publish(1, rr);
+    fetch(z0 + 1, rr);
+    __syncthreads();
+    if (outr) rows(1, A0, C0);
+    publish(0, rr);  // slot 0's plane z0 - 1 was read before the last barrier
+    if (z0 + 2 <= z1 + 1) fetch(z0 + 2, rr);
+    RawRow<T, 4> bq;
+    if (MODE != 2 && outr) fetch_row<T, 4>(b + g.at(x0, y, z0), bq);
+    RawRow<double, 4> rq, uq;
+    if (MODE == 2 && outr) {
+        fetch_row<double, 4>(R + g.at(x0, y, z0), rq);
+        if (!DEFER) fetch_row<double, 4>(U + g.at(x0, y, z0), uq);
+    }
+    __syncthreads();
+    for (int z = z0; z <= z1; ++z) {
+        const int it = z - z0;
+        const int sp = it & 1;  // slot of plane z + 1
+        RawRow<T, 4> bcur = bq;
+        RawRow<double, 4> rcur = rq, ucur = uq;
+        if (outr) {
+            rows(sp, Ap, Cp);
+            if (z + 1 <= z1) {
+                if (MODE != 2) fetch_row<T, 4>(b + g.at(x0, y, z + 1), bq);
+                if (MODE == 2) {
+                    fetch_row<double, 4>(R + g.at(x0, y, z + 1), rq);
+                    if (!DEFER) fetch_row<double, 4>(U + g.at(x0, y, z + 1), uq);
+                }
+            }
+            const size_t o = g.at(x0, y, z);
+            A sc[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = i + 1;
+                const A e =
+                    ((A0[k - 1] + A0[k + 1]) + ((Cm[k - 1] + Cm[k + 1]) + (Cp[k - 1] + Cp[k + 1]))) + (Am[k] + Ap[k]);
+                const A cn = (Am[k - 1] + Am[k + 1]) + (Ap[k - 1] + Ap[k + 1]);
+                sc[i] = fmaT<A>(A(32), C0[k], -fmaT<A>(A(2), e, cn)) * q1_scale<3, A>();
+            }
+            if constexpr (MODE == 0) {
+                A bv[4];
+                widen_row<T, 4>(bcur, bv);
+                T ov[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    ov[i] = (i == 0 && first) ? zero_of<T>() : Store<T>::from_acc(fmaT<A>(w, bv[i] - sc[i], C0[i + 1]));
+                store_row<T, 4>(static_cast<T *>(out) + o, ov);
+            } else if constexpr (MODE == 1) {
+                A bv[4];
+                widen_row<T, 4>(bcur, bv);
+                A ov[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ov[i] = (i == 0 && first) ? A(0) : bv[i] - sc[i];
+                store_row<A, 4>(static_cast<A *>(out) + o, ov);
+            } else {
+                double rv[4], uv[4] = {};
+                widen_row<double, 4>(rcur, rv);
+                if (!DEFER) widen_row<double, 4>(ucur, uv);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bool ghost = i == 0 && first;
+                    const double r = ghost ? 0.0 : fmaT<double>(-a, sc[i], rv[i]);
+                    uv[i] = ghost ? 0.0 : fmaT<double>(a * f, C0[i + 1], uv[i]);
+                    rv[i] = r;
+                    ss += r * r;
+                    mx = nanmax(mx, fabs(r));
+                }
+                store_row<double, 4>(R + o, rv);
+                if constexpr (DEFER) {
+                    T cv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cv[i] = (i == 0 && first) ? zero_of<T>() : store_as<T>(C0[i + 1]);
+                    store_row<T, 4>(cd + o, cv);
+                } else {
+                    store_row<double, 4>(U + o, uv);
+                }
+            }
+        }
+        // plane z + 2 into the slot plane z occupied (read before the last barrier)
+        if (z + 1 <= z1) {
+            publish(sp ^ 1, rr);
+            if (z + 3 <= z1 + 1) fetch(z + 3, rr);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            Am[k] = A0[k], Cm[k] = C0[k];
+            A0[k] = Ap[k], C0[k] = Cp[k];
+        }
+    }
+    if constexpr (MODE == 2) {
+        block_reduce(ss, mx, red);
+        if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = ss;
+            part[2 * blockIdx.x + 1] = mx;
+        }
+    }
+}
+
 // Full weighting of r at coarse point (X, Y, Z), whose fine twin is
 // (2X, 2Y, 2Z): 1-D weights 1, 2, 1 summed exactly and scaled by 4^-D.
 template <int D, class A, class TC>
@@ -673,10 +852,52 @@ hipError_t first_t(int D, int n, int P, const void *b, const double *R, const do
     return hipGetLastError();
 }
 
+// Shape of k_q1_lds on a 3-D level of pitch P (a multiple of 4): the most rows
+// per block that 1024 threads and 64 KB of LDS allow, up to 6, and up to 16
+// planes, fewer where that leaves under about four blocks per CU.
+struct Q1LdsShape {
+    int TY, zc, ytiles, blocks;
+    size_t lds;
+};
+Q1LdsShape q1_lds_shape(int n, int P, size_t sb) {
+    Q1LdsShape s{};
+    const int TX = P / 4;
+    s.TY = std::min(6, 1024 / TX - 2);
+    while (s.TY > 1 && 2 * (((size_t)s.TY + 2) * P + 8) * sb > 65536 - 512) --s.TY;
+    s.ytiles = (n + s.TY - 1) / s.TY;
+    s.zc = std::max(2, std::min(16, (int)(((long)n * s.ytiles + 1023) / 1024)));
+    s.zc = std::min(s.zc, n);
+    s.blocks = s.ytiles * ((n + s.zc - 1) / s.zc);
+    s.lds = 2 * (((size_t)s.TY + 2) * P + 8) * sb;
+    return s;
+}
+// Whether the 3-D level takes k_q1_lds (2-byte format, pitch a multiple of 4,
+// room for two rows of threads plus one owned row, and no more blocks than the
+// update's partials allow).
+bool q1_lds_ok(int n, int P, size_t sb) {
+    // the 2-byte formats (the 4- and 8-byte ones measured faster marching with
+    // their own row loads one plane ahead)
+    if (sb != 2 || P % 4 != 0 || P / 4 > 1024 / 3) return false;
+    const Q1LdsShape s = q1_lds_shape(n, P, sb);
+    return s.TY >= 1 && s.blocks <= flat_blocks((long)npoints(3, n));
+}
+
+template <class T, int MODE, bool DEFER = false>
+hipError_t q1_lds_launch(int n, int P, const void *b, const void *c, void *out, acc_t<T> w, double *R, double *U,
+                         const double *scal, double f, double *part, const Q1Ring &ring, hipStream_t st) {
+    const Q1LdsShape s = q1_lds_shape(n, P, sizeof(T));
+    hipLaunchKernelGGL((k_q1_lds<T, MODE, DEFER>), dim3(s.blocks), dim3((s.TY + 2) * (P / 4)), s.lds, st,
+                       static_cast<const T *>(b), static_cast<const T *>(c), out, n, P, s.TY, s.zc, s.ytiles, w, R, U,
+                       scal, f, part, ring);
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout, double omega, hipStream_t st) {
     typedef acc_t<T> A;
     const A w = (A)(omega * 0.375);
+    if (D == 3 && q1_lds_ok(n, P, sizeof(T)))
+        return q1_lds_launch<T, 0>(n, P, b, c, cout, w, nullptr, nullptr, nullptr, 0.0, nullptr, Q1Ring{}, st);
     if (P % 4 == 0) {
         const dim3 g4 = q1_grid4(D, n, P);
         if (D == 3)
@@ -704,7 +925,11 @@ hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *r
     A *r = static_cast<A *>(rs);
     if (P % 4 == 0) {
         const dim3 g4 = q1_grid4(D, n, P);
-        if (D == 3)
+        if (D == 3 && q1_lds_ok(n, P, sizeof(T))) {
+            const hipError_t e = q1_lds_launch<T, 1>(n, P, b, c, static_cast<void *>(r), A(0), nullptr, nullptr,
+                                                     nullptr, 0.0, nullptr, Q1Ring{}, st);
+            if (e != hipSuccess) return e;
+        } else if (D == 3)
             hipLaunchKernelGGL((k_q1_march4<T, true>), q1_grid4z(n, P), dim3(q1_bx4(P)), 0, st,
                                static_cast<const T *>(b), static_cast<const T *>(c), static_cast<void *>(r), n, P,
                                kMarchZ, A(0));
@@ -781,6 +1006,8 @@ dim3 q1_outer_grid(int D, int n) {
 template <class T, bool DEFER>
 hipError_t outer_t(int D, int n, int P, const void *c, double *R, double *U, const double *scal, double f,
                    double *part, const Q1Ring &ring, hipStream_t st) {
+    if (D == 3 && q1_lds_ok(n, P, sizeof(T)))
+        return q1_lds_launch<T, 2, DEFER>(n, P, nullptr, c, nullptr, acc_t<T>(0), R, U, scal, f, part, ring, st);
     const dim3 g = q1_outer_grid(D, n);
     if (q1_outer_marches(D, n)) {
         const int zc = (n + (int)g.z - 1) / (int)g.z;
@@ -824,7 +1051,9 @@ size_t q1_resid_bytes(int D, int prec, int P) {
     return level_elems(D, P) * (prec == P_F64 ? sizeof(double) : sizeof(float));
 }
 
-int q1_outer_blocks(int D, int n) {
+int q1_outer_blocks(int D, int n, int prec) {
+    const int P = n + 1;
+    if (D == 3 && q1_lds_ok(n, P, prec_bytes(prec))) return q1_lds_shape(n, P, prec_bytes(prec)).blocks;
     const dim3 g = q1_outer_grid(D, n);
     return (int)(g.x * g.y * g.z);
 }
