@@ -517,7 +517,7 @@ def main():
     def shapes_of(s):
         return {"smooth": s.get_shape(0, mgir.SHAPE_SMOOTH), "sweep": s.get_shape(0, mgir.SHAPE_SWEEP),
                 "prolong": s.get_shape(0, mgir.SHAPE_PROLONG, 7), "restrict": s.get_shape(0, mgir.SHAPE_RESTRICT),
-                "update": s.get_shape(0, mgir.SHAPE_UPDATE), "fused_sweep_update": s.get_shape(0, mgir.SHAPE_FUSE),
+                "update": s.get_shape(0, mgir.SHAPE_UPDATE), "fused_sweep_update": s.get_shape(0, mgir.SHAPE_FUSE, 6),
                 "fused_smooth_restrict": s.get_shape(0, mgir.SHAPE_FUSE_SR, 4),
                 "fused_coarse_end": s.get_shape(0, mgir.SHAPE_TAIL)}
 

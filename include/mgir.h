@@ -389,14 +389,21 @@ typedef enum {
                                workspace copies of those levels are then not
                                updated. */
     MG_SHAPE_FUSE = 7,      /* 3-D, level argument 0: {on (0|1)[, V (4), zc, xcd,
-                               ty]}.  When on (the default; the autotuner keeps it
-                               only where it is faster), the last post-smoothing
-                               sweep of the finest level and the refinement update
-                               run as one kernel inside ir_solve (same result).  With
-                               an FP64 finest level and no residual scaling, whose
-                               right-hand side is r itself, the kernel writes the new
-                               residual to a second array of the workspace and the
-                               two swap roles every step.  Not used when nu2 < 2.
+                               ty[, from_r (0|1)]]}.  When on (the default; the
+                               autotuner keeps it only where it is faster), the last
+                               post-smoothing sweep of the finest level and the
+                               refinement update run as one kernel inside ir_solve
+                               (same result).  from_r = 1 forms the sweep's
+                               right-hand side round(r / alpha) from the FP64
+                               residual r, as the first smoothing did, instead of
+                               reading it back (the element size fewer bytes per
+                               point; r is also read on the tile's halo rows); the
+                               kernel then writes the new residual to a second array
+                               of the workspace and the two swap roles every step.
+                               An FP64 finest level without residual scaling, whose
+                               right-hand side is r itself, takes only from_r = 1.
+                               Default: 1 for FP32/FP64 finest levels, 0 for 2-byte
+                               ones; the autotuner times both.  Not used when nu2 < 2.
                                Reading returns whether it is in use and its shape. */
     MG_SHAPE_FUSE_SR = 8    /* 3-D, level l below the base: {on (0|1)[, tyc, zcc[, lds16]]}.  When
                                on, the level's first pre-smoothing (two sweeps from zero)

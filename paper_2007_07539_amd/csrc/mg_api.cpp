@@ -107,6 +107,7 @@ struct mg_ctx {
     bool fuse_on = true;   // allow the fused last sweep + update on the finest level
     bool fused = false;    // ... and it is in use
     Shape fsh{4, 16, 256, 1, 4};
+    bool su_r = true;      // ... forming b from r (else reading b back); needs the second residual array
     bool fuse_sr_on = true;  // allow the fused first smoothing + restriction on the finest level
     bool fused_sr = false;   // ... and it is in use
     RShape srsh{8, 2, 16, 3};
@@ -574,17 +575,21 @@ hipError_t enq_vcycle(mg_ctx *h, hipStream_t st, RhsMode mode, bool warm = false
 
 bool finest_alias(mg_ctx *h) { return h->lv[0].prec == P_F64 && !h->opt.residual_scaling; }
 
-// The fused last sweep + update needs at least two post-sweeps.  With the
-// FP64 map and no scaling, r itself is the right-hand side, which a block reads
-// on rows its neighbours update: the new residual then goes to a second array
-// (swaps_r).
+// The fused last sweep + update needs at least two post-sweeps.  It reads
+// the stored right-hand side b, or (su_r) forms b = round(r / alpha) from the
+// FP64 residual r, as the first smoothing did: s bytes per point fewer, but r
+// is read on the tile's halo rows too.  With the FP64 map and no scaling r
+// itself is the right-hand side, so that form is the only one.  A block then
+// reads r on rows its neighbours update, so the new residual goes to a second
+// array (swaps_r).
 bool fusion_possible(mg_ctx *h) {
     return h->fuse_on && !h->batched && !h->nrhs && h->dim == 3 && h->nl >= 2 && h->opt.nu2 >= 2 &&
-           (!finest_alias(h) || h->off_R2) && sweep_update_ok(h->lv[0].P, h->lv[0].prec, h->fsh);
+           (!h->su_r || h->off_R2) && (h->su_r || !finest_alias(h)) &&
+           sweep_update_ok(h->lv[0].P, h->lv[0].prec, h->fsh);
 }
 
 // Whether a refinement step writes its residual to the other array.
-bool swaps_r(const mg_ctx *h) { return h->fused && h->lv[0].prec == P_F64 && !h->opt.residual_scaling; }
+bool swaps_r(const mg_ctx *h) { return h->fused && h->su_r; }
 
 // Whether the step postpones the solution update (the fused finite-difference
 // update, or the Q1 update).
@@ -604,9 +609,9 @@ SweepUpdateArgs su_args(mg_ctx *h, const void *c) {
     const double hh = 1.0 / (double)(L.n + 1);
     SweepUpdateArgs a;
     a.c = c;
-    a.b = finest_alias(h) ? (const void *)Rbuf(h) : bbuf(h, 0);
+    a.b = h->su_r ? (const void *)Rbuf(h) : bbuf(h, 0);  // b == R: b is formed from r
     a.R = Rbuf(h);
-    a.Rout = finest_alias(h) ? Rnext(h) : Rbuf(h);
+    a.Rout = h->su_r ? Rnext(h) : Rbuf(h);
     a.U = Ubuf(h);
     if (defers(h)) {
         a.cdefer = h->ws + h->off_cdef;
@@ -684,11 +689,11 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
     const double hh = 1.0 / (double)(L.n + 1);
     const double N = (double)points(h->dim, L.n);
     if (h->fused) {
-        // bytes: c, b, r read, r written, u read and written; with the
-        // residual as right-hand side r is not read apart from b; a postponed
-        // update writes c' instead of reading and writing u
+        // bytes: c, b, r read, r written, u read and written; b formed from
+        // r is not read; a postponed update writes c' instead of reading and
+        // writing u
         const double s = sb(L.prec);
-        const double by = (finest_alias(h) ? s + 8 : 2 * s + 16) + (defers(h) ? s : 16);
+        const double by = (h->su_r ? s + 16 : 2 * s + 16) + (defers(h) ? s : 16);
         RUN(h, st, defers(h) ? "sweep_update_defer" : "sweep_update", 0, N * by,
             launch_sweep_update(L.prec, L.P, su_args(h, cbuf(h, 0, h->cur[0])), h->fsh, st));
     } else if (h->q1) {
@@ -970,12 +975,13 @@ void tune_state(const mg_ctx *h, std::vector<int> &v) {
     v.push_back(h->fused_sr ? 1 : 0);
     sh(h->fsh);
     v.push_back(h->fused ? 1 : 0);
+    v.push_back(h->su_r ? 1 : 0);
 }
 
 // Apply a state read from the cache; false (and nothing changed) when any
 // shape is not valid for this handle.
 bool apply_tune_state(mg_ctx *h, const std::vector<int> &v) {
-    const size_t per = 4 * 7 + 4 + 4 + 1, need = per * (h->nl - 1) + 4 + 1 + 7 + 1;
+    const size_t per = 4 * 7 + 4 + 4 + 1, need = per * (h->nl - 1) + 4 + 1 + 7 + 1 + 1;
     if (v.size() != need) return false;
     size_t i = 0;
     auto sh = [&]() {
@@ -1003,11 +1009,14 @@ bool apply_tune_state(mg_ctx *h, const std::vector<int> &v) {
     const bool fused_sr = v[i++] != 0;
     const Shape fsh = sh();
     const bool fused = v[i++] != 0;
+    const bool su_r = v[i++] != 0;
+    if (!su_r && finest_alias(h)) return false;
     h->lv = lv;
     for (int l = 1; l + 1 < h->nl; ++l) set_fused_srb(h, l, fsr[l]);
     h->srsh = srsh;
     set_fused_sr(h, fused_sr);
     h->fsh = fsh;
+    h->su_r = su_r;
     set_fused(h, fused);
     return true;
 }
@@ -1144,21 +1153,29 @@ mg_status_t autotune_timed(mg_ctx *h, hipStream_t st) {
             L.osh = bo;
             h->outer_parts = stencil_blocks(D, L.P, bo);
             // the fused last sweep + update against the two kernels it replaces
+            // (both ways of getting the right-hand side where both apply)
             if (fusion_possible(h)) {
                 float bf = 1e30f;
                 Shape bsu = h->fsh;
-                for (int ty : {1, 2, 3, 4})
-                    for (int zc : {4, 8, 16, 32, 64}) {
-                        const Shape s{4, zc, 256, 1, ty};
-                        if (!sweep_update_ok(L.P, L.prec, s)) continue;
-                        const bool was = h->fused;
-                        h->fused = true;  // the arguments of the form the step would use
-                        const SweepUpdateArgs q = su_args(h, cbuf(h, 0, 0));
-                        h->fused = was;
-                        const float t = time_ms(st, [&]() { return launch_sweep_update(L.prec, L.P, q, s, st); }, 3);
-                        if (t < bf) bf = t, bsu = s;
-                    }
+                bool bsr = h->su_r;
+                const bool keep_r = h->su_r;
+                for (int from_r = finest_alias(h) ? 1 : 0; from_r <= 1; ++from_r)
+                    for (int ty : {1, 2, 3, 4})
+                        for (int zc : {4, 8, 16, 32, 64}) {
+                            const Shape s{4, zc, 256, 1, ty};
+                            if (!sweep_update_ok(L.P, L.prec, s)) continue;
+                            const bool was = h->fused;
+                            h->fused = true;  // the arguments of the form the step would use
+                            h->su_r = from_r != 0;
+                            const SweepUpdateArgs q = su_args(h, cbuf(h, 0, 0));
+                            h->fused = was;
+                            h->su_r = keep_r;
+                            const float t =
+                                time_ms(st, [&]() { return launch_sweep_update(L.prec, L.P, q, s, st); }, 3);
+                            if (t < bf) bf = t, bsu = s, bsr = from_r != 0;
+                        }
                 h->fsh = bsu;
+                h->su_r = bsr;
                 set_fused(h, bf < best + fam_best[SH_SWEEP]);
             }
         }
@@ -1360,9 +1377,10 @@ mg_status_t mg_setup(mg_handle *out, int dim, int n, int nlevels, const mg_prec_
     off += fin;
     // the forms of the fused finest-level update (3-D finite differences)
     const bool fusable = dim == 3 && !q1 && m >= 2;
-    if (fusable && prec[0] == P_F64 && !o.residual_scaling) {
-        // the residual is the right-hand side: the fused update writes the
-        // new residual to a second array
+    if (fusable) {
+        // the fused update that forms its right-hand side from r writes the
+        // new residual to a second array (FP16/BF16 maps default to reading b)
+        h->su_r = prec_bytes(prec[0]) >= 4;
         h->off_R2 = off;
         off += fin;
     }
@@ -1809,13 +1827,16 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE) {
-        if ((np != 1 && np != 5) || (p[0] != 0 && p[0] != 1))
-            return fail(MG_ERR_ARG, "the fused-update shape is {on (0|1)[, V, zc, xcd, ty]}");
-        if (np == 5) {
+        if ((np != 1 && np != 5 && np != 6) || (p[0] != 0 && p[0] != 1))
+            return fail(MG_ERR_ARG, "the fused-update shape is {on (0|1)[, V, zc, xcd, ty[, from_r]]}");
+        if (np >= 5) {
             const Shape f{p[1], p[2], 256, p[3], p[4]};
             if (h->nl < 2 || !sweep_update_ok(h->lv[0].P, h->lv[0].prec, f) || (f.xcd != 0 && f.xcd != 1))
                 return fail(MG_ERR_ARG, "fused-update shape {V=4, zc, xcd, ty} not valid here");
+            if (np == 6 && (p[5] < 0 || p[5] > 1 || (p[5] == 0 && finest_alias(h)) || (p[5] == 1 && !h->off_R2)))
+                return fail(MG_ERR_ARG, "from_r = %d not valid here (0: read b, 1: form b from r)", p[5]);
             h->fsh = f;
+            if (np == 6) h->su_r = p[5] != 0;
         }
         h->fuse_on = p[0] != 0;
         set_fused(h, h->fuse_on);
@@ -1890,6 +1911,7 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
         if (np < 1) return fail(MG_ERR_ARG, "too few values");
         p[0] = h->fused ? 1 : 0;
         if (np >= 5) p[1] = h->fsh.V, p[2] = h->fsh.zc, p[3] = h->fsh.xcd, p[4] = h->fsh.ty;
+        if (np >= 6) p[5] = h->su_r ? 1 : 0;
         return MG_OK;
     }
     if (level < 0 || level >= h->nl - 1) return fail(MG_ERR_ARG, "level %d has no launch shape", level);

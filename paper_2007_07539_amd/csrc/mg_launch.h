@@ -92,7 +92,7 @@ hipError_t launch_probe(void *dst, const void *src, size_t bytes, int kind, int 
 // update (LDS-plane kernel; s.ty rows per block, s.V values per thread).
 struct SweepUpdateArgs {
     const void *c = nullptr;    // correction before the sweep (level format)
-    const void *b = nullptr;    // right-hand side (level format); == R for the FP64 map without scaling
+    const void *b = nullptr;    // right-hand side (level format), or R: then b = round(R * scal[1]) is formed
     const double *R = nullptr;  // residual in
     double *Rout = nullptr;     // residual out: == R (in place) unless b == R, then another array
     double *U = nullptr;        // iterate, updated unless cdefer is set

@@ -7,12 +7,13 @@
 // instead of 3 s for the sweep and s + 32 for the update).
 //
 // Two variants change what is read and written, not the arithmetic:
-//   ALIAS  the FP64 map without residual scaling, whose right-hand side b is
-//          the residual r itself.  A block reads b on halo rows that its
-//          neighbours update, so the new residual goes to a second array
-//          (Rout != R, swapped every step), and r of a point is the b value
-//          the block already holds: c, r and u read, r and u written
-//          (8 + 32 bytes per point in FP64).
+//   ALIAS  the right-hand side is formed from the residual r itself: b =
+//          round_T(r / alpha), the value the first smoothing stored (for the
+//          FP64 map without residual scaling, alpha = 1 and b is r).  A block
+//          reads r on halo rows that its neighbours update, so the new
+//          residual goes to a second array (Rout != R, swapped every step),
+//          and r of a point is the row the block already holds: c, r and u
+//          read, r and u written (s + 32 bytes per point instead of 2 s + 32).
 //   DEFER  the update of u is postponed: c' is stored in its storage format
 //          in slot k of a ring of corrections (k read from *ctr) and alpha in
 //          adef[k]; launch_defer_flush later forms u += alpha_j h^2 c'_j for
@@ -33,6 +34,8 @@
 #include "mg_device.h"
 #include "mg_launch.h"
 
+#include <type_traits>
+
 namespace mg {
 namespace {
 
@@ -45,8 +48,8 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
     T *__restrict__ Cd, const int *__restrict__ ctr, size_t cstride, double *__restrict__ adef,
     const double *__restrict__ scal, double h2, double omega, double *__restrict__ part, int P, int TY, int zc,
     int ytiles, int xcd) {
-    static_assert(!ALIAS || sizeof(T) == 8, "the residual is the right-hand side only in FP64");
     typedef acc_t<T> A;
+    typedef typename std::conditional<ALIAS, double, T>::type TB;  // what the b queue holds
     typedef LdsRun<T, V> LR;  // LDS rows, chunk-major
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[32];
@@ -73,6 +76,8 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
     const bool out_row = gi >= 2 && gi <= TY + 1 && y <= P - 1;
     const A k = (A)(omega / 6.0);
     const double a = scal[0];
+    const double inv = scal[1];  // ALIAS: b = round_T(r * (1 / alpha)), as the first smoothing formed it
+    const TB *bsrc = ALIAS ? reinterpret_cast<const TB *>(R) : reinterpret_cast<const TB *>(b);
     const double ah2 = a * h2;
     T *cd = nullptr;  // DEFER: this step's slot
     if constexpr (DEFER) {
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
     // c' of the own row: planes w-1, w, w+1 around the plane w being updated
     A fm[V], fc[V], fp[V];
     RawRow<T, V> cnext;       // c, plane s + 2
-    RawRow<T, V> bcur, bnext; // b, planes s and s + 1
+    RawRow<TB, V> bcur, bnext; // b (ALIAS: r), planes s and s + 1
     RawRow<double, V> rcur, ucur, rnext, unext;
     double ss = 0.0, mx = 0.0;
 #pragma unroll
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
         widen_row<T, V>(t, pp);
         fetch_c(wb + 3, cnext);
         const int s0 = wb + 1;
-        if (sweep_row && row_in && s0 >= 1 && s0 <= P - 1) fetch_row<T, V>(b + g.at(x0, y, s0), bnext);
+        if (sweep_row && row_in && s0 >= 1 && s0 <= P - 1) fetch_row<TB, V>(bsrc + g.at(x0, y, s0), bnext);
         if (out_row && z0 < z1) {
             if constexpr (!ALIAS) fetch_row<double, V>(R + g.at(x0, y, z0), rnext);
             if constexpr (!DEFER) fetch_row<double, V>(U + g.at(x0, y, z0), unext);
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
         }
         bcur = bnext;
         if (sweep_row && row_in && s + 1 >= 1 && s + 1 <= P - 1 && s + 1 <= z1)
-            fetch_row<T, V>(b + g.at(x0, y, s + 1), bnext);
+            fetch_row<TB, V>(bsrc + g.at(x0, y, s + 1), bnext);
         if (w >= z0) {
             if constexpr (!ALIAS) rcur = rnext;
             if constexpr (!DEFER) ucur = unext;
@@ -150,7 +155,14 @@ __global__ __launch_bounds__(su_bound<T>()) void k_sweep_update(
                 A ym[V], yp[V], bv[V];
                 LR::load(row - P, xc, TXR, ym);
                 LR::load(row + P, xc, TXR, yp);
-                widen_row<T, V>(bcur, bv);
+                if constexpr (ALIAS) {
+                    double rv[V];
+                    widen_row<double, V>(bcur, rv);
+#pragma unroll
+                    for (int i = 0; i < V; ++i) bv[i] = (A)widen(Store<T>::from_f64(rv[i] * inv));
+                } else {
+                    widen_row<T, V>(bcur, bv);
+                }
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
                     nb[i] += ym[i];
@@ -254,13 +266,9 @@ hipError_t sweep_update_t(int P, const SweepUpdateArgs &q, const Shape &s, hipSt
 
 template <class T> hipError_t sweep_update_mode(int P, const SweepUpdateArgs &q, const Shape &s, hipStream_t st) {
     const bool alias = q.b == (const void *)q.R, defer = q.cdefer != nullptr;
-    if constexpr (sizeof(T) == 8) {
-        if (alias) {
-            if (q.Rout == q.R) return hipErrorInvalidValue;  // the residual must not be updated in place
-            return defer ? sweep_update_t<T, true, true>(P, q, s, st) : sweep_update_t<T, true, false>(P, q, s, st);
-        }
-    } else if (alias) {
-        return hipErrorInvalidValue;
+    if (alias) {
+        if (q.Rout == q.R) return hipErrorInvalidValue;  // the residual must not be updated in place
+        return defer ? sweep_update_t<T, true, true>(P, q, s, st) : sweep_update_t<T, true, false>(P, q, s, st);
     }
     return defer ? sweep_update_t<T, false, true>(P, q, s, st) : sweep_update_t<T, false, false>(P, q, s, st);
 }
@@ -275,10 +283,12 @@ constexpr size_t kSuDynLdsMax = kLdsMax - 1024;
 hipError_t sweep_update_prepare() {
     static hipError_t done = [] {
         const void *fns[] = {
-#define MG_SU_FN(T) (const void *)k_sweep_update<4, T, false, false>, (const void *)k_sweep_update<4, T, false, true>
-            MG_SU_FN(double), MG_SU_FN(float), MG_SU_FN(f16), MG_SU_FN(bf16),
+#define MG_SU_FN(T)                                                                                       \
+    (const void *)k_sweep_update<4, T, false, false>, (const void *)k_sweep_update<4, T, false, true>,       \
+        (const void *)k_sweep_update<4, T, true, false>, (const void *)k_sweep_update<4, T, true, true>
+            MG_SU_FN(double), MG_SU_FN(float), MG_SU_FN(f16), MG_SU_FN(bf16)
 #undef MG_SU_FN
-            (const void *)k_sweep_update<4, double, true, false>, (const void *)k_sweep_update<4, double, true, true>};
+        };
         for (const void *f : fns) {
             // what the function's static LDS leaves of the workgroup's kLdsMax
             hipFuncAttributes fa{};

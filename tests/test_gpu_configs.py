@@ -78,8 +78,8 @@ def test_poisson3d_511_maps(dev, ref, name):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name,scaling,sr,fuse", [("f16", True, [1, 3, 85], [1, 4, 64, 1, 4]),
-                                                  ("f16", True, [1, 3, 85, 1], [1, 4, 64, 1, 4]),
+@pytest.mark.parametrize("name,scaling,sr,fuse", [("f16", True, [1, 3, 85], [1, 4, 64, 1, 4, 0]),
+                                                  ("f16", True, [1, 3, 85, 1], [1, 4, 64, 1, 4, 1]),
                                                   ("f64", False, [1, 1, 16], [1, 4, 32, 1, 2])])
 def test_fused_kernels_in_their_511_shapes_bitwise(dev, name, scaling, sr, fuse):
     """At 511^3 the fused first smoothing + restriction runs with its largest
@@ -100,7 +100,7 @@ def test_fused_kernels_in_their_511_shapes_bitwise(dev, name, scaling, sr, fuse)
             s.set_shape(0, mgir.SHAPE_FUSE_SR, sr)
             s.set_shape(0, mgir.SHAPE_FUSE, fuse)
             assert s.get_shape(0, mgir.SHAPE_FUSE_SR, len(sr)) == sr
-            assert s.get_shape(0, mgir.SHAPE_FUSE) == fuse
+            assert s.get_shape(0, mgir.SHAPE_FUSE, len(fuse)) == fuse
         else:
             s.set_shape(0, mgir.SHAPE_FUSE_SR, [0])
             s.set_shape(0, mgir.SHAPE_FUSE, [0])

@@ -96,7 +96,7 @@ def test_tuning_cache_round_trip(dev, tmp_path, monkeypatch, name, scaling, defe
 
     def shapes(s):
         return [s.get_shape(l, k) for l in range(s.nlevels - 1) for k in kinds if k in kinds[:4] or l == 0] + \
-            [s.get_shape(0, mgir.SHAPE_UPDATE)]
+            [s.get_shape(0, mgir.SHAPE_UPDATE), s.get_shape(0, mgir.SHAPE_FUSE, 6)]
 
     a = mgir.Solver(3, n, prec, residual_scaling=scaling, autotune=True, defer_update=defer)
     lines = path.read_text().splitlines()
@@ -146,12 +146,14 @@ def test_fused_sweep_update_bitwise(dev, name, n, scaling):
     assert s.get_shape(0, mgir.SHAPE_FUSE)[0] == 0
     u_ref, r_ref = s.solve(b64)
     u_ref = u_ref.clone()
-    for shape in ([1, 4, 16, 1, 4], [1, 4, 3, 0, 1], [1, 4, 64, 1, 2], [1, 4, 5, 1, 3]):
+    # the sixth value: the right-hand side read back (0) or formed from r (1)
+    for shape in ([1, 4, 16, 1, 4], [1, 4, 3, 0, 1], [1, 4, 64, 1, 2], [1, 4, 5, 1, 3], [1, 4, 16, 1, 4, 0],
+                  [1, 4, 16, 1, 4, 1], [1, 4, 3, 0, 1, 1], [1, 4, 64, 1, 2, 1], [1, 4, 5, 1, 3, 0]):
         try:
             s.set_shape(0, mgir.SHAPE_FUSE, shape)
         except mgir.MgError:
             continue
-        assert s.get_shape(0, mgir.SHAPE_FUSE) == shape
+        assert s.get_shape(0, mgir.SHAPE_FUSE, len(shape)) == shape
         u, r = s.solve(b64)
         # the norms are summed over the kernel's blocks, so the history may
         # differ in the last bits between shapes; the iterates may not
@@ -199,12 +201,18 @@ def test_fp64_baseline_fused_forms_bitwise(dev, n, graph):
         assert np.allclose(r.history, r_on.history, rtol=1e-13, atol=0), (fuse, sr)
         assert torch.equal(u, u_on), (fuse, sr)
     assert tried >= 2
+    with pytest.raises(mgir.MgError):  # r is the right-hand side: there is no stored b to read
+        s.set_shape(0, mgir.SHAPE_FUSE, [1, 4, 8, 1, 1, 0])
 
 
-@pytest.mark.parametrize("name,n,depth,cycles", [("f16", 63, 1, 1), ("f16", 63, 3, 1), ("f16", 127, 64, 1),
-                                                 ("bf16", 31, 2, 1), ("f32", 63, 5, 1), ("hsd", 127, 3, 1),
-                                                 ("f64", 63, 4, 1), ("f16", 63, 4, 2), ("f64", 31, 2, 2)])
-def test_deferred_update_bitwise(dev, name, n, depth, cycles):
+@pytest.mark.parametrize("name,n,depth,cycles,from_r", [("f16", 63, 1, 1, None), ("f16", 63, 3, 1, None),
+                                                        ("f16", 127, 64, 1, None), ("bf16", 31, 2, 1, None),
+                                                        ("f32", 63, 5, 1, None), ("hsd", 127, 3, 1, None),
+                                                        ("f64", 63, 4, 1, None), ("f16", 63, 4, 2, None),
+                                                        ("f64", 31, 2, 2, None), ("f16", 63, 3, 1, 1),
+                                                        ("bf16", 127, 5, 1, 1), ("f32", 31, 2, 2, 0),
+                                                        ("f16", 63, 4, 2, 1)])
+def test_deferred_update_bitwise(dev, name, n, depth, cycles, from_r):
     """Postponing the solution update (a ring of `depth` stored corrections,
     added to u in step order when full and before u is read) gives the same u
     bit for bit, the same iteration count and the same residual history: from
@@ -220,6 +228,10 @@ def test_deferred_update_bitwise(dev, name, n, depth, cycles):
         ref = mgir.Solver(3, n, prec, use_initial_guess=guess, max_iter=max_iter, **kw)
         dfr = mgir.Solver(3, n, prec, use_initial_guess=guess, max_iter=max_iter, defer_update=depth, **kw)
         assert dfr.get_shape(0, mgir.SHAPE_FUSE)[0] == 1
+        if from_r is not None:  # both take the given way to the right-hand side
+            for x in (ref, dfr):
+                x.set_shape(0, mgir.SHAPE_FUSE, x.get_shape(0, mgir.SHAPE_FUSE) + [from_r])
+                assert x.get_shape(0, mgir.SHAPE_FUSE, 6)[5] == from_r
         for rep in range(2):
             ua, ra = ref.solve(b64, u0.clone() if guess else None, check=False)
             ub, rb = dfr.solve(b64, u0.clone() if guess else None, check=False)
