@@ -99,6 +99,7 @@ struct mg_ctx {
     int defer = 0;      // ring depth in use; 0: u is updated every step
     size_t off_cdef = 0, cdef_stride = 0, off_adef = 0, off_dctr = 0;
     int pending = 0;    // corrections in the ring not yet added to u
+    bool u_zero = false;  // u is zero and not yet stored (a solve from zero with postponed updates)
     hipEvent_t ev_norm = nullptr;     // single grid: the norm readback of a step is done
     int outer_parts = 0;
     bool tail_on = true;
@@ -718,13 +719,15 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
 // Add the postponed corrections to u (their slots in order) and empty the
 // ring; nothing to do without postponed corrections.
 hipError_t enq_flush(mg_ctx *h, hipStream_t st) {
-    if (h->pending == 0) return hipSuccess;
     const LevelPlan &L = h->lv[0];
+    const bool zero = h->u_zero;  // the first flush of a solve from zero starts from 0 instead of reading u
+    h->u_zero = false;
+    if (h->pending == 0) return zero ? launch_fill_zero(Ubuf(h), align_up(L.elems * sizeof(double), 16), st) : hipSuccess;
     const int k = h->pending;
     h->pending = 0;
-    RUN(h, st, "defer_flush", 0, (double)points(h->dim, L.n) * (16 + k * sb(L.prec)),
+    RUN(h, st, "defer_flush", 0, (double)points(h->dim, L.n) * ((zero ? 8 : 16) + k * sb(L.prec)),
         launch_defer_flush(L.prec, h->ws + h->off_cdef, h->cdef_stride, at_ws<double>(h, h->off_adef), k,
-                           update_factor(h), Ubuf(h), L.elems, at_ws<int>(h, h->off_dctr), st));
+                           update_factor(h), Ubuf(h), L.elems, at_ws<int>(h, h->off_dctr), st, zero));
     return hipSuccess;
 }
 
@@ -1680,18 +1683,23 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
     // ||b||_2 first (and the initial residual when u starts at zero)
     h->rpar = 0;
     h->pending = 0;
+    h->u_zero = false;
     if (h->defer) HIPCHK(launch_fill_zero(h->ws + h->off_dctr, 16, st));
     if (h->opt.use_initial_guess) {
         HIPCHK(finest_resid(h, b, nullptr, nullptr, nullptr, st));
     } else {
         HIPCHK(finest_resid(h, b, nullptr, Rbuf(h), nullptr, st));
-        HIPCHK(launch_fill_zero(Ubuf(h), align_up(L.elems * sizeof(double), 16), st));
+        // with postponed updates nothing reads u before the first flush,
+        // which then starts from zero (enq_flush)
+        if (h->defer) h->u_zero = true;
+        else HIPCHK(launch_fill_zero(Ubuf(h), align_up(L.elems * sizeof(double), 16), st));
     }
     const int fparts = flat_blocks(points(D, L.n));
     HIPCHK(launch_finalize(part(h), fparts, scal(h), scaling, st));
     HIPCHK(hipMemcpyAsync(h->host_scal, scal(h), 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const double nb = h->host_scal[2];
+    if (!std::isfinite(nb) || nb == 0.0) HIPCHK(enq_flush(h, st));  // u = 0 in the handle too
     if (!std::isfinite(nb)) {
         finish_stats(0, NAN);
         return fail(MG_ERR_NONFINITE, "||b|| is not finite");

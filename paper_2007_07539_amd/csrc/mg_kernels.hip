@@ -1411,13 +1411,21 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 
 // u += a_j h^2 c_j over the postponed corrections in order; one thread per
 // eight consecutive elements (the padded arrays have a multiple of 8).
+// from_zero: u starts from 0 (the same sums as from a zero-filled U, which is
+// then neither filled nor read).
 template <class T>
 __global__ __launch_bounds__(256) void k_defer_flush(const T *__restrict__ cd, size_t cstride,
                                                      const double *__restrict__ adef, int count, double h2,
-                                                     double *__restrict__ U, size_t n8, int *__restrict__ ctr) {
+                                                     double *__restrict__ U, size_t n8, int *__restrict__ ctr,
+                                                     int from_zero) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += (size_t)gridDim.x * blockDim.x) {
         double u[8];
-        load_row<double, 8>(U + 8 * i, u);
+        if (from_zero) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) u[e] = 0.0;
+        } else {
+            load_row<double, 8>(U + 8 * i, u);
+        }
         for (int j = 0; j < count; ++j) {
             const double ah2 = adef[j] * h2;
             double cv[8];
@@ -1890,13 +1898,13 @@ hipError_t launch_resid_flat(int D, int n, int P, const double *b, const double 
 }
 
 hipError_t launch_defer_flush(int prec, const void *cdefer, size_t cstride, const double *adef, int count, double h2,
-                              double *U, size_t elems, int *ctr, hipStream_t st) {
+                              double *U, size_t elems, int *ctr, hipStream_t st, bool from_zero) {
     if (elems % 8 || count < 0) return hipErrorInvalidValue;
     const size_t n8 = elems / 8;
     const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>((n8 + 255) / 256, 8192));
 #define MG_FL(T) \
     hipLaunchKernelGGL(k_defer_flush<T>, dim3(blocks), dim3(256), 0, st, static_cast<const T *>(cdefer), cstride, adef, \
-                       count, h2, U, n8, ctr)
+                       count, h2, U, n8, ctr, from_zero ? 1 : 0)
     switch (prec) {
     case P_F64: MG_FL(double); break;
     case P_F32: MG_FL(float); break;

@@ -116,7 +116,7 @@ hipError_t launch_sweep_update(int prec, int P, const SweepUpdateArgs &a, const 
 // order (c_j at cdefer + j * cstride elements, level format prec; elems
 // padded elements each), then *ctr = 0.
 hipError_t launch_defer_flush(int prec, const void *cdefer, size_t cstride, const double *adef, int count, double h2,
-                              double *U, size_t elems, int *ctr, hipStream_t st);
+                              double *U, size_t elems, int *ctr, hipStream_t st, bool from_zero = false);
 
 // First pre-smoothing of the finest 3-D level from the FP64 residual (scaled
 // and cast) fused with the residual + full-weighting restriction of its

@@ -258,6 +258,26 @@ def test_deferred_update_profile_step(dev):
     assert torch.equal(ref.read(0, mgir.BUF_RES), dfr.read(0, mgir.BUF_RES))
 
 
+@pytest.mark.parametrize("disc,dim,n", [("fd", 3, 31), ("q1", 3, 21), ("q1", 2, 63)])
+def test_deferred_update_zero_rhs_clears_u(dev, disc, dim, n):
+    """A solve from zero with postponed updates neither fills nor reads u
+    before its first flush; with b = 0 it returns at once, and the handle's
+    own u is zero too, not the previous solve's."""
+    prec = W.precision_map("f16", mgir.full_levels(n))
+    s = mgir.Solver(dim, n, prec, disc=disc, defer_update=4)
+    b64 = torch.from_numpy(W.q1_load_vector(dim, n, seed=16) if disc == "q1" else W.uniform_rhs(dim, n, seed=16))
+    b64 = b64.to(dev)
+    s.solve(b64)
+    assert s.read(0, mgir.BUF_SOL).abs().max().item() > 0
+    u, r = s.solve(torch.zeros_like(b64))
+    assert r.status == 0 and r.iterations == 0
+    assert not u.any() and not s.read(0, mgir.BUF_SOL).any()
+    u2, r2 = s.solve(b64)  # and the next solve from zero again
+    ref = mgir.Solver(dim, n, prec, disc=disc)
+    u3, r3 = ref.solve(b64)
+    assert r2.iterations == r3.iterations and torch.equal(u2, u3)
+
+
 @pytest.mark.parametrize("name,n", [("f16", 63), ("bf16", 31), ("f32", 127), ("f16", 15), ("h_mg", 31),
                                     ("hsd", 255), ("f64", 63), ("f64", 255)])
 def test_fused_smooth_restrict_bitwise(dev, name, n):
