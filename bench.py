@@ -366,7 +366,10 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
             for name in ("f16", "f64"):
                 log(f"[bench] Q1 {dim}-D n={nq}, map {name}")
                 s = mgir.Solver(dim, nq, W.precision_map(name, Lq), disc="q1", residual_scaling=name != "f64",
-                                device=dev, **(dk if name != "f64" else {}))
+                                device=dev, autotune=tune, **(dk if name != "f64" else {}))
+                q1sh = [s.get_shape(l, k) for l in range(s.nlevels - 1)
+                        for k in (mgir.SHAPE_SWEEP, mgir.SHAPE_RESTRICT, mgir.SHAPE_UPDATE)[: 3 if l == 0 else 2]
+                        if s.get_shape(l, mgir.SHAPE_SWEEP) != [0, 0]]
                 u0 = torch.zeros_like(bq)
                 s.solve(bq, u0)
                 torch.cuda.synchronize()
@@ -377,7 +380,8 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
                 ms = (time.perf_counter() - t0) / steps * 1e3
                 e[name] = {"ms": ms, "dof_per_s": nq**dim / ms * 1e3, "iterations": r.iterations,
                            "rel_residual": r.rel_residual, "status": r.status,
-                           "defer_update": dk.get("defer_update", 0) if name != "f64" else 0}
+                           "defer_update": dk.get("defer_update", 0) if name != "f64" else 0,
+                           "autotune": bool(tune), "lds_shapes": q1sh}
                 del s, u0
                 torch.cuda.empty_cache()
             e["speedup_f16_vs_f64"] = e["f64"]["ms"] / e["f16"]["ms"]
@@ -495,7 +499,8 @@ def main():
         bq = torch.from_numpy(W.q1_load_vector(3, n, seed=12)).to(dev)
         Lq = mgir.full_levels(n)
         s = mgir.Solver(3, n, W.precision_map(args.map, Lq), disc="q1", residual_scaling=args.map != "f64",
-                        device=dev, defer_update=args.defer if args.map != "f64" else 0)
+                        device=dev, defer_update=args.defer if args.map != "f64" else 0,
+                        autotune=not args.no_autotune)
         for k in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -113,9 +113,9 @@ typedef struct {
                                 Section 4.2) */
     int base_max_iter;       /* ... at most this many CG steps; 0: min(10000, base points) */
     int discretization;      /* an mg_disc_t, default MG_DISC_FD.  MG_DISC_Q1 runs its own
-                                kernels (no fused forms, no launch-shape tuning:
-                                opt.autotune is ignored and mg_set_shape returns
-                                MG_ERR_STATE); single-grid handles only, as rescale_half. */
+                                kernels (no fused forms; the launch shapes are those of
+                                the LDS-staged 3-D kernels, see "Q1 handles" under
+                                mg_set_shape); single-grid handles only, as rescale_half. */
     int defer_update;        /* 0 (default): ir_solve adds alpha c to u in every step, as
                                 Algorithm 2 writes it.  k in 1..64: the step's update
                                 kernel (3-D finite differences with the fused last
@@ -423,6 +423,17 @@ typedef enum {
                                whether it is in use and its shape (lds16 as a fourth value
                                when nparams >= 4). */
 } mg_shape_kind_t;
+/* Q1 handles: the levels stored in a 2-byte format on a 3-D grid of pitch a
+ * multiple of 4 run their sweep, their residual (ahead of the restriction) and,
+ * on level 0, the refinement update as LDS-staged kernels (every plane read
+ * from memory once per block row).
+ * MG_SHAPE_SWEEP, MG_SHAPE_RESTRICT and MG_SHAPE_UPDATE then take {ty (rows per
+ * block), zc (planes per block)}, or {0, 0} for the built-in choice; a shape
+ * must fit 1024 threads ((ty + 2) P / 4), 64 KB of LDS and the update's partial
+ * budget (MG_ERR_ARG otherwise, and on other levels for any shape but {0, 0}).
+ * The other kinds return MG_ERR_STATE.  opt.autotune times these shapes per
+ * level and kernel against the built-in one (cached as for finite differences).
+ * Reading returns the {ty, zc} in use, {0, 0} on levels without such kernels. */
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *params, int nparams);
 /* Reading a shape: the values mg_set_shape takes (up to nparams).  On a
  * many-right-hand-side handle, the stencil kinds and MG_SHAPE_RESTRICT of

@@ -57,6 +57,7 @@ struct LevelPlan {
     Shape shs[3];   // kernel families: SH_SMOOTH (first pre-smoothing), SH_SWEEP, SH_PROLONG
     Shape osh;      // refinement update (finest level only)
     RShape rsh;     // residual + restriction onto the next level
+    Q1Shape q1s[3];  // Q1: the LDS-staged sweep, residual and update (finest level only); {0, 0}: built-in
 };
 
 // One kernel launch recorded by the profiling mode.
@@ -315,10 +316,10 @@ double sb(int prec) { return (double)prec_bytes(prec); }
     } while (0)
 
 // Launches that differ between the discretisations.  The Q1 forms have no
-// launch shapes and no fused variants (mg_q1.hip).
+// fused variants (mg_q1.hip); their shapes are those of the LDS-staged kernels.
 hipError_t level_sweep(mg_ctx *h, int l, int prec, const void *b, const void *c, void *c_out, hipStream_t st) {
     const LevelPlan &L = h->lv[l];
-    if (h->q1) return launch_q1_sweep(h->dim, prec, L.n, L.P, b, c, c_out, h->opt.omega, st);
+    if (h->q1) return launch_q1_sweep(h->dim, prec, L.n, L.P, b, c, c_out, h->opt.omega, st, L.q1s[0]);
     return launch_sweep(h->dim, prec, L.P, b, c, c_out, h->opt.omega, L.shs[SH_SWEEP], st);
 }
 
@@ -331,14 +332,14 @@ hipError_t level_first(mg_ctx *h, int l, int prec, const void *b, const double *
 
 hipError_t level_restrict(mg_ctx *h, int l, int pf, int pc, const void *b, const void *c, void *bc, hipStream_t st) {
     const LevelPlan &L = h->lv[l];
-    if (h->q1) return launch_q1_restrict(h->dim, pf, pc, L.n, L.P, b, c, h->ws + h->off_q1r, bc, st);
+    if (h->q1) return launch_q1_restrict(h->dim, pf, pc, L.n, L.P, b, c, h->ws + h->off_q1r, bc, st, L.q1s[1]);
     return launch_restrict(h->dim, pf, pc, L.P, b, c, bc, L.rsh, st);
 }
 
 hipError_t level_prolong(mg_ctx *h, int l, int pf, int pc, const void *c, const void *ec, const void *b, void *c_out,
                          hipStream_t st) {
     const LevelPlan &L = h->lv[l];
-    if (h->q1) return launch_q1_prolong(h->dim, pf, pc, L.n, L.P, c, ec, b, c_out, h->opt.omega, st);
+    if (h->q1) return launch_q1_prolong(h->dim, pf, pc, L.n, L.P, c, ec, b, c_out, h->opt.omega, st, L.q1s[0]);
     return launch_prolong(h->dim, pf, pc, L.P, c, ec, b, c_out, h->opt.omega, true, L.shs[SH_PROLONG], st);
 }
 
@@ -660,7 +661,7 @@ RShape default_srshape(const LevelPlan &L) {
 void set_fused(mg_ctx *h, bool on) {
     h->fused = on && fusion_possible(h);
     const LevelPlan &L = h->lv[0];
-    h->outer_parts = h->q1      ? q1_outer_blocks(h->dim, L.n, L.prec)
+    h->outer_parts = h->q1      ? q1_outer_blocks(h->dim, L.n, L.prec, L.q1s[2])
                      : h->fused ? sweep_update_blocks(L.P, h->fsh)
                                 : stencil_blocks(h->dim, L.P, L.osh);
 }
@@ -704,7 +705,7 @@ hipError_t enq_update(mg_ctx *h, hipStream_t st) {
             launch_q1_outer(h->dim, L.prec, L.n, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h),
                             update_factor(h), part(h), st, d ? (void *)(h->ws + h->off_cdef) : nullptr,
                             h->cdef_stride, d ? at_ws<double>(h, h->off_adef) : nullptr,
-                            d ? at_ws<int>(h, h->off_dctr) : nullptr));
+                            d ? at_ws<int>(h, h->off_dctr) : nullptr, L.q1s[2]));
     } else {
         RUN(h, st, "ir_update", 0, N * (32 + sb(L.prec)),
             launch_outer_update(h->dim, L.prec, L.P, cbuf(h, 0, h->cur[0]), Rbuf(h), Ubuf(h), scal(h), hh * hh,
@@ -1187,6 +1188,75 @@ mg_status_t autotune_timed(mg_ctx *h, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     return MG_OK;
 }
+
+// Q1 handles: which of a level's LDS-staged kernels a shape kind names (0 the
+// sweep, 1 the residual ahead of the restriction, 2 the update; -1 none).
+int q1_kind(int kind) {
+    return kind == MG_SHAPE_SWEEP ? 0 : kind == MG_SHAPE_RESTRICT ? 1 : kind == MG_SHAPE_UPDATE ? 2 : -1;
+}
+
+// The Q1 shapes as integers: per level {ty, zc} of the sweep, the residual
+// and the update.
+bool apply_q1_state(mg_ctx *h, const std::vector<int> &v) {
+    if (v.size() != (size_t)6 * (h->nl - 1)) return false;
+    std::vector<LevelPlan> lv = h->lv;
+    for (int l = 0; l + 1 < h->nl; ++l)
+        for (int k = 0; k < 3; ++k) {
+            const Q1Shape q{v[6 * l + 2 * k], v[6 * l + 2 * k + 1]};
+            if (!q1_shape_ok(h->dim, lv[l].prec, lv[l].n, lv[l].P, q) || (k == 2 && l > 0 && q.ty != 0)) return false;
+            lv[l].q1s[k] = q;
+        }
+    h->lv = lv;
+    set_fused(h, h->fused);  // the update's partial count
+    return true;
+}
+
+// The Q1 autotuner: on each level that takes the LDS-staged kernels, each of
+// them timed over {ty, zc} against the built-in shape, which stays unless
+// another is faster.  The result is cached like the finite-difference one.
+mg_status_t autotune_q1(mg_ctx *h, hipStream_t st) {
+    const std::string key = tune_key(h).empty() ? std::string() : tune_key(h) + "|q1";
+    std::vector<int> v;
+    if (cache_read(key, v) && apply_q1_state(h, v)) return MG_OK;
+    const int D = h->dim;
+    for (int l = 0; l + 1 < h->nl; ++l) {
+        LevelPlan &L = h->lv[l];
+        if (!q1_lds_level(D, L.prec, L.n, L.P)) continue;
+        for (int k = 0; k < (l == 0 ? 3 : 2); ++k) {
+            auto run = [&](const Q1Shape &q) -> hipError_t {
+                if (k == 0)
+                    return launch_q1_sweep(D, L.prec, L.n, L.P, bbuf(h, l), cbuf(h, l, 0), cbuf(h, l, 1), h->opt.omega,
+                                           st, q);
+                if (k == 1)
+                    return launch_q1_restrict(D, L.prec, h->lv[l + 1].prec, L.n, L.P, bbuf(h, l), cbuf(h, l, 0),
+                                              h->ws + h->off_q1r, bbuf(h, l + 1), st, q);
+                const bool d = h->defer > 0;  // the ring counter is zero: slot 0
+                return launch_q1_outer(D, L.prec, L.n, L.P, cbuf(h, 0, 0), Rbuf(h), Ubuf(h), scal(h),
+                                       update_factor(h), part(h), st, d ? (void *)(h->ws + h->off_cdef) : nullptr,
+                                       h->cdef_stride, d ? at_ws<double>(h, h->off_adef) : nullptr,
+                                       d ? at_ws<int>(h, h->off_dctr) : nullptr, q);
+            };
+            Q1Shape best{};
+            float tb = time_ms(st, [&]() { return run(Q1Shape{}); }, 5);
+            for (int ty = 1; ty <= 8; ++ty)
+                for (int zc : {2, 4, 8, 16, 32}) {
+                    const Q1Shape q{ty, zc};
+                    if (!q1_shape_ok(D, L.prec, L.n, L.P, q)) continue;
+                    const float t = time_ms(st, [&]() { return run(q); }, 5);
+                    if (t < tb) tb = t, best = q;
+                }
+            L.q1s[k] = best;
+        }
+    }
+    set_fused(h, h->fused);
+    HIPCHK(hipMemsetAsync(h->ws, 0, h->ws_need, st));
+    HIPCHK(hipStreamSynchronize(st));
+    v.clear();
+    for (int l = 0; l + 1 < h->nl; ++l)
+        for (int k = 0; k < 3; ++k) v.insert(v.end(), {h->lv[l].q1s[k].ty, h->lv[l].q1s[k].zc});
+    cache_write(key, v);
+    return MG_OK;
+}
 }  // namespace
 
 namespace {
@@ -1473,8 +1543,8 @@ mg_status_t mg_bind_workspace(mg_handle h, void *dev_ptr, size_t bytes, void *st
         if (h->opt.autotune) return autotune_batched(h, st);
         return batched_upload(h);
     }
-    if (h->opt.autotune && !h->q1) {
-        mg_status_t s = autotune(h, st);
+    if (h->opt.autotune) {
+        mg_status_t s = h->q1 ? autotune_q1(h, st) : autotune(h, st);
         if (s != MG_OK) return s;
     }
     return MG_OK;
@@ -1807,7 +1877,24 @@ mg_status_t ir_solve(mg_handle h, const double *b, double *u, mg_stats_t *stats,
 mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np) {
     if (!h || !p) return fail(MG_ERR_ARG, "null argument");
     if (h->batched || h->nrhs) return fail(MG_ERR_STATE, "not available on a batched or many-right-hand-side handle");
-    if (h->q1) return fail(MG_ERR_STATE, "the Q1 kernels have no launch shapes");
+    if (h->q1) {
+        // the LDS-staged kernels' {ty, zc}: the sweep (MG_SHAPE_SWEEP), the
+        // residual (MG_SHAPE_RESTRICT), the update (MG_SHAPE_UPDATE, level 0)
+        const int k = q1_kind(kind);
+        if (k < 0) return fail(MG_ERR_STATE, "a Q1 handle has sweep, residual and update shapes only");
+        if (level < 0 || level >= h->nl - 1 || (k == 2 && level != 0))
+            return fail(MG_ERR_ARG, "level %d has no such Q1 kernel", level);
+        if (np != 2) return fail(MG_ERR_ARG, "a Q1 shape is {ty, zc} ({0, 0}: the built-in one)");
+        LevelPlan &L = h->lv[level];
+        const Q1Shape q{p[0], p[1]};
+        if (!q1_shape_ok(h->dim, L.prec, L.n, L.P, q))
+            return fail(MG_ERR_ARG, "Q1 shape {%d, %d} not valid on level %d (3-D levels in a 2-byte format only)",
+                        q.ty, q.zc, level);
+        L.q1s[k] = q;
+        set_fused(h, h->fused);  // the update's partial count
+        drop_graph(h);
+        return MG_OK;
+    }
     if (kind == MG_SHAPE_TAIL) {
         if (np != 1 || (p[0] != 0 && p[0] != 1)) return fail(MG_ERR_ARG, "the tail shape is {0|1}");
         h->tail_on = p[0] != 0;
@@ -1904,6 +1991,18 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
     if (kind == MG_SHAPE_TAIL) {
         if (np < 1) return fail(MG_ERR_ARG, "too few values");
         p[0] = h->tail_on ? 1 : 0;
+        return MG_OK;
+    }
+    if (h->q1) {
+        // the {ty, zc} the LDS-staged kernel uses ({0, 0}: the level has none)
+        const int k = q1_kind(kind);
+        if (k < 0) return fail(MG_ERR_STATE, "a Q1 handle has sweep, residual and update shapes only");
+        if (level < 0 || level >= h->nl - 1 || (k == 2 && level != 0))
+            return fail(MG_ERR_ARG, "level %d has no such Q1 kernel", level);
+        if (np < 2) return fail(MG_ERR_ARG, "too few values");
+        const LevelPlan &L = h->lv[level];
+        const Q1Shape u = q1_shape_used(h->dim, L.prec, L.n, L.P, L.q1s[k]);
+        p[0] = u.ty, p[1] = u.zc;
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE_SR) {

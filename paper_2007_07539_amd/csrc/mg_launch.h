@@ -153,21 +153,33 @@ hipError_t launch_cg_base(int D, int prec, int n, int P, const void *b, void *c,
 // Q1 finite elements (grid-scaled stencil S, see mg_q1.hip).  n is the level's
 // interior size (odd for levels with a coarser one), P = n + 1.
 // launch_q1_restrict writes the fine residual into rs (q1_resid_bytes) first.
+// Launch shape of the LDS-staged Q1 sweep, residual and update (3-D levels
+// stored in a 2-byte format, P a multiple of 4): ty rows per block, zc planes
+// per chunk; {0, 0} is the built-in choice.  Other levels ignore it.
+struct Q1Shape {
+    int ty = 0, zc = 0;
+};
+// Whether the level takes the LDS-staged kernels; whether s fits it (threads,
+// LDS, at most flat_blocks(points) blocks); the shape the kernels use for s.
+bool q1_lds_level(int D, int prec, int n, int P);
+bool q1_shape_ok(int D, int prec, int n, int P, const Q1Shape &s);
+Q1Shape q1_shape_used(int D, int prec, int n, int P, const Q1Shape &s);
 size_t q1_resid_bytes(int D, int prec, int P);
-int q1_outer_blocks(int D, int n, int prec);
+int q1_outer_blocks(int D, int n, int prec, const Q1Shape &s = Q1Shape{});
 hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const double *R, const double *scal,
                            void *b_out, void *c_out, double omega, hipStream_t st);
 hipError_t launch_q1_sweep(int D, int prec, int n, int P, const void *b, const void *c, void *c_out, double omega,
-                           hipStream_t st);
+                           hipStream_t st, const Q1Shape &s = Q1Shape{});
 hipError_t launch_q1_restrict(int D, int pf, int pc, int n, int P, const void *b, const void *c, void *rs, void *bc,
-                              hipStream_t st);
+                              hipStream_t st, const Q1Shape &s = Q1Shape{});
+// s: the shape of the sweep that follows the prolongation
 hipError_t launch_q1_prolong(int D, int pf, int pc, int n, int P, const void *c, const void *ec, const void *b,
-                             void *c_out, double omega, hipStream_t st);
+                             void *c_out, double omega, hipStream_t st, const Q1Shape &s = Q1Shape{});
 // cdefer != nullptr: postponed update (the correction goes to ring slot *ctr
 // of cstride elements, alpha to adef[*ctr]; U untouched).
 hipError_t launch_q1_outer(int D, int prec, int n, int P, const void *c, double *R, double *U, const double *scal,
                            double f, double *part, hipStream_t st, void *cdefer = nullptr, size_t cstride = 0,
-                           double *adef = nullptr, const int *ctr = nullptr);
+                           double *adef = nullptr, const int *ctr = nullptr, const Q1Shape &s = Q1Shape{});
 hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,
                                 double hd, double *part, hipStream_t st);
 hipError_t launch_q1_coarse(int D, int prec, const void *b, void *c, hipStream_t st);

@@ -852,40 +852,49 @@ hipError_t first_t(int D, int n, int P, const void *b, const double *R, const do
     return hipGetLastError();
 }
 
-// Shape of k_q1_lds on a 3-D level of pitch P (a multiple of 4): the most rows
-// per block that 1024 threads and 64 KB of LDS allow, up to 6, and up to 16
+// Shape of k_q1_lds on a 3-D level of pitch P (a multiple of 4), o.ty rows
+// and o.zc planes, or with o.ty = 0 the built-in choice: the most rows per
+// block that 1024 threads and 64 KB of LDS allow, up to 6, and up to 16
 // planes, fewer where that leaves under about four blocks per CU.
 struct Q1LdsShape {
     int TY, zc, ytiles, blocks;
     size_t lds;
 };
-Q1LdsShape q1_lds_shape(int n, int P, size_t sb) {
+Q1LdsShape q1_lds_shape(int n, int P, size_t sb, const Q1Shape &o = Q1Shape{}) {
     Q1LdsShape s{};
     const int TX = P / 4;
-    s.TY = std::min(6, 1024 / TX - 2);
-    while (s.TY > 1 && 2 * (((size_t)s.TY + 2) * P + 8) * sb > 65536 - 512) --s.TY;
+    if (o.ty > 0) {
+        s.TY = o.ty;
+        s.zc = o.zc;
+    } else {
+        s.TY = std::min(6, 1024 / TX - 2);
+        while (s.TY > 1 && 2 * (((size_t)s.TY + 2) * P + 8) * sb > 65536 - 512) --s.TY;
+        s.zc = std::max(2, std::min(16, (int)(((long)n * ((n + s.TY - 1) / s.TY) + 1023) / 1024)));
+        s.zc = std::min(s.zc, n);
+    }
     s.ytiles = (n + s.TY - 1) / s.TY;
-    s.zc = std::max(2, std::min(16, (int)(((long)n * s.ytiles + 1023) / 1024)));
-    s.zc = std::min(s.zc, n);
-    s.blocks = s.ytiles * ((n + s.zc - 1) / s.zc);
+    s.blocks = s.zc >= 1 ? s.ytiles * ((n + s.zc - 1) / s.zc) : 0;
     s.lds = 2 * (((size_t)s.TY + 2) * P + 8) * sb;
     return s;
 }
 // Whether the 3-D level takes k_q1_lds (2-byte format, pitch a multiple of 4,
 // room for two rows of threads plus one owned row, and no more blocks than the
-// update's partials allow).
-bool q1_lds_ok(int n, int P, size_t sb) {
+// update's partials allow) in shape o.
+bool q1_lds_ok(int n, int P, size_t sb, const Q1Shape &o = Q1Shape{}) {
     // the 2-byte formats (the 4- and 8-byte ones measured faster marching with
     // their own row loads one plane ahead)
     if (sb != 2 || P % 4 != 0 || P / 4 > 1024 / 3) return false;
-    const Q1LdsShape s = q1_lds_shape(n, P, sb);
-    return s.TY >= 1 && s.blocks <= flat_blocks((long)npoints(3, n));
+    const Q1LdsShape s = q1_lds_shape(n, P, sb, o);
+    return s.TY >= 1 && (s.TY + 2) * (P / 4) <= 1024 && s.lds <= 65536 - 512 && s.zc >= 1 && s.zc <= n &&
+           s.blocks <= flat_blocks((long)npoints(3, n));
 }
 
 template <class T, int MODE, bool DEFER = false>
 hipError_t q1_lds_launch(int n, int P, const void *b, const void *c, void *out, acc_t<T> w, double *R, double *U,
-                         const double *scal, double f, double *part, const Q1Ring &ring, hipStream_t st) {
-    const Q1LdsShape s = q1_lds_shape(n, P, sizeof(T));
+                         const double *scal, double f, double *part, const Q1Ring &ring, const Q1Shape &o,
+                         hipStream_t st) {
+    if (!q1_lds_ok(n, P, sizeof(T), o)) return hipErrorInvalidValue;
+    const Q1LdsShape s = q1_lds_shape(n, P, sizeof(T), o);
     hipLaunchKernelGGL((k_q1_lds<T, MODE, DEFER>), dim3(s.blocks), dim3((s.TY + 2) * (P / 4)), s.lds, st,
                        static_cast<const T *>(b), static_cast<const T *>(c), out, n, P, s.TY, s.zc, s.ytiles, w, R, U,
                        scal, f, part, ring);
@@ -893,11 +902,12 @@ hipError_t q1_lds_launch(int n, int P, const void *b, const void *c, void *out, 
 }
 
 template <class T>
-hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout, double omega, hipStream_t st) {
+hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout, double omega, const Q1Shape &qs,
+                   hipStream_t st) {
     typedef acc_t<T> A;
     const A w = (A)(omega * 0.375);
     if (D == 3 && q1_lds_ok(n, P, sizeof(T)))
-        return q1_lds_launch<T, 0>(n, P, b, c, cout, w, nullptr, nullptr, nullptr, 0.0, nullptr, Q1Ring{}, st);
+        return q1_lds_launch<T, 0>(n, P, b, c, cout, w, nullptr, nullptr, nullptr, 0.0, nullptr, Q1Ring{}, qs, st);
     if (P % 4 == 0) {
         const dim3 g4 = q1_grid4(D, n, P);
         if (D == 3)
@@ -918,7 +928,8 @@ hipError_t sweep_t(int D, int n, int P, const void *b, const void *c, void *cout
 }
 
 template <class T, class TC>
-hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *rs, void *bc, hipStream_t st) {
+hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *rs, void *bc, const Q1Shape &qs,
+                      hipStream_t st) {
     typedef acc_t<T> A;
     const int nc = (n - 1) / 2, Pc = nc + 1;
     const unsigned Nc = npoints(D, nc);
@@ -927,7 +938,7 @@ hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *r
         const dim3 g4 = q1_grid4(D, n, P);
         if (D == 3 && q1_lds_ok(n, P, sizeof(T))) {
             const hipError_t e = q1_lds_launch<T, 1>(n, P, b, c, static_cast<void *>(r), A(0), nullptr, nullptr,
-                                                     nullptr, 0.0, nullptr, Q1Ring{}, st);
+                                                     nullptr, 0.0, nullptr, Q1Ring{}, qs, st);
             if (e != hipSuccess) return e;
         } else if (D == 3)
             hipLaunchKernelGGL((k_q1_march4<T, true>), q1_grid4z(n, P), dim3(q1_bx4(P)), 0, st,
@@ -1005,9 +1016,9 @@ dim3 q1_outer_grid(int D, int n) {
 
 template <class T, bool DEFER>
 hipError_t outer_t(int D, int n, int P, const void *c, double *R, double *U, const double *scal, double f,
-                   double *part, const Q1Ring &ring, hipStream_t st) {
+                   double *part, const Q1Ring &ring, const Q1Shape &qs, hipStream_t st) {
     if (D == 3 && q1_lds_ok(n, P, sizeof(T)))
-        return q1_lds_launch<T, 2, DEFER>(n, P, nullptr, c, nullptr, acc_t<T>(0), R, U, scal, f, part, ring, st);
+        return q1_lds_launch<T, 2, DEFER>(n, P, nullptr, c, nullptr, acc_t<T>(0), R, U, scal, f, part, ring, qs, st);
     const dim3 g = q1_outer_grid(D, n);
     if (q1_outer_marches(D, n)) {
         const int zc = (n + (int)g.z - 1) / (int)g.z;
@@ -1051,9 +1062,22 @@ size_t q1_resid_bytes(int D, int prec, int P) {
     return level_elems(D, P) * (prec == P_F64 ? sizeof(double) : sizeof(float));
 }
 
-int q1_outer_blocks(int D, int n, int prec) {
+bool q1_lds_level(int D, int prec, int n, int P) { return D == 3 && q1_lds_ok(n, P, prec_bytes(prec)); }
+
+bool q1_shape_ok(int D, int prec, int n, int P, const Q1Shape &s) {
+    if (s.ty == 0 && s.zc == 0) return true;
+    return q1_lds_level(D, prec, n, P) && s.ty > 0 && q1_lds_ok(n, P, prec_bytes(prec), s);
+}
+
+Q1Shape q1_shape_used(int D, int prec, int n, int P, const Q1Shape &s) {
+    if (!q1_lds_level(D, prec, n, P)) return Q1Shape{};
+    const Q1LdsShape u = q1_lds_shape(n, P, prec_bytes(prec), s);
+    return Q1Shape{u.TY, u.zc};
+}
+
+int q1_outer_blocks(int D, int n, int prec, const Q1Shape &qs) {
     const int P = n + 1;
-    if (D == 3 && q1_lds_ok(n, P, prec_bytes(prec))) return q1_lds_shape(n, P, prec_bytes(prec)).blocks;
+    if (D == 3 && q1_lds_ok(n, P, prec_bytes(prec))) return q1_lds_shape(n, P, prec_bytes(prec), qs).blocks;
     const dim3 g = q1_outer_grid(D, n);
     return (int)(g.x * g.y * g.z);
 }
@@ -1064,35 +1088,35 @@ hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const d
 }
 
 hipError_t launch_q1_sweep(int D, int prec, int n, int P, const void *b, const void *c, void *c_out, double omega,
-                           hipStream_t st) {
-    Q1_DISPATCH(prec, TT, return sweep_t<TT>(D, n, P, b, c, c_out, omega, st));
+                           hipStream_t st, const Q1Shape &s) {
+    Q1_DISPATCH(prec, TT, return sweep_t<TT>(D, n, P, b, c, c_out, omega, s, st));
 }
 
 hipError_t launch_q1_restrict(int D, int pf, int pc, int n, int P, const void *b, const void *c, void *rs, void *bc,
-                              hipStream_t st) {
+                              hipStream_t st, const Q1Shape &s) {
     if (n < 3 || n % 2 == 0) return hipErrorInvalidValue;
-    Q1_DISPATCH(pf, TF, Q1_DISPATCH(pc, TC, return (restrict_t<TF, TC>(D, n, P, b, c, rs, bc, st))));
+    Q1_DISPATCH(pf, TF, Q1_DISPATCH(pc, TC, return (restrict_t<TF, TC>(D, n, P, b, c, rs, bc, s, st))));
 }
 
 hipError_t launch_q1_prolong(int D, int pf, int pc, int n, int P, const void *c, const void *ec, const void *b,
-                             void *c_out, double omega, hipStream_t st) {
+                             void *c_out, double omega, hipStream_t st, const Q1Shape &s) {
     if (n < 3 || n % 2 == 0) return hipErrorInvalidValue;
     hipError_t e = hipErrorInvalidValue;
     Q1_DISPATCH(pf, TF, Q1_DISPATCH(pc, TC, e = (prolong_t<TF, TC>(D, n, P, const_cast<void *>(c), ec, st)); break);
                 break);
     if (e != hipSuccess) return e;
-    return launch_q1_sweep(D, pf, n, P, b, c, c_out, omega, st);
+    return launch_q1_sweep(D, pf, n, P, b, c, c_out, omega, st, s);
 }
 
 hipError_t launch_q1_outer(int D, int prec, int n, int P, const void *c, double *R, double *U, const double *scal,
                            double f, double *part, hipStream_t st, void *cdefer, size_t cstride, double *adef,
-                           const int *ctr) {
+                           const int *ctr, const Q1Shape &s) {
     const Q1Ring ring{cdefer, cstride, adef, ctr};
     if (cdefer) {
         if (!adef || !ctr) return hipErrorInvalidValue;
-        Q1_DISPATCH(prec, TT, return (outer_t<TT, true>(D, n, P, c, R, U, scal, f, part, ring, st)));
+        Q1_DISPATCH(prec, TT, return (outer_t<TT, true>(D, n, P, c, R, U, scal, f, part, ring, s, st)));
     }
-    Q1_DISPATCH(prec, TT, return (outer_t<TT, false>(D, n, P, c, R, U, scal, f, part, ring, st)));
+    Q1_DISPATCH(prec, TT, return (outer_t<TT, false>(D, n, P, c, R, U, scal, f, part, ring, s, st)));
 }
 
 hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const double *U, double *R, double *uout,

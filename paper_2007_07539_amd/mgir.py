@@ -283,9 +283,12 @@ class Solver:
 
     def get_shape(self, level: int, kind: int, count: int | None = None):
         """The shape's values (count of them; default: the set a caller passes
-        to set_shape, e.g. three for SHAPE_FUSE_SR, four to include lds16)."""
+        to set_shape, e.g. three for SHAPE_FUSE_SR, four to include lds16, two
+        ({ty, zc}) on a Q1 handle)."""
         arr = (ctypes.c_int * 7)()
         _check(self.lib.mg_get_shape(self._h, level, kind, arr, 7), "mg_get_shape")
+        if count is None and getattr(self, "disc", "fd") == "q1":
+            count = 2
         n = {SHAPE_RESTRICT: 4, SHAPE_TAIL: 1, SHAPE_FUSE: 5, SHAPE_FUSE_SR: 3}.get(kind, 6) if count is None else count
         return list(arr[:n])
 

@@ -260,3 +260,108 @@ def test_q1_deferred_update_bitwise(dev, name, dim, n):
         assert r1.status == 0 and r1.iterations == r0.iterations, k
         assert r1.history == r0.history, k
         assert torch.equal(u1, u0), k
+
+
+Q1_KINDS = (mgir.SHAPE_SWEEP, mgir.SHAPE_RESTRICT, mgir.SHAPE_UPDATE)
+
+
+def _q1_lds_levels(s):
+    return [l for l in range(s.nlevels - 1) if s.get_shape(l, mgir.SHAPE_SWEEP) != [0, 0]]
+
+
+@pytest.mark.parametrize("name,n,defer", [("f16", 63, 4), ("bf16", 95, 0), ("f16", 127, 0), ("hsd", 63, 0)])
+def test_q1_lds_shapes_bitwise(dev, name, n, defer):
+    """The LDS-staged Q1 sweep, residual and update in other launch shapes
+    (rows and planes per block, ragged last tiles and chunks) give u bit for bit
+    and the same iteration count as the built-in shapes; the norms are summed
+    over other blocks, so the history may differ in the last bits."""
+    print(f"q1 shapes {name} n={n} defer={defer}", flush=True)
+    prec = W.precision_map(name, mgir.full_levels(n))
+    b = torch.from_numpy(W.q1_load_vector(3, n, seed=121)).to(dev)
+    s = mgir.Solver(3, n, prec, disc="q1", defer_update=defer, residual_scaling=True)
+    levels = _q1_lds_levels(s)
+    assert levels and levels[0] == 0
+    for l in levels:
+        for k in Q1_KINDS[: 3 if l == 0 else 2]:
+            ty, zc = s.get_shape(l, k)
+            assert ty >= 1 and zc >= 1
+    u0, r0 = s.solve(b)
+    u0 = u0.clone()
+    tried = 0
+    for ty, zc in ((1, 2), (3, 5), (5, 16), (2, 32), (4, 7), (6, 1)):
+        set_any = False
+        for l in levels:
+            for k in Q1_KINDS[: 3 if l == 0 else 2]:
+                try:
+                    s.set_shape(l, k, [ty, zc])
+                    set_any = True
+                    assert s.get_shape(l, k) == [ty, zc]
+                except mgir.MgError:
+                    s.set_shape(l, k, [0, 0])
+        if not set_any:
+            continue
+        tried += 1
+        print(f"  shape ty={ty} zc={zc}", flush=True)
+        u, r = s.solve(b)
+        assert r.status == 0 and r.iterations == r0.iterations, (ty, zc)
+        assert np.allclose(r.history, r0.history, rtol=1e-12, atol=0), (ty, zc)
+        assert torch.equal(u, u0), (ty, zc)
+    assert tried >= 4
+
+
+def test_q1_shapes_refused(dev):
+    """Q1 shapes exist only for the LDS-staged kernels: other kinds, levels
+    without such kernels, the update below level 0 and shapes that do not fit
+    are refused; {0, 0} restores the built-in shape."""
+    n = 63
+    m = mgir.full_levels(n)
+    s = mgir.Solver(3, n, W.precision_map("hsd", m), disc="q1")
+    builtin = s.get_shape(0, mgir.SHAPE_SWEEP)
+    for kind in (mgir.SHAPE_FUSE, mgir.SHAPE_SMOOTH, mgir.SHAPE_PROLONG, mgir.SHAPE_TAIL):
+        with pytest.raises(mgir.MgError):
+            s.set_shape(0, kind, [1])
+    with pytest.raises(mgir.MgError):
+        s.set_shape(1, mgir.SHAPE_UPDATE, [2, 4])
+    for bad in ([300, 2], [2, 0], [0, 4], [-1, 2], [2, n + 1]):
+        with pytest.raises(mgir.MgError):
+            s.set_shape(0, mgir.SHAPE_SWEEP, bad)
+    with pytest.raises(mgir.MgError):
+        s.set_shape(0, mgir.SHAPE_SWEEP, [2, 4, 1])
+    s.set_shape(0, mgir.SHAPE_SWEEP, [2, 4])
+    assert s.get_shape(0, mgir.SHAPE_SWEEP) == [2, 4]
+    s.set_shape(0, mgir.SHAPE_SWEEP, [0, 0])
+    assert s.get_shape(0, mgir.SHAPE_SWEEP) == builtin
+    f64 = mgir.Solver(3, n, W.precision_map("f64", m), disc="q1", residual_scaling=False)
+    assert f64.get_shape(0, mgir.SHAPE_SWEEP) == [0, 0]
+    with pytest.raises(mgir.MgError):
+        f64.set_shape(0, mgir.SHAPE_SWEEP, [2, 4])
+    f64.set_shape(0, mgir.SHAPE_SWEEP, [0, 0])
+    s2 = mgir.Solver(2, 255, W.precision_map("f16", mgir.full_levels(255)), disc="q1")
+    assert s2.get_shape(0, mgir.SHAPE_SWEEP) == [0, 0]
+    with pytest.raises(mgir.MgError):
+        s2.set_shape(0, mgir.SHAPE_SWEEP, [2, 4])
+
+
+def test_q1_autotuned_bitwise_and_cached(dev, tmp_path, monkeypatch):
+    """The Q1 autotuner picks shapes that fit, the solve matches the built-in
+    shapes bit for bit, and a second handle of the same configuration reads
+    the shapes back from the cache instead of timing."""
+    n = 95
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MGIR_TUNE_CACHE", str(path))
+    prec = W.precision_map("f16", mgir.full_levels(n))
+    b = torch.from_numpy(W.q1_load_vector(3, n, seed=122)).to(dev)
+    u0, r0 = mgir.Solver(3, n, prec, disc="q1", defer_update=8).solve(b)
+    a = mgir.Solver(3, n, prec, disc="q1", defer_update=8, autotune=True)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and "|q1\t" in lines[0]
+    c = mgir.Solver(3, n, prec, disc="q1", defer_update=8, autotune=True)
+    assert path.read_text().splitlines() == lines
+
+    def shapes(s):
+        return [s.get_shape(l, k) for l in _q1_lds_levels(s) for k in Q1_KINDS[: 3 if l == 0 else 2]]
+
+    assert shapes(a) == shapes(c) and all(t >= 1 and z >= 1 for t, z in shapes(a))
+    for s in (a, c):
+        u, r = s.solve(b)
+        assert r.iterations == r0.iterations and torch.equal(u, u0)
