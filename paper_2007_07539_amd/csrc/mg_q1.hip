@@ -430,14 +430,19 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
 // for x0 - 1 .. x0 + 4 from LDS, with the same sums as k_q1_march4, so the
 // results are identical.  MODE 0: the sweep (out = c + w (b - S c) in T),
 // 1: the residual (out = b - S c in the accumulator format), 2: the FP64
-// update (R -= alpha S c; U += alpha f c, or the correction into the ring).
+// update (R -= alpha S c; U += alpha f c, or the correction into the ring),
+// 3: the FP64 residual r = b - f S c of the iterate c = u from the dense b
+// (n x n x n, x fastest) into R, u copied to the dense out (if not null).
+// Modes 2 and 3 write one (sum r^2, max |r|) partial per block, and mode 3
+// zeros for blocks gridDim.x .. nparts - 1 (the count the caller reduces).
 template <class T, int MODE, bool DEFER = false>
 __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const T *__restrict__ c,
                                                  void *__restrict__ out, int n, int P, int TY, int zc, int ytiles,
                                                  acc_t<T> w, double *__restrict__ R, double *__restrict__ U,
                                                  const double *__restrict__ scal, double f, double *__restrict__ part,
-                                                 Q1Ring ring) {
-    typedef typename std::conditional<MODE == 2, double, acc_t<T>>::type A;
+                                                 Q1Ring ring, int nparts) {
+    static_assert(MODE != 3 || sizeof(T) == 8, "the final residual is formed from the FP64 u");
+    typedef typename std::conditional<MODE >= 2, double, acc_t<T>>::type A;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[32];
     T *lds = reinterpret_cast<T *>(smem_raw);
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
     publish(0, rr);  // slot 0's plane z0 - 1 was read before the last barrier
     if (z0 + 2 <= z1 + 1) fetch(z0 + 2, rr);
     RawRow<T, 4> bq;
-    if (MODE != 2 && outr) fetch_row<T, 4>(b + g.at(x0, y, z0), bq);
+    if (MODE < 2 && outr) fetch_row<T, 4>(b + g.at(x0, y, z0), bq);
     RawRow<double, 4> rq, uq;
     if (MODE == 2 && outr) {
         fetch_row<double, 4>(R + g.at(x0, y, z0), rq);
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
         if (outr) {
             rows(sp, Ap, Cp);
             if (z + 1 <= z1) {
-                if (MODE != 2) fetch_row<T, 4>(b + g.at(x0, y, z + 1), bq);
+                if (MODE < 2) fetch_row<T, 4>(b + g.at(x0, y, z + 1), bq);
                 if (MODE == 2) {
                     fetch_row<double, 4>(R + g.at(x0, y, z + 1), rq);
                     if (!DEFER) fetch_row<double, 4>(U + g.at(x0, y, z + 1), uq);
@@ -554,6 +559,23 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ov[i] = (i == 0 && first) ? A(0) : bv[i] - sc[i];
                 store_row<A, 4>(static_cast<A *>(out) + o, ov);
+            } else if constexpr (MODE == 3) {
+                // dense b and out: point (x, y, z) at ((z-1) n + (y-1)) n + x-1
+                // (the ghost x = 0 reads the row's first point and drops it)
+                const size_t d = ((size_t)(z - 1) * n + (y - 1)) * n;
+                double rv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bool ghost = i == 0 && first;
+                    const size_t at = d + (size_t)(ghost ? 0 : x0 + i - 1);
+                    const double bv = reinterpret_cast<const double *>(b)[at];
+                    const double r = ghost ? 0.0 : bv - f * sc[i];
+                    rv[i] = r;
+                    ss += r * r;
+                    mx = nanmax(mx, fabs(r));
+                    if (out && !ghost) static_cast<double *>(out)[at] = C0[i + 1];
+                }
+                store_row<double, 4>(R + o, rv);
             } else {
                 double rv[4], uv[4] = {};
                 widen_row<double, 4>(rcur, rv);
@@ -590,11 +612,13 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
             A0[k] = Ap[k], C0[k] = Cp[k];
         }
     }
-    if constexpr (MODE == 2) {
+    if constexpr (MODE >= 2) {
         block_reduce(ss, mx, red);
         if (threadIdx.x == 0) {
             part[2 * blockIdx.x] = ss;
             part[2 * blockIdx.x + 1] = mx;
+            if constexpr (MODE == 3)
+                for (int i = blockIdx.x + gridDim.x; i < nparts; i += gridDim.x) part[2 * i] = part[2 * i + 1] = 0.0;
         }
     }
 }
@@ -897,8 +921,18 @@ hipError_t q1_lds_launch(int n, int P, const void *b, const void *c, void *out, 
     const Q1LdsShape s = q1_lds_shape(n, P, sizeof(T), o);
     hipLaunchKernelGGL((k_q1_lds<T, MODE, DEFER>), dim3(s.blocks), dim3((s.TY + 2) * (P / 4)), s.lds, st,
                        static_cast<const T *>(b), static_cast<const T *>(c), out, n, P, s.TY, s.zc, s.ytiles, w, R, U,
-                       scal, f, part, ring);
+                       scal, f, part, ring, s.blocks);
     return hipGetLastError();
+}
+
+// The final residual r = b - hd S u of a 3-D level from the dense b (k_q1_lds
+// mode 3): FP64 rows in LDS, the built-in shape for 8-byte elements; false
+// where it does not apply (pitch, threads, LDS, more blocks than partials).
+bool q1_final_lds_ok(int n, int P) {
+    if (P % 4 != 0 || P / 4 > 1024 / 3) return false;
+    const Q1LdsShape s = q1_lds_shape(n, P, sizeof(double));
+    return s.TY >= 1 && (s.TY + 2) * (P / 4) <= 1024 && s.lds <= 65536 - 512 &&
+           s.blocks <= flat_blocks((long)npoints(3, n));
 }
 
 template <class T>
@@ -1123,6 +1157,14 @@ hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const doub
                                 double hd, double *part, hipStream_t st) {
     const unsigned N = npoints(D, n);
     const int blocks = flat_blocks((long)N);
+    if (D == 3 && U && R && q1_final_lds_ok(n, P)) {
+        // the LDS-staged form; it writes the partials of all `blocks`
+        const Q1LdsShape s = q1_lds_shape(n, P, sizeof(double));
+        hipLaunchKernelGGL((k_q1_lds<double, 3>), dim3(s.blocks), dim3((s.TY + 2) * (P / 4)), s.lds, st, b, U,
+                           static_cast<void *>(uout), n, P, s.TY, s.zc, s.ytiles, 0.0, R, nullptr, nullptr, hd, part,
+                           Q1Ring{}, blocks);
+        return hipGetLastError();
+    }
     if (D == 3)
         hipLaunchKernelGGL(k_q1_resid_flat<3>, dim3(blocks), dim3(kThreads), 0, st, b, U, R, uout, n, P, N, hd, part);
     else
