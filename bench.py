@@ -73,10 +73,14 @@ def measured_traffic(kernel):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def kernel_table(prof, level=0):
-    """Aggregate one profiled refinement step by kernel name on one level."""
+def kernel_table(profs, level=0):
+    """Aggregate profiled refinement steps (one step's list, or a list of
+    them) by kernel name on one level: launches, total time and bytes, and the
+    mean launch duration."""
+    if profs and isinstance(profs[0], tuple):
+        profs = [profs]
     agg = {}
-    for name, lvl, ms, by in prof:
+    for name, lvl, ms, by in (rec for prof in profs for rec in prof):
         if lvl != level:
             continue
         a = agg.setdefault(name, {"launches": 0, "ms": 0.0, "bytes": 0.0})
@@ -87,6 +91,12 @@ def kernel_table(prof, level=0):
         a["avg_ms"] = a["ms"] / a["launches"]
         a["GBps"] = a["bytes"] / (a["ms"] * 1e-3) / 1e9 if a["ms"] > 0 else 0.0
     return agg
+
+
+def profiled_steps(s, k=5):
+    """k refinement steps run eagerly with every launch timed (HIP events on
+    the solver's stream), after the timed solves."""
+    return [s.profile_step() for _ in range(k)]
 
 
 def bandwidth_ceiling(torch, mgir, reps=5):
@@ -539,7 +549,7 @@ def main():
         ms, res = timed_solves(s, bt, u, args.steps, args.warmup, torch)
         log(f"[bench] mixed defer={depth}: {ms:.2f} ms/solve, {res[-1].iterations} it, "
             f"rel {res[-1].rel_residual:.2e}")
-        mixed_runs[depth] = {"ms": ms, "res": res[-1], "shapes": shapes_of(s), "prof": s.profile_step(),
+        mixed_runs[depth] = {"ms": ms, "res": res[-1], "shapes": shapes_of(s), "prof": profiled_steps(s),
                              "u": u.cpu().numpy() if not args.profile_only else None}
         del s
         torch.cuda.empty_cache()
@@ -569,7 +579,7 @@ def main():
                 s.set_shape(0, mgir.SHAPE_FUSE_SR, [0])
             ms, res = timed_solves(s, bt, u, args.steps, args.warmup, torch)
             log(f"[bench] fp64 {label}: {ms:.2f} ms/solve, {res[-1].iterations} it, rel {res[-1].rel_residual:.2e}")
-            fp64_runs[label] = {"ms": ms, "res": res[-1], "shapes": shapes_of(s), "prof": s.profile_step(),
+            fp64_runs[label] = {"ms": ms, "res": res[-1], "shapes": shapes_of(s), "prof": profiled_steps(s),
                                 "u": u.cpu().numpy() if label == "fused" else None}
             del s
             torch.cuda.empty_cache()
