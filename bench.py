@@ -377,7 +377,7 @@ def extra_workloads(torch, mgir, W, dev, steps, bt=None, n=511, ms64=None, tune=
                 log(f"[bench] Q1 {dim}-D n={nq}, map {name}")
                 s = mgir.Solver(dim, nq, W.precision_map(name, Lq), disc="q1", residual_scaling=name != "f64",
                                 device=dev, autotune=tune, **(dk if name != "f64" else {}))
-                q1sh = [s.get_shape(l, k) for l in range(s.nlevels - 1)
+                q1sh = [s.get_shape(l, k, 3 if k == mgir.SHAPE_RESTRICT else 2) for l in range(s.nlevels - 1)
                         for k in (mgir.SHAPE_SWEEP, mgir.SHAPE_RESTRICT, mgir.SHAPE_UPDATE)[: 3 if l == 0 else 2]
                         if s.get_shape(l, mgir.SHAPE_SWEEP) != [0, 0]]
                 u0 = torch.zeros_like(bq)

@@ -431,6 +431,9 @@ typedef enum {
  * block), zc (planes per block)}, or {0, 0} for the built-in choice; a shape
  * must fit 1024 threads ((ty + 2) P / 4), 64 KB of LDS and the update's partial
  * budget (MG_ERR_ARG otherwise, and on other levels for any shape but {0, 0}).
+ * The residual runs fused with its restriction (the fine residual kept in LDS,
+ * bitwise the same coarse b): its shape takes even ty and zc and (ty + 3) P / 4
+ * threads; {ty, zc, 1} runs residual and restriction as two kernels instead.
  * The other kinds return MG_ERR_STATE.  opt.autotune times these shapes per
  * level and kernel against the built-in one (cached as for finite differences).
  * Reading returns the {ty, zc} in use, {0, 0} on levels without such kernels. */

@@ -1195,15 +1195,17 @@ int q1_kind(int kind) {
     return kind == MG_SHAPE_SWEEP ? 0 : kind == MG_SHAPE_RESTRICT ? 1 : kind == MG_SHAPE_UPDATE ? 2 : -1;
 }
 
-// The Q1 shapes as integers: per level {ty, zc} of the sweep, the residual
-// and the update.
+// The Q1 shapes as integers: per level {ty, zc, split} of the sweep, the
+// residual and the update.
 bool apply_q1_state(mg_ctx *h, const std::vector<int> &v) {
-    if (v.size() != (size_t)6 * (h->nl - 1)) return false;
+    if (v.size() != (size_t)9 * (h->nl - 1)) return false;
     std::vector<LevelPlan> lv = h->lv;
     for (int l = 0; l + 1 < h->nl; ++l)
         for (int k = 0; k < 3; ++k) {
-            const Q1Shape q{v[6 * l + 2 * k], v[6 * l + 2 * k + 1]};
-            if (!q1_shape_ok(h->dim, lv[l].prec, lv[l].n, lv[l].P, q) || (k == 2 && l > 0 && q.ty != 0)) return false;
+            const int *e = &v[9 * l + 3 * k];
+            const Q1Shape q{e[0], e[1], e[2]};
+            if (!q1_shape_ok(h->dim, lv[l].prec, lv[l].n, lv[l].P, k, q) || (k == 2 && l > 0 && q.ty != 0))
+                return false;
             lv[l].q1s[k] = q;
         }
     h->lv = lv;
@@ -1212,8 +1214,9 @@ bool apply_q1_state(mg_ctx *h, const std::vector<int> &v) {
 }
 
 // The Q1 autotuner: on each level that takes the LDS-staged kernels, each of
-// them timed over {ty, zc} against the built-in shape, which stays unless
-// another is faster.  The result is cached like the finite-difference one.
+// them timed over {ty, zc} (the residual also as two kernels, split = 1)
+// against the built-in shape, which stays unless another is faster.  The
+// result is cached like the finite-difference one.
 mg_status_t autotune_q1(mg_ctx *h, hipStream_t st) {
     const std::string key = tune_key(h).empty() ? std::string() : tune_key(h) + "|q1";
     std::vector<int> v;
@@ -1238,13 +1241,15 @@ mg_status_t autotune_q1(mg_ctx *h, hipStream_t st) {
             };
             Q1Shape best{};
             float tb = time_ms(st, [&]() { return run(Q1Shape{}); }, 5);
-            for (int ty = 1; ty <= 8; ++ty)
-                for (int zc : {2, 4, 8, 16, 32}) {
-                    const Q1Shape q{ty, zc};
-                    if (!q1_shape_ok(D, L.prec, L.n, L.P, q)) continue;
-                    const float t = time_ms(st, [&]() { return run(q); }, 5);
-                    if (t < tb) tb = t, best = q;
-                }
+            for (int split = 0; split <= (k == 1 ? 1 : 0); ++split)
+                for (int ty = split ? 0 : 1; ty <= 8; ++ty)
+                    for (int zc : {0, 2, 4, 8, 16, 32}) {
+                        const Q1Shape q{ty, zc, split};
+                        if ((ty == 0) != (zc == 0) || (ty == 0 && !split)) continue;
+                        if (!q1_shape_ok(D, L.prec, L.n, L.P, k, q)) continue;
+                        const float t = time_ms(st, [&]() { return run(q); }, 5);
+                        if (t < tb) tb = t, best = q;
+                    }
             L.q1s[k] = best;
         }
     }
@@ -1253,7 +1258,7 @@ mg_status_t autotune_q1(mg_ctx *h, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     v.clear();
     for (int l = 0; l + 1 < h->nl; ++l)
-        for (int k = 0; k < 3; ++k) v.insert(v.end(), {h->lv[l].q1s[k].ty, h->lv[l].q1s[k].zc});
+        for (int k = 0; k < 3; ++k) v.insert(v.end(), {h->lv[l].q1s[k].ty, h->lv[l].q1s[k].zc, h->lv[l].q1s[k].split});
     cache_write(key, v);
     return MG_OK;
 }
@@ -1884,12 +1889,15 @@ mg_status_t mg_set_shape(mg_handle h, int level, int kind, const int *p, int np)
         if (k < 0) return fail(MG_ERR_STATE, "a Q1 handle has sweep, residual and update shapes only");
         if (level < 0 || level >= h->nl - 1 || (k == 2 && level != 0))
             return fail(MG_ERR_ARG, "level %d has no such Q1 kernel", level);
-        if (np != 2) return fail(MG_ERR_ARG, "a Q1 shape is {ty, zc} ({0, 0}: the built-in one)");
+        if (np != 2 && !(np == 3 && k == 1))
+            return fail(MG_ERR_ARG, "a Q1 shape is {ty, zc} ({0, 0}: the built-in one), the residual's {ty, zc[, split]}");
         LevelPlan &L = h->lv[level];
-        const Q1Shape q{p[0], p[1]};
-        if (!q1_shape_ok(h->dim, L.prec, L.n, L.P, q))
-            return fail(MG_ERR_ARG, "Q1 shape {%d, %d} not valid on level %d (3-D levels in a 2-byte format only)",
-                        q.ty, q.zc, level);
+        const Q1Shape q{p[0], p[1], np == 3 ? p[2] : 0};
+        if (!q1_shape_ok(h->dim, L.prec, L.n, L.P, k, q))
+            return fail(MG_ERR_ARG,
+                        "Q1 shape {%d, %d, split %d} not valid on level %d (3-D levels in a 2-byte format only; the "
+                        "fused residual + restriction takes even ty and zc)",
+                        q.ty, q.zc, q.split, level);
         L.q1s[k] = q;
         set_fused(h, h->fused);  // the update's partial count
         drop_graph(h);
@@ -2001,8 +2009,9 @@ mg_status_t mg_get_shape(mg_handle h, int level, int kind, int *p, int np) {
             return fail(MG_ERR_ARG, "level %d has no such Q1 kernel", level);
         if (np < 2) return fail(MG_ERR_ARG, "too few values");
         const LevelPlan &L = h->lv[level];
-        const Q1Shape u = q1_shape_used(h->dim, L.prec, L.n, L.P, L.q1s[k]);
+        const Q1Shape u = q1_shape_used(h->dim, L.prec, L.n, L.P, k, L.q1s[k]);
         p[0] = u.ty, p[1] = u.zc;
+        if (np >= 3) p[2] = k == 1 ? u.split : 0;
         return MG_OK;
     }
     if (kind == MG_SHAPE_FUSE_SR) {

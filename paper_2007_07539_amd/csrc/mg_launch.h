@@ -155,15 +155,18 @@ hipError_t launch_cg_base(int D, int prec, int n, int P, const void *b, void *c,
 // launch_q1_restrict writes the fine residual into rs (q1_resid_bytes) first.
 // Launch shape of the LDS-staged Q1 sweep, residual and update (3-D levels
 // stored in a 2-byte format, P a multiple of 4): ty rows per block, zc planes
-// per chunk; {0, 0} is the built-in choice.  Other levels ignore it.
+// per chunk; {0, 0} is the built-in choice.  Other levels ignore it.  The
+// residual runs fused with the restriction (even ty and zc) unless split = 1.
 struct Q1Shape {
     int ty = 0, zc = 0;
+    int split = 0;  // residual kernel: 1 = residual and restriction as two kernels
 };
-// Whether the level takes the LDS-staged kernels; whether s fits it (threads,
-// LDS, at most flat_blocks(points) blocks); the shape the kernels use for s.
+// Whether the level takes the LDS-staged kernels; whether s fits its kernel
+// (0 sweep, 1 residual, 2 update: threads, LDS, at most flat_blocks(points)
+// blocks where they write partials); the shape the kernel uses for s.
 bool q1_lds_level(int D, int prec, int n, int P);
-bool q1_shape_ok(int D, int prec, int n, int P, const Q1Shape &s);
-Q1Shape q1_shape_used(int D, int prec, int n, int P, const Q1Shape &s);
+bool q1_shape_ok(int D, int prec, int n, int P, int kernel, const Q1Shape &s);
+Q1Shape q1_shape_used(int D, int prec, int n, int P, int kernel, const Q1Shape &s);
 size_t q1_resid_bytes(int D, int prec, int P);
 int q1_outer_blocks(int D, int n, int prec, const Q1Shape &s = Q1Shape{});
 hipError_t launch_q1_first(int D, int prec, int n, int P, const void *b, const double *R, const double *scal,

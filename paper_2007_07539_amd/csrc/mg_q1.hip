@@ -435,28 +435,40 @@ __global__ __launch_bounds__(kThreads) void k_q1_outer_march(const T *__restrict
 // (n x n x n, x fastest) into R, u copied to the dense out (if not null).
 // Modes 2 and 3 write one (sum r^2, max |r|) partial per block, and mode 3
 // zeros for blocks gridDim.x .. nparts - 1 (the count the caller reduces).
-template <class T, int MODE, bool DEFER = false>
+// Mode 4: the residual of mode 1 restricted at once (full weighting into the
+// coarse b, format TC, at out): TY (even) owned rows y0 .. y0+TY-1 and the
+// row after them, whose residuals the coarse rows (y0+1)/2 .. (y0+TY-1)/2
+// need, zc (even) owned planes and the plane after them; each plane's
+// residual rows go to LDS (two slots), and after the plane's barrier the
+// coarse threads form the x and y sums and carry the z sums in registers, in
+// the order of k_q1_restrict (the same result).
+template <class T, int MODE, bool DEFER = false, class TC = T>
 __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const T *__restrict__ c,
                                                  void *__restrict__ out, int n, int P, int TY, int zc, int ytiles,
                                                  acc_t<T> w, double *__restrict__ R, double *__restrict__ U,
                                                  const double *__restrict__ scal, double f, double *__restrict__ part,
                                                  Q1Ring ring, int nparts) {
     static_assert(MODE != 3 || sizeof(T) == 8, "the final residual is formed from the FP64 u");
-    typedef typename std::conditional<MODE >= 2, double, acc_t<T>>::type A;
+    typedef typename std::conditional<MODE == 2 || MODE == 3, double, acc_t<T>>::type A;
+    constexpr bool FR = MODE == 4;  // residual + restriction
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[32];
     T *lds = reinterpret_cast<T *>(smem_raw);
-    const int TX = P / 4, G = TY + 2;
+    const int TX = P / 4, G = TY + (FR ? 3 : 2);
     const size_t slot = (size_t)G * P + 8;  // G rows and the ghost after the last one
+    // mode 4: the residual rows of a plane, two slots after the c slots
+    A *rbuf = reinterpret_cast<A *>(smem_raw + ((2 * slot * sizeof(T) + 15) & ~(size_t)15));
+    const size_t rslot = (size_t)(TY + 1) * P;
     const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int yt = blk % ytiles, zch = blk / ytiles;
     const int y0 = 1 + yt * TY;
-    const int z0 = 1 + zch * zc, z1 = min(z0 + zc - 1, n);
+    const int z0 = 1 + zch * zc, z1 = min(z0 + zc - (FR ? 0 : 1), n);
     const int tx = (int)threadIdx.x % TX, gi = (int)threadIdx.x / TX;
     const int x0 = 4 * tx;
     const int y = y0 - 1 + gi;
     const bool row_in = y >= 1 && y <= n;  // other rows are zero ghosts
-    const bool outr = gi >= 1 && gi <= TY && y <= n;
+    const bool outr = gi >= 1 && gi <= TY + (FR ? 1 : 0) && y <= n;
+    A pm = A(0), p0 = A(0);  // mode 4: the coarse thread's y/x sums of planes 2Z - 1 and 2Z
     const bool first = x0 == 0;
     const Grid<3> g{P};
     double ss = 0.0, mx = 0.0;
@@ -512,8 +524,9 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
     if (outr) rows(1, A0, C0);
     publish(0, rr);  // slot 0's plane z0 - 1 was read before the last barrier
     if (z0 + 2 <= z1 + 1) fetch(z0 + 2, rr);
+    constexpr bool READS_B = MODE <= 1 || MODE == 4;
     RawRow<T, 4> bq;
-    if (MODE < 2 && outr) fetch_row<T, 4>(b + g.at(x0, y, z0), bq);
+    if (READS_B && outr) fetch_row<T, 4>(b + g.at(x0, y, z0), bq);
     RawRow<double, 4> rq, uq;
     if (MODE == 2 && outr) {
         fetch_row<double, 4>(R + g.at(x0, y, z0), rq);
@@ -528,7 +541,7 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
         if (outr) {
             rows(sp, Ap, Cp);
             if (z + 1 <= z1) {
-                if (MODE < 2) fetch_row<T, 4>(b + g.at(x0, y, z + 1), bq);
+                if (READS_B) fetch_row<T, 4>(b + g.at(x0, y, z + 1), bq);
                 if (MODE == 2) {
                     fetch_row<double, 4>(R + g.at(x0, y, z + 1), rq);
                     if (!DEFER) fetch_row<double, 4>(U + g.at(x0, y, z + 1), uq);
@@ -552,13 +565,14 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
                 for (int i = 0; i < 4; ++i)
                     ov[i] = (i == 0 && first) ? zero_of<T>() : Store<T>::from_acc(fmaT<A>(w, bv[i] - sc[i], C0[i + 1]));
                 store_row<T, 4>(static_cast<T *>(out) + o, ov);
-            } else if constexpr (MODE == 1) {
+            } else if constexpr (MODE == 1 || MODE == 4) {
                 A bv[4];
                 widen_row<T, 4>(bcur, bv);
                 A ov[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ov[i] = (i == 0 && first) ? A(0) : bv[i] - sc[i];
-                store_row<A, 4>(static_cast<A *>(out) + o, ov);
+                if constexpr (MODE == 1) store_row<A, 4>(static_cast<A *>(out) + o, ov);
+                else store_row<A, 4>(rbuf + (size_t)(it & 1) * rslot + (size_t)(gi - 1) * P + x0, ov);
             } else if constexpr (MODE == 3) {
                 // dense b and out: point (x, y, z) at ((z-1) n + (y-1)) n + x-1
                 // (the ghost x = 0 reads the row's first point and drops it)
@@ -606,13 +620,34 @@ __global__ __launch_bounds__(1024) void k_q1_lds(const T *__restrict__ b, const 
             if (z + 3 <= z1 + 1) fetch(z + 3, rr);
         }
         __syncthreads();
+        if constexpr (FR) {
+            // coarse point (X, Y) of this tile: fine rows 2Y - 1 .. 2Y + 1 are
+            // residual rows 2j .. 2j + 2 of the slot written before the barrier
+            const int Pc = (n - 1) / 2 + 1, nc = Pc - 1;
+            const int t = (int)threadIdx.x, j = t / Pc, X = t - j * Pc, Y = (y0 + 1) / 2 + j;
+            if (j < TY / 2 && X >= 1 && Y <= nc) {
+                const A *q = rbuf + (size_t)(it & 1) * rslot + (size_t)(2 * j) * P + 2 * X;
+                auto row = [&](const A *v) -> A { return (v[-1] + v[1]) + A(2) * v[0]; };
+                const A py = (row(q) + row(q + 2 * P)) + A(2) * row(q + P);
+                if (z & 1) {
+                    if (z > z0) {
+                        A sum = (pm + py) + A(2) * p0;
+                        sum *= A(1.0 / 64.0);
+                        static_cast<TC *>(out)[Grid<3>{Pc}.at(X, Y, (z - 1) / 2)] = store_as<TC>(sum);
+                    }
+                    pm = py;
+                } else {
+                    p0 = py;
+                }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             Am[k] = A0[k], Cm[k] = C0[k];
             A0[k] = Ap[k], C0[k] = Cp[k];
         }
     }
-    if constexpr (MODE >= 2) {
+    if constexpr (MODE == 2 || MODE == 3) {
         block_reduce(ss, mx, red);
         if (threadIdx.x == 0) {
             part[2 * blockIdx.x] = ss;
@@ -925,6 +960,38 @@ hipError_t q1_lds_launch(int n, int P, const void *b, const void *c, void *out, 
     return hipGetLastError();
 }
 
+// Shape of the fused residual + restriction (k_q1_lds mode 4): o.ty fine rows
+// and o.zc fine planes per block (both even), or with o.ty = 0 the most rows,
+// up to 6, that 1024 threads ((ty + 3) P / 4) and 64 KB of LDS (two slots of
+// c rows, two of residual rows in the accumulator format) allow, and planes
+// so that the blocks about fill four rounds over the CUs.
+Q1LdsShape q1_fr_shape(int n, int P, size_t sb, size_t sa, const Q1Shape &o) {
+    Q1LdsShape s{};
+    const int TX = P / 4, nc = (n - 1) / 2;
+    auto lds = [&](int ty) {
+        return ((2 * (((size_t)ty + 3) * P + 8) * sb + 15) & ~(size_t)15) + 2 * ((size_t)ty + 1) * P * sa;
+    };
+    if (o.ty > 0) {
+        s.TY = o.ty;
+        s.zc = o.zc;
+    } else {
+        s.TY = std::min(6, 1024 / TX - 3) & ~1;
+        while (s.TY > 2 && lds(s.TY) > 65536 - 512) s.TY -= 2;
+        const int yt = s.TY >= 2 ? (nc + s.TY / 2 - 1) / (s.TY / 2) : 1;
+        s.zc = 2 * std::max(1, std::min(8, (int)(((long)nc * yt + 1023) / 1024)));
+    }
+    s.ytiles = s.TY >= 2 ? (nc + s.TY / 2 - 1) / (s.TY / 2) : 0;
+    s.blocks = s.zc >= 2 ? s.ytiles * ((nc + s.zc / 2 - 1) / (s.zc / 2)) : 0;
+    s.lds = lds(std::max(s.TY, 0));
+    return s;
+}
+bool q1_fr_ok(int n, int P, size_t sb, size_t sa, const Q1Shape &o) {
+    if (sb != 2 || P % 4 != 0 || n < 3 || n % 2 == 0 || o.split) return false;
+    const Q1LdsShape s = q1_fr_shape(n, P, sb, sa, o);
+    return s.TY >= 2 && s.TY % 2 == 0 && (s.TY + 3) * (P / 4) <= 1024 && s.zc >= 2 && s.zc % 2 == 0 &&
+           s.zc <= n + 1 && s.lds <= 65536 - 512 && s.blocks >= 1;
+}
+
 // The final residual r = b - hd S u of a 3-D level from the dense b (k_q1_lds
 // mode 3): FP64 rows in LDS, the built-in shape for 8-byte elements; false
 // where it does not apply (pitch, threads, LDS, more blocks than partials).
@@ -968,6 +1035,20 @@ hipError_t restrict_t(int D, int n, int P, const void *b, const void *c, void *r
     const int nc = (n - 1) / 2, Pc = nc + 1;
     const unsigned Nc = npoints(D, nc);
     A *r = static_cast<A *>(rs);
+    const bool builtin = qs.ty == 0 && qs.zc == 0;
+    if constexpr (sizeof(T) == 2) {  // the levels that take the LDS-staged kernels
+        if (D == 3 && q1_lds_ok(n, P, sizeof(T)) && !qs.split &&
+            (!builtin || q1_fr_ok(n, P, sizeof(T), sizeof(A), qs))) {
+            // residual and restriction in one pass (the fine residual stays in
+            // LDS; the built-in shape falls back to two kernels where no tile fits)
+            if (!q1_fr_ok(n, P, sizeof(T), sizeof(A), qs)) return hipErrorInvalidValue;
+            const Q1LdsShape s = q1_fr_shape(n, P, sizeof(T), sizeof(A), qs);
+            hipLaunchKernelGGL((k_q1_lds<T, 4, false, TC>), dim3(s.blocks), dim3((s.TY + 3) * (P / 4)), s.lds, st,
+                               static_cast<const T *>(b), static_cast<const T *>(c), bc, n, P, s.TY, s.zc, s.ytiles,
+                               A(0), nullptr, nullptr, nullptr, 0.0, nullptr, Q1Ring{}, 0);
+            return hipGetLastError();
+        }
+    }
     if (P % 4 == 0) {
         const dim3 g4 = q1_grid4(D, n, P);
         if (D == 3 && q1_lds_ok(n, P, sizeof(T))) {
@@ -1098,15 +1179,30 @@ size_t q1_resid_bytes(int D, int prec, int P) {
 
 bool q1_lds_level(int D, int prec, int n, int P) { return D == 3 && q1_lds_ok(n, P, prec_bytes(prec)); }
 
-bool q1_shape_ok(int D, int prec, int n, int P, const Q1Shape &s) {
+namespace {
+size_t q1_acc_bytes(int prec) { return prec == P_F64 ? 8 : 4; }
+bool q1_fused_restrict(int kernel, const Q1Shape &s) { return kernel == 1 && !s.split; }
+}  // namespace
+
+bool q1_shape_ok(int D, int prec, int n, int P, int kernel, const Q1Shape &s) {
+    if (s.split != 0 && (s.split != 1 || kernel != 1)) return false;
+    if (!q1_lds_level(D, prec, n, P)) return s.ty == 0 && s.zc == 0 && s.split == 0;
     if (s.ty == 0 && s.zc == 0) return true;
-    return q1_lds_level(D, prec, n, P) && s.ty > 0 && q1_lds_ok(n, P, prec_bytes(prec), s);
+    if (s.ty <= 0) return false;
+    if (q1_fused_restrict(kernel, s)) return q1_fr_ok(n, P, prec_bytes(prec), q1_acc_bytes(prec), s);
+    return q1_lds_ok(n, P, prec_bytes(prec), s);
 }
 
-Q1Shape q1_shape_used(int D, int prec, int n, int P, const Q1Shape &s) {
+Q1Shape q1_shape_used(int D, int prec, int n, int P, int kernel, const Q1Shape &s) {
     if (!q1_lds_level(D, prec, n, P)) return Q1Shape{};
+    const bool builtin = s.ty == 0 && s.zc == 0;
+    if (q1_fused_restrict(kernel, s) &&
+        (!builtin || q1_fr_ok(n, P, prec_bytes(prec), q1_acc_bytes(prec), s))) {
+        const Q1LdsShape u = q1_fr_shape(n, P, prec_bytes(prec), q1_acc_bytes(prec), s);
+        return Q1Shape{u.TY, u.zc, 0};
+    }
     const Q1LdsShape u = q1_lds_shape(n, P, prec_bytes(prec), s);
-    return Q1Shape{u.TY, u.zc};
+    return Q1Shape{u.TY, u.zc, kernel == 1 ? 1 : 0};
 }
 
 int q1_outer_blocks(int D, int n, int prec, const Q1Shape &qs) {

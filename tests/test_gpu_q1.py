@@ -104,6 +104,40 @@ def test_q1_resid_restrict(dev, ref, pf, pc, dim, n):
     assert rel_err(out, expect) <= max(TOL[pc], ACC_TOL[pf])
 
 
+@pytest.mark.parametrize("pf,pc", [("f16", "f16"), ("f16", "f32"), ("bf16", "f64"), ("bf16", "bf16")])
+@pytest.mark.parametrize("n", [31, 47, 63, 95, 127])
+def test_q1_fused_restrict_bitwise(dev, pf, pc, n):
+    """On 3-D levels in a 2-byte format the residual and its restriction run
+    as one kernel (the fine residual kept in LDS); for several tile shapes,
+    ragged last tiles and chunks included, the restricted b equals that of the
+    two kernels bit for bit."""
+    print(f"q1 fused restrict {pf}->{pc} n={n}", flush=True)
+    s = _solver(3, n, pf, pc)
+    assert s.get_shape(0, mgir.SHAPE_SWEEP) != [0, 0]  # a level with the LDS-staged kernels
+    assert s.get_shape(0, mgir.SHAPE_RESTRICT, 3)[2] == 0  # fused by default
+    rng = np.random.default_rng(31 * n)
+    _put(s, 0, mgir.BUF_RHS, rng.uniform(-1, 1, (n,) * 3), dev)
+    _put(s, 0, mgir.BUF_COR, 0.3 * rng.uniform(-1, 1, (n,) * 3), dev)
+    s.set_shape(0, mgir.SHAPE_RESTRICT, [0, 0, 1])
+    assert s.get_shape(0, mgir.SHAPE_RESTRICT, 3)[2] == 1
+    s.stage(mgir.STAGE_RESTRICT, 0)
+    ref = s.read(1, mgir.BUF_RHS).clone()
+    tried = 0
+    for shape in ([0, 0], [2, 2], [4, 4], [2, 16], [6, 8], [4, 32], [8, 6]):
+        try:
+            s.set_shape(0, mgir.SHAPE_RESTRICT, shape)
+        except mgir.MgError:
+            continue
+        tried += 1
+        s.write(1, mgir.BUF_RHS, torch.full_like(ref, 7.0))
+        s.stage(mgir.STAGE_RESTRICT, 0)
+        assert torch.equal(s.read(1, mgir.BUF_RHS), ref), shape
+    assert tried >= 3
+    for bad in ([3, 4], [2, 3], [2, 4, 2]):
+        with pytest.raises(mgir.MgError):
+            s.set_shape(0, mgir.SHAPE_RESTRICT, bad)
+
+
 @pytest.mark.parametrize("pf,pc", [(a, b) for a in PRECS for b in PRECS])
 @pytest.mark.parametrize("dim,n", [(3, 15), (3, 47), (2, 63), (2, 95), (3, 9), (3, 21), (2, 9)])
 def test_q1_prolong_sweep(dev, ref, pf, pc, dim, n):
@@ -288,14 +322,16 @@ def test_q1_lds_shapes_bitwise(dev, name, n, defer):
     u0, r0 = s.solve(b)
     u0 = u0.clone()
     tried = 0
-    for ty, zc in ((1, 2), (3, 5), (5, 16), (2, 32), (4, 7), (6, 1)):
+    for ty, zc, split in ((1, 2, 1), (3, 5, 1), (5, 16, 1), (2, 32, 0), (4, 7, 1), (6, 1, 1), (2, 2, 0), (4, 8, 0),
+                          (6, 16, 0)):
         set_any = False
         for l in levels:
             for k in Q1_KINDS[: 3 if l == 0 else 2]:
+                shape = [ty, zc, split] if k == mgir.SHAPE_RESTRICT else [ty, zc]
                 try:
-                    s.set_shape(l, k, [ty, zc])
+                    s.set_shape(l, k, shape)
                     set_any = True
-                    assert s.get_shape(l, k) == [ty, zc]
+                    assert s.get_shape(l, k, len(shape)) == shape
                 except mgir.MgError:
                     s.set_shape(l, k, [0, 0])
         if not set_any:
@@ -359,9 +395,9 @@ def test_q1_autotuned_bitwise_and_cached(dev, tmp_path, monkeypatch):
     assert path.read_text().splitlines() == lines
 
     def shapes(s):
-        return [s.get_shape(l, k) for l in _q1_lds_levels(s) for k in Q1_KINDS[: 3 if l == 0 else 2]]
+        return [s.get_shape(l, k, 3) for l in _q1_lds_levels(s) for k in Q1_KINDS[: 3 if l == 0 else 2]]
 
-    assert shapes(a) == shapes(c) and all(t >= 1 and z >= 1 for t, z in shapes(a))
+    assert shapes(a) == shapes(c) and all(t >= 1 and z >= 1 for t, z, _ in shapes(a))
     for s in (a, c):
         u, r = s.solve(b)
         assert r.iterations == r0.iterations and torch.equal(u, u0)
