@@ -87,6 +87,45 @@ __global__ __launch_bounds__(kThreads) void k_q1_first(const T *__restrict__ b, 
     cout[o] = Store<T>::from_acc(w * bv);
 }
 
+// The same first sweep on a pitch that is a multiple of 4: one thread per
+// four-point segment x0 = 4t of a row (vector loads and stores; the ghost
+// x = 0 of the first segment receives zero, as it holds).
+template <int D, class T, bool FROM_R>
+__global__ __launch_bounds__(kThreads) void k_q1_first4(const T *__restrict__ b, const double *__restrict__ R,
+                                                        const double *__restrict__ scal, T *__restrict__ bout,
+                                                        T *__restrict__ cout, int n, int P, acc_t<T> w) {
+    typedef acc_t<T> A;
+    const int TX = P / 4;
+    const long rows = D == 3 ? (long)n * n : (long)n;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)TX * rows) return;
+    const int tx = (int)(t % TX);
+    const long row = t / TX;
+    const int y = D == 3 ? (int)(row % n) + 1 : 0;
+    const int z = D == 3 ? (int)(row / n) + 1 : (int)row + 1;
+    const size_t o = Grid<D>{P}.at(4 * tx, y, z);
+    A bv[4];
+    if constexpr (FROM_R) {
+        double rv[4];
+        load_row<double, 4>(R + o, rv);
+        const double inv = scal[1];
+        T bh[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bh[i] = Store<T>::from_f64(rv[i] * inv);
+        if (tx == 0) bh[0] = zero_of<T>();
+        store_row<T, 4>(bout + o, bh);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[i] = (A)widen(bh[i]);
+    } else {
+        load_row<T, 4>(b + o, bv);
+        if (tx == 0) bv[0] = A(0);
+    }
+    T cv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cv[i] = Store<T>::from_acc(w * bv[i]);
+    store_row<T, 4>(cout + o, cv);
+}
+
 // One Jacobi sweep: cout = c + w (b - S c).
 template <int D, class T>
 __global__ __launch_bounds__(kThreads) void k_q1_sweep(const T *__restrict__ b, const T *__restrict__ c,
@@ -893,6 +932,21 @@ hipError_t first_t(int D, int n, int P, const void *b, const double *R, const do
     const A w = (A)(omega * 0.375);
     const T *bb = static_cast<const T *>(b);
     T *bo = static_cast<T *>(bout), *co = static_cast<T *>(cout);
+    if (P % 4 == 0) {
+        const long segs = (long)(P / 4) * (D == 3 ? (long)n * n : (long)n);
+        const unsigned blocks = (unsigned)((segs + kThreads - 1) / kThreads);
+#define MG_Q1F4(DD, FR)                                                                                        \
+    hipLaunchKernelGGL((k_q1_first4<DD, T, FR>), dim3(blocks), dim3(kThreads), 0, st, bb, R, scal, bo, co, n, P, w)
+        if (D == 3) {
+            if (R) MG_Q1F4(3, true);
+            else MG_Q1F4(3, false);
+        } else {
+            if (R) MG_Q1F4(2, true);
+            else MG_Q1F4(2, false);
+        }
+#undef MG_Q1F4
+        return hipGetLastError();
+    }
     if (R) {
         if (D == 3)
             hipLaunchKernelGGL((k_q1_first<3, T, true>), q1_grid(D, n), dim3(q1_bx(n)), 0, st, bb, R, scal, bo, co,
@@ -1253,6 +1307,9 @@ hipError_t launch_q1_resid_flat(int D, int n, int P, const double *b, const doub
                                 double hd, double *part, hipStream_t st) {
     const unsigned N = npoints(D, n);
     const int blocks = flat_blocks((long)N);
+    // r = b (no operator): the row-wise copy of the finite-difference path,
+    // which writes the same flat_blocks(points) partials
+    if (!U) return launch_resid_flat(D, n, P, b, nullptr, R, uout, 0.0, part, st);
     if (D == 3 && U && R && q1_final_lds_ok(n, P)) {
         // the LDS-staged form; it writes the partials of all `blocks`
         const Q1LdsShape s = q1_lds_shape(n, P, sizeof(double));
