@@ -18,10 +18,15 @@
 // threads on consecutive x.  Where the pitch is a multiple of 4 the sweep, the
 // residual and the FP64 update take four x points per thread with one vector
 // load per row: in 3-D marching z with three planes of row sums kept in
-// registers, in 2-D row by row.  Elsewhere they take one point per thread on
-// a (x blocks, n, n) grid.  The interpolation takes four fine points per thread
-// (each coarse value loaded once).  The restriction and interpolation remap
-// work-group numbers so that each XCD takes one contiguous range of points.
+// registers, in 2-D row by row.  On 3-D levels stored in a 2-byte format they
+// run as one LDS-staged kernel (k_q1_lds: a block's rows and the two around
+// them staged plane by plane, so each plane is read once per block row), which
+// also fuses the residual with its restriction and forms the final FP64 check
+// b - S u.  Elsewhere they take one point per thread on a (x blocks, n, n)
+// grid.  The first sweep from zero and the interpolation take four fine points
+// per thread (each coarse value loaded once).  The restriction and
+// interpolation remap work-group numbers so that each XCD takes one contiguous
+// range of points.
 #include "mg_device.h"
 #include "mg_launch.h"
 
